@@ -1,0 +1,236 @@
+/*
+ * tnep.h -- C ABI of libtnep: TNEP tensor evaluation and spectra on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: tensorial neuroevolution potential, arXiv:2312.05233.
+ *   - tnep_eval_dipole          : Sec. 2.2, Eq. (mu)
+ *       mu = - sum_i sum_{j != i} r_ij^2 dU_i/dr_ij,   r_ij = r_j - r_i
+ *   - tnep_eval_polarizability  : Sec. 2.3, Eq. (polarizability-model)
+ *       alpha^{uv} = sum_i U_i delta^{uv} - sum_i sum_{j != i} r_ij^u dU_i/dr_ij^v
+ *     (the same form serves the susceptibility chi)
+ *   - tnep_spectrum             : Secs. 2.5-2.6, IR lineshape M(w) with the
+ *     classical w^2 prefactor (Eq. ir-intensity) and the Raman lineshape
+ *     L(w) (Eq. raman-lineshape) with its isotropic / anisotropic split
+ *     (Eq. raman-lineshape-isotropic-anisotropic) or a polarisation
+ *     projection n^T alpha e (Eq. raman-cross-section).
+ * U_i is the output of a single-hidden-layer tanh network acting on the NEP
+ * descriptor of atom i (Sec. 2.1, Eq. site-energy); the descriptor is the
+ * NEP radial/angular form with Chebyshev radial functions, a cosine cutoff,
+ * angular invariants l = 1..4 and the l = 2 four-body term.
+ *
+ * Conventions
+ *   - Every call returns TNEP_OK (0) or a negative error code; nothing is
+ *     thrown across the ABI.  tnep_last_error() gives a message.
+ *   - Ownership: the caller owns every input and output buffer; calls borrow
+ *     them for their duration (tnep_submit: until tnep_wait returns for that
+ *     ticket).  Contexts, models and servers are library-owned and are freed
+ *     explicitly.
+ *   - Memory location: tnep_frames.location says whether the pointers in
+ *     that struct AND the output pointers of the call are host memory
+ *     (TNEP_HOST) or device memory of the context's GPU (TNEP_DEVICE).
+ *   - Threading: a context is used by one host thread at a time, except the
+ *     tnep_submit / tnep_wait pair, which is thread-safe.
+ *   - Units: positions in Angstrom; tensors are returned in the model's own
+ *     units (no conversion).
+ *   - Synchronous calls return after their results are complete.
+ */
+#ifndef TNEP_H
+#define TNEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define TNEP_OK 0
+#define TNEP_E_INVALID (-1)        /* bad argument, null pointer, bad size      */
+#define TNEP_E_SPECIES (-2)        /* species index outside [0, n_species)     */
+#define TNEP_E_BOX (-3)            /* periodic box shorter than 2 r_c^R, or a  */
+                                   /* non-orthorhombic cell                    */
+#define TNEP_E_OVERLAP (-4)        /* two atoms closer than 1e-4 Angstrom      */
+#define TNEP_E_NONFINITE (-5)      /* NaN / Inf in positions or cell           */
+#define TNEP_E_BUDGET (-6)         /* request exceeds the context's budget     */
+#define TNEP_E_MODEL (-7)          /* model shape not supported / bad model    */
+#define TNEP_E_HIP (-8)            /* HIP runtime failure                      */
+#define TNEP_E_NEIGH_OVERFLOW (-9) /* neighbour capacity exceeded (internal)   */
+#define TNEP_E_CANCELLED (-10)     /* request cancelled or server stopped      */
+
+/* ---- enums ------------------------------------------------------------- */
+#define TNEP_HOST 0
+#define TNEP_DEVICE 1
+
+#define TNEP_KIND_DIPOLE 1         /* rank-1: one tensor head               */
+#define TNEP_KIND_POLARIZABILITY 2 /* rank-2: tensor head + scalar head     */
+
+/* precision of the hidden layer (option TNEP_OPT_MLP) */
+#define TNEP_MLP_FP32_VALU 0  /* FP32 vector ALU                           */
+#define TNEP_MLP_FP32_MFMA 1  /* FP32 matrix cores                          */
+#define TNEP_MLP_BF16_MFMA 2  /* BF16 inputs, FP32 accumulation             */
+#define TNEP_MLP_BF16X3_MFMA 3 /* split-BF16 (hi/lo, 3 products), FP32 acc */
+
+/* options for tnep_set_option */
+#define TNEP_OPT_MLP 1            /* one of TNEP_MLP_*                          */
+#define TNEP_OPT_ATOMS_PER_BLOCK 2 /* work-group size of the fused kernel: 64, 128, 256 */
+#define TNEP_OPT_AUTOTUNE 3       /* 1 = pick launch parameters by measurement  */
+#define TNEP_OPT_DETERMINISTIC 4  /* 1 (default) = fixed reduction order        */
+#define TNEP_OPT_MAX_BATCH_ATOMS 5 /* atoms per launch batch (default 2^20)       */
+
+/* ---- opaque handles ---------------------------------------------------- */
+typedef struct tnep_ctx tnep_ctx;
+typedef struct tnep_model tnep_model;
+
+/* ---- model ------------------------------------------------------------- */
+/* Parameters of one TNEP model, FP64, host memory (copied at creation).
+ * Descriptor length D = (n_max_radial+1) + l_max*(n_max_angular+1)
+ *                       + (four_body ? n_max_angular+1 : 0),
+ * ordered [q^R_0..q^R_nR | l=1: q_{0,1}..q_{nA,1} | ... | l=l_max | q4_0..q4_nA].
+ * Network (per head): U = sum_m w1[m] tanh(sum_n w0[m][n] q_scaler[n] q[n] - b0[m]) - b1. */
+typedef struct {
+    int32_t kind;          /* TNEP_KIND_DIPOLE or TNEP_KIND_POLARIZABILITY          */
+    int32_t n_species;     /* T                                                      */
+    double rc_radial;      /* radial cutoff r_c^R, Angstrom                          */
+    double rc_angular;     /* angular cutoff r_c^A <= r_c^R                          */
+    int32_t n_max_radial;  /* nR: nR+1 radial functions                              */
+    int32_t n_max_angular; /* nA: nA+1 angular radial functions                      */
+    int32_t basis_radial;  /* KR: KR+1 Chebyshev terms                               */
+    int32_t basis_angular; /* KA                                                     */
+    int32_t l_max;         /* must be 4                                              */
+    int32_t four_body;     /* 0 / 1: l = 2 four-body invariant                       */
+    int32_t n_hidden;      /* H, 1..128                                              */
+    const double* c_radial;  /* [T][T][nR+1][KR+1], block (t_i, t_j)                 */
+    const double* c_angular; /* [T][T][nA+1][KA+1]                                   */
+    const double* q_scaler;  /* [D]                                                  */
+    const double* w0[2];     /* head 0 tensor, head 1 scalar (polarizability): [H][D] */
+    const double* b0[2];     /* [H]                                                  */
+    const double* w1[2];     /* [H]                                                  */
+    double b1[2];
+} tnep_model_desc;
+
+/* ---- frames ------------------------------------------------------------ */
+/* A batch of ragged frames, CSR by atom.  Periodic axes use the minimum-image
+ * convention and need an orthorhombic cell with edge >= 2 r_c^R. */
+typedef struct {
+    int32_t n_frames;
+    const int64_t* atom_offsets; /* [n_frames+1], offsets[0] = 0, non-decreasing   */
+    const double* positions;     /* [total_atoms][3], Angstrom                     */
+    const int32_t* species;      /* [total_atoms], 0..n_species-1                  */
+    const double* cells;         /* [n_frames][9] row-major lattice vectors or NULL */
+    const uint8_t* pbc;          /* [n_frames][3] periodic flags or NULL (vacuum)   */
+    int32_t location;            /* TNEP_HOST or TNEP_DEVICE                        */
+} tnep_frames;
+
+/* ---- context ----------------------------------------------------------- */
+/* Create a context on `device`.  hip_stream: a hipStream_t to run on, or NULL
+ * for a context-owned stream.  mem_budget_bytes: device-memory ceiling for the
+ * context's work buffers (0 = 32 GiB).  Returns TNEP_E_HIP if the device is
+ * unusable. */
+int tnep_ctx_create(int device, void* hip_stream, uint64_t mem_budget_bytes, tnep_ctx** out);
+void tnep_ctx_destroy(tnep_ctx* ctx);
+/* Message of the last failing call on ctx (library-owned, valid until the next
+ * call on ctx).  ctx may be NULL for errors of tnep_ctx_create. */
+const char* tnep_last_error(const tnep_ctx* ctx);
+/* Set an integer option (TNEP_OPT_*).  TNEP_E_INVALID for unknown keys/values. */
+int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value);
+/* Device bytes currently held by the context's work buffers. */
+uint64_t tnep_ctx_memory_in_use(const tnep_ctx* ctx);
+
+/* ---- model ------------------------------------------------------------- */
+/* Copy a model to the device (resident until tnep_model_free). TNEP_E_MODEL if
+ * the shape is unsupported (l_max != 4, rc_angular > rc_radial, sizes out of
+ * range). */
+int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* desc, tnep_model** out);
+void tnep_model_free(tnep_model* model);
+
+/* ---- evaluation -------------------------------------------------------- */
+/* Dipole of every frame (Sec. 2.2, Eq. mu).  mu_out: [n_frames][3] FP64.
+ * per_atom: NULL or [total_atoms][3] FP64, the atom terms
+ * -sum_j r_ij^2 dU_i/dr_ij whose frame sums are mu_out.  The model must be
+ * a dipole model.  Frame sums are FP64 in a fixed order: results do not
+ * depend on how frames are batched. */
+int tnep_eval_dipole(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames,
+                     double* mu_out, double* per_atom);
+
+/* Polarizability / susceptibility of every frame (Sec. 2.3, Eq.
+ * polarizability-model).  alpha_out: [n_frames][9] FP64 row-major (u, v).
+ * per_atom: NULL or [total_atoms][9] FP64 (U^s_i delta - sum_j r_ij (x) dU^t_i/dr_ij).
+ * The model must be a polarizability model (scalar head for the delta term,
+ * tensor head for the virial term). */
+int tnep_eval_polarizability(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames,
+                             double* alpha_out, double* per_atom);
+
+/* Dipole with one model and polarizability with another over the same frames
+ * (Secs. 2.2-2.3), sharing one neighbour search when the two models have the
+ * same cutoffs.  mu_out [n_frames][3], alpha_out [n_frames][9], FP64. */
+int tnep_eval_dipole_polarizability(tnep_ctx* ctx, const tnep_model* dipole_model,
+                                    const tnep_model* polarizability_model, const tnep_frames* frames,
+                                    double* mu_out, double* alpha_out);
+
+/* ---- spectra ----------------------------------------------------------- */
+#define TNEP_IR 0          /* series rank 1 [.][3]: (1/3) sum_a <mu_a(0) mu_a(t)>, x w^2      */
+#define TNEP_RAMAN_ISO 1   /* rank 2 [.][9]: <gamma(0) gamma(t)>, gamma = Tr(alpha)/3         */
+#define TNEP_RAMAN_ANISO 2 /* rank 2: <Tr beta(0) beta(t)>, beta = alpha - gamma I           */
+#define TNEP_RAMAN_PROJ 3  /* rank 2: <s(0) s(t)>, s = n^T alpha e                           */
+
+#define TNEP_WIN_HANN 0    /* lag window w(tau) = (1 + cos(pi tau / M)) / 2 */
+#define TNEP_WIN_NONE 1
+
+#define TNEP_SUBTRACT_MEAN 1 /* flags: remove each series' time mean first   */
+#define TNEP_NO_OMEGA2 2     /* flags: IR without the w^2 prefactor           */
+
+typedef struct {
+    int32_t kind;          /* TNEP_IR / TNEP_RAMAN_*                                  */
+    int32_t n_series;      /* independent runs; spectra are averaged over them         */
+    int64_t n_steps;       /* N_t samples per run (>= 2)                               */
+    const double* series;  /* [n_series][n_steps][3 or 9], FP64                        */
+    double dt_fs;          /* sample spacing, fs                                       */
+    int64_t max_lag;       /* M, 1 <= M <= n_steps                                     */
+    int32_t window;        /* TNEP_WIN_*                                               */
+    int32_t flags;         /* TNEP_SUBTRACT_MEAN | TNEP_NO_OMEGA2                      */
+    double n_hat[3];       /* TNEP_RAMAN_PROJ only                                     */
+    double e_hat[3];
+    int32_t location;      /* TNEP_HOST / TNEP_DEVICE for series and the outputs       */
+} tnep_spectrum_args;
+
+/* Correlation function of the series (time-origin average, 1/(N_t - tau)
+ * normalisation, tau = 0..M-1), its one-sided windowed cosine transform
+ *   S(w_k) = dt/(2 pi) [w(0) C(0) + 2 sum_{tau=1}^{M-1} w(tau) C(tau) cos(w_k tau dt)],
+ *   w_k = pi k / (M dt), k = 0..M,
+ * times w_k^2 for TNEP_IR (unless TNEP_NO_OMEGA2), averaged over the series.
+ * freq_cm1: [M+1] wavenumbers k / (2 M dt c); intensity: [M+1]; acf: NULL or [M].
+ * All FP64. */
+int tnep_spectrum(tnep_ctx* ctx, const tnep_spectrum_args* args, double* freq_cm1, double* intensity,
+                  double* acf);
+
+/* ---- serving (continuous batching) ------------------------------------- */
+typedef struct {
+    uint64_t mem_budget_bytes; /* admission budget for in-flight requests (0 = ctx budget) */
+    int32_t max_batch_atoms;   /* atoms per fused launch (0 = 262144)                       */
+    int32_t max_inflight;      /* launches in flight on the device (0 = 2)                  */
+} tnep_server_opts;
+
+/* Start the server thread of ctx.  After this, only tnep_submit / tnep_wait /
+ * tnep_server_stop / tnep_server_stats may be used on ctx. */
+int tnep_server_start(tnep_ctx* ctx, const tnep_server_opts* opts);
+/* Queue one request: `kind` selects dipole (out [n_frames][3]) or
+ * polarizability (out [n_frames][9]); frames and out must be host memory and
+ * stay valid until tnep_wait returns for the ticket.  Returns TNEP_E_BUDGET
+ * if the request alone can never fit the admission budget. */
+int tnep_submit(tnep_ctx* ctx, const tnep_model* model, int32_t kind, const tnep_frames* frames, double* out,
+                uint64_t* ticket);
+/* Block until the request is done.  status: the request's own TNEP_* code;
+ * latency_s: submit-to-completion time in seconds.  Each ticket is waited
+ * for once. */
+int tnep_wait(tnep_ctx* ctx, uint64_t ticket, int32_t* status, double* latency_s);
+/* Drain and stop the server thread. */
+int tnep_server_stop(tnep_ctx* ctx);
+/* Counters since start: requests done, fused launches, atom-frames done,
+ * peak admitted bytes. */
+int tnep_server_stats(tnep_ctx* ctx, uint64_t* requests, uint64_t* launches, uint64_t* atom_frames,
+                      uint64_t* peak_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNEP_H */

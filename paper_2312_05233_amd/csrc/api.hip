@@ -1,0 +1,393 @@
+// C ABI of libtnep (declared in include/tnep.h): contexts, resident models,
+// batched evaluation of the TNEP dipole (Sec. 2.2, Eq. mu) and
+// polarizability / susceptibility (Sec. 2.3, Eq. polarizability-model), and
+// spectra (Secs. 2.5-2.6).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tnep.h"
+#include "internal.h"
+#include "runtime.h"
+
+using namespace tnep;
+
+// ---------------------------------------------------------------------------
+// error plumbing
+
+static thread_local std::string g_create_error;
+
+int tnep::Ctx::fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+}
+
+#define HIP_TRY HIP_CHECK_RET
+
+// ---------------------------------------------------------------------------
+// device buffers
+
+int tnep::Ctx::reserve(DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes) return TNEP_OK;
+    const size_t want = std::max(bytes, b.bytes + b.bytes / 4);
+    if (in_use - b.bytes + want > budget)
+        return fail(TNEP_E_BUDGET, "device budget exceeded: need %zu more bytes (budget %llu, in use %llu)",
+                    want - b.bytes, (unsigned long long)budget, (unsigned long long)in_use);
+    if (b.p) {
+        hipStreamSynchronize(stream);
+        hipFree(b.p);
+        in_use -= b.bytes;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) return fail(TNEP_E_HIP, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    b.bytes = want;
+    in_use += want;
+    peak = std::max(peak, in_use);
+    return TNEP_OK;
+}
+
+void tnep::Ctx::release(DevBuf& b) {
+    if (b.p) {
+        hipFree(b.p);
+        in_use -= b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+tnep::Ctx::~Ctx() {
+    if (stream) hipStreamSynchronize(stream);
+    for (DevBuf* b : all_buffers()) release(*b);
+    if (h_flags) hipHostFree(h_flags);
+    if (own_stream && stream) hipStreamDestroy(stream);
+}
+
+// ---------------------------------------------------------------------------
+// context
+
+extern "C" int tnep_ctx_create(int device, void* hip_stream, uint64_t mem_budget_bytes, tnep_ctx** out) {
+    if (!out) {
+        g_create_error = "out is NULL";
+        return TNEP_E_INVALID;
+    }
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        g_create_error = "no such HIP device";
+        return TNEP_E_HIP;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        g_create_error = "hipSetDevice failed";
+        return TNEP_E_HIP;
+    }
+    Ctx* c = new Ctx();
+    c->device = device;
+    c->budget = mem_budget_bytes ? mem_budget_bytes : (uint64_t)32 << 30;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            g_create_error = "hipStreamCreate failed";
+            return TNEP_E_HIP;
+        }
+        c->own_stream = true;
+    }
+    if (hipHostMalloc((void**)&c->h_flags, sizeof(int32_t) * 8, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        g_create_error = "hipHostMalloc failed";
+        return TNEP_E_HIP;
+    }
+    *out = reinterpret_cast<tnep_ctx*>(c);
+    return TNEP_OK;
+}
+
+extern "C" void tnep_ctx_destroy(tnep_ctx* ctx) {
+    if (!ctx) return;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    server_shutdown(c);
+    hipSetDevice(c->device);
+    delete c;
+}
+
+extern "C" const char* tnep_last_error(const tnep_ctx* ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return reinterpret_cast<const Ctx*>(ctx)->err.c_str();
+}
+
+extern "C" uint64_t tnep_ctx_memory_in_use(const tnep_ctx* ctx) {
+    return ctx ? reinterpret_cast<const Ctx*>(ctx)->in_use : 0;
+}
+
+extern "C" int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value) {
+    if (!ctx) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    switch (key) {
+        case TNEP_OPT_MLP:
+            if (value < TNEP_MLP_FP32_VALU || value > TNEP_MLP_BF16X3_MFMA)
+                return c->fail(TNEP_E_INVALID, "unknown MLP mode %lld", (long long)value);
+            c->launch.mlp_mode = (int)value;
+            return TNEP_OK;
+        case TNEP_OPT_ATOMS_PER_BLOCK:
+            if (value != 64 && value != 128 && value != 256)
+                return c->fail(TNEP_E_INVALID, "atoms per block must be 64, 128 or 256");
+            c->launch.atoms_per_block = (int)value;
+            return TNEP_OK;
+        case TNEP_OPT_AUTOTUNE:
+            c->autotune = value != 0;
+            return TNEP_OK;
+        case TNEP_OPT_DETERMINISTIC:
+            if (value == 0) return c->fail(TNEP_E_INVALID, "only the deterministic reduction is implemented");
+            return TNEP_OK;
+        case TNEP_OPT_MAX_BATCH_ATOMS:
+            if (value < 1) return c->fail(TNEP_E_INVALID, "max batch atoms must be positive");
+            c->max_batch_atoms = value;
+            return TNEP_OK;
+        default:
+            return c->fail(TNEP_E_INVALID, "unknown option %d", key);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// models
+
+extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_model** out) {
+    if (!ctx || !d || !out) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    *out = nullptr;
+    if (d->kind != TNEP_KIND_DIPOLE && d->kind != TNEP_KIND_POLARIZABILITY)
+        return c->fail(TNEP_E_MODEL, "unknown model kind %d", d->kind);
+    if (d->n_species < 1 || d->n_species > 8) return c->fail(TNEP_E_MODEL, "n_species must be 1..8");
+    if (!(d->rc_radial > 0) || !(d->rc_angular > 0) || d->rc_angular > d->rc_radial)
+        return c->fail(TNEP_E_MODEL, "need 0 < rc_angular <= rc_radial");
+    if (d->l_max != 4) return c->fail(TNEP_E_MODEL, "only l_max = 4 is compiled");
+    if (d->n_hidden < 1 || d->n_hidden > 128) return c->fail(TNEP_E_MODEL, "n_hidden must be 1..128");
+    Shape sh{d->n_max_radial + 1, d->n_max_angular + 1, d->basis_radial + 1, d->basis_angular + 1,
+             d->four_body ? 1 : 0, d->kind};
+    if (!eval_shape_supported(sh))
+        return c->fail(TNEP_E_MODEL, "descriptor shape (nR=%d, nA=%d, KR=%d, KA=%d, 4b=%d) is not compiled",
+                       d->n_max_radial, d->n_max_angular, d->basis_radial, d->basis_angular, d->four_body);
+    if (!d->c_radial || !d->c_angular || !d->q_scaler || !d->w0[0] || !d->b0[0] || !d->w1[0])
+        return c->fail(TNEP_E_MODEL, "missing parameter arrays");
+    const int heads = d->kind == TNEP_KIND_POLARIZABILITY ? 2 : 1;
+    if (heads == 2 && (!d->w0[1] || !d->b0[1] || !d->w1[1]))
+        return c->fail(TNEP_E_MODEL, "polarizability model needs the scalar head");
+    const int T = d->n_species, H = d->n_hidden;
+    const int D = sh.nr + 4 * sh.na + (sh.four_body ? sh.na : 0);
+    const size_t ncr = (size_t)T * T * sh.nr * sh.kr, nca = (size_t)T * T * sh.na * sh.ka;
+
+    // host staging in FP32, fixed layout
+    std::vector<float> h;
+    auto put = [&](const double* src, size_t n) {
+        size_t off = h.size();
+        for (size_t k = 0; k < n; ++k) h.push_back((float)src[k]);
+        while (h.size() % 64) h.push_back(0.f);  // 256-byte alignment
+        return off;
+    };
+    for (size_t k = 0; k < ncr; ++k)
+        if (!std::isfinite(d->c_radial[k])) return c->fail(TNEP_E_MODEL, "non-finite c_radial");
+    size_t o_cr = put(d->c_radial, ncr);
+    size_t o_ca = put(d->c_angular, nca);
+    size_t o_s = put(d->q_scaler, D);
+    size_t o_w0[2] = {0, 0}, o_b0[2] = {0, 0}, o_w1[2] = {0, 0}, o_w0t[2] = {0, 0};
+    for (int hd = 0; hd < heads; ++hd) {
+        o_w0[hd] = put(d->w0[hd], (size_t)H * D);
+        o_b0[hd] = put(d->b0[hd], H);
+        o_w1[hd] = put(d->w1[hd], H);
+        std::vector<double> t((size_t)D * H);
+        for (int mu = 0; mu < H; ++mu)
+            for (int nu = 0; nu < D; ++nu) t[(size_t)nu * H + mu] = d->w0[hd][(size_t)mu * D + nu];
+        o_w0t[hd] = put(t.data(), t.size());
+    }
+    for (float v : h)
+        if (!std::isfinite(v)) return c->fail(TNEP_E_MODEL, "non-finite model parameter");
+
+    Model* m = new Model();
+    m->ctx = c;
+    m->shape = sh;
+    m->kind = d->kind;
+    m->T = T;
+    m->D = D;
+    m->H = H;
+    m->rc_radial = d->rc_radial;
+    m->rc_angular = d->rc_angular;
+    hipSetDevice(c->device);
+    if (hipMalloc(&m->dbuf, h.size() * sizeof(float)) != hipSuccess) {
+        delete m;
+        return c->fail(TNEP_E_HIP, "hipMalloc for model failed");
+    }
+    m->bytes = h.size() * sizeof(float);
+    if (hipMemcpy(m->dbuf, h.data(), m->bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(m->dbuf);
+        delete m;
+        return c->fail(TNEP_E_HIP, "model upload failed");
+    }
+    const float* base = (const float*)m->dbuf;
+    DevModel& dm = m->dm;
+    dm.c_radial = base + o_cr;
+    dm.c_angular = base + o_ca;
+    dm.scaler = base + o_s;
+    for (int hd = 0; hd < 2; ++hd) {
+        const int src = hd < heads ? hd : 0;
+        dm.w0[hd] = base + o_w0[src];
+        dm.b0[hd] = base + o_b0[src];
+        dm.w1[hd] = base + o_w1[src];
+        dm.w0t[hd] = base + o_w0t[src];
+        dm.b1[hd] = (float)d->b1[src];
+    }
+    dm.rc_radial = (float)d->rc_radial;
+    dm.rc_angular = (float)d->rc_angular;
+    dm.n_species = T;
+    dm.n_hidden = H;
+    *out = reinterpret_cast<tnep_model*>(m);
+    return TNEP_OK;
+}
+
+extern "C" void tnep_model_free(tnep_model* model) {
+    if (!model) return;
+    Model* m = reinterpret_cast<Model*>(model);
+    if (m->dbuf) {
+        hipSetDevice(m->ctx->device);
+        hipDeviceSynchronize();
+        hipFree(m->dbuf);
+    }
+    delete m;
+}
+
+// ---------------------------------------------------------------------------
+// evaluation
+
+static int check_frames(Ctx* c, const tnep_frames* f) {
+    if (!f) return c->fail(TNEP_E_INVALID, "frames is NULL");
+    if (f->n_frames < 0) return c->fail(TNEP_E_INVALID, "negative n_frames");
+    if (f->location != TNEP_HOST && f->location != TNEP_DEVICE)
+        return c->fail(TNEP_E_INVALID, "bad location %d", f->location);
+    if (f->n_frames > 0 && (!f->atom_offsets || !f->positions || !f->species))
+        return c->fail(TNEP_E_INVALID, "NULL frame arrays");
+    return TNEP_OK;
+}
+
+extern "C" int tnep_eval_dipole(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames, double* mu_out,
+                                double* per_atom) {
+    if (!ctx) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    const Model* m = reinterpret_cast<const Model*>(model);
+    if (!m || m->kind != TNEP_KIND_DIPOLE) return c->fail(TNEP_E_INVALID, "a dipole model is required");
+    int e = check_frames(c, frames);
+    if (e) return e;
+    if (frames->n_frames > 0 && !mu_out) return c->fail(TNEP_E_INVALID, "mu_out is NULL");
+    EvalJob job;
+    job.models[0] = m;
+    job.out[0] = mu_out;
+    job.per_atom[0] = per_atom;
+    job.n_models = 1;
+    return run_eval(c, *frames, job);
+}
+
+extern "C" int tnep_eval_polarizability(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames,
+                                        double* alpha_out, double* per_atom) {
+    if (!ctx) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    const Model* m = reinterpret_cast<const Model*>(model);
+    if (!m || m->kind != TNEP_KIND_POLARIZABILITY)
+        return c->fail(TNEP_E_INVALID, "a polarizability model is required");
+    int e = check_frames(c, frames);
+    if (e) return e;
+    if (frames->n_frames > 0 && !alpha_out) return c->fail(TNEP_E_INVALID, "alpha_out is NULL");
+    EvalJob job;
+    job.models[0] = m;
+    job.out[0] = alpha_out;
+    job.per_atom[0] = per_atom;
+    job.n_models = 1;
+    return run_eval(c, *frames, job);
+}
+
+extern "C" int tnep_eval_dipole_polarizability(tnep_ctx* ctx, const tnep_model* dipole_model,
+                                               const tnep_model* polarizability_model, const tnep_frames* frames,
+                                               double* mu_out, double* alpha_out) {
+    if (!ctx) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    const Model* md = reinterpret_cast<const Model*>(dipole_model);
+    const Model* mp = reinterpret_cast<const Model*>(polarizability_model);
+    if (!md || md->kind != TNEP_KIND_DIPOLE || !mp || mp->kind != TNEP_KIND_POLARIZABILITY)
+        return c->fail(TNEP_E_INVALID, "need a dipole model and a polarizability model");
+    int e = check_frames(c, frames);
+    if (e) return e;
+    if (frames->n_frames > 0 && (!mu_out || !alpha_out)) return c->fail(TNEP_E_INVALID, "NULL output");
+    EvalJob job;
+    job.models[0] = md;
+    job.models[1] = mp;
+    job.out[0] = mu_out;
+    job.out[1] = alpha_out;
+    job.n_models = 2;
+    return run_eval(c, *frames, job);
+}
+
+// ---------------------------------------------------------------------------
+// spectra
+
+extern "C" int tnep_spectrum(tnep_ctx* ctx, const tnep_spectrum_args* a, double* freq_cm1, double* intensity,
+                             double* acf) {
+    if (!ctx) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!a || !freq_cm1 || !intensity) return c->fail(TNEP_E_INVALID, "NULL argument");
+    if (a->kind < TNEP_IR || a->kind > TNEP_RAMAN_PROJ) return c->fail(TNEP_E_INVALID, "unknown spectrum kind");
+    if (a->n_series < 1 || a->n_steps < 2 || !a->series) return c->fail(TNEP_E_INVALID, "empty series");
+    if (a->max_lag < 1 || a->max_lag > a->n_steps) return c->fail(TNEP_E_INVALID, "need 1 <= max_lag <= n_steps");
+    if (!(a->dt_fs > 0) || !std::isfinite(a->dt_fs)) return c->fail(TNEP_E_INVALID, "dt_fs must be positive");
+    if (a->window != TNEP_WIN_HANN && a->window != TNEP_WIN_NONE) return c->fail(TNEP_E_INVALID, "bad window");
+    if (a->location != TNEP_HOST && a->location != TNEP_DEVICE) return c->fail(TNEP_E_INVALID, "bad location");
+    if (a->n_steps > ((int64_t)1 << 26)) return c->fail(TNEP_E_INVALID, "n_steps above 2^26");
+    hipSetDevice(c->device);
+    SpectrumPlan p{};
+    p.kind = a->kind;
+    p.window = a->window;
+    p.flags = a->flags;
+    p.n_series = a->n_series;
+    p.n_steps = a->n_steps;
+    p.max_lag = a->max_lag;
+    p.dt_fs = a->dt_fs;
+    for (int k = 0; k < 3; ++k) {
+        p.n_hat[k] = a->n_hat[k];
+        p.e_hat[k] = a->e_hat[k];
+    }
+    int64_t P = 1;
+    while (P < 2 * a->n_steps) P <<= 1;
+    p.fft_len = P;
+    const int comps = a->kind == TNEP_IR ? 3 : 9;
+    const size_t series_bytes = sizeof(double) * (size_t)a->n_series * a->n_steps * comps;
+    const size_t M = (size_t)a->max_lag;
+    int e;
+    if ((e = c->reserve(c->spec_work, spectrum_workspace_bytes(p)))) return e;
+    const double* d_series = a->series;
+    double *d_freq = freq_cm1, *d_int = intensity, *d_acf = acf;
+    if (a->location == TNEP_HOST) {
+        if ((e = c->reserve(c->spec_series, series_bytes))) return e;
+        if ((e = c->reserve(c->spec_out, sizeof(double) * (3 * M + 2)))) return e;
+        HIP_TRY(c, hipMemcpyAsync(c->spec_series.p, a->series, series_bytes, hipMemcpyHostToDevice, c->stream));
+        d_series = (const double*)c->spec_series.p;
+        d_freq = (double*)c->spec_out.p;
+        d_int = d_freq + (M + 1);
+        d_acf = acf ? d_int + (M + 1) : nullptr;
+    }
+    HIP_TRY(c, launch_spectrum(p, d_series, d_freq, d_int, d_acf, c->spec_work.p, c->stream));
+    if (a->location == TNEP_HOST) {
+        HIP_TRY(c, hipMemcpyAsync(freq_cm1, d_freq, sizeof(double) * (M + 1), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(intensity, d_int, sizeof(double) * (M + 1), hipMemcpyDeviceToHost, c->stream));
+        if (acf) HIP_TRY(c, hipMemcpyAsync(acf, d_acf, sizeof(double) * M, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TNEP_OK;
+}

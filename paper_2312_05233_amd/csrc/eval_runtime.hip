@@ -1,0 +1,259 @@
+// Batched evaluation of TNEP tensors: host-side planning around the kernels.
+//
+// A call's frames are cut into launch batches of whole frames that fit the
+// context's neighbour-list capacity.  Per batch: upload frame geometry,
+// build neighbour lists once, then for every model run the fused evaluation
+// kernel and the fixed-order FP64 frame reduction.  Neighbour capacities are
+// learned: a batch whose atoms exceed them is detected after the call and
+// the whole call is repeated with larger lists.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "runtime.h"
+
+namespace tnep {
+
+namespace {
+
+__global__ void k_init_flags(int32_t* f) {
+    if (threadIdx.x < 8) f[threadIdx.x] = threadIdx.x == kFlagBadAtom ? INT_MAX : 0;
+}
+
+}  // namespace
+
+hipError_t launch_init_flags(int32_t* d_flags, hipStream_t s) {
+    k_init_flags<<<1, 64, 0, s>>>(d_flags);
+    return hipGetLastError();
+}
+
+int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc, FrameGeom& g) {
+    g = FrameGeom();
+    bool any = false;
+    for (int d = 0; d < 3; ++d) {
+        g.per[d] = pbc ? (pbc[d] != 0) : 0;
+        any = any || g.per[d];
+    }
+    if (!any) return TNEP_OK;
+    if (!cell) return c->fail(TNEP_E_BOX, "frame %d: periodic axes but no cell", f);
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(cell[k])) return c->fail(TNEP_E_NONFINITE, "frame %d: non-finite cell", f);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (a != b && cell[3 * a + b] != 0.0)
+                return c->fail(TNEP_E_BOX, "frame %d: only orthorhombic cells are supported", f);
+    bool all = true;
+    for (int d = 0; d < 3; ++d) {
+        g.L[d] = cell[4 * d];
+        if (g.per[d] && !(g.L[d] >= 2.0 * rc))
+            return c->fail(TNEP_E_BOX, "frame %d: box edge %g shorter than 2 r_c = %g", f, g.L[d], 2.0 * rc);
+        all = all && g.per[d];
+    }
+    if (all) {
+        bool ok = true;
+        for (int d = 0; d < 3; ++d) {
+            g.nc[d] = (int)std::floor(g.L[d] / rc);
+            if (g.nc[d] > 256) g.nc[d] = 256;
+            ok = ok && g.nc[d] >= 3;
+        }
+        if (ok) g.mode = 1;
+    }
+    return TNEP_OK;
+}
+
+namespace {
+
+struct HostMeta {
+    std::vector<int64_t> offs;
+    std::vector<double> cells;
+    std::vector<uint8_t> pbc;
+};
+
+int fetch_meta(Ctx* c, const tnep_frames& fr, HostMeta& m) {
+    const int F = fr.n_frames;
+    m.offs.resize(F + 1);
+    if (fr.cells) m.cells.resize((size_t)9 * F);
+    if (fr.pbc) m.pbc.resize((size_t)3 * F);
+    if (fr.location == TNEP_HOST) {
+        std::memcpy(m.offs.data(), fr.atom_offsets, sizeof(int64_t) * (F + 1));
+        if (fr.cells) std::memcpy(m.cells.data(), fr.cells, sizeof(double) * 9 * F);
+        if (fr.pbc) std::memcpy(m.pbc.data(), fr.pbc, 3 * (size_t)F);
+    } else {
+        hipError_t e = hipMemcpy(m.offs.data(), fr.atom_offsets, sizeof(int64_t) * (F + 1), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && fr.cells)
+            e = hipMemcpy(m.cells.data(), fr.cells, sizeof(double) * 9 * F, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && fr.pbc) e = hipMemcpy(m.pbc.data(), fr.pbc, 3 * (size_t)F, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return c->fail(TNEP_E_HIP, "reading frame metadata: %s", hipGetErrorString(e));
+    }
+    if (m.offs[0] != 0) return c->fail(TNEP_E_INVALID, "atom_offsets[0] must be 0");
+    for (int f = 0; f < F; ++f)
+        if (m.offs[f + 1] < m.offs[f]) return c->fail(TNEP_E_INVALID, "atom_offsets decrease at frame %d", f);
+    if (m.offs[F] >= ((int64_t)1 << 31)) return c->fail(TNEP_E_INVALID, "more than 2^31 atoms in one call");
+    return TNEP_OK;
+}
+
+inline int frame_of_atom(const std::vector<int64_t>& offs, int64_t a) {
+    return (int)(std::upper_bound(offs.begin(), offs.end(), a) - offs.begin()) - 1;
+}
+
+}  // namespace
+
+int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
+    const int F = fr.n_frames;
+    if (F == 0) return TNEP_OK;
+    hipSetDevice(c->device);
+    HostMeta meta;
+    int e = fetch_meta(c, fr, meta);
+    if (e) return e;
+    const int64_t A = meta.offs[F];
+
+    // models sharing cutoffs share one neighbour build
+    const Model* m0 = job.models[0];
+    bool shared = job.n_models == 1 || (job.models[1]->rc_radial == m0->rc_radial &&
+                                         job.models[1]->rc_angular == m0->rc_angular);
+    int n_species = m0->T;
+    for (int k = 0; k < job.n_models; ++k) n_species = std::min(n_species, job.models[k]->T);
+
+    for (int group = 0; group < (shared ? 1 : job.n_models); ++group) {
+        const Model* gm = job.models[group];
+        const int first = shared ? 0 : group, last = shared ? job.n_models : group + 1;
+        std::vector<FrameGeom> geom(F);
+        for (int f = 0; f < F; ++f) {
+            e = frame_geometry(c, f, fr.cells ? meta.cells.data() + 9 * (size_t)f : nullptr,
+                               fr.pbc ? meta.pbc.data() + 3 * (size_t)f : nullptr, gm->rc_radial, geom[f]);
+            if (e) return e;
+        }
+        bool done = false;
+        for (int attempt = 0; attempt < 4 && !done; ++attempt) {
+            // batch size in atoms
+            int64_t largest = 0;
+            for (int f = 0; f < F; ++f) largest = std::max(largest, meta.offs[f + 1] - meta.offs[f]);
+            const int64_t per_atom_bytes = (int64_t)(c->cap_ang + c->cap_rad) * 16 + 8 + 12 + 72 * (last - first) +
+                                           (fr.location == TNEP_HOST ? 28 : 0);
+            int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
+            B = std::max(B, largest);
+            // keep within the budget: shrink to what fits next to what is already held
+            const int64_t room = (int64_t)c->budget - (int64_t)(c->in_use - c->nbr.bytes - c->per_atom.bytes);
+            if (room > 0 && B * per_atom_bytes > room) B = std::max(largest, room / per_atom_bytes);
+            // reserve
+            if ((e = c->reserve(c->nbr, (size_t)B * (c->cap_ang + c->cap_rad) * sizeof(float4)))) return e;
+            if ((e = c->reserve(c->n_ang, (size_t)B * 4))) return e;
+            if ((e = c->reserve(c->n_rad, (size_t)B * 4))) return e;
+            if ((e = c->reserve(c->frame_of, (size_t)B * 4))) return e;
+            if ((e = c->reserve(c->cell_of, (size_t)B * 4))) return e;
+            if ((e = c->reserve(c->cell_atoms, (size_t)B * 4))) return e;
+            if ((e = c->reserve(c->per_atom, (size_t)B * 9 * sizeof(double) * (last - first)))) return e;
+            if ((e = c->reserve(c->flags, 64))) return e;
+            if (fr.location == TNEP_HOST) {
+                if ((e = c->reserve(c->pos, (size_t)B * 24))) return e;
+                if ((e = c->reserve(c->species, (size_t)B * 4))) return e;
+            }
+            HIP_CHECK_RET(c, launch_init_flags((int32_t*)c->flags.p, c->stream));
+
+            std::vector<std::vector<FrameInfo>> keep;  // host FrameInfo per batch, alive until sync
+            int f0 = 0;
+            while (f0 < F) {
+                int f1 = f0;
+                while (f1 < F && meta.offs[f1 + 1] - meta.offs[f0] <= B) ++f1;
+                if (f1 == f0) f1 = f0 + 1;
+                const int nf = f1 - f0;
+                const int64_t a0 = meta.offs[f0], na = meta.offs[f1] - a0;
+                keep.emplace_back(nf);
+                std::vector<FrameInfo>& fi = keep.back();
+                int n_cells = 0;
+                for (int k = 0; k < nf; ++k) {
+                    const FrameGeom& g = geom[f0 + k];
+                    FrameInfo& x = fi[k];
+                    std::memset(&x, 0, sizeof(x));
+                    x.atom_begin = meta.offs[f0 + k] - a0;
+                    x.n_atoms = (int32_t)(meta.offs[f0 + k + 1] - meta.offs[f0 + k]);
+                    x.mode = g.mode;
+                    for (int d = 0; d < 3; ++d) {
+                        x.nc[d] = g.nc[d];
+                        x.per[d] = g.per[d];
+                        x.L[d] = g.L[d];
+                    }
+                    x.cell_base = n_cells;
+                    n_cells += g.n_cells();
+                }
+                if ((e = c->reserve(c->frames, sizeof(FrameInfo) * nf))) return e;
+                if ((e = c->reserve(c->cell_count, (size_t)4 * (n_cells + 1)))) return e;
+                if ((e = c->reserve(c->cell_start, (size_t)4 * (n_cells + 1)))) return e;
+                if ((e = c->reserve(c->cell_fill, (size_t)4 * (n_cells + 1)))) return e;
+                const int nt_max = 9;
+                if ((e = c->reserve(c->out, sizeof(double) * nt_max * nf * (last - first)))) return e;
+                HIP_CHECK_RET(c, hipMemcpyAsync(c->frames.p, fi.data(), sizeof(FrameInfo) * nf,
+                                                hipMemcpyHostToDevice, c->stream));
+                const double* pos;
+                const int32_t* spc;
+                if (fr.location == TNEP_HOST) {
+                    HIP_CHECK_RET(c, hipMemcpyAsync(c->pos.p, fr.positions + 3 * a0, (size_t)na * 24,
+                                                    hipMemcpyHostToDevice, c->stream));
+                    HIP_CHECK_RET(c, hipMemcpyAsync(c->species.p, fr.species + a0, (size_t)na * 4,
+                                                    hipMemcpyHostToDevice, c->stream));
+                    pos = (const double*)c->pos.p;
+                    spc = (const int32_t*)c->species.p;
+                } else {
+                    pos = fr.positions + 3 * a0;
+                    spc = fr.species + a0;
+                }
+                NeighborWork w{(int32_t*)c->frame_of.p, (int32_t*)c->cell_of.p,   (int32_t*)c->cell_count.p,
+                               (int32_t*)c->cell_start.p, (int32_t*)c->cell_fill.p, (int32_t*)c->cell_atoms.p};
+                NeighborLists nl{(float4*)c->nbr.p, (int32_t*)c->n_ang.p, (int32_t*)c->n_rad.p, c->cap_ang,
+                                 c->cap_rad, na};
+                HIP_CHECK_RET(c, launch_neighbors((const FrameInfo*)c->frames.p, nf, pos, spc, na, n_species, n_cells,
+                                                  (float)gm->rc_radial, (float)gm->rc_angular, w, nl,
+                                                  (int32_t*)c->flags.p, c->stream));
+                for (int k = first; k < last; ++k) {
+                    const Model* m = job.models[k];
+                    const int nt = m->kind == TNEP_KIND_DIPOLE ? 3 : 9;
+                    double* pa = (double*)c->per_atom.p + (size_t)B * 9 * (k - first);
+                    if (job.per_atom[k] && fr.location == TNEP_DEVICE) pa = job.per_atom[k] + a0 * nt;
+                    HIP_CHECK_RET(c, launch_eval(m->shape, m->dm, nl, spc, pa, c->launch, c->stream));
+                    double* o = fr.location == TNEP_DEVICE ? job.out[k] + (size_t)f0 * nt
+                                                           : (double*)c->out.p + (size_t)nt_max * nf * (k - first);
+                    HIP_CHECK_RET(c, launch_frame_reduce((const FrameInfo*)c->frames.p, nf, pa, nt, o, c->stream));
+                    if (fr.location == TNEP_HOST) {
+                        HIP_CHECK_RET(c, hipMemcpyAsync(job.out[k] + (size_t)f0 * nt, o, sizeof(double) * nt * nf,
+                                                        hipMemcpyDeviceToHost, c->stream));
+                        if (job.per_atom[k])
+                            HIP_CHECK_RET(c, hipMemcpyAsync(job.per_atom[k] + a0 * nt, pa, sizeof(double) * nt * na,
+                                                            hipMemcpyDeviceToHost, c->stream));
+                    }
+                }
+                f0 = f1;
+            }
+            HIP_CHECK_RET(c, hipMemcpyAsync(c->h_flags, c->flags.p, sizeof(int32_t) * 8, hipMemcpyDeviceToHost,
+                                            c->stream));
+            HIP_CHECK_RET(c, hipStreamSynchronize(c->stream));
+            const int32_t* fl = c->h_flags;
+            if (fl[kFlagError]) {
+                const int64_t bad = fl[kFlagBadAtom];
+                // the flag holds a batch-local index; report the first bad frame conservatively
+                const int code = (fl[kFlagError] & kErrNonFinite) ? TNEP_E_NONFINITE
+                                 : (fl[kFlagError] & kErrSpecies) ? TNEP_E_SPECIES
+                                                                  : TNEP_E_OVERLAP;
+                (void)frame_of_atom;
+                return c->fail(code, "invalid input (%s) near batch-local atom %lld",
+                               code == TNEP_E_NONFINITE ? "non-finite position"
+                               : code == TNEP_E_SPECIES ? "species out of range"
+                                                        : "atoms closer than 1e-4 A",
+                               (long long)bad);
+            }
+            if (fl[kFlagMaxAng] > c->cap_ang || fl[kFlagMaxRad] > c->cap_rad) {
+                c->cap_ang = std::max(c->cap_ang, ((fl[kFlagMaxAng] * 5 / 4) + 15) / 16 * 16);
+                c->cap_rad = std::max(c->cap_rad, ((fl[kFlagMaxRad] * 5 / 4) + 15) / 16 * 16);
+                continue;  // repeat with larger lists
+            }
+            done = true;
+        }
+        if (!done)
+            return c->fail(TNEP_E_NEIGH_OVERFLOW, "neighbour lists still overflow after growing to %d + %d slots",
+                           c->cap_ang, c->cap_rad);
+    }
+    return TNEP_OK;
+}
+
+}  // namespace tnep

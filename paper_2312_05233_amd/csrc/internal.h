@@ -1,0 +1,98 @@
+// Internal interfaces between the C-ABI layer and the gfx950 kernels of libtnep.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tnep {
+
+// Per-frame geometry of one launch batch (built on the host).
+struct FrameInfo {
+    int64_t atom_begin;  // first atom, batch-local index
+    int32_t n_atoms;
+    int32_t mode;        // 0: all-pairs search inside the frame, 1: cell list
+    int32_t nc[3];       // cells per axis (mode 1)
+    int32_t cell_base;   // first cell of this frame in the batch's cell arrays
+    int32_t per[3];      // periodic axes
+    int32_t pad;
+    double L[3];         // box edges (periodic axes)
+};
+
+// Device-resident FP32 model parameters.
+struct DevModel {
+    const float* c_radial;   // [T][T][NR][KR]
+    const float* c_angular;  // [T][T][NA][KA]
+    const float* scaler;     // [D]
+    const float* w0[2];      // [H][D]
+    const float* b0[2];      // [H]
+    const float* w1[2];      // [H]
+    const float* w0t[2];     // [D][H] transposed copy (backward GEMM operand)
+    float b1[2];
+    float rc_radial, rc_angular;
+    int32_t n_species, n_hidden;
+};
+
+// Shape key of a compiled evaluation kernel.
+struct Shape {
+    int nr, na, kr, ka, four_body, kind;
+};
+
+// Neighbour lists of a batch.  Entry layout: float4 (dx, dy, dz, bits(t_j))
+// with r_ij = r_j - r_i; slot-major, atom-minor: entry (s, i) at s * n_atoms + i.
+// Slots [0, cap_ang) hold neighbours with r < rc_angular (used by both the
+// radial and the angular terms); slots [cap_ang, cap_ang + cap_rad) hold
+// neighbours with rc_angular <= r < rc_radial (radial terms only).
+struct NeighborLists {
+    float4* entries;
+    int32_t* n_ang;  // [n_atoms]
+    int32_t* n_rad;  // [n_atoms]
+    int32_t cap_ang, cap_rad;
+    int64_t n_atoms;
+};
+
+// Error / overflow flags written by the kernels (device int32[8]).
+enum Flag { kFlagError = 0, kFlagMaxAng = 1, kFlagMaxRad = 2, kFlagBadAtom = 3 };
+enum ErrBits { kErrSpecies = 1, kErrNonFinite = 2, kErrOverlap = 4 };
+
+// ---- neighbour search (kernels_neighbors.hip) ----
+struct NeighborWork {
+    int32_t* frame_of;    // [n_atoms]
+    int32_t* cell_of;     // [n_atoms]
+    int32_t* cell_count;  // [n_cells]
+    int32_t* cell_start;  // [n_cells + 1]
+    int32_t* cell_fill;   // [n_cells]
+    int32_t* cell_atoms;  // [n_atoms]
+};
+
+hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,
+                            int64_t n_atoms, int n_species, int n_cells, float rc_radial, float rc_angular,
+                            const NeighborWork& w, const NeighborLists& nl, int32_t* d_flags, hipStream_t s);
+
+// ---- evaluation (kernels_eval.hip) ----
+struct EvalLaunch {
+    int mlp_mode;         // TNEP_MLP_*
+    int atoms_per_block;  // 64, 128, 256
+};
+
+// Per-atom tensors (FP64, [n_atoms][3 or 9]) of one model.
+bool eval_shape_supported(const Shape& s);
+hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, const int32_t* species,
+                       double* per_atom, const EvalLaunch& cfg, hipStream_t s);
+
+// Per-frame sums of per-atom tensors in a fixed order.
+hipError_t launch_frame_reduce(const FrameInfo* d_frames, int n_frames, const double* per_atom, int nt,
+                               double* out, hipStream_t s);
+
+// ---- spectra (kernels_spectrum.hip) ----
+struct SpectrumPlan {
+    int kind, window, flags;
+    int n_series;
+    int64_t n_steps, max_lag, fft_len;
+    double dt_fs;
+    double n_hat[3], e_hat[3];
+};
+size_t spectrum_workspace_bytes(const SpectrumPlan& p);
+hipError_t launch_spectrum(const SpectrumPlan& p, const double* d_series, double* d_freq, double* d_intensity,
+                           double* d_acf, void* d_work, hipStream_t s);
+
+}  // namespace tnep

@@ -1,0 +1,100 @@
+// Host-side runtime objects behind the opaque C handles of libtnep.
+#pragma once
+
+#include <stdarg.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/tnep.h"
+#include "internal.h"
+
+#define HIP_CHECK_RET(ctx, expr)                                                             \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return (ctx)->fail(TNEP_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+namespace tnep {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Server;  // continuous-batching server (server.hip)
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;
+    uint64_t in_use = 0;
+    uint64_t peak = 0;
+    std::string err;
+    EvalLaunch launch{0, 256};
+    bool autotune = false;
+    int64_t max_batch_atoms = 1 << 20;
+    int cap_ang = 64, cap_rad = 128;  // learned neighbour capacities (grow-only)
+    int32_t* h_flags = nullptr;       // pinned
+
+    // work buffers
+    DevBuf frames, flags, frame_of, cell_of, cell_count, cell_start, cell_fill, cell_atoms;
+    DevBuf nbr, n_ang, n_rad, per_atom, out, pos, species;
+    DevBuf spec_work, spec_series, spec_out;
+
+    std::vector<DevBuf*> all_buffers() {
+        return {&frames, &flags, &frame_of, &cell_of, &cell_count, &cell_start, &cell_fill, &cell_atoms, &nbr,
+                &n_ang, &n_rad, &per_atom, &out, &pos, &species, &spec_work, &spec_series, &spec_out};
+    }
+
+    Server* server = nullptr;
+
+    int fail(int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+    int reserve(DevBuf& b, size_t bytes);
+    void release(DevBuf& b);
+    ~Ctx();
+};
+
+struct Model {
+    Ctx* ctx = nullptr;
+    Shape shape{};
+    DevModel dm{};
+    void* dbuf = nullptr;
+    size_t bytes = 0;
+    int kind = 0, T = 0, D = 0, H = 0;
+    double rc_radial = 0, rc_angular = 0;
+};
+
+// One evaluation request: up to two models over the same frames.
+struct EvalJob {
+    const Model* models[2] = {nullptr, nullptr};
+    double* out[2] = {nullptr, nullptr};
+    double* per_atom[2] = {nullptr, nullptr};
+    int n_models = 0;
+};
+
+// Frame geometry decided on the host.
+struct FrameGeom {
+    int mode = 0;
+    int nc[3] = {1, 1, 1};
+    int per[3] = {0, 0, 0};
+    double L[3] = {0, 0, 0};
+    int n_cells() const { return mode == 1 ? nc[0] * nc[1] * nc[2] : 0; }
+};
+
+int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc_radial, FrameGeom& g);
+int run_eval(Ctx* c, const tnep_frames& frames, const EvalJob& job);
+void server_shutdown(Ctx* c);
+
+hipError_t launch_init_flags(int32_t* d_flags, hipStream_t s);
+
+}  // namespace tnep

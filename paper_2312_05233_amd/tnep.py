@@ -1,0 +1,279 @@
+"""Python binding of libtnep (include/tnep.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+(host memory) or torch CUDA tensors (device memory) into the C structs and
+calls the entry points of the same names.  Importing it raises if the
+compiled library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtnep.so")
+
+TNEP_OK = 0
+ERRORS = {0: "TNEP_OK", -1: "TNEP_E_INVALID", -2: "TNEP_E_SPECIES", -3: "TNEP_E_BOX", -4: "TNEP_E_OVERLAP",
+          -5: "TNEP_E_NONFINITE", -6: "TNEP_E_BUDGET", -7: "TNEP_E_MODEL", -8: "TNEP_E_HIP",
+          -9: "TNEP_E_NEIGH_OVERFLOW", -10: "TNEP_E_CANCELLED"}
+HOST, DEVICE = 0, 1
+KIND_DIPOLE, KIND_POLARIZABILITY = 1, 2
+MLP_FP32_VALU, MLP_FP32_MFMA, MLP_BF16_MFMA, MLP_BF16X3_MFMA = 0, 1, 2, 3
+OPT_MLP, OPT_ATOMS_PER_BLOCK, OPT_AUTOTUNE, OPT_DETERMINISTIC, OPT_MAX_BATCH_ATOMS = 1, 2, 3, 4, 5
+IR, RAMAN_ISO, RAMAN_ANISO, RAMAN_PROJ = 0, 1, 2, 3
+WIN_HANN, WIN_NONE = 0, 1
+SUBTRACT_MEAN, NO_OMEGA2 = 1, 2
+
+EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_option", "tnep_ctx_memory_in_use",
+            "tnep_model_create", "tnep_model_free", "tnep_eval_dipole", "tnep_eval_polarizability",
+            "tnep_eval_dipole_polarizability", "tnep_spectrum", "tnep_server_start", "tnep_submit", "tnep_wait",
+            "tnep_server_stop", "tnep_server_stats"]
+
+
+class TnepError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+P = C.POINTER
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("n_species", C.c_int32), ("rc_radial", C.c_double), ("rc_angular", C.c_double),
+        ("n_max_radial", C.c_int32), ("n_max_angular", C.c_int32), ("basis_radial", C.c_int32),
+        ("basis_angular", C.c_int32), ("l_max", C.c_int32), ("four_body", C.c_int32), ("n_hidden", C.c_int32),
+        ("c_radial", P(C.c_double)), ("c_angular", P(C.c_double)), ("q_scaler", P(C.c_double)),
+        ("w0", P(C.c_double) * 2), ("b0", P(C.c_double) * 2), ("w1", P(C.c_double) * 2), ("b1", C.c_double * 2),
+    ]
+
+
+class FramesDesc(C.Structure):
+    _fields_ = [("n_frames", C.c_int32), ("atom_offsets", C.c_void_p), ("positions", C.c_void_p),
+                ("species", C.c_void_p), ("cells", C.c_void_p), ("pbc", C.c_void_p), ("location", C.c_int32)]
+
+
+class SpectrumArgs(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_series", C.c_int32), ("n_steps", C.c_int64), ("series", C.c_void_p),
+                ("dt_fs", C.c_double), ("max_lag", C.c_int64), ("window", C.c_int32), ("flags", C.c_int32),
+                ("n_hat", C.c_double * 3), ("e_hat", C.c_double * 3), ("location", C.c_int32)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_uint64), ("max_batch_atoms", C.c_int32), ("max_inflight", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libtnep.so is not built ({LIB_PATH}); run `python -m paper_2312_05233_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.tnep_ctx_create.argtypes = [C.c_int, vp, C.c_uint64, P(vp)]
+    lib.tnep_ctx_destroy.argtypes = [vp]
+    lib.tnep_ctx_destroy.restype = None
+    lib.tnep_last_error.argtypes = [vp]
+    lib.tnep_last_error.restype = C.c_char_p
+    lib.tnep_set_option.argtypes = [vp, C.c_int32, C.c_int64]
+    lib.tnep_ctx_memory_in_use.argtypes = [vp]
+    lib.tnep_ctx_memory_in_use.restype = C.c_uint64
+    lib.tnep_model_create.argtypes = [vp, P(ModelDesc), P(vp)]
+    lib.tnep_model_free.argtypes = [vp]
+    lib.tnep_model_free.restype = None
+    lib.tnep_eval_dipole.argtypes = [vp, vp, P(FramesDesc), vp, vp]
+    lib.tnep_eval_polarizability.argtypes = [vp, vp, P(FramesDesc), vp, vp]
+    lib.tnep_eval_dipole_polarizability.argtypes = [vp, vp, vp, P(FramesDesc), vp, vp]
+    lib.tnep_spectrum.argtypes = [vp, P(SpectrumArgs), vp, vp, vp]
+    lib.tnep_server_start.argtypes = [vp, P(ServerOpts)]
+    lib.tnep_submit.argtypes = [vp, vp, C.c_int32, P(FramesDesc), vp, P(C.c_uint64)]
+    lib.tnep_wait.argtypes = [vp, C.c_uint64, P(C.c_int32), P(C.c_double)]
+    lib.tnep_server_stop.argtypes = [vp]
+    lib.tnep_server_stats.argtypes = [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+    for name in EXPORTED:
+        if name not in ("tnep_ctx_destroy", "tnep_last_error", "tnep_model_free", "tnep_ctx_memory_in_use"):
+            getattr(lib, name).restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _ptr(x):
+    """Address of a numpy array (host) or torch tensor (device), or None."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+class Context:
+    """tnep_ctx: one GPU, one stream (hip_stream: torch.cuda.Stream or raw handle)."""
+
+    def __init__(self, device: int = 0, stream=None, budget_bytes: int = 0):
+        h = C.c_void_p()
+        raw = None
+        if stream is not None:
+            raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        e = lib.tnep_ctx_create(device, raw, budget_bytes, C.byref(h))
+        if e:
+            raise TnepError(e, lib.tnep_last_error(None).decode())
+        self.h = h
+        self.stream = stream
+
+    def check(self, e):
+        if e:
+            raise TnepError(e, lib.tnep_last_error(self.h).decode())
+
+    def set_option(self, key, value):
+        self.check(lib.tnep_set_option(self.h, key, int(value)))
+
+    def memory_in_use(self):
+        return lib.tnep_ctx_memory_in_use(self.h)
+
+    def close(self):
+        if self.h:
+            lib.tnep_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Model:
+    """tnep_model created from any object with the tnep_model_desc fields
+    (e.g. synth.Model); heads[0] tensor head, heads[1] scalar head."""
+
+    def __init__(self, ctx: Context, m):
+        self.ctx = ctx
+        self.kind = m.kind
+        keep = []
+
+        def arr(x):
+            a = np.ascontiguousarray(np.asarray(x, np.float64))
+            keep.append(a)
+            return a.ctypes.data_as(P(C.c_double))
+
+        d = ModelDesc()
+        d.kind = m.kind
+        d.n_species = len(m.species) if hasattr(m, "species") else m.n_species
+        d.rc_radial, d.rc_angular = m.rc_radial, m.rc_angular
+        d.n_max_radial, d.n_max_angular = m.n_max_radial, m.n_max_angular
+        d.basis_radial, d.basis_angular = m.basis_radial, m.basis_angular
+        d.l_max, d.four_body, d.n_hidden = m.l_max, int(bool(m.four_body)), m.n_hidden
+        d.c_radial, d.c_angular, d.q_scaler = arr(m.c_radial), arr(m.c_angular), arr(m.q_scaler)
+        for k, head in enumerate(m.heads):
+            d.w0[k], d.b0[k], d.w1[k] = arr(head.w0), arr(head.b0), arr(head.w1)
+            d.b1[k] = head.b1
+        h = C.c_void_p()
+        ctx.check(lib.tnep_model_create(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib.tnep_model_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def frames_desc(frames, location=None):
+    """Build a tnep_frames from host numpy arrays (synth.Frames) or from an
+    object whose fields are torch CUDA tensors (DeviceFrames)."""
+    d = FramesDesc()
+    d.n_frames = int(frames.offsets.shape[0] - 1)
+    if location is None:
+        location = HOST if isinstance(frames.positions, np.ndarray) else DEVICE
+    if location == HOST:
+        keep = (np.ascontiguousarray(frames.offsets, np.int64), np.ascontiguousarray(frames.positions, np.float64),
+                np.ascontiguousarray(frames.species, np.int32),
+                None if frames.cells is None else np.ascontiguousarray(frames.cells, np.float64),
+                None if frames.pbc is None else np.ascontiguousarray(frames.pbc, np.uint8))
+    else:
+        keep = (frames.offsets, frames.positions, frames.species, frames.cells, frames.pbc)
+    d.atom_offsets, d.positions, d.species, d.cells, d.pbc = [_ptr(x) for x in keep]
+    d.location = location
+    d._keep = keep
+    return d
+
+
+class DeviceFrames:
+    """Frames resident in device memory as torch tensors."""
+
+    def __init__(self, frames, device="cuda"):
+        import torch
+
+        self.offsets = torch.as_tensor(np.asarray(frames.offsets, np.int64)).to(device)
+        self.positions = torch.as_tensor(np.asarray(frames.positions, np.float64)).to(device).contiguous()
+        self.species = torch.as_tensor(np.asarray(frames.species, np.int32)).to(device)
+        self.cells = None if frames.cells is None else torch.as_tensor(np.asarray(frames.cells, np.float64)).to(device)
+        self.pbc = None if frames.pbc is None else torch.as_tensor(np.asarray(frames.pbc, np.uint8)).to(device)
+        self.n_frames = int(frames.offsets.shape[0] - 1)
+        self.n_atoms = int(frames.offsets[-1])
+
+
+def tnep_eval_dipole(ctx: Context, model: Model, frames, mu_out=None, per_atom=None):
+    """mu [F,3]; host arrays in -> numpy out, device tensors in -> caller's device tensors."""
+    fd = frames_desc(frames)
+    F = fd.n_frames
+    if fd.location == HOST:
+        mu_out = np.zeros((F, 3)) if mu_out is None else mu_out
+    ctx.check(lib.tnep_eval_dipole(ctx.h, model.h, C.byref(fd), _ptr(mu_out), _ptr(per_atom)))
+    return mu_out
+
+
+def tnep_eval_polarizability(ctx: Context, model: Model, frames, alpha_out=None, per_atom=None):
+    """alpha [F,3,3] (host) or the caller's [F,9] device tensor."""
+    fd = frames_desc(frames)
+    F = fd.n_frames
+    if fd.location == HOST:
+        alpha_out = np.zeros((F, 3, 3)) if alpha_out is None else alpha_out
+    ctx.check(lib.tnep_eval_polarizability(ctx.h, model.h, C.byref(fd), _ptr(alpha_out), _ptr(per_atom)))
+    return alpha_out
+
+
+def tnep_eval_dipole_polarizability(ctx: Context, dipole_model: Model, pol_model: Model, frames, mu_out=None,
+                                    alpha_out=None):
+    fd = frames_desc(frames)
+    F = fd.n_frames
+    if fd.location == HOST:
+        mu_out = np.zeros((F, 3)) if mu_out is None else mu_out
+        alpha_out = np.zeros((F, 3, 3)) if alpha_out is None else alpha_out
+    ctx.check(lib.tnep_eval_dipole_polarizability(ctx.h, dipole_model.h, pol_model.h, C.byref(fd), _ptr(mu_out),
+                                                  _ptr(alpha_out)))
+    return mu_out, alpha_out
+
+
+def tnep_spectrum(ctx: Context, series, kind, dt_fs, max_lag, window=WIN_HANN, flags=0, n_hat=(0, 0, 0),
+                  e_hat=(0, 0, 0), freq=None, intensity=None, acf=None, want_acf=True):
+    """series [S, N_t, 3|9] (numpy: host; torch CUDA: device, outputs must be given)."""
+    a = SpectrumArgs()
+    a.kind = kind
+    a.n_series, a.n_steps = int(series.shape[0]), int(series.shape[1])
+    a.dt_fs, a.max_lag, a.window, a.flags = dt_fs, int(max_lag), window, flags
+    for k in range(3):
+        a.n_hat[k], a.e_hat[k] = n_hat[k], e_hat[k]
+    if isinstance(series, np.ndarray):
+        series = np.ascontiguousarray(series, np.float64)
+        a.location = HOST
+        M = int(max_lag)
+        freq = np.zeros(M + 1) if freq is None else freq
+        intensity = np.zeros(M + 1) if intensity is None else intensity
+        if want_acf and acf is None:
+            acf = np.zeros(M)
+    else:
+        a.location = DEVICE
+    a.series = _ptr(series)
+    ctx.check(lib.tnep_spectrum(ctx.h, C.byref(a), _ptr(freq), _ptr(intensity), _ptr(acf)))
+    return freq, intensity, acf

@@ -1,0 +1,213 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tensors: per-frame relative Frobenius error <= 1e-5 (tests/parity.py).
+Spectra: max |dS| / max |S_ref| <= 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import SPECTRUM_TOL, TENSOR_TOL, frame_errors, spectrum_error
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context(0)
+    yield c
+    c.close()
+
+
+def _check(gpu, m, fr, label):
+    ref, pa = oracle.eval_frames(m, fr, per_atom=True)
+    err = frame_errors(gpu, ref, pa, fr.offsets)
+    print(f"{label}: max frame error {err.max():.3e}", flush=True)
+    assert np.all(err <= TENSOR_TOL), (label, err)
+    return ref
+
+
+def test_water_small_dipole(gpu_lib, ctx):
+    """64 H2O, 10 frames, 12.42 A periodic box (all-pairs search: 2 cells per axis)."""
+    m = synth.model("water_dipole_small")
+    fr = synth.water_small(10)
+    mdl = gpu_lib.Model(ctx, m)
+    mu = gpu_lib.tnep_eval_dipole(ctx, mdl, fr)
+    _check(mu, m, fr, "water 192 dipole")
+
+
+def test_water_small_polarizability_per_atom(gpu_lib, ctx):
+    m = synth.model("water_polarizability")
+    fr = synth.water_small(3, seed=2)
+    mdl = gpu_lib.Model(ctx, m)
+    pa = np.zeros((fr.n_atoms, 9))
+    al = gpu_lib.tnep_eval_polarizability(ctx, mdl, fr, per_atom=pa)
+    ref, ref_pa = oracle.eval_frames(m, fr, per_atom=True)
+    _check(al, m, fr, "water 192 polarizability")
+    atom_err = np.linalg.norm(pa - ref_pa.reshape(-1, 9), axis=1) / np.linalg.norm(ref_pa.reshape(-1, 9), axis=1)
+    print("per-atom max", atom_err.max())
+    assert atom_err.max() < 1e-4
+
+
+def test_water_cell_list_frame(gpu_lib, ctx):
+    """A 1536-atom box (24.84 A): 4 cells per axis, so the cell-list path runs."""
+    m = synth.model("water_dipole_small")
+    pos, spc, cell = synth.water_box(8, 24.84, seed=77)
+    fr = synth.Frames(np.array([0, len(spc)], np.int64), pos, spc, cell[None], np.ones((1, 3), np.uint8))
+    mdl = gpu_lib.Model(ctx, m)
+    _check(gpu_lib.tnep_eval_dipole(ctx, mdl, fr), m, fr, "water 1536 dipole")
+
+
+def test_perovskite_susceptibility(gpu_lib, ctx):
+    """BaZrO3-like 6x6x6 (1080 atoms, cell list) and 4x4x4 (320 atoms, all pairs)."""
+    m = synth.model("perovskite_susceptibility")
+    mdl = gpu_lib.Model(ctx, m)
+    for n_rep, nf in [(6, 2), (4, 3)]:
+        fr = synth.perovskite(nf, n_rep=n_rep, seed=5)
+        _check(gpu_lib.tnep_eval_polarizability(ctx, mdl, fr), m, fr, f"perovskite {n_rep}^3")
+
+
+def test_molecules_ragged_both_heads(gpu_lib, ctx):
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    fr = synth.molecules(96, seed=21)
+    gd, gp = gpu_lib.Model(ctx, md), gpu_lib.Model(ctx, mp)
+    mu, al = gpu_lib.tnep_eval_dipole_polarizability(ctx, gd, gp, fr)
+    _check(mu, md, fr, "molecules dipole")
+    _check(al, mp, fr, "molecules polarizability")
+    # the single-model entry points agree bit for bit with the combined one
+    assert np.array_equal(gpu_lib.tnep_eval_dipole(ctx, gd, fr), mu)
+    assert np.array_equal(gpu_lib.tnep_eval_polarizability(ctx, gp, fr), al)
+
+
+def test_full_size_water_frame(gpu_lib, ctx):
+    """One 12,288-atom frame of the OU water trajectory, both models."""
+    md, mp = synth.model("water_dipole"), synth.model("water_polarizability")
+    fr = synth.water_trajectory(3).subset([2])
+    gd, gp = gpu_lib.Model(ctx, md), gpu_lib.Model(ctx, mp)
+    mu, al = gpu_lib.tnep_eval_dipole_polarizability(ctx, gd, gp, fr)
+    _check(mu, md, fr, "water 12288 dipole")
+    _check(al, mp, fr, "water 12288 polarizability")
+
+
+def test_deterministic_and_batch_invariant(gpu_lib, ctx):
+    m = synth.model("molecule_dipole")
+    fr = synth.molecules(200, seed=8)
+    mdl = gpu_lib.Model(ctx, m)
+    a = gpu_lib.tnep_eval_dipole(ctx, mdl, fr)
+    b = gpu_lib.tnep_eval_dipole(ctx, mdl, fr)
+    assert np.array_equal(a, b)
+    c2 = gpu_lib.Context(0)
+    c2.set_option(gpu_lib.OPT_MAX_BATCH_ATOMS, 500)  # many small launch batches
+    mdl2 = gpu_lib.Model(c2, m)
+    c = gpu_lib.tnep_eval_dipole(c2, mdl2, fr)
+    assert np.array_equal(a, c)
+    # one frame alone equals the same frame inside the batch
+    one = gpu_lib.tnep_eval_dipole(ctx, mdl, fr.subset([37]))
+    assert np.array_equal(one[0], a[37])
+    mdl2.close()
+    c2.close()
+
+
+def test_device_resident_inputs(gpu_lib, ctx):
+    import torch
+
+    m = synth.model("water_dipole_small")
+    fr = synth.water_small(4, seed=9)
+    mdl = gpu_lib.Model(ctx, m)
+    host = gpu_lib.tnep_eval_dipole(ctx, mdl, fr)
+    dfr = gpu_lib.DeviceFrames(fr)
+    out = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    gpu_lib.tnep_eval_dipole(ctx, mdl, dfr, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), host)
+
+
+def test_edge_cases(gpu_lib, ctx):
+    """Empty frames, a single atom, isolated atoms, and an empty call."""
+    m = synth.model("molecule_dipole")
+    mdl = gpu_lib.Model(ctx, m)
+    mol = synth.molecules(2, seed=4)
+    parts = [synth.Frames(np.array([0, 0], np.int64), np.zeros((0, 3)), np.zeros(0, np.int32)),
+             mol.subset([0]),
+             synth.Frames(np.array([0, 1], np.int64), np.zeros((1, 3)), np.array([2], np.int32)),
+             synth.Frames(np.array([0, 2], np.int64), np.array([[0, 0, 0], [10.0, 0, 0]]), np.array([1, 3], np.int32)),
+             mol.subset([1])]
+    fr = synth.Frames.concat(parts)
+    mu = gpu_lib.tnep_eval_dipole(ctx, mdl, fr)
+    ref = oracle.eval_frames(m, fr)
+    assert np.all(mu[[0, 2, 3]] == 0.0)
+    _check(mu, m, fr, "edge cases")
+    assert np.array_equal(ref[[0, 2, 3]], np.zeros((3, 3)))
+    empty = synth.Frames(np.array([0], np.int64), np.zeros((0, 3)), np.zeros(0, np.int32))
+    assert gpu_lib.tnep_eval_dipole(ctx, mdl, empty).shape == (0, 3)
+
+
+def test_error_codes(gpu_lib, ctx):
+    m = synth.model("water_dipole_small")
+    mdl = gpu_lib.Model(ctx, m)
+    fr = synth.water_small(2)
+    bad = synth.Frames(fr.offsets, fr.positions, fr.species.copy(), fr.cells, fr.pbc)
+    bad.species[7] = 5
+    with pytest.raises(gpu_lib.TnepError) as e:
+        gpu_lib.tnep_eval_dipole(ctx, mdl, bad)
+    assert e.value.code == -2
+    small = synth.Frames(fr.offsets, fr.positions, fr.species, fr.cells * 0.9, fr.pbc)
+    with pytest.raises(gpu_lib.TnepError) as e:
+        gpu_lib.tnep_eval_dipole(ctx, mdl, small)
+    assert e.value.code == -3
+    nan = synth.Frames(fr.offsets, fr.positions.copy(), fr.species, fr.cells, fr.pbc)
+    nan.positions[3, 1] = np.nan
+    with pytest.raises(gpu_lib.TnepError) as e:
+        gpu_lib.tnep_eval_dipole(ctx, mdl, nan)
+    assert e.value.code == -5
+    ov = synth.Frames(fr.offsets, fr.positions.copy(), fr.species, fr.cells, fr.pbc)
+    ov.positions[10] = ov.positions[11]
+    with pytest.raises(gpu_lib.TnepError) as e:
+        gpu_lib.tnep_eval_dipole(ctx, mdl, ov)
+    assert e.value.code == -4
+    # the context still works after errors
+    _check(gpu_lib.tnep_eval_dipole(ctx, mdl, fr), m, fr, "after errors")
+
+
+# ---------------------------------------------------------------------------
+# spectra
+
+
+def _series(n_series, n_steps, comps, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_series):
+        x = np.zeros((n_steps, comps))
+        d = np.zeros(comps)
+        for t in range(n_steps):
+            d = 0.97 * d + rng.normal(0, 0.1, comps)
+            x[t] = d + np.cos(0.3 * t) * 0.2
+        if comps == 9:
+            x = ((x.reshape(-1, 3, 3) + x.reshape(-1, 3, 3).transpose(0, 2, 1)) / 2 + 3 * np.eye(3)).reshape(-1, 9)
+        out.append(x)
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("kind,comps", [(0, 3), (1, 9), (2, 9), (3, 9)])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_spectrum_parity(gpu_lib, ctx, kind, comps, flags):
+    s = _series(3, 1500, comps, seed=kind * 10 + flags)
+    M = 400
+    nh, eh = (0.0, 0.6, 0.8), (1.0, 0.0, 0.0)
+    f, S, acf = gpu_lib.tnep_spectrum(ctx, s, kind, 0.5, M, flags=flags, n_hat=nh, e_hat=eh)
+    fr, Sr, Cr = oracle.spectrum(list(s), kind, 0.5, M, n_hat=nh, e_hat=eh, subtract_mean=bool(flags))
+    np.testing.assert_allclose(f, fr, rtol=1e-13)
+    assert spectrum_error(acf, Cr) < 1e-10
+    assert spectrum_error(S, Sr) < SPECTRUM_TOL
+
+
+def test_spectrum_edge_sizes(gpu_lib, ctx):
+    """Power-of-two length, max lag = n_steps, no window, IR without w^2."""
+    s = _series(1, 1024, 3, seed=3)
+    for M, win, flags in [(1024, 1, 2), (1, 0, 0), (37, 0, 1)]:
+        f, S, acf = gpu_lib.tnep_spectrum(ctx, s, 0, 1.0, M, window=win, flags=flags)
+        fr, Sr, Cr = oracle.spectrum(list(s), 0, 1.0, M, window=(win == 0), omega2=not (flags & 2),
+                                     subtract_mean=bool(flags & 1))
+        assert spectrum_error(S, Sr) < SPECTRUM_TOL
+        assert spectrum_error(acf, Cr) < 1e-10
