@@ -69,6 +69,11 @@ class ServerOpts(C.Structure):
 
 
 def _load():
+    # torch and libtnep must share one HIP runtime in the process: torch's
+    # libraries ask for "libamdhip64.so", libtnep for "libamdhip64.so.7"; once
+    # torch's copy (soname libamdhip64.so.7) is loaded, libtnep binds to it.
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libtnep.so is not built ({LIB_PATH}); run `python -m paper_2312_05233_amd.build`")
     lib = C.CDLL(LIB_PATH)
