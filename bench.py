@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark: TNEP atom-frames/s for dipole + polarizability on one MI355X.
+
+Workload (one step = the whole hot path over one synthetic job):
+  liquid-water box of 4096 H2O (12,288 atoms, 49.7 A, periodic), 2000-frame
+  Ornstein-Uhlenbeck displacement trajectory (sigma 0.02 A, tau 50 steps),
+  dipole model + polarizability model (scalar + tensor heads), NEP
+  descriptor r_c 6/4 A, n_max 4/4, basis 8/8, l_max 4 + four-body, 30 tanh
+  neurons; then the IR spectrum of mu(t) and the isotropic / anisotropic
+  Raman spectra of alpha(t) (dt = 1 fs, max lag 500).
+Inputs (positions, species, frame offsets, cells) are resident in HBM when
+the timed region starts; outputs stay in HBM.
+
+Printed: one JSON line with the metric, a roofline record for the dominant
+kernel (the polarizability evaluation kernel, FP32 VALU bound) measured with
+HIP events inside the library, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X, published FP32 vector peak
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "eval_polarizability_water12288_traffic.md")
+
+
+def flops_per_atom_frame(model, n_rad_mean, n_ang_mean):
+    """Algorithmic FP32 work per atom-frame (FMA = 2 flops), no recomputation:
+    f_R per radial pair, f_A per angular pair, f_atom per atom."""
+    nR, nA = model.n_max_radial + 1, model.n_max_angular + 1
+    KR, KA = model.basis_radial + 1, model.basis_angular + 1
+    L = (model.l_max + 1) ** 2 - 1
+    D, H = model.dim, model.n_hidden
+    f_R = 4 * nR * KR + 12 * KR + 3 * nR + 40
+    f_A = 4 * nA * KA + 12 * KA + 6 * nA * L + 8 * L + 180
+    heads = len(model.heads)
+    f_atom = 4 * D * H + (2 * D * H if heads == 2 else 0) + 10 * H * heads + 4 * nA * L + \
+        (120 * nA if model.four_body else 0) + 4 * D
+    return n_rad_mean * f_R + n_ang_mean * f_A + f_atom
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels_eval.hip", "tnep_math.h"):
+        with open(os.path.join(ROOT, "paper_2312_05233_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(atoms_per_launch):
+    """HBM bytes per launch of the evaluation kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None
+    txt = open(TRAFFIC_RECORD).read()
+    m_hash = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", txt)
+    m_bpa = re.search(r"hbm_bytes_per_atom:\s*([0-9.eE+-]+)", txt)
+    if not m_hash or not m_bpa or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bpa.group(1)) * atoms_per_launch
+
+
+def cpu_baseline(frames, md, mp, n_sample, gpu_mu, gpu_alpha):
+    import oracle
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import frame_errors
+
+    idx = list(range(n_sample))
+    sub = frames.subset(idx)
+    t0 = time.perf_counter()
+    mu_ref, mu_pa = oracle.eval_frames(md, sub, per_atom=True)
+    al_ref, al_pa = oracle.eval_frames(mp, sub, per_atom=True)
+    dt = time.perf_counter() - t0
+    atoms = sub.n_atoms
+    err_mu = frame_errors(gpu_mu[idx], mu_ref, mu_pa, sub.offsets).max()
+    err_al = frame_errors(gpu_alpha[idx], al_ref.reshape(-1, 9), al_pa, sub.offsets).max()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": atoms / dt, "unit": "atom-frames/s", "cores": cores, "kind": "oracle",
+        "sample": f"frames 0..{n_sample - 1} of the trajectory ({atoms} atom-frames), dipole + polarizability "
+                  f"models, FP64, {dt:.1f} s wall",
+    }, float(err_mu), float(err_al)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=2000)
+    ap.add_argument("--max-lag", type=int, default=500)
+    ap.add_argument("--cpu-frames", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mlp", type=int, default=None, help="TNEP_MLP_* mode of the hidden layer")
+    ap.add_argument("--atoms-per-block", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (frames shard trivially "
+              "across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2312_05233_amd import tnep
+
+    dev = torch.device("cuda:0")
+    frames = synth.water_trajectory(args.frames)
+    md, mp = synth.model("water_dipole"), synth.model("water_polarizability")
+    F, A = frames.n_frames, frames.n_atoms
+    stream = torch.cuda.Stream(device=dev)
+    ctx = tnep.Context(0, stream=stream)
+    if args.mlp is not None:
+        ctx.set_option(tnep.OPT_MLP, args.mlp)
+    if args.atoms_per_block is not None:
+        ctx.set_option(tnep.OPT_ATOMS_PER_BLOCK, args.atoms_per_block)
+    gd, gp = tnep.Model(ctx, md), tnep.Model(ctx, mp)
+    dfr = tnep.DeviceFrames(frames)
+    mu = torch.zeros((F, 3), dtype=torch.float64, device=dev)
+    alpha = torch.zeros((F, 9), dtype=torch.float64, device=dev)
+    M = args.max_lag
+    spec = {k: [torch.zeros(M + 1, dtype=torch.float64, device=dev) for _ in range(2)] + [
+        torch.zeros(M, dtype=torch.float64, device=dev)] for k in ("ir", "iso", "aniso")}
+    torch.cuda.synchronize()
+
+    def step():
+        tnep.tnep_eval_dipole_polarizability(ctx, gd, gp, dfr, mu, alpha)
+        for name, kind, ser in (("ir", tnep.IR, mu.view(1, F, 3)), ("iso", tnep.RAMAN_ISO, alpha.view(1, F, 9)),
+                                ("aniso", tnep.RAMAN_ANISO, alpha.view(1, F, 9))):
+            f, s, c = spec[name]
+            tnep.tnep_spectrum(ctx, ser, kind, 1.0, M, freq=f, intensity=s, acf=c)
+
+    for _ in range(args.warmup):
+        step()
+    ctx.set_option(tnep.OPT_TIMING, 1)
+    ctx.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+
+    # live kernel timing (HIP events on the context's stream)
+    kt = {name: ctx.kernel_time(k) for name, k in (
+        ("neighbors", tnep.KERNEL_NEIGHBORS), ("eval_dipole", tnep.KERNEL_EVAL_DIPOLE),
+        ("eval_polarizability", tnep.KERNEL_EVAL_POLARIZABILITY), ("frame_reduce", tnep.KERNEL_FRAME_REDUCE),
+        ("spectrum", tnep.KERNEL_SPECTRUM))}
+    atoms, rad_pairs, ang_pairs = ctx.pair_counts()
+    n_rad = rad_pairs / atoms
+    n_ang = ang_pairs / atoms
+    pol_ms, pol_launches = kt["eval_polarizability"]
+    atoms_per_launch = atoms / pol_launches
+    flop_af = flops_per_atom_frame(mp, n_rad, n_ang)
+    achieved = flop_af * atoms_per_launch / (pol_ms / pol_launches * 1e-3) / 1e12
+    traffic = read_traffic(atoms_per_launch)
+
+    mu_h = mu.cpu().numpy()
+    al_h = alpha.cpu().numpy()
+    result = {
+        "metric": "TNEP atom-frames/s (dipole+polarizability) at FP32 tol",
+        "value": A / (ms_step * 1e-3),
+        "unit": "atom-frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "water 4096 H2O (12288 atoms, 49.7 A PBC) x 2000-frame OU trajectory; dipole + "
+                        "polarizability models; IR + Raman iso/aniso spectra (M=500)",
+            "frames": F, "atoms_per_frame": A // F, "atom_frames_per_step": A,
+            "descriptor": "rc 6/4 A, n_max 4/4, basis 8/8, l_max 4 + 4-body, H=30",
+            "precision": "FP32 descriptor/network/partial forces, FP64 frame sums and spectra",
+        },
+        "roofline": {
+            "kernel": "k_eval<5,5,9,9,4-body,polarizability>",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+            "traffic": traffic,
+            "flop_per_atom_frame": flop_af,
+            "atoms_per_launch": atoms_per_launch,
+            "avg_launch_ms": pol_ms / pol_launches,
+            "mean_radial_neighbors": n_rad,
+            "mean_angular_neighbors": n_ang,
+        },
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+    }
+    if not args.no_cpu_baseline:
+        cb, e_mu, e_al = cpu_baseline(frames, md, mp, min(args.cpu_frames, F), mu_h, al_h)
+        result["cpu_baseline"] = cb
+        result["max_frame_error_vs_oracle"] = {"dipole": e_mu, "polarizability": e_al}
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

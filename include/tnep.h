@@ -76,6 +76,14 @@ extern "C" {
 #define TNEP_OPT_AUTOTUNE 3       /* 1 = pick launch parameters by measurement  */
 #define TNEP_OPT_DETERMINISTIC 4  /* 1 (default) = fixed reduction order        */
 #define TNEP_OPT_MAX_BATCH_ATOMS 5 /* atoms per launch batch (default 2^20)       */
+#define TNEP_OPT_TIMING 6         /* 1 = time every launch with HIP events and count pairs */
+
+/* kernel classes for tnep_ctx_kernel_time */
+#define TNEP_KERNEL_NEIGHBORS 0
+#define TNEP_KERNEL_EVAL_DIPOLE 1
+#define TNEP_KERNEL_EVAL_POLARIZABILITY 2
+#define TNEP_KERNEL_FRAME_REDUCE 3
+#define TNEP_KERNEL_SPECTRUM 4
 
 /* ---- opaque handles ---------------------------------------------------- */
 typedef struct tnep_ctx tnep_ctx;
@@ -135,6 +143,14 @@ const char* tnep_last_error(const tnep_ctx* ctx);
 int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value);
 /* Device bytes currently held by the context's work buffers. */
 uint64_t tnep_ctx_memory_in_use(const tnep_ctx* ctx);
+/* With TNEP_OPT_TIMING on: summed device time (ms, HIP events on the context's
+ * stream, one pair per launch) and number of launches of one kernel class
+ * (TNEP_KERNEL_*) since the last reset; atoms and neighbour pairs processed by
+ * the evaluation kernels (radial pairs r < rc_radial, angular pairs r < rc_angular).
+ * Any output pointer may be NULL. */
+int tnep_ctx_kernel_time(const tnep_ctx* ctx, int32_t kernel_class, double* total_ms, uint64_t* launches);
+int tnep_ctx_pair_counts(const tnep_ctx* ctx, uint64_t* atoms, uint64_t* radial_pairs, uint64_t* angular_pairs);
+int tnep_ctx_reset_timing(tnep_ctx* ctx);
 
 /* ---- model ------------------------------------------------------------- */
 /* Copy a model to the device (resident until tnep_model_free). TNEP_E_MODEL if

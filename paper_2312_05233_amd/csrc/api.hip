@@ -43,8 +43,8 @@ int tnep::Ctx::reserve(DevBuf& b, size_t bytes) {
         return fail(TNEP_E_BUDGET, "device budget exceeded: need %zu more bytes (budget %llu, in use %llu)",
                     want - b.bytes, (unsigned long long)budget, (unsigned long long)in_use);
     if (b.p) {
-        hipStreamSynchronize(stream);
-        hipFree(b.p);
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(b.p);
         in_use -= b.bytes;
         b.p = nullptr;
         b.bytes = 0;
@@ -59,18 +59,58 @@ int tnep::Ctx::reserve(DevBuf& b, size_t bytes) {
 
 void tnep::Ctx::release(DevBuf& b) {
     if (b.p) {
-        hipFree(b.p);
+        (void)hipFree(b.p);
         in_use -= b.bytes;
     }
     b.p = nullptr;
     b.bytes = 0;
 }
 
+int tnep::Ctx::timer_begin(int which) {
+    if (!timing) return -1;
+    hipEvent_t ev[2];
+    for (int k = 0; k < 2; ++k) {
+        if (event_pool.empty()) {
+            if (hipEventCreate(&ev[k]) != hipSuccess) return -1;
+        } else {
+            ev[k] = event_pool.back();
+            event_pool.pop_back();
+        }
+    }
+    (void)hipEventRecord(ev[0], stream);
+    pending.push_back({ev[0], ev[1], which});
+    return (int)pending.size() - 1;
+}
+
+void tnep::Ctx::timer_end(int idx) {
+    if (idx < 0) return;
+    (void)hipEventRecord(pending[idx].b, stream);
+}
+
+void tnep::Ctx::timer_flush() {
+    for (Range& r : pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            kernel_ms[r.which] += ms;
+            kernel_launches[r.which] += 1;
+        }
+        event_pool.push_back(r.a);
+        event_pool.push_back(r.b);
+    }
+    pending.clear();
+    if (timing && counters.p) {
+        unsigned long long h[3];
+        if (hipMemcpy(h, counters.p, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess)
+            for (int k = 0; k < 3; ++k) pair_counts[k] = h[k];
+    }
+}
+
 tnep::Ctx::~Ctx() {
-    if (stream) hipStreamSynchronize(stream);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (hipEvent_t ev : event_pool) (void)hipEventDestroy(ev);
     for (DevBuf* b : all_buffers()) release(*b);
-    if (h_flags) hipHostFree(h_flags);
-    if (own_stream && stream) hipStreamDestroy(stream);
+    if (h_flags) (void)hipHostFree(h_flags);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -118,7 +158,7 @@ extern "C" void tnep_ctx_destroy(tnep_ctx* ctx) {
     if (!ctx) return;
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
     server_shutdown(c);
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     delete c;
 }
 
@@ -129,6 +169,40 @@ extern "C" const char* tnep_last_error(const tnep_ctx* ctx) {
 
 extern "C" uint64_t tnep_ctx_memory_in_use(const tnep_ctx* ctx) {
     return ctx ? reinterpret_cast<const Ctx*>(ctx)->in_use : 0;
+}
+
+extern "C" int tnep_ctx_kernel_time(const tnep_ctx* ctx, int32_t which, double* total_ms, uint64_t* launches) {
+    if (!ctx || which < 0 || which > TNEP_KERNEL_SPECTRUM) return TNEP_E_INVALID;
+    const Ctx* c = reinterpret_cast<const Ctx*>(ctx);
+    if (total_ms) *total_ms = c->kernel_ms[which];
+    if (launches) *launches = c->kernel_launches[which];
+    return TNEP_OK;
+}
+
+extern "C" int tnep_ctx_pair_counts(const tnep_ctx* ctx, uint64_t* atoms, uint64_t* radial_pairs,
+                                    uint64_t* angular_pairs) {
+    if (!ctx) return TNEP_E_INVALID;
+    const Ctx* c = reinterpret_cast<const Ctx*>(ctx);
+    if (atoms) *atoms = c->pair_counts[0];
+    if (radial_pairs) *radial_pairs = c->pair_counts[1];
+    if (angular_pairs) *angular_pairs = c->pair_counts[2];
+    return TNEP_OK;
+}
+
+extern "C" int tnep_ctx_reset_timing(tnep_ctx* ctx) {
+    if (!ctx) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    (void)hipStreamSynchronize(c->stream);
+    c->timer_flush();
+    for (int k = 0; k < 8; ++k) {
+        c->kernel_ms[k] = 0;
+        c->kernel_launches[k] = 0;
+    }
+    for (int k = 0; k < 3; ++k) c->pair_counts[k] = 0;
+    if (c->counters.p) {
+        if (hipMemset(c->counters.p, 0, 64) != hipSuccess) return c->fail(TNEP_E_HIP, "counter reset failed");
+    }
+    return TNEP_OK;
 }
 
 extern "C" int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value) {
@@ -150,6 +224,9 @@ extern "C" int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value) {
             return TNEP_OK;
         case TNEP_OPT_DETERMINISTIC:
             if (value == 0) return c->fail(TNEP_E_INVALID, "only the deterministic reduction is implemented");
+            return TNEP_OK;
+        case TNEP_OPT_TIMING:
+            c->timing = value != 0;
             return TNEP_OK;
         case TNEP_OPT_MAX_BATCH_ATOMS:
             if (value < 1) return c->fail(TNEP_E_INVALID, "max batch atoms must be positive");
@@ -223,14 +300,14 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
     m->H = H;
     m->rc_radial = d->rc_radial;
     m->rc_angular = d->rc_angular;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     if (hipMalloc(&m->dbuf, h.size() * sizeof(float)) != hipSuccess) {
         delete m;
         return c->fail(TNEP_E_HIP, "hipMalloc for model failed");
     }
     m->bytes = h.size() * sizeof(float);
     if (hipMemcpy(m->dbuf, h.data(), m->bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(m->dbuf);
+        (void)hipFree(m->dbuf);
         delete m;
         return c->fail(TNEP_E_HIP, "model upload failed");
     }
@@ -259,9 +336,9 @@ extern "C" void tnep_model_free(tnep_model* model) {
     if (!model) return;
     Model* m = reinterpret_cast<Model*>(model);
     if (m->dbuf) {
-        hipSetDevice(m->ctx->device);
-        hipDeviceSynchronize();
-        hipFree(m->dbuf);
+        (void)hipSetDevice(m->ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(m->dbuf);
     }
     delete m;
 }
@@ -350,7 +427,7 @@ extern "C" int tnep_spectrum(tnep_ctx* ctx, const tnep_spectrum_args* a, double*
     if (a->window != TNEP_WIN_HANN && a->window != TNEP_WIN_NONE) return c->fail(TNEP_E_INVALID, "bad window");
     if (a->location != TNEP_HOST && a->location != TNEP_DEVICE) return c->fail(TNEP_E_INVALID, "bad location");
     if (a->n_steps > ((int64_t)1 << 26)) return c->fail(TNEP_E_INVALID, "n_steps above 2^26");
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     SpectrumPlan p{};
     p.kind = a->kind;
     p.window = a->window;
@@ -382,12 +459,15 @@ extern "C" int tnep_spectrum(tnep_ctx* ctx, const tnep_spectrum_args* a, double*
         d_int = d_freq + (M + 1);
         d_acf = acf ? d_int + (M + 1) : nullptr;
     }
+    const int tr = c->timer_begin(TNEP_KERNEL_SPECTRUM);
     HIP_TRY(c, launch_spectrum(p, d_series, d_freq, d_int, d_acf, c->spec_work.p, c->stream));
+    c->timer_end(tr);
     if (a->location == TNEP_HOST) {
         HIP_TRY(c, hipMemcpyAsync(freq_cm1, d_freq, sizeof(double) * (M + 1), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipMemcpyAsync(intensity, d_int, sizeof(double) * (M + 1), hipMemcpyDeviceToHost, c->stream));
         if (acf) HIP_TRY(c, hipMemcpyAsync(acf, d_acf, sizeof(double) * M, hipMemcpyDeviceToHost, c->stream));
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->timer_flush();
     return TNEP_OK;
 }

@@ -103,7 +103,7 @@ inline int frame_of_atom(const std::vector<int64_t>& offs, int64_t a) {
 int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
     const int F = fr.n_frames;
     if (F == 0) return TNEP_OK;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     HostMeta meta;
     int e = fetch_meta(c, fr, meta);
     if (e) return e;
@@ -146,6 +146,10 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if ((e = c->reserve(c->cell_atoms, (size_t)B * 4))) return e;
             if ((e = c->reserve(c->per_atom, (size_t)B * 9 * sizeof(double) * (last - first)))) return e;
             if ((e = c->reserve(c->flags, 64))) return e;
+            if (c->timing && !c->counters.p) {
+                if ((e = c->reserve(c->counters, 64))) return e;
+                HIP_CHECK_RET(c, hipMemsetAsync(c->counters.p, 0, 64, c->stream));
+            }
             if (fr.location == TNEP_HOST) {
                 if ((e = c->reserve(c->pos, (size_t)B * 24))) return e;
                 if ((e = c->reserve(c->species, (size_t)B * 4))) return e;
@@ -203,18 +207,27 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                (int32_t*)c->cell_start.p, (int32_t*)c->cell_fill.p, (int32_t*)c->cell_atoms.p};
                 NeighborLists nl{(float4*)c->nbr.p, (int32_t*)c->n_ang.p, (int32_t*)c->n_rad.p, c->cap_ang,
                                  c->cap_rad, na};
+                int tr = c->timer_begin(TNEP_KERNEL_NEIGHBORS);
                 HIP_CHECK_RET(c, launch_neighbors((const FrameInfo*)c->frames.p, nf, pos, spc, na, n_species, n_cells,
                                                   (float)gm->rc_radial, (float)gm->rc_angular, w, nl,
                                                   (int32_t*)c->flags.p, c->stream));
+                c->timer_end(tr);
+                if (c->timing)
+                    HIP_CHECK_RET(c, launch_count_pairs(nl, (unsigned long long*)c->counters.p, c->stream));
                 for (int k = first; k < last; ++k) {
                     const Model* m = job.models[k];
                     const int nt = m->kind == TNEP_KIND_DIPOLE ? 3 : 9;
                     double* pa = (double*)c->per_atom.p + (size_t)B * 9 * (k - first);
                     if (job.per_atom[k] && fr.location == TNEP_DEVICE) pa = job.per_atom[k] + a0 * nt;
+                    tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE ? TNEP_KERNEL_EVAL_DIPOLE
+                                                                    : TNEP_KERNEL_EVAL_POLARIZABILITY);
                     HIP_CHECK_RET(c, launch_eval(m->shape, m->dm, nl, spc, pa, c->launch, c->stream));
+                    c->timer_end(tr);
                     double* o = fr.location == TNEP_DEVICE ? job.out[k] + (size_t)f0 * nt
                                                            : (double*)c->out.p + (size_t)nt_max * nf * (k - first);
+                    tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);
                     HIP_CHECK_RET(c, launch_frame_reduce((const FrameInfo*)c->frames.p, nf, pa, nt, o, c->stream));
+                    c->timer_end(tr);
                     if (fr.location == TNEP_HOST) {
                         HIP_CHECK_RET(c, hipMemcpyAsync(job.out[k] + (size_t)f0 * nt, o, sizeof(double) * nt * nf,
                                                         hipMemcpyDeviceToHost, c->stream));
@@ -228,6 +241,7 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             HIP_CHECK_RET(c, hipMemcpyAsync(c->h_flags, c->flags.p, sizeof(int32_t) * 8, hipMemcpyDeviceToHost,
                                             c->stream));
             HIP_CHECK_RET(c, hipStreamSynchronize(c->stream));
+            c->timer_flush();
             const int32_t* fl = c->h_flags;
             if (fl[kFlagError]) {
                 const int64_t bad = fl[kFlagBadAtom];

@@ -79,6 +79,9 @@ bool eval_shape_supported(const Shape& s);
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, const int32_t* species,
                        double* per_atom, const EvalLaunch& cfg, hipStream_t s);
 
+// Add the batch's atom count and neighbour-pair counts to counters[0..2].
+hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* counters, hipStream_t s);
+
 // Per-frame sums of per-atom tensors in a fixed order.
 hipError_t launch_frame_reduce(const FrameInfo* d_frames, int n_frames, const double* per_atom, int nt,
                                double* out, hipStream_t s);

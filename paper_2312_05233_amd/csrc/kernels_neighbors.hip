@@ -212,7 +212,35 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+__global__ void k_count_pairs(const int32_t* __restrict__ n_ang, const int32_t* __restrict__ n_rad, int64_t n,
+                              unsigned long long* __restrict__ counters) {
+    __shared__ unsigned long long s_ang[kBlock], s_rad[kBlock];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    s_ang[threadIdx.x] = i < n ? (unsigned long long)n_ang[i] : 0ull;
+    s_rad[threadIdx.x] = i < n ? (unsigned long long)n_rad[i] : 0ull;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            s_ang[threadIdx.x] += s_ang[threadIdx.x + off];
+            s_rad[threadIdx.x] += s_rad[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long na = (unsigned long long)min<int64_t>(kBlock, n - (int64_t)blockIdx.x * kBlock);
+        atomicAdd(&counters[0], na);
+        atomicAdd(&counters[1], s_ang[0] + s_rad[0]);
+        atomicAdd(&counters[2], s_ang[0]);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* counters, hipStream_t s) {
+    if (nl.n_atoms == 0) return hipSuccess;
+    k_count_pairs<<<blocks_for(nl.n_atoms, kBlock), kBlock, 0, s>>>(nl.n_ang, nl.n_rad, nl.n_atoms, counters);
+    return hipGetLastError();
+}
 
 hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,
                             int64_t n_atoms, int n_species, int n_cells, float rc_radial, float rc_angular,

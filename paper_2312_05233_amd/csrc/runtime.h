@@ -53,10 +53,26 @@ struct Ctx {
 
     std::vector<DevBuf*> all_buffers() {
         return {&frames, &flags, &frame_of, &cell_of, &cell_count, &cell_start, &cell_fill, &cell_atoms, &nbr,
-                &n_ang, &n_rad, &per_atom, &out, &pos, &species, &spec_work, &spec_series, &spec_out};
+                &n_ang, &n_rad, &per_atom, &out, &pos, &species, &spec_work, &spec_series, &spec_out, &counters};
     }
 
     Server* server = nullptr;
+
+    // launch timing (TNEP_OPT_TIMING)
+    bool timing = false;
+    struct Range {
+        hipEvent_t a, b;
+        int which;
+    };
+    std::vector<hipEvent_t> event_pool;
+    std::vector<Range> pending;
+    double kernel_ms[8] = {0};
+    uint64_t kernel_launches[8] = {0};
+    uint64_t pair_counts[3] = {0, 0, 0};  // atoms, radial pairs, angular pairs
+    DevBuf counters;                       // device uint64[3]
+    int timer_begin(int which);            // returns a range index or -1
+    void timer_end(int idx);
+    void timer_flush();                    // after a stream sync
 
     int fail(int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
     int reserve(DevBuf& b, size_t bytes);

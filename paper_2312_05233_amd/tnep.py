@@ -23,7 +23,8 @@ ERRORS = {0: "TNEP_OK", -1: "TNEP_E_INVALID", -2: "TNEP_E_SPECIES", -3: "TNEP_E_
 HOST, DEVICE = 0, 1
 KIND_DIPOLE, KIND_POLARIZABILITY = 1, 2
 MLP_FP32_VALU, MLP_FP32_MFMA, MLP_BF16_MFMA, MLP_BF16X3_MFMA = 0, 1, 2, 3
-OPT_MLP, OPT_ATOMS_PER_BLOCK, OPT_AUTOTUNE, OPT_DETERMINISTIC, OPT_MAX_BATCH_ATOMS = 1, 2, 3, 4, 5
+OPT_MLP, OPT_ATOMS_PER_BLOCK, OPT_AUTOTUNE, OPT_DETERMINISTIC, OPT_MAX_BATCH_ATOMS, OPT_TIMING = 1, 2, 3, 4, 5, 6
+KERNEL_NEIGHBORS, KERNEL_EVAL_DIPOLE, KERNEL_EVAL_POLARIZABILITY, KERNEL_FRAME_REDUCE, KERNEL_SPECTRUM = 0, 1, 2, 3, 4
 IR, RAMAN_ISO, RAMAN_ANISO, RAMAN_PROJ = 0, 1, 2, 3
 WIN_HANN, WIN_NONE = 0, 1
 SUBTRACT_MEAN, NO_OMEGA2 = 1, 2
@@ -31,7 +32,8 @@ SUBTRACT_MEAN, NO_OMEGA2 = 1, 2
 EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_option", "tnep_ctx_memory_in_use",
             "tnep_model_create", "tnep_model_free", "tnep_eval_dipole", "tnep_eval_polarizability",
             "tnep_eval_dipole_polarizability", "tnep_spectrum", "tnep_server_start", "tnep_submit", "tnep_wait",
-            "tnep_server_stop", "tnep_server_stats"]
+            "tnep_server_stop", "tnep_server_stats", "tnep_ctx_kernel_time", "tnep_ctx_pair_counts",
+            "tnep_ctx_reset_timing"]
 
 
 class TnepError(RuntimeError):
@@ -98,6 +100,9 @@ def _load():
     lib.tnep_wait.argtypes = [vp, C.c_uint64, P(C.c_int32), P(C.c_double)]
     lib.tnep_server_stop.argtypes = [vp]
     lib.tnep_server_stats.argtypes = [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+    lib.tnep_ctx_kernel_time.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_uint64)]
+    lib.tnep_ctx_pair_counts.argtypes = [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+    lib.tnep_ctx_reset_timing.argtypes = [vp]
     for name in EXPORTED:
         if name not in ("tnep_ctx_destroy", "tnep_last_error", "tnep_model_free", "tnep_ctx_memory_in_use"):
             getattr(lib, name).restype = C.c_int
@@ -139,6 +144,21 @@ class Context:
 
     def memory_in_use(self):
         return lib.tnep_ctx_memory_in_use(self.h)
+
+    def kernel_time(self, kernel_class):
+        """(total ms, launches) of one kernel class since the last reset."""
+        ms, n = C.c_double(), C.c_uint64()
+        self.check(lib.tnep_ctx_kernel_time(self.h, kernel_class, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def pair_counts(self):
+        """(atoms, radial pairs, angular pairs) processed since the last reset."""
+        a, r, g = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        self.check(lib.tnep_ctx_pair_counts(self.h, C.byref(a), C.byref(r), C.byref(g)))
+        return a.value, r.value, g.value
+
+    def reset_timing(self):
+        self.check(lib.tnep_ctx_reset_timing(self.h))
 
     def close(self):
         if self.h:
