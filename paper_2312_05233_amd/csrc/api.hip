@@ -145,7 +145,7 @@ extern "C" int tnep_ctx_create(int device, void* hip_stream, uint64_t mem_budget
         }
         c->own_stream = true;
     }
-    if (hipHostMalloc((void**)&c->h_flags, sizeof(int32_t) * 8, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->h_flags, sizeof(int32_t) * 32, hipHostMallocDefault) != hipSuccess) {
         delete c;
         g_create_error = "hipHostMalloc failed";
         return TNEP_E_HIP;

@@ -19,7 +19,7 @@ namespace tnep {
 namespace {
 
 __global__ void k_init_flags(int32_t* f) {
-    if (threadIdx.x < 8) f[threadIdx.x] = threadIdx.x == kFlagBadAtom ? INT_MAX : 0;
+    if (threadIdx.x < 32) f[threadIdx.x] = threadIdx.x == kFlagBadAtom ? INT_MAX : 0;
 }
 
 }  // namespace
@@ -94,10 +94,6 @@ int fetch_meta(Ctx* c, const tnep_frames& fr, HostMeta& m) {
     return TNEP_OK;
 }
 
-inline int frame_of_atom(const std::vector<int64_t>& offs, int64_t a) {
-    return (int)(std::upper_bound(offs.begin(), offs.end(), a) - offs.begin()) - 1;
-}
-
 }  // namespace
 
 int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
@@ -109,16 +105,16 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
     if (e) return e;
     const int64_t A = meta.offs[F];
 
-    // models sharing cutoffs share one neighbour build
+    // models with the same cutoffs and species count share one neighbour build
     const Model* m0 = job.models[0];
-    bool shared = job.n_models == 1 || (job.models[1]->rc_radial == m0->rc_radial &&
-                                         job.models[1]->rc_angular == m0->rc_angular);
-    int n_species = m0->T;
-    for (int k = 0; k < job.n_models; ++k) n_species = std::min(n_species, job.models[k]->T);
+    const bool shared = job.n_models == 1 ||
+                        (job.models[1]->rc_radial == m0->rc_radial && job.models[1]->rc_angular == m0->rc_angular &&
+                         job.models[1]->T == m0->T);
 
     for (int group = 0; group < (shared ? 1 : job.n_models); ++group) {
         const Model* gm = job.models[group];
         const int first = shared ? 0 : group, last = shared ? job.n_models : group + 1;
+        const int T = gm->T;
         std::vector<FrameGeom> geom(F);
         for (int f = 0; f < F; ++f) {
             e = frame_geometry(c, f, fr.cells ? meta.cells.data() + 9 * (size_t)f : nullptr,
@@ -127,32 +123,53 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
         }
         bool done = false;
         for (int attempt = 0; attempt < 4 && !done; ++attempt) {
+            // rows per tile slot: per-species angular and radial-only segments
+            int segA[8] = {0}, segR[8] = {0}, slots = 0;
+            for (int t = 0; t < T; ++t) {
+                segA[t] = slots;
+                slots += c->cap_ang[t];
+                segR[t] = slots;
+                slots += c->cap_rad[t];
+            }
             // batch size in atoms
             int64_t largest = 0;
             for (int f = 0; f < F; ++f) largest = std::max(largest, meta.offs[f + 1] - meta.offs[f]);
-            const int64_t per_atom_bytes = (int64_t)(c->cap_ang + c->cap_rad) * 16 + 8 + 12 + 72 * (last - first) +
+            const int64_t per_atom_bytes = (int64_t)slots * 16 + 8 * T + 24 + 72 * (last - first) +
                                            (fr.location == TNEP_HOST ? 28 : 0);
             int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
             B = std::max(B, largest);
-            // keep within the budget: shrink to what fits next to what is already held
             const int64_t room = (int64_t)c->budget - (int64_t)(c->in_use - c->nbr.bytes - c->per_atom.bytes);
             if (room > 0 && B * per_atom_bytes > room) B = std::max(largest, room / per_atom_bytes);
-            // reserve
-            if ((e = c->reserve(c->nbr, (size_t)B * (c->cap_ang + c->cap_rad) * sizeof(float4)))) return e;
-            if ((e = c->reserve(c->n_ang, (size_t)B * 4))) return e;
-            if ((e = c->reserve(c->n_rad, (size_t)B * 4))) return e;
-            if ((e = c->reserve(c->frame_of, (size_t)B * 4))) return e;
-            if ((e = c->reserve(c->cell_of, (size_t)B * 4))) return e;
-            if ((e = c->reserve(c->cell_atoms, (size_t)B * 4))) return e;
-            if ((e = c->reserve(c->per_atom, (size_t)B * 9 * sizeof(double) * (last - first)))) return e;
-            if ((e = c->reserve(c->flags, 64))) return e;
-            if (c->timing && !c->counters.p) {
-                if ((e = c->reserve(c->counters, 64))) return e;
-                HIP_CHECK_RET(c, hipMemsetAsync(c->counters.p, 0, 64, c->stream));
+            const int64_t n_pad_max = (B + 63) / 64 * 64 + 64 * T;
+            if ((e = c->reserve(c->nbr, (size_t)n_pad_max * slots * sizeof(float4)))) return e;
+            if ((e = c->reserve(c->counts, (size_t)n_pad_max * 2 * T * 4))) return e;
+            if ((e = c->reserve(c->perm, (size_t)n_pad_max * 4))) return e;
+            if ((e = c->reserve(c->tile_base, sizeof(int32_t) * kMetaInts))) return e;
+            {
+                int32_t h[kMetaInts] = {0};
+                for (int t = 0; t < T; ++t) {
+                    h[kMetaSegA + t] = segA[t];
+                    h[kMetaSegR + t] = segR[t];
+                    h[kMetaCapA + t] = c->cap_ang[t];
+                    h[kMetaCapR + t] = c->cap_rad[t];
+                }
+                // only the host part: the tile bases are written by the scan kernel
+                HIP_CHECK_RET(c, hipMemcpyAsync((int32_t*)c->tile_base.p + kMetaSegA, h + kMetaSegA,
+                                                sizeof(int32_t) * (kMetaInts - kMetaSegA), hipMemcpyHostToDevice,
+                                                c->stream));
             }
+            if ((e = c->reserve(c->frame_of, (size_t)B * 4))) return e;
+            if ((e = c->reserve(c->key_of, (size_t)B * 4))) return e;
+            if ((e = c->reserve(c->bucket_atoms, (size_t)B * 4))) return e;
+            if ((e = c->reserve(c->per_atom, (size_t)B * 9 * sizeof(double) * (last - first)))) return e;
+            if ((e = c->reserve(c->flags, 32 * 4))) return e;
             if (fr.location == TNEP_HOST) {
                 if ((e = c->reserve(c->pos, (size_t)B * 24))) return e;
                 if ((e = c->reserve(c->species, (size_t)B * 4))) return e;
+            }
+            if (c->timing && !c->counters.p) {
+                if ((e = c->reserve(c->counters, 64))) return e;
+                HIP_CHECK_RET(c, hipMemsetAsync(c->counters.p, 0, 64, c->stream));
             }
             HIP_CHECK_RET(c, launch_init_flags((int32_t*)c->flags.p, c->stream));
 
@@ -180,12 +197,15 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         x.L[d] = g.L[d];
                     }
                     x.cell_base = n_cells;
-                    n_cells += g.n_cells();
+                    n_cells += g.mode == 1 ? g.n_cells() : 1;
                 }
+                const int64_t n_buckets = (int64_t)n_cells * T;
+                if (n_buckets >= ((int64_t)1 << 30)) return c->fail(TNEP_E_INVALID, "too many cells in one batch");
                 if ((e = c->reserve(c->frames, sizeof(FrameInfo) * nf))) return e;
-                if ((e = c->reserve(c->cell_count, (size_t)4 * (n_cells + 1)))) return e;
-                if ((e = c->reserve(c->cell_start, (size_t)4 * (n_cells + 1)))) return e;
-                if ((e = c->reserve(c->cell_fill, (size_t)4 * (n_cells + 1)))) return e;
+                if ((e = c->reserve(c->bucket_count, (size_t)4 * (n_buckets + 1)))) return e;
+                if ((e = c->reserve(c->bucket_start, (size_t)4 * (n_buckets + 1)))) return e;
+                if ((e = c->reserve(c->bucket_fill, (size_t)4 * (n_buckets + 1)))) return e;
+                if ((e = c->reserve(c->perm_start, (size_t)4 * (n_buckets + 1)))) return e;
                 const int nt_max = 9;
                 if ((e = c->reserve(c->out, sizeof(double) * nt_max * nf * (last - first)))) return e;
                 HIP_CHECK_RET(c, hipMemcpyAsync(c->frames.p, fi.data(), sizeof(FrameInfo) * nf,
@@ -203,12 +223,19 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     pos = fr.positions + 3 * a0;
                     spc = fr.species + a0;
                 }
-                NeighborWork w{(int32_t*)c->frame_of.p, (int32_t*)c->cell_of.p,   (int32_t*)c->cell_count.p,
-                               (int32_t*)c->cell_start.p, (int32_t*)c->cell_fill.p, (int32_t*)c->cell_atoms.p};
-                NeighborLists nl{(float4*)c->nbr.p, (int32_t*)c->n_ang.p, (int32_t*)c->n_rad.p, c->cap_ang,
-                                 c->cap_rad, na};
+                NeighborWork w{(int32_t*)c->frame_of.p,     (int32_t*)c->key_of.p,       (int32_t*)c->bucket_count.p,
+                               (int32_t*)c->bucket_start.p, (int32_t*)c->bucket_fill.p,  (int32_t*)c->bucket_atoms.p,
+                               (int32_t*)c->perm_start.p,   (int32_t*)c->perm.p,         (int32_t*)c->tile_base.p};
+                NeighborLists nl{};
+                nl.entries = (float4*)c->nbr.p;
+                nl.counts = (int32_t*)c->counts.p;
+                nl.perm = (const int32_t*)c->perm.p;
+                nl.meta = (const int32_t*)c->tile_base.p;
+                nl.n_pad = (na + 63) / 64 * 64 + 64 * T;
+                nl.T = T;
+                nl.slots = slots;
                 int tr = c->timer_begin(TNEP_KERNEL_NEIGHBORS);
-                HIP_CHECK_RET(c, launch_neighbors((const FrameInfo*)c->frames.p, nf, pos, spc, na, n_species, n_cells,
+                HIP_CHECK_RET(c, launch_neighbors((const FrameInfo*)c->frames.p, nf, pos, spc, na, n_cells,
                                                   (float)gm->rc_radial, (float)gm->rc_angular, w, nl,
                                                   (int32_t*)c->flags.p, c->stream));
                 c->timer_end(tr);
@@ -221,7 +248,7 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     if (job.per_atom[k] && fr.location == TNEP_DEVICE) pa = job.per_atom[k] + a0 * nt;
                     tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE ? TNEP_KERNEL_EVAL_DIPOLE
                                                                     : TNEP_KERNEL_EVAL_POLARIZABILITY);
-                    HIP_CHECK_RET(c, launch_eval(m->shape, m->dm, nl, spc, pa, c->launch, c->stream));
+                    HIP_CHECK_RET(c, launch_eval(m->shape, m->dm, nl, pa, c->launch, c->stream));
                     c->timer_end(tr);
                     double* o = fr.location == TNEP_DEVICE ? job.out[k] + (size_t)f0 * nt
                                                            : (double*)c->out.p + (size_t)nt_max * nf * (k - first);
@@ -238,34 +265,35 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 }
                 f0 = f1;
             }
-            HIP_CHECK_RET(c, hipMemcpyAsync(c->h_flags, c->flags.p, sizeof(int32_t) * 8, hipMemcpyDeviceToHost,
+            HIP_CHECK_RET(c, hipMemcpyAsync(c->h_flags, c->flags.p, sizeof(int32_t) * 32, hipMemcpyDeviceToHost,
                                             c->stream));
             HIP_CHECK_RET(c, hipStreamSynchronize(c->stream));
             c->timer_flush();
             const int32_t* fl = c->h_flags;
             if (fl[kFlagError]) {
-                const int64_t bad = fl[kFlagBadAtom];
-                // the flag holds a batch-local index; report the first bad frame conservatively
                 const int code = (fl[kFlagError] & kErrNonFinite) ? TNEP_E_NONFINITE
                                  : (fl[kFlagError] & kErrSpecies) ? TNEP_E_SPECIES
                                                                   : TNEP_E_OVERLAP;
-                (void)frame_of_atom;
-                return c->fail(code, "invalid input (%s) near batch-local atom %lld",
+                return c->fail(code, "invalid input (%s) near batch-local atom %d",
                                code == TNEP_E_NONFINITE ? "non-finite position"
                                : code == TNEP_E_SPECIES ? "species out of range"
                                                         : "atoms closer than 1e-4 A",
-                               (long long)bad);
+                               fl[kFlagBadAtom]);
             }
-            if (fl[kFlagMaxAng] > c->cap_ang || fl[kFlagMaxRad] > c->cap_rad) {
-                c->cap_ang = std::max(c->cap_ang, ((fl[kFlagMaxAng] * 5 / 4) + 15) / 16 * 16);
-                c->cap_rad = std::max(c->cap_rad, ((fl[kFlagMaxRad] * 5 / 4) + 15) / 16 * 16);
-                continue;  // repeat with larger lists
+            bool grow = false;
+            for (int t = 0; t < T; ++t) {
+                if (fl[kFlagCapAng + t] > c->cap_ang[t]) {
+                    c->cap_ang[t] = (fl[kFlagCapAng + t] * 5 / 4 + 3) / 4 * 4;
+                    grow = true;
+                }
+                if (fl[kFlagCapRad + t] > c->cap_rad[t]) {
+                    c->cap_rad[t] = (fl[kFlagCapRad + t] * 5 / 4 + 3) / 4 * 4;
+                    grow = true;
+                }
             }
-            done = true;
+            if (!grow) done = true;
         }
-        if (!done)
-            return c->fail(TNEP_E_NEIGH_OVERFLOW, "neighbour lists still overflow after growing to %d + %d slots",
-                           c->cap_ang, c->cap_rad);
+        if (!done) return c->fail(TNEP_E_NEIGH_OVERFLOW, "neighbour lists still overflow after growing them");
     }
     return TNEP_OK;
 }

@@ -37,36 +37,50 @@ struct Shape {
     int nr, na, kr, ka, four_body, kind;
 };
 
-// Neighbour lists of a batch.  Entry layout: float4 (dx, dy, dz, bits(t_j))
-// with r_ij = r_j - r_i; slot-major, atom-minor: entry (s, i) at s * n_atoms + i.
-// Slots [0, cap_ang) hold neighbours with r < rc_angular (used by both the
-// radial and the angular terms); slots [cap_ang, cap_ang + cap_rad) hold
-// neighbours with rc_angular <= r < rc_radial (radial terms only).
+// Neighbour lists of a batch.
+// Atoms are processed in 64-atom tiles of one species: tile slot p = 64 * tile
+// + lane holds atom perm[p] (-1 = padding).  The neighbours of that atom are
+// stored by neighbour species t in two segments: rows [segA[t], segA[t] +
+// capA[t]) for r < rc_angular (used by the radial and the angular terms) and
+// rows [segR[t], segR[t] + capR[t]) for rc_angular <= r < rc_radial (radial
+// terms only).  Entry (row r) of slot p is the float4 (dx, dy, dz, 0) with
+// r_ij = r_j - r_i, stored at entries[((tile * slots/4 + r/4) * 64 + lane) * 4
+// + r % 4]: four consecutive rows of one lane are 64 contiguous bytes.
+// Per-species segment tables live in device memory (meta) so that kernels
+// index them with scalar loads.
+enum Meta { kMetaTileBase = 0, kMetaSegA = 16, kMetaSegR = 24, kMetaCapA = 32, kMetaCapR = 40, kMetaInts = 48 };
+
 struct NeighborLists {
     float4* entries;
-    int32_t* n_ang;  // [n_atoms]
-    int32_t* n_rad;  // [n_atoms]
-    int32_t cap_ang, cap_rad;
-    int64_t n_atoms;
+    int32_t* counts;      // [2T][n_pad]: row 2t angular count, 2t+1 radial-only count
+    const int32_t* perm;  // [n_pad]
+    const int32_t* meta;  // [kMetaInts]: tile_base[T + 1] (first tile of species t, tiles in use at
+                          // T), segA[t], segR[t], capA[t], capR[t]
+    int64_t n_pad;        // tile slots (multiple of 64)
+    int32_t T;
+    int32_t slots;        // rows per slot (multiple of 4)
 };
 
-// Error / overflow flags written by the kernels (device int32[8]).
-enum Flag { kFlagError = 0, kFlagMaxAng = 1, kFlagMaxRad = 2, kFlagBadAtom = 3 };
+// Error / overflow flags written by the kernels (device int32[32]).
+enum Flag { kFlagError = 0, kFlagBadAtom = 1, kFlagCapAng = 8, kFlagCapRad = 16 };
 enum ErrBits { kErrSpecies = 1, kErrNonFinite = 2, kErrOverlap = 4 };
 
 // ---- neighbour search (kernels_neighbors.hip) ----
 struct NeighborWork {
-    int32_t* frame_of;    // [n_atoms]
-    int32_t* cell_of;     // [n_atoms]
-    int32_t* cell_count;  // [n_cells]
-    int32_t* cell_start;  // [n_cells + 1]
-    int32_t* cell_fill;   // [n_cells]
-    int32_t* cell_atoms;  // [n_atoms]
+    int32_t* frame_of;      // [n_atoms]
+    int32_t* key_of;        // [n_atoms] bucket (cell * T + species)
+    int32_t* bucket_count;  // [n_buckets]
+    int32_t* bucket_start;  // [n_buckets + 1]
+    int32_t* bucket_fill;   // [n_buckets]
+    int32_t* bucket_atoms;  // [n_atoms]
+    int32_t* perm_start;    // [n_buckets]
+    int32_t* perm;          // [n_pad]
+    int32_t* meta;          // [kMetaInts], tile_base part written on the device
 };
 
 hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,
-                            int64_t n_atoms, int n_species, int n_cells, float rc_radial, float rc_angular,
-                            const NeighborWork& w, const NeighborLists& nl, int32_t* d_flags, hipStream_t s);
+                            int64_t n_atoms, int n_cells, float rc_radial, float rc_angular, const NeighborWork& w,
+                            const NeighborLists& nl, int32_t* d_flags, hipStream_t s);
 
 // ---- evaluation (kernels_eval.hip) ----
 struct EvalLaunch {
@@ -74,10 +88,10 @@ struct EvalLaunch {
     int atoms_per_block;  // 64, 128, 256
 };
 
-// Per-atom tensors (FP64, [n_atoms][3 or 9]) of one model.
+// Per-atom tensors (FP64, [n_atoms][3 or 9], batch atom order) of one model.
 bool eval_shape_supported(const Shape& s);
-hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, const int32_t* species,
-                       double* per_atom, const EvalLaunch& cfg, hipStream_t s);
+hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
+                       const EvalLaunch& cfg, hipStream_t s);
 
 // Add the batch's atom count and neighbour-pair counts to counters[0..2].
 hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* counters, hipStream_t s);

@@ -2,15 +2,24 @@
 //
 // The sums over j != i of the method (Sec. 2.1, Eq. virial; Sec. 2.2, Eq. mu;
 // Sec. 2.3, Eq. polarizability-model) run over the atoms inside the radial
-// cutoff.  Fully periodic orthorhombic frames with at least three cells of
-// edge >= rc_radial per axis use a cell list (counting sort of atoms into
-// cells, then the 27-cell stencil); every other frame (vacuum molecules,
-// small boxes) uses an all-pairs scan inside the frame.  Pair vectors are
-// formed in FP64 with the minimum-image convention and stored as FP32.
+// cutoff.  Pair vectors are formed in FP64 with the minimum-image convention
+// and stored as FP32.
 //
-// Results are independent of thread scheduling: atoms inside a cell are
-// sorted by index after the atomic scatter, and neighbours are written in
-// stencil order, then index order.
+// Pipeline (all on the device):
+//   1. bin every atom into a bucket (cell, species).  Fully periodic
+//      orthorhombic frames with >= 3 cells of edge >= rc_radial per axis use a
+//      cell grid; every other frame (vacuum molecules, small boxes) is one cell;
+//   2. scan the bucket counts twice: in (cell, species) order for the
+//      candidate lists and in (species, cell) order for the atom tiles;
+//   3. scatter atoms into buckets and sort each bucket by atom index, which
+//      makes the whole result independent of thread scheduling;
+//   4. build the tile permutation: atoms ordered by (species, cell, index),
+//      each species padded to whole 64-atom tiles (species-pure wavefronts);
+//   5. one lane per tile slot walks the 27-cell stencil (or its frame) once per
+//      neighbour species t and writes the neighbours of species t into that
+//      species' angular (r < rc_angular) and radial-only segments.
+// Entries are grouped four to a lane (64 contiguous bytes), so every store and
+// load of a wavefront covers one contiguous 4 KB block.
 #include "internal.h"
 
 namespace tnep {
@@ -31,15 +40,15 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 }
 
 __device__ __forceinline__ int cell_coord(double p, double L, int nc) {
-    double s = p - L * floor(p / L);
-    int c = (int)(s * (double)nc / L);
+    const double s = p - L * floor(p / L);
+    const int c = (int)(s * (double)nc / L);
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
+// key = (frame cell) * T + species; invalid atoms get key -1.
 __global__ void k_bin(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ frame_of,
-                      const double* __restrict__ pos, const int32_t* __restrict__ species, int64_t n_atoms,
-                      int n_species, int32_t* __restrict__ cell_of, int32_t* __restrict__ cell_count,
-                      int32_t* __restrict__ flags) {
+                      const double* __restrict__ pos, const int32_t* __restrict__ species, int64_t n_atoms, int T,
+                      int32_t* __restrict__ key_of, int32_t* __restrict__ bucket_count, int32_t* __restrict__ flags) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n_atoms) return;
     const FrameInfo& fi = frames[frame_of[a]];
@@ -47,218 +56,293 @@ __global__ void k_bin(const FrameInfo* __restrict__ frames, const int32_t* __res
     const int t = species[a];
     int err = 0;
     if (!(isfinite(x) && isfinite(y) && isfinite(z))) err |= kErrNonFinite;
-    if (t < 0 || t >= n_species) err |= kErrSpecies;
+    if (t < 0 || t >= T) err |= kErrSpecies;
     if (err) {
         atomicOr(&flags[kFlagError], err);
         atomicMin(&flags[kFlagBadAtom], (int)a);
-        cell_of[a] = -1;
+        key_of[a] = -1;
         return;
     }
-    if (fi.mode != 1) {
-        cell_of[a] = -1;
-        return;
+    int c = fi.cell_base;
+    if (fi.mode == 1) {
+        const int ix = cell_coord(x, fi.L[0], fi.nc[0]);
+        const int iy = cell_coord(y, fi.L[1], fi.nc[1]);
+        const int iz = cell_coord(z, fi.L[2], fi.nc[2]);
+        c += (ix * fi.nc[1] + iy) * fi.nc[2] + iz;
     }
-    const int ix = cell_coord(x, fi.L[0], fi.nc[0]);
-    const int iy = cell_coord(y, fi.L[1], fi.nc[1]);
-    const int iz = cell_coord(z, fi.L[2], fi.nc[2]);
-    const int c = fi.cell_base + (ix * fi.nc[1] + iy) * fi.nc[2] + iz;
-    cell_of[a] = c;
-    atomicAdd(&cell_count[c], 1);
+    const int key = c * T + t;
+    key_of[a] = key;
+    atomicAdd(&bucket_count[key], 1);
 }
 
-// Exclusive scan of cell_count into cell_start (n + 1 entries); one work-group.
-__global__ void __launch_bounds__(1024) k_scan(const int32_t* __restrict__ count, int32_t* __restrict__ start,
-                                               int32_t* __restrict__ fill, int n) {
-    __shared__ int32_t part[1024];
+// Block-wide exclusive scan over 1024 threads; *total receives the sum.
+__device__ int32_t block_exclusive(int32_t v, int32_t* part, int32_t* total) {
     const int tid = threadIdx.x;
-    const int chunk = (n + 1023) / 1024;
-    const int b = tid * chunk;
-    const int e = min(b + chunk, n);
-    int32_t s = 0;
-    for (int i = b; i < e; ++i) s += count[i];
-    part[tid] = s;
+    part[tid] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = tid >= off ? part[tid - off] : 0;
+        const int32_t u = tid >= off ? part[tid - off] : 0;
         __syncthreads();
-        part[tid] += v;
+        part[tid] += u;
         __syncthreads();
     }
-    int32_t run = part[tid] - s;  // exclusive prefix of this chunk
-    for (int i = b; i < e; ++i) {
-        start[i] = run;
-        fill[i] = 0;
-        run += count[i];
-    }
-    if (tid == 1023) start[n] = part[1023];
+    const int32_t incl = part[tid];
+    *total = part[1023];
+    __syncthreads();
+    return incl - v;
 }
 
-__global__ void k_scatter(const int32_t* __restrict__ cell_of, const int32_t* __restrict__ cell_start,
-                          int32_t* __restrict__ cell_fill, int32_t* __restrict__ cell_atoms, int64_t n_atoms) {
+// One work-group: bucket_start in key order (n_buckets + 1 entries),
+// tile_base[t] (first 64-atom tile of species t, T + 1 entries) and
+// perm_start[key] (first tile slot of the bucket in (species, cell) order).
+__global__ void __launch_bounds__(1024) k_scan(const int32_t* __restrict__ count, int n_cells, int T,
+                                               int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_fill,
+                                               int32_t* __restrict__ perm_start, int32_t* __restrict__ meta) {
+    __shared__ int32_t part[1024];
+    __shared__ int32_t s_tile_base[9];
+    const int tid = threadIdx.x;
+    const int n = n_cells * T;
+    {
+        const int chunk = (n + 1023) / 1024;
+        const int b = tid * chunk, e = min(b + chunk, n);
+        int32_t s = 0;
+        for (int i = b; i < e; ++i) s += count[i];
+        int32_t total;
+        int32_t run = block_exclusive(s, part, &total);
+        for (int i = b; i < e; ++i) {
+            bucket_start[i] = run;
+            bucket_fill[i] = 0;
+            run += count[i];
+        }
+        if (tid == 0) bucket_start[n] = total;
+    }
+    const int chunk = (n_cells + 1023) / 1024;
+    const int b = tid * chunk, e = min(b + chunk, n_cells);
+    int32_t tiles = 0;
+    for (int t = 0; t < T; ++t) {
+        int32_t s = 0;
+        for (int c = b; c < e; ++c) s += count[c * T + t];
+        int32_t total;
+        int32_t run = block_exclusive(s, part, &total) + tiles * 64;
+        for (int c = b; c < e; ++c) {
+            perm_start[c * T + t] = run;
+            run += count[c * T + t];
+        }
+        if (tid == 0) s_tile_base[t] = tiles;
+        tiles += (total + 63) / 64;
+    }
+    if (tid == 0) s_tile_base[T] = tiles;
+    __syncthreads();
+    if (tid <= T) meta[kMetaTileBase + tid] = s_tile_base[tid];
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
+                          int32_t* __restrict__ bucket_fill, int32_t* __restrict__ bucket_atoms, int64_t n_atoms) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n_atoms) return;
-    const int c = cell_of[a];
-    if (c < 0) return;
-    const int slot = atomicAdd(&cell_fill[c], 1);
-    cell_atoms[cell_start[c] + slot] = (int32_t)a;
+    const int k = key_of[a];
+    if (k < 0) return;
+    const int slot = atomicAdd(&bucket_fill[k], 1);
+    bucket_atoms[bucket_start[k] + slot] = (int32_t)a;
 }
 
-__global__ void k_sort_cells(const int32_t* __restrict__ cell_start, int32_t* __restrict__ cell_atoms, int n_cells) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    const int b = cell_start[c], e = cell_start[c + 1];
+// Sort each bucket by atom index, then place it into the tile permutation.
+__global__ void k_sort_place(const int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_atoms,
+                             const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm, int n_buckets) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_buckets) return;
+    const int b = bucket_start[k], e = bucket_start[k + 1];
     for (int i = b + 1; i < e; ++i) {
-        const int32_t v = cell_atoms[i];
+        const int32_t v = bucket_atoms[i];
         int j = i - 1;
-        while (j >= b && cell_atoms[j] > v) {
-            cell_atoms[j + 1] = cell_atoms[j];
+        while (j >= b && bucket_atoms[j] > v) {
+            bucket_atoms[j + 1] = bucket_atoms[j];
             --j;
         }
-        cell_atoms[j + 1] = v;
+        bucket_atoms[j + 1] = v;
     }
+    const int p = perm_start[k];
+    for (int i = b; i < e; ++i) perm[p + (i - b)] = bucket_atoms[i];
 }
-
-struct PairSink {
-    float4* entries;
-    int64_t n_atoms;
-    int64_t i;
-    int cap_ang, cap_rad;
-    int n_ang, n_rad;
-    float rc2_ang, rc2_rad;
-    bool overlap;
-
-    __device__ __forceinline__ void add(double dx, double dy, double dz, int tj) {
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= (double)rc2_rad) return;
-        if (r2 < 1e-8) overlap = true;
-        const float4 e = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(tj));
-        if (r2 < (double)rc2_ang) {
-            if (n_ang < cap_ang) entries[(int64_t)n_ang * n_atoms + i] = e;
-            ++n_ang;
-        } else {
-            if (n_rad < cap_rad) entries[(int64_t)(cap_ang + n_rad) * n_atoms + i] = e;
-            ++n_rad;
-        }
-    }
-};
 
 __device__ __forceinline__ double min_image(double d, double L, int per) {
     return per ? d - L * rint(d / L) : d;
 }
 
+// Four entries buffered in registers, written as one 64-byte group.
+// A group row (4 entries x 64 lanes) is 256 float4.
+struct Stream {
+    float4 b0, b1, b2, b3;
+    int n;
+    __device__ __forceinline__ void push(const float4& e, float4* base, int cap) {
+        b0 = b1;
+        b1 = b2;
+        b2 = b3;
+        b3 = e;
+        ++n;
+        if ((n & 3) == 0 && n <= cap) {
+            float4* g = base + (int64_t)((n - 4) >> 2) * 256;
+            g[0] = b0;
+            g[1] = b1;
+            g[2] = b2;
+            g[3] = b3;
+        }
+    }
+    __device__ __forceinline__ void flush(float4* base, int cap) {
+        const int k = n & 3;
+        if (k == 0 || n > cap) return;
+        float4* g = base + (int64_t)((n - k) >> 2) * 256;
+        if (k == 3) {
+            g[0] = b1;
+            g[1] = b2;
+            g[2] = b3;
+        } else if (k == 2) {
+            g[0] = b2;
+            g[1] = b3;
+        } else {
+            g[0] = b3;
+        }
+    }
+};
+
 __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restrict__ frames,
                                                       const int32_t* __restrict__ frame_of,
                                                       const double* __restrict__ pos,
-                                                      const int32_t* __restrict__ species,
-                                                      const int32_t* __restrict__ cell_of,
-                                                      const int32_t* __restrict__ cell_start,
-                                                      const int32_t* __restrict__ cell_atoms, int64_t n_atoms,
-                                                      float rc_radial, float rc_angular, NeighborLists nl,
+                                                      const int32_t* __restrict__ key_of,
+                                                      const int32_t* __restrict__ bucket_start,
+                                                      const int32_t* __restrict__ bucket_atoms, float rc_radial,
+                                                      float rc_angular, NeighborLists nl,
                                                       int32_t* __restrict__ flags) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_atoms) return;
-    const FrameInfo& fi = frames[frame_of[i]];
-    PairSink sink{nl.entries, n_atoms, i, nl.cap_ang, nl.cap_rad, 0, 0,
-                  rc_angular * rc_angular, rc_radial * rc_radial, false};
-    const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-    if (fi.mode == 1) {
-        const int c = cell_of[i];
-        if (c < 0) {
-            nl.n_ang[i] = 0;
-            nl.n_rad[i] = 0;
-            return;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nl.n_pad) return;
+    const int T = nl.T;
+    const int a = nl.perm[p];
+    const int tile = (int)(p >> 6), lane = (int)(p & 63);
+    if (a < 0) {
+        for (int t = 0; t < T; ++t) {
+            nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = 0;
+            nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = 0;
         }
-        const int local = c - fi.cell_base;
-        const int nz = fi.nc[2], ny = fi.nc[1], nx = fi.nc[0];
-        const int iz = local % nz, iy = (local / nz) % ny, ix = local / (nz * ny);
-        for (int ddx = -1; ddx <= 1; ++ddx) {
-            const int cx = (ix + ddx + nx) % nx;
-            for (int ddy = -1; ddy <= 1; ++ddy) {
-                const int cy = (iy + ddy + ny) % ny;
-                for (int ddz = -1; ddz <= 1; ++ddz) {
-                    const int cz = (iz + ddz + nz) % nz;
-                    const int cc = fi.cell_base + (cx * ny + cy) * nz + cz;
-                    const int b = cell_start[cc], e = cell_start[cc + 1];
-                    for (int k = b; k < e; ++k) {
-                        const int j = cell_atoms[k];
-                        if (j == i) continue;
-                        const double dx = min_image(pos[3 * j] - xi, fi.L[0], 1);
-                        const double dy = min_image(pos[3 * j + 1] - yi, fi.L[1], 1);
-                        const double dz = min_image(pos[3 * j + 2] - zi, fi.L[2], 1);
-                        sink.add(dx, dy, dz, species[j]);
-                    }
-                }
+        return;
+    }
+    const FrameInfo& fi = frames[frame_of[a]];
+    const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
+    const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
+    // entry (row r) of this lane: lane_base + (r / 4) * 256 + r % 4
+    float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
+    int ix = 0, iy = 0, iz = 0;
+    const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
+    if (fi.mode == 1) {
+        const int local = key_of[a] / T - fi.cell_base;
+        iz = local % nz;
+        iy = (local / nz) % ny;
+        ix = local / (nz * ny);
+    }
+    bool overlap = false;
+    for (int t = 0; t < T; ++t) {
+        Stream sa, sr;
+        sa.n = 0;
+        sr.n = 0;
+        float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
+        float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
+        const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
+        const int n_visit = fi.mode == 1 ? 27 : 1;
+        for (int vb = 0; vb < n_visit; ++vb) {
+            int bucket = fi.cell_base * T + t;
+            if (fi.mode == 1) {
+                const int cx = (ix + vb / 9 - 1 + nx) % nx;
+                const int cy = (iy + (vb / 3) % 3 - 1 + ny) % ny;
+                const int cz = (iz + vb % 3 - 1 + nz) % nz;
+                bucket = (fi.cell_base + (cx * ny + cy) * nz + cz) * T + t;
+            }
+            const int b = bucket_start[bucket], e = bucket_start[bucket + 1];
+            for (int k = b; k < e; ++k) {
+                const int j = bucket_atoms[k];
+                if (j == a) continue;
+                const double dx = min_image(pos[3 * j] - xi, fi.L[0], fi.per[0]);
+                const double dy = min_image(pos[3 * j + 1] - yi, fi.L[1], fi.per[1]);
+                const double dz = min_image(pos[3 * j + 2] - zi, fi.L[2], fi.per[2]);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= rc2r) continue;
+                if (r2 < 1e-8) overlap = true;
+                const float4 ent = make_float4((float)dx, (float)dy, (float)dz, 0.f);
+                if (r2 < rc2a)
+                    sa.push(ent, ga, capA);
+                else
+                    sr.push(ent, gr, capR);
             }
         }
-    } else {
-        const int64_t b = fi.atom_begin, e = fi.atom_begin + fi.n_atoms;
-        for (int64_t j = b; j < e; ++j) {
-            if (j == i) continue;
-            const double dx = min_image(pos[3 * j] - xi, fi.L[0], fi.per[0]);
-            const double dy = min_image(pos[3 * j + 1] - yi, fi.L[1], fi.per[1]);
-            const double dz = min_image(pos[3 * j + 2] - zi, fi.L[2], fi.per[2]);
-            sink.add(dx, dy, dz, species[j]);
-        }
+        sa.flush(ga, capA);
+        sr.flush(gr, capR);
+        nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(sa.n, capA);
+        nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(sr.n, capR);
+        if (sa.n > capA) atomicMax(&flags[kFlagCapAng + t], sa.n);
+        if (sr.n > capR) atomicMax(&flags[kFlagCapRad + t], sr.n);
     }
-    nl.n_ang[i] = min(sink.n_ang, nl.cap_ang);
-    nl.n_rad[i] = min(sink.n_rad, nl.cap_rad);
-    if (sink.n_ang > nl.cap_ang) atomicMax(&flags[kFlagMaxAng], sink.n_ang);
-    if (sink.n_rad > nl.cap_rad) atomicMax(&flags[kFlagMaxRad], sink.n_rad);
-    if (sink.overlap) {
+    if (overlap) {
         atomicOr(&flags[kFlagError], kErrOverlap);
-        atomicMin(&flags[kFlagBadAtom], (int)i);
+        atomicMin(&flags[kFlagBadAtom], a);
     }
 }
 
-inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-
-__global__ void k_count_pairs(const int32_t* __restrict__ n_ang, const int32_t* __restrict__ n_rad, int64_t n,
-                              unsigned long long* __restrict__ counters) {
-    __shared__ unsigned long long s_ang[kBlock], s_rad[kBlock];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    s_ang[threadIdx.x] = i < n ? (unsigned long long)n_ang[i] : 0ull;
-    s_rad[threadIdx.x] = i < n ? (unsigned long long)n_rad[i] : 0ull;
+__global__ void k_count_pairs(const NeighborLists nl, unsigned long long* __restrict__ counters) {
+    __shared__ unsigned long long s_ang[kBlock], s_rad[kBlock], s_at[kBlock];
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long na = 0, nr = 0, at = 0;
+    if (p < nl.n_pad && nl.perm[p] >= 0) {
+        at = 1;
+        for (int t = 0; t < nl.T; ++t) {
+            na += (unsigned long long)nl.counts[(int64_t)(2 * t) * nl.n_pad + p];
+            nr += (unsigned long long)nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
+        }
+    }
+    s_ang[threadIdx.x] = na;
+    s_rad[threadIdx.x] = nr;
+    s_at[threadIdx.x] = at;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) {
             s_ang[threadIdx.x] += s_ang[threadIdx.x + off];
             s_rad[threadIdx.x] += s_rad[threadIdx.x + off];
+            s_at[threadIdx.x] += s_at[threadIdx.x + off];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const unsigned long long na = (unsigned long long)min<int64_t>(kBlock, n - (int64_t)blockIdx.x * kBlock);
-        atomicAdd(&counters[0], na);
+        atomicAdd(&counters[0], s_at[0]);
         atomicAdd(&counters[1], s_ang[0] + s_rad[0]);
         atomicAdd(&counters[2], s_ang[0]);
     }
 }
 
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
 }  // namespace
 
-hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* counters, hipStream_t s) {
-    if (nl.n_atoms == 0) return hipSuccess;
-    k_count_pairs<<<blocks_for(nl.n_atoms, kBlock), kBlock, 0, s>>>(nl.n_ang, nl.n_rad, nl.n_atoms, counters);
+hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,
+                            int64_t n_atoms, int n_cells, float rc_radial, float rc_angular, const NeighborWork& w,
+                            const NeighborLists& nl, int32_t* d_flags, hipStream_t s) {
+    if (n_atoms == 0 || n_frames == 0) return hipSuccess;
+    const int T = nl.T;
+    const int n_buckets = n_cells * T;
+    k_frame_of<<<n_frames, kBlock, 0, s>>>(d_frames, w.frame_of);
+    k_fill_i32<<<blocks_for(n_buckets, kBlock), kBlock, 0, s>>>(w.bucket_count, n_buckets, 0);
+    k_fill_i32<<<blocks_for(nl.n_pad, kBlock), kBlock, 0, s>>>(w.perm, nl.n_pad, -1);
+    k_bin<<<blocks_for(n_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, species, n_atoms, T, w.key_of,
+                                                        w.bucket_count, d_flags);
+    k_scan<<<1, 1024, 0, s>>>(w.bucket_count, n_cells, T, w.bucket_start, w.bucket_fill, w.perm_start, w.meta);
+    k_scatter<<<blocks_for(n_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill, w.bucket_atoms,
+                                                            n_atoms);
+    k_sort_place<<<blocks_for(n_buckets, kBlock), kBlock, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
+                                                                 w.perm, n_buckets);
+    k_neighbors<<<blocks_for(nl.n_pad, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
+                                                               w.bucket_atoms, rc_radial, rc_angular, nl, d_flags);
     return hipGetLastError();
 }
 
-hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,
-                            int64_t n_atoms, int n_species, int n_cells, float rc_radial, float rc_angular,
-                            const NeighborWork& w, const NeighborLists& nl, int32_t* d_flags, hipStream_t s) {
-    if (n_atoms == 0 || n_frames == 0) return hipSuccess;
-    k_frame_of<<<n_frames, kBlock, 0, s>>>(d_frames, w.frame_of);
-    if (n_cells > 0) k_fill_i32<<<blocks_for(n_cells, kBlock), kBlock, 0, s>>>(w.cell_count, n_cells, 0);
-    k_bin<<<blocks_for(n_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, species, n_atoms, n_species,
-                                                        w.cell_of, w.cell_count, d_flags);
-    if (n_cells > 0) {
-        k_scan<<<1, 1024, 0, s>>>(w.cell_count, w.cell_start, w.cell_fill, n_cells);
-        k_scatter<<<blocks_for(n_atoms, kBlock), kBlock, 0, s>>>(w.cell_of, w.cell_start, w.cell_fill, w.cell_atoms,
-                                                                n_atoms);
-        k_sort_cells<<<blocks_for(n_cells, kBlock), kBlock, 0, s>>>(w.cell_start, w.cell_atoms, n_cells);
-    }
-    k_neighbors<<<blocks_for(n_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, species, w.cell_of,
-                                                              w.cell_start, w.cell_atoms, n_atoms, rc_radial,
-                                                              rc_angular, nl, d_flags);
+hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* counters, hipStream_t s) {
+    if (nl.n_pad == 0) return hipSuccess;
+    k_count_pairs<<<blocks_for(nl.n_pad, kBlock), kBlock, 0, s>>>(nl, counters);
     return hipGetLastError();
 }
 

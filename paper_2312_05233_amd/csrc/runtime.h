@@ -43,17 +43,19 @@ struct Ctx {
     EvalLaunch launch{0, 256};
     bool autotune = false;
     int64_t max_batch_atoms = 1 << 20;
-    int cap_ang = 64, cap_rad = 128;  // learned neighbour capacities (grow-only)
+    int cap_ang[8] = {16, 16, 16, 16, 16, 16, 16, 16};  // learned per-species neighbour capacities
+    int cap_rad[8] = {32, 32, 32, 32, 32, 32, 32, 32};  // (grow-only, multiples of 4)
     int32_t* h_flags = nullptr;       // pinned
 
     // work buffers
-    DevBuf frames, flags, frame_of, cell_of, cell_count, cell_start, cell_fill, cell_atoms;
-    DevBuf nbr, n_ang, n_rad, per_atom, out, pos, species;
+    DevBuf frames, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, perm_start;
+    DevBuf perm, tile_base, nbr, counts, per_atom, out, pos, species;
     DevBuf spec_work, spec_series, spec_out;
 
     std::vector<DevBuf*> all_buffers() {
-        return {&frames, &flags, &frame_of, &cell_of, &cell_count, &cell_start, &cell_fill, &cell_atoms, &nbr,
-                &n_ang, &n_rad, &per_atom, &out, &pos, &species, &spec_work, &spec_series, &spec_out, &counters};
+        return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
+                &bucket_atoms, &perm_start, &perm, &tile_base, &nbr, &counts, &per_atom, &out, &pos, &species,
+                &spec_work, &spec_series, &spec_out, &counters};
     }
 
     Server* server = nullptr;
