@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mlp", type=int, default=None, help="TNEP_MLP_* mode of the hidden layer")
     ap.add_argument("--atoms-per-block", type=int, default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (frames shard trivially "
@@ -112,6 +114,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4}))
+        return
 
     from paper_2312_05233_amd import tnep
 
@@ -129,7 +141,7 @@ def main():
     dfr = tnep.DeviceFrames(frames)
     mu = torch.zeros((F, 3), dtype=torch.float64, device=dev)
     alpha = torch.zeros((F, 9), dtype=torch.float64, device=dev)
-    M = args.max_lag
+    M = min(args.max_lag, F)
     spec = {k: [torch.zeros(M + 1, dtype=torch.float64, device=dev) for _ in range(2)] + [
         torch.zeros(M, dtype=torch.float64, device=dev)] for k in ("ir", "iso", "aniso")}
     torch.cuda.synchronize()

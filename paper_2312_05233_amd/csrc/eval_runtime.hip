@@ -161,6 +161,7 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if ((e = c->reserve(c->frame_of, (size_t)B * 4))) return e;
             if ((e = c->reserve(c->key_of, (size_t)B * 4))) return e;
             if ((e = c->reserve(c->bucket_atoms, (size_t)B * 4))) return e;
+            if ((e = c->reserve(c->bucket_pos, (size_t)B * 32))) return e;
             if ((e = c->reserve(c->per_atom, (size_t)B * 9 * sizeof(double) * (last - first)))) return e;
             if ((e = c->reserve(c->flags, 32 * 4))) return e;
             if (fr.location == TNEP_HOST) {
@@ -195,6 +196,7 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         x.nc[d] = g.nc[d];
                         x.per[d] = g.per[d];
                         x.L[d] = g.L[d];
+                        x.Linv[d] = g.per[d] ? 1.0 / g.L[d] : 0.0;
                     }
                     x.cell_base = n_cells;
                     n_cells += g.mode == 1 ? g.n_cells() : 1;
@@ -206,6 +208,7 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if ((e = c->reserve(c->bucket_start, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->bucket_fill, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->perm_start, (size_t)4 * (n_buckets + 1)))) return e;
+                if ((e = c->reserve(c->scan_chunks, (size_t)4 * 18 * (n_cells / 1024 + 1)))) return e;
                 const int nt_max = 9;
                 if ((e = c->reserve(c->out, sizeof(double) * nt_max * nf * (last - first)))) return e;
                 HIP_CHECK_RET(c, hipMemcpyAsync(c->frames.p, fi.data(), sizeof(FrameInfo) * nf,
@@ -225,7 +228,8 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 }
                 NeighborWork w{(int32_t*)c->frame_of.p,     (int32_t*)c->key_of.p,       (int32_t*)c->bucket_count.p,
                                (int32_t*)c->bucket_start.p, (int32_t*)c->bucket_fill.p,  (int32_t*)c->bucket_atoms.p,
-                               (int32_t*)c->perm_start.p,   (int32_t*)c->perm.p,         (int32_t*)c->tile_base.p};
+                               (double4*)c->bucket_pos.p,   (int32_t*)c->perm_start.p,   (int32_t*)c->perm.p,
+                               (int32_t*)c->tile_base.p,    (int32_t*)c->scan_chunks.p};
                 NeighborLists nl{};
                 nl.entries = (float4*)c->nbr.p;
                 nl.counts = (int32_t*)c->counts.p;

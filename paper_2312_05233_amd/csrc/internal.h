@@ -16,6 +16,7 @@ struct FrameInfo {
     int32_t per[3];      // periodic axes
     int32_t pad;
     double L[3];         // box edges (periodic axes)
+    double Linv[3];      // 1 / L (periodic axes), else 0
 };
 
 // Device-resident FP32 model parameters.
@@ -73,9 +74,11 @@ struct NeighborWork {
     int32_t* bucket_start;  // [n_buckets + 1]
     int32_t* bucket_fill;   // [n_buckets]
     int32_t* bucket_atoms;  // [n_atoms]
+    double4* bucket_pos;    // [n_atoms] positions in bucket order, w = atom index
     int32_t* perm_start;    // [n_buckets]
     int32_t* perm;          // [n_pad]
     int32_t* meta;          // [kMetaInts], tile_base part written on the device
+    int32_t* chunk;         // [2 * 9 * n_chunks] scan partials (n_chunks = ceil(n_cells / 1024))
 };
 
 hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,

@@ -75,65 +75,118 @@ __global__ void k_bin(const FrameInfo* __restrict__ frames, const int32_t* __res
     atomicAdd(&bucket_count[key], 1);
 }
 
-// Block-wide exclusive scan over 1024 threads; *total receives the sum.
-__device__ int32_t block_exclusive(int32_t v, int32_t* part, int32_t* total) {
+// Bucket scans in three phases over chunks of kScanCells cells (all T species
+// of a cell are adjacent in key order):
+//   phase 1: per chunk, the total count and the per-species totals;
+//   phase 2 (one work-group): chunk offsets in key order and, per species, in
+//            (species, cell) order; species totals give the tile bases;
+//   phase 3: per chunk, bucket_start (key order) and perm_start (first tile
+//            slot of the bucket in (species, cell) order).
+constexpr int kScanCells = 1024;  // cells per chunk; 256 threads x 4 cells
+
+__device__ int32_t block_exclusive_256(int32_t v, int32_t* part) {
     const int tid = threadIdx.x;
     part[tid] = v;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
+    for (int off = 1; off < 256; off <<= 1) {
         const int32_t u = tid >= off ? part[tid - off] : 0;
         __syncthreads();
         part[tid] += u;
         __syncthreads();
     }
     const int32_t incl = part[tid];
-    *total = part[1023];
     __syncthreads();
     return incl - v;
 }
 
-// One work-group: bucket_start in key order (n_buckets + 1 entries),
-// tile_base[t] (first 64-atom tile of species t, T + 1 entries) and
-// perm_start[key] (first tile slot of the bucket in (species, cell) order).
-__global__ void __launch_bounds__(1024) k_scan(const int32_t* __restrict__ count, int n_cells, int T,
-                                               int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_fill,
-                                               int32_t* __restrict__ perm_start, int32_t* __restrict__ meta) {
-    __shared__ int32_t part[1024];
-    __shared__ int32_t s_tile_base[9];
-    const int tid = threadIdx.x;
-    const int n = n_cells * T;
-    {
-        const int chunk = (n + 1023) / 1024;
-        const int b = tid * chunk, e = min(b + chunk, n);
+__global__ void __launch_bounds__(256) k_scan_partials(const int32_t* __restrict__ count, int n_cells, int T,
+                                                       int32_t* __restrict__ chunk_sums) {
+    __shared__ int32_t red[256];
+    const int c0 = blockIdx.x * kScanCells + threadIdx.x * 4;
+    for (int t = 0; t <= T; ++t) {
         int32_t s = 0;
-        for (int i = b; i < e; ++i) s += count[i];
-        int32_t total;
-        int32_t run = block_exclusive(s, part, &total);
-        for (int i = b; i < e; ++i) {
-            bucket_start[i] = run;
-            bucket_fill[i] = 0;
-            run += count[i];
+        for (int c = c0; c < min(c0 + 4, n_cells); ++c) {
+            if (t < T)
+                s += count[c * T + t];
+            else
+                for (int u = 0; u < T; ++u) s += count[c * T + u];
         }
-        if (tid == 0) bucket_start[n] = total;
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) chunk_sums[blockIdx.x * 9 + t] = red[0];
+        __syncthreads();
     }
-    const int chunk = (n_cells + 1023) / 1024;
-    const int b = tid * chunk, e = min(b + chunk, n_cells);
+}
+
+// chunk_sums[k*9 + t] (t < T: species t, t = T: all) -> chunk_off[k*9 + t]:
+// species t: slot offset in (species, cell) order incl. tile padding; T: key order.
+__global__ void __launch_bounds__(256) k_scan_chunks(const int32_t* __restrict__ chunk_sums, int n_chunks, int T,
+                                                     int32_t* __restrict__ chunk_off, int32_t* __restrict__ meta,
+                                                     int32_t* __restrict__ bucket_start_end, int n_buckets) {
+    __shared__ int32_t part[256];
+    __shared__ int32_t s_carry;
     int32_t tiles = 0;
+    for (int t = 0; t <= T; ++t) {
+        if (threadIdx.x == 0) s_carry = 0;
+        __syncthreads();
+        for (int base = 0; base < n_chunks; base += 256) {
+            const int k = base + threadIdx.x;
+            const int32_t v = k < n_chunks ? chunk_sums[k * 9 + t] : 0;
+            const int32_t ex = block_exclusive_256(v, part);
+            const int32_t carry = s_carry;
+            if (k < n_chunks) chunk_off[k * 9 + t] = carry + ex + (t < T ? tiles * 64 : 0);
+            __syncthreads();
+            if (threadIdx.x == 255) s_carry = carry + ex + v;
+            __syncthreads();
+        }
+        const int32_t total = s_carry;
+        if (t < T) {
+            if (threadIdx.x == 0) meta[kMetaTileBase + t] = tiles;
+            tiles += (total + 63) / 64;
+        } else if (threadIdx.x == 0) {
+            bucket_start_end[n_buckets] = total;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) meta[kMetaTileBase + T] = tiles;
+}
+
+__global__ void __launch_bounds__(256) k_scan_final(const int32_t* __restrict__ count, int n_cells, int T,
+                                                    const int32_t* __restrict__ chunk_off,
+                                                    int32_t* __restrict__ bucket_start,
+                                                    int32_t* __restrict__ bucket_fill,
+                                                    int32_t* __restrict__ perm_start) {
+    __shared__ int32_t part[256];
+    const int k = blockIdx.x;
+    const int c0 = k * kScanCells + threadIdx.x * 4;
+    const int c1 = min(c0 + 4, n_cells);
+    // key order (cell-major, species-minor)
+    {
+        int32_t s = 0;
+        for (int c = c0; c < c1; ++c)
+            for (int u = 0; u < T; ++u) s += count[c * T + u];
+        int32_t run = block_exclusive_256(s, part) + chunk_off[k * 9 + T];
+        for (int c = c0; c < c1; ++c)
+            for (int u = 0; u < T; ++u) {
+                bucket_start[c * T + u] = run;
+                bucket_fill[c * T + u] = 0;
+                run += count[c * T + u];
+            }
+    }
+    // species-major order
     for (int t = 0; t < T; ++t) {
         int32_t s = 0;
-        for (int c = b; c < e; ++c) s += count[c * T + t];
-        int32_t total;
-        int32_t run = block_exclusive(s, part, &total) + tiles * 64;
-        for (int c = b; c < e; ++c) {
+        for (int c = c0; c < c1; ++c) s += count[c * T + t];
+        int32_t run = block_exclusive_256(s, part) + chunk_off[k * 9 + t];
+        for (int c = c0; c < c1; ++c) {
             perm_start[c * T + t] = run;
             run += count[c * T + t];
         }
-        if (tid == 0) s_tile_base[t] = tiles;
-        tiles += (total + 63) / 64;
     }
-    if (tid == 0) s_tile_base[T] = tiles;
-    __syncthreads();
-    if (tid <= T) meta[kMetaTileBase + tid] = s_tile_base[tid];
 }
 
 __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
@@ -146,9 +199,11 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
     bucket_atoms[bucket_start[k] + slot] = (int32_t)a;
 }
 
-// Sort each bucket by atom index, then place it into the tile permutation.
+// Sort each bucket by atom index, place it into the tile permutation and
+// store its positions contiguously in bucket order (w = atom index).
 __global__ void k_sort_place(const int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_atoms,
-                             const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm, int n_buckets) {
+                             const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm,
+                             const double* __restrict__ pos, double4* __restrict__ bucket_pos, int n_buckets) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_buckets) return;
     const int b = bucket_start[k], e = bucket_start[k + 1];
@@ -162,12 +217,15 @@ __global__ void k_sort_place(const int32_t* __restrict__ bucket_start, int32_t* 
         bucket_atoms[j + 1] = v;
     }
     const int p = perm_start[k];
-    for (int i = b; i < e; ++i) perm[p + (i - b)] = bucket_atoms[i];
+    for (int i = b; i < e; ++i) {
+        const int a = bucket_atoms[i];
+        perm[p + (i - b)] = a;
+        bucket_pos[i] = make_double4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], __longlong_as_double(a));
+    }
 }
 
-__device__ __forceinline__ double min_image(double d, double L, int per) {
-    return per ? d - L * rint(d / L) : d;
-}
+// Minimum image along one axis; Linv = 1/L on periodic axes, 0 otherwise.
+__device__ __forceinline__ double min_image(double d, double L, double Linv) { return d - L * rint(d * Linv); }
 
 // Four entries buffered in registers, written as one 64-byte group.
 // A group row (4 entries x 64 lanes) is 256 float4.
@@ -210,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
                                                       const double* __restrict__ pos,
                                                       const int32_t* __restrict__ key_of,
                                                       const int32_t* __restrict__ bucket_start,
-                                                      const int32_t* __restrict__ bucket_atoms, float rc_radial,
+                                                      const double4* __restrict__ bucket_pos, float rc_radial,
                                                       float rc_angular, NeighborLists nl,
                                                       int32_t* __restrict__ flags) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,12 +314,14 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
                 bucket = (fi.cell_base + (cx * ny + cy) * nz + cz) * T + t;
             }
             const int b = bucket_start[bucket], e = bucket_start[bucket + 1];
+            double4 q = b < e ? bucket_pos[b] : make_double4(0.0, 0.0, 0.0, 0.0);
             for (int k = b; k < e; ++k) {
-                const int j = bucket_atoms[k];
-                if (j == a) continue;
-                const double dx = min_image(pos[3 * j] - xi, fi.L[0], fi.per[0]);
-                const double dy = min_image(pos[3 * j + 1] - yi, fi.L[1], fi.per[1]);
-                const double dz = min_image(pos[3 * j + 2] - zi, fi.L[2], fi.per[2]);
+                const double4 cur = q;
+                if (k + 1 < e) q = bucket_pos[k + 1];
+                if ((int)__double_as_longlong(cur.w) == a) continue;
+                const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
+                const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
+                const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 if (r2 >= rc2r) continue;
                 if (r2 < 1e-8) overlap = true;
@@ -330,13 +390,17 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const doubl
     k_fill_i32<<<blocks_for(nl.n_pad, kBlock), kBlock, 0, s>>>(w.perm, nl.n_pad, -1);
     k_bin<<<blocks_for(n_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, species, n_atoms, T, w.key_of,
                                                         w.bucket_count, d_flags);
-    k_scan<<<1, 1024, 0, s>>>(w.bucket_count, n_cells, T, w.bucket_start, w.bucket_fill, w.perm_start, w.meta);
+    const int n_chunks = (n_cells + kScanCells - 1) / kScanCells;
+    k_scan_partials<<<n_chunks, 256, 0, s>>>(w.bucket_count, n_cells, T, w.chunk);
+    k_scan_chunks<<<1, 256, 0, s>>>(w.chunk, n_chunks, T, w.chunk + 9 * n_chunks, w.meta, w.bucket_start, n_buckets);
+    k_scan_final<<<n_chunks, 256, 0, s>>>(w.bucket_count, n_cells, T, w.chunk + 9 * n_chunks, w.bucket_start,
+                                         w.bucket_fill, w.perm_start);
     k_scatter<<<blocks_for(n_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill, w.bucket_atoms,
                                                             n_atoms);
     k_sort_place<<<blocks_for(n_buckets, kBlock), kBlock, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
-                                                                 w.perm, n_buckets);
+                                                                 w.perm, pos, w.bucket_pos, n_buckets);
     k_neighbors<<<blocks_for(nl.n_pad, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
-                                                               w.bucket_atoms, rc_radial, rc_angular, nl, d_flags);
+                                                               w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
     return hipGetLastError();
 }
 

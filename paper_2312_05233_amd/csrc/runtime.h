@@ -48,13 +48,13 @@ struct Ctx {
     int32_t* h_flags = nullptr;       // pinned
 
     // work buffers
-    DevBuf frames, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, perm_start;
-    DevBuf perm, tile_base, nbr, counts, per_atom, out, pos, species;
+    DevBuf frames, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, bucket_pos, perm_start;
+    DevBuf perm, tile_base, scan_chunks, nbr, counts, per_atom, out, pos, species;
     DevBuf spec_work, spec_series, spec_out;
 
     std::vector<DevBuf*> all_buffers() {
         return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
-                &bucket_atoms, &perm_start, &perm, &tile_base, &nbr, &counts, &per_atom, &out, &pos, &species,
+                &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
                 &spec_work, &spec_series, &spec_out, &counters};
     }
 
