@@ -291,6 +291,77 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
     for (float v : h)
         if (!std::isfinite(v)) return c->fail(TNEP_E_MODEL, "non-finite model parameter");
 
+    // matrix-core fragments (see DevModel)
+    auto rup = [](int x, int m) { return (x + m - 1) / m * m; };
+    const int Hp = rup(H, 32), Dp4 = rup(D, 4), Dp16 = rup(D, 16), Dp32 = rup(D, 32);
+    auto W = [&](int hd, int mu, int nu) -> double {
+        return (mu < H && nu < D) ? d->w0[hd][(size_t)mu * D + nu] : 0.0;
+    };
+    auto bf16_bits = [](float x) -> uint16_t {  // round to nearest even
+        uint32_t u;
+        std::memcpy(&u, &x, 4);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    };
+    auto bf16_value = [](uint16_t b) -> float {
+        uint32_t u = (uint32_t)b << 16;
+        float x;
+        std::memcpy(&x, &u, 4);
+        return x;
+    };
+    auto put_u16 = [&](const std::vector<uint16_t>& v) {
+        size_t off = h.size();
+        const size_t nf = (v.size() * 2 + 3) / 4;
+        h.resize(off + nf, 0.f);
+        std::memcpy(h.data() + off, v.data(), v.size() * 2);
+        while (h.size() % 64) h.push_back(0.f);
+        return off;
+    };
+    size_t o_f32_fwd[2] = {0, 0}, o_bf_fwd_hi[2] = {0, 0}, o_bf_fwd_lo[2] = {0, 0};
+    for (int hd = 0; hd < heads; ++hd) {
+        std::vector<double> f((size_t)(Hp / 16) * (Dp4 / 4) * 64);
+        for (int nt = 0; nt < Hp / 16; ++nt)
+            for (int ks = 0; ks < Dp4 / 4; ++ks)
+                for (int l = 0; l < 64; ++l)
+                    f[((size_t)nt * (Dp4 / 4) + ks) * 64 + l] = W(hd, 16 * nt + l % 16, 4 * ks + l / 16);
+        o_f32_fwd[hd] = put(f.data(), f.size());
+        std::vector<uint16_t> bh((size_t)(Hp / 16) * (Dp32 / 32) * 64 * 8), bl(bh.size());
+        for (int nt = 0; nt < Hp / 16; ++nt)
+            for (int kc = 0; kc < Dp32 / 32; ++kc)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 8; ++j) {
+                        const float x = (float)W(hd, 16 * nt + l % 16, 32 * kc + 8 * (l / 16) + j);
+                        const uint16_t hi = bf16_bits(x);
+                        const size_t idx = (((size_t)nt * (Dp32 / 32) + kc) * 64 + l) * 8 + j;
+                        bh[idx] = hi;
+                        bl[idx] = bf16_bits(x - bf16_value(hi));
+                    }
+        o_bf_fwd_hi[hd] = put_u16(bh);
+        o_bf_fwd_lo[hd] = put_u16(bl);
+    }
+    size_t o_f32_bwd, o_bf_bwd_hi, o_bf_bwd_lo;
+    {
+        std::vector<double> f((size_t)(Dp16 / 16) * (Hp / 4) * 64);
+        for (int kt = 0; kt < Dp16 / 16; ++kt)
+            for (int ns = 0; ns < Hp / 4; ++ns)
+                for (int l = 0; l < 64; ++l)
+                    f[((size_t)kt * (Hp / 4) + ns) * 64 + l] = W(0, 4 * ns + l / 16, 16 * kt + l % 16);
+        o_f32_bwd = put(f.data(), f.size());
+        std::vector<uint16_t> bh((size_t)(Dp16 / 16) * (Hp / 32) * 64 * 8), bl(bh.size());
+        for (int kt = 0; kt < Dp16 / 16; ++kt)
+            for (int nc = 0; nc < Hp / 32; ++nc)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 8; ++j) {
+                        const float x = (float)W(0, 32 * nc + 8 * (l / 16) + j, 16 * kt + l % 16);
+                        const uint16_t hi = bf16_bits(x);
+                        const size_t idx = (((size_t)kt * (Hp / 32) + nc) * 64 + l) * 8 + j;
+                        bh[idx] = hi;
+                        bl[idx] = bf16_bits(x - bf16_value(hi));
+                    }
+        o_bf_bwd_hi = put_u16(bh);
+        o_bf_bwd_lo = put_u16(bl);
+    }
+
     Model* m = new Model();
     m->ctx = c;
     m->shape = sh;
@@ -323,7 +394,13 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
         dm.w1[hd] = base + o_w1[src];
         dm.w0t[hd] = base + o_w0t[src];
         dm.b1[hd] = (float)d->b1[src];
+        dm.f32_fwd[hd] = base + o_f32_fwd[src];
+        dm.bf_fwd_hi[hd] = reinterpret_cast<const uint4*>(base + o_bf_fwd_hi[src]);
+        dm.bf_fwd_lo[hd] = reinterpret_cast<const uint4*>(base + o_bf_fwd_lo[src]);
     }
+    dm.f32_bwd = base + o_f32_bwd;
+    dm.bf_bwd_hi = reinterpret_cast<const uint4*>(base + o_bf_bwd_hi);
+    dm.bf_bwd_lo = reinterpret_cast<const uint4*>(base + o_bf_bwd_lo);
     dm.rc_radial = (float)d->rc_radial;
     dm.rc_angular = (float)d->rc_angular;
     dm.n_species = T;

@@ -28,6 +28,18 @@ struct DevModel {
     const float* b0[2];      // [H]
     const float* w1[2];      // [H]
     const float* w0t[2];     // [D][H] transposed copy (backward GEMM operand)
+    // Matrix-core operand fragments, one element (or 8 bf16) per lane:
+    //   f32_fwd[h]  [Hp/16][Dp4/4][64]   W0[16 nt + l%16][4 ks + l/16]
+    //   f32_bwd     [Dp16/16][Hp/4][64]  W0[4 ns + l/16][16 kt + l%16]   (tensor head)
+    //   bf_fwd_*[h] [Hp/16][Dp32/32][64] W0[16 nt + l%16][32 kc + 8 (l/16) + j], j < 8
+    //   bf_bwd_*    [Dp16/16][Hp/32][64] W0[32 nc + 8 (l/16) + j][16 kt + l%16]
+    // with Hp = H rounded up to 32, hi/lo = the bf16 rounding and its remainder.
+    const float* f32_fwd[2];
+    const float* f32_bwd;
+    const uint4* bf_fwd_hi[2];
+    const uint4* bf_fwd_lo[2];
+    const uint4* bf_bwd_hi;
+    const uint4* bf_bwd_lo;
     float b1[2];
     float rc_radial, rc_angular;
     int32_t n_species, n_hidden;
@@ -93,6 +105,9 @@ struct EvalLaunch {
 
 // Per-atom tensors (FP64, [n_atoms][3 or 9], batch atom order) of one model.
 bool eval_shape_supported(const Shape& s);
+// Whether the matrix-core hidden layer is compiled for this shape (else the
+// FP32 vector path runs whatever TNEP_OPT_MLP says).
+bool eval_matrix_supported(const Shape& s, int n_hidden);
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
                        const EvalLaunch& cfg, hipStream_t s);
 

@@ -13,6 +13,7 @@
 //      -r_ij (x) dU_i/dr_ij plus U^s_i delta (Sec. 2.3, Eq. polarizability-model).
 // Per-pair work is FP32; the atom terms are written as FP64 and summed per
 // frame by k_frame_reduce in a fixed order.
+#include "../../include/tnep.h"
 #include "internal.h"
 #include "tnep_math.h"
 
@@ -66,9 +67,172 @@ __device__ __forceinline__ int tile_species(const int32_t* tile_base, int T, int
     return __builtin_amdgcn_readfirstlane(ti);
 }
 
-// One lane per tile slot (atom); 4 wavefronts per work-group, no LDS.  The
-// coefficient blocks c[t_i][t] are wave-uniform and read with scalar loads.
-template <int NR, int NA, int KR, int KA, bool FOURB, int KIND>
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+// Order the wavefront's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Hidden layer of the 64 atoms of one wavefront on the matrix cores
+// (Sec. 2.1: one shared single-hidden-layer tanh network per head):
+//   X = Qs W0^T (64 x H), h = tanh(X - b0),
+//   scalar head: U^s = h w1 - b1;   tensor head: dU/dq = ((1 - h^2) * w1) W0 * s.
+// Qs, dU/dq and the hidden activations pass through a per-wavefront LDS tile;
+// W0 comes as per-lane operand fragments prepared at model creation.
+// MODE: TNEP_MLP_FP32_MFMA (v_mfma_f32_16x16x4_f32), TNEP_MLP_BF16_MFMA
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation) or TNEP_MLP_BF16X3_MFMA
+// (both operands split into bf16 hi + lo, three products hi*hi + hi*lo + lo*hi).
+template <int D, int KIND, int MODE>
+__device__ __forceinline__ void mlp_matrix(const DevModel& m, const float (&qs)[D], float (&dq)[D], float& Us,
+                                           float* wl, int lane) {
+    constexpr int Dp4 = (D + 3) / 4 * 4;
+    constexpr int Dp16 = (D + 15) / 16 * 16;
+    constexpr int Dp32 = (D + 31) / 32 * 32;
+    constexpr int LDQ = Dp32 + 4;
+    const int H = m.n_hidden;
+    const int Hp = (H + 31) / 32 * 32;
+    const int LDT = Hp + 4;
+    float* Qs = wl;
+    float* Tb = wl + 64 * LDQ;
+    const int r16 = lane & 15, g4 = lane >> 4;
+#pragma unroll
+    for (int k = 0; k < Dp32; ++k) Qs[lane * LDQ + k] = k < D ? qs[k] : 0.f;
+    wave_lds_sync();
+
+    auto split8 = [](const float* src, bf8v& hi, bf8v& lo) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float x = src[j];
+            const __bf16 h = (__bf16)x;
+            hi[j] = h;
+            lo[j] = (__bf16)(x - (float)h);
+        }
+    };
+    // acc[mt][i] = X[16 mt + 4 g4 + i][16 nt + r16]
+    auto forward = [&](int hd, int nt, f4v (&acc)[4]) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[mt] = f4v{0.f, 0.f, 0.f, 0.f};
+        if constexpr (MODE == TNEP_MLP_FP32_MFMA) {
+            const float* fr = m.f32_fwd[hd] + (size_t)nt * (Dp4 / 4) * 64 + lane;
+#pragma unroll
+            for (int ks = 0; ks < Dp4 / 4; ++ks) {
+                const float b = fr[ks * 64];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const float a = Qs[(16 * mt + r16) * LDQ + 4 * ks + g4];
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[mt], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kc = 0; kc < Dp32 / 32; ++kc) {
+                const size_t fi = ((size_t)nt * (Dp32 / 32) + kc) * 64 + lane;
+                const bf8v bh = __builtin_bit_cast(bf8v, m.bf_fwd_hi[hd][fi]);
+                const bf8v bl = __builtin_bit_cast(bf8v, m.bf_fwd_lo[hd][fi]);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    bf8v ah, al;
+                    split8(Qs + (16 * mt + r16) * LDQ + 32 * kc + 8 * g4, ah, al);
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[mt], 0, 0, 0);
+                    if constexpr (MODE == TNEP_MLP_BF16X3_MFMA) {
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[mt], 0, 0, 0);
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[mt], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+
+    if constexpr (KIND == 2) {
+        for (int nt = 0; nt < Hp / 16; ++nt) {
+            f4v acc[4];
+            forward(1, nt, acc);
+            const int n = 16 * nt + r16;
+            const bool nv = n < H;
+            const float b0n = nv ? m.b0[1][n] : 0.f, w1n = nv ? m.w1[1][n] : 0.f;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) Tb[(16 * mt + 4 * g4 + i) * LDT + n] = w1n * tanhf(acc[mt][i] - b0n);
+        }
+        wave_lds_sync();
+        float u = -m.b1[1];
+        for (int n = 0; n < H; ++n) u += Tb[lane * LDT + n];
+        Us = u;
+        wave_lds_sync();
+    }
+    for (int nt = 0; nt < Hp / 16; ++nt) {
+        f4v acc[4];
+        forward(0, nt, acc);
+        const int n = 16 * nt + r16;
+        const bool nv = n < H;
+        const float b0n = nv ? m.b0[0][n] : 0.f, w1n = nv ? m.w1[0][n] : 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float h = tanhf(acc[mt][i] - b0n);
+                Tb[(16 * mt + 4 * g4 + i) * LDT + n] = w1n * (1.f - h * h);
+            }
+    }
+    wave_lds_sync();
+    // dU/dq~[atom][k] = sum_n Tb[atom][n] W0[n][k], written over Qs
+#pragma unroll
+    for (int kt = 0; kt < Dp16 / 16; ++kt) {
+        f4v acc[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[mt] = f4v{0.f, 0.f, 0.f, 0.f};
+        if constexpr (MODE == TNEP_MLP_FP32_MFMA) {
+            const float* fr = m.f32_bwd + (size_t)kt * (Hp / 4) * 64 + lane;
+            for (int ns = 0; ns < Hp / 4; ++ns) {
+                const float b = fr[ns * 64];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const float a = Tb[(16 * mt + r16) * LDT + 4 * ns + g4];
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[mt], 0, 0, 0);
+                }
+            }
+        } else {
+            for (int nc = 0; nc < Hp / 32; ++nc) {
+                const size_t fi = ((size_t)kt * (Hp / 32) + nc) * 64 + lane;
+                const bf8v bh = __builtin_bit_cast(bf8v, m.bf_bwd_hi[fi]);
+                const bf8v bl = __builtin_bit_cast(bf8v, m.bf_bwd_lo[fi]);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    bf8v ah, al;
+                    split8(Tb + (16 * mt + r16) * LDT + 32 * nc + 8 * g4, ah, al);
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[mt], 0, 0, 0);
+                    if constexpr (MODE == TNEP_MLP_BF16X3_MFMA) {
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[mt], 0, 0, 0);
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[mt], 0, 0, 0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Qs[(16 * mt + 4 * g4 + i) * LDQ + 16 * kt + r16] = acc[mt][i];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < D; ++k) dq[k] = Qs[lane * LDQ + k] * m.scaler[k];
+}
+
+// LDS floats per wavefront used by mlp_matrix.
+__host__ __device__ constexpr int mlp_lds_floats(int D, int H) {
+    return 64 * (((D + 31) / 32 * 32 + 4) + ((H + 31) / 32 * 32 + 4));
+}
+
+// One lane per tile slot (atom).  The coefficient blocks c[t_i][t] are
+// wave-uniform and read with scalar loads.  MODE selects the hidden layer:
+// FP32 vector ALU (no LDS) or one of the matrix-core variants (LDS tile per
+// wavefront).  Padding lanes run with empty neighbour lists and store nothing.
+template <int NR, int NA, int KR, int KA, bool FOURB, int KIND, int MODE>
 __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, double* __restrict__ per_atom) {
     constexpr int D = NR + 4 * NA + (FOURB ? NA : 0);
     constexpr int NT = KIND == 1 ? 3 : 9;
@@ -78,7 +242,6 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     const int lane = (int)(p & 63);
     if (tile >= nl.meta[kMetaTileBase + T]) return;
     const int a = nl.perm[p];
-    if (a < 0) return;
     const int ti = tile_species(nl.meta + kMetaTileBase, T, tile);
     const float rcR_inv = 1.f / m.rc_radial, rcA_inv = 1.f / m.rc_angular;
     const float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
@@ -176,39 +339,45 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 #pragma unroll
     for (int v = 0; v < D; ++v) qs[v] *= m.scaler[v];
 
-    const int H = m.n_hidden;
     float Us = 0.f;
-    if constexpr (KIND == 2) {
-        const float* __restrict__ w0 = m.w0[1];
-        const float* __restrict__ b0 = m.b0[1];
-        const float* __restrict__ w1 = m.w1[1];
-        Us = -m.b1[1];
-        for (int mu = 0; mu < H; ++mu) {
-            float x = -b0[mu];
-#pragma unroll
-            for (int v = 0; v < D; ++v) x += w0[mu * D + v] * qs[v];
-            Us += w1[mu] * tanhf(x);
-        }
-    }
     float dq[D];
+    if constexpr (MODE == TNEP_MLP_FP32_VALU) {
+        const int H = m.n_hidden;
+        if constexpr (KIND == 2) {
+            const float* __restrict__ w0 = m.w0[1];
+            const float* __restrict__ b0 = m.b0[1];
+            const float* __restrict__ w1 = m.w1[1];
+            Us = -m.b1[1];
+            for (int mu = 0; mu < H; ++mu) {
+                float x = -b0[mu];
 #pragma unroll
-    for (int v = 0; v < D; ++v) dq[v] = 0.f;
-    {
-        const float* __restrict__ w0 = m.w0[0];
-        const float* __restrict__ b0 = m.b0[0];
-        const float* __restrict__ w1 = m.w1[0];
-        for (int mu = 0; mu < H; ++mu) {
-            float x = -b0[mu];
-#pragma unroll
-            for (int v = 0; v < D; ++v) x += w0[mu * D + v] * qs[v];
-            const float h = tanhf(x);
-            const float t = w1[mu] * (1.f - h * h);
-#pragma unroll
-            for (int v = 0; v < D; ++v) dq[v] += t * w0[mu * D + v];
+                for (int v = 0; v < D; ++v) x += w0[mu * D + v] * qs[v];
+                Us += w1[mu] * tanhf(x);
+            }
         }
-    }
 #pragma unroll
-    for (int v = 0; v < D; ++v) dq[v] *= m.scaler[v];
+        for (int v = 0; v < D; ++v) dq[v] = 0.f;
+        {
+            const float* __restrict__ w0 = m.w0[0];
+            const float* __restrict__ b0 = m.b0[0];
+            const float* __restrict__ w1 = m.w1[0];
+            for (int mu = 0; mu < H; ++mu) {
+                float x = -b0[mu];
+#pragma unroll
+                for (int v = 0; v < D; ++v) x += w0[mu * D + v] * qs[v];
+                const float h = tanhf(x);
+                const float t = w1[mu] * (1.f - h * h);
+#pragma unroll
+                for (int v = 0; v < D; ++v) dq[v] += t * w0[mu * D + v];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < D; ++v) dq[v] *= m.scaler[v];
+    } else {
+        extern __shared__ float lds[];
+        float* wl = lds + (threadIdx.x >> 6) * mlp_lds_floats(D, m.n_hidden);
+        mlp_matrix<D, KIND, MODE>(m, qs, dq, Us, wl, lane);
+    }
 
     // G_nlm = dU/dA_nlm, stored over A.
 #pragma unroll
@@ -324,6 +493,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
         }
     }
 
+    if (a < 0) return;
     double* out = per_atom + (int64_t)a * NT;
     if constexpr (KIND == 1) {
 #pragma unroll
@@ -365,24 +535,70 @@ __global__ void __launch_bounds__(256) k_frame_reduce(const FrameInfo* __restric
     if (lane < nt) out[(int64_t)f * nt + lane] = part[lane][0];
 }
 
-template <int NR, int NA, int KR, int KA, bool FOURB, int KIND>
+template <int NR, int NA, int KR, int KA, bool FOURB, int KIND, int MODE>
 hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom, hipStream_t s) {
-    const unsigned grid = (unsigned)((nl.n_pad + 255) / 256);
-    k_eval<NR, NA, KR, KA, FOURB, KIND><<<grid, 256, 0, s>>>(m, nl, per_atom);
+    constexpr int D = NR + 4 * NA + (FOURB ? NA : 0);
+    if constexpr (MODE == TNEP_MLP_FP32_VALU) {
+        const unsigned grid = (unsigned)((nl.n_pad + 255) / 256);
+        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, 256, 0, s>>>(m, nl, per_atom);
+    } else {
+        // two wavefronts per work-group keep the LDS tiles at <= 2 x 27 KB
+        const unsigned grid = (unsigned)((nl.n_pad + 127) / 128);
+        const size_t lds = sizeof(float) * 2 * (size_t)mlp_lds_floats(D, m.n_hidden);
+        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom);
+    }
     return hipGetLastError();
+}
+
+template <int NR, int NA, int KR, int KA, bool FOURB, int KIND>
+hipError_t launch_mode(int mode, bool matrix, const DevModel& m, const NeighborLists& nl, double* per_atom,
+                       hipStream_t s) {
+    if (matrix) {
+        if (mode == TNEP_MLP_FP32_MFMA)
+            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, s);
+        if (mode == TNEP_MLP_BF16_MFMA)
+            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, s);
+        if (mode == TNEP_MLP_BF16X3_MFMA)
+            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, s);
+    }
+    return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, s);
+}
+
+template <int NR, int NA, int KR, int KA, bool FOURB, bool MX>
+hipError_t dispatch(const Shape& shape, int mode, bool matrix, const DevModel& m, const NeighborLists& nl,
+                    double* per_atom, hipStream_t s) {
+    if constexpr (MX) {
+        if (shape.kind == 1) return launch_mode<NR, NA, KR, KA, FOURB, 1>(mode, matrix, m, nl, per_atom, s);
+        return launch_mode<NR, NA, KR, KA, FOURB, 2>(mode, matrix, m, nl, per_atom, s);
+    } else {
+        if (shape.kind == 1) return launch_t<NR, NA, KR, KA, FOURB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, s);
+        return launch_t<NR, NA, KR, KA, FOURB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, s);
+    }
 }
 
 }  // namespace
 
-#define TNEP_SHAPES(X)   \
-    X(5, 5, 9, 9, true)  \
-    X(5, 5, 9, 9, false) \
-    X(7, 5, 9, 9, false) \
-    X(7, 5, 9, 9, true)
+// Compiled descriptor shapes (radial functions, angular functions, radial and
+// angular Chebyshev terms, four-body) and whether the matrix-core hidden
+// layers are compiled for them.
+#define TNEP_SHAPES(X)         \
+    X(5, 5, 9, 9, true, true)   \
+    X(5, 5, 9, 9, false, false) \
+    X(7, 5, 9, 9, false, true)  \
+    X(7, 5, 9, 9, true, false)
 
 bool eval_shape_supported(const Shape& s) {
-#define X(NR_, NA_, KR_, KA_, FB_) \
+#define X(NR_, NA_, KR_, KA_, FB_, MX_) \
     if (s.nr == NR_ && s.na == NA_ && s.kr == KR_ && s.ka == KA_ && (bool)s.four_body == FB_) return true;
+    TNEP_SHAPES(X)
+#undef X
+    return false;
+}
+
+bool eval_matrix_supported(const Shape& s, int n_hidden) {
+    if (n_hidden > 64) return false;
+#define X(NR_, NA_, KR_, KA_, FB_, MX_) \
+    if (s.nr == NR_ && s.na == NA_ && s.kr == KR_ && s.ka == KA_ && (bool)s.four_body == FB_) return MX_;
     TNEP_SHAPES(X)
 #undef X
     return false;
@@ -390,14 +606,12 @@ bool eval_shape_supported(const Shape& s) {
 
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
                        const EvalLaunch& cfg, hipStream_t s) {
-    (void)cfg;
     if (nl.n_pad == 0) return hipSuccess;
-#define X(NR_, NA_, KR_, KA_, FB_)                                                                         \
-    if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                         \
-        (bool)shape.four_body == FB_) {                                                                    \
-        if (shape.kind == 1) return launch_t<NR_, NA_, KR_, KA_, FB_, 1>(m, nl, per_atom, s);               \
-        return launch_t<NR_, NA_, KR_, KA_, FB_, 2>(m, nl, per_atom, s);                                    \
-    }
+    const bool matrix = cfg.mlp_mode != TNEP_MLP_FP32_VALU && eval_matrix_supported(shape, m.n_hidden);
+#define X(NR_, NA_, KR_, KA_, FB_, MX_)                                                             \
+    if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                \
+        (bool)shape.four_body == FB_)                                                             \
+        return dispatch<NR_, NA_, KR_, KA_, FB_, MX_>(shape, cfg.mlp_mode, matrix, m, nl, per_atom, s);
     TNEP_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

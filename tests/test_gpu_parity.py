@@ -211,3 +211,29 @@ def test_spectrum_edge_sizes(gpu_lib, ctx):
                                      subtract_mean=bool(flags & 1))
         assert spectrum_error(S, Sr) < SPECTRUM_TOL
         assert spectrum_error(acf, Cr) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# hidden layer on the matrix cores: FP32, BF16 and split-BF16 against the oracle
+
+@pytest.mark.parametrize("name,frames", [("water_dipole_small", "water"), ("water_polarizability", "water"),
+                                         ("perovskite_susceptibility", "perovskite")])
+def test_hidden_layer_precision_modes(gpu_lib, name, frames):
+    m = synth.model(name)
+    fr = synth.water_small(3, seed=31) if frames == "water" else synth.perovskite(2, n_rep=6, seed=32)
+    ref, pa = oracle.eval_frames(m, fr, per_atom=True)
+    errs = {}
+    for mode in (gpu_lib.MLP_FP32_VALU, gpu_lib.MLP_FP32_MFMA, gpu_lib.MLP_BF16_MFMA, gpu_lib.MLP_BF16X3_MFMA):
+        c = gpu_lib.Context(0)
+        c.set_option(gpu_lib.OPT_MLP, mode)
+        mdl = gpu_lib.Model(c, m)
+        out = (gpu_lib.tnep_eval_dipole if m.kind == 1 else gpu_lib.tnep_eval_polarizability)(c, mdl, fr)
+        errs[mode] = frame_errors(out, ref, pa, fr.offsets).max()
+        mdl.close()
+        c.close()
+    print(name, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert errs[gpu_lib.MLP_FP32_VALU] <= TENSOR_TOL
+    assert errs[gpu_lib.MLP_FP32_MFMA] <= TENSOR_TOL
+    # bf16 operands (8-bit mantissa) cannot meet 1e-5; the split form must stay within 10x of it
+    assert errs[gpu_lib.MLP_BF16_MFMA] < 5e-2
+    assert errs[gpu_lib.MLP_BF16X3_MFMA] < 1e-4
