@@ -283,18 +283,30 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
         }
         return;
     }
-    const FrameInfo& fi = frames[frame_of[a]];
+    const FrameInfo fi = frames[frame_of[a]];  // by value: kept in registers across the stores below
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
     // entry (row r) of this lane: lane_base + (r / 4) * 256 + r % 4
     float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
     int ix = 0, iy = 0, iz = 0;
     const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
+    // distances from the atom to the lower / upper faces of its cell (cell list)
+    double lo_x = 0, hi_x = 0, lo_y = 0, hi_y = 0, lo_z = 0, hi_z = 0;
     if (fi.mode == 1) {
         const int local = key_of[a] / T - fi.cell_base;
         iz = local % nz;
         iy = (local / nz) % ny;
         ix = local / (nz * ny);
+        const double hx = fi.L[0] / nx, hy = fi.L[1] / ny, hz = fi.L[2] / nz;
+        const double wx = xi - fi.L[0] * floor(xi * fi.Linv[0]);
+        const double wy = yi - fi.L[1] * floor(yi * fi.Linv[1]);
+        const double wz = zi - fi.L[2] * floor(zi * fi.Linv[2]);
+        lo_x = fmax(wx - ix * hx, 0.0);
+        hi_x = fmax((ix + 1) * hx - wx, 0.0);
+        lo_y = fmax(wy - iy * hy, 0.0);
+        hi_y = fmax((iy + 1) * hy - wy, 0.0);
+        lo_z = fmax(wz - iz * hz, 0.0);
+        hi_z = fmax((iz + 1) * hz - wz, 0.0);
     }
     bool overlap = false;
     for (int t = 0; t < T; ++t) {
@@ -308,9 +320,15 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
         for (int vb = 0; vb < n_visit; ++vb) {
             int bucket = fi.cell_base * T + t;
             if (fi.mode == 1) {
-                const int cx = (ix + vb / 9 - 1 + nx) % nx;
-                const int cy = (iy + (vb / 3) % 3 - 1 + ny) % ny;
-                const int cz = (iz + vb % 3 - 1 + nz) % nz;
+                const int ox = vb / 9 - 1, oy = (vb / 3) % 3 - 1, oz = vb % 3 - 1;
+                // skip cells whose nearest point is beyond the radial cutoff
+                const double gx = ox < 0 ? lo_x : (ox > 0 ? hi_x : 0.0);
+                const double gy = oy < 0 ? lo_y : (oy > 0 ? hi_y : 0.0);
+                const double gz = oz < 0 ? lo_z : (oz > 0 ? hi_z : 0.0);
+                if (gx * gx + gy * gy + gz * gz >= rc2r) continue;
+                const int cx = (ix + ox + nx) % nx;
+                const int cy = (iy + oy + ny) % ny;
+                const int cz = (iz + oz + nz) % nz;
                 bucket = (fi.cell_base + (cx * ny + cy) * nz + cz) * T + t;
             }
             const int b = bucket_start[bucket], e = bucket_start[bucket + 1];
