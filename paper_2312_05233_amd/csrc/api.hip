@@ -505,6 +505,7 @@ extern "C" int tnep_spectrum(tnep_ctx* ctx, const tnep_spectrum_args* a, double*
     if (a->location != TNEP_HOST && a->location != TNEP_DEVICE) return c->fail(TNEP_E_INVALID, "bad location");
     if (a->n_steps > ((int64_t)1 << 26)) return c->fail(TNEP_E_INVALID, "n_steps above 2^26");
     (void)hipSetDevice(c->device);
+    (void)hipGetLastError();  // launch checks below must only see this call's launches
     SpectrumPlan p{};
     p.kind = a->kind;
     p.window = a->window;

@@ -100,6 +100,7 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
     const int F = fr.n_frames;
     if (F == 0) return TNEP_OK;
     (void)hipSetDevice(c->device);
+    (void)hipGetLastError();  // launch checks below must only see this call's launches
     HostMeta meta;
     int e = fetch_meta(c, fr, meta);
     if (e) return e;

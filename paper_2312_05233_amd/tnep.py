@@ -302,3 +302,42 @@ def tnep_spectrum(ctx: Context, series, kind, dt_fs, max_lag, window=WIN_HANN, f
     a.series = _ptr(series)
     ctx.check(lib.tnep_spectrum(ctx.h, C.byref(a), _ptr(freq), _ptr(intensity), _ptr(acf)))
     return freq, intensity, acf
+
+
+class Server:
+    """Continuous-batching server on a context (tnep_server_*).  Requests are
+    host numpy frames; their buffers stay referenced until wait()."""
+
+    def __init__(self, ctx: Context, budget_bytes: int = 0, max_batch_atoms: int = 0, max_inflight: int = 0):
+        self.ctx = ctx
+        o = ServerOpts()
+        o.mem_budget_bytes, o.max_batch_atoms, o.max_inflight = budget_bytes, max_batch_atoms, max_inflight
+        ctx.check(lib.tnep_server_start(ctx.h, C.byref(o)))
+        self._live = {}
+
+    def submit(self, model: Model, frames, out=None):
+        fd = frames_desc(frames, HOST)
+        nt = 3 if model.kind == KIND_DIPOLE else 9
+        if out is None:
+            out = np.zeros((fd.n_frames, nt))
+        t = C.c_uint64()
+        e = lib.tnep_submit(self.ctx.h, model.h, model.kind, C.byref(fd), _ptr(out), C.byref(t))
+        if e:
+            raise TnepError(e, "submit rejected")
+        self._live[t.value] = (fd, out)
+        return t.value
+
+    def wait(self, ticket):
+        """(status, latency_s, output array)."""
+        st, lat = C.c_int32(), C.c_double()
+        self.ctx.check(lib.tnep_wait(self.ctx.h, ticket, C.byref(st), C.byref(lat)))
+        fd, out = self._live.pop(ticket)
+        return st.value, lat.value, out
+
+    def stats(self):
+        r, l, a, p = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_uint64()
+        self.ctx.check(lib.tnep_server_stats(self.ctx.h, C.byref(r), C.byref(l), C.byref(a), C.byref(p)))
+        return {"requests": r.value, "launches": l.value, "atom_frames": a.value, "peak_bytes": p.value}
+
+    def stop(self):
+        self.ctx.check(lib.tnep_server_stop(self.ctx.h))
