@@ -94,6 +94,192 @@ def cpu_baseline(frames, md, mp, n_sample, gpu_mu, gpu_alpha):
     }, float(err_mu), float(err_al)
 
 
+def _timed(fn, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_perovskite(args):
+    """BaZrO3-like 12x12x12 supercell (8,640 atoms), batches of 64 frames,
+    susceptibility model (H = 50); FP32 vs matrix-core hidden layers, with the
+    error of each against the FP64 oracle on two frames."""
+    import torch
+
+    import oracle
+    from paper_2312_05233_amd import tnep
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import frame_errors
+
+    frames = synth.perovskite(64)
+    m = synth.model("perovskite_susceptibility")
+    dfr = tnep.DeviceFrames(frames)
+    out = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
+    ref, pa = oracle.eval_frames(m, frames.subset([0, 1]), per_atom=True)
+    modes = {}
+    for mode, name in ((tnep.MLP_FP32_VALU, "fp32_valu"), (tnep.MLP_FP32_MFMA, "fp32_mfma"),
+                       (tnep.MLP_BF16_MFMA, "bf16_mfma"), (tnep.MLP_BF16X3_MFMA, "bf16x3_mfma")):
+        ctx = tnep.Context(0)
+        ctx.set_option(tnep.OPT_MLP, mode)
+        gm = tnep.Model(ctx, m)
+        t = _timed(lambda: tnep.tnep_eval_polarizability(ctx, gm, dfr, out), args.steps, args.warmup)
+        err = frame_errors(out[:2].cpu().numpy(), ref.reshape(2, 9), pa, frames.subset([0, 1]).offsets).max()
+        modes[name] = {"atom_frames_per_s": frames.n_atoms / t, "ms_per_batch": 1e3 * t, "max_frame_error": float(err)}
+        gm.close()
+        ctx.close()
+    print(json.dumps({"metric": "TNEP atom-frames/s (susceptibility) at FP32 tol", "value": modes["fp32_valu"][
+        "atom_frames_per_s"], "unit": "atom-frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "dtype": "f32", "data": "synthetic", "config": {
+            "workload": "perovskite Ba/Zr/O 12x12x12 (8640 atoms, a=4.19 A, sigma 0.08 A), batch of 64 frames, "
+                        "susceptibility model rc 7/5 A, n_max 6/4, H=50"}, "hidden_layer_modes": modes}), flush=True)
+
+
+def bench_molecules(args):
+    """8192 ragged vacuum molecules (20-80 atoms, C/H/N/O/F), dipole +
+    polarizability heads in one call (one launch per model per batch)."""
+    import torch
+
+    from paper_2312_05233_amd import tnep
+
+    frames = synth.molecules(8192)
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    ctx = tnep.Context(0)
+    gd, gp = tnep.Model(ctx, md), tnep.Model(ctx, mp)
+    dfr = tnep.DeviceFrames(frames)
+    mu = torch.zeros((frames.n_frames, 3), dtype=torch.float64, device="cuda")
+    al = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
+    t = _timed(lambda: tnep.tnep_eval_dipole_polarizability(ctx, gd, gp, dfr, mu, al), args.steps, args.warmup)
+    print(json.dumps({"metric": "TNEP atom-frames/s (dipole+polarizability) at FP32 tol", "value": frames.n_atoms / t,
+                      "unit": "atom-frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": 1e3 * t, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "8192 vacuum molecules, 20-80 atoms (%d atoms), C/H/N/O/F, dipole + "
+                                             "polarizability" % frames.n_atoms}}), flush=True)
+
+
+def _serving_requests(n_requests, seed=4):
+    """Request mix: half water boxes of 64..8000 H2O (consecutive OU frames,
+    species O=3, H=1 of the five-species models), half batches of vacuum
+    molecules; each a dipole or polarizability evaluation of 1-64 frames."""
+    rng = np.random.default_rng(seed)
+    mols = synth.molecules(4096, seed=seed + 1)
+    sides = [4, 6, 8, 10, 16, 20]
+    reqs = []
+    for k in range(n_requests):
+        kind = 1 + int(rng.integers(0, 2))
+        nf = int(rng.integers(1, 65))
+        if k % 2 == 0:
+            n = int(rng.choice(sides))
+            pos, spc, cell = synth.water_box(n, 3.105 * n, seed=seed * 1000 + k, o_species=3, h_species=1)
+            fr = synth.ou_trajectory(pos, spc, cell, nf, seed=k)
+        else:
+            start = int(rng.integers(0, 4096 - nf))
+            fr = mols.subset(range(start, start + nf))
+        reqs.append((kind, fr))
+    return reqs
+
+
+def bench_serving(args):
+    """Poisson request stream through the continuous-batching server versus
+    the plain per-frame path (one synchronous call per frame, FIFO)."""
+    import threading
+
+    from paper_2312_05233_amd import tnep
+
+    reqs = _serving_requests(args.requests)
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    total_af = sum(fr.n_atoms for _, fr in reqs)
+
+    def run_server(qps, seed):
+        ctx = tnep.Context(0, budget_bytes=32 << 30)
+        gm = {1: tnep.Model(ctx, md), 2: tnep.Model(ctx, mp)}
+        srv = tnep.Server(ctx, budget_bytes=32 << 30, max_batch_atoms=1 << 19, max_inflight=3)
+        # warm-up: one request of each kind
+        for kind, fr in reqs[:4]:
+            srv.wait(srv.submit(gm[kind], fr))
+        rng = np.random.default_rng(seed)
+        lat = [None] * len(reqs)
+        tickets = [None] * len(reqs)
+        ready = threading.Semaphore(0)
+
+        def waiter():
+            for i in range(len(reqs)):
+                ready.acquire()
+                st, l, _ = srv.wait(tickets[i])
+                lat[i] = l if st == 0 else float("nan")
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        t_next = t0
+        for i, (kind, fr) in enumerate(reqs):
+            if qps:
+                t_next += rng.exponential(1.0 / qps)
+                dt = t_next - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            tickets[i] = srv.submit(gm[kind], fr)
+            ready.release()
+        th.join()
+        wall = time.perf_counter() - t0
+        stats = srv.stats()
+        srv.stop()
+        ctx.close()
+        lat = np.array(lat) * 1e3
+        return {"qps": qps, "atom_frames_per_s": total_af / wall, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "launches": stats["launches"],
+                "peak_device_bytes": stats["peak_bytes"]}
+
+    def run_plain(qps, seed):
+        """Single FIFO worker, one synchronous evaluation call per frame."""
+        ctx = tnep.Context(0)
+        gm = {1: tnep.Model(ctx, md), 2: tnep.Model(ctx, mp)}
+        for kind, fr in reqs[:4]:
+            (tnep.tnep_eval_dipole if kind == 1 else tnep.tnep_eval_polarizability)(ctx, gm[kind], fr)
+        rng = np.random.default_rng(seed)
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, len(reqs))) if qps else np.zeros(len(reqs))
+        t0 = time.perf_counter()
+        lat = []
+        for (kind, fr), ta in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            f = tnep.tnep_eval_dipole if kind == 1 else tnep.tnep_eval_polarizability
+            for k in range(fr.n_frames):
+                f(ctx, gm[kind], fr.subset([k]))
+            lat.append(time.perf_counter() - t0 - ta)
+        wall = time.perf_counter() - t0
+        ctx.close()
+        lat = np.array(lat) * 1e3
+        return {"qps": qps, "atom_frames_per_s": total_af / wall, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99))}
+
+    sat = run_server(0, 1)
+    sat_qps = len(reqs) / (total_af / sat["atom_frames_per_s"])
+    plain_sat = run_plain(0, 1)
+    loads = []
+    for frac in (0.25, 0.5, 0.8, 0.95):
+        loads.append(dict(run_server(frac * sat_qps, 10 + int(100 * frac)), load=frac))
+    plain_qps = len(reqs) / (total_af / plain_sat["atom_frames_per_s"])
+    plain_half = dict(run_plain(0.5 * plain_qps, 60), load=0.5)
+    print(json.dumps({
+        "metric": "TNEP atom-frames/s (dipole+polarizability) at FP32 tol; p50/p99 request latency",
+        "value": sat["atom_frames_per_s"], "unit": "atom-frames/s", "n_gpus": 1, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving: Poisson arrivals, %d requests (water boxes 192-24000 atoms / vacuum "
+                               "molecules, 1-64 frames each, dipole or polarizability), 32 GB budget" % len(reqs),
+                   "atom_frames": total_af},
+        "saturation": sat, "saturation_qps": sat_qps, "poisson_loads": loads,
+        "plain_per_frame_path": {"saturation": plain_sat, "at_half_load": plain_half}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,9 +288,12 @@ def main():
     ap.add_argument("--frames", type=int, default=2000)
     ap.add_argument("--max-lag", type=int, default=500)
     ap.add_argument("--cpu-frames", type=int, default=32)
+    ap.add_argument("--requests", type=int, default=200, help="serving workload: number of requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mlp", type=int, default=None, help="TNEP_MLP_* mode of the hidden layer")
     ap.add_argument("--atoms-per-block", type=int, default=None)
+    ap.add_argument("--workload", default="water", choices=["water", "perovskite", "molecules", "serving"],
+                    help="water: the headline line; the others print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -126,6 +315,10 @@ def main():
         return
 
     from paper_2312_05233_amd import tnep
+
+    if args.workload != "water":
+        {"perovskite": bench_perovskite, "molecules": bench_molecules, "serving": bench_serving}[args.workload](args)
+        return
 
     dev = torch.device("cuda:0")
     frames = synth.water_trajectory(args.frames)
