@@ -8,7 +8,7 @@
  *   - tnep_eval_polarizability  : Sec. 2.3, Eq. (polarizability-model)
  *       alpha^{uv} = sum_i U_i delta^{uv} - sum_i sum_{j != i} r_ij^u dU_i/dr_ij^v
  *     (the same form serves the susceptibility chi)
- *   - tnep_spectrum             : Secs. 2.5-2.6, IR lineshape M(w) with the
+ *   - tnep_spectrum             : Secs. 2.6-2.7, IR lineshape M(w) with the
  *     classical w^2 prefactor (Eq. ir-intensity) and the Raman lineshape
  *     L(w) (Eq. raman-lineshape) with its isotropic / anisotropic split
  *     (Eq. raman-lineshape-isotropic-anisotropic) or a polarisation

@@ -5,7 +5,8 @@ import this package.  It shares no code with the HIP library.
 
 * tensor evaluation (Eqs. virial, mu, polarizability-model) lives in
   ``tnep_oracle.c`` and is reached through ctypes;
-* the spectrum step (Secs. 2.5-2.6: time-origin-averaged correlation
+* the spectrum step (Sec. 2.6 The IR intensity, Sec. 2.7 The Raman
+  intensity: time-origin-averaged correlation
   functions, their Fourier transform, the omega^2 IR prefactor and the
   isotropic/anisotropic Raman split) is written here in numpy as plain
   lag sums and cosine sums.
@@ -263,7 +264,7 @@ def eval_frames(m, frames, per_atom=False):
 
 
 # -------------------------------------------------------------------------
-# Spectrum step (Secs. 2.5-2.6), numpy.
+# Spectrum step (Secs. 2.6-2.7), numpy.
 
 SPEED_OF_LIGHT_CM_PER_FS = 2.99792458e-5
 

@@ -1,7 +1,7 @@
 // C ABI of libtnep (declared in include/tnep.h): contexts, resident models,
 // batched evaluation of the TNEP dipole (Sec. 2.2, Eq. mu) and
 // polarizability / susceptibility (Sec. 2.3, Eq. polarizability-model), and
-// spectra (Secs. 2.5-2.6).
+// spectra (Sec. 2.6 The IR intensity, Sec. 2.7 The Raman intensity).
 #include <algorithm>
 #include <climits>
 #include <cmath>

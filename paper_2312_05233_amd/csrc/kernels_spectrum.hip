@@ -1,6 +1,7 @@
-// Spectra from tensor time series on gfx950, all FP64 (Secs. 2.5-2.6).
+// Spectra from tensor time series on gfx950, all FP64 (Sec. 2.6 The IR
+// intensity, Sec. 2.7 The Raman intensity).
 //
-// Correlation functions are averages over time origins (Sec. 2.5):
+// Correlation functions are averages over time origins (Sec. 2.6):
 //   C_xy(tau) = 1/(N - tau) sum_{t=0}^{N-1-tau} x(t) y(t + tau).
 // They are computed through zero-padded FFTs of length P >= 2N (no circular
 // wrap-around): IFFT(conj(X) Y)[tau] / P = sum_t x(t) y(t + tau).

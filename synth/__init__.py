@@ -9,7 +9,8 @@ the method's arithmetic.  It builds
 * models: TNEP dipole / polarizability parameter sets drawn from a seed.
 
 The workloads are stand-ins for the paper's water, BaZrO3 and molecular
-data sets (Sec. 3 and Sec. 4), which are not available here.
+data sets (Sec. 3 Performance evaluation and Sec. 4 Applications), which are
+not available here.
 """
 from __future__ import annotations
 
