@@ -292,6 +292,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mlp", type=int, default=None, help="TNEP_MLP_* mode of the hidden layer")
     ap.add_argument("--atoms-per-block", type=int, default=None)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
     ap.add_argument("--workload", default="water", choices=["water", "perovskite", "molecules", "serving"],
                     help="water: the headline line; the others print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -330,6 +331,8 @@ def main():
         ctx.set_option(tnep.OPT_MLP, args.mlp)
     if args.atoms_per_block is not None:
         ctx.set_option(tnep.OPT_ATOMS_PER_BLOCK, args.atoms_per_block)
+    if not args.no_autotune:
+        ctx.set_option(tnep.OPT_AUTOTUNE, 1)  # tuned during the warm-up step
     gd, gp = tnep.Model(ctx, md), tnep.Model(ctx, mp)
     dfr = tnep.DeviceFrames(frames)
     mu = torch.zeros((F, 3), dtype=torch.float64, device=dev)
@@ -346,7 +349,7 @@ def main():
             f, s, c = spec[name]
             tnep.tnep_spectrum(ctx, ser, kind, 1.0, M, freq=f, intensity=s, acf=c)
 
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 0 if args.no_autotune else 1)):
         step()
     ctx.set_option(tnep.OPT_TIMING, 1)
     ctx.reset_timing()
@@ -409,6 +412,7 @@ def main():
             "mean_angular_neighbors": n_ang,
         },
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+        "autotune": ctx.autotune_report(),
     }
     if not args.no_cpu_baseline:
         cb, e_mu, e_al = cpu_baseline(frames, md, mp, min(args.cpu_frames, F), mu_h, al_h)

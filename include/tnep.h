@@ -73,10 +73,13 @@ extern "C" {
 /* options for tnep_set_option */
 #define TNEP_OPT_MLP 1            /* one of TNEP_MLP_*                          */
 #define TNEP_OPT_ATOMS_PER_BLOCK 2 /* work-group size of the fused kernel: 64, 128, 256 */
-#define TNEP_OPT_AUTOTUNE 3       /* 1 = pick launch parameters by measurement  */
+#define TNEP_OPT_AUTOTUNE 3       /* 1 = time candidate work-group and batch sizes on the first
+                                     call of each (model shape, frame size class, location) and
+                                     keep the fastest; results do not depend on the choice  */
 #define TNEP_OPT_DETERMINISTIC 4  /* 1 (default) = fixed reduction order        */
 #define TNEP_OPT_MAX_BATCH_ATOMS 5 /* atoms per launch batch (default 2^20)       */
 #define TNEP_OPT_TIMING 6         /* 1 = time every launch with HIP events and count pairs */
+#define TNEP_OPT_NEIGH_BLOCK 7    /* work-group size of the neighbour kernel: 64, 128, 256 */
 
 /* kernel classes for tnep_ctx_kernel_time */
 #define TNEP_KERNEL_NEIGHBORS 0
@@ -141,6 +144,9 @@ void tnep_ctx_destroy(tnep_ctx* ctx);
 const char* tnep_last_error(const tnep_ctx* ctx);
 /* Set an integer option (TNEP_OPT_*).  TNEP_E_INVALID for unknown keys/values. */
 int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value);
+/* Text of the last autotuning decision (candidates and their times), library-owned,
+ * empty if none was made. */
+const char* tnep_autotune_report(const tnep_ctx* ctx);
 /* Device bytes currently held by the context's work buffers. */
 uint64_t tnep_ctx_memory_in_use(const tnep_ctx* ctx);
 /* With TNEP_OPT_TIMING on: summed device time (ms, HIP events on the context's

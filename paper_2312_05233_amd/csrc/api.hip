@@ -167,6 +167,10 @@ extern "C" const char* tnep_last_error(const tnep_ctx* ctx) {
     return reinterpret_cast<const Ctx*>(ctx)->err.c_str();
 }
 
+extern "C" const char* tnep_autotune_report(const tnep_ctx* ctx) {
+    return ctx ? reinterpret_cast<const Ctx*>(ctx)->tune_log.c_str() : "";
+}
+
 extern "C" uint64_t tnep_ctx_memory_in_use(const tnep_ctx* ctx) {
     return ctx ? reinterpret_cast<const Ctx*>(ctx)->in_use : 0;
 }
@@ -218,6 +222,11 @@ extern "C" int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value) {
             if (value != 64 && value != 128 && value != 256)
                 return c->fail(TNEP_E_INVALID, "atoms per block must be 64, 128 or 256");
             c->launch.atoms_per_block = (int)value;
+            return TNEP_OK;
+        case TNEP_OPT_NEIGH_BLOCK:
+            if (value != 64 && value != 128 && value != 256)
+                return c->fail(TNEP_E_INVALID, "neighbour work-group size must be 64, 128 or 256");
+            c->launch.neigh_block = (int)value;
             return TNEP_OK;
         case TNEP_OPT_AUTOTUNE:
             c->autotune = value != 0;

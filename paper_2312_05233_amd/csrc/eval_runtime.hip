@@ -8,6 +8,8 @@
 // the whole call is repeated with larger lists.
 #include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <string>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -96,7 +98,130 @@ int fetch_meta(Ctx* c, const tnep_frames& fr, HostMeta& m) {
 
 }  // namespace
 
+static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job);
+
+// Autotuning of launch parameters that do not change results: the work-group
+// sizes of the evaluation and neighbour kernels and the launch-batch size.
+// The call's leading frames (up to 2^20 atoms) are evaluated once per
+// candidate; every candidate writes the same values, which the real run then
+// overwrites.  Coordinate search: work-group sizes at the default batch size,
+// then the batch size with the best work-group sizes.
+static int autotune(Ctx* c, const tnep_frames& fr, const EvalJob& job, const std::string& key,
+                    const std::vector<int64_t>& offs) {
+    int K = 0;
+    while (K < fr.n_frames && offs[K + 1] <= ((int64_t)1 << 20)) ++K;
+    if (K == 0) K = 1;
+    tnep_frames sub = fr;
+    sub.n_frames = K;
+    const int64_t atoms = offs[K];
+    const EvalLaunch saved = c->launch;
+    const int64_t saved_batch = c->max_batch_atoms;
+    const bool saved_timing = c->timing;
+    c->timing = false;
+    auto measure = [&](double& ms) -> int {
+        int e = run_eval_core(c, sub, job);  // warm-up (also grows neighbour capacities)
+        if (e) return e;
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+            return c->fail(TNEP_E_HIP, "hipEventCreate failed");
+        (void)hipEventRecord(a, c->stream);
+        e = run_eval_core(c, sub, job);
+        (void)hipEventRecord(b, c->stream);
+        (void)hipEventSynchronize(b);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, a, b);
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        ms = t;
+        return e;
+    };
+    Ctx::Tuned best{saved.atoms_per_block, saved.neigh_block, saved_batch};
+    double best_ms = 1e30;
+    char buf[160];
+    std::string log = "autotune " + key + ":";
+    const int sizes[3] = {64, 128, 256};
+    for (int eb : sizes)
+        for (int nb : sizes) {
+            c->launch.atoms_per_block = eb;
+            c->launch.neigh_block = nb;
+            double ms;
+            int e = measure(ms);
+            if (e) {
+                c->launch = saved;
+                c->timing = saved_timing;
+                return e;
+            }
+            snprintf(buf, sizeof(buf), " eval%d/neigh%d=%.3fms", eb, nb, ms);
+            log += buf;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best.atoms_per_block = eb;
+                best.neigh_block = nb;
+            }
+        }
+    c->launch.atoms_per_block = best.atoms_per_block;
+    c->launch.neigh_block = best.neigh_block;
+    double best_rate = atoms / best_ms;
+    for (int64_t bsz : {(int64_t)1 << 18, (int64_t)1 << 19}) {
+        if (bsz >= atoms) continue;
+        c->max_batch_atoms = bsz;
+        double ms;
+        int e = measure(ms);
+        if (e) {
+            c->launch = saved;
+            c->max_batch_atoms = saved_batch;
+            c->timing = saved_timing;
+            return e;
+        }
+        snprintf(buf, sizeof(buf), " batch%lld=%.3fms", (long long)bsz, ms);
+        log += buf;
+        if (atoms / ms > best_rate * 1.02) {
+            best_rate = atoms / ms;
+            best.max_batch_atoms = bsz;
+        }
+    }
+    c->launch = saved;
+    c->max_batch_atoms = saved_batch;
+    c->timing = saved_timing;
+    c->tuned[key] = best;
+    snprintf(buf, sizeof(buf), " -> eval%d neigh%d batch%lld", best.atoms_per_block, best.neigh_block,
+             (long long)best.max_batch_atoms);
+    c->tune_log = log + buf;
+    return TNEP_OK;
+}
+
 int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
+    if (!c->autotune || fr.n_frames == 0) return run_eval_core(c, fr, job);
+    HostMeta meta;
+    int e = fetch_meta(c, fr, meta);
+    if (e) return e;
+    int64_t largest = 1;
+    for (int f = 0; f < fr.n_frames; ++f) largest = std::max(largest, meta.offs[f + 1] - meta.offs[f]);
+    int size_class = 0;
+    while (((int64_t)1 << (size_class + 1)) <= largest) ++size_class;
+    char key[160];
+    const Shape& sh = job.models[0]->shape;
+    snprintf(key, sizeof(key), "%d.%d.%d.%d.%d.%d/T%d/H%d/n%d/m%d/loc%d/mlp%d", sh.nr, sh.na, sh.kr, sh.ka,
+             sh.four_body, sh.kind, job.models[0]->T, job.models[0]->H, size_class, job.n_models, fr.location,
+             c->launch.mlp_mode);
+    auto it = c->tuned.find(key);
+    if (it == c->tuned.end()) {
+        e = autotune(c, fr, job, key, meta.offs);
+        if (e) return e;
+        it = c->tuned.find(key);
+    }
+    const EvalLaunch saved = c->launch;
+    const int64_t saved_batch = c->max_batch_atoms;
+    c->launch.atoms_per_block = it->second.atoms_per_block;
+    c->launch.neigh_block = it->second.neigh_block;
+    c->max_batch_atoms = it->second.max_batch_atoms;
+    e = run_eval_core(c, fr, job);
+    c->launch = saved;
+    c->max_batch_atoms = saved_batch;
+    return e;
+}
+
+static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
     const int F = fr.n_frames;
     if (F == 0) return TNEP_OK;
     (void)hipSetDevice(c->device);
@@ -242,7 +367,7 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 int tr = c->timer_begin(TNEP_KERNEL_NEIGHBORS);
                 HIP_CHECK_RET(c, launch_neighbors((const FrameInfo*)c->frames.p, nf, pos, spc, na, n_cells,
                                                   (float)gm->rc_radial, (float)gm->rc_angular, w, nl,
-                                                  (int32_t*)c->flags.p, c->stream));
+                                                  (int32_t*)c->flags.p, c->launch.neigh_block, c->stream));
                 c->timer_end(tr);
                 if (c->timing)
                     HIP_CHECK_RET(c, launch_count_pairs(nl, (unsigned long long*)c->counters.p, c->stream));

@@ -95,12 +95,13 @@ struct NeighborWork {
 
 hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,
                             int64_t n_atoms, int n_cells, float rc_radial, float rc_angular, const NeighborWork& w,
-                            const NeighborLists& nl, int32_t* d_flags, hipStream_t s);
+                            const NeighborLists& nl, int32_t* d_flags, int neigh_block, hipStream_t s);
 
 // ---- evaluation (kernels_eval.hip) ----
 struct EvalLaunch {
     int mlp_mode;         // TNEP_MLP_*
-    int atoms_per_block;  // 64, 128, 256
+    int atoms_per_block;  // work-group size of the FP32-VALU evaluation kernel: 64, 128, 256
+    int neigh_block;      // work-group size of the neighbour kernel: 64, 128, 256
 };
 
 // Per-atom tensors (FP64, [n_atoms][3 or 9], batch atom order) of one model.

@@ -536,11 +536,12 @@ __global__ void __launch_bounds__(256) k_frame_reduce(const FrameInfo* __restric
 }
 
 template <int NR, int NA, int KR, int KA, bool FOURB, int KIND, int MODE>
-hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom, hipStream_t s) {
+hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom, int block, hipStream_t s) {
     constexpr int D = NR + 4 * NA + (FOURB ? NA : 0);
     if constexpr (MODE == TNEP_MLP_FP32_VALU) {
-        const unsigned grid = (unsigned)((nl.n_pad + 255) / 256);
-        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, 256, 0, s>>>(m, nl, per_atom);
+        const int bs = (block == 64 || block == 128) ? block : 256;
+        const unsigned grid = (unsigned)((nl.n_pad + bs - 1) / bs);
+        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom);
     } else {
         // two wavefronts per work-group keep the LDS tiles at <= 2 x 27 KB
         const unsigned grid = (unsigned)((nl.n_pad + 127) / 128);
@@ -552,27 +553,28 @@ hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom
 
 template <int NR, int NA, int KR, int KA, bool FOURB, int KIND>
 hipError_t launch_mode(int mode, bool matrix, const DevModel& m, const NeighborLists& nl, double* per_atom,
-                       hipStream_t s) {
+                       int block, hipStream_t s) {
     if (matrix) {
         if (mode == TNEP_MLP_FP32_MFMA)
-            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, s);
+            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, block, s);
         if (mode == TNEP_MLP_BF16_MFMA)
-            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, s);
+            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, block, s);
         if (mode == TNEP_MLP_BF16X3_MFMA)
-            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, s);
+            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, block, s);
     }
-    return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, s);
+    return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, block, s);
 }
 
 template <int NR, int NA, int KR, int KA, bool FOURB, bool MX>
 hipError_t dispatch(const Shape& shape, int mode, bool matrix, const DevModel& m, const NeighborLists& nl,
-                    double* per_atom, hipStream_t s) {
+                    double* per_atom, int block, hipStream_t s) {
     if constexpr (MX) {
-        if (shape.kind == 1) return launch_mode<NR, NA, KR, KA, FOURB, 1>(mode, matrix, m, nl, per_atom, s);
-        return launch_mode<NR, NA, KR, KA, FOURB, 2>(mode, matrix, m, nl, per_atom, s);
+        if (shape.kind == 1) return launch_mode<NR, NA, KR, KA, FOURB, 1>(mode, matrix, m, nl, per_atom, block, s);
+        return launch_mode<NR, NA, KR, KA, FOURB, 2>(mode, matrix, m, nl, per_atom, block, s);
     } else {
-        if (shape.kind == 1) return launch_t<NR, NA, KR, KA, FOURB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, s);
-        return launch_t<NR, NA, KR, KA, FOURB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, s);
+        if (shape.kind == 1)
+            return launch_t<NR, NA, KR, KA, FOURB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, block, s);
+        return launch_t<NR, NA, KR, KA, FOURB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, block, s);
     }
 }
 
@@ -611,7 +613,8 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
 #define X(NR_, NA_, KR_, KA_, FB_, MX_)                                                             \
     if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                \
         (bool)shape.four_body == FB_)                                                             \
-        return dispatch<NR_, NA_, KR_, KA_, FB_, MX_>(shape, cfg.mlp_mode, matrix, m, nl, per_atom, s);
+        return dispatch<NR_, NA_, KR_, KA_, FB_, MX_>(shape, cfg.mlp_mode, matrix, m, nl, per_atom,           \
+                                                      cfg.atoms_per_block, s);
     TNEP_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

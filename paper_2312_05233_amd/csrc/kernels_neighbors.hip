@@ -399,8 +399,9 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,
                             int64_t n_atoms, int n_cells, float rc_radial, float rc_angular, const NeighborWork& w,
-                            const NeighborLists& nl, int32_t* d_flags, hipStream_t s) {
+                            const NeighborLists& nl, int32_t* d_flags, int neigh_block, hipStream_t s) {
     if (n_atoms == 0 || n_frames == 0) return hipSuccess;
+    const int nb = (neigh_block == 64 || neigh_block == 128) ? neigh_block : kBlock;
     const int T = nl.T;
     const int n_buckets = n_cells * T;
     k_frame_of<<<n_frames, kBlock, 0, s>>>(d_frames, w.frame_of);
@@ -417,7 +418,7 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const doubl
                                                             n_atoms);
     k_sort_place<<<blocks_for(n_buckets, kBlock), kBlock, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
                                                                  w.perm, pos, w.bucket_pos, n_buckets);
-    k_neighbors<<<blocks_for(nl.n_pad, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
+    k_neighbors<<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
                                                                w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
     return hipGetLastError();
 }

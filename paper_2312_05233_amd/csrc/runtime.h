@@ -40,8 +40,15 @@ struct Ctx {
     uint64_t in_use = 0;
     uint64_t peak = 0;
     std::string err;
-    EvalLaunch launch{0, 256};
+    EvalLaunch launch{0, 256, 256};
     bool autotune = false;
+    // autotuned launch parameters per (shape, species count, frame-size class, location)
+    struct Tuned {
+        int atoms_per_block, neigh_block;
+        int64_t max_batch_atoms;
+    };
+    std::map<std::string, Tuned> tuned;
+    std::string tune_log;  // last autotuning decision (for tnep_last_error-style inspection)
     int64_t max_batch_atoms = 1 << 20;
     int cap_ang[8] = {16, 16, 16, 16, 16, 16, 16, 16};  // learned per-species neighbour capacities
     int cap_rad[8] = {32, 32, 32, 32, 32, 32, 32, 32};  // (grow-only, multiples of 4)

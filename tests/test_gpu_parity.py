@@ -237,3 +237,24 @@ def test_hidden_layer_precision_modes(gpu_lib, name, frames):
     # bf16 operands (8-bit mantissa) cannot meet 1e-5; the split form must stay within 10x of it
     assert errs[gpu_lib.MLP_BF16_MFMA] < 5e-2
     assert errs[gpu_lib.MLP_BF16X3_MFMA] < 1e-4
+
+
+def test_autotune_keeps_results(gpu_lib):
+    """Autotuned launch parameters change speed only, never the numbers."""
+    m = synth.model("molecule_polarizability")
+    fr = synth.molecules(300, seed=14)
+    c1 = gpu_lib.Context(0)
+    g1 = gpu_lib.Model(c1, m)
+    a = gpu_lib.tnep_eval_polarizability(c1, g1, fr)
+    c2 = gpu_lib.Context(0)
+    c2.set_option(gpu_lib.OPT_AUTOTUNE, 1)
+    g2 = gpu_lib.Model(c2, m)
+    b = gpu_lib.tnep_eval_polarizability(c2, g2, fr)
+    rep = c2.autotune_report()
+    print(rep)
+    assert rep.startswith("autotune") and "->" in rep
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, gpu_lib.tnep_eval_polarizability(c2, g2, fr))
+    for c, g in ((c1, g1), (c2, g2)):
+        g.close()
+        c.close()
