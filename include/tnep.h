@@ -80,6 +80,13 @@ extern "C" {
 #define TNEP_OPT_MAX_BATCH_ATOMS 5 /* atoms per launch batch (default 2^20)       */
 #define TNEP_OPT_TIMING 6         /* 1 = time every launch with HIP events and count pairs */
 #define TNEP_OPT_NEIGH_BLOCK 7    /* work-group size of the neighbour kernel: 64, 128, 256 */
+#define TNEP_OPT_GRAPHS 8         /* 1 = for TNEP_HOST frames (timing off), capture each launch
+                                     batch's kernels once per signature (models, neighbour
+                                     capacities, launch sizes, power-of-two bucket of atoms,
+                                     frames and cells) as a HIP graph and replay it; results are
+                                     bitwise those of the plain launches.  Needs a non-null
+                                     stream.  A call on a context must not overlap another
+                                     call on the same context (as for every entry point). */
 
 /* kernel classes for tnep_ctx_kernel_time */
 #define TNEP_KERNEL_NEIGHBORS 0
@@ -157,12 +164,18 @@ uint64_t tnep_ctx_memory_in_use(const tnep_ctx* ctx);
 int tnep_ctx_kernel_time(const tnep_ctx* ctx, int32_t kernel_class, double* total_ms, uint64_t* launches);
 int tnep_ctx_pair_counts(const tnep_ctx* ctx, uint64_t* atoms, uint64_t* radial_pairs, uint64_t* angular_pairs);
 int tnep_ctx_reset_timing(tnep_ctx* ctx);
+/* With TNEP_OPT_GRAPHS on: graphs captured and graph launches since the
+ * context was created (with a running server: its slots' counts added).
+ * Either pointer may be NULL. */
+int tnep_ctx_graph_counts(const tnep_ctx* ctx, uint64_t* captures, uint64_t* launches);
 
 /* ---- model ------------------------------------------------------------- */
 /* Copy a model to the device (resident until tnep_model_free). TNEP_E_MODEL if
  * the shape is unsupported (l_max != 4, rc_angular > rc_radial, sizes out of
  * range). */
 int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* desc, tnep_model** out);
+/* Free a model (waits for the device first); valid before or after its
+ * context is destroyed. */
 void tnep_model_free(tnep_model* model);
 
 /* ---- evaluation -------------------------------------------------------- */
@@ -233,7 +246,8 @@ typedef struct {
 } tnep_server_opts;
 
 /* Start the server thread of ctx.  After this, only tnep_submit / tnep_wait /
- * tnep_server_stop / tnep_server_stats may be used on ctx. */
+ * tnep_server_stop / tnep_server_stats / tnep_ctx_graph_counts may be used on
+ * ctx.  Slot contexts inherit the launch options of ctx, TNEP_OPT_GRAPHS included. */
 int tnep_server_start(tnep_ctx* ctx, const tnep_server_opts* opts);
 /* Queue one request: `kind` selects dipole (out [n_frames][3]) or
  * polarizability (out [n_frames][9]); frames and out must be host memory and

@@ -49,6 +49,7 @@ int tnep::Ctx::reserve(DevBuf& b, size_t bytes) {
         b.p = nullptr;
         b.bytes = 0;
     }
+    ++epoch;
     hipError_t e = hipMalloc(&b.p, want);
     if (e != hipSuccess) return fail(TNEP_E_HIP, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
     b.bytes = want;
@@ -61,6 +62,7 @@ void tnep::Ctx::release(DevBuf& b) {
     if (b.p) {
         (void)hipFree(b.p);
         in_use -= b.bytes;
+        ++epoch;
     }
     b.p = nullptr;
     b.bytes = 0;
@@ -105,8 +107,16 @@ void tnep::Ctx::timer_flush() {
     }
 }
 
+void tnep::Ctx::drop_graphs() {
+    if (graphs.empty()) return;
+    (void)hipStreamSynchronize(stream);
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second.exec);
+    graphs.clear();
+}
+
 tnep::Ctx::~Ctx() {
     if (stream) (void)hipStreamSynchronize(stream);
+    drop_graphs();
     for (hipEvent_t ev : event_pool) (void)hipEventDestroy(ev);
     for (DevBuf* b : all_buffers()) release(*b);
     if (h_flags) (void)hipHostFree(h_flags);
@@ -193,6 +203,16 @@ extern "C" int tnep_ctx_pair_counts(const tnep_ctx* ctx, uint64_t* atoms, uint64
     return TNEP_OK;
 }
 
+extern "C" int tnep_ctx_graph_counts(const tnep_ctx* ctx, uint64_t* captures, uint64_t* launches) {
+    if (!ctx) return TNEP_E_INVALID;
+    const Ctx* c = reinterpret_cast<const Ctx*>(ctx);
+    uint64_t nc = c->graph_captures, nl = c->graph_launches;
+    if (c->server) server_graph_counts(c, nc, nl);
+    if (captures) *captures = nc;
+    if (launches) *launches = nl;
+    return TNEP_OK;
+}
+
 extern "C" int tnep_ctx_reset_timing(tnep_ctx* ctx) {
     if (!ctx) return TNEP_E_INVALID;
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
@@ -236,6 +256,11 @@ extern "C" int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value) {
             return TNEP_OK;
         case TNEP_OPT_TIMING:
             c->timing = value != 0;
+            return TNEP_OK;
+        case TNEP_OPT_GRAPHS:
+            if (value != 0 && !c->stream) return c->fail(TNEP_E_INVALID, "graphs need a non-null stream");
+            c->use_graphs = value != 0;
+            if (!c->use_graphs) c->drop_graphs();
             return TNEP_OK;
         case TNEP_OPT_MAX_BATCH_ATOMS:
             if (value < 1) return c->fail(TNEP_E_INVALID, "max batch atoms must be positive");
@@ -371,8 +396,11 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
         o_bf_bwd_lo = put_u16(bl);
     }
 
+    static std::atomic<uint64_t> next_serial{1};
     Model* m = new Model();
+    m->serial = next_serial++;
     m->ctx = c;
+    m->device = c->device;
     m->shape = sh;
     m->kind = d->kind;
     m->T = T;
@@ -422,7 +450,7 @@ extern "C" void tnep_model_free(tnep_model* model) {
     if (!model) return;
     Model* m = reinterpret_cast<Model*>(model);
     if (m->dbuf) {
-        (void)hipSetDevice(m->ctx->device);
+        (void)hipSetDevice(m->device);  // the context may already be destroyed
         (void)hipDeviceSynchronize();
         (void)hipFree(m->dbuf);
     }

@@ -12,6 +12,7 @@
 #include <string>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "runtime.h"
@@ -221,6 +222,61 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
     return e;
 }
 
+static int64_t pow2_at_least(int64_t n) {
+    int64_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Everything that a captured batch bakes into its kernel arguments and grids,
+// apart from work-buffer addresses (covered by the context's epoch).
+static std::string graph_key(const Ctx* c, const EvalJob& job, int first, int last, int T, int64_t cap_atoms,
+                             int cap_frames, int64_t cap_cells, int64_t B_res) {
+    std::string k;
+    char buf[96];
+    for (int m = first; m < last; ++m) {
+        snprintf(buf, sizeof(buf), "m%llu.", (unsigned long long)job.models[m]->serial);
+        k += buf;
+    }
+    for (int t = 0; t < T; ++t) {
+        snprintf(buf, sizeof(buf), "c%d.%d.", c->cap_ang[t], c->cap_rad[t]);
+        k += buf;
+    }
+    snprintf(buf, sizeof(buf), "l%d.%d.%d/a%lld/f%d/c%lld/b%lld", c->launch.mlp_mode, c->launch.atoms_per_block,
+             c->launch.neigh_block, (long long)cap_atoms, cap_frames, (long long)cap_cells, (long long)B_res);
+    return k + buf;
+}
+
+// Launch the graph stored under `key`, capturing `launch` into it first if it
+// is missing or older than the last work-buffer reallocation.
+template <class Launch>
+static int replay_graph(Ctx* c, const std::string& key, Launch&& launch) {
+    // all stored graphs share one epoch: a reallocation drops them together
+    if (!c->graphs.empty() && c->graphs.begin()->second.epoch != c->epoch) c->drop_graphs();
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        if (c->graphs.size() >= 64) c->drop_graphs();
+        HIP_CHECK_RET(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t le = launch();
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(c->stream, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return c->fail(TNEP_E_HIP, "graph capture failed: %s",
+                           hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return c->fail(TNEP_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+        it = c->graphs.emplace(key, Ctx::Graph{ex, c->epoch}).first;
+        ++c->graph_captures;
+    }
+    HIP_CHECK_RET(c, hipGraphLaunch(it->second.exec, c->stream));
+    ++c->graph_launches;
+    return TNEP_OK;
+}
+
 static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
     const int F = fr.n_frames;
     if (F == 0) return TNEP_OK;
@@ -266,7 +322,15 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             B = std::max(B, largest);
             const int64_t room = (int64_t)c->budget - (int64_t)(c->in_use - c->nbr.bytes - c->per_atom.bytes);
             if (room > 0 && B * per_atom_bytes > room) B = std::max(largest, room / per_atom_bytes);
-            const int64_t n_pad_max = (B + 63) / 64 * 64 + 64 * T;
+            // Graph replay: grids are sized for power-of-two capacities of the
+            // batch's atoms, frames and cells; kernels read the actual sizes
+            // from meta.  Host-resident frames only (every address a kernel
+            // sees is then a work buffer of this context).
+            const int64_t B_graph = pow2_at_least(std::max<int64_t>(B, 64));
+            const bool graphs = c->use_graphs && !c->timing && fr.location == TNEP_HOST && c->stream &&
+                                (room <= 0 || B_graph * per_atom_bytes <= room);
+            const int64_t B_res = graphs ? B_graph : B;
+            const int64_t n_pad_max = (B_res + 63) / 64 * 64 + 64 * T;
             if ((e = c->reserve(c->nbr, (size_t)n_pad_max * slots * sizeof(float4)))) return e;
             if ((e = c->reserve(c->counts, (size_t)n_pad_max * 2 * T * 4))) return e;
             if ((e = c->reserve(c->perm, (size_t)n_pad_max * 4))) return e;
@@ -281,18 +345,18 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 }
                 // only the host part: the tile bases are written by the scan kernel
                 HIP_CHECK_RET(c, hipMemcpyAsync((int32_t*)c->tile_base.p + kMetaSegA, h + kMetaSegA,
-                                                sizeof(int32_t) * (kMetaInts - kMetaSegA), hipMemcpyHostToDevice,
+                                                sizeof(int32_t) * (kMetaNAtoms - kMetaSegA), hipMemcpyHostToDevice,
                                                 c->stream));
             }
-            if ((e = c->reserve(c->frame_of, (size_t)B * 4))) return e;
-            if ((e = c->reserve(c->key_of, (size_t)B * 4))) return e;
-            if ((e = c->reserve(c->bucket_atoms, (size_t)B * 4))) return e;
-            if ((e = c->reserve(c->bucket_pos, (size_t)B * 32))) return e;
-            if ((e = c->reserve(c->per_atom, (size_t)B * 9 * sizeof(double) * (last - first)))) return e;
+            if ((e = c->reserve(c->frame_of, (size_t)B_res * 4))) return e;
+            if ((e = c->reserve(c->key_of, (size_t)B_res * 4))) return e;
+            if ((e = c->reserve(c->bucket_atoms, (size_t)B_res * 4))) return e;
+            if ((e = c->reserve(c->bucket_pos, (size_t)B_res * 32))) return e;
+            if ((e = c->reserve(c->per_atom, (size_t)B_res * 9 * sizeof(double) * (last - first)))) return e;
             if ((e = c->reserve(c->flags, 32 * 4))) return e;
             if (fr.location == TNEP_HOST) {
-                if ((e = c->reserve(c->pos, (size_t)B * 24))) return e;
-                if ((e = c->reserve(c->species, (size_t)B * 4))) return e;
+                if ((e = c->reserve(c->pos, (size_t)B_res * 24))) return e;
+                if ((e = c->reserve(c->species, (size_t)B_res * 4))) return e;
             }
             if (c->timing && !c->counters.p) {
                 if ((e = c->reserve(c->counters, 64))) return e;
@@ -300,7 +364,12 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             }
             HIP_CHECK_RET(c, launch_init_flags((int32_t*)c->flags.p, c->stream));
 
-            std::vector<std::vector<FrameInfo>> keep;  // host FrameInfo per batch, alive until sync
+            // host FrameInfo and batch sizes per batch, alive until the sync below
+            struct BatchHost {
+                std::vector<FrameInfo> fi;
+                int32_t sizes[3];
+            };
+            std::vector<std::unique_ptr<BatchHost>> keep;
             int f0 = 0;
             while (f0 < F) {
                 int f1 = f0;
@@ -308,8 +377,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if (f1 == f0) f1 = f0 + 1;
                 const int nf = f1 - f0;
                 const int64_t a0 = meta.offs[f0], na = meta.offs[f1] - a0;
-                keep.emplace_back(nf);
-                std::vector<FrameInfo>& fi = keep.back();
+                keep.emplace_back(new BatchHost());
+                BatchHost& bh = *keep.back();
+                bh.fi.resize(nf);
+                std::vector<FrameInfo>& fi = bh.fi;
                 int n_cells = 0;
                 for (int k = 0; k < nf; ++k) {
                     const FrameGeom& g = geom[f0 + k];
@@ -327,16 +398,25 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     x.cell_base = n_cells;
                     n_cells += g.mode == 1 ? g.n_cells() : 1;
                 }
-                const int64_t n_buckets = (int64_t)n_cells * T;
+                // launch capacities: exact sizes, or power-of-two buckets for graphs
+                const int64_t cap_atoms = graphs ? pow2_at_least(std::max<int64_t>(na, 64)) : na;
+                const int cap_frames = graphs ? (int)pow2_at_least(nf) : nf;
+                const int64_t cap_cells = graphs ? pow2_at_least(n_cells) : n_cells;
+                const int64_t n_buckets = cap_cells * T;
                 if (n_buckets >= ((int64_t)1 << 30)) return c->fail(TNEP_E_INVALID, "too many cells in one batch");
-                if ((e = c->reserve(c->frames, sizeof(FrameInfo) * nf))) return e;
+                if ((e = c->reserve(c->frames, sizeof(FrameInfo) * cap_frames))) return e;
                 if ((e = c->reserve(c->bucket_count, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->bucket_start, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->bucket_fill, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->perm_start, (size_t)4 * (n_buckets + 1)))) return e;
-                if ((e = c->reserve(c->scan_chunks, (size_t)4 * 18 * (n_cells / 1024 + 1)))) return e;
+                if ((e = c->reserve(c->scan_chunks, (size_t)4 * 18 * (cap_cells / 1024 + 1)))) return e;
                 const int nt_max = 9;
-                if ((e = c->reserve(c->out, sizeof(double) * nt_max * nf * (last - first)))) return e;
+                if ((e = c->reserve(c->out, sizeof(double) * nt_max * cap_frames * (last - first)))) return e;
+                bh.sizes[0] = (int32_t)na;
+                bh.sizes[1] = nf;
+                bh.sizes[2] = n_cells;
+                HIP_CHECK_RET(c, hipMemcpyAsync((int32_t*)c->tile_base.p + kMetaNAtoms, bh.sizes, sizeof(bh.sizes),
+                                                hipMemcpyHostToDevice, c->stream));
                 HIP_CHECK_RET(c, hipMemcpyAsync(c->frames.p, fi.data(), sizeof(FrameInfo) * nf,
                                                 hipMemcpyHostToDevice, c->stream));
                 const double* pos;
@@ -361,36 +441,64 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 nl.counts = (int32_t*)c->counts.p;
                 nl.perm = (const int32_t*)c->perm.p;
                 nl.meta = (const int32_t*)c->tile_base.p;
-                nl.n_pad = (na + 63) / 64 * 64 + 64 * T;
+                nl.n_pad = (cap_atoms + 63) / 64 * 64 + 64 * T;
                 nl.T = T;
                 nl.slots = slots;
-                int tr = c->timer_begin(TNEP_KERNEL_NEIGHBORS);
-                HIP_CHECK_RET(c, launch_neighbors((const FrameInfo*)c->frames.p, nf, pos, spc, na, n_cells,
-                                                  (float)gm->rc_radial, (float)gm->rc_angular, w, nl,
-                                                  (int32_t*)c->flags.p, c->launch.neigh_block, c->stream));
-                c->timer_end(tr);
-                if (c->timing)
-                    HIP_CHECK_RET(c, launch_count_pairs(nl, (unsigned long long*)c->counters.p, c->stream));
+                double* pa_of[2];
+                double* out_of[2];
                 for (int k = first; k < last; ++k) {
-                    const Model* m = job.models[k];
-                    const int nt = m->kind == TNEP_KIND_DIPOLE ? 3 : 9;
-                    double* pa = (double*)c->per_atom.p + (size_t)B * 9 * (k - first);
-                    if (job.per_atom[k] && fr.location == TNEP_DEVICE) pa = job.per_atom[k] + a0 * nt;
-                    tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE ? TNEP_KERNEL_EVAL_DIPOLE
-                                                                    : TNEP_KERNEL_EVAL_POLARIZABILITY);
-                    HIP_CHECK_RET(c, launch_eval(m->shape, m->dm, nl, pa, c->launch, c->stream));
+                    const int nt = job.models[k]->kind == TNEP_KIND_DIPOLE ? 3 : 9;
+                    pa_of[k - first] = (double*)c->per_atom.p + (size_t)B_res * 9 * (k - first);
+                    if (job.per_atom[k] && fr.location == TNEP_DEVICE) pa_of[k - first] = job.per_atom[k] + a0 * nt;
+                    out_of[k - first] = fr.location == TNEP_DEVICE
+                                            ? job.out[k] + (size_t)f0 * nt
+                                            : (double*)c->out.p + (size_t)nt_max * cap_frames * (k - first);
+                }
+                // the batch's kernels; with graphs on, captured once and replayed
+                auto launch_batch = [&]() -> hipError_t {
+                    hipError_t he;
+                    int tr = c->timer_begin(TNEP_KERNEL_NEIGHBORS);
+                    he = launch_neighbors((const FrameInfo*)c->frames.p, cap_frames, pos, spc, cap_atoms,
+                                          (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl,
+                                          (int32_t*)c->flags.p, c->launch.neigh_block, c->stream);
                     c->timer_end(tr);
-                    double* o = fr.location == TNEP_DEVICE ? job.out[k] + (size_t)f0 * nt
-                                                           : (double*)c->out.p + (size_t)nt_max * nf * (k - first);
-                    tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);
-                    HIP_CHECK_RET(c, launch_frame_reduce((const FrameInfo*)c->frames.p, nf, pa, nt, o, c->stream));
-                    c->timer_end(tr);
-                    if (fr.location == TNEP_HOST) {
-                        HIP_CHECK_RET(c, hipMemcpyAsync(job.out[k] + (size_t)f0 * nt, o, sizeof(double) * nt * nf,
-                                                        hipMemcpyDeviceToHost, c->stream));
+                    if (he != hipSuccess) return he;
+                    if (c->timing) {
+                        he = launch_count_pairs(nl, (unsigned long long*)c->counters.p, c->stream);
+                        if (he != hipSuccess) return he;
+                    }
+                    for (int k = first; k < last; ++k) {
+                        const Model* m = job.models[k];
+                        const int nt = m->kind == TNEP_KIND_DIPOLE ? 3 : 9;
+                        tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE ? TNEP_KERNEL_EVAL_DIPOLE
+                                                                        : TNEP_KERNEL_EVAL_POLARIZABILITY);
+                        he = launch_eval(m->shape, m->dm, nl, pa_of[k - first], c->launch, c->stream);
+                        c->timer_end(tr);
+                        if (he != hipSuccess) return he;
+                        tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);
+                        he = launch_frame_reduce((const FrameInfo*)c->frames.p, cap_frames, nl.meta,
+                                                 pa_of[k - first], nt, out_of[k - first], c->stream);
+                        c->timer_end(tr);
+                        if (he != hipSuccess) return he;
+                    }
+                    return hipSuccess;
+                };
+                if (graphs) {
+                    if ((e = replay_graph(c, graph_key(c, job, first, last, T, cap_atoms, cap_frames, cap_cells, B_res),
+                                          launch_batch)))
+                        return e;
+                } else {
+                    HIP_CHECK_RET(c, launch_batch());
+                }
+                if (fr.location == TNEP_HOST) {
+                    for (int k = first; k < last; ++k) {
+                        const int nt = job.models[k]->kind == TNEP_KIND_DIPOLE ? 3 : 9;
+                        HIP_CHECK_RET(c, hipMemcpyAsync(job.out[k] + (size_t)f0 * nt, out_of[k - first],
+                                                        sizeof(double) * nt * nf, hipMemcpyDeviceToHost, c->stream));
                         if (job.per_atom[k])
-                            HIP_CHECK_RET(c, hipMemcpyAsync(job.per_atom[k] + a0 * nt, pa, sizeof(double) * nt * na,
-                                                            hipMemcpyDeviceToHost, c->stream));
+                            HIP_CHECK_RET(c, hipMemcpyAsync(job.per_atom[k] + a0 * nt, pa_of[k - first],
+                                                            sizeof(double) * nt * na, hipMemcpyDeviceToHost,
+                                                            c->stream));
                     }
                 }
                 f0 = f1;

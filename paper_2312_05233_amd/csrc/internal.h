@@ -61,7 +61,20 @@ struct Shape {
 // + r % 4]: four consecutive rows of one lane are 64 contiguous bytes.
 // Per-species segment tables live in device memory (meta) so that kernels
 // index them with scalar loads.
-enum Meta { kMetaTileBase = 0, kMetaSegA = 16, kMetaSegR = 24, kMetaCapA = 32, kMetaCapR = 40, kMetaInts = 48 };
+// The batch's actual sizes are read from meta too, so that one captured graph
+// (launched with grids sized for a capacity bucket) serves every batch that
+// fits the bucket; blocks beyond the actual sizes return at once.
+enum Meta {
+    kMetaTileBase = 0,
+    kMetaSegA = 16,
+    kMetaSegR = 24,
+    kMetaCapA = 32,
+    kMetaCapR = 40,
+    kMetaNAtoms = 48,
+    kMetaNFrames = 49,
+    kMetaNCells = 50,
+    kMetaInts = 56
+};
 
 struct NeighborLists {
     float4* entries;
@@ -93,8 +106,11 @@ struct NeighborWork {
     int32_t* chunk;         // [2 * 9 * n_chunks] scan partials (n_chunks = ceil(n_cells / 1024))
 };
 
-hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,
-                            int64_t n_atoms, int n_cells, float rc_radial, float rc_angular, const NeighborWork& w,
+// Sizes: the actual atoms, frames and cells of the batch are in meta
+// (kMetaNAtoms, kMetaNFrames, kMetaNCells); cap_* are the launch capacities
+// (>= the actual sizes) that size the grids.
+hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
+                            int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, int32_t* d_flags, int neigh_block, hipStream_t s);
 
 // ---- evaluation (kernels_eval.hip) ----
@@ -116,8 +132,9 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
 hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* counters, hipStream_t s);
 
 // Per-frame sums of per-atom tensors in a fixed order.
-hipError_t launch_frame_reduce(const FrameInfo* d_frames, int n_frames, const double* per_atom, int nt,
-                               double* out, hipStream_t s);
+// Frames beyond meta[kMetaNFrames] are skipped (cap_frames sizes the grid).
+hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const int32_t* meta, const double* per_atom,
+                               int nt, double* out, hipStream_t s);
 
 // ---- spectra (kernels_spectrum.hip) ----
 struct SpectrumPlan {

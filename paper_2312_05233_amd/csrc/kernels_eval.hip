@@ -508,10 +508,12 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 // FP64, then a fixed pairwise tree in LDS; the order depends only on the
 // frame's atom count, never on how frames were batched.
 __global__ void __launch_bounds__(256) k_frame_reduce(const FrameInfo* __restrict__ frames,
+                                                      const int32_t* __restrict__ meta,
                                                       const double* __restrict__ per_atom, int nt,
                                                       double* __restrict__ out) {
     __shared__ double part[9][256];
     const int f = blockIdx.x;
+    if (f >= meta[kMetaNFrames]) return;
     const FrameInfo fi = frames[f];
     const int lane = threadIdx.x;
     double s[9];
@@ -620,10 +622,10 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_frame_reduce(const FrameInfo* d_frames, int n_frames, const double* per_atom, int nt, double* out,
-                               hipStream_t s) {
-    if (n_frames == 0) return hipSuccess;
-    k_frame_reduce<<<n_frames, 256, 0, s>>>(d_frames, per_atom, nt, out);
+hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const int32_t* meta, const double* per_atom,
+                               int nt, double* out, hipStream_t s) {
+    if (cap_frames == 0) return hipSuccess;
+    k_frame_reduce<<<cap_frames, 256, 0, s>>>(d_frames, meta, per_atom, nt, out);
     return hipGetLastError();
 }
 

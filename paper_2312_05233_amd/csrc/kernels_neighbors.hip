@@ -28,8 +28,10 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__global__ void k_frame_of(const FrameInfo* __restrict__ frames, int32_t* __restrict__ frame_of) {
+__global__ void k_frame_of(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ meta,
+                           int32_t* __restrict__ frame_of) {
     const int f = blockIdx.x;
+    if (f >= meta[kMetaNFrames]) return;
     const FrameInfo fi = frames[f];
     for (int64_t a = threadIdx.x; a < fi.n_atoms; a += blockDim.x) frame_of[fi.atom_begin + a] = f;
 }
@@ -47,10 +49,11 @@ __device__ __forceinline__ int cell_coord(double p, double L, int nc) {
 
 // key = (frame cell) * T + species; invalid atoms get key -1.
 __global__ void k_bin(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ frame_of,
-                      const double* __restrict__ pos, const int32_t* __restrict__ species, int64_t n_atoms, int T,
-                      int32_t* __restrict__ key_of, int32_t* __restrict__ bucket_count, int32_t* __restrict__ flags) {
+                      const double* __restrict__ pos, const int32_t* __restrict__ species,
+                      const int32_t* __restrict__ meta, int T, int32_t* __restrict__ key_of,
+                      int32_t* __restrict__ bucket_count, int32_t* __restrict__ flags) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n_atoms) return;
+    if (a >= meta[kMetaNAtoms]) return;
     const FrameInfo& fi = frames[frame_of[a]];
     const double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
     const int t = species[a];
@@ -99,9 +102,12 @@ __device__ int32_t block_exclusive_256(int32_t v, int32_t* part) {
     return incl - v;
 }
 
-__global__ void __launch_bounds__(256) k_scan_partials(const int32_t* __restrict__ count, int n_cells, int T,
+__global__ void __launch_bounds__(256) k_scan_partials(const int32_t* __restrict__ count,
+                                                       const int32_t* __restrict__ meta, int T,
                                                        int32_t* __restrict__ chunk_sums) {
     __shared__ int32_t red[256];
+    const int n_cells = meta[kMetaNCells];
+    if ((int)blockIdx.x * kScanCells >= n_cells) return;
     const int c0 = blockIdx.x * kScanCells + threadIdx.x * 4;
     for (int t = 0; t <= T; ++t) {
         int32_t s = 0;
@@ -124,10 +130,14 @@ __global__ void __launch_bounds__(256) k_scan_partials(const int32_t* __restrict
 
 // chunk_sums[k*9 + t] (t < T: species t, t = T: all) -> chunk_off[k*9 + t]:
 // species t: slot offset in (species, cell) order incl. tile padding; T: key order.
-__global__ void __launch_bounds__(256) k_scan_chunks(const int32_t* __restrict__ chunk_sums, int n_chunks, int T,
+__global__ void __launch_bounds__(256) k_scan_chunks(const int32_t* __restrict__ chunk_sums, int T,
                                                      int32_t* __restrict__ chunk_off, int32_t* __restrict__ meta,
-                                                     int32_t* __restrict__ bucket_start_end, int n_buckets) {
+                                                     int32_t* __restrict__ bucket_start) {
     __shared__ int32_t part[256];
+    const int n_cells = meta[kMetaNCells];
+    const int n_chunks = (n_cells + kScanCells - 1) / kScanCells;
+    const int n_buckets = n_cells * T;
+    int32_t* bucket_start_end = bucket_start;
     __shared__ int32_t s_carry;
     int32_t tiles = 0;
     for (int t = 0; t <= T; ++t) {
@@ -155,13 +165,16 @@ __global__ void __launch_bounds__(256) k_scan_chunks(const int32_t* __restrict__
     if (threadIdx.x == 0) meta[kMetaTileBase + T] = tiles;
 }
 
-__global__ void __launch_bounds__(256) k_scan_final(const int32_t* __restrict__ count, int n_cells, int T,
+__global__ void __launch_bounds__(256) k_scan_final(const int32_t* __restrict__ count,
+                                                    const int32_t* __restrict__ meta, int T,
                                                     const int32_t* __restrict__ chunk_off,
                                                     int32_t* __restrict__ bucket_start,
                                                     int32_t* __restrict__ bucket_fill,
                                                     int32_t* __restrict__ perm_start) {
     __shared__ int32_t part[256];
+    const int n_cells = meta[kMetaNCells];
     const int k = blockIdx.x;
+    if (k * kScanCells >= n_cells) return;
     const int c0 = k * kScanCells + threadIdx.x * 4;
     const int c1 = min(c0 + 4, n_cells);
     // key order (cell-major, species-minor)
@@ -190,9 +203,10 @@ __global__ void __launch_bounds__(256) k_scan_final(const int32_t* __restrict__ 
 }
 
 __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
-                          int32_t* __restrict__ bucket_fill, int32_t* __restrict__ bucket_atoms, int64_t n_atoms) {
+                          int32_t* __restrict__ bucket_fill, int32_t* __restrict__ bucket_atoms,
+                          const int32_t* __restrict__ meta) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n_atoms) return;
+    if (a >= meta[kMetaNAtoms]) return;
     const int k = key_of[a];
     if (k < 0) return;
     const int slot = atomicAdd(&bucket_fill[k], 1);
@@ -203,9 +217,10 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 // store its positions contiguously in bucket order (w = atom index).
 __global__ void k_sort_place(const int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_atoms,
                              const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm,
-                             const double* __restrict__ pos, double4* __restrict__ bucket_pos, int n_buckets) {
+                             const double* __restrict__ pos, double4* __restrict__ bucket_pos,
+                             const int32_t* __restrict__ meta, int T) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_buckets) return;
+    if (k >= meta[kMetaNCells] * T) return;
     const int b = bucket_start[k], e = bucket_start[k + 1];
     for (int i = b + 1; i < e; ++i) {
         const int32_t v = bucket_atoms[i];
@@ -397,29 +412,29 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
-hipError_t launch_neighbors(const FrameInfo* d_frames, int n_frames, const double* pos, const int32_t* species,
-                            int64_t n_atoms, int n_cells, float rc_radial, float rc_angular, const NeighborWork& w,
+hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
+                            int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, int32_t* d_flags, int neigh_block, hipStream_t s) {
-    if (n_atoms == 0 || n_frames == 0) return hipSuccess;
+    if (cap_atoms == 0 || cap_frames == 0) return hipSuccess;
     const int nb = (neigh_block == 64 || neigh_block == 128) ? neigh_block : kBlock;
     const int T = nl.T;
-    const int n_buckets = n_cells * T;
-    k_frame_of<<<n_frames, kBlock, 0, s>>>(d_frames, w.frame_of);
-    k_fill_i32<<<blocks_for(n_buckets, kBlock), kBlock, 0, s>>>(w.bucket_count, n_buckets, 0);
+    const int cap_buckets = cap_cells * T;
+    const int cap_chunks = (cap_cells + kScanCells - 1) / kScanCells;
+    k_frame_of<<<cap_frames, kBlock, 0, s>>>(d_frames, nl.meta, w.frame_of);
+    k_fill_i32<<<blocks_for(cap_buckets, kBlock), kBlock, 0, s>>>(w.bucket_count, cap_buckets, 0);
     k_fill_i32<<<blocks_for(nl.n_pad, kBlock), kBlock, 0, s>>>(w.perm, nl.n_pad, -1);
-    k_bin<<<blocks_for(n_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, species, n_atoms, T, w.key_of,
-                                                        w.bucket_count, d_flags);
-    const int n_chunks = (n_cells + kScanCells - 1) / kScanCells;
-    k_scan_partials<<<n_chunks, 256, 0, s>>>(w.bucket_count, n_cells, T, w.chunk);
-    k_scan_chunks<<<1, 256, 0, s>>>(w.chunk, n_chunks, T, w.chunk + 9 * n_chunks, w.meta, w.bucket_start, n_buckets);
-    k_scan_final<<<n_chunks, 256, 0, s>>>(w.bucket_count, n_cells, T, w.chunk + 9 * n_chunks, w.bucket_start,
-                                         w.bucket_fill, w.perm_start);
-    k_scatter<<<blocks_for(n_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill, w.bucket_atoms,
-                                                            n_atoms);
-    k_sort_place<<<blocks_for(n_buckets, kBlock), kBlock, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
-                                                                 w.perm, pos, w.bucket_pos, n_buckets);
+    k_bin<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, species, nl.meta, T, w.key_of,
+                                                          w.bucket_count, d_flags);
+    k_scan_partials<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk);
+    k_scan_chunks<<<1, 256, 0, s>>>(w.chunk, T, w.chunk + 9 * cap_chunks, w.meta, w.bucket_start);
+    k_scan_final<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk + 9 * cap_chunks, w.bucket_start,
+                                           w.bucket_fill, w.perm_start);
+    k_scatter<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill,
+                                                              w.bucket_atoms, nl.meta);
+    k_sort_place<<<blocks_for(cap_buckets, kBlock), kBlock, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
+                                                                   w.perm, pos, w.bucket_pos, nl.meta, T);
     k_neighbors<<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
-                                                               w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
+                                                       w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
     return hipGetLastError();
 }
 

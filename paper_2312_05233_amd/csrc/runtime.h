@@ -67,6 +67,20 @@ struct Ctx {
 
     Server* server = nullptr;
 
+    // HIP graphs (TNEP_OPT_GRAPHS): one executable graph per launch-batch
+    // signature, replayed for every batch with that signature.  Kernel
+    // arguments hold work-buffer addresses, so every reallocation bumps
+    // `epoch` and drops all graphs.
+    bool use_graphs = false;
+    uint64_t epoch = 0;
+    struct Graph {
+        hipGraphExec_t exec;
+        uint64_t epoch;
+    };
+    std::map<std::string, Graph> graphs;
+    std::atomic<uint64_t> graph_captures{0}, graph_launches{0};
+    void drop_graphs();
+
     // launch timing (TNEP_OPT_TIMING)
     bool timing = false;
     struct Range {
@@ -91,6 +105,8 @@ struct Ctx {
 
 struct Model {
     Ctx* ctx = nullptr;
+    int device = 0;
+    uint64_t serial = 0;  // unique per process: identifies the model in graph keys
     Shape shape{};
     DevModel dm{};
     void* dbuf = nullptr;
@@ -119,6 +135,7 @@ struct FrameGeom {
 int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc_radial, FrameGeom& g);
 int run_eval(Ctx* c, const tnep_frames& frames, const EvalJob& job);
 void server_shutdown(Ctx* c);
+void server_graph_counts(const Ctx* c, uint64_t& captures, uint64_t& launches);  // adds the slots' counts
 
 hipError_t launch_init_flags(int32_t* d_flags, hipStream_t s);
 

@@ -84,6 +84,7 @@ Ctx* slot_ctx_new(Ctx* parent, uint64_t budget) {
     c->budget = budget;
     c->launch = parent->launch;
     c->max_batch_atoms = parent->max_batch_atoms;
+    c->use_graphs = parent->use_graphs;
     for (int t = 0; t < 8; ++t) {
         c->cap_ang[t] = parent->cap_ang[t];
         c->cap_rad[t] = parent->cap_rad[t];
@@ -256,6 +257,16 @@ void server_shutdown(Ctx* c) {
     for (auto& kv : s->live) delete kv.second;
     delete s;
     c->server = nullptr;
+}
+
+void server_graph_counts(const Ctx* c, uint64_t& captures, uint64_t& launches) {
+    Server* s = c->server;
+    if (!s) return;
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (const Ctx* sc : s->slots) {
+        captures += sc->graph_captures;
+        launches += sc->graph_launches;
+    }
 }
 
 }  // namespace tnep

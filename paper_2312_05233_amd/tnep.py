@@ -25,6 +25,7 @@ KIND_DIPOLE, KIND_POLARIZABILITY = 1, 2
 MLP_FP32_VALU, MLP_FP32_MFMA, MLP_BF16_MFMA, MLP_BF16X3_MFMA = 0, 1, 2, 3
 OPT_MLP, OPT_ATOMS_PER_BLOCK, OPT_AUTOTUNE, OPT_DETERMINISTIC, OPT_MAX_BATCH_ATOMS, OPT_TIMING = 1, 2, 3, 4, 5, 6
 OPT_NEIGH_BLOCK = 7
+OPT_GRAPHS = 8
 KERNEL_NEIGHBORS, KERNEL_EVAL_DIPOLE, KERNEL_EVAL_POLARIZABILITY, KERNEL_FRAME_REDUCE, KERNEL_SPECTRUM = 0, 1, 2, 3, 4
 IR, RAMAN_ISO, RAMAN_ANISO, RAMAN_PROJ = 0, 1, 2, 3
 WIN_HANN, WIN_NONE = 0, 1
@@ -34,7 +35,7 @@ EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_
             "tnep_model_create", "tnep_model_free", "tnep_eval_dipole", "tnep_eval_polarizability",
             "tnep_eval_dipole_polarizability", "tnep_spectrum", "tnep_server_start", "tnep_submit", "tnep_wait",
             "tnep_server_stop", "tnep_server_stats", "tnep_ctx_kernel_time", "tnep_ctx_pair_counts",
-            "tnep_ctx_reset_timing", "tnep_autotune_report"]
+            "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts"]
 
 
 class TnepError(RuntimeError):
@@ -104,6 +105,7 @@ def _load():
     lib.tnep_ctx_kernel_time.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_uint64)]
     lib.tnep_ctx_pair_counts.argtypes = [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
     lib.tnep_ctx_reset_timing.argtypes = [vp]
+    lib.tnep_ctx_graph_counts.argtypes = [vp, P(C.c_uint64), P(C.c_uint64)]
     lib.tnep_autotune_report.argtypes = [vp]
     lib.tnep_autotune_report.restype = C.c_char_p
     for name in EXPORTED:
@@ -160,6 +162,12 @@ class Context:
         a, r, g = C.c_uint64(), C.c_uint64(), C.c_uint64()
         self.check(lib.tnep_ctx_pair_counts(self.h, C.byref(a), C.byref(r), C.byref(g)))
         return a.value, r.value, g.value
+
+    def graph_counts(self):
+        """(graphs captured, graph launches) since the context was created."""
+        n, k = C.c_uint64(), C.c_uint64()
+        self.check(lib.tnep_ctx_graph_counts(self.h, C.byref(n), C.byref(k)))
+        return n.value, k.value
 
     def reset_timing(self):
         self.check(lib.tnep_ctx_reset_timing(self.h))

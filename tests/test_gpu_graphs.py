@@ -1,0 +1,147 @@
+"""HIP-graph replay of launch batches (TNEP_OPT_GRAPHS) against plain launches.
+
+Every replay is compared bit for bit with the plain-launch result of the same
+input, with other eager GPU work and stream synchronisations between replays;
+batches of different actual sizes share one graph when they fall into the same
+power-of-two bucket of atoms, frames and cells.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity import TENSOR_TOL, frame_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx_pair(gpu_lib):
+    plain = gpu_lib.Context(0)
+    graph = gpu_lib.Context(0)
+    graph.set_option(gpu_lib.OPT_GRAPHS, 1)
+    return plain, graph
+
+
+def _eager_noise(step):
+    """Unrelated eager device work between replays, then a full sync."""
+    x = torch.arange(4096, device="cuda:0", dtype=torch.int64) * (step + 1)
+    y = torch.cumsum(x, 0)
+    torch.cuda.synchronize()
+    assert int(y[-1]) == int(x.sum()) == 4095 * 4096 // 2 * (step + 1)
+
+
+def test_replays_match_plain_launches(gpu_lib):
+    plain, graph = _ctx_pair(gpu_lib)
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    wd, wp = synth.model("water_dipole_small"), synth.model("water_polarizability")
+    pd_, pp_ = gpu_lib.Model(plain, md), gpu_lib.Model(plain, mp)
+    gd_, gp_ = gpu_lib.Model(graph, md), gpu_lib.Model(graph, mp)
+    pwd, pwp = gpu_lib.Model(plain, wd), gpu_lib.Model(plain, wp)
+    gwd, gwp = gpu_lib.Model(graph, wd), gpu_lib.Model(graph, wp)
+    mols = synth.molecules(64, seed=31)
+    # molecule batches of 5..7 frames (same frame bucket, different atom counts)
+    inputs = [("mol", mols.subset(range(s, s + n))) for s, n in [(0, 5), (9, 6), (20, 7), (40, 5)]]
+    inputs += [("water", synth.water_small(k, seed=40 + k)) for k in (2, 3)]
+    for rep in range(4):
+        for label, fr in inputs:
+            if label == "mol":
+                g = gpu_lib.tnep_eval_dipole_polarizability(graph, gd_, gp_, fr)
+                _eager_noise(rep)
+                p = gpu_lib.tnep_eval_dipole_polarizability(plain, pd_, pp_, fr)
+            else:
+                g = gpu_lib.tnep_eval_dipole_polarizability(graph, gwd, gwp, fr)
+                _eager_noise(rep)
+                p = gpu_lib.tnep_eval_dipole_polarizability(plain, pwd, pwp, fr)
+            for a, b in zip(g, p):
+                assert np.array_equal(a, b), (rep, label, fr.n_frames)
+    captures, launches = graph.graph_counts()
+    print("graph captures", captures, "launches", launches, flush=True)
+    assert launches >= 4 * len(inputs)
+    assert 1 <= captures < launches
+    assert plain.graph_counts() == (0, 0)
+    # and the replayed results are right, not only equal to each other
+    fr = inputs[1][1]
+    mu, al = gpu_lib.tnep_eval_dipole_polarizability(graph, gd_, gp_, fr)
+    for out, m in ((mu, md), (al, mp)):
+        ref, pa = oracle.eval_frames(m, fr, per_atom=True)
+        assert np.all(frame_errors(out, ref, pa, fr.offsets) <= TENSOR_TOL)
+    for c in (plain, graph):
+        c.close()
+
+
+def test_replays_with_per_atom_and_batches(gpu_lib):
+    """Per-atom outputs and calls split into several launch batches."""
+    plain, graph = _ctx_pair(gpu_lib)
+    for c in (plain, graph):
+        c.set_option(gpu_lib.OPT_MAX_BATCH_ATOMS, 700)
+    m = synth.model("molecule_polarizability")
+    pm, gm = gpu_lib.Model(plain, m), gpu_lib.Model(graph, m)
+    mols = synth.molecules(120, seed=32)
+    for rep in range(3):
+        for lo, hi in [(0, 40), (40, 100), (100, 120)]:
+            fr = mols.subset(range(lo, hi))
+            pa_g = np.zeros((fr.n_atoms, 9))
+            pa_p = np.zeros((fr.n_atoms, 9))
+            g = gpu_lib.tnep_eval_polarizability(graph, gm, fr, per_atom=pa_g)
+            _eager_noise(rep)
+            p = gpu_lib.tnep_eval_polarizability(plain, pm, fr, per_atom=pa_p)
+            assert np.array_equal(g, p)
+            assert np.array_equal(pa_g, pa_p)
+    captures, launches = graph.graph_counts()
+    assert launches > captures >= 1
+    for c in (plain, graph):
+        c.close()
+
+
+def test_capacity_growth_recaptures(gpu_lib):
+    """A denser input grows the neighbour capacities: graphs are recaptured."""
+    plain, graph = _ctx_pair(gpu_lib)
+    m = synth.model("perovskite_susceptibility")
+    pm, gm = gpu_lib.Model(plain, m), gpu_lib.Model(graph, m)
+    small = synth.perovskite(2, n_rep=4, seed=6)
+    dense = synth.perovskite(2, n_rep=4, seed=7, sigma=0.3)
+    for rep in range(2):
+        for fr in (small, dense, small):
+            g = gpu_lib.tnep_eval_polarizability(graph, gm, fr)
+            _eager_noise(rep)
+            p = gpu_lib.tnep_eval_polarizability(plain, pm, fr)
+            assert np.array_equal(g, p)
+    captures, launches = graph.graph_counts()
+    assert captures >= 1 and launches >= 6
+    for c in (plain, graph):
+        c.close()
+
+
+def test_server_slots_use_graphs(gpu_lib):
+    """Server slot contexts inherit graphs; results equal the plain path."""
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    plain = gpu_lib.Context(0)
+    pm = {1: gpu_lib.Model(plain, md), 2: gpu_lib.Model(plain, mp)}
+    ctx = gpu_lib.Context(0)
+    ctx.set_option(gpu_lib.OPT_GRAPHS, 1)
+    sm = {1: gpu_lib.Model(ctx, md), 2: gpu_lib.Model(ctx, mp)}
+    mols = synth.molecules(300, seed=33)
+    rng = np.random.default_rng(5)
+    reqs = []
+    for k in range(40):
+        s = int(rng.integers(0, 290))
+        reqs.append((1 + k % 2, mols.subset(range(s, s + 1 + int(rng.integers(0, 8))))))
+    srv = gpu_lib.Server(ctx, max_batch_atoms=1500, max_inflight=2)
+    results = []
+    for wave in range(2):
+        tickets = [srv.submit(sm[kind], fr) for kind, fr in reqs]
+        for t in tickets:
+            st, _, out = srv.wait(t)
+            assert st == 0
+            results.append(out.copy())
+        _eager_noise(wave)
+    captures, launches = ctx.graph_counts()
+    srv.stop()
+    assert launches > captures >= 1
+    for i, (kind, fr) in enumerate(reqs + reqs):
+        f = gpu_lib.tnep_eval_dipole if kind == 1 else gpu_lib.tnep_eval_polarizability
+        ref = np.asarray(f(plain, pm[kind], fr)).reshape(fr.n_frames, -1)
+        assert np.array_equal(ref, results[i]), i
+    for c in (plain, ctx):
+        c.close()
