@@ -197,8 +197,9 @@ def bench_serving(args):
     md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
     total_af = sum(fr.n_atoms for _, fr in reqs)
 
-    def run_server(qps, seed):
+    def run_server(qps, seed, graphs=False):
         ctx = tnep.Context(0, budget_bytes=32 << 30)
+        ctx.set_option(tnep.OPT_GRAPHS, int(graphs))
         gm = {1: tnep.Model(ctx, md), 2: tnep.Model(ctx, mp)}
         srv = tnep.Server(ctx, budget_bytes=32 << 30, max_batch_atoms=1 << 19, max_inflight=3)
         # warm-up: one request of each kind
@@ -235,11 +236,12 @@ def bench_serving(args):
         lat = np.array(lat) * 1e3
         return {"qps": qps, "atom_frames_per_s": total_af / wall, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "launches": stats["launches"],
-                "peak_device_bytes": stats["peak_bytes"]}
+                "peak_device_bytes": stats["peak_bytes"], "graphs": graphs}
 
-    def run_plain(qps, seed):
+    def run_plain(qps, seed, graphs=False):
         """Single FIFO worker, one synchronous evaluation call per frame."""
         ctx = tnep.Context(0)
+        ctx.set_option(tnep.OPT_GRAPHS, int(graphs))
         gm = {1: tnep.Model(ctx, md), 2: tnep.Model(ctx, mp)}
         for kind, fr in reqs[:4]:
             (tnep.tnep_eval_dipole if kind == 1 else tnep.tnep_eval_polarizability)(ctx, gm[kind], fr)
@@ -259,16 +261,45 @@ def bench_serving(args):
         ctx.close()
         lat = np.array(lat) * 1e3
         return {"qps": qps, "atom_frames_per_s": total_af / wall, "p50_ms": float(np.percentile(lat, 50)),
-                "p99_ms": float(np.percentile(lat, 99))}
+                "p99_ms": float(np.percentile(lat, 99)), "graphs": graphs}
+
+    def call_latency(graphs, n_calls=300):
+        """Wall time of one synchronous host-to-host call on a small input."""
+        ctx = tnep.Context(0)
+        ctx.set_option(tnep.OPT_GRAPHS, int(graphs))
+        gm = {1: tnep.Model(ctx, md), 2: tnep.Model(ctx, mp)}
+        mol = synth.molecules(4, seed=9)
+        res = {}
+        for label, fr in (("1 molecule frame", mol.subset([0])), ("4 molecule frames", mol)):
+            for kind in (1, 2):
+                f = tnep.tnep_eval_dipole if kind == 1 else tnep.tnep_eval_polarizability
+                for _ in range(10):
+                    f(ctx, gm[kind], fr)
+                ts = []
+                for _ in range(n_calls):
+                    t0 = time.perf_counter()
+                    f(ctx, gm[kind], fr)
+                    ts.append(time.perf_counter() - t0)
+                ts = np.array(ts) * 1e3
+                res["%s %s" % (label, "dipole" if kind == 1 else "polarizability")] = {
+                    "p50_ms": float(np.percentile(ts, 50)), "p99_ms": float(np.percentile(ts, 99))}
+        res["graph_captures_launches"] = list(ctx.graph_counts())
+        ctx.close()
+        return res
 
     sat = run_server(0, 1)
+    sat_g = run_server(0, 1, graphs=True)
     sat_qps = len(reqs) / (total_af / sat["atom_frames_per_s"])
     plain_sat = run_plain(0, 1)
+    plain_sat_g = run_plain(0, 1, graphs=True)
     loads = []
     for frac in (0.25, 0.5, 0.8, 0.95):
         loads.append(dict(run_server(frac * sat_qps, 10 + int(100 * frac)), load=frac))
+        loads.append(dict(run_server(frac * sat_qps, 10 + int(100 * frac), graphs=True), load=frac))
     plain_qps = len(reqs) / (total_af / plain_sat["atom_frames_per_s"])
     plain_half = dict(run_plain(0.5 * plain_qps, 60), load=0.5)
+    plain_half_g = dict(run_plain(0.5 * plain_qps, 60, graphs=True), load=0.5)
+    small_calls = {"plain launches": call_latency(False), "graph replay": call_latency(True)}
     print(json.dumps({
         "metric": "TNEP atom-frames/s (dipole+polarizability) at FP32 tol; p50/p99 request latency",
         "value": sat["atom_frames_per_s"], "unit": "atom-frames/s", "n_gpus": 1, "dtype": "f32",
@@ -276,8 +307,10 @@ def bench_serving(args):
         "config": {"workload": "serving: Poisson arrivals, %d requests (water boxes 192-24000 atoms / vacuum "
                                "molecules, 1-64 frames each, dipole or polarizability), 32 GB budget" % len(reqs),
                    "atom_frames": total_af},
-        "saturation": sat, "saturation_qps": sat_qps, "poisson_loads": loads,
-        "plain_per_frame_path": {"saturation": plain_sat, "at_half_load": plain_half}}), flush=True)
+        "saturation": sat, "saturation_with_graphs": sat_g, "saturation_qps": sat_qps, "poisson_loads": loads,
+        "plain_per_frame_path": {"saturation": plain_sat, "saturation_with_graphs": plain_sat_g,
+                                 "at_half_load": plain_half, "at_half_load_with_graphs": plain_half_g},
+        "small_call_latency": small_calls}), flush=True)
 
 
 def main():
