@@ -3,8 +3,9 @@
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the HIP library.
 
-* tensor evaluation (Eqs. virial, mu, polarizability-model) lives in
-  ``tnep_oracle.c`` and is reached through ctypes;
+* tensor evaluation (Eqs. virial, mu, polarizability-model) and the
+  potential-energy surface of Sec. 2.1 (energy, virial, forces) live in
+  ``tnep_oracle.c`` and are reached through ctypes;
 * the spectrum step (Sec. 2.6 The IR intensity, Sec. 2.7 The Raman
   intensity: time-origin-averaged correlation
   functions, their Fourier transform, the omega^2 IR prefactor and the
@@ -90,6 +91,10 @@ def _lib_handle():
             lib.or_eval_frames.restype = C.c_int
             lib.or_eval_frames.argtypes = [P(_Model), C.c_int, P(C.c_int64), P(C.c_double), P(C.c_int32),
                                            P(C.c_double), P(C.c_uint8), P(C.c_double), P(C.c_double)]
+            lib.or_eval_pes.restype = C.c_int
+            lib.or_eval_pes.argtypes = [P(_Model), C.c_int, P(C.c_int64), P(C.c_double), P(C.c_int32),
+                                        P(C.c_double), P(C.c_uint8), P(C.c_double), P(C.c_double),
+                                        P(C.c_double), P(C.c_double)]
             lib.or_init()
             _lib = lib
     return _lib
@@ -261,6 +266,32 @@ def eval_frames(m, frames, per_atom=False):
         if pa is not None:
             pa = pa.reshape(-1, 3, 3)
     return (out, pa) if per_atom else out
+
+
+def eval_pes(m, frames, per_atom=False):
+    """Potential-energy surface model (kind 3, Sec. 2.1): per frame the energy
+    U = sum_i U_i [F], the virial W = -sum_i sum_j r_ij (x) dU_i/dr_ij [F,3,3]
+    and the forces F_k = -dU/dr_k [A,3], FP64.  per_atom=True adds U_i [A]."""
+    om = _model(m)
+    lib = _lib_handle()
+    F = frames.n_frames
+    energy = np.zeros(F)
+    virial = np.zeros((F, 9))
+    forces = np.zeros((frames.n_atoms, 3))
+    pa = np.zeros(frames.n_atoms) if per_atom else None
+    offs = np.ascontiguousarray(frames.offsets.astype(np.int64))
+    pos = np.ascontiguousarray(frames.positions.astype(np.float64))
+    spc = np.ascontiguousarray(frames.species.astype(np.int32))
+    cells = None if frames.cells is None else np.ascontiguousarray(frames.cells.astype(np.float64))
+    pbc = None if frames.pbc is None else np.ascontiguousarray(frames.pbc.astype(np.uint8))
+    e = lib.or_eval_pes(C.byref(om.s), F, offs.ctypes.data_as(C.POINTER(C.c_int64)), _dp(pos),
+                        spc.ctypes.data_as(C.POINTER(C.c_int32)), _dp(cells),
+                        None if pbc is None else pbc.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(energy),
+                        _dp(virial), _dp(forces), _dp(pa))
+    if e:
+        raise OracleError(e)
+    out = (energy, virial.reshape(F, 3, 3), forces)
+    return out + (pa,) if per_atom else out
 
 
 # -------------------------------------------------------------------------

@@ -11,6 +11,8 @@
  *   - virial  W = -sum_i sum_{j!=i} r_ij (x) dU_i/dr_ij         (Sec. 2.1, Eq. virial)
  *   - dipole  mu = -sum_i sum_{j!=i} r_ij^2 dU_i/dr_ij          (Sec. 2.2, Eq. mu)
  *   - polarizability alpha = sum_i U_i I + W                    (Sec. 2.3, Eq. polarizability-model)
+ *   - potential-energy surface (Sec. 2.1): energy U, virial W and forces
+ *     F_k = -dU/dr_k = sum_j dU_k/dr_kj - sum_i dU_i/dr_ik
  * with r_ij = r_j - r_i (Sec. 2.1, text after Eq. virial).
  *
  * The descriptor q_i is only cited by the paper (NEP, Sec. 2.1); this file
@@ -48,7 +50,8 @@ enum { OR_OK = 0, OR_E_INVALID = -1, OR_E_SPECIES = -2, OR_E_BOX = -3,
 
 /* Model as seen by the oracle (own definition; mirrors the paper's notions). */
 typedef struct {
-    int32_t kind;       /* 1 = dipole (tensor head only), 2 = polarizability (tensor + scalar head) */
+    int32_t kind;       /* 1 = dipole (tensor head only), 2 = polarizability (tensor + scalar head),
+                           3 = potential-energy surface (one head: the site energy) */
     int32_t n_species;
     double rc_radial, rc_angular;
     int32_t n_max_radial, n_max_angular; /* number of functions = n_max + 1 */
@@ -632,6 +635,115 @@ int or_eval_frames(const or_model* mdl, int n_frames, const int64_t* atom_offset
         }
         if (per_atom) memcpy(per_atom + (size_t)a0 * nt, tens, sizeof(double) * nt * n_at);
         free(tens);
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Potential-energy surface (kind 3): per frame U = sum_i U_i (Sec. 2.1, Eq.  */
+/* site-energy), W = -sum_i sum_j r_ij (x) dU_i/dr_ij (Sec. 2.1, Eq. virial)  */
+/* and forces F_k = -dU/dr_k.  With r_ij = r_j - r_i, dr_ij/dr_k is +1 for    */
+/* j = k and -1 for i = k, so atom i gets +dU_i/dr_ij and atom j gets          */
+/* -dU_i/dr_ij from every pair (i, j).                                         */
+
+typedef struct {
+    int n;
+    int32_t* j;   /* frame-local neighbour index */
+    double* dudr; /* [n][3] dU_i/dr_ij */
+} pes_pairs;
+
+int or_eval_pes(const or_model* mdl, int n_frames, const int64_t* atom_offsets, const double* pos,
+                const int32_t* species, const double* cells, const uint8_t* pbc, double* energy, double* virial,
+                double* forces, double* per_atom_energy) {
+    or_init();
+    if (mdl->kind != 3) return OR_E_INVALID;
+    for (int f = 0; f < n_frames; ++f) {
+        const int64_t a0 = atom_offsets[f], a1 = atom_offsets[f + 1];
+        const int n_at = (int)(a1 - a0);
+        double L[3];
+        int per[3];
+        int e = frame_box(cells ? cells + 9 * f : NULL, pbc ? pbc + 3 * f : NULL, mdl->rc_radial, L, per);
+        if (e) return e;
+        for (int64_t a = a0; a < a1; ++a)
+            for (int d = 0; d < 3; ++d)
+                if (!isfinite(pos[3 * a + d])) return OR_E_NONFINITE;
+        const double* p = pos + 3 * a0;
+        const int32_t* spc = species + a0;
+        const int nn = n_at > 0 ? n_at : 1;
+        double* U = (double*)malloc(sizeof(double) * nn);
+        double* W = (double*)malloc(sizeof(double) * 9 * nn);
+        pes_pairs* pairs = (pes_pairs*)calloc((size_t)nn, sizeof(pes_pairs));
+        int err = 0;
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int i = 0; i < n_at; ++i) {
+            const double rc = mdl->rc_radial;
+            int n = 0;
+            for (int j = 0; j < n_at; ++j) {
+                if (j == i) continue;
+                double v[3];
+                pair_vector(p + 3 * i, p + 3 * j, L, per, v);
+                if (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] < rc * rc) ++n;
+            }
+            double* vec = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+            int32_t* tj = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+            int32_t* jj = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+            double* dudr = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+            int k = 0;
+            for (int j = 0; j < n_at; ++j) {
+                if (j == i) continue;
+                double v[3];
+                pair_vector(p + 3 * i, p + 3 * j, L, per, v);
+                if (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] < rc * rc) {
+                    memcpy(vec + 3 * k, v, sizeof(v));
+                    tj[k] = spc[j];
+                    jj[k] = j;
+                    ++k;
+                }
+            }
+            int ei = or_atom_eval(mdl, 0, spc[i], n, vec, tj, &U[i], NULL, NULL, dudr);
+            for (int c = 0; c < 9; ++c) W[9 * i + c] = 0.0;
+            for (int q = 0; q < n && !ei; ++q)
+                for (int u = 0; u < 3; ++u)
+                    for (int w = 0; w < 3; ++w) W[9 * i + 3 * u + w] -= vec[3 * q + u] * dudr[3 * q + w];
+            pairs[i].n = n;
+            pairs[i].j = jj;
+            pairs[i].dudr = dudr;
+            free(vec);
+            free(tj);
+            if (ei) {
+#pragma omp critical
+                err = ei;
+            }
+        }
+        if (!err) {
+            double* F = forces + 3 * a0;
+            for (int i = 0; i < 3 * n_at; ++i) F[i] = 0.0;
+            for (int i = 0; i < n_at; ++i)
+                for (int q = 0; q < pairs[i].n; ++q) {
+                    const int j = pairs[i].j[q];
+                    for (int d = 0; d < 3; ++d) {
+                        F[3 * i + d] += pairs[i].dudr[3 * q + d];
+                        F[3 * j + d] -= pairs[i].dudr[3 * q + d];
+                    }
+                }
+            double es = 0.0;
+            for (int i = 0; i < n_at; ++i) es += U[i];
+            energy[f] = es;
+            for (int c = 0; c < 9; ++c) {
+                double s = 0.0;
+                for (int i = 0; i < n_at; ++i) s += W[9 * i + c];
+                virial[(size_t)9 * f + c] = s;
+            }
+            if (per_atom_energy) memcpy(per_atom_energy + a0, U, sizeof(double) * n_at);
+        }
+        for (int i = 0; i < n_at; ++i) {
+            free(pairs[i].j);
+            free(pairs[i].dudr);
+        }
+        free(pairs);
+        free(U);
+        free(W);
+        if (err) return err;
     }
     return OR_OK;
 }

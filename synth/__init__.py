@@ -23,6 +23,7 @@ import numpy as np
 
 KIND_DIPOLE = 1
 KIND_POLARIZABILITY = 2
+KIND_PES = 3  # potential-energy surface: one head, the site energy
 
 WATER_SPECIES = ("O", "H")
 PEROVSKITE_SPECIES = ("Ba", "Zr", "O")
@@ -227,8 +228,9 @@ class Head:
 
 @dataclasses.dataclass
 class Model:
-    """TNEP parameter set.  heads[0] is the tensor head (virial term);
-    heads[1], polarizability only, is the scalar head (the U_i delta term)."""
+    """TNEP parameter set.  heads[0] is the tensor head (virial term; for a
+    potential-energy model, the site energy); heads[1], polarizability only,
+    is the scalar head (the U_i delta term)."""
 
     kind: int
     species: tuple
@@ -290,7 +292,7 @@ def make_model(seed: int, kind: int, species, rc_radial: float, rc_angular: floa
     na = n_max_angular + 1
     D = n_max_radial + 1 + na * l_max + (na if four_body else 0)
     heads = []
-    for _ in range(1 if kind == KIND_DIPOLE else 2):
+    for _ in range(2 if kind == KIND_POLARIZABILITY else 1):
         heads.append(Head(rng.normal(0.0, scale, (n_hidden, D)), rng.normal(0.0, scale, n_hidden),
                           rng.normal(0.0, scale, n_hidden), float(rng.normal(0.0, scale))))
     qs = np.ones(D) if q_scaler is None else np.asarray(q_scaler, np.float64)
@@ -314,6 +316,8 @@ MODEL_SPECS = {
     "perovskite_susceptibility": (103, KIND_POLARIZABILITY, PEROVSKITE_SPECIES, PEROVSKITE_DESCRIPTOR),
     "molecule_dipole": (104, KIND_DIPOLE, MOLECULE_SPECIES, WATER_DESCRIPTOR),
     "molecule_polarizability": (105, KIND_POLARIZABILITY, MOLECULE_SPECIES, WATER_DESCRIPTOR),
+    "water_pes": (106, KIND_PES, WATER_SPECIES, WATER_DESCRIPTOR),
+    "molecule_pes": (107, KIND_PES, MOLECULE_SPECIES, WATER_DESCRIPTOR),
 }
 
 

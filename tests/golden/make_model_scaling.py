@@ -22,7 +22,7 @@ import synth  # noqa: E402
 def reference_frames(name):
     if name == "water_dipole_small":
         return synth.water_small(1), [0]
-    if name in ("water_dipole", "water_polarizability"):
+    if name in ("water_dipole", "water_polarizability", "water_pes"):
         pos, spc, cell = synth.water_large_reference()
         fr = synth.Frames(np.array([0, len(spc)], np.int64), pos, spc, cell[None], np.ones((1, 3), np.uint8))
         return fr, [0]
