@@ -63,6 +63,8 @@ extern "C" {
 
 #define TNEP_KIND_DIPOLE 1         /* rank-1: one tensor head               */
 #define TNEP_KIND_POLARIZABILITY 2 /* rank-2: tensor head + scalar head     */
+#define TNEP_KIND_PES 3            /* potential-energy surface (Sec. 2.1): one head, the site
+                                      energy U_i; hidden layer always FP32 vector ALU */
 
 /* precision of the hidden layer (option TNEP_OPT_MLP) */
 #define TNEP_MLP_FP32_VALU 0  /* FP32 vector ALU                           */
@@ -94,6 +96,7 @@ extern "C" {
 #define TNEP_KERNEL_EVAL_POLARIZABILITY 2
 #define TNEP_KERNEL_FRAME_REDUCE 3
 #define TNEP_KERNEL_SPECTRUM 4
+#define TNEP_KERNEL_EVAL_PES 5
 
 /* ---- opaque handles ---------------------------------------------------- */
 typedef struct tnep_ctx tnep_ctx;
@@ -106,7 +109,7 @@ typedef struct tnep_model tnep_model;
  * ordered [q^R_0..q^R_nR | l=1: q_{0,1}..q_{nA,1} | ... | l=l_max | q4_0..q4_nA].
  * Network (per head): U = sum_m w1[m] tanh(sum_n w0[m][n] q_scaler[n] q[n] - b0[m]) - b1. */
 typedef struct {
-    int32_t kind;          /* TNEP_KIND_DIPOLE or TNEP_KIND_POLARIZABILITY          */
+    int32_t kind;          /* TNEP_KIND_DIPOLE, TNEP_KIND_POLARIZABILITY or TNEP_KIND_PES */
     int32_t n_species;     /* T                                                      */
     double rc_radial;      /* radial cutoff r_c^R, Angstrom                          */
     double rc_angular;     /* angular cutoff r_c^A <= r_c^R                          */
@@ -202,6 +205,21 @@ int tnep_eval_dipole_polarizability(tnep_ctx* ctx, const tnep_model* dipole_mode
                                     const tnep_model* polarizability_model, const tnep_frames* frames,
                                     double* mu_out, double* alpha_out);
 
+/* Potential-energy surface of every frame (Sec. 2.1) with a TNEP_KIND_PES
+ * model, whose one head gives the site energies U_i:
+ *   energy  [n_frames]        U = sum_i U_i (Eq. site-energy), FP64;
+ *   virial  [n_frames][9]     W = -sum_i sum_j r_ij (x) dU_i/dr_ij (Eq. virial),
+ *                             row-major (u, v); NULL to skip;
+ *   forces  [total_atoms][3]  F_k = -dU/dr_k = sum_j dU_k/dr_kj - sum_i dU_i/dr_ik
+ *                             (r_ij = r_j - r_i), input atom order; NULL to skip;
+ *   per_atom_energy [total_atoms] U_i; NULL to skip.
+ * Forces are summed as 64-bit fixed-point integers (resolution 2^-32 in model
+ * units per Angstrom), so they do not depend on the order of the sums;
+ * TNEP_E_NONFINITE if a pair term reaches 2^20 in magnitude.  Location,
+ * ownership and errors as for tnep_eval_dipole. */
+int tnep_eval_pes(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames, double* energy,
+                  double* virial, double* forces, double* per_atom_energy);
+
 /* ---- spectra ----------------------------------------------------------- */
 #define TNEP_IR 0          /* series rank 1 [.][3]: (1/3) sum_a <mu_a(0) mu_a(t)>, x w^2      */
 #define TNEP_RAMAN_ISO 1   /* rank 2 [.][9]: <gamma(0) gamma(t)>, gamma = Tr(alpha)/3         */
@@ -250,7 +268,8 @@ typedef struct {
  * ctx.  Slot contexts inherit the launch options of ctx, TNEP_OPT_GRAPHS included. */
 int tnep_server_start(tnep_ctx* ctx, const tnep_server_opts* opts);
 /* Queue one request: `kind` selects dipole (out [n_frames][3]) or
- * polarizability (out [n_frames][9]); frames and out must be host memory and
+ * polarizability (out [n_frames][9]); potential-energy models are not served
+ * (TNEP_E_INVALID).  frames and out must be host memory and
  * stay valid until tnep_wait returns for the ticket.  Returns TNEP_E_BUDGET
  * if the request alone can never fit the admission budget. */
 int tnep_submit(tnep_ctx* ctx, const tnep_model* model, int32_t kind, const tnep_frames* frames, double* out,

@@ -186,7 +186,7 @@ extern "C" uint64_t tnep_ctx_memory_in_use(const tnep_ctx* ctx) {
 }
 
 extern "C" int tnep_ctx_kernel_time(const tnep_ctx* ctx, int32_t which, double* total_ms, uint64_t* launches) {
-    if (!ctx || which < 0 || which > TNEP_KERNEL_SPECTRUM) return TNEP_E_INVALID;
+    if (!ctx || which < 0 || which > TNEP_KERNEL_EVAL_PES) return TNEP_E_INVALID;
     const Ctx* c = reinterpret_cast<const Ctx*>(ctx);
     if (total_ms) *total_ms = c->kernel_ms[which];
     if (launches) *launches = c->kernel_launches[which];
@@ -278,7 +278,7 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
     if (!ctx || !d || !out) return TNEP_E_INVALID;
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
     *out = nullptr;
-    if (d->kind != TNEP_KIND_DIPOLE && d->kind != TNEP_KIND_POLARIZABILITY)
+    if (d->kind != TNEP_KIND_DIPOLE && d->kind != TNEP_KIND_POLARIZABILITY && d->kind != TNEP_KIND_PES)
         return c->fail(TNEP_E_MODEL, "unknown model kind %d", d->kind);
     if (d->n_species < 1 || d->n_species > 8) return c->fail(TNEP_E_MODEL, "n_species must be 1..8");
     if (!(d->rc_radial > 0) || !(d->rc_angular > 0) || d->rc_angular > d->rc_radial)
@@ -523,6 +523,25 @@ extern "C" int tnep_eval_dipole_polarizability(tnep_ctx* ctx, const tnep_model* 
     job.out[0] = mu_out;
     job.out[1] = alpha_out;
     job.n_models = 2;
+    return run_eval(c, *frames, job);
+}
+
+extern "C" int tnep_eval_pes(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames, double* energy,
+                             double* virial, double* forces, double* per_atom_energy) {
+    if (!ctx) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    const Model* m = reinterpret_cast<const Model*>(model);
+    if (!m || m->kind != TNEP_KIND_PES) return c->fail(TNEP_E_INVALID, "a potential-energy model is required");
+    int e = check_frames(c, frames);
+    if (e) return e;
+    if (frames->n_frames > 0 && !energy) return c->fail(TNEP_E_INVALID, "energy is NULL");
+    EvalJob job;
+    job.models[0] = m;
+    job.out[0] = energy;
+    job.aux[0] = virial;
+    job.per_atom[0] = per_atom_energy;
+    job.forces = forces;
+    job.n_models = 1;
     return run_eval(c, *frames, job);
 }
 

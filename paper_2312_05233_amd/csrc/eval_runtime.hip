@@ -316,8 +316,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             // batch size in atoms
             int64_t largest = 0;
             for (int f = 0; f < F; ++f) largest = std::max(largest, meta.offs[f + 1] - meta.offs[f]);
-            const int64_t per_atom_bytes = (int64_t)slots * 16 + 8 * T + 24 + 72 * (last - first) +
-                                           (fr.location == TNEP_HOST ? 28 : 0);
+            bool pes = false;
+            for (int k = first; k < last; ++k) pes = pes || job.models[k]->kind == TNEP_KIND_PES;
+            const int64_t per_atom_bytes = (int64_t)slots * 16 + 8 * T + 24 + 80 * (last - first) +
+                                           (fr.location == TNEP_HOST ? 28 : 0) + (pes ? 24 + 32 : 0);
             int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
             B = std::max(B, largest);
             const int64_t room = (int64_t)c->budget - (int64_t)(c->in_use - c->nbr.bytes - c->per_atom.bytes);
@@ -352,7 +354,12 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if ((e = c->reserve(c->key_of, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->bucket_atoms, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->bucket_pos, (size_t)B_res * 32))) return e;
-            if ((e = c->reserve(c->per_atom, (size_t)B_res * 9 * sizeof(double) * (last - first)))) return e;
+            if ((e = c->reserve(c->per_atom, (size_t)B_res * 10 * sizeof(double) * (last - first)))) return e;
+            if (pes) {
+                if ((e = c->reserve(c->force_acc, (size_t)B_res * 3 * sizeof(unsigned long long)))) return e;
+                if (fr.location == TNEP_HOST && (e = c->reserve(c->pes_stage, (size_t)B_res * 4 * sizeof(double))))
+                    return e;
+            }
             if ((e = c->reserve(c->flags, 32 * 4))) return e;
             if (fr.location == TNEP_HOST) {
                 if ((e = c->reserve(c->pos, (size_t)B_res * 24))) return e;
@@ -410,7 +417,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if ((e = c->reserve(c->bucket_fill, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->perm_start, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->scan_chunks, (size_t)4 * 18 * (cap_cells / 1024 + 1)))) return e;
-                const int nt_max = 9;
+                const int nt_max = 10;
                 if ((e = c->reserve(c->out, sizeof(double) * nt_max * cap_frames * (last - first)))) return e;
                 bh.sizes[0] = (int32_t)na;
                 bh.sizes[1] = nf;
@@ -444,16 +451,36 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 nl.n_pad = (cap_atoms + 63) / 64 * 64 + 64 * T;
                 nl.T = T;
                 nl.slots = slots;
+                // per model: per-atom records, per-frame outputs (a: tensor or
+                // energy, b: virial of a potential-energy model)
                 double* pa_of[2];
                 double* out_of[2];
+                double* aux_of[2] = {nullptr, nullptr};
+                int nt_of[2], na_of[2];
+                double *forces_dst = nullptr, *energies_dst = nullptr;
                 for (int k = first; k < last; ++k) {
-                    const int nt = job.models[k]->kind == TNEP_KIND_DIPOLE ? 3 : 9;
-                    pa_of[k - first] = (double*)c->per_atom.p + (size_t)B_res * 9 * (k - first);
-                    if (job.per_atom[k] && fr.location == TNEP_DEVICE) pa_of[k - first] = job.per_atom[k] + a0 * nt;
-                    out_of[k - first] = fr.location == TNEP_DEVICE
-                                            ? job.out[k] + (size_t)f0 * nt
-                                            : (double*)c->out.p + (size_t)nt_max * cap_frames * (k - first);
+                    const int kind = job.models[k]->kind;
+                    const int q = k - first;
+                    nt_of[q] = kind == TNEP_KIND_DIPOLE ? 3 : (kind == TNEP_KIND_POLARIZABILITY ? 9 : 10);
+                    na_of[q] = kind == TNEP_KIND_PES ? 1 : nt_of[q];
+                    pa_of[q] = (double*)c->per_atom.p + (size_t)B_res * 10 * q;
+                    if (kind != TNEP_KIND_PES && job.per_atom[k] && fr.location == TNEP_DEVICE)
+                        pa_of[q] = job.per_atom[k] + a0 * nt_of[q];
+                    double* staged = (double*)c->out.p + (size_t)nt_max * cap_frames * q;
+                    out_of[q] = fr.location == TNEP_DEVICE ? job.out[k] + (size_t)f0 * na_of[q] : staged;
+                    if (kind == TNEP_KIND_PES) {
+                        if (fr.location == TNEP_DEVICE) {
+                            aux_of[q] = job.aux[k] ? job.aux[k] + (size_t)f0 * 9 : nullptr;
+                            forces_dst = job.forces ? job.forces + a0 * 3 : nullptr;
+                            energies_dst = job.per_atom[k] ? job.per_atom[k] + a0 : nullptr;
+                        } else {
+                            aux_of[q] = staged + cap_frames;
+                            forces_dst = job.forces ? (double*)c->pes_stage.p : nullptr;
+                            energies_dst = job.per_atom[k] ? (double*)c->pes_stage.p + 3 * B_res : nullptr;
+                        }
+                    }
                 }
+                const PesOut pes_out{(unsigned long long*)c->force_acc.p, (int32_t*)c->flags.p};
                 // the batch's kernels; with graphs on, captured once and replayed
                 auto launch_batch = [&]() -> hipError_t {
                     hipError_t he;
@@ -469,15 +496,23 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     }
                     for (int k = first; k < last; ++k) {
                         const Model* m = job.models[k];
-                        const int nt = m->kind == TNEP_KIND_DIPOLE ? 3 : 9;
-                        tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE ? TNEP_KERNEL_EVAL_DIPOLE
-                                                                        : TNEP_KERNEL_EVAL_POLARIZABILITY);
-                        he = launch_eval(m->shape, m->dm, nl, pa_of[k - first], c->launch, c->stream);
+                        const int q = k - first;
+                        if (m->kind == TNEP_KIND_PES) {
+                            he = launch_pes_clear(pes_out.force_acc, cap_atoms, c->stream);
+                            if (he != hipSuccess) return he;
+                        }
+                        tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE           ? TNEP_KERNEL_EVAL_DIPOLE
+                                            : m->kind == TNEP_KIND_POLARIZABILITY ? TNEP_KERNEL_EVAL_POLARIZABILITY
+                                                                                  : TNEP_KERNEL_EVAL_PES);
+                        he = launch_eval(m->shape, m->dm, nl, pa_of[q], pes_out, c->launch, c->stream);
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;
                         tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);
-                        he = launch_frame_reduce((const FrameInfo*)c->frames.p, cap_frames, nl.meta,
-                                                 pa_of[k - first], nt, out_of[k - first], c->stream);
+                        he = launch_frame_reduce((const FrameInfo*)c->frames.p, cap_frames, nl.meta, pa_of[q],
+                                                 nt_of[q], na_of[q], out_of[q], aux_of[q], c->stream);
+                        if (he == hipSuccess && m->kind == TNEP_KIND_PES)
+                            he = launch_pes_finish(pes_out.force_acc, pa_of[q], nl.meta, cap_atoms, forces_dst,
+                                                   energies_dst, c->stream);
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;
                     }
@@ -492,13 +527,28 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 }
                 if (fr.location == TNEP_HOST) {
                     for (int k = first; k < last; ++k) {
-                        const int nt = job.models[k]->kind == TNEP_KIND_DIPOLE ? 3 : 9;
-                        HIP_CHECK_RET(c, hipMemcpyAsync(job.out[k] + (size_t)f0 * nt, out_of[k - first],
-                                                        sizeof(double) * nt * nf, hipMemcpyDeviceToHost, c->stream));
-                        if (job.per_atom[k])
-                            HIP_CHECK_RET(c, hipMemcpyAsync(job.per_atom[k] + a0 * nt, pa_of[k - first],
-                                                            sizeof(double) * nt * na, hipMemcpyDeviceToHost,
+                        const int q = k - first;
+                        const int na_ = na_of[q];
+                        HIP_CHECK_RET(c, hipMemcpyAsync(job.out[k] + (size_t)f0 * na_, out_of[q],
+                                                        sizeof(double) * na_ * nf, hipMemcpyDeviceToHost, c->stream));
+                        if (job.models[k]->kind == TNEP_KIND_PES) {
+                            if (job.aux[k])
+                                HIP_CHECK_RET(c, hipMemcpyAsync(job.aux[k] + (size_t)f0 * 9, aux_of[q],
+                                                                sizeof(double) * 9 * nf, hipMemcpyDeviceToHost,
+                                                                c->stream));
+                            if (job.forces)
+                                HIP_CHECK_RET(c, hipMemcpyAsync(job.forces + a0 * 3, forces_dst,
+                                                                sizeof(double) * 3 * na, hipMemcpyDeviceToHost,
+                                                                c->stream));
+                            if (job.per_atom[k])
+                                HIP_CHECK_RET(c, hipMemcpyAsync(job.per_atom[k] + a0, energies_dst,
+                                                                sizeof(double) * na, hipMemcpyDeviceToHost,
+                                                                c->stream));
+                        } else if (job.per_atom[k]) {
+                            HIP_CHECK_RET(c, hipMemcpyAsync(job.per_atom[k] + a0 * nt_of[q], pa_of[q],
+                                                            sizeof(double) * nt_of[q] * na, hipMemcpyDeviceToHost,
                                                             c->stream));
+                        }
                     }
                 }
                 f0 = f1;
@@ -513,7 +563,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                  : (fl[kFlagError] & kErrSpecies) ? TNEP_E_SPECIES
                                                                   : TNEP_E_OVERLAP;
                 return c->fail(code, "invalid input (%s) near batch-local atom %d",
-                               code == TNEP_E_NONFINITE ? "non-finite position"
+                               code == TNEP_E_NONFINITE ? "non-finite position, or a force term beyond 2^20"
                                : code == TNEP_E_SPECIES ? "species out of range"
                                                         : "atoms closer than 1e-4 A",
                                fl[kFlagBadAtom]);

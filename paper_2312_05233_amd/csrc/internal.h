@@ -57,7 +57,8 @@ struct Shape {
 // capA[t]) for r < rc_angular (used by the radial and the angular terms) and
 // rows [segR[t], segR[t] + capR[t]) for rc_angular <= r < rc_radial (radial
 // terms only).  Entry (row r) of slot p is the float4 (dx, dy, dz, 0) with
-// r_ij = r_j - r_i, stored at entries[((tile * slots/4 + r/4) * 64 + lane) * 4
+// r_ij = r_j - r_i (x, y, z; w holds the batch-local index j as int bits),
+// stored at entries[((tile * slots/4 + r/4) * 64 + lane) * 4
 // + r % 4]: four consecutive rows of one lane are 64 contiguous bytes.
 // Per-species segment tables live in device memory (meta) so that kernels
 // index them with scalar loads.
@@ -120,21 +121,42 @@ struct EvalLaunch {
     int neigh_block;      // work-group size of the neighbour kernel: 64, 128, 256
 };
 
-// Per-atom tensors (FP64, [n_atoms][3 or 9], batch atom order) of one model.
+// Forces of a potential-energy model: every pair term is added to
+// force_acc[3 * atom + c] as a 64-bit fixed-point integer (value * 2^32), so
+// the sums do not depend on the order of the atomic additions.
+constexpr double kForceScale = 4294967296.0;  // 2^32
+constexpr float kForceTermMax = 1048576.f;    // |pair term| limit (2^20): sums stay below 2^63
+struct PesOut {
+    unsigned long long* force_acc;  // [n_atoms][3] two's-complement fixed point, zeroed before the launch
+    int32_t* flags;        // kFlagError |= kErrNonFinite for terms outside the fixed-point range
+};
+
+// Per-atom records (FP64, batch atom order) of one model: dipole [n][3],
+// polarizability [n][9], potential energy [n][10] = (U_i, W_i row-major).
 bool eval_shape_supported(const Shape& s);
 // Whether the matrix-core hidden layer is compiled for this shape (else the
 // FP32 vector path runs whatever TNEP_OPT_MLP says).
 bool eval_matrix_supported(const Shape& s, int n_hidden);
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
-                       const EvalLaunch& cfg, hipStream_t s);
+                       const PesOut& pes, const EvalLaunch& cfg, hipStream_t s);
+
+// Potential-energy batches: zero the fixed-point force accumulators of the
+// batch (cap_atoms sizes the grid), and afterwards convert them to FP64 forces
+// (forces may be NULL) and copy the site energies (column 0 of the per-atom
+// records, energies may be NULL).
+hipError_t launch_pes_clear(unsigned long long* force_acc, int64_t cap_atoms, hipStream_t s);
+hipError_t launch_pes_finish(const unsigned long long* force_acc, const double* per_atom, const int32_t* meta,
+                             int64_t cap_atoms, double* forces, double* energies, hipStream_t s);
 
 // Add the batch's atom count and neighbour-pair counts to counters[0..2].
 hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* counters, hipStream_t s);
 
-// Per-frame sums of per-atom tensors in a fixed order.
-// Frames beyond meta[kMetaNFrames] are skipped (cap_frames sizes the grid).
+// Per-frame sums of per-atom records (nt <= 10 values) in a fixed order:
+// values 0..na-1 go to out_a[f][na], values na..nt-1 to out_b[f][nt - na]
+// (out_b may be NULL).  Frames beyond meta[kMetaNFrames] are skipped
+// (cap_frames sizes the grid).
 hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const int32_t* meta, const double* per_atom,
-                               int nt, double* out, hipStream_t s);
+                               int nt, int na, double* out_a, double* out_b, hipStream_t s);
 
 // ---- spectra (kernels_spectrum.hip) ----
 struct SpectrumPlan {

@@ -228,14 +228,21 @@ __host__ __device__ constexpr int mlp_lds_floats(int D, int H) {
     return 64 * (((D + 31) / 32 * 32 + 4) + ((H + 31) / 32 * 32 + 4));
 }
 
+// A force term as a 64-bit two's-complement fixed-point integer (x * 2^32,
+// rounded to nearest); integer addition makes the sums order-independent.
+__device__ __forceinline__ unsigned long long to_fixed(float x) {
+    return (unsigned long long)(long long)rint((double)x * kForceScale);
+}
+
 // One lane per tile slot (atom).  The coefficient blocks c[t_i][t] are
 // wave-uniform and read with scalar loads.  MODE selects the hidden layer:
 // FP32 vector ALU (no LDS) or one of the matrix-core variants (LDS tile per
 // wavefront).  Padding lanes run with empty neighbour lists and store nothing.
 template <int NR, int NA, int KR, int KA, bool FOURB, int KIND, int MODE>
-__global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, double* __restrict__ per_atom) {
+__global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, double* __restrict__ per_atom,
+                                                 PesOut pes) {
     constexpr int D = NR + 4 * NA + (FOURB ? NA : 0);
-    constexpr int NT = KIND == 1 ? 3 : 9;
+    constexpr int NT = KIND == 1 ? 3 : 9;  // accumulated tensor: mu, or the virial-like W
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int T = nl.T;
     const int tile = __builtin_amdgcn_readfirstlane((int)(p >> 6));
@@ -339,7 +346,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 #pragma unroll
     for (int v = 0; v < D; ++v) qs[v] *= m.scaler[v];
 
-    float Us = 0.f;
+    float Us = 0.f;  // scalar head (polarizability) or site energy (potential)
     float dq[D];
     if constexpr (MODE == TNEP_MLP_FP32_VALU) {
         const int H = m.n_hidden;
@@ -361,11 +368,13 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float* __restrict__ w0 = m.w0[0];
             const float* __restrict__ b0 = m.b0[0];
             const float* __restrict__ w1 = m.w1[0];
+            if constexpr (KIND == 3) Us = -m.b1[0];
             for (int mu = 0; mu < H; ++mu) {
                 float x = -b0[mu];
 #pragma unroll
                 for (int v = 0; v < D; ++v) x += w0[mu * D + v] * qs[v];
                 const float h = tanhf(x);
+                if constexpr (KIND == 3) Us += w1[mu] * h;
                 const float t = w1[mu] * (1.f - h * h);
 #pragma unroll
                 for (int v = 0; v < D; ++v) dq[v] += t * w0[mu * D + v];
@@ -399,7 +408,24 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     float acc[NT];
 #pragma unroll
     for (int k = 0; k < NT; ++k) acc[k] = 0.f;
-    auto contract = [&](float dx, float dy, float dz, float r2, float Fx, float Fy, float Fz) {
+    float own[3] = {0.f, 0.f, 0.f};  // potential: sum_j dU_i/dr_ij, the atom's own force term
+    bool bad_term = false;
+    // (Fx, Fy, Fz) = dU_i/dr_ij for the pair vector (dx, dy, dz) to neighbour j
+    auto contract = [&](float dx, float dy, float dz, float r2, float Fx, float Fy, float Fz, int j) {
+        if constexpr (KIND == 3) {
+            // F_j -= dU_i/dr_ij (r_ij = r_j - r_i), as fixed-point integers
+            own[0] += Fx;
+            own[1] += Fy;
+            own[2] += Fz;
+            const float f[3] = {Fx, Fy, Fz};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (fabsf(f[c]) < kForceTermMax)
+                    atomicAdd(&pes.force_acc[3 * (int64_t)j + c], to_fixed(-f[c]));
+                else
+                    bad_term = true;
+            }
+        }
         if constexpr (KIND == 1) {
             acc[0] -= r2 * Fx;
             acc[1] -= r2 * Fy;
@@ -480,7 +506,8 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
                 sc += (bv - (float)l * av * rinv) * P;
             });
             const float su = sc + sr;
-            contract(e.x, e.y, e.z, r2, Fx * rinv + ux * su, Fy * rinv + uy * su, Fz * rinv + uz * su);
+            contract(e.x, e.y, e.z, r2, Fx * rinv + ux * su, Fy * rinv + uy * su, Fz * rinv + uz * su,
+                     __float_as_int(e.w));
         }
         nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int s = 0; s < n_rad; ++s) {
@@ -489,11 +516,29 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
             const float rinv = rsqrtf(r2);
             const float su = radial_slope(r2 * rinv) * rinv;
-            contract(e.x, e.y, e.z, r2, e.x * su, e.y * su, e.z * su);
+            contract(e.x, e.y, e.z, r2, e.x * su, e.y * su, e.z * su, __float_as_int(e.w));
         }
     }
 
     if (a < 0) return;
+    if constexpr (KIND == 3) {
+        double* out = per_atom + (int64_t)a * 10;
+        out[0] = (double)Us;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[1 + k] = (double)acc[k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (fabsf(own[c]) < kForceTermMax)
+                atomicAdd(&pes.force_acc[3 * (int64_t)a + c], to_fixed(own[c]));
+            else
+                bad_term = true;
+        }
+        if (bad_term) {
+            atomicOr(&pes.flags[kFlagError], kErrNonFinite);
+            atomicMin(&pes.flags[kFlagBadAtom], a);
+        }
+        return;
+    }
     double* out = per_atom + (int64_t)a * NT;
     if constexpr (KIND == 1) {
 #pragma unroll
@@ -509,74 +554,99 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 // frame's atom count, never on how frames were batched.
 __global__ void __launch_bounds__(256) k_frame_reduce(const FrameInfo* __restrict__ frames,
                                                       const int32_t* __restrict__ meta,
-                                                      const double* __restrict__ per_atom, int nt,
-                                                      double* __restrict__ out) {
-    __shared__ double part[9][256];
+                                                      const double* __restrict__ per_atom, int nt, int na,
+                                                      double* __restrict__ out_a, double* __restrict__ out_b) {
+    __shared__ double part[10][256];
     const int f = blockIdx.x;
     if (f >= meta[kMetaNFrames]) return;
     const FrameInfo fi = frames[f];
     const int lane = threadIdx.x;
-    double s[9];
+    double s[10];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) s[k] = 0.0;
+    for (int k = 0; k < 10; ++k) s[k] = 0.0;
     for (int64_t a = lane; a < fi.n_atoms; a += 256) {
         const double* q = per_atom + (fi.atom_begin + a) * nt;
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
+        for (int k = 0; k < 10; ++k)
             if (k < nt) s[k] += q[k];
     }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) part[k][lane] = s[k];
+    for (int k = 0; k < 10; ++k) part[k][lane] = s[k];
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (lane < off)
 #pragma unroll
-            for (int k = 0; k < 9; ++k) part[k][lane] += part[k][lane + off];
+            for (int k = 0; k < 10; ++k) part[k][lane] += part[k][lane + off];
         __syncthreads();
     }
-    if (lane < nt) out[(int64_t)f * nt + lane] = part[lane][0];
+    if (lane < na)
+        out_a[(int64_t)f * na + lane] = part[lane][0];
+    else if (lane < nt && out_b)
+        out_b[(int64_t)f * (nt - na) + lane - na] = part[lane][0];
+}
+
+__global__ void k_pes_clear(unsigned long long* __restrict__ acc, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) acc[i] = 0;
+}
+
+// forces[a][c] = acc[a][c] / 2^32 (exact: |acc| < 2^63, FP64 keeps 53 bits of it)
+__global__ void k_pes_finish(const unsigned long long* __restrict__ acc, const double* __restrict__ per_atom,
+                             const int32_t* __restrict__ meta, double* __restrict__ forces,
+                             double* __restrict__ energies) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= meta[kMetaNAtoms]) return;
+    if (forces)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) forces[3 * a + c] = (double)(long long)acc[3 * a + c] * (1.0 / kForceScale);
+    if (energies) energies[a] = per_atom[10 * a];
 }
 
 template <int NR, int NA, int KR, int KA, bool FOURB, int KIND, int MODE>
-hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom, int block, hipStream_t s) {
+hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom, const PesOut& pes, int block,
+                    hipStream_t s) {
     constexpr int D = NR + 4 * NA + (FOURB ? NA : 0);
     if constexpr (MODE == TNEP_MLP_FP32_VALU) {
         const int bs = (block == 64 || block == 128) ? block : 256;
         const unsigned grid = (unsigned)((nl.n_pad + bs - 1) / bs);
-        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom);
+        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom, pes);
     } else {
         // two wavefronts per work-group keep the LDS tiles at <= 2 x 27 KB
         const unsigned grid = (unsigned)((nl.n_pad + 127) / 128);
         const size_t lds = sizeof(float) * 2 * (size_t)mlp_lds_floats(D, m.n_hidden);
-        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom);
+        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom, pes);
     }
     return hipGetLastError();
 }
 
 template <int NR, int NA, int KR, int KA, bool FOURB, int KIND>
 hipError_t launch_mode(int mode, bool matrix, const DevModel& m, const NeighborLists& nl, double* per_atom,
-                       int block, hipStream_t s) {
+                       const PesOut& pes, int block, hipStream_t s) {
     if (matrix) {
         if (mode == TNEP_MLP_FP32_MFMA)
-            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, block, s);
+            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, pes, block, s);
         if (mode == TNEP_MLP_BF16_MFMA)
-            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, block, s);
+            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, pes, block, s);
         if (mode == TNEP_MLP_BF16X3_MFMA)
-            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, block, s);
+            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, pes, block, s);
     }
-    return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, block, s);
+    return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
 }
 
+// Potential-energy models always use the FP32 vector hidden layer.
 template <int NR, int NA, int KR, int KA, bool FOURB, bool MX>
 hipError_t dispatch(const Shape& shape, int mode, bool matrix, const DevModel& m, const NeighborLists& nl,
-                    double* per_atom, int block, hipStream_t s) {
+                    double* per_atom, const PesOut& pes, int block, hipStream_t s) {
+    if (shape.kind == 3)
+        return launch_t<NR, NA, KR, KA, FOURB, 3, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
     if constexpr (MX) {
-        if (shape.kind == 1) return launch_mode<NR, NA, KR, KA, FOURB, 1>(mode, matrix, m, nl, per_atom, block, s);
-        return launch_mode<NR, NA, KR, KA, FOURB, 2>(mode, matrix, m, nl, per_atom, block, s);
+        if (shape.kind == 1)
+            return launch_mode<NR, NA, KR, KA, FOURB, 1>(mode, matrix, m, nl, per_atom, pes, block, s);
+        return launch_mode<NR, NA, KR, KA, FOURB, 2>(mode, matrix, m, nl, per_atom, pes, block, s);
     } else {
         if (shape.kind == 1)
-            return launch_t<NR, NA, KR, KA, FOURB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, block, s);
-        return launch_t<NR, NA, KR, KA, FOURB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, block, s);
+            return launch_t<NR, NA, KR, KA, FOURB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
+        return launch_t<NR, NA, KR, KA, FOURB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
     }
 }
 
@@ -609,13 +679,13 @@ bool eval_matrix_supported(const Shape& s, int n_hidden) {
 }
 
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
-                       const EvalLaunch& cfg, hipStream_t s) {
+                       const PesOut& pes, const EvalLaunch& cfg, hipStream_t s) {
     if (nl.n_pad == 0) return hipSuccess;
     const bool matrix = cfg.mlp_mode != TNEP_MLP_FP32_VALU && eval_matrix_supported(shape, m.n_hidden);
 #define X(NR_, NA_, KR_, KA_, FB_, MX_)                                                             \
     if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                \
         (bool)shape.four_body == FB_)                                                             \
-        return dispatch<NR_, NA_, KR_, KA_, FB_, MX_>(shape, cfg.mlp_mode, matrix, m, nl, per_atom,           \
+        return dispatch<NR_, NA_, KR_, KA_, FB_, MX_>(shape, cfg.mlp_mode, matrix, m, nl, per_atom, pes,      \
                                                       cfg.atoms_per_block, s);
     TNEP_SHAPES(X)
 #undef X
@@ -623,9 +693,23 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
 }
 
 hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const int32_t* meta, const double* per_atom,
-                               int nt, double* out, hipStream_t s) {
+                               int nt, int na, double* out_a, double* out_b, hipStream_t s) {
     if (cap_frames == 0) return hipSuccess;
-    k_frame_reduce<<<cap_frames, 256, 0, s>>>(d_frames, meta, per_atom, nt, out);
+    k_frame_reduce<<<cap_frames, 256, 0, s>>>(d_frames, meta, per_atom, nt, na, out_a, out_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_pes_clear(unsigned long long* force_acc, int64_t cap_atoms, hipStream_t s) {
+    if (cap_atoms == 0) return hipSuccess;
+    const int64_t n = 3 * cap_atoms;
+    k_pes_clear<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(force_acc, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pes_finish(const unsigned long long* force_acc, const double* per_atom, const int32_t* meta,
+                             int64_t cap_atoms, double* forces, double* energies, hipStream_t s) {
+    if (cap_atoms == 0 || (!forces && !energies)) return hipSuccess;
+    k_pes_finish<<<(unsigned)((cap_atoms + 255) / 256), 256, 0, s>>>(force_acc, per_atom, meta, forces, energies);
     return hipGetLastError();
 }
 

@@ -351,14 +351,15 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
             for (int k = b; k < e; ++k) {
                 const double4 cur = q;
                 if (k + 1 < e) q = bucket_pos[k + 1];
-                if ((int)__double_as_longlong(cur.w) == a) continue;
+                const int j = (int)__double_as_longlong(cur.w);
+                if (j == a) continue;
                 const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
                 const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
                 const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 if (r2 >= rc2r) continue;
                 if (r2 < 1e-8) overlap = true;
-                const float4 ent = make_float4((float)dx, (float)dy, (float)dz, 0.f);
+                const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
                 if (r2 < rc2a)
                     sa.push(ent, ga, capA);
                 else

@@ -58,11 +58,12 @@ struct Ctx {
     DevBuf frames, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, bucket_pos, perm_start;
     DevBuf perm, tile_base, scan_chunks, nbr, counts, per_atom, out, pos, species;
     DevBuf spec_work, spec_series, spec_out;
+    DevBuf force_acc, pes_stage;  // potential-energy models: fixed-point forces, host-bound staging
 
     std::vector<DevBuf*> all_buffers() {
         return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
-                &spec_work, &spec_series, &spec_out, &counters};
+                &spec_work, &spec_series, &spec_out, &counters, &force_acc, &pes_stage};
     }
 
     Server* server = nullptr;
@@ -116,10 +117,15 @@ struct Model {
 };
 
 // One evaluation request: up to two models over the same frames.
+// Potential-energy model (one model per job): out = energies [F], aux =
+// virials [F][9] (or NULL), per_atom = site energies [A] (or NULL), forces
+// [A][3] (or NULL).
 struct EvalJob {
     const Model* models[2] = {nullptr, nullptr};
     double* out[2] = {nullptr, nullptr};
+    double* aux[2] = {nullptr, nullptr};
     double* per_atom[2] = {nullptr, nullptr};
+    double* forces = nullptr;
     int n_models = 0;
 };
 

@@ -304,7 +304,8 @@ extern "C" int tnep_submit(tnep_ctx* ctx, const tnep_model* model, int32_t kind,
     Server* s = c->server;
     if (!s) return TNEP_E_INVALID;
     const Model* m = reinterpret_cast<const Model*>(model);
-    if (!m || !frames || !out || !ticket || m->kind != kind || frames->location != TNEP_HOST ||
+    // the server takes dipole and polarizability requests (one output array each)
+    if (!m || !frames || !out || !ticket || m->kind != kind || kind == TNEP_KIND_PES || frames->location != TNEP_HOST ||
         frames->n_frames < 1 || !frames->atom_offsets || !frames->positions || !frames->species)
         return TNEP_E_INVALID;
     // admission: the largest frame must fit one slot's budget

@@ -21,12 +21,13 @@ ERRORS = {0: "TNEP_OK", -1: "TNEP_E_INVALID", -2: "TNEP_E_SPECIES", -3: "TNEP_E_
           -5: "TNEP_E_NONFINITE", -6: "TNEP_E_BUDGET", -7: "TNEP_E_MODEL", -8: "TNEP_E_HIP",
           -9: "TNEP_E_NEIGH_OVERFLOW", -10: "TNEP_E_CANCELLED"}
 HOST, DEVICE = 0, 1
-KIND_DIPOLE, KIND_POLARIZABILITY = 1, 2
+KIND_DIPOLE, KIND_POLARIZABILITY, KIND_PES = 1, 2, 3
 MLP_FP32_VALU, MLP_FP32_MFMA, MLP_BF16_MFMA, MLP_BF16X3_MFMA = 0, 1, 2, 3
 OPT_MLP, OPT_ATOMS_PER_BLOCK, OPT_AUTOTUNE, OPT_DETERMINISTIC, OPT_MAX_BATCH_ATOMS, OPT_TIMING = 1, 2, 3, 4, 5, 6
 OPT_NEIGH_BLOCK = 7
 OPT_GRAPHS = 8
 KERNEL_NEIGHBORS, KERNEL_EVAL_DIPOLE, KERNEL_EVAL_POLARIZABILITY, KERNEL_FRAME_REDUCE, KERNEL_SPECTRUM = 0, 1, 2, 3, 4
+KERNEL_EVAL_PES = 5
 IR, RAMAN_ISO, RAMAN_ANISO, RAMAN_PROJ = 0, 1, 2, 3
 WIN_HANN, WIN_NONE = 0, 1
 SUBTRACT_MEAN, NO_OMEGA2 = 1, 2
@@ -35,7 +36,7 @@ EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_
             "tnep_model_create", "tnep_model_free", "tnep_eval_dipole", "tnep_eval_polarizability",
             "tnep_eval_dipole_polarizability", "tnep_spectrum", "tnep_server_start", "tnep_submit", "tnep_wait",
             "tnep_server_stop", "tnep_server_stats", "tnep_ctx_kernel_time", "tnep_ctx_pair_counts",
-            "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts"]
+            "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts", "tnep_eval_pes"]
 
 
 class TnepError(RuntimeError):
@@ -96,6 +97,7 @@ def _load():
     lib.tnep_eval_dipole.argtypes = [vp, vp, P(FramesDesc), vp, vp]
     lib.tnep_eval_polarizability.argtypes = [vp, vp, P(FramesDesc), vp, vp]
     lib.tnep_eval_dipole_polarizability.argtypes = [vp, vp, vp, P(FramesDesc), vp, vp]
+    lib.tnep_eval_pes.argtypes = [vp, vp, P(FramesDesc), vp, vp, vp, vp]
     lib.tnep_spectrum.argtypes = [vp, P(SpectrumArgs), vp, vp, vp]
     lib.tnep_server_start.argtypes = [vp, P(ServerOpts)]
     lib.tnep_submit.argtypes = [vp, vp, C.c_int32, P(FramesDesc), vp, P(C.c_uint64)]
@@ -293,6 +295,24 @@ def tnep_eval_dipole_polarizability(ctx: Context, dipole_model: Model, pol_model
     ctx.check(lib.tnep_eval_dipole_polarizability(ctx.h, dipole_model.h, pol_model.h, C.byref(fd), _ptr(mu_out),
                                                   _ptr(alpha_out)))
     return mu_out, alpha_out
+
+
+def tnep_eval_pes(ctx: Context, model: Model, frames, energy=None, virial=None, forces=None, per_atom_energy=None,
+                  want_virial=True, want_forces=True):
+    """Potential-energy surface: (energy [F], virial [F,3,3] or None, forces [A,3] or None).
+    Host frames -> numpy outputs (allocated unless given); device frames ->
+    the caller's device tensors (pass None to skip virial / forces)."""
+    fd = frames_desc(frames)
+    F = fd.n_frames
+    if fd.location == HOST:
+        energy = np.zeros(F) if energy is None else energy
+        if want_virial and virial is None:
+            virial = np.zeros((F, 3, 3))
+        if want_forces and forces is None:
+            forces = np.zeros((int(np.asarray(frames.offsets)[-1]), 3))
+    ctx.check(lib.tnep_eval_pes(ctx.h, model.h, C.byref(fd), _ptr(energy), _ptr(virial), _ptr(forces),
+                                _ptr(per_atom_energy)))
+    return energy, virial, forces
 
 
 def tnep_spectrum(ctx: Context, series, kind, dt_fs, max_lag, window=WIN_HANN, flags=0, n_hat=(0, 0, 0),
