@@ -164,6 +164,66 @@ def bench_molecules(args):
                                              "polarizability" % frames.n_atoms}}), flush=True)
 
 
+def bench_pes(args):
+    """Potential-energy surface (Sec. 2.1) on the 12,288-atom water box: energy,
+    virial and forces of every frame, device-resident inputs and outputs; the
+    evaluation kernel's time from HIP events and its FP32 roofline; errors of
+    one frame against the FP64 oracle."""
+    import torch
+
+    import oracle
+    from paper_2312_05233_amd import tnep
+
+    n_frames = min(args.frames, 340)
+    frames = synth.water_trajectory(n_frames)
+    m = synth.model("water_pes")
+    ctx = tnep.Context(0)
+    gm = tnep.Model(ctx, m)
+    dfr = tnep.DeviceFrames(frames)
+    E = torch.zeros(frames.n_frames, dtype=torch.float64, device="cuda")
+    W = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
+    F = torch.zeros((frames.n_atoms, 3), dtype=torch.float64, device="cuda")
+    step = lambda: tnep.tnep_eval_pes(ctx, gm, dfr, E, W, F)  # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_option(tnep.OPT_TIMING, 1)
+    ctx.reset_timing()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    ms, n = ctx.kernel_time(tnep.KERNEL_EVAL_PES)
+    atoms, rad, ang = ctx.pair_counts()
+    kt = {name: ctx.kernel_time(k)[0] / args.steps for name, k in (
+        ("neighbors", tnep.KERNEL_NEIGHBORS), ("eval_pes", tnep.KERNEL_EVAL_PES),
+        ("frame_reduce_and_forces", tnep.KERNEL_FRAME_REDUCE))}
+    flop = flops_per_atom_frame(m, rad / atoms, ang / atoms)
+    atoms_per_launch = frames.n_atoms / (n / args.steps)
+    achieved = flop * atoms_per_launch / (ms / n * 1e-3) / 1e12
+    # errors of one frame against the oracle
+    sub = frames.subset([0])
+    Er, Wr, Fr, Ur = oracle.eval_pes(m, sub, per_atom=True)
+    n0 = sub.n_atoms
+    errs = {"energy_vs_sum_abs_site_energies": float(abs(E[0].item() - Er[0]) / np.abs(Ur).sum()),
+            "virial_frobenius": float(np.linalg.norm(W[0].cpu().numpy() - Wr[0].reshape(9)) / np.linalg.norm(Wr[0])),
+            "forces_frobenius": float(np.linalg.norm(F[:n0].cpu().numpy() - Fr) / np.linalg.norm(Fr))}
+    print(json.dumps({
+        "metric": "NEP PES atom-frames/s (energy + virial + forces) at FP32 tol", "value": frames.n_atoms / t,
+        "unit": "atom-frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "water 4096 H2O (12288 atoms, 49.7 A PBC) x %d-frame OU trajectory, potential-energy "
+                               "model rc 6/4 A, n_max 4/4, basis 8/8, l_max 4 + 4-body, H=30" % n_frames},
+        "roofline": {"kernel": "k_eval<5,5,9,9,4-body,potential>", "bound": "alu", "achieved": achieved,
+                     "peak": 157.3, "unit": "TFLOP/s", "frac": achieved / 157.3,
+                     "flop_per_atom_frame": flop, "atoms_per_launch": atoms_per_launch,
+                     "avg_launch_ms": ms / n, "mean_radial_neighbors": rad / atoms,
+                     "mean_angular_neighbors": ang / atoms,
+                     "fixed_point_atomics_per_atom_frame": 3 * (rad / atoms + 1)},
+        "kernels_ms_per_step": kt, "errors_vs_oracle_frame0": errs}), flush=True)
+
+
 def _serving_requests(n_requests, seed=4):
     """Request mix: half water boxes of 64..8000 H2O (consecutive OU frames,
     species O=3, H=1 of the five-species models), half batches of vacuum
@@ -326,7 +386,7 @@ def main():
     ap.add_argument("--mlp", type=int, default=None, help="TNEP_MLP_* mode of the hidden layer")
     ap.add_argument("--atoms-per-block", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
-    ap.add_argument("--workload", default="water", choices=["water", "perovskite", "molecules", "serving"],
+    ap.add_argument("--workload", default="water", choices=["water", "perovskite", "molecules", "serving", "pes"],
                     help="water: the headline line; the others print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
@@ -351,7 +411,8 @@ def main():
     from paper_2312_05233_amd import tnep
 
     if args.workload != "water":
-        {"perovskite": bench_perovskite, "molecules": bench_molecules, "serving": bench_serving}[args.workload](args)
+        {"perovskite": bench_perovskite, "molecules": bench_molecules, "serving": bench_serving,
+         "pes": bench_pes}[args.workload](args)
         return
 
     dev = torch.device("cuda:0")
