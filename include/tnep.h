@@ -97,6 +97,7 @@ extern "C" {
 #define TNEP_KERNEL_FRAME_REDUCE 3
 #define TNEP_KERNEL_SPECTRUM 4
 #define TNEP_KERNEL_EVAL_PES 5
+#define TNEP_KERNEL_PES_FORCES 6
 
 /* ---- opaque handles ---------------------------------------------------- */
 typedef struct tnep_ctx tnep_ctx;
@@ -213,10 +214,11 @@ int tnep_eval_dipole_polarizability(tnep_ctx* ctx, const tnep_model* dipole_mode
  *   forces  [total_atoms][3]  F_k = -dU/dr_k = sum_j dU_k/dr_kj - sum_i dU_i/dr_ik
  *                             (r_ij = r_j - r_i), input atom order; NULL to skip;
  *   per_atom_energy [total_atoms] U_i; NULL to skip.
- * Forces are summed as 64-bit fixed-point integers (resolution 2^-32 in model
- * units per Angstrom), so they do not depend on the order of the sums;
- * TNEP_E_NONFINITE if a pair term reaches 2^20 in magnitude.  Location,
- * ownership and errors as for tnep_eval_dipole. */
+ * Forces: a first kernel leaves every atom's own pair terms and its network
+ * derivatives; a second evaluates, for each atom k and neighbour j, the term
+ * -dU_j/dr_jk from j's derivatives, and sums all terms in a fixed order, so
+ * results do not depend on scheduling or batching.  Location, ownership and
+ * errors as for tnep_eval_dipole. */
 int tnep_eval_pes(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames, double* energy,
                   double* virial, double* forces, double* per_atom_energy);
 

@@ -186,7 +186,7 @@ extern "C" uint64_t tnep_ctx_memory_in_use(const tnep_ctx* ctx) {
 }
 
 extern "C" int tnep_ctx_kernel_time(const tnep_ctx* ctx, int32_t which, double* total_ms, uint64_t* launches) {
-    if (!ctx || which < 0 || which > TNEP_KERNEL_EVAL_PES) return TNEP_E_INVALID;
+    if (!ctx || which < 0 || which > TNEP_KERNEL_PES_FORCES) return TNEP_E_INVALID;
     const Ctx* c = reinterpret_cast<const Ctx*>(ctx);
     if (total_ms) *total_ms = c->kernel_ms[which];
     if (launches) *launches = c->kernel_launches[which];

@@ -316,10 +316,12 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             // batch size in atoms
             int64_t largest = 0;
             for (int f = 0; f < F; ++f) largest = std::max(largest, meta.offs[f + 1] - meta.offs[f]);
-            bool pes = false;
-            for (int k = first; k < last; ++k) pes = pes || job.models[k]->kind == TNEP_KIND_PES;
+            int rec_stride = 0;  // potential-energy model: floats per atom record
+            for (int k = first; k < last; ++k)
+                if (job.models[k]->kind == TNEP_KIND_PES) rec_stride = pes_rec_stride(job.models[k]->shape, T);
+            const bool pes = rec_stride > 0;
             const int64_t per_atom_bytes = (int64_t)slots * 16 + 8 * T + 24 + 80 * (last - first) +
-                                           (fr.location == TNEP_HOST ? 28 : 0) + (pes ? 24 + 32 : 0);
+                                           (fr.location == TNEP_HOST ? 28 : 0) + (pes ? 4 * rec_stride + 32 : 0);
             int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
             B = std::max(B, largest);
             const int64_t room = (int64_t)c->budget - (int64_t)(c->in_use - c->nbr.bytes - c->per_atom.bytes);
@@ -356,7 +358,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if ((e = c->reserve(c->bucket_pos, (size_t)B_res * 32))) return e;
             if ((e = c->reserve(c->per_atom, (size_t)B_res * 10 * sizeof(double) * (last - first)))) return e;
             if (pes) {
-                if ((e = c->reserve(c->force_acc, (size_t)B_res * 3 * sizeof(unsigned long long)))) return e;
+                if ((e = c->reserve(c->pes_rec, (size_t)n_pad_max * rec_stride * sizeof(float)))) return e;
                 if (fr.location == TNEP_HOST && (e = c->reserve(c->pes_stage, (size_t)B_res * 4 * sizeof(double))))
                     return e;
             }
@@ -480,7 +482,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         }
                     }
                 }
-                const PesOut pes_out{(unsigned long long*)c->force_acc.p, (int32_t*)c->flags.p};
+                const PesOut pes_out{(float*)c->pes_rec.p, rec_stride};
                 // the batch's kernels; with graphs on, captured once and replayed
                 auto launch_batch = [&]() -> hipError_t {
                     hipError_t he;
@@ -497,10 +499,6 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     for (int k = first; k < last; ++k) {
                         const Model* m = job.models[k];
                         const int q = k - first;
-                        if (m->kind == TNEP_KIND_PES) {
-                            he = launch_pes_clear(pes_out.force_acc, cap_atoms, c->stream);
-                            if (he != hipSuccess) return he;
-                        }
                         tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE           ? TNEP_KERNEL_EVAL_DIPOLE
                                             : m->kind == TNEP_KIND_POLARIZABILITY ? TNEP_KERNEL_EVAL_POLARIZABILITY
                                                                                   : TNEP_KERNEL_EVAL_PES);
@@ -510,11 +508,15 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);
                         he = launch_frame_reduce((const FrameInfo*)c->frames.p, cap_frames, nl.meta, pa_of[q],
                                                  nt_of[q], na_of[q], out_of[q], aux_of[q], c->stream);
-                        if (he == hipSuccess && m->kind == TNEP_KIND_PES)
-                            he = launch_pes_finish(pes_out.force_acc, pa_of[q], nl.meta, cap_atoms, forces_dst,
-                                                   energies_dst, c->stream);
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;
+                        if (m->kind == TNEP_KIND_PES) {
+                            tr = c->timer_begin(TNEP_KERNEL_PES_FORCES);
+                            he = launch_pes_forces(m->shape, m->dm, nl, pes_out, pa_of[q], forces_dst, energies_dst,
+                                                   c->launch.atoms_per_block, c->stream);
+                            c->timer_end(tr);
+                            if (he != hipSuccess) return he;
+                        }
                     }
                     return hipSuccess;
                 };
@@ -563,7 +565,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                  : (fl[kFlagError] & kErrSpecies) ? TNEP_E_SPECIES
                                                                   : TNEP_E_OVERLAP;
                 return c->fail(code, "invalid input (%s) near batch-local atom %d",
-                               code == TNEP_E_NONFINITE ? "non-finite position, or a force term beyond 2^20"
+                               code == TNEP_E_NONFINITE ? "non-finite position"
                                : code == TNEP_E_SPECIES ? "species out of range"
                                                         : "atoms closer than 1e-4 A",
                                fl[kFlagBadAtom]);

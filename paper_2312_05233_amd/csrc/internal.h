@@ -57,7 +57,7 @@ struct Shape {
 // capA[t]) for r < rc_angular (used by the radial and the angular terms) and
 // rows [segR[t], segR[t] + capR[t]) for rc_angular <= r < rc_radial (radial
 // terms only).  Entry (row r) of slot p is the float4 (dx, dy, dz, 0) with
-// r_ij = r_j - r_i (x, y, z; w holds the batch-local index j as int bits),
+// r_ij = r_j - r_i (x, y, z; w holds the tile slot of j as int bits),
 // stored at entries[((tile * slots/4 + r/4) * 64 + lane) * 4
 // + r % 4]: four consecutive rows of one lane are 64 contiguous bytes.
 // Per-species segment tables live in device memory (meta) so that kernels
@@ -121,15 +121,19 @@ struct EvalLaunch {
     int neigh_block;      // work-group size of the neighbour kernel: 64, 128, 256
 };
 
-// Forces of a potential-energy model: every pair term is added to
-// force_acc[3 * atom + c] as a 64-bit fixed-point integer (value * 2^32), so
-// the sums do not depend on the order of the atomic additions.
-constexpr double kForceScale = 4294967296.0;  // 2^32
-constexpr float kForceTermMax = 1048576.f;    // |pair term| limit (2^20): sums stay below 2^63
+// Potential-energy models: the evaluation kernel leaves, per atom a in tile
+// slot p, a record of rec_stride floats at rec + p * rec_stride (slots keep
+// atoms of one cell together, so the records of a lane's neighbours are close):
+//   [t * KRP + k]        sum_n dU_a/dq^R_n c^R_{t_a t}[n][k]   (t < T, KRP = KR rounded up to 4)
+//   [T * KRP + 24 n + c] (-1)^l(c) dU_a/dA_{a,n,c}             (n < NA, the 24 (l, m) channels)
+//   [T * KRP + 24 NA + d] sum_j dU_a/dr_aj, component d < 3
+// from which the second kernel forms, for every pair (k, j), the term that
+// U_j contributes to the force on k.
 struct PesOut {
-    unsigned long long* force_acc;  // [n_atoms][3] two's-complement fixed point, zeroed before the launch
-    int32_t* flags;        // kFlagError |= kErrNonFinite for terms outside the fixed-point range
+    float* rec;
+    int32_t rec_stride;
 };
+inline int pes_rec_stride(const Shape& s, int T) { return T * ((s.kr + 3) / 4 * 4) + 24 * s.na + 4; }
 
 // Per-atom records (FP64, batch atom order) of one model: dipole [n][3],
 // polarizability [n][9], potential energy [n][10] = (U_i, W_i row-major).
@@ -140,13 +144,11 @@ bool eval_matrix_supported(const Shape& s, int n_hidden);
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
                        const PesOut& pes, const EvalLaunch& cfg, hipStream_t s);
 
-// Potential-energy batches: zero the fixed-point force accumulators of the
-// batch (cap_atoms sizes the grid), and afterwards convert them to FP64 forces
-// (forces may be NULL) and copy the site energies (column 0 of the per-atom
-// records, energies may be NULL).
-hipError_t launch_pes_clear(unsigned long long* force_acc, int64_t cap_atoms, hipStream_t s);
-hipError_t launch_pes_finish(const unsigned long long* force_acc, const double* per_atom, const int32_t* meta,
-                             int64_t cap_atoms, double* forces, double* energies, hipStream_t s);
+// Potential-energy models, after launch_eval over the same lists: forces[a]
+// (FP64, NULL to skip) = sum_j dU_a/dr_aj - sum_j dU_j/dr_ja, summed in a fixed
+// order, and energies[a] = U_a (column 0 of the per-atom records, NULL to skip).
+hipError_t launch_pes_forces(const Shape& shape, const DevModel& m, const NeighborLists& nl, const PesOut& pes,
+                             const double* per_atom, double* forces, double* energies, int block, hipStream_t s);
 
 // Add the batch's atom count and neighbour-pair counts to counters[0..2].
 hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* counters, hipStream_t s);

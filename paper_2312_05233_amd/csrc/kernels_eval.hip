@@ -228,10 +228,9 @@ __host__ __device__ constexpr int mlp_lds_floats(int D, int H) {
     return 64 * (((D + 31) / 32 * 32 + 4) + ((H + 31) / 32 * 32 + 4));
 }
 
-// A force term as a 64-bit two's-complement fixed-point integer (x * 2^32,
-// rounded to nearest); integer addition makes the sums order-independent.
-__device__ __forceinline__ unsigned long long to_fixed(float x) {
-    return (unsigned long long)(long long)rint((double)x * kForceScale);
+// Sign of the (l, m) channel c of sh_foreach under r -> -r: (-1)^l.
+__device__ __forceinline__ constexpr float parity_sign(int c) {
+    return (c < 3 || (c >= 8 && c < 15)) ? -1.f : 1.f;
 }
 
 // One lane per tile slot (atom).  The coefficient blocks c[t_i][t] are
@@ -404,27 +403,45 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
         }
     }
 
+    // potential: the record that the force kernel reads for this atom as a neighbour
+    constexpr int KRP = (KR + 3) / 4 * 4;
+    float* rec = nullptr;
+    if constexpr (KIND == 3) {
+        if (a >= 0) {
+            rec = pes.rec + p * pes.rec_stride;
+            for (int t = 0; t < T; ++t) {
+                const float* __restrict__ cR = m.c_radial + (ti * T + t) * (NR * KR);
+#pragma unroll
+                for (int k = 0; k < KRP; ++k) {
+                    float v = 0.f;
+                    if (k < KR)
+#pragma unroll
+                        for (int n = 0; n < NR; ++n) v += dq[n] * cR[n * KR + (k < KR ? k : 0)];
+                    rec[t * KRP + k] = v;
+                }
+            }
+            float* g = rec + T * KRP;
+#pragma unroll
+            for (int n = 0; n < NA; ++n)
+#pragma unroll
+                for (int c = 0; c < kLM; c += 4)
+                    *reinterpret_cast<float4*>(g + n * kLM + c) =
+                        make_float4(parity_sign(c) * A[n][c], parity_sign(c + 1) * A[n][c + 1],
+                                    parity_sign(c + 2) * A[n][c + 2], parity_sign(c + 3) * A[n][c + 3]);
+        }
+    }
+
     // ---- 3. partial forces and contraction --------------------------------
     float acc[NT];
 #pragma unroll
     for (int k = 0; k < NT; ++k) acc[k] = 0.f;
     float own[3] = {0.f, 0.f, 0.f};  // potential: sum_j dU_i/dr_ij, the atom's own force term
-    bool bad_term = false;
-    // (Fx, Fy, Fz) = dU_i/dr_ij for the pair vector (dx, dy, dz) to neighbour j
-    auto contract = [&](float dx, float dy, float dz, float r2, float Fx, float Fy, float Fz, int j) {
+    // (Fx, Fy, Fz) = dU_i/dr_ij for the pair vector (dx, dy, dz)
+    auto contract = [&](float dx, float dy, float dz, float r2, float Fx, float Fy, float Fz) {
         if constexpr (KIND == 3) {
-            // F_j -= dU_i/dr_ij (r_ij = r_j - r_i), as fixed-point integers
             own[0] += Fx;
             own[1] += Fy;
             own[2] += Fz;
-            const float f[3] = {Fx, Fy, Fz};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (fabsf(f[c]) < kForceTermMax)
-                    atomicAdd(&pes.force_acc[3 * (int64_t)j + c], to_fixed(-f[c]));
-                else
-                    bad_term = true;
-            }
         }
         if constexpr (KIND == 1) {
             acc[0] -= r2 * Fx;
@@ -506,8 +523,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
                 sc += (bv - (float)l * av * rinv) * P;
             });
             const float su = sc + sr;
-            contract(e.x, e.y, e.z, r2, Fx * rinv + ux * su, Fy * rinv + uy * su, Fz * rinv + uz * su,
-                     __float_as_int(e.w));
+            contract(e.x, e.y, e.z, r2, Fx * rinv + ux * su, Fy * rinv + uy * su, Fz * rinv + uz * su);
         }
         nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int s = 0; s < n_rad; ++s) {
@@ -516,7 +532,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
             const float rinv = rsqrtf(r2);
             const float su = radial_slope(r2 * rinv) * rinv;
-            contract(e.x, e.y, e.z, r2, e.x * su, e.y * su, e.z * su, __float_as_int(e.w));
+            contract(e.x, e.y, e.z, r2, e.x * su, e.y * su, e.z * su);
         }
     }
 
@@ -526,17 +542,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
         out[0] = (double)Us;
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[1 + k] = (double)acc[k];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (fabsf(own[c]) < kForceTermMax)
-                atomicAdd(&pes.force_acc[3 * (int64_t)a + c], to_fixed(own[c]));
-            else
-                bad_term = true;
-        }
-        if (bad_term) {
-            atomicOr(&pes.flags[kFlagError], kErrNonFinite);
-            atomicMin(&pes.flags[kFlagBadAtom], a);
-        }
+        *reinterpret_cast<float4*>(rec + T * KRP + NA * kLM) = make_float4(own[0], own[1], own[2], 0.f);
         return;
     }
     double* out = per_atom + (int64_t)a * NT;
@@ -585,21 +591,127 @@ __global__ void __launch_bounds__(256) k_frame_reduce(const FrameInfo* __restric
         out_b[(int64_t)f * (nt - na) + lane - na] = part[lane][0];
 }
 
-__global__ void k_pes_clear(unsigned long long* __restrict__ acc, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) acc[i] = 0;
-}
-
-// forces[a][c] = acc[a][c] / 2^32 (exact: |acc| < 2^63, FP64 keeps 53 bits of it)
-__global__ void k_pes_finish(const unsigned long long* __restrict__ acc, const double* __restrict__ per_atom,
-                             const int32_t* __restrict__ meta, double* __restrict__ forces,
-                             double* __restrict__ energies) {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= meta[kMetaNAtoms]) return;
-    if (forces)
+// Forces of a potential-energy model (Sec. 2.1): with r_ij = r_j - r_i,
+//   F_k = -dU/dr_k = sum_j dU_k/dr_kj - sum_j dU_j/dr_jk.
+// The first sum is in the atom's record (evaluation kernel).  For the second,
+// the lane of atom k evaluates, for every neighbour j, the partial force of
+// U_j at r_jk = -r_kj from j's record: radial part sum_k' Dk_j[k'] f'_k'(r) with
+// j's coefficients c_{t_j t_k}; angular part from G_j, whose stored sign
+// (-1)^l turns Y_lm(-u) and its gradient back into functions of u.  Every
+// term is summed in the lane's fixed list order: no atomics.
+template <int NR, int NA, int KR, int KA, bool FOURB>
+__global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl, PesOut pes,
+                                                    const double* __restrict__ per_atom,
+                                                    double* __restrict__ forces, double* __restrict__ energies) {
+    constexpr int KRP = (KR + 3) / 4 * 4;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int T = nl.T;
+    const int tile = __builtin_amdgcn_readfirstlane((int)(p >> 6));
+    const int lane = (int)(p & 63);
+    if (tile >= nl.meta[kMetaTileBase + T]) return;
+    const int a = nl.perm[p];
+    const int tk = tile_species(nl.meta + kMetaTileBase, T, tile);
+    const float rcR_inv = 1.f / m.rc_radial, rcA_inv = 1.f / m.rc_angular;
+    const float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;  // - sum_j dU_j/dr_jk
+    for (int t = 0; t < T; ++t) {
+        // neighbours of species t see atom k through c_{t, t_k}
+        const float* __restrict__ cA = m.c_angular + (t * T + tk) * (NA * KA);
+        const int n_ang = nl.counts[(int64_t)(2 * t) * nl.n_pad + p];
+        const int n_rad = nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
+        const float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
+        const float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
+        auto radial_slope = [&](const float* rj, float r) {
+            float fc, dfc, f[KR], df[KR];
+            cutoff_fc_d(1.f - r * rcR_inv, rcR_inv, fc, dfc);
+            cheb_basis_d<KR>(r, rcR_inv, fc, dfc, f, df);
+            const float4* d4 = reinterpret_cast<const float4*>(rj + tk * KRP);
+            float sr = 0.f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) forces[3 * a + c] = (double)(long long)acc[3 * a + c] * (1.0 / kForceScale);
-    if (energies) energies[a] = per_atom[10 * a];
+            for (int k = 0; k < KRP; k += 4) {
+                const float4 d = d4[k / 4];
+                sr += d.x * df[k];
+                if (k + 1 < KR) sr += d.y * df[k + 1];
+                if (k + 2 < KR) sr += d.z * df[k + 2];
+                if (k + 3 < KR) sr += d.w * df[k + 3];
+            }
+            return sr;
+        };
+        float4 nxt = n_ang > 0 ? ga[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int s = 0; s < n_ang; ++s) {
+            const float4 e = nxt;
+            if (s + 1 < n_ang) nxt = ga[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
+            const float* rj = pes.rec + (int64_t)__float_as_int(e.w) * pes.rec_stride;
+            const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
+            const float rinv = rsqrtf(r2);
+            const float r = r2 * rinv;
+            const float ux = e.x * rinv, uy = e.y * rinv, uz = e.z * rinv;
+            const float sr = radial_slope(rj, r);
+            float fc, dfc, f[KA], df[KA];
+            cutoff_fc_d(1.f - r * rcA_inv, rcA_inv, fc, dfc);
+            cheb_basis_d<KA>(r, rcA_inv, fc, dfc, f, df);
+            // a_c = sum_n G~_j[n][c] g_n(r), b_c = sum_n G~_j[n][c] g_n'(r)
+            float av[kLM], bv[kLM];
+#pragma unroll
+            for (int c = 0; c < kLM; ++c) {
+                av[c] = 0.f;
+                bv[c] = 0.f;
+            }
+            const float4* gj = reinterpret_cast<const float4*>(rj + T * KRP);
+#pragma unroll
+            for (int n = 0; n < NA; ++n) {
+                float g = 0.f, dg = 0.f;
+#pragma unroll
+                for (int k = 0; k < KA; ++k) {
+                    g += cA[n * KA + k] * f[k];
+                    dg += cA[n * KA + k] * df[k];
+                }
+#pragma unroll
+                for (int c = 0; c < kLM; c += 4) {
+                    const float4 w = gj[(n * kLM + c) / 4];
+                    av[c] += w.x * g;
+                    av[c + 1] += w.y * g;
+                    av[c + 2] += w.z * g;
+                    av[c + 3] += w.w * g;
+                    bv[c] += w.x * dg;
+                    bv[c + 1] += w.y * dg;
+                    bv[c + 2] += w.z * dg;
+                    bv[c + 3] += w.w * dg;
+                }
+            }
+            float Px = 0.f, Py = 0.f, Pz = 0.f, sc = 0.f;
+            sh_foreach(ux, uy, uz, [&](int idx, int l, float P, float px, float py, float pz) {
+                Px += av[idx] * px;
+                Py += av[idx] * py;
+                Pz += av[idx] * pz;
+                sc += (bv[idx] - (float)l * av[idx] * rinv) * P;
+            });
+            const float su = sc + sr;
+            Fx += Px * rinv + ux * su;
+            Fy += Py * rinv + uy * su;
+            Fz += Pz * rinv + uz * su;
+        }
+        nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int s = 0; s < n_rad; ++s) {
+            const float4 e = nxt;
+            if (s + 1 < n_rad) nxt = gr[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
+            const float* rj = pes.rec + (int64_t)__float_as_int(e.w) * pes.rec_stride;
+            const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
+            const float rinv = rsqrtf(r2);
+            const float su = radial_slope(rj, r2 * rinv) * rinv;
+            Fx += e.x * su;
+            Fy += e.y * su;
+            Fz += e.z * su;
+        }
+    }
+    if (a < 0) return;
+    const float4 own = *reinterpret_cast<const float4*>(pes.rec + p * pes.rec_stride + T * KRP + NA * kLM);
+    if (forces) {
+        forces[3 * (int64_t)a] = (double)own.x + (double)Fx;
+        forces[3 * (int64_t)a + 1] = (double)own.y + (double)Fy;
+        forces[3 * (int64_t)a + 2] = (double)own.z + (double)Fz;
+    }
+    if (energies) energies[a] = per_atom[10 * (int64_t)a];
 }
 
 template <int NR, int NA, int KR, int KA, bool FOURB, int KIND, int MODE>
@@ -699,18 +811,20 @@ hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const 
     return hipGetLastError();
 }
 
-hipError_t launch_pes_clear(unsigned long long* force_acc, int64_t cap_atoms, hipStream_t s) {
-    if (cap_atoms == 0) return hipSuccess;
-    const int64_t n = 3 * cap_atoms;
-    k_pes_clear<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(force_acc, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_pes_finish(const unsigned long long* force_acc, const double* per_atom, const int32_t* meta,
-                             int64_t cap_atoms, double* forces, double* energies, hipStream_t s) {
-    if (cap_atoms == 0 || (!forces && !energies)) return hipSuccess;
-    k_pes_finish<<<(unsigned)((cap_atoms + 255) / 256), 256, 0, s>>>(force_acc, per_atom, meta, forces, energies);
-    return hipGetLastError();
+hipError_t launch_pes_forces(const Shape& shape, const DevModel& m, const NeighborLists& nl, const PesOut& pes,
+                             const double* per_atom, double* forces, double* energies, int block, hipStream_t s) {
+    if (nl.n_pad == 0 || (!forces && !energies)) return hipSuccess;
+    const int bs = (block == 64 || block == 128) ? block : 256;
+    const unsigned grid = (unsigned)((nl.n_pad + bs - 1) / bs);
+#define X(NR_, NA_, KR_, KA_, FB_, MX_)                                                                 \
+    if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                    \
+        (bool)shape.four_body == FB_) {                                                               \
+        k_pes_forces<NR_, NA_, KR_, KA_, FB_><<<grid, bs, 0, s>>>(m, nl, pes, per_atom, forces, energies); \
+        return hipGetLastError();                                                                     \
+    }
+    TNEP_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
 }
 
 }  // namespace tnep

@@ -214,7 +214,7 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 }
 
 // Sort each bucket by atom index, place it into the tile permutation and
-// store its positions contiguously in bucket order (w = atom index).
+// store its positions contiguously in bucket order (w = the atom's tile slot).
 __global__ void k_sort_place(const int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_atoms,
                              const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm,
                              const double* __restrict__ pos, double4* __restrict__ bucket_pos,
@@ -235,7 +235,8 @@ __global__ void k_sort_place(const int32_t* __restrict__ bucket_start, int32_t* 
     for (int i = b; i < e; ++i) {
         const int a = bucket_atoms[i];
         perm[p + (i - b)] = a;
-        bucket_pos[i] = make_double4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2], __longlong_as_double(a));
+        bucket_pos[i] = make_double4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2],
+                                     __longlong_as_double((long long)(p + (i - b))));
     }
 }
 
@@ -351,8 +352,8 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
             for (int k = b; k < e; ++k) {
                 const double4 cur = q;
                 if (k + 1 < e) q = bucket_pos[k + 1];
-                const int j = (int)__double_as_longlong(cur.w);
-                if (j == a) continue;
+                const int j = (int)__double_as_longlong(cur.w);  // tile slot of the candidate
+                if (j == (int)p) continue;
                 const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
                 const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
                 const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);

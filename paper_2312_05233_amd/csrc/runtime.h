@@ -58,12 +58,12 @@ struct Ctx {
     DevBuf frames, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, bucket_pos, perm_start;
     DevBuf perm, tile_base, scan_chunks, nbr, counts, per_atom, out, pos, species;
     DevBuf spec_work, spec_series, spec_out;
-    DevBuf force_acc, pes_stage;  // potential-energy models: fixed-point forces, host-bound staging
+    DevBuf pes_rec, pes_stage;  // potential-energy models: per-atom records, host-bound staging
 
     std::vector<DevBuf*> all_buffers() {
         return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
-                &spec_work, &spec_series, &spec_out, &counters, &force_acc, &pes_stage};
+                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage};
     }
 
     Server* server = nullptr;

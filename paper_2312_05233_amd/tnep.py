@@ -27,7 +27,7 @@ OPT_MLP, OPT_ATOMS_PER_BLOCK, OPT_AUTOTUNE, OPT_DETERMINISTIC, OPT_MAX_BATCH_ATO
 OPT_NEIGH_BLOCK = 7
 OPT_GRAPHS = 8
 KERNEL_NEIGHBORS, KERNEL_EVAL_DIPOLE, KERNEL_EVAL_POLARIZABILITY, KERNEL_FRAME_REDUCE, KERNEL_SPECTRUM = 0, 1, 2, 3, 4
-KERNEL_EVAL_PES = 5
+KERNEL_EVAL_PES, KERNEL_PES_FORCES = 5, 6
 IR, RAMAN_ISO, RAMAN_ANISO, RAMAN_PROJ = 0, 1, 2, 3
 WIN_HANN, WIN_NONE = 0, 1
 SUBTRACT_MEAN, NO_OMEGA2 = 1, 2
