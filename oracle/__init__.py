@@ -344,12 +344,15 @@ def channel_acf(series, kind, max_lag, n_hat=None, e_hat=None, subtract_mean=Fal
 
 
 def spectrum(series_list, kind, dt_fs, max_lag, window=True, omega2=None, n_hat=None, e_hat=None,
-             subtract_mean=False, acf_fn=None):
+             subtract_mean=False, acf_fn=None, laser_cm1=None):
     """One-sided windowed cosine transform of the averaged correlation function.
 
     S(w_k) = dt/(2 pi) [w(0) C(0) + 2 sum_{tau=1}^{M-1} w(tau) C(tau) cos(w_k tau dt)],
     w_k = pi k / (M dt), k = 0..M, Hann lag window w(tau) = (1 + cos(pi tau / M)) / 2.
     IR multiplies by w_k^2 (classical prefactor).  Frequencies in cm^-1.
+    Raman kinds with laser_cm1 (incoming wavenumber) multiply by the
+    ((w_in - w) / c)^4 factor of Eq. raman-cross-section, (2 pi (laser - nu_k))^4
+    in cm^-4.
     Returns (freq_cm1 [M+1], intensity [M+1], acf [M])."""
     M = int(max_lag)
     fn = acf_fn or channel_acf
@@ -367,4 +370,21 @@ def spectrum(series_list, kind, dt_fs, max_lag, window=True, omega2=None, n_hat=
     if omega2:
         S = S * omega ** 2
     freq = k / (2.0 * M * dt_fs * SPEED_OF_LIGHT_CM_PER_FS)
+    if laser_cm1 is not None and kind != SPEC_IR:
+        S = S * (2.0 * np.pi * (laser_cm1 - freq)) ** 4
     return freq, S, C_
+
+
+def raman_map(series_list, dt_fs, max_lag, n_hats, e_hats, window=True, subtract_mean=False, laser_cm1=None):
+    """Orientation-resolved Raman lineshapes (Eq. raman-cross-section with the
+    lineshape of Eq. raman-lineshape): for each polarisation pair (n, e),
+    sum n_g n_m L_gdmn e_d e_n, which is the spectrum of s(t) = n^T alpha(t) e.
+    Evaluated per orientation by the direct lag sums of the projected signal.
+    Returns (freq_cm1 [M+1], intensity [n_orient, M+1])."""
+    out = []
+    freq = None
+    for n_hat, e_hat in zip(n_hats, e_hats):
+        freq, S, _ = spectrum(series_list, SPEC_RAMAN_PROJ, dt_fs, max_lag, window=window, n_hat=n_hat,
+                              e_hat=e_hat, subtract_mean=subtract_mean, laser_cm1=laser_cm1)
+        out.append(S)
+    return freq, np.array(out)
