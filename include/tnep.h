@@ -227,6 +227,7 @@ int tnep_eval_pes(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* fra
 #define TNEP_RAMAN_ISO 1   /* rank 2 [.][9]: <gamma(0) gamma(t)>, gamma = Tr(alpha)/3         */
 #define TNEP_RAMAN_ANISO 2 /* rank 2: <Tr beta(0) beta(t)>, beta = alpha - gamma I           */
 #define TNEP_RAMAN_PROJ 3  /* rank 2: <s(0) s(t)>, s = n^T alpha e                           */
+#define TNEP_RAMAN_MAP 4   /* streams only: all nine components, for orientation maps       */
 
 #define TNEP_WIN_HANN 0    /* lag window w(tau) = (1 + cos(pi tau / M)) / 2 */
 #define TNEP_WIN_NONE 1
@@ -246,6 +247,8 @@ typedef struct {
     double n_hat[3];       /* TNEP_RAMAN_PROJ only                                     */
     double e_hat[3];
     int32_t location;      /* TNEP_HOST / TNEP_DEVICE for series and the outputs       */
+    double laser_cm1;      /* > 0: Raman kinds times ((w_in - w)/c)^4 = (2 pi (laser_cm1 - nu_k))^4,
+                              cm^-4 (Eq. raman-cross-section); 0 = off; ignored for IR     */
 } tnep_spectrum_args;
 
 /* Correlation function of the series (time-origin average, 1/(N_t - tau)
@@ -257,6 +260,49 @@ typedef struct {
  * All FP64. */
 int tnep_spectrum(tnep_ctx* ctx, const tnep_spectrum_args* args, double* freq_cm1, double* intensity,
                   double* acf);
+
+/* Orientation-resolved Raman lineshapes (Sec. 2.7, Eqs. raman-cross-section
+ * and raman-lineshape; Sec. 4 maps the crystal-orientation dependence): for
+ * each polarisation pair o, sum_{g d m n} n_g n_m L_{g d m n}(w) e_d e_n, i.e.
+ * the spectrum of s(t) = n_o^T alpha(t) e_o, for all n_orient pairs from one
+ * pass over the series (the 45 symmetrised cross-correlations of alpha's nine
+ * components are transformed once, then contracted).  args as for
+ * tnep_spectrum with series [n_series][n_steps][9]; args->kind, n_hat, e_hat
+ * are ignored; TNEP_SUBTRACT_MEAN and laser_cm1 apply.  n_hat, e_hat:
+ * [n_orient][3] host memory (used as given, not normalised); intensity:
+ * [n_orient][M+1]; freq_cm1 [M+1]; location of series and outputs from args. */
+int tnep_raman_map(tnep_ctx* ctx, const tnep_spectrum_args* args, int32_t n_orient, const double* n_hat,
+                   const double* e_hat, double* freq_cm1, double* intensity);
+
+/* ---- streaming correlation accumulators --------------------------------- */
+/* For series too long (or arriving too late) to hold whole: samples are
+ * pushed in chunks of any size; each run's pair sums
+ * S(tau) = sum_{t + tau < N} x(t) y(t + tau) are accumulated in FP64 on the
+ * device (a chunk's contribution by zero-padded FFT against the run's last
+ * M - 1 samples), and at the end of a run C(tau) = S(tau) / (N - tau) (with the
+ * run means removed under TNEP_SUBTRACT_MEAN) joins the average over runs.
+ * The results equal tnep_spectrum / tnep_raman_map on the whole runs (up to
+ * rounding).  A stream belongs to its context, which must outlive it; calls
+ * on a stream are synchronous and not thread-safe. */
+typedef struct tnep_acf_stream tnep_acf_stream;
+/* kind: TNEP_IR (samples [.][3]), TNEP_RAMAN_ISO / ANISO / PROJ (with n_hat,
+ * e_hat) or TNEP_RAMAN_MAP (samples [.][9]); max_lag M >= 1; flags:
+ * TNEP_SUBTRACT_MEAN | TNEP_NO_OMEGA2. */
+int tnep_acf_stream_create(tnep_ctx* ctx, int32_t kind, int64_t max_lag, int32_t flags, const double* n_hat,
+                           const double* e_hat, tnep_acf_stream** out);
+/* Append n_samples samples ([n_samples][3 or 9] FP64, host or device) to the current run. */
+int tnep_acf_stream_push(tnep_acf_stream* s, const double* samples, int64_t n_samples, int32_t location);
+/* Close the current run (it needs at least max_lag samples). */
+int tnep_acf_stream_end_run(tnep_acf_stream* s);
+/* Spectrum over the finished runs (as tnep_spectrum; host outputs freq [M+1],
+ * intensity [M+1], acf NULL or [M]).  Not for TNEP_RAMAN_MAP streams. */
+int tnep_acf_stream_spectrum(tnep_acf_stream* s, double dt_fs, int32_t window, double laser_cm1, double* freq_cm1,
+                             double* intensity, double* acf);
+/* Orientation map over the finished runs of a TNEP_RAMAN_MAP stream (as
+ * tnep_raman_map; host arrays). */
+int tnep_acf_stream_raman_map(tnep_acf_stream* s, double dt_fs, int32_t window, double laser_cm1, int32_t n_orient,
+                              const double* n_hat, const double* e_hat, double* freq_cm1, double* intensity);
+void tnep_acf_stream_free(tnep_acf_stream* s);
 
 /* ---- serving (continuous batching) ------------------------------------- */
 typedef struct {

@@ -560,9 +560,11 @@ extern "C" int tnep_spectrum(tnep_ctx* ctx, const tnep_spectrum_args* a, double*
     if (a->window != TNEP_WIN_HANN && a->window != TNEP_WIN_NONE) return c->fail(TNEP_E_INVALID, "bad window");
     if (a->location != TNEP_HOST && a->location != TNEP_DEVICE) return c->fail(TNEP_E_INVALID, "bad location");
     if (a->n_steps > ((int64_t)1 << 26)) return c->fail(TNEP_E_INVALID, "n_steps above 2^26");
+    if (!(a->laser_cm1 >= 0) || !std::isfinite(a->laser_cm1)) return c->fail(TNEP_E_INVALID, "bad laser_cm1");
     (void)hipSetDevice(c->device);
     (void)hipGetLastError();  // launch checks below must only see this call's launches
     SpectrumPlan p{};
+    p.laser_cm1 = a->laser_cm1;
     p.kind = a->kind;
     p.window = a->window;
     p.flags = a->flags;

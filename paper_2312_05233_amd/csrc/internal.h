@@ -167,9 +167,44 @@ struct SpectrumPlan {
     int64_t n_steps, max_lag, fft_len;
     double dt_fs;
     double n_hat[3], e_hat[3];
+    double laser_cm1;  // > 0: Raman (w_in - w)^4 factor
 };
 size_t spectrum_workspace_bytes(const SpectrumPlan& p);
 hipError_t launch_spectrum(const SpectrumPlan& p, const double* d_series, double* d_freq, double* d_intensity,
                            double* d_acf, void* d_work, hipStream_t s);
+
+// Orientation map: h_weights [n_orient][45] host array (v_P v_Q, doubled off
+// the diagonal, v = n (x) e flattened), intensity [n_orient][M+1].
+size_t raman_map_workspace_bytes(const SpectrumPlan& p, int n_orient);
+hipError_t launch_raman_map(const SpectrumPlan& p, const double* d_series, const double* h_weights, int n_orient,
+                            double* d_freq, double* d_intensity, void* d_work, hipStream_t s);
+
+// Streaming correlation accumulators (device pointers; host-side sizes).
+struct StreamState {
+    int kind, nsig, nch;
+    int64_t M;
+    double n_hat[3], e_hat[3];
+    const int32_t *chx, *chy, *chsym;  // [nch] channel signal pairs, symmetric flag
+    const double* chw;                 // [nch] channel weights (kinds 0-3)
+    double* carry;                     // [nsig][carry_cap] last samples of the run
+    double* carry_next;                // same size: written by a push, then swapped
+    int64_t carry_cap, carry_len;      // carry_cap = M - 1 (at least 1)
+    double* head;                      // [nsig][M] first samples of the run
+    double* totals;                    // [nsig] sums over the run
+    double* S;                         // [nch][M] pair sums of the run
+    double* run_sum;                   // [nch][M] sum over finished runs of C(tau)
+    int64_t run_len;                   // samples in the current run
+    int64_t n_runs;                    // finished runs
+};
+size_t stream_push_workspace_bytes(int nsig, int nch, int64_t P);
+hipError_t launch_stream_push(const StreamState& st, const double* d_chunk, int64_t n, int64_t P, void* d_work,
+                              hipStream_t s);
+hipError_t launch_stream_end_run(const StreamState& st, int subtract, hipStream_t s);
+hipError_t launch_stream_spectrum(const StreamState& st, double dt_fs, int window, int omega2, double laser_cm1,
+                                  double* d_tab, double* d_acf, double* d_freq, double* d_intensity, hipStream_t s);
+hipError_t launch_stream_map(const StreamState& st, double dt_fs, int window, double laser_cm1, const double* d_w,
+                             int n_orient, double* d_tab, double* d_acf, double* d_L, double* d_freq,
+                             double* d_intensity, hipStream_t s);
+hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s);
 
 }  // namespace tnep

@@ -10,10 +10,16 @@
 //   iso    C_{gamma gamma},  gamma = Tr(alpha)/3             (Eq. raman-lineshape-isotropic-anisotropic)
 //   aniso  sum_ab C_{beta_ab beta_ba}, beta = alpha - gamma I  (<Tr beta(0) beta(t)>)
 //   proj   C_{s s}, s = n^T alpha e                          (Eq. raman-cross-section)
+//   map    C_{PQ}, P, Q over the nine components of alpha, symmetrised, for the
+//          orientation-resolved lineshape sum n_g n_m L_gdmn e_d e_n
+//          (Eqs. raman-cross-section, raman-lineshape): one pass, any number
+//          of polarisation pairs by contraction of the 45 channel spectra
 // The one-sided cosine transform with the lag window,
 //   S(w_k) = dt/(2 pi) [w(0) C(0) + 2 sum_{tau=1}^{M-1} w(tau) C(tau) cos(pi k tau / M)],
 // is summed directly with an exact integer phase index into a cosine table;
-// IR spectra carry the classical w^2 prefactor (Eq. ir-intensity).
+// IR spectra carry the classical w^2 prefactor (Eq. ir-intensity); Raman
+// spectra optionally the ((w_in - w) / c)^4 factor of Eq. raman-cross-section.
+// Long series can also be fed in chunks (streaming accumulators below).
 #include "internal.h"
 
 namespace tnep {
@@ -33,6 +39,7 @@ int signals_per_series(int kind) {
         case 0: return 3;   // mu_x, mu_y, mu_z
         case 1: return 1;   // gamma
         case 2: return 9;   // beta_ab
+        case 4: return 9;   // alpha_ab (orientation map)
         default: return 1;  // n^T alpha e
     }
 }
@@ -70,6 +77,8 @@ __global__ void k_signals(const double* __restrict__ series, const double* __res
     for (int c = 0; c < comps; ++c) v[c] = row[c] - (means ? means[s * comps + c] : 0.0);
     if (kind == 0) {
         for (int a = 0; a < 3; ++a) out[(int64_t)a * P + t] = {v[a], 0.0};
+    } else if (kind == 4) {
+        for (int c = 0; c < 9; ++c) out[(int64_t)c * P + t] = {v[c], 0.0};
     } else {
         const double gamma = (v[0] + v[4] + v[8]) / 3.0;
         if (kind == 1) {
@@ -148,18 +157,21 @@ __global__ void k_cos_table(int64_t M, double* __restrict__ tab) {
     if (j < 2 * M) tab[j] = cospi((double)j / (double)M);
 }
 
-// S_k for k = 0..M; one thread per k.  Phase index (k tau) mod 2M kept exact.
-__global__ void k_transform(const double* __restrict__ acf, const double* __restrict__ tab, int64_t M, int window,
-                            int omega2, double dt_fs, double* __restrict__ freq, double* __restrict__ intensity) {
+// S_k for k = 0..M of channel blockIdx.y; one thread per k.  Phase index
+// (k tau) mod 2M kept exact.  laser_cm1 > 0 multiplies by (2 pi (laser - nu_k))^4.
+__global__ void k_transform(const double* __restrict__ acf, int64_t acf_stride, const double* __restrict__ tab,
+                            int64_t M, int window, int omega2, double laser_cm1, double dt_fs,
+                            double* __restrict__ freq, double* __restrict__ intensity, int64_t out_stride) {
     const int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (k > M) return;
+    const double* a = acf + (int64_t)blockIdx.y * acf_stride;
     const int64_t twoM = 2 * M;
     const int64_t step = k % twoM;
     int64_t idx = step;  // (k * tau) mod 2M for tau = 1
-    double s = acf[0];   // w(0) = 1
+    double s = a[0];     // w(0) = 1
     for (int64_t tau = 1; tau < M; ++tau) {
         const double w = window == 0 ? 0.5 * (1.0 + tab[tau]) : 1.0;  // tab[tau] = cos(pi tau / M)
-        s += 2.0 * w * acf[tau] * tab[idx];
+        s += 2.0 * w * a[tau] * tab[idx];
         idx += step;
         if (idx >= twoM) idx -= twoM;
     }
@@ -167,8 +179,222 @@ __global__ void k_transform(const double* __restrict__ acf, const double* __rest
     s *= dt_fs / (2.0 * pi);
     const double omega = pi * (double)k / ((double)M * dt_fs);
     if (omega2) s *= omega * omega;
-    intensity[k] = s;
-    freq[k] = (double)k / (2.0 * (double)M * dt_fs * 2.99792458e-5);
+    const double nu = (double)k / (2.0 * (double)M * dt_fs * 2.99792458e-5);
+    if (laser_cm1 > 0.0) {
+        const double d = 2.0 * pi * (laser_cm1 - nu);
+        s *= (d * d) * (d * d);
+    }
+    intensity[(int64_t)blockIdx.y * out_stride + k] = s;
+    if (blockIdx.y == 0 && freq) freq[k] = nu;
+}
+
+// ---- orientation map: 45 symmetrised channels (P <= Q over the nine components)
+
+__device__ __forceinline__ void pair_of(int q, int& P, int& Q) {
+    P = 0;
+    int left = q;
+    while (left >= 9 - P) {
+        left -= 9 - P;
+        ++P;
+    }
+    Q = P + left;
+}
+
+// Z[q][f] = sum_s Re(conj(X_sP) X_sQ): the spectrum of (C_PQ + C_QP) / 2, summed over series.
+__global__ void k_power_sym(const cplx* __restrict__ X, int64_t P_len, int n_series, cplx* __restrict__ Z) {
+    const int64_t f = (int64_t)blockIdx.x * kB + threadIdx.x;
+    const int q = blockIdx.y;
+    if (f >= P_len) return;
+    int P, Q;
+    pair_of(q, P, Q);
+    double acc = 0.0;
+    for (int sr = 0; sr < n_series; ++sr) {
+        const cplx u = X[((int64_t)sr * 9 + P) * P_len + f];
+        const cplx v = X[((int64_t)sr * 9 + Q) * P_len + f];
+        acc += u.re * v.re + u.im * v.im;
+    }
+    Z[(int64_t)q * P_len + f] = {acc, 0.0};
+}
+
+// acf[q][tau] = Re(Z[q][tau]) / P / (N - tau) / n_series
+__global__ void k_acf_channels(const cplx* __restrict__ Z, int64_t P_len, int n_series, int64_t n_steps, int64_t M,
+                               double* __restrict__ acf) {
+    const int64_t tau = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (tau >= M) return;
+    const int q = blockIdx.y;
+    acf[(int64_t)q * M + tau] = Z[(int64_t)q * P_len + tau].re / (double)P_len / (double)(n_steps - tau) /
+                                (double)n_series;
+}
+
+// out[o][k] = sum_q W[o][q] L[q][k]
+__global__ void k_contract(const double* __restrict__ L, int64_t M, const double* __restrict__ W, int nq,
+                           double* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (k > M) return;
+    const int o = blockIdx.y;
+    double s = 0.0;
+    for (int q = 0; q < nq; ++q) s += W[o * nq + q] * L[(int64_t)q * (M + 1) + k];
+    out[(int64_t)o * (M + 1) + k] = s;
+}
+
+// ---- streaming accumulators ------------------------------------------------
+// A run is fed in chunks.  For every channel (x, y) the run keeps
+// S(tau) = sum_{t + tau < N} x(t) y(t + tau); a chunk adds the pairs whose
+// later sample is new: with u = [carry | chunk] (carry = last M - 1 samples)
+// and v = [0 | chunk], IFFT(conj(U) V)[tau] / P.
+
+__device__ __forceinline__ void derive_signals(int kind, const double* v, double nx, double ny, double nz, double ex,
+                                               double ey, double ez, double* out) {
+    if (kind == 0) {
+        for (int a = 0; a < 3; ++a) out[a] = v[a];
+    } else if (kind == 4) {
+        for (int c = 0; c < 9; ++c) out[c] = v[c];
+    } else {
+        const double gamma = (v[0] + v[4] + v[8]) / 3.0;
+        if (kind == 1) {
+            out[0] = gamma;
+        } else if (kind == 2) {
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) out[3 * a + b] = v[3 * a + b] - (a == b ? gamma : 0.0);
+        } else {
+            const double n[3] = {nx, ny, nz}, e[3] = {ex, ey, ez};
+            double p = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) p += n[a] * v[3 * a + b] * e[b];
+            out[0] = p;
+        }
+    }
+}
+
+// U[g][t] = (carry | signals of the chunk | 0), V[g][t] = (0 | signals | 0).
+__global__ void k_stream_build(const double* __restrict__ chunk, int64_t n, int comps, int kind, int nsig,
+                               double nx, double ny, double nz, double ex, double ey, double ez,
+                               const double* __restrict__ carry, int64_t carry_cap, int64_t c, int64_t P_len,
+                               cplx* __restrict__ U, cplx* __restrict__ V) {
+    const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (t >= P_len) return;
+    if (t < c) {
+        for (int g = 0; g < nsig; ++g) {
+            U[(int64_t)g * P_len + t] = {carry[(int64_t)g * carry_cap + t], 0.0};
+            V[(int64_t)g * P_len + t] = {0.0, 0.0};
+        }
+    } else if (t < c + n) {
+        double v[9], sg[9];
+        const double* row = chunk + (t - c) * comps;
+        for (int k = 0; k < comps; ++k) v[k] = row[k];
+        derive_signals(kind, v, nx, ny, nz, ex, ey, ez, sg);
+        for (int g = 0; g < nsig; ++g) {
+            U[(int64_t)g * P_len + t] = {sg[g], 0.0};
+            V[(int64_t)g * P_len + t] = {sg[g], 0.0};
+        }
+    } else {
+        for (int g = 0; g < nsig; ++g) {
+            U[(int64_t)g * P_len + t] = {0.0, 0.0};
+            V[(int64_t)g * P_len + t] = {0.0, 0.0};
+        }
+    }
+}
+
+// Run state from U before its transform: new carry (last min(M-1, c+n)
+// samples), the first M samples of the run (head) and per-signal totals.
+// One work-group per signal.
+__global__ void k_stream_state(const cplx* __restrict__ U, int64_t P_len, int64_t c, int64_t n,
+                               int64_t carry_cap, double* __restrict__ carry_new, int64_t run_len,
+                               double* __restrict__ head, int64_t M, double* __restrict__ totals) {
+    const int g = blockIdx.x;
+    const cplx* u = U + (int64_t)g * P_len;
+    const int64_t L = c + n;
+    const int64_t keep = L < carry_cap ? L : carry_cap;
+    for (int64_t i = threadIdx.x; i < keep; i += kB) carry_new[(int64_t)g * carry_cap + i] = u[L - keep + i].re;
+    for (int64_t i = threadIdx.x; i < n; i += kB) {
+        const int64_t r = run_len + i;  // position in the run
+        if (r < M) head[(int64_t)g * M + r] = u[c + i].re;
+    }
+    __shared__ double part[kB];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kB) acc += u[c + i].re;
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[g] += part[0];
+}
+
+// Z[ch][f] = conj(U_x) V_y, or (conj(U_x) V_y + conj(U_y) V_x) / 2 for symmetric channels.
+__global__ void k_stream_power(const cplx* __restrict__ U, const cplx* __restrict__ V, int64_t P_len,
+                               const int32_t* __restrict__ chx, const int32_t* __restrict__ chy,
+                               const int32_t* __restrict__ chsym, cplx* __restrict__ Z) {
+    const int64_t f = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (f >= P_len) return;
+    const int ch = blockIdx.y;
+    const int x = chx[ch], y = chy[ch];
+    const cplx ux = U[(int64_t)x * P_len + f], vy = V[(int64_t)y * P_len + f];
+    cplx z = {ux.re * vy.re + ux.im * vy.im, ux.re * vy.im - ux.im * vy.re};
+    if (chsym[ch]) {
+        const cplx uy = U[(int64_t)y * P_len + f], vx = V[(int64_t)x * P_len + f];
+        z.re = 0.5 * (z.re + uy.re * vx.re + uy.im * vx.im);
+        z.im = 0.5 * (z.im + uy.re * vx.im - uy.im * vx.re);
+    }
+    Z[(int64_t)ch * P_len + f] = z;
+}
+
+// S[ch][tau] += Re(Z[ch][tau]) / P
+__global__ void k_stream_accum(const cplx* __restrict__ Z, int64_t P_len, int64_t M, double* __restrict__ S) {
+    const int64_t tau = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (tau >= M) return;
+    const int ch = blockIdx.y;
+    S[(int64_t)ch * M + tau] += Z[(int64_t)ch * P_len + tau].re / (double)P_len;
+}
+
+// End of a run of N samples: C(tau) = S'(tau) / (N - tau) added to run_sum,
+// where S' subtracts the run means when asked:
+//   S' = S - xm sum_{t>=tau} y(t) - ym sum_{t<N-tau} x(t) + (N - tau) xm ym,
+// sum_{t>=tau} y = Y - (first tau samples of y), sum_{t<N-tau} x = X - (last tau of x).
+__global__ void k_stream_end(const double* __restrict__ S, int64_t M, int64_t N, int subtract,
+                             const double* __restrict__ totals, const double* __restrict__ head,
+                             const double* __restrict__ tail, int64_t tail_cap, int64_t tail_len,
+                             const int32_t* __restrict__ chx, const int32_t* __restrict__ chy,
+                             const int32_t* __restrict__ chsym, double* __restrict__ run_sum) {
+    const int64_t tau = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (tau >= M) return;
+    const int ch = blockIdx.y;
+    double v = S[(int64_t)ch * M + tau];
+    if (subtract) {
+        auto corr = [&](int x, int y) {
+            const double xm = totals[x] / (double)N, ym = totals[y] / (double)N;
+            double hy = 0.0, tx = 0.0;
+            for (int64_t i = 0; i < tau; ++i) {
+                hy += head[(int64_t)y * M + i];
+                tx += tail[(int64_t)x * tail_cap + tail_len - 1 - i];
+            }
+            return -xm * (totals[y] - hy) - ym * (totals[x] - tx) + (double)(N - tau) * xm * ym;
+        };
+        const int x = chx[ch], y = chy[ch];
+        v += chsym[ch] ? 0.5 * (corr(x, y) + corr(y, x)) : corr(x, y);
+    }
+    run_sum[(int64_t)ch * M + tau] += v / (double)(N - tau);
+}
+
+// acf[tau] = sum_ch w[ch] run_sum[ch][tau] / n_runs
+__global__ void k_stream_combine(const double* __restrict__ run_sum, int nch, int64_t M,
+                                 const double* __restrict__ w, double inv_runs, double* __restrict__ acf) {
+    const int64_t tau = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (tau >= M) return;
+    double s = 0.0;
+    for (int ch = 0; ch < nch; ++ch) s += w[ch] * run_sum[(int64_t)ch * M + tau];
+    acf[tau] = s * inv_runs;
+}
+
+__global__ void k_scale(const double* __restrict__ a, int64_t n, double f, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i < n) out[i] = a[i] * f;
+}
+
+__global__ void k_zero(double* __restrict__ a, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i < n) a[i] = 0.0;
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
@@ -231,8 +457,157 @@ hipError_t launch_spectrum(const SpectrumPlan& p, const double* d_series, double
     k_acf<<<nblk(p.max_lag), kB, 0, s>>>(c, P, p.n_series, p.n_steps, p.max_lag, acf);
     k_cos_table<<<nblk(2 * p.max_lag), kB, 0, s>>>(p.max_lag, tab);
     const int omega2 = (p.kind == 0 && !(p.flags & 2)) ? 1 : 0;
-    k_transform<<<nblk(p.max_lag + 1), kB, 0, s>>>(acf, tab, p.max_lag, p.window, omega2, p.dt_fs, d_freq,
-                                                   d_intensity);
+    k_transform<<<dim3(nblk(p.max_lag + 1), 1), kB, 0, s>>>(acf, p.max_lag, tab, p.max_lag, p.window, omega2,
+                                                            p.kind == 0 ? 0.0 : p.laser_cm1, p.dt_fs, d_freq,
+                                                            d_intensity, p.max_lag + 1);
+    return hipGetLastError();
+}
+
+// ---- orientation map ------------------------------------------------------
+
+size_t raman_map_workspace_bytes(const SpectrumPlan& p, int n_orient) {
+    const size_t P = (size_t)p.fft_len, M = (size_t)p.max_lag;
+    size_t b = 0;
+    b += sizeof(double) * (size_t)p.n_series * 9 + 256;
+    b += 2 * (sizeof(cplx) * P * p.n_series * 9 + 256);  // X and ping-pong
+    b += 2 * (sizeof(cplx) * P * 45 + 256);              // channel spectra and ping-pong
+    b += sizeof(double) * (2 * M + 2) + 256;             // cos table
+    b += sizeof(double) * 45 * M + 256;                  // channel acfs
+    b += sizeof(double) * 45 * (M + 1) + 256;            // channel lineshapes
+    b += sizeof(double) * (size_t)n_orient * 45 + 256;   // weights
+    return b + 1024;
+}
+
+hipError_t launch_raman_map(const SpectrumPlan& p, const double* d_series, const double* h_weights, int n_orient,
+                            double* d_freq, double* d_intensity, void* d_work, hipStream_t s) {
+    const int64_t P = p.fft_len, M = p.max_lag;
+    char* w = (char*)d_work;
+    auto take = [&](size_t bytes) {
+        char* r = w;
+        w += (bytes + 255) & ~(size_t)255;
+        return r;
+    };
+    double* means = (double*)take(sizeof(double) * p.n_series * 9);
+    cplx* X = (cplx*)take(sizeof(cplx) * (size_t)P * p.n_series * 9);
+    cplx* Y = (cplx*)take(sizeof(cplx) * (size_t)P * p.n_series * 9);
+    cplx* Z1 = (cplx*)take(sizeof(cplx) * (size_t)P * 45);
+    cplx* Z2 = (cplx*)take(sizeof(cplx) * (size_t)P * 45);
+    double* tab = (double*)take(sizeof(double) * (size_t)(2 * M + 2));
+    double* acf = (double*)take(sizeof(double) * (size_t)(45 * M));
+    double* L = (double*)take(sizeof(double) * (size_t)(45 * (M + 1)));
+    double* W = (double*)take(sizeof(double) * (size_t)n_orient * 45);
+    hipError_t e = hipMemcpyAsync(W, h_weights, sizeof(double) * (size_t)n_orient * 45, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    const bool sub = (p.flags & 1) != 0;
+    if (sub) k_means<<<p.n_series * 9, kB, 0, s>>>(d_series, p.n_steps, 9, means);
+    k_signals<<<dim3(nblk(P), p.n_series), kB, 0, s>>>(d_series, sub ? means : nullptr, p.n_steps, P, 4, 9, 9, 0, 0,
+                                                        0, 0, 0, 0, X);
+    cplx* a = X;
+    cplx* b = Y;
+    for (int64_t m = 1; m < P; m <<= 1) {
+        k_fft_pass<<<dim3(nblk(P / 2), (unsigned)(p.n_series * 9)), kB, 0, s>>>(a, b, P, m, -1.0);
+        cplx* t = a;
+        a = b;
+        b = t;
+    }
+    k_power_sym<<<dim3(nblk(P), 45), kB, 0, s>>>(a, P, p.n_series, Z1);
+    cplx* c = Z1;
+    cplx* d = Z2;
+    for (int64_t m = 1; m < P; m <<= 1) {
+        k_fft_pass<<<dim3(nblk(P / 2), 45), kB, 0, s>>>(c, d, P, m, 1.0);
+        cplx* t = c;
+        c = d;
+        d = t;
+    }
+    k_acf_channels<<<dim3(nblk(M), 45), kB, 0, s>>>(c, P, p.n_series, p.n_steps, M, acf);
+    k_cos_table<<<nblk(2 * M), kB, 0, s>>>(M, tab);
+    k_transform<<<dim3(nblk(M + 1), 45), kB, 0, s>>>(acf, M, tab, M, p.window, 0, p.laser_cm1, p.dt_fs, d_freq, L,
+                                                     M + 1);
+    k_contract<<<dim3(nblk(M + 1), (unsigned)n_orient), kB, 0, s>>>(L, M, W, 45, d_intensity);
+    return hipGetLastError();
+}
+
+// ---- streaming ------------------------------------------------------------
+
+size_t stream_push_workspace_bytes(int nsig, int nch, int64_t P) {
+    return 2 * (sizeof(cplx) * (size_t)P * 2 * nsig + 256) + 2 * (sizeof(cplx) * (size_t)P * nch + 256) + 1024;
+}
+
+hipError_t launch_stream_push(const StreamState& st, const double* d_chunk, int64_t n, int64_t P, void* d_work,
+                              hipStream_t s) {
+    char* w = (char*)d_work;
+    auto take = [&](size_t bytes) {
+        char* r = w;
+        w += (bytes + 255) & ~(size_t)255;
+        return r;
+    };
+    cplx* UV = (cplx*)take(sizeof(cplx) * (size_t)P * 2 * st.nsig);
+    cplx* UV2 = (cplx*)take(sizeof(cplx) * (size_t)P * 2 * st.nsig);
+    cplx* Z1 = (cplx*)take(sizeof(cplx) * (size_t)P * st.nch);
+    cplx* Z2 = (cplx*)take(sizeof(cplx) * (size_t)P * st.nch);
+    cplx* U = UV;
+    cplx* V = UV + (size_t)P * st.nsig;
+    const int comps = st.kind == 0 ? 3 : 9;
+    k_stream_build<<<nblk(P), kB, 0, s>>>(d_chunk, n, comps, st.kind, st.nsig, st.n_hat[0], st.n_hat[1],
+                                          st.n_hat[2], st.e_hat[0], st.e_hat[1], st.e_hat[2], st.carry,
+                                          st.carry_cap, st.carry_len, P, U, V);
+    k_stream_state<<<st.nsig, kB, 0, s>>>(U, P, st.carry_len, n, st.carry_cap, st.carry_next, st.run_len, st.head,
+                                          st.M, st.totals);
+    cplx* a = UV;
+    cplx* b = UV2;
+    for (int64_t m = 1; m < P; m <<= 1) {
+        k_fft_pass<<<dim3(nblk(P / 2), (unsigned)(2 * st.nsig)), kB, 0, s>>>(a, b, P, m, -1.0);
+        cplx* t = a;
+        a = b;
+        b = t;
+    }
+    k_stream_power<<<dim3(nblk(P), (unsigned)st.nch), kB, 0, s>>>(a, a + (size_t)P * st.nsig, P, st.chx, st.chy,
+                                                                  st.chsym, Z1);
+    cplx* c = Z1;
+    cplx* d = Z2;
+    for (int64_t m = 1; m < P; m <<= 1) {
+        k_fft_pass<<<dim3(nblk(P / 2), (unsigned)st.nch), kB, 0, s>>>(c, d, P, m, 1.0);
+        cplx* t = c;
+        c = d;
+        d = t;
+    }
+    k_stream_accum<<<dim3(nblk(st.M), (unsigned)st.nch), kB, 0, s>>>(c, P, st.M, st.S);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_end_run(const StreamState& st, int subtract, hipStream_t s) {
+    k_stream_end<<<dim3(nblk(st.M), (unsigned)st.nch), kB, 0, s>>>(st.S, st.M, st.run_len, subtract, st.totals,
+                                                                   st.head, st.carry, st.carry_cap, st.carry_len,
+                                                                   st.chx, st.chy, st.chsym, st.run_sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_zero<<<nblk(n), kB, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_spectrum(const StreamState& st, double dt_fs, int window, int omega2, double laser_cm1,
+                                  double* d_tab, double* d_acf, double* d_freq, double* d_intensity, hipStream_t s) {
+    const int64_t M = st.M;
+    k_stream_combine<<<nblk(M), kB, 0, s>>>(st.run_sum, st.nch, M, st.chw, 1.0 / (double)st.n_runs, d_acf);
+    k_cos_table<<<nblk(2 * M), kB, 0, s>>>(M, d_tab);
+    k_transform<<<dim3(nblk(M + 1), 1), kB, 0, s>>>(d_acf, M, d_tab, M, window, omega2, laser_cm1, dt_fs, d_freq,
+                                                    d_intensity, M + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_map(const StreamState& st, double dt_fs, int window, double laser_cm1, const double* d_w,
+                             int n_orient, double* d_tab, double* d_acf, double* d_L, double* d_freq,
+                             double* d_intensity, hipStream_t s) {
+    const int64_t M = st.M;
+    k_scale<<<nblk((int64_t)st.nch * M), kB, 0, s>>>(st.run_sum, (int64_t)st.nch * M, 1.0 / (double)st.n_runs,
+                                                     d_acf);
+    k_cos_table<<<nblk(2 * M), kB, 0, s>>>(M, d_tab);
+    k_transform<<<dim3(nblk(M + 1), (unsigned)st.nch), kB, 0, s>>>(d_acf, M, d_tab, M, window, 0, laser_cm1, dt_fs,
+                                                                   d_freq, d_L, M + 1);
+    k_contract<<<dim3(nblk(M + 1), (unsigned)n_orient), kB, 0, s>>>(d_L, M, d_w, st.nch, d_intensity);
     return hipGetLastError();
 }
 

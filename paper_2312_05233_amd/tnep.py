@@ -28,7 +28,7 @@ OPT_NEIGH_BLOCK = 7
 OPT_GRAPHS = 8
 KERNEL_NEIGHBORS, KERNEL_EVAL_DIPOLE, KERNEL_EVAL_POLARIZABILITY, KERNEL_FRAME_REDUCE, KERNEL_SPECTRUM = 0, 1, 2, 3, 4
 KERNEL_EVAL_PES, KERNEL_PES_FORCES = 5, 6
-IR, RAMAN_ISO, RAMAN_ANISO, RAMAN_PROJ = 0, 1, 2, 3
+IR, RAMAN_ISO, RAMAN_ANISO, RAMAN_PROJ, RAMAN_MAP = 0, 1, 2, 3, 4
 WIN_HANN, WIN_NONE = 0, 1
 SUBTRACT_MEAN, NO_OMEGA2 = 1, 2
 
@@ -36,7 +36,9 @@ EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_
             "tnep_model_create", "tnep_model_free", "tnep_eval_dipole", "tnep_eval_polarizability",
             "tnep_eval_dipole_polarizability", "tnep_spectrum", "tnep_server_start", "tnep_submit", "tnep_wait",
             "tnep_server_stop", "tnep_server_stats", "tnep_ctx_kernel_time", "tnep_ctx_pair_counts",
-            "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts", "tnep_eval_pes"]
+            "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts", "tnep_eval_pes",
+            "tnep_raman_map", "tnep_acf_stream_create", "tnep_acf_stream_push", "tnep_acf_stream_end_run",
+            "tnep_acf_stream_spectrum", "tnep_acf_stream_raman_map", "tnep_acf_stream_free"]
 
 
 class TnepError(RuntimeError):
@@ -66,7 +68,8 @@ class FramesDesc(C.Structure):
 class SpectrumArgs(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_series", C.c_int32), ("n_steps", C.c_int64), ("series", C.c_void_p),
                 ("dt_fs", C.c_double), ("max_lag", C.c_int64), ("window", C.c_int32), ("flags", C.c_int32),
-                ("n_hat", C.c_double * 3), ("e_hat", C.c_double * 3), ("location", C.c_int32)]
+                ("n_hat", C.c_double * 3), ("e_hat", C.c_double * 3), ("location", C.c_int32),
+                ("laser_cm1", C.c_double)]
 
 
 class ServerOpts(C.Structure):
@@ -98,6 +101,14 @@ def _load():
     lib.tnep_eval_polarizability.argtypes = [vp, vp, P(FramesDesc), vp, vp]
     lib.tnep_eval_dipole_polarizability.argtypes = [vp, vp, vp, P(FramesDesc), vp, vp]
     lib.tnep_eval_pes.argtypes = [vp, vp, P(FramesDesc), vp, vp, vp, vp]
+    lib.tnep_raman_map.argtypes = [vp, P(SpectrumArgs), C.c_int32, vp, vp, vp, vp]
+    lib.tnep_acf_stream_create.argtypes = [vp, C.c_int32, C.c_int64, C.c_int32, vp, vp, P(vp)]
+    lib.tnep_acf_stream_push.argtypes = [vp, vp, C.c_int64, C.c_int32]
+    lib.tnep_acf_stream_end_run.argtypes = [vp]
+    lib.tnep_acf_stream_spectrum.argtypes = [vp, C.c_double, C.c_int32, C.c_double, vp, vp, vp]
+    lib.tnep_acf_stream_raman_map.argtypes = [vp, C.c_double, C.c_int32, C.c_double, C.c_int32, vp, vp, vp, vp]
+    lib.tnep_acf_stream_free.argtypes = [vp]
+    lib.tnep_acf_stream_free.restype = None
     lib.tnep_spectrum.argtypes = [vp, P(SpectrumArgs), vp, vp, vp]
     lib.tnep_server_start.argtypes = [vp, P(ServerOpts)]
     lib.tnep_submit.argtypes = [vp, vp, C.c_int32, P(FramesDesc), vp, P(C.c_uint64)]
@@ -112,7 +123,7 @@ def _load():
     lib.tnep_autotune_report.restype = C.c_char_p
     for name in EXPORTED:
         if name not in ("tnep_ctx_destroy", "tnep_last_error", "tnep_model_free", "tnep_ctx_memory_in_use",
-                        "tnep_autotune_report"):
+                        "tnep_autotune_report", "tnep_acf_stream_free"):
             getattr(lib, name).restype = C.c_int
     return lib
 
@@ -316,12 +327,13 @@ def tnep_eval_pes(ctx: Context, model: Model, frames, energy=None, virial=None, 
 
 
 def tnep_spectrum(ctx: Context, series, kind, dt_fs, max_lag, window=WIN_HANN, flags=0, n_hat=(0, 0, 0),
-                  e_hat=(0, 0, 0), freq=None, intensity=None, acf=None, want_acf=True):
+                  e_hat=(0, 0, 0), freq=None, intensity=None, acf=None, want_acf=True, laser_cm1=0.0):
     """series [S, N_t, 3|9] (numpy: host; torch CUDA: device, outputs must be given)."""
     a = SpectrumArgs()
     a.kind = kind
     a.n_series, a.n_steps = int(series.shape[0]), int(series.shape[1])
     a.dt_fs, a.max_lag, a.window, a.flags = dt_fs, int(max_lag), window, flags
+    a.laser_cm1 = float(laser_cm1)
     for k in range(3):
         a.n_hat[k], a.e_hat[k] = n_hat[k], e_hat[k]
     if isinstance(series, np.ndarray):
@@ -337,6 +349,77 @@ def tnep_spectrum(ctx: Context, series, kind, dt_fs, max_lag, window=WIN_HANN, f
     a.series = _ptr(series)
     ctx.check(lib.tnep_spectrum(ctx.h, C.byref(a), _ptr(freq), _ptr(intensity), _ptr(acf)))
     return freq, intensity, acf
+
+
+def tnep_raman_map(ctx: Context, series, dt_fs, max_lag, n_hats, e_hats, window=WIN_HANN, flags=0, laser_cm1=0.0,
+                   freq=None, intensity=None):
+    """Orientation map: series [S, N_t, 9]; n_hats, e_hats [n_orient, 3] (host).
+    Returns (freq [M+1], intensity [n_orient, M+1])."""
+    n_hats = np.ascontiguousarray(n_hats, np.float64).reshape(-1, 3)
+    e_hats = np.ascontiguousarray(e_hats, np.float64).reshape(-1, 3)
+    a = SpectrumArgs()
+    a.kind = RAMAN_PROJ
+    a.n_series, a.n_steps = int(series.shape[0]), int(series.shape[1])
+    a.dt_fs, a.max_lag, a.window, a.flags, a.laser_cm1 = dt_fs, int(max_lag), window, flags, float(laser_cm1)
+    M = int(max_lag)
+    if isinstance(series, np.ndarray):
+        series = np.ascontiguousarray(series, np.float64)
+        a.location = HOST
+        freq = np.zeros(M + 1) if freq is None else freq
+        intensity = np.zeros((len(n_hats), M + 1)) if intensity is None else intensity
+    else:
+        a.location = DEVICE
+    a.series = _ptr(series)
+    ctx.check(lib.tnep_raman_map(ctx.h, C.byref(a), len(n_hats), _ptr(n_hats), _ptr(e_hats), _ptr(freq),
+                                 _ptr(intensity)))
+    return freq, intensity
+
+
+class AcfStream:
+    """Streaming correlation accumulator (tnep_acf_stream_*)."""
+
+    def __init__(self, ctx: Context, kind, max_lag, flags=0, n_hat=None, e_hat=None):
+        self.ctx, self.kind, self.M = ctx, kind, int(max_lag)
+        nh = None if n_hat is None else np.ascontiguousarray(n_hat, np.float64)
+        eh = None if e_hat is None else np.ascontiguousarray(e_hat, np.float64)
+        h = C.c_void_p()
+        ctx.check(lib.tnep_acf_stream_create(ctx.h, kind, self.M, flags, _ptr(nh), _ptr(eh), C.byref(h)))
+        self.h = h
+
+    def push(self, samples):
+        if isinstance(samples, np.ndarray):
+            samples = np.ascontiguousarray(samples, np.float64)
+            loc = HOST
+        else:
+            loc = DEVICE
+        self.ctx.check(lib.tnep_acf_stream_push(self.h, _ptr(samples), int(samples.shape[0]), loc))
+
+    def end_run(self):
+        self.ctx.check(lib.tnep_acf_stream_end_run(self.h))
+
+    def spectrum(self, dt_fs, window=WIN_HANN, laser_cm1=0.0):
+        f, s, a = np.zeros(self.M + 1), np.zeros(self.M + 1), np.zeros(self.M)
+        self.ctx.check(lib.tnep_acf_stream_spectrum(self.h, dt_fs, window, float(laser_cm1), _ptr(f), _ptr(s), _ptr(a)))
+        return f, s, a
+
+    def raman_map(self, dt_fs, n_hats, e_hats, window=WIN_HANN, laser_cm1=0.0):
+        n_hats = np.ascontiguousarray(n_hats, np.float64).reshape(-1, 3)
+        e_hats = np.ascontiguousarray(e_hats, np.float64).reshape(-1, 3)
+        f, s = np.zeros(self.M + 1), np.zeros((len(n_hats), self.M + 1))
+        self.ctx.check(lib.tnep_acf_stream_raman_map(self.h, dt_fs, window, float(laser_cm1), len(n_hats),
+                                                     _ptr(n_hats), _ptr(e_hats), _ptr(f), _ptr(s)))
+        return f, s
+
+    def close(self):
+        if self.h:
+            lib.tnep_acf_stream_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:
