@@ -379,3 +379,29 @@ def sinusoid_series(n_steps: int, omega_per_step: float, amp: float = 1.0, offse
     if noise:
         x = x + rng.normal(0.0, noise, x.shape)
     return x
+
+
+def susceptibility_runs(n_runs: int = 20, n_steps: int = 100000, seed: int = 5, n_modes: int = 6,
+                        dt_fs: float = 5.0) -> np.ndarray:
+    """Stand-in for the recorded chi(t) of the perovskite runs (20 runs of
+    500 ps at 5 fs): per run a symmetric tensor series = a static part, a sum
+    of damped-random-phase modes (wavenumbers 50-800 cm^-1, random symmetric
+    mode tensors) and white noise.  [n_runs, n_steps, 9]."""
+    rng = np.random.default_rng(seed)
+    c_cm_per_fs = 2.99792458e-5
+    t = np.arange(n_steps) * dt_fs
+    out = np.empty((n_runs, n_steps, 9))
+    base = rng.normal(size=(3, 3))
+    base = 0.5 * (base + base.T) + 5.0 * np.eye(3)
+    for r in range(n_runs):
+        x = np.broadcast_to(base, (n_steps, 3, 3)).copy()
+        for _ in range(n_modes):
+            nu = rng.uniform(50.0, 800.0)
+            w = 2.0 * np.pi * nu * c_cm_per_fs
+            phase = np.cumsum(rng.normal(0.0, 0.02, n_steps))  # slow phase diffusion: finite line width
+            T = rng.normal(size=(3, 3))
+            T = 0.5 * (T + T.T)
+            x += (0.3 * np.cos(w * t + phase))[:, None, None] * T[None]
+        x += rng.normal(0.0, 0.05, x.shape)
+        out[r] = x.reshape(n_steps, 9)
+    return out
