@@ -279,7 +279,9 @@ struct Stream {
     }
 };
 
-__global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restrict__ frames,
+// Four waves per SIMD (<= 128 VGPRs): the candidate loop is bound by load
+// latency, so occupancy matters more than anything the registers could buy.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_neighbors(const FrameInfo* __restrict__ frames,
                                                       const int32_t* __restrict__ frame_of,
                                                       const double* __restrict__ pos,
                                                       const int32_t* __restrict__ key_of,
@@ -302,12 +304,14 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
     const FrameInfo fi = frames[frame_of[a]];  // by value: kept in registers across the stores below
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
+    // cell pruning in FP32 with a 1e-3 A margin: a cell is skipped only when surely beyond r_c
+    const float prune2 = (rc_radial + 1e-3f) * (rc_radial + 1e-3f);
     // entry (row r) of this lane: lane_base + (r / 4) * 256 + r % 4
     float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
     int ix = 0, iy = 0, iz = 0;
     const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
     // distances from the atom to the lower / upper faces of its cell (cell list)
-    double lo_x = 0, hi_x = 0, lo_y = 0, hi_y = 0, lo_z = 0, hi_z = 0;
+    float lo_x = 0, hi_x = 0, lo_y = 0, hi_y = 0, lo_z = 0, hi_z = 0;
     if (fi.mode == 1) {
         const int local = key_of[a] / T - fi.cell_base;
         iz = local % nz;
@@ -317,12 +321,12 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
         const double wx = xi - fi.L[0] * floor(xi * fi.Linv[0]);
         const double wy = yi - fi.L[1] * floor(yi * fi.Linv[1]);
         const double wz = zi - fi.L[2] * floor(zi * fi.Linv[2]);
-        lo_x = fmax(wx - ix * hx, 0.0);
-        hi_x = fmax((ix + 1) * hx - wx, 0.0);
-        lo_y = fmax(wy - iy * hy, 0.0);
-        hi_y = fmax((iy + 1) * hy - wy, 0.0);
-        lo_z = fmax(wz - iz * hz, 0.0);
-        hi_z = fmax((iz + 1) * hz - wz, 0.0);
+        lo_x = (float)fmax(wx - ix * hx, 0.0);
+        hi_x = (float)fmax((ix + 1) * hx - wx, 0.0);
+        lo_y = (float)fmax(wy - iy * hy, 0.0);
+        hi_y = (float)fmax((iy + 1) * hy - wy, 0.0);
+        lo_z = (float)fmax(wz - iz * hz, 0.0);
+        hi_z = (float)fmax((iz + 1) * hz - wz, 0.0);
     }
     bool overlap = false;
     for (int t = 0; t < T; ++t) {
@@ -338,33 +342,38 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(const FrameInfo* __restric
             if (fi.mode == 1) {
                 const int ox = vb / 9 - 1, oy = (vb / 3) % 3 - 1, oz = vb % 3 - 1;
                 // skip cells whose nearest point is beyond the radial cutoff
-                const double gx = ox < 0 ? lo_x : (ox > 0 ? hi_x : 0.0);
-                const double gy = oy < 0 ? lo_y : (oy > 0 ? hi_y : 0.0);
-                const double gz = oz < 0 ? lo_z : (oz > 0 ? hi_z : 0.0);
-                if (gx * gx + gy * gy + gz * gz >= rc2r) continue;
+                const float gx = ox < 0 ? lo_x : (ox > 0 ? hi_x : 0.f);
+                const float gy = oy < 0 ? lo_y : (oy > 0 ? hi_y : 0.f);
+                const float gz = oz < 0 ? lo_z : (oz > 0 ? hi_z : 0.f);
+                if (gx * gx + gy * gy + gz * gz >= prune2) continue;
                 const int cx = (ix + ox + nx) % nx;
                 const int cy = (iy + oy + ny) % ny;
                 const int cz = (iz + oz + nz) % nz;
                 bucket = (fi.cell_base + (cx * ny + cy) * nz + cz) * T + t;
             }
             const int b = bucket_start[bucket], e = bucket_start[bucket + 1];
-            double4 q = b < e ? bucket_pos[b] : make_double4(0.0, 0.0, 0.0, 0.0);
-            for (int k = b; k < e; ++k) {
-                const double4 cur = q;
-                if (k + 1 < e) q = bucket_pos[k + 1];
-                const int j = (int)__double_as_longlong(cur.w);  // tile slot of the candidate
-                if (j == (int)p) continue;
-                const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
-                const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
-                const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 >= rc2r) continue;
-                if (r2 < 1e-8) overlap = true;
-                const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
-                if (r2 < rc2a)
-                    sa.push(ent, ga, capA);
-                else
-                    sr.push(ent, gr, capR);
+            // candidates two at a time: both loads in flight before either is used
+            for (int k0 = b; k0 < e; k0 += 2) {
+                const double4 q0 = bucket_pos[k0];
+                const double4 q1 = k0 + 1 < e ? bucket_pos[k0 + 1] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (k0 + u >= e) break;
+                    const double4 cur = u == 0 ? q0 : q1;
+                    const int j = (int)__double_as_longlong(cur.w);  // tile slot of the candidate
+                    if (j == (int)p) continue;
+                    const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
+                    const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
+                    const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 >= rc2r) continue;
+                    if (r2 < 1e-8) overlap = true;
+                    const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
+                    if (r2 < rc2a)
+                        sa.push(ent, ga, capA);
+                    else
+                        sr.push(ent, gr, capR);
+                }
             }
         }
         sa.flush(ga, capA);
