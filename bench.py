@@ -463,6 +463,9 @@ def main():
     ap.add_argument("--mlp", type=int, default=None, help="TNEP_MLP_* mode of the hidden layer")
     ap.add_argument("--atoms-per-block", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
+    ap.add_argument("--trajectory-window", type=int, default=0,
+                    help="frames per neighbour-candidate window of the trajectory (0 = plain searches)")
+    ap.add_argument("--skin", type=float, default=1.0, help="candidate skin in Angstrom")
     ap.add_argument("--workload", default="water", choices=["water", "perovskite", "molecules", "serving", "pes", "spectra"],
                     help="water: the headline line; the others print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -504,6 +507,9 @@ def main():
         ctx.set_option(tnep.OPT_ATOMS_PER_BLOCK, args.atoms_per_block)
     if not args.no_autotune:
         ctx.set_option(tnep.OPT_AUTOTUNE, 1)  # tuned during the warm-up step
+    if args.trajectory_window > 1:
+        ctx.set_option(tnep.OPT_TRAJECTORY_WINDOW, args.trajectory_window)
+        ctx.set_option(tnep.OPT_SKIN_MA, int(round(args.skin * 1000)))
     gd, gp = tnep.Model(ctx, md), tnep.Model(ctx, mp)
     dfr = tnep.DeviceFrames(frames)
     mu = torch.zeros((F, 3), dtype=torch.float64, device=dev)
@@ -567,6 +573,8 @@ def main():
             "frames": F, "atoms_per_frame": A // F, "atom_frames_per_step": A,
             "descriptor": "rc 6/4 A, n_max 4/4, basis 8/8, l_max 4 + 4-body, H=30",
             "precision": "FP32 descriptor/network/partial forces, FP64 frame sums and spectra",
+            "neighbour_reuse": {"window": args.trajectory_window, "skin_A": args.skin,
+                                "fallbacks": ctx.reuse_fallbacks()},
         },
         "roofline": {
             "kernel": "k_eval<5,5,9,9,4-body,polarizability>",

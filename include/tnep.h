@@ -89,6 +89,18 @@ extern "C" {
                                      bitwise those of the plain launches.  Needs a non-null
                                      stream.  A call on a context must not overlap another
                                      call on the same context (as for every entry point). */
+#define TNEP_OPT_TRAJECTORY_WINDOW 9 /* W >= 2: consecutive frames of a call with equal atom counts
+                                     and boxes (all axes periodic, edges >= 2 (r_c + skin)) are
+                                     taken as frames of one trajectory: in each window of W
+                                     frames the first searches its cells out to r_c + skin and
+                                     the others test only those candidates (exact r < r_c
+                                     test).  If any atom moved more than skin/2 from the
+                                     window's first frame or changed species, the call is
+                                     redone with plain searches.  Results agree with plain
+                                     searches up to FP32 summation order (the neighbour order
+                                     differs).  0 (default) = off */
+#define TNEP_OPT_SKIN_MA 10       /* skin for TNEP_OPT_TRAJECTORY_WINDOW in 1e-3 Angstrom
+                                     (1..5000, default 1000) */
 
 /* kernel classes for tnep_ctx_kernel_time */
 #define TNEP_KERNEL_NEIGHBORS 0
@@ -172,6 +184,9 @@ int tnep_ctx_reset_timing(tnep_ctx* ctx);
  * context was created (with a running server: its slots' counts added).
  * Either pointer may be NULL. */
 int tnep_ctx_graph_counts(const tnep_ctx* ctx, uint64_t* captures, uint64_t* launches);
+/* Calls redone with plain searches because a trajectory window's guard
+ * failed (TNEP_OPT_TRAJECTORY_WINDOW). */
+int tnep_ctx_reuse_fallbacks(const tnep_ctx* ctx, uint64_t* count);
 
 /* ---- model ------------------------------------------------------------- */
 /* Copy a model to the device (resident until tnep_model_free). TNEP_E_MODEL if

@@ -203,6 +203,12 @@ extern "C" int tnep_ctx_pair_counts(const tnep_ctx* ctx, uint64_t* atoms, uint64
     return TNEP_OK;
 }
 
+extern "C" int tnep_ctx_reuse_fallbacks(const tnep_ctx* ctx, uint64_t* count) {
+    if (!ctx || !count) return TNEP_E_INVALID;
+    *count = reinterpret_cast<const Ctx*>(ctx)->reuse_fallbacks;
+    return TNEP_OK;
+}
+
 extern "C" int tnep_ctx_graph_counts(const tnep_ctx* ctx, uint64_t* captures, uint64_t* launches) {
     if (!ctx) return TNEP_E_INVALID;
     const Ctx* c = reinterpret_cast<const Ctx*>(ctx);
@@ -261,6 +267,14 @@ extern "C" int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value) {
             if (value != 0 && !c->stream) return c->fail(TNEP_E_INVALID, "graphs need a non-null stream");
             c->use_graphs = value != 0;
             if (!c->use_graphs) c->drop_graphs();
+            return TNEP_OK;
+        case TNEP_OPT_TRAJECTORY_WINDOW:
+            if (value < 0 || value > 4096) return c->fail(TNEP_E_INVALID, "trajectory window must be 0..4096");
+            c->traj_window = (int)value;
+            return TNEP_OK;
+        case TNEP_OPT_SKIN_MA:
+            if (value < 1 || value > 5000) return c->fail(TNEP_E_INVALID, "skin must be 1..5000 mA");
+            c->skin = (double)value * 1e-3;
             return TNEP_OK;
         case TNEP_OPT_MAX_BATCH_ATOMS:
             if (value < 1) return c->fail(TNEP_E_INVALID, "max batch atoms must be positive");

@@ -303,8 +303,26 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                fr.pbc ? meta.pbc.data() + 3 * (size_t)f : nullptr, gm->rc_radial, geom[f]);
             if (e) return e;
         }
+        // trajectory reuse: frames whose cell grid can hold r_c + skin (all
+        // axes periodic, every edge >= 2 (r_c + skin), >= 3 cells per axis)
+        const double rc_search = gm->rc_radial + c->skin;
+        bool reuse = c->traj_window > 1;
+        std::vector<FrameGeom> geom_rs(reuse ? F : 0);
+        std::vector<char> eligible(reuse ? F : 0, 0);
+        for (int f = 0; reuse && f < F; ++f) {
+            const FrameGeom& g = geom[f];
+            bool ok = g.per[0] && g.per[1] && g.per[2];
+            for (int d = 0; d < 3 && ok; ++d) ok = g.L[d] >= 2.0 * rc_search;
+            if (ok) {
+                e = frame_geometry(c, f, meta.cells.data() + 9 * (size_t)f, meta.pbc.data() + 3 * (size_t)f,
+                                   rc_search, geom_rs[f]);
+                if (e) return e;
+                ok = geom_rs[f].mode == 1;
+            }
+            eligible[f] = ok;
+        }
         bool done = false;
-        for (int attempt = 0; attempt < 4 && !done; ++attempt) {
+        for (int attempt = 0; attempt < 6 && !done; ++attempt) {
             // rows per tile slot: per-species angular and radial-only segments
             int segA[8] = {0}, segR[8] = {0}, slots = 0;
             for (int t = 0; t < T; ++t) {
@@ -353,6 +371,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                                 c->stream));
             }
             if ((e = c->reserve(c->frame_of, (size_t)B_res * 4))) return e;
+            if ((e = c->reserve(c->slot_of, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->key_of, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->bucket_atoms, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->bucket_pos, (size_t)B_res * 32))) return e;
@@ -391,12 +410,35 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 bh.fi.resize(nf);
                 std::vector<FrameInfo>& fi = bh.fi;
                 int n_cells = 0;
+                int64_t n_ref_atoms = 0;
+                bool followers = false;
+                int ref_k = -1;  // reference frame of the open window
                 for (int k = 0; k < nf; ++k) {
-                    const FrameGeom& g = geom[f0 + k];
+                    const int f = f0 + k;
                     FrameInfo& x = fi[k];
                     std::memset(&x, 0, sizeof(x));
-                    x.atom_begin = meta.offs[f0 + k] - a0;
-                    x.n_atoms = (int32_t)(meta.offs[f0 + k + 1] - meta.offs[f0 + k]);
+                    x.atom_begin = meta.offs[f] - a0;
+                    x.n_atoms = (int32_t)(meta.offs[f + 1] - meta.offs[f]);
+                    x.role = kRolePlain;
+                    if (reuse && eligible[f]) {
+                        const FrameInfo* r = ref_k >= 0 ? &fi[ref_k] : nullptr;
+                        bool follow = r && k - ref_k < c->traj_window && r->n_atoms == x.n_atoms;
+                        for (int d = 0; d < 3 && follow; ++d) follow = geom_rs[f].L[d] == r->L[d];
+                        if (follow) {
+                            x.role = kRoleFollower;
+                            x.ref_begin = r->atom_begin;
+                            x.cl_base = r->cl_base;
+                            followers = true;
+                        } else {
+                            x.role = kRoleReference;
+                            x.cl_base = n_ref_atoms;
+                            n_ref_atoms += x.n_atoms;
+                            ref_k = k;
+                        }
+                    } else {
+                        ref_k = -1;
+                    }
+                    const FrameGeom& g = x.role == kRolePlain ? geom[f] : geom_rs[f];
                     x.mode = g.mode;
                     for (int d = 0; d < 3; ++d) {
                         x.nc[d] = g.nc[d];
@@ -414,6 +456,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 const int64_t n_buckets = cap_cells * T;
                 if (n_buckets >= ((int64_t)1 << 30)) return c->fail(TNEP_E_INVALID, "too many cells in one batch");
                 if ((e = c->reserve(c->frames, sizeof(FrameInfo) * cap_frames))) return e;
+                if (n_ref_atoms > 0) {
+                    if ((e = c->reserve(c->cand, (size_t)n_ref_atoms * T * c->cap_cand * 4))) return e;
+                    if ((e = c->reserve(c->cand_count, (size_t)n_ref_atoms * T * 4))) return e;
+                }
                 if ((e = c->reserve(c->bucket_count, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->bucket_start, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->bucket_fill, (size_t)4 * (n_buckets + 1)))) return e;
@@ -444,7 +490,9 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 NeighborWork w{(int32_t*)c->frame_of.p,     (int32_t*)c->key_of.p,       (int32_t*)c->bucket_count.p,
                                (int32_t*)c->bucket_start.p, (int32_t*)c->bucket_fill.p,  (int32_t*)c->bucket_atoms.p,
                                (double4*)c->bucket_pos.p,   (int32_t*)c->perm_start.p,   (int32_t*)c->perm.p,
-                               (int32_t*)c->tile_base.p,    (int32_t*)c->scan_chunks.p};
+                               (int32_t*)c->tile_base.p,    (int32_t*)c->scan_chunks.p,  (int32_t*)c->slot_of.p};
+                const CandLists cl{(int32_t*)c->cand.p, (int32_t*)c->cand_count.p, c->cap_cand,
+                                   (float)rc_search, (float)(0.25 * c->skin * c->skin)};
                 NeighborLists nl{};
                 nl.entries = (float4*)c->nbr.p;
                 nl.counts = (int32_t*)c->counts.p;
@@ -488,8 +536,9 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     hipError_t he;
                     int tr = c->timer_begin(TNEP_KERNEL_NEIGHBORS);
                     he = launch_neighbors((const FrameInfo*)c->frames.p, cap_frames, pos, spc, cap_atoms,
-                                          (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl,
-                                          (int32_t*)c->flags.p, c->launch.neigh_block, c->stream);
+                                          (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl, cl,
+                                          n_ref_atoms > 0, followers, (int32_t*)c->flags.p, c->launch.neigh_block,
+                                          c->stream);
                     c->timer_end(tr);
                     if (he != hipSuccess) return he;
                     if (c->timing) {
@@ -521,8 +570,13 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     return hipSuccess;
                 };
                 if (graphs) {
-                    if ((e = replay_graph(c, graph_key(c, job, first, last, T, cap_atoms, cap_frames, cap_cells, B_res),
-                                          launch_batch)))
+                    std::string key = graph_key(c, job, first, last, T, cap_atoms, cap_frames, cap_cells, B_res);
+                    if (n_ref_atoms > 0) {
+                        char rb[64];
+                        snprintf(rb, sizeof(rb), "/r%d.%d", c->cap_cand, followers ? 1 : 0);
+                        key += rb;
+                    }
+                    if ((e = replay_graph(c, key, launch_batch)))
                         return e;
                 } else {
                     HIP_CHECK_RET(c, launch_batch());
@@ -560,6 +614,12 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             HIP_CHECK_RET(c, hipStreamSynchronize(c->stream));
             c->timer_flush();
             const int32_t* fl = c->h_flags;
+            if (reuse && fl[kFlagReuse]) {
+                // an atom moved more than skin / 2 (or changed species): plain searches
+                reuse = false;
+                ++c->reuse_fallbacks;
+                continue;
+            }
             if (fl[kFlagError]) {
                 const int code = (fl[kFlagError] & kErrNonFinite) ? TNEP_E_NONFINITE
                                  : (fl[kFlagError] & kErrSpecies) ? TNEP_E_SPECIES
@@ -580,6 +640,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     c->cap_rad[t] = (fl[kFlagCapRad + t] * 5 / 4 + 3) / 4 * 4;
                     grow = true;
                 }
+            }
+            if (reuse && fl[kFlagCapCand] > c->cap_cand) {
+                c->cap_cand = (fl[kFlagCapCand] * 5 / 4 + 3) / 4 * 4;
+                grow = true;
             }
             if (!grow) done = true;
         }

@@ -7,6 +7,15 @@
 namespace tnep {
 
 // Per-frame geometry of one launch batch (built on the host).
+// Trajectory reuse of neighbour candidates (TNEP_OPT_TRAJECTORY_WINDOW): a
+// reference frame (role 1) searches its cells out to r_c + skin and keeps,
+// per atom and neighbour species, the frame-local indices of the candidates;
+// the following frames of its window (role 2: same atom count, species and
+// box) test only those candidates against the exact r < r_c.  Every follower
+// atom checks that it moved at most skin / 2 from the reference (minimum
+// image) and kept its species, else the call is redone with plain searches.
+enum FrameRole { kRolePlain = 0, kRoleReference = 1, kRoleFollower = 2 };
+
 struct FrameInfo {
     int64_t atom_begin;  // first atom, batch-local index
     int32_t n_atoms;
@@ -14,9 +23,11 @@ struct FrameInfo {
     int32_t nc[3];       // cells per axis (mode 1)
     int32_t cell_base;   // first cell of this frame in the batch's cell arrays
     int32_t per[3];      // periodic axes
-    int32_t pad;
+    int32_t role;        // FrameRole
     double L[3];         // box edges (periodic axes)
     double Linv[3];      // 1 / L (periodic axes), else 0
+    int64_t ref_begin;   // follower: atom_begin of its reference frame
+    int64_t cl_base;     // reference / follower: first candidate list of the reference's atoms
 };
 
 // Device-resident FP32 model parameters.
@@ -89,10 +100,20 @@ struct NeighborLists {
 };
 
 // Error / overflow flags written by the kernels (device int32[32]).
-enum Flag { kFlagError = 0, kFlagBadAtom = 1, kFlagCapAng = 8, kFlagCapRad = 16 };
+enum Flag { kFlagError = 0, kFlagBadAtom = 1, kFlagCapAng = 8, kFlagCapRad = 16, kFlagCapCand = 24, kFlagReuse = 25 };
 enum ErrBits { kErrSpecies = 1, kErrNonFinite = 2, kErrOverlap = 4 };
 
 // ---- neighbour search (kernels_neighbors.hip) ----
+// Candidate lists of reference-frame atoms: list (cl_base + i) * T + t holds
+// up to cap frame-local indices of species-t candidates of atom i.
+struct CandLists {
+    int32_t* idx;      // [lists][cap]
+    int32_t* count;    // [lists]
+    int32_t cap;       // multiple of 4
+    float rc_search;   // r_c + skin
+    float half_skin2;  // (skin / 2)^2
+};
+
 struct NeighborWork {
     int32_t* frame_of;      // [n_atoms]
     int32_t* key_of;        // [n_atoms] bucket (cell * T + species)
@@ -105,14 +126,19 @@ struct NeighborWork {
     int32_t* perm;          // [n_pad]
     int32_t* meta;          // [kMetaInts], tile_base part written on the device
     int32_t* chunk;         // [2 * 9 * n_chunks] scan partials (n_chunks = ceil(n_cells / 1024))
+    int32_t* slot_of;       // [n_atoms] tile slot of every atom
 };
 
 // Sizes: the actual atoms, frames and cells of the batch are in meta
 // (kMetaNAtoms, kMetaNFrames, kMetaNCells); cap_* are the launch capacities
 // (>= the actual sizes) that size the grids.
+// references / followers: the batch has frames of role 1 / role 2 (each
+// role has a pass over the slots of its own; followers run after the
+// reference frames' lists are complete).
 hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
-                            const NeighborLists& nl, int32_t* d_flags, int neigh_block, hipStream_t s);
+                            const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
+                            int32_t* d_flags, int neigh_block, hipStream_t s);
 
 // ---- evaluation (kernels_eval.hip) ----
 struct EvalLaunch {

@@ -214,11 +214,12 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 }
 
 // Sort each bucket by atom index, place it into the tile permutation and
-// store its positions contiguously in bucket order (w = the atom's tile slot).
+// store its positions contiguously in bucket order (w = the atom's tile slot
+// in the low 32 bits, its batch index in the high 32 bits).
 __global__ void k_sort_place(const int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_atoms,
                              const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm,
-                             const double* __restrict__ pos, double4* __restrict__ bucket_pos,
-                             const int32_t* __restrict__ meta, int T) {
+                             int32_t* __restrict__ slot_of, const double* __restrict__ pos,
+                             double4* __restrict__ bucket_pos, const int32_t* __restrict__ meta, int T) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= meta[kMetaNCells] * T) return;
     const int b = bucket_start[k], e = bucket_start[k + 1];
@@ -234,9 +235,11 @@ __global__ void k_sort_place(const int32_t* __restrict__ bucket_start, int32_t* 
     const int p = perm_start[k];
     for (int i = b; i < e; ++i) {
         const int a = bucket_atoms[i];
-        perm[p + (i - b)] = a;
+        const int slot = p + (i - b);
+        perm[slot] = a;
+        slot_of[a] = slot;
         bucket_pos[i] = make_double4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2],
-                                     __longlong_as_double((long long)(p + (i - b))));
+                                     __longlong_as_double((long long)(((uint64_t)(uint32_t)a << 32) | (uint32_t)slot)));
     }
 }
 
@@ -281,13 +284,18 @@ struct Stream {
 
 // Four waves per SIMD (<= 128 VGPRs): the candidate loop is bound by load
 // latency, so occupancy matters more than anything the registers could buy.
+// REF = false: plain frames and padding slots; REF = true: reference frames,
+// which also keep their candidates out to r_c + skin.
+template <bool REF>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_neighbors(const FrameInfo* __restrict__ frames,
                                                       const int32_t* __restrict__ frame_of,
                                                       const double* __restrict__ pos,
+                                                      const int32_t* __restrict__ species,
+                                                      const int32_t* __restrict__ slot_of,
                                                       const int32_t* __restrict__ key_of,
                                                       const int32_t* __restrict__ bucket_start,
                                                       const double4* __restrict__ bucket_pos, float rc_radial,
-                                                      float rc_angular, NeighborLists nl,
+                                                      float rc_angular, NeighborLists nl, CandLists cl,
                                                       int32_t* __restrict__ flags) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nl.n_pad) return;
@@ -295,6 +303,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const int a = nl.perm[p];
     const int tile = (int)(p >> 6), lane = (int)(p & 63);
     if (a < 0) {
+        if (REF) return;
         for (int t = 0; t < T; ++t) {
             nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = 0;
             nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = 0;
@@ -302,10 +311,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         return;
     }
     const FrameInfo fi = frames[frame_of[a]];  // by value: kept in registers across the stores below
+    // followers: k_neighbors_follow, after the reference lists are complete
+    if (fi.role != (REF ? kRoleReference : kRolePlain)) return;
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
-    // cell pruning in FP32 with a 1e-3 A margin: a cell is skipped only when surely beyond r_c
-    const float prune2 = (rc_radial + 1e-3f) * (rc_radial + 1e-3f);
+    // references collect candidates out to r_c + skin
+    const float rs = REF ? cl.rc_search : rc_radial;
+    const double rcs2 = (double)rs * rs;
+    // cell pruning in FP32 with a 1e-3 A margin: a cell is skipped only when surely beyond the radius
+    const float prune2 = (rs + 1e-3f) * (rs + 1e-3f);
     // entry (row r) of this lane: lane_base + (r / 4) * 256 + r % 4
     float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
     int ix = 0, iy = 0, iz = 0;
@@ -336,6 +350,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
         float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
         const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
+        int n_cand = 0;
+        int32_t* cand = REF ? cl.idx + ((fi.cl_base + (a - fi.atom_begin)) * T + t) * cl.cap : nullptr;
         const int n_visit = fi.mode == 1 ? 27 : 1;
         for (int vb = 0; vb < n_visit; ++vb) {
             int bucket = fi.cell_base * T + t;
@@ -360,12 +376,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                 for (int u = 0; u < 2; ++u) {
                     if (k0 + u >= e) break;
                     const double4 cur = u == 0 ? q0 : q1;
-                    const int j = (int)__double_as_longlong(cur.w);  // tile slot of the candidate
+                    const uint64_t wj = (uint64_t)__double_as_longlong(cur.w);
+                    const int j = (int)(uint32_t)wj;  // tile slot of the candidate
                     if (j == (int)p) continue;
                     const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
                     const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
                     const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
                     const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 >= rcs2) continue;
+                    if constexpr (REF) {
+                        if (n_cand < cl.cap) cand[n_cand] = (int)(wj >> 32) - (int)fi.atom_begin;
+                        ++n_cand;
+                    }
                     if (r2 >= rc2r) continue;
                     if (r2 < 1e-8) overlap = true;
                     const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
@@ -374,6 +396,90 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                     else
                         sr.push(ent, gr, capR);
                 }
+            }
+        }
+        if constexpr (REF) {
+            cl.count[(fi.cl_base + (a - fi.atom_begin)) * T + t] = n_cand;
+            if (n_cand > cl.cap) atomicMax(&flags[kFlagCapCand], n_cand);
+        }
+        sa.flush(ga, capA);
+        sr.flush(gr, capR);
+        nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(sa.n, capA);
+        nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(sr.n, capR);
+        if (sa.n > capA) atomicMax(&flags[kFlagCapAng + t], sa.n);
+        if (sr.n > capR) atomicMax(&flags[kFlagCapRad + t], sr.n);
+    }
+    if (overlap) {
+        atomicOr(&flags[kFlagError], kErrOverlap);
+        atomicMin(&flags[kFlagBadAtom], a);
+    }
+}
+
+// Frames that follow a reference frame of their trajectory window: test the
+// reference atom's candidates (same frame-local indices) with the exact
+// r < r_c, and check the guard (displacement <= skin / 2, same species).
+__global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __restrict__ frames,
+                                                             const int32_t* __restrict__ frame_of,
+                                                             const double* __restrict__ pos,
+                                                             const int32_t* __restrict__ species,
+                                                             const int32_t* __restrict__ slot_of, float rc_radial,
+                                                             float rc_angular, NeighborLists nl, CandLists cl,
+                                                             int32_t* __restrict__ flags) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nl.n_pad) return;
+    const int T = nl.T;
+    const int a = nl.perm[p];
+    if (a < 0) return;
+    const FrameInfo fi = frames[frame_of[a]];
+    if (fi.role != kRoleFollower) return;
+    const int tile = (int)(p >> 6), lane = (int)(p & 63);
+    const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
+    const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
+    float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
+    const int64_t il = a - fi.atom_begin;
+    const int64_t aref = fi.ref_begin + il;
+    const double mx = min_image(xi - pos[3 * aref], fi.L[0], fi.Linv[0]);
+    const double my = min_image(yi - pos[3 * aref + 1], fi.L[1], fi.Linv[1]);
+    const double mz = min_image(zi - pos[3 * aref + 2], fi.L[2], fi.Linv[2]);
+    if (!(mx * mx + my * my + mz * mz <= (double)cl.half_skin2) || species[a] != species[aref])
+        atomicOr(&flags[kFlagReuse], 1);
+    bool overlap = false;
+    for (int t = 0; t < T; ++t) {
+        Stream sa, sr;
+        sa.n = 0;
+        sr.n = 0;
+        float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
+        float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
+        const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
+        const int64_t list = (fi.cl_base + il) * T + t;
+        const int n = min(cl.count[list], cl.cap);
+        const int4* idx4 = reinterpret_cast<const int4*>(cl.idx + list * cl.cap);
+        for (int k0 = 0; k0 < n; k0 += 4) {
+            const int4 jj = idx4[k0 >> 2];
+            const int jl[4] = {jj.x, jj.y, jj.z, jj.w};
+            double cx[4], cy[4], cz[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t j = fi.atom_begin + (k0 + u < n ? jl[u] : 0);
+                cx[u] = pos[3 * j];
+                cy[u] = pos[3 * j + 1];
+                cz[u] = pos[3 * j + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k0 + u >= n) break;
+                const double dx = min_image(cx[u] - xi, fi.L[0], fi.Linv[0]);
+                const double dy = min_image(cy[u] - yi, fi.L[1], fi.Linv[1]);
+                const double dz = min_image(cz[u] - zi, fi.L[2], fi.Linv[2]);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= rc2r) continue;
+                if (r2 < 1e-8) overlap = true;
+                const int js = slot_of[fi.atom_begin + jl[u]];
+                const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(js));
+                if (r2 < rc2a)
+                    sa.push(ent, ga, capA);
+                else
+                    sr.push(ent, gr, capR);
             }
         }
         sa.flush(ga, capA);
@@ -387,6 +493,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         atomicOr(&flags[kFlagError], kErrOverlap);
         atomicMin(&flags[kFlagBadAtom], a);
     }
+    return;
 }
 
 __global__ void k_count_pairs(const NeighborLists nl, unsigned long long* __restrict__ counters) {
@@ -425,7 +532,8 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
-                            const NeighborLists& nl, int32_t* d_flags, int neigh_block, hipStream_t s) {
+                            const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
+                            int32_t* d_flags, int neigh_block, hipStream_t s) {
     if (cap_atoms == 0 || cap_frames == 0) return hipSuccess;
     const int nb = (neigh_block == 64 || neigh_block == 128) ? neigh_block : kBlock;
     const int T = nl.T;
@@ -443,9 +551,17 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
     k_scatter<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill,
                                                               w.bucket_atoms, nl.meta);
     k_sort_place<<<blocks_for(cap_buckets, kBlock), kBlock, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
-                                                                   w.perm, pos, w.bucket_pos, nl.meta, T);
-    k_neighbors<<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
-                                                       w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
+                                                                   w.perm, w.slot_of, pos, w.bucket_pos, nl.meta, T);
+    k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+                                                              w.key_of, w.bucket_start, w.bucket_pos, rc_radial,
+                                                              rc_angular, nl, cl, d_flags);
+    if (references)
+        k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+                                                                 w.key_of, w.bucket_start, w.bucket_pos, rc_radial,
+                                                                 rc_angular, nl, cl, d_flags);
+    if (followers)
+        k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+                                                                  rc_radial, rc_angular, nl, cl, d_flags);
     return hipGetLastError();
 }
 

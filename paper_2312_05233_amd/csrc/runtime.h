@@ -52,6 +52,10 @@ struct Ctx {
     int64_t max_batch_atoms = 1 << 20;
     int cap_ang[8] = {16, 16, 16, 16, 16, 16, 16, 16};  // learned per-species neighbour capacities
     int cap_rad[8] = {32, 32, 32, 32, 32, 32, 32, 32};  // (grow-only, multiples of 4)
+    int cap_cand = 64;                                   // trajectory candidates per atom and species
+    int traj_window = 0;                                 // TNEP_OPT_TRAJECTORY_WINDOW (0 = off)
+    double skin = 1.0;                                   // TNEP_OPT_SKIN_MA / 1000, Angstrom
+    uint64_t reuse_fallbacks = 0;                        // calls redone with plain searches
     int32_t* h_flags = nullptr;       // pinned
 
     // work buffers
@@ -59,11 +63,12 @@ struct Ctx {
     DevBuf perm, tile_base, scan_chunks, nbr, counts, per_atom, out, pos, species;
     DevBuf spec_work, spec_series, spec_out;
     DevBuf pes_rec, pes_stage;  // potential-energy models: per-atom records, host-bound staging
+    DevBuf slot_of, cand, cand_count;  // tile slot per atom; trajectory candidate lists
 
     std::vector<DevBuf*> all_buffers() {
         return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
-                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage};
+                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &slot_of, &cand, &cand_count};
     }
 
     Server* server = nullptr;

@@ -85,6 +85,8 @@ Ctx* slot_ctx_new(Ctx* parent, uint64_t budget) {
     c->launch = parent->launch;
     c->max_batch_atoms = parent->max_batch_atoms;
     c->use_graphs = parent->use_graphs;
+    c->traj_window = parent->traj_window;
+    c->skin = parent->skin;
     for (int t = 0; t < 8; ++t) {
         c->cap_ang[t] = parent->cap_ang[t];
         c->cap_rad[t] = parent->cap_rad[t];

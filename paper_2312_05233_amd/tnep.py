@@ -26,6 +26,7 @@ MLP_FP32_VALU, MLP_FP32_MFMA, MLP_BF16_MFMA, MLP_BF16X3_MFMA = 0, 1, 2, 3
 OPT_MLP, OPT_ATOMS_PER_BLOCK, OPT_AUTOTUNE, OPT_DETERMINISTIC, OPT_MAX_BATCH_ATOMS, OPT_TIMING = 1, 2, 3, 4, 5, 6
 OPT_NEIGH_BLOCK = 7
 OPT_GRAPHS = 8
+OPT_TRAJECTORY_WINDOW, OPT_SKIN_MA = 9, 10
 KERNEL_NEIGHBORS, KERNEL_EVAL_DIPOLE, KERNEL_EVAL_POLARIZABILITY, KERNEL_FRAME_REDUCE, KERNEL_SPECTRUM = 0, 1, 2, 3, 4
 KERNEL_EVAL_PES, KERNEL_PES_FORCES = 5, 6
 IR, RAMAN_ISO, RAMAN_ANISO, RAMAN_PROJ, RAMAN_MAP = 0, 1, 2, 3, 4
@@ -38,7 +39,8 @@ EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_
             "tnep_server_stop", "tnep_server_stats", "tnep_ctx_kernel_time", "tnep_ctx_pair_counts",
             "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts", "tnep_eval_pes",
             "tnep_raman_map", "tnep_acf_stream_create", "tnep_acf_stream_push", "tnep_acf_stream_end_run",
-            "tnep_acf_stream_spectrum", "tnep_acf_stream_raman_map", "tnep_acf_stream_free"]
+            "tnep_acf_stream_spectrum", "tnep_acf_stream_raman_map", "tnep_acf_stream_free",
+            "tnep_ctx_reuse_fallbacks"]
 
 
 class TnepError(RuntimeError):
@@ -119,6 +121,7 @@ def _load():
     lib.tnep_ctx_pair_counts.argtypes = [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
     lib.tnep_ctx_reset_timing.argtypes = [vp]
     lib.tnep_ctx_graph_counts.argtypes = [vp, P(C.c_uint64), P(C.c_uint64)]
+    lib.tnep_ctx_reuse_fallbacks.argtypes = [vp, P(C.c_uint64)]
     lib.tnep_autotune_report.argtypes = [vp]
     lib.tnep_autotune_report.restype = C.c_char_p
     for name in EXPORTED:
@@ -181,6 +184,12 @@ class Context:
         n, k = C.c_uint64(), C.c_uint64()
         self.check(lib.tnep_ctx_graph_counts(self.h, C.byref(n), C.byref(k)))
         return n.value, k.value
+
+    def reuse_fallbacks(self):
+        """Calls redone with plain neighbour searches (trajectory guard failed)."""
+        n = C.c_uint64()
+        self.check(lib.tnep_ctx_reuse_fallbacks(self.h, C.byref(n)))
+        return n.value
 
     def reset_timing(self):
         self.check(lib.tnep_ctx_reset_timing(self.h))
