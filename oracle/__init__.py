@@ -268,6 +268,25 @@ def eval_frames(m, frames, per_atom=False):
     return (out, pa) if per_atom else out
 
 
+def dipole_charged(m, frames, charges, species_masses, length_unit=1.0):
+    """Dipole of charged molecules (Sec. 3, charged molecules): the model gives
+    mu_r, the permanent dipole relative to the centre of mass, and the absolute
+    dipole is mu = mu_r + Q e r_COM, r_COM = sum_i m_i r_i / sum_i m_i, with Q the
+    frame's net charge in units of e and length_unit the model's dipole units
+    per (e * Angstrom).  Frames without atoms get no shift.  [F, 3], FP64."""
+    mu = eval_frames(m, frames)
+    masses = np.asarray(species_masses, np.float64)
+    out = mu.copy()
+    for f in range(frames.n_frames):
+        a0, a1 = frames.offsets[f], frames.offsets[f + 1]
+        if a1 == a0:
+            continue
+        w = masses[frames.species[a0:a1]]
+        com = (w[:, None] * frames.positions[a0:a1]).sum(0) / w.sum()
+        out[f] += float(charges[f]) * length_unit * com
+    return out
+
+
 def eval_pes(m, frames, per_atom=False):
     """Potential-energy surface model (kind 3, Sec. 2.1): per frame the energy
     U = sum_i U_i [F], the virial W = -sum_i sum_j r_ij (x) dU_i/dr_ij [F,3,3]
