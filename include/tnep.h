@@ -221,6 +221,19 @@ int tnep_eval_dipole_polarizability(tnep_ctx* ctx, const tnep_model* dipole_mode
                                     const tnep_model* polarizability_model, const tnep_frames* frames,
                                     double* mu_out, double* alpha_out);
 
+/* Dipole of charged molecules (Sec. 3, charged molecules): a model trained on
+ * mu_r, the permanent dipole relative to the centre of mass, gives the
+ * absolute dipole mu = mu_r + Q e r_COM, r_COM = sum_i m_i r_i / sum_i m_i.
+ *   charges [n_frames]: net charge of each frame in units of e (location of
+ *     the frames); species_masses [n_species]: host; length_unit: the model's
+ *     dipole unit per (e * Angstrom), e.g. 1/0.529177210903 for e*bohr;
+ *   mu_out, per_atom as for tnep_eval_dipole (per_atom holds the mu_r terms).
+ * A charged frame with a periodic axis is TNEP_E_BOX (its centre of mass is
+ * not defined); frames without atoms get no shift. */
+int tnep_eval_dipole_charged(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames,
+                             const double* charges, const double* species_masses, double length_unit,
+                             double* mu_out, double* per_atom);
+
 /* Potential-energy surface of every frame (Sec. 2.1) with a TNEP_KIND_PES
  * model, whose one head gives the site energies U_i:
  *   energy  [n_frames]        U = sum_i U_i (Eq. site-energy), FP64;

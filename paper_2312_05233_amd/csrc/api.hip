@@ -540,6 +540,72 @@ extern "C" int tnep_eval_dipole_polarizability(tnep_ctx* ctx, const tnep_model* 
     return run_eval(c, *frames, job);
 }
 
+extern "C" int tnep_eval_dipole_charged(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames,
+                                        const double* charges, const double* species_masses, double length_unit,
+                                        double* mu_out, double* per_atom) {
+    if (!ctx) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    const Model* m = reinterpret_cast<const Model*>(model);
+    if (!m || m->kind != TNEP_KIND_DIPOLE) return c->fail(TNEP_E_INVALID, "a dipole model is required");
+    int e = check_frames(c, frames);
+    if (e) return e;
+    const int F = frames->n_frames;
+    if (F > 0 && (!charges || !species_masses || !mu_out)) return c->fail(TNEP_E_INVALID, "NULL argument");
+    if (!(length_unit > 0) || !std::isfinite(length_unit)) return c->fail(TNEP_E_INVALID, "length_unit must be > 0");
+    for (int t = 0; t < m->T && F > 0; ++t)
+        if (!(species_masses[t] > 0) || !std::isfinite(species_masses[t]))
+            return c->fail(TNEP_E_INVALID, "species mass %d must be positive", t);
+    if (F == 0) return TNEP_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipGetLastError();
+    // host copies of the charges, periodic flags and offsets
+    std::vector<double> q(F);
+    std::vector<uint8_t> pbc(frames->pbc ? 3 * (size_t)F : 0);
+    std::vector<int64_t> offs(F + 1);
+    const hipMemcpyKind to_host = frames->location == TNEP_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+    HIP_TRY(c, hipMemcpy(q.data(), charges, sizeof(double) * F, to_host));
+    HIP_TRY(c, hipMemcpy(offs.data(), frames->atom_offsets, sizeof(int64_t) * (F + 1), to_host));
+    if (frames->pbc) HIP_TRY(c, hipMemcpy(pbc.data(), frames->pbc, 3 * (size_t)F, to_host));
+    for (int f = 0; f < F; ++f) {
+        if (!std::isfinite(q[f])) return c->fail(TNEP_E_INVALID, "frame %d: non-finite charge", f);
+        const bool periodic = !pbc.empty() && (pbc[3 * f] || pbc[3 * f + 1] || pbc[3 * f + 2]);
+        if (q[f] != 0.0 && periodic)
+            return c->fail(TNEP_E_BOX, "frame %d: charged frame with periodic axes (no centre of mass)", f);
+    }
+    if ((e = tnep_eval_dipole(ctx, model, frames, mu_out, per_atom))) return e;
+    const int64_t A = offs[F];
+    const int T = m->T;
+    // device layout: masses [T], then for host frames: charges [F], mu [F][3], offsets, positions, species
+    size_t bytes = sizeof(double) * T + 256;
+    if (frames->location == TNEP_HOST)
+        bytes += sizeof(double) * 4 * (size_t)F + sizeof(int64_t) * (F + 1) + sizeof(double) * 3 * A +
+                 sizeof(int32_t) * A + 1024;
+    if ((e = c->reserve(c->com, bytes))) return e;
+    char* base = (char*)c->com.p;
+    double* d_masses = (double*)base;
+    HIP_TRY(c, hipMemcpyAsync(d_masses, species_masses, sizeof(double) * T, hipMemcpyHostToDevice, c->stream));
+    if (frames->location == TNEP_DEVICE) {
+        HIP_TRY(c, launch_com_shift(frames->atom_offsets, F, frames->positions, frames->species, d_masses, charges,
+                                    length_unit, mu_out, c->stream));
+    } else {
+        const size_t o = (sizeof(double) * T + 255) & ~(size_t)255;
+        double* d_q = (double*)(base + o);
+        double* d_mu = d_q + F;
+        int64_t* d_offs = (int64_t*)(d_mu + 3 * (size_t)F);
+        double* d_pos = (double*)(d_offs + F + 1);
+        int32_t* d_spc = (int32_t*)(d_pos + 3 * (size_t)A);
+        HIP_TRY(c, hipMemcpyAsync(d_q, q.data(), sizeof(double) * F, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(d_mu, mu_out, sizeof(double) * 3 * F, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(d_offs, offs.data(), sizeof(int64_t) * (F + 1), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(d_pos, frames->positions, sizeof(double) * 3 * A, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(d_spc, frames->species, sizeof(int32_t) * A, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, launch_com_shift(d_offs, F, d_pos, d_spc, d_masses, d_q, length_unit, d_mu, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(mu_out, d_mu, sizeof(double) * 3 * F, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TNEP_OK;
+}
+
 extern "C" int tnep_eval_pes(tnep_ctx* ctx, const tnep_model* model, const tnep_frames* frames, double* energy,
                              double* virial, double* forces, double* per_atom_energy) {
     if (!ctx) return TNEP_E_INVALID;

@@ -176,6 +176,11 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
 hipError_t launch_pes_forces(const Shape& shape, const DevModel& m, const NeighborLists& nl, const PesOut& pes,
                              const double* per_atom, double* forces, double* energies, int block, hipStream_t s);
 
+// Charged molecules: mu[f] += charges[f] * unit * (mass-weighted mean of the
+// frame's positions); frames without atoms unchanged.  All device pointers.
+hipError_t launch_com_shift(const int64_t* offsets, int n_frames, const double* pos, const int32_t* species,
+                            const double* masses, const double* charges, double unit, double* mu, hipStream_t s);
+
 // Add the batch's atom count and neighbour-pair counts to counters[0..2].
 hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* counters, hipStream_t s);
 

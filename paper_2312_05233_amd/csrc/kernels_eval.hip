@@ -591,6 +591,40 @@ __global__ void __launch_bounds__(256) k_frame_reduce(const FrameInfo* __restric
         out_b[(int64_t)f * (nt - na) + lane - na] = part[lane][0];
 }
 
+// Charged molecules (the dipole of a charged system depends on the reference
+// point; the model gives it relative to the centre of mass):
+//   mu[f] += Q_f * unit * sum_i m_i r_i / sum_i m_i,
+// one work-group per frame, FP64 sums in a fixed order.
+__global__ void __launch_bounds__(256) k_com_shift(const int64_t* __restrict__ offsets,
+                                                   const double* __restrict__ pos,
+                                                   const int32_t* __restrict__ species,
+                                                   const double* __restrict__ masses,
+                                                   const double* __restrict__ charges, double unit,
+                                                   double* __restrict__ mu) {
+    __shared__ double part[4][256];
+    const int f = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t a0 = offsets[f], a1 = offsets[f + 1];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t a = a0 + lane; a < a1; a += 256) {
+        const double w = masses[species[a]];
+        s[0] += w * pos[3 * a];
+        s[1] += w * pos[3 * a + 1];
+        s[2] += w * pos[3 * a + 2];
+        s[3] += w;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) part[k][lane] = s[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (lane < off)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) part[k][lane] += part[k][lane + off];
+        __syncthreads();
+    }
+    if (lane < 3 && part[3][0] > 0.0) mu[3 * (int64_t)f + lane] += charges[f] * unit * part[lane][0] / part[3][0];
+}
+
 // Forces of a potential-energy model (Sec. 2.1): with r_ij = r_j - r_i,
 //   F_k = -dU/dr_k = sum_j dU_k/dr_kj - sum_j dU_j/dr_jk.
 // The first sum is in the atom's record (evaluation kernel).  For the second,
@@ -808,6 +842,13 @@ hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const 
                                int nt, int na, double* out_a, double* out_b, hipStream_t s) {
     if (cap_frames == 0) return hipSuccess;
     k_frame_reduce<<<cap_frames, 256, 0, s>>>(d_frames, meta, per_atom, nt, na, out_a, out_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_com_shift(const int64_t* offsets, int n_frames, const double* pos, const int32_t* species,
+                            const double* masses, const double* charges, double unit, double* mu, hipStream_t s) {
+    if (n_frames == 0) return hipSuccess;
+    k_com_shift<<<n_frames, 256, 0, s>>>(offsets, pos, species, masses, charges, unit, mu);
     return hipGetLastError();
 }
 

@@ -64,11 +64,12 @@ struct Ctx {
     DevBuf spec_work, spec_series, spec_out;
     DevBuf pes_rec, pes_stage;  // potential-energy models: per-atom records, host-bound staging
     DevBuf slot_of, cand, cand_count;  // tile slot per atom; trajectory candidate lists
+    DevBuf com;                        // charged-dipole shift: staging of frames, masses, charges, mu
 
     std::vector<DevBuf*> all_buffers() {
         return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
-                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &slot_of, &cand, &cand_count};
+                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &slot_of, &cand, &cand_count, &com};
     }
 
     Server* server = nullptr;

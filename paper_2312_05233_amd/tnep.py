@@ -40,7 +40,7 @@ EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_
             "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts", "tnep_eval_pes",
             "tnep_raman_map", "tnep_acf_stream_create", "tnep_acf_stream_push", "tnep_acf_stream_end_run",
             "tnep_acf_stream_spectrum", "tnep_acf_stream_raman_map", "tnep_acf_stream_free",
-            "tnep_ctx_reuse_fallbacks"]
+            "tnep_ctx_reuse_fallbacks", "tnep_eval_dipole_charged"]
 
 
 class TnepError(RuntimeError):
@@ -103,6 +103,7 @@ def _load():
     lib.tnep_eval_polarizability.argtypes = [vp, vp, P(FramesDesc), vp, vp]
     lib.tnep_eval_dipole_polarizability.argtypes = [vp, vp, vp, P(FramesDesc), vp, vp]
     lib.tnep_eval_pes.argtypes = [vp, vp, P(FramesDesc), vp, vp, vp, vp]
+    lib.tnep_eval_dipole_charged.argtypes = [vp, vp, P(FramesDesc), vp, vp, C.c_double, vp, vp]
     lib.tnep_raman_map.argtypes = [vp, P(SpectrumArgs), C.c_int32, vp, vp, vp, vp]
     lib.tnep_acf_stream_create.argtypes = [vp, C.c_int32, C.c_int64, C.c_int32, vp, vp, P(vp)]
     lib.tnep_acf_stream_push.argtypes = [vp, vp, C.c_int64, C.c_int32]
@@ -315,6 +316,21 @@ def tnep_eval_dipole_polarizability(ctx: Context, dipole_model: Model, pol_model
     ctx.check(lib.tnep_eval_dipole_polarizability(ctx.h, dipole_model.h, pol_model.h, C.byref(fd), _ptr(mu_out),
                                                   _ptr(alpha_out)))
     return mu_out, alpha_out
+
+
+def tnep_eval_dipole_charged(ctx: Context, model: Model, frames, charges, species_masses, length_unit=1.0,
+                             mu_out=None, per_atom=None):
+    """mu = mu_r + Q e r_COM: charges [F] (numpy for host frames, device tensor
+    for device frames), species_masses [n_species] host."""
+    fd = frames_desc(frames)
+    F = fd.n_frames
+    if fd.location == HOST:
+        mu_out = np.zeros((F, 3)) if mu_out is None else mu_out
+        charges = np.ascontiguousarray(charges, np.float64)
+    masses = np.ascontiguousarray(species_masses, np.float64)
+    ctx.check(lib.tnep_eval_dipole_charged(ctx.h, model.h, C.byref(fd), _ptr(charges), _ptr(masses),
+                                           float(length_unit), _ptr(mu_out), _ptr(per_atom)))
+    return mu_out
 
 
 def tnep_eval_pes(ctx: Context, model: Model, frames, energy=None, virial=None, forces=None, per_atom_energy=None,
