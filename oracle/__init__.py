@@ -61,6 +61,7 @@ class _Model(C.Structure):
         ("q_scaler", C.POINTER(C.c_double)),
         ("w0", C.POINTER(C.c_double) * 2), ("b0", C.POINTER(C.c_double) * 2),
         ("w1", C.POINTER(C.c_double) * 2), ("b1", C.c_double * 2),
+        ("per_species", C.c_int32), ("b1_species", C.POINTER(C.c_double) * 2),
     ]
 
 
@@ -135,7 +136,11 @@ class OracleModel:
             s.w0[h] = arr(head.w0)
             s.b0[h] = arr(head.b0)
             s.w1[h] = arr(head.w1)
-            s.b1[h] = head.b1
+            if getattr(m, "per_species", False):
+                s.b1_species[h] = arr(head.b1)
+            else:
+                s.b1[h] = head.b1
+        s.per_species = int(bool(getattr(m, "per_species", False)))
         self.s = s
 
 

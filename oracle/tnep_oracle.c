@@ -66,6 +66,9 @@ typedef struct {
     const double* b0[2];      /* [H] */
     const double* w1[2];      /* [H] */
     double b1[2];
+    int32_t per_species;         /* 1: one network per centre species: w0 [T][H][D], b0 and
+                                    w1 [T][H], output biases b1_species[head] [T] */
+    const double* b1_species[2];
 } or_model;
 
 /* ------------------------------------------------------------------------ */
@@ -412,12 +415,13 @@ int or_atom_eval(const or_model* mdl, int head, int ti, int n, const double* vec
     }
     if (q_out) memcpy(q_out, q, sizeof(double) * D);
 
-    /* network */
-    const double* W0 = mdl->w0[head];
-    const double* b0 = mdl->b0[head];
-    const double* w1 = mdl->w1[head];
+    /* network (the centre species' own network when per_species is set) */
+    const size_t sp = mdl->per_species ? (size_t)ti : 0;
+    const double* W0 = mdl->w0[head] + sp * H * D;
+    const double* b0 = mdl->b0[head] + sp * H;
+    const double* w1 = mdl->w1[head] + sp * H;
     double h[OR_HMAX];
-    double U = -mdl->b1[head];
+    double U = -(mdl->per_species ? mdl->b1_species[head][ti] : mdl->b1[head]);
     for (int mu = 0; mu < H; ++mu) {
         double x = -b0[mu];
         for (int nu = 0; nu < D; ++nu) x += W0[mu * D + nu] * mdl->q_scaler[nu] * q[nu];

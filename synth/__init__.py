@@ -220,10 +220,10 @@ def molecule_frames(n_frames: int, seed: int, n_min: int = 20, n_max: int = 80) 
 
 @dataclasses.dataclass
 class Head:
-    w0: np.ndarray  # [H, D]
-    b0: np.ndarray  # [H]
-    w1: np.ndarray  # [H]
-    b1: float
+    w0: np.ndarray  # [H, D]  ([T, H, D] for per-species networks)
+    b0: np.ndarray  # [H]     ([T, H])
+    w1: np.ndarray  # [H]     ([T, H])
+    b1: float       # scalar  ([T] array)
 
 
 @dataclasses.dataclass
@@ -247,6 +247,7 @@ class Model:
     c_angular: np.ndarray  # [T, T, n_A+1, K_A+1]
     q_scaler: np.ndarray  # [D]
     heads: List[Head]
+    per_species: bool = False  # one network per centre species
 
     @property
     def n_species(self) -> int:
@@ -266,7 +267,9 @@ class Model:
             "basis_angular": self.basis_angular, "l_max": self.l_max, "four_body": bool(self.four_body),
             "n_hidden": self.n_hidden, "c_radial": self.c_radial.tolist(), "c_angular": self.c_angular.tolist(),
             "q_scaler": self.q_scaler.tolist(),
-            "heads": [{"w0": h.w0.tolist(), "b0": h.b0.tolist(), "w1": h.w1.tolist(), "b1": h.b1} for h in self.heads],
+            "heads": [{"w0": np.asarray(h.w0).tolist(), "b0": np.asarray(h.b0).tolist(),
+                       "w1": np.asarray(h.w1).tolist(), "b1": np.asarray(h.b1).tolist()} for h in self.heads],
+            "per_species": bool(self.per_species),
         }
 
     @staticmethod
@@ -277,7 +280,8 @@ class Model:
             d["n_hidden"], np.array(d["c_radial"], np.float64), np.array(d["c_angular"], np.float64),
             np.array(d["q_scaler"], np.float64),
             [Head(np.array(h["w0"], np.float64), np.array(h["b0"], np.float64), np.array(h["w1"], np.float64),
-                  float(h["b1"])) for h in d["heads"]],
+                  np.array(h["b1"], np.float64) if d.get("per_species") else float(h["b1"])) for h in d["heads"]],
+            bool(d.get("per_species", False)),
         )
 
 
@@ -309,6 +313,29 @@ PEROVSKITE_DESCRIPTOR = dict(rc_radial=7.0, rc_angular=5.0, n_max_radial=6, n_ma
                              basis_angular=8, l_max=4, four_body=False, n_hidden=50)
 
 # name -> (seed, kind, species, descriptor)
+def per_species_model(networks: List["Model"], species_network: List[int]) -> "Model":
+    """A per-species-network model: the descriptor (coefficients, scaler) of
+    networks[0], and for centre species t the heads of networks[species_network[t]]
+    (all networks of one kind, descriptor shape and width)."""
+    base = networks[species_network[0]]
+    heads = []
+    for h in range(len(base.heads)):
+        src = [networks[species_network[t]].heads[h] for t in range(len(base.species))]
+        heads.append(Head(np.stack([x.w0 for x in src]), np.stack([x.b0 for x in src]),
+                          np.stack([x.w1 for x in src]), np.array([x.b1 for x in src], np.float64)))
+    d = networks[0]
+    return Model(d.kind, d.species, d.rc_radial, d.rc_angular, d.n_max_radial, d.n_max_angular, d.basis_radial,
+                 d.basis_angular, d.l_max, d.four_body, d.n_hidden, d.c_radial, d.c_angular, d.q_scaler, heads,
+                 True)
+
+
+def with_descriptor_of(m: "Model", ref: "Model") -> "Model":
+    """m's network heads on ref's descriptor coefficients and scaler."""
+    return Model(m.kind, ref.species, ref.rc_radial, ref.rc_angular, ref.n_max_radial, ref.n_max_angular,
+                 ref.basis_radial, ref.basis_angular, ref.l_max, ref.four_body, ref.n_hidden, ref.c_radial,
+                 ref.c_angular, ref.q_scaler, m.heads, m.per_species)
+
+
 MODEL_SPECS = {
     "water_dipole_small": (100, KIND_DIPOLE, WATER_SPECIES, WATER_DESCRIPTOR),
     "water_dipole": (101, KIND_DIPOLE, WATER_SPECIES, WATER_DESCRIPTOR),
