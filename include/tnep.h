@@ -140,6 +140,10 @@ typedef struct {
     const double* b0[2];     /* [H]                                                  */
     const double* w1[2];     /* [H]                                                  */
     double b1[2];
+    int32_t per_species;     /* 1: one network per centre species: w0 [T][H][D], b0 and w1
+                                [T][H], output biases b1_species[head] [T] (b1 unused); the
+                                hidden layer then always runs on the FP32 vector ALU      */
+    const double* b1_species[2];
 } tnep_model_desc;
 
 /* ---- frames ------------------------------------------------------------ */

@@ -309,7 +309,11 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
     const int heads = d->kind == TNEP_KIND_POLARIZABILITY ? 2 : 1;
     if (heads == 2 && (!d->w0[1] || !d->b0[1] || !d->w1[1]))
         return c->fail(TNEP_E_MODEL, "polarizability model needs the scalar head");
+    const bool per_species = d->per_species != 0;
+    for (int hd = 0; hd < heads && per_species; ++hd)
+        if (!d->b1_species[hd]) return c->fail(TNEP_E_MODEL, "per-species model needs b1_species");
     const int T = d->n_species, H = d->n_hidden;
+    const size_t NS = per_species ? (size_t)T : 1;  // networks per head
     const int D = sh.nr + 4 * sh.na + (sh.four_body ? sh.na : 0);
     const size_t ncr = (size_t)T * T * sh.nr * sh.kr, nca = (size_t)T * T * sh.na * sh.ka;
 
@@ -326,11 +330,12 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
     size_t o_cr = put(d->c_radial, ncr);
     size_t o_ca = put(d->c_angular, nca);
     size_t o_s = put(d->q_scaler, D);
-    size_t o_w0[2] = {0, 0}, o_b0[2] = {0, 0}, o_w1[2] = {0, 0}, o_w0t[2] = {0, 0};
+    size_t o_w0[2] = {0, 0}, o_b0[2] = {0, 0}, o_w1[2] = {0, 0}, o_w0t[2] = {0, 0}, o_b1s[2] = {0, 0};
     for (int hd = 0; hd < heads; ++hd) {
-        o_w0[hd] = put(d->w0[hd], (size_t)H * D);
-        o_b0[hd] = put(d->b0[hd], H);
-        o_w1[hd] = put(d->w1[hd], H);
+        o_w0[hd] = put(d->w0[hd], NS * H * D);
+        o_b0[hd] = put(d->b0[hd], NS * H);
+        o_w1[hd] = put(d->w1[hd], NS * H);
+        if (per_species) o_b1s[hd] = put(d->b1_species[hd], T);
         std::vector<double> t((size_t)D * H);
         for (int mu = 0; mu < H; ++mu)
             for (int nu = 0; nu < D; ++nu) t[(size_t)nu * H + mu] = d->w0[hd][(size_t)mu * D + nu];
@@ -445,6 +450,7 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
         dm.w1[hd] = base + o_w1[src];
         dm.w0t[hd] = base + o_w0t[src];
         dm.b1[hd] = (float)d->b1[src];
+        dm.b1s[hd] = per_species ? base + o_b1s[src] : nullptr;
         dm.f32_fwd[hd] = base + o_f32_fwd[src];
         dm.bf_fwd_hi[hd] = reinterpret_cast<const uint4*>(base + o_bf_fwd_hi[src]);
         dm.bf_fwd_lo[hd] = reinterpret_cast<const uint4*>(base + o_bf_fwd_lo[src]);
@@ -452,6 +458,8 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
     dm.f32_bwd = base + o_f32_bwd;
     dm.bf_bwd_hi = reinterpret_cast<const uint4*>(base + o_bf_bwd_hi);
     dm.bf_bwd_lo = reinterpret_cast<const uint4*>(base + o_bf_bwd_lo);
+    dm.sp_w0 = per_species ? H * D : 0;
+    dm.sp_h = per_species ? H : 0;
     dm.rc_radial = (float)d->rc_radial;
     dm.rc_angular = (float)d->rc_angular;
     dm.n_species = T;

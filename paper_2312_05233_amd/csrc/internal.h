@@ -52,6 +52,11 @@ struct DevModel {
     const uint4* bf_bwd_hi;
     const uint4* bf_bwd_lo;
     float b1[2];
+    // per-species networks: head h of centre species t at w0[h] + t * sp_w0,
+    // b0[h] / w1[h] + t * sp_h, output bias b1s[h][t]; sp_w0 = sp_h = 0 and
+    // b1s = null for one shared network
+    int32_t sp_w0, sp_h;
+    const float* b1s[2];
     float rc_radial, rc_angular;
     int32_t n_species, n_hidden;
 };

@@ -350,10 +350,10 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     if constexpr (MODE == TNEP_MLP_FP32_VALU) {
         const int H = m.n_hidden;
         if constexpr (KIND == 2) {
-            const float* __restrict__ w0 = m.w0[1];
-            const float* __restrict__ b0 = m.b0[1];
-            const float* __restrict__ w1 = m.w1[1];
-            Us = -m.b1[1];
+            const float* __restrict__ w0 = m.w0[1] + ti * m.sp_w0;
+            const float* __restrict__ b0 = m.b0[1] + ti * m.sp_h;
+            const float* __restrict__ w1 = m.w1[1] + ti * m.sp_h;
+            Us = -(m.b1s[1] ? m.b1s[1][ti] : m.b1[1]);
             for (int mu = 0; mu < H; ++mu) {
                 float x = -b0[mu];
 #pragma unroll
@@ -364,10 +364,10 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 #pragma unroll
         for (int v = 0; v < D; ++v) dq[v] = 0.f;
         {
-            const float* __restrict__ w0 = m.w0[0];
-            const float* __restrict__ b0 = m.b0[0];
-            const float* __restrict__ w1 = m.w1[0];
-            if constexpr (KIND == 3) Us = -m.b1[0];
+            const float* __restrict__ w0 = m.w0[0] + ti * m.sp_w0;
+            const float* __restrict__ b0 = m.b0[0] + ti * m.sp_h;
+            const float* __restrict__ w1 = m.w1[0] + ti * m.sp_h;
+            if constexpr (KIND == 3) Us = -(m.b1s[0] ? m.b1s[0][ti] : m.b1[0]);
             for (int mu = 0; mu < H; ++mu) {
                 float x = -b0[mu];
 #pragma unroll
@@ -827,7 +827,9 @@ bool eval_matrix_supported(const Shape& s, int n_hidden) {
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
                        const PesOut& pes, const EvalLaunch& cfg, hipStream_t s) {
     if (nl.n_pad == 0) return hipSuccess;
-    const bool matrix = cfg.mlp_mode != TNEP_MLP_FP32_VALU && eval_matrix_supported(shape, m.n_hidden);
+    // the matrix-core hidden layer holds one shared network
+    const bool matrix =
+        cfg.mlp_mode != TNEP_MLP_FP32_VALU && eval_matrix_supported(shape, m.n_hidden) && m.sp_w0 == 0;
 #define X(NR_, NA_, KR_, KA_, FB_, MX_)                                                             \
     if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                \
         (bool)shape.four_body == FB_)                                                             \

@@ -59,6 +59,7 @@ class ModelDesc(C.Structure):
         ("basis_angular", C.c_int32), ("l_max", C.c_int32), ("four_body", C.c_int32), ("n_hidden", C.c_int32),
         ("c_radial", P(C.c_double)), ("c_angular", P(C.c_double)), ("q_scaler", P(C.c_double)),
         ("w0", P(C.c_double) * 2), ("b0", P(C.c_double) * 2), ("w1", P(C.c_double) * 2), ("b1", C.c_double * 2),
+        ("per_species", C.c_int32), ("b1_species", P(C.c_double) * 2),
     ]
 
 
@@ -232,9 +233,14 @@ class Model:
         d.basis_radial, d.basis_angular = m.basis_radial, m.basis_angular
         d.l_max, d.four_body, d.n_hidden = m.l_max, int(bool(m.four_body)), m.n_hidden
         d.c_radial, d.c_angular, d.q_scaler = arr(m.c_radial), arr(m.c_angular), arr(m.q_scaler)
+        per_species = bool(getattr(m, "per_species", False))
+        d.per_species = int(per_species)
         for k, head in enumerate(m.heads):
             d.w0[k], d.b0[k], d.w1[k] = arr(head.w0), arr(head.b0), arr(head.w1)
-            d.b1[k] = head.b1
+            if per_species:
+                d.b1_species[k] = arr(head.b1)
+            else:
+                d.b1[k] = head.b1
         h = C.c_void_p()
         ctx.check(lib.tnep_model_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
