@@ -232,6 +232,8 @@ def frame_descriptors(m, frames, f, head=0, forces=False):
     pbc = None if frames.pbc is None else frames.pbc[f]
     nb = neighbors(pos, cell, pbc, m.rc_radial)
     per = np.zeros(3, bool) if pbc is None else np.asarray(pbc, bool)
+    if cell is not None and np.any(np.asarray(cell, np.float64).reshape(3, 3)[~np.eye(3, dtype=bool)] != 0):
+        raise ValueError("frame_descriptors takes orthorhombic cells only (use eval_frames)")
     box = np.zeros(3) if cell is None else np.array([cell[0], cell[4], cell[8]])
     om = _model(m)
     qs, us, frc = [], [], []

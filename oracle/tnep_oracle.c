@@ -486,36 +486,90 @@ int or_atom_eval(const or_model* mdl, int head, int ti, int n, const double* vec
 /* ------------------------------------------------------------------------ */
 /* Neighbour search (brute force, minimum image).                           */
 
-/* Frame geometry check. cell: 9 doubles, row-major lattice vectors, or NULL.
- * Only orthorhombic cells are accepted. L[d] receives the box lengths. */
-static int frame_box(const double* cell, const uint8_t* pbc, double rc, double L[3], int per[3]) {
-    for (int d = 0; d < 3; ++d) {
-        per[d] = pbc ? (pbc[d] != 0) : 0;
-        L[d] = 0.0;
-    }
+/* Simulation box of one frame: periodic flags, and either the orthorhombic
+ * edges L or (triclinic) the lattice vectors as the rows of H with the inverse
+ * Hinv (Cramer's rule). */
+typedef struct {
+    int per[3];
+    int tric;
+    double L[3];
+    double H[9], Hinv[9];
+} or_box;
+
+static int frame_box(const double* cell, const uint8_t* pbc, double rc, or_box* b) {
+    memset(b, 0, sizeof(*b));
+    for (int d = 0; d < 3; ++d) b->per[d] = pbc ? (pbc[d] != 0) : 0;
     if (!pbc) return OR_OK;
     if (!cell) {
         for (int d = 0; d < 3; ++d)
-            if (per[d]) return OR_E_BOX;
+            if (b->per[d]) return OR_E_BOX;
         return OR_OK;
     }
+    int skew = 0;
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-            if (a != b && cell[3 * a + b] != 0.0 && (per[a] || per[b])) return OR_E_BOX;
-    for (int d = 0; d < 3; ++d) {
-        L[d] = cell[4 * d];
-        if (per[d] && !(L[d] >= 2.0 * rc)) return OR_E_BOX;
+        for (int c = 0; c < 3; ++c)
+            if (a != c && cell[3 * a + c] != 0.0 && (b->per[a] || b->per[c])) skew = 1;
+    if (!skew) {
+        for (int d = 0; d < 3; ++d) {
+            b->L[d] = cell[4 * d];
+            if (b->per[d] && !(b->L[d] >= 2.0 * rc)) return OR_E_BOX;
+        }
+        return OR_OK;
+    }
+    /* triclinic: all axes periodic, every face-to-face width >= 2 rc */
+    if (!(b->per[0] && b->per[1] && b->per[2])) return OR_E_BOX;
+    b->tric = 1;
+    memcpy(b->H, cell, sizeof(b->H));
+    const double* h = cell;
+    double cof[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            cof[3 * i + j] = h[3 * i1 + j1] * h[3 * i2 + j2] - h[3 * i1 + j2] * h[3 * i2 + j1];
+        }
+    const double det = h[0] * cof[0] + h[1] * cof[1] + h[2] * cof[2];
+    if (!(fabs(det) > 0.0)) return OR_E_BOX;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) b->Hinv[3 * i + j] = cof[3 * j + i] / det;
+    for (int k = 0; k < 3; ++k) {
+        /* width along k: |det| / |h_{k+1} x h_{k+2}| = |det| / |cofactor row k| */
+        const double n = sqrt(cof[3 * k] * cof[3 * k] + cof[3 * k + 1] * cof[3 * k + 1] + cof[3 * k + 2] * cof[3 * k + 2]);
+        if (!(fabs(det) / n >= 2.0 * rc)) return OR_E_BOX;
     }
     return OR_OK;
 }
 
-static void pair_vector(const double* pi, const double* pj, const double L[3], const int per[3],
-                        double v[3]) {
-    for (int d = 0; d < 3; ++d) {
-        double x = pj[d] - pi[d];
-        if (per[d]) x -= L[d] * nearbyint(x / L[d]);
-        v[d] = x;
+/* r_j - r_i under the minimum-image convention.  Triclinic: the difference is
+ * first brought into the unit cell in fractional coordinates s = d Hinv, then
+ * the shortest of the images s + n, n in {-2..1}^3, is taken. */
+static void pair_vector(const double* pi, const double* pj, const or_box* b, double v[3]) {
+    if (!b->tric) {
+        for (int d = 0; d < 3; ++d) {
+            double x = pj[d] - pi[d];
+            if (b->per[d]) x -= b->L[d] * nearbyint(x / b->L[d]);
+            v[d] = x;
+        }
+        return;
     }
+    double d0[3], f[3];
+    for (int d = 0; d < 3; ++d) d0[d] = pj[d] - pi[d];
+    for (int k = 0; k < 3; ++k) {
+        f[k] = d0[0] * b->Hinv[k] + d0[1] * b->Hinv[3 + k] + d0[2] * b->Hinv[6 + k];
+        f[k] -= floor(f[k]);
+    }
+    double best = INFINITY;
+    for (int n0 = -2; n0 <= 1; ++n0)
+        for (int n1 = -2; n1 <= 1; ++n1)
+            for (int n2 = -2; n2 <= 1; ++n2) {
+                const double g[3] = {f[0] + n0, f[1] + n1, f[2] + n2};
+                double w[3];
+                for (int d = 0; d < 3; ++d) w[d] = g[0] * b->H[d] + g[1] * b->H[3 + d] + g[2] * b->H[6 + d];
+                const double r2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+                if (r2 < best) {
+                    best = r2;
+                    memcpy(v, w, sizeof(w));
+                }
+            }
 }
 
 /* For each atom i (0..n-1) write the neighbours j != i with |r_ij| < rc into
@@ -523,9 +577,8 @@ static void pair_vector(const double* pi, const double* pj, const double L[3], c
  * Returns OR_E_CAP if any atom has more than cap neighbours. */
 int or_neighbors(int n, const double* pos, const double* cell, const uint8_t* pbc, double rc,
                  int cap, int32_t* count, int32_t* list) {
-    double L[3];
-    int per[3];
-    int e = frame_box(cell, pbc, rc, L, per);
+    or_box box;
+    int e = frame_box(cell, pbc, rc, &box);
     if (e) return e;
     int overflow = 0;
     for (int i = 0; i < n; ++i) {
@@ -533,7 +586,7 @@ int or_neighbors(int n, const double* pos, const double* cell, const uint8_t* pb
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
             double v[3];
-            pair_vector(pos + 3 * i, pos + 3 * j, L, per, v);
+            pair_vector(pos + 3 * i, pos + 3 * j, &box, v);
             double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
             if (r2 < rc * rc) {
                 if (c < cap) list[(size_t)i * cap + c] = j;
@@ -550,7 +603,7 @@ int or_neighbors(int n, const double* pos, const double* cell, const uint8_t* pb
 /* Whole frames: mu (kind 1, 3 values) or alpha (kind 2, 9 values).          */
 
 static int eval_atom_tensor(const or_model* mdl, int n_at, const double* pos, const int32_t* spc,
-                            const double L[3], const int per[3], int i, double* t_out) {
+                            const or_box* box, int i, double* t_out) {
     /* gather neighbours within rc_radial */
     const double rc = mdl->rc_radial;
     int cap = 64, n = 0;
@@ -559,7 +612,7 @@ static int eval_atom_tensor(const or_model* mdl, int n_at, const double* pos, co
     for (int j = 0; j < n_at; ++j) {
         if (j == i) continue;
         double v[3];
-        pair_vector(pos + 3 * i, pos + 3 * j, L, per, v);
+        pair_vector(pos + 3 * i, pos + 3 * j, box, v);
         if (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] < rc * rc) {
             if (n == cap) {
                 cap *= 2;
@@ -611,9 +664,8 @@ int or_eval_frames(const or_model* mdl, int n_frames, const int64_t* atom_offset
     for (int f = 0; f < n_frames; ++f) {
         const int64_t a0 = atom_offsets[f], a1 = atom_offsets[f + 1];
         const int n_at = (int)(a1 - a0);
-        double L[3];
-        int per[3];
-        int e = frame_box(cells ? cells + 9 * f : NULL, pbc ? pbc + 3 * f : NULL, mdl->rc_radial, L, per);
+        or_box box;
+        int e = frame_box(cells ? cells + 9 * f : NULL, pbc ? pbc + 3 * f : NULL, mdl->rc_radial, &box);
         if (e) return e;
         for (int64_t a = a0; a < a1; ++a)
             for (int d = 0; d < 3; ++d)
@@ -622,7 +674,7 @@ int or_eval_frames(const or_model* mdl, int n_frames, const int64_t* atom_offset
         int err = 0;
 #pragma omp parallel for schedule(dynamic, 16)
         for (int i = 0; i < n_at; ++i) {
-            int ei = eval_atom_tensor(mdl, n_at, pos + 3 * a0, species + a0, L, per, i, tens + nt * i);
+            int ei = eval_atom_tensor(mdl, n_at, pos + 3 * a0, species + a0, &box, i, tens + nt * i);
             if (ei) {
 #pragma omp critical
                 err = ei;
@@ -664,9 +716,8 @@ int or_eval_pes(const or_model* mdl, int n_frames, const int64_t* atom_offsets, 
     for (int f = 0; f < n_frames; ++f) {
         const int64_t a0 = atom_offsets[f], a1 = atom_offsets[f + 1];
         const int n_at = (int)(a1 - a0);
-        double L[3];
-        int per[3];
-        int e = frame_box(cells ? cells + 9 * f : NULL, pbc ? pbc + 3 * f : NULL, mdl->rc_radial, L, per);
+        or_box box;
+        int e = frame_box(cells ? cells + 9 * f : NULL, pbc ? pbc + 3 * f : NULL, mdl->rc_radial, &box);
         if (e) return e;
         for (int64_t a = a0; a < a1; ++a)
             for (int d = 0; d < 3; ++d)
@@ -685,7 +736,7 @@ int or_eval_pes(const or_model* mdl, int n_frames, const int64_t* atom_offsets, 
             for (int j = 0; j < n_at; ++j) {
                 if (j == i) continue;
                 double v[3];
-                pair_vector(p + 3 * i, p + 3 * j, L, per, v);
+                pair_vector(p + 3 * i, p + 3 * j, &box, v);
                 if (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] < rc * rc) ++n;
             }
             double* vec = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
@@ -696,7 +747,7 @@ int or_eval_pes(const or_model* mdl, int n_frames, const int64_t* atom_offsets, 
             for (int j = 0; j < n_at; ++j) {
                 if (j == i) continue;
                 double v[3];
-                pair_vector(p + 3 * i, p + 3 * j, L, per, v);
+                pair_vector(p + 3 * i, p + 3 * j, &box, v);
                 if (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] < rc * rc) {
                     memcpy(vec + 3 * k, v, sizeof(v));
                     tj[k] = spc[j];
