@@ -43,10 +43,40 @@ int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double
     if (!cell) return c->fail(TNEP_E_BOX, "frame %d: periodic axes but no cell", f);
     for (int k = 0; k < 9; ++k)
         if (!std::isfinite(cell[k])) return c->fail(TNEP_E_NONFINITE, "frame %d: non-finite cell", f);
+    bool skew = false;
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-            if (a != b && cell[3 * a + b] != 0.0)
-                return c->fail(TNEP_E_BOX, "frame %d: only orthorhombic cells are supported", f);
+        for (int b = 0; b < 3; ++b) skew = skew || (a != b && cell[3 * a + b] != 0.0);
+    if (skew) {
+        // triclinic: all axes periodic, every face-to-face width >= 2 r_c
+        if (!(g.per[0] && g.per[1] && g.per[2]))
+            return c->fail(TNEP_E_BOX, "frame %d: a skewed cell needs all three axes periodic", f);
+        double cof[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+                cof[3 * i + j] = cell[3 * i1 + j1] * cell[3 * i2 + j2] - cell[3 * i1 + j2] * cell[3 * i2 + j1];
+            }
+        const double det = cell[0] * cof[0] + cell[1] * cof[1] + cell[2] * cof[2];
+        if (!(std::fabs(det) > 0.0)) return c->fail(TNEP_E_BOX, "frame %d: singular cell", f);
+        g.tric = 1;
+        bool ok = true;
+        for (int i = 0; i < 9; ++i) g.H[i] = cell[i];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) g.Hinv[3 * i + j] = cof[3 * j + i] / det;
+        for (int k = 0; k < 3; ++k) {
+            g.w[k] = std::fabs(det) / std::sqrt(cof[3 * k] * cof[3 * k] + cof[3 * k + 1] * cof[3 * k + 1] +
+                                                cof[3 * k + 2] * cof[3 * k + 2]);
+            if (!(g.w[k] >= 2.0 * rc))
+                return c->fail(TNEP_E_BOX, "frame %d: cell width %g shorter than 2 r_c = %g", f, g.w[k], 2.0 * rc);
+            g.nc[k] = (int)std::floor(g.w[k] / rc);
+            if (g.nc[k] > 256) g.nc[k] = 256;
+            ok = ok && g.nc[k] >= 3;
+        }
+        if (ok) g.mode = 1;
+        else
+            for (int k = 0; k < 3; ++k) g.nc[k] = 1;
+        return TNEP_OK;
+    }
     bool all = true;
     for (int d = 0; d < 3; ++d) {
         g.L[d] = cell[4 * d];
@@ -411,7 +441,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 std::vector<FrameInfo>& fi = bh.fi;
                 int n_cells = 0;
                 int64_t n_ref_atoms = 0;
-                bool followers = false;
+                bool followers = false, triclinic = false;
                 int ref_k = -1;  // reference frame of the open window
                 for (int k = 0; k < nf; ++k) {
                     const int f = f0 + k;
@@ -444,7 +474,16 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         x.nc[d] = g.nc[d];
                         x.per[d] = g.per[d];
                         x.L[d] = g.L[d];
-                        x.Linv[d] = g.per[d] ? 1.0 / g.L[d] : 0.0;
+                        x.Linv[d] = (g.per[d] && !g.tric) ? 1.0 / g.L[d] : 0.0;
+                    }
+                    x.tric = g.tric;
+                    if (g.tric) {
+                        triclinic = true;
+                        for (int i = 0; i < 9; ++i) {
+                            x.H[i] = g.H[i];
+                            x.Hinv[i] = g.Hinv[i];
+                        }
+                        for (int k = 0; k < 3; ++k) x.w[k] = g.w[k];
                     }
                     x.cell_base = n_cells;
                     n_cells += g.mode == 1 ? g.n_cells() : 1;
@@ -537,8 +576,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     int tr = c->timer_begin(TNEP_KERNEL_NEIGHBORS);
                     he = launch_neighbors((const FrameInfo*)c->frames.p, cap_frames, pos, spc, cap_atoms,
                                           (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl, cl,
-                                          n_ref_atoms > 0, followers, (int32_t*)c->flags.p, c->launch.neigh_block,
-                                          c->stream);
+                                          n_ref_atoms > 0, followers, triclinic, (int32_t*)c->flags.p,
+                                          c->launch.neigh_block, c->stream);
                     c->timer_end(tr);
                     if (he != hipSuccess) return he;
                     if (c->timing) {
@@ -576,6 +615,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         snprintf(rb, sizeof(rb), "/r%d.%d", c->cap_cand, followers ? 1 : 0);
                         key += rb;
                     }
+                    if (triclinic) key += "/tric";
                     if ((e = replay_graph(c, key, launch_batch)))
                         return e;
                 } else {

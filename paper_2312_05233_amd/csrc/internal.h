@@ -28,6 +28,12 @@ struct FrameInfo {
     double Linv[3];      // 1 / L (periodic axes), else 0
     int64_t ref_begin;   // follower: atom_begin of its reference frame
     int64_t cl_base;     // reference / follower: first candidate list of the reference's atoms
+    // Triclinic cells (all axes periodic): lattice vectors as the rows of H,
+    // fractional coordinates s = r Hinv, cells binned in s, widths w[k] between
+    // opposite faces (>= 2 r_c).  tric = 0: orthorhombic or non-periodic.
+    int32_t tric;
+    int32_t pad_;
+    double H[9], Hinv[9], w[3];
 };
 
 // Device-resident FP32 model parameters.
@@ -140,10 +146,11 @@ struct NeighborWork {
 // references / followers: the batch has frames of role 1 / role 2 (each
 // role has a pass over the slots of its own; followers run after the
 // reference frames' lists are complete).
+// triclinic: the batch has triclinic frames (a pass of their own).
 hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
-                            int32_t* d_flags, int neigh_block, hipStream_t s);
+                            bool triclinic, int32_t* d_flags, int neigh_block, hipStream_t s);
 
 // ---- evaluation (kernels_eval.hip) ----
 struct EvalLaunch {

@@ -67,7 +67,17 @@ __global__ void k_bin(const FrameInfo* __restrict__ frames, const int32_t* __res
         return;
     }
     int c = fi.cell_base;
-    if (fi.mode == 1) {
+    if (fi.mode == 1 && fi.tric) {
+        // triclinic: bins of the wrapped fractional coordinates s = r Hinv
+        int b[3];
+        for (int k = 0; k < 3; ++k) {
+            double sk = x * fi.Hinv[k] + y * fi.Hinv[3 + k] + z * fi.Hinv[6 + k];
+            sk -= floor(sk);
+            const int q = (int)(sk * (double)fi.nc[k]);
+            b[k] = q < 0 ? 0 : (q >= fi.nc[k] ? fi.nc[k] - 1 : q);
+        }
+        c += (b[0] * fi.nc[1] + b[1]) * fi.nc[2] + b[2];
+    } else if (fi.mode == 1) {
         const int ix = cell_coord(x, fi.L[0], fi.nc[0]);
         const int iy = cell_coord(y, fi.L[1], fi.nc[1]);
         const int iz = cell_coord(z, fi.L[2], fi.nc[2]);
@@ -311,8 +321,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         return;
     }
     const FrameInfo fi = frames[frame_of[a]];  // by value: kept in registers across the stores below
-    // followers: k_neighbors_follow, after the reference lists are complete
-    if (fi.role != (REF ? kRoleReference : kRolePlain)) return;
+    // followers: k_neighbors_follow, after the reference lists are complete;
+    // triclinic frames: k_neighbors_tri
+    if (fi.role != (REF ? kRoleReference : kRolePlain) || fi.tric) return;
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
     // references collect candidates out to r_c + skin
@@ -496,6 +507,114 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
     return;
 }
 
+// Triclinic frames: one lane per tile slot.  Pair vectors by the minimum
+// image in fractional coordinates, f = d Hinv, f -= rint(f), d = f H: with
+// every width >= 2 r_c an image within r_c has all |f_k| < 1/2, so rounding
+// finds it.  Cell-list frames visit the 27 neighbouring fractional bins
+// (a neighbour within r_c is at most one bin away per axis since the bin
+// width w_k / nc_k >= r_c); a bin is skipped when the perpendicular distance
+// to it along one axis already reaches r_c (the sum of squares would not be
+// a lower bound on skewed cells).
+__global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __restrict__ frames,
+                                                          const int32_t* __restrict__ frame_of,
+                                                          const double* __restrict__ pos,
+                                                          const int32_t* __restrict__ key_of,
+                                                          const int32_t* __restrict__ bucket_start,
+                                                          const double4* __restrict__ bucket_pos, float rc_radial,
+                                                          float rc_angular, NeighborLists nl,
+                                                          int32_t* __restrict__ flags) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nl.n_pad) return;
+    const int T = nl.T;
+    const int a = nl.perm[p];
+    if (a < 0) return;
+    const int fidx = frame_of[a];
+    if (!frames[fidx].tric) return;
+    const FrameInfo& fi = frames[fidx];
+    const int tile = (int)(p >> 6), lane = (int)(p & 63);
+    const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
+    const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
+    const float prune = rc_radial + 1e-3f;
+    float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
+    const int mode = fi.mode, cell_base = fi.cell_base;
+    const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
+    int ib[3] = {0, 0, 0};
+    float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+    if (mode == 1) {
+        const int local = key_of[a] / T - cell_base;
+        ib[2] = local % nz;
+        ib[1] = (local / nz) % ny;
+        ib[0] = local / (nz * ny);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double sk = xi * fi.Hinv[k] + yi * fi.Hinv[3 + k] + zi * fi.Hinv[6 + k];
+            sk -= floor(sk);
+            const double inv = 1.0 / (double)fi.nc[k];
+            lo[k] = (float)fmax((sk - ib[k] * inv) * fi.w[k], 0.0);
+            hi[k] = (float)fmax(((ib[k] + 1) * inv - sk) * fi.w[k], 0.0);
+        }
+    }
+    bool overlap = false;
+    for (int t = 0; t < T; ++t) {
+        Stream sa, sr;
+        sa.n = 0;
+        sr.n = 0;
+        float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
+        float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
+        const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
+        const int n_visit = mode == 1 ? 27 : 1;
+        for (int vb = 0; vb < n_visit; ++vb) {
+            int bucket = cell_base * T + t;
+            if (mode == 1) {
+                const int o[3] = {vb / 9 - 1, (vb / 3) % 3 - 1, vb % 3 - 1};
+                float g = 0.f;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) g = fmaxf(g, o[k] < 0 ? lo[k] : (o[k] > 0 ? hi[k] : 0.f));
+                if (g >= prune) continue;
+                const int cx = (ib[0] + o[0] + nx) % nx;
+                const int cy = (ib[1] + o[1] + ny) % ny;
+                const int cz = (ib[2] + o[2] + nz) % nz;
+                bucket = (cell_base + (cx * ny + cy) * nz + cz) * T + t;
+            }
+            const int b = bucket_start[bucket], e = bucket_start[bucket + 1];
+            for (int k = b; k < e; ++k) {
+                const double4 cur = bucket_pos[k];
+                const uint64_t wj = (uint64_t)__double_as_longlong(cur.w);
+                const int j = (int)(uint32_t)wj;
+                if (j == (int)p) continue;
+                const double d0[3] = {cur.x - xi, cur.y - yi, cur.z - zi};
+                double f[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    f[q] = d0[0] * fi.Hinv[q] + d0[1] * fi.Hinv[3 + q] + d0[2] * fi.Hinv[6 + q];
+                    f[q] -= rint(f[q]);
+                }
+                const double dx = f[0] * fi.H[0] + f[1] * fi.H[3] + f[2] * fi.H[6];
+                const double dy = f[0] * fi.H[1] + f[1] * fi.H[4] + f[2] * fi.H[7];
+                const double dz = f[0] * fi.H[2] + f[1] * fi.H[5] + f[2] * fi.H[8];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= rc2r) continue;
+                if (r2 < 1e-8) overlap = true;
+                const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
+                if (r2 < rc2a)
+                    sa.push(ent, ga, capA);
+                else
+                    sr.push(ent, gr, capR);
+            }
+        }
+        sa.flush(ga, capA);
+        sr.flush(gr, capR);
+        nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(sa.n, capA);
+        nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(sr.n, capR);
+        if (sa.n > capA) atomicMax(&flags[kFlagCapAng + t], sa.n);
+        if (sr.n > capR) atomicMax(&flags[kFlagCapRad + t], sr.n);
+    }
+    if (overlap) {
+        atomicOr(&flags[kFlagError], kErrOverlap);
+        atomicMin(&flags[kFlagBadAtom], a);
+    }
+}
+
 __global__ void k_count_pairs(const NeighborLists nl, unsigned long long* __restrict__ counters) {
     __shared__ unsigned long long s_ang[kBlock], s_rad[kBlock], s_at[kBlock];
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -533,7 +652,7 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
-                            int32_t* d_flags, int neigh_block, hipStream_t s) {
+                            bool triclinic, int32_t* d_flags, int neigh_block, hipStream_t s) {
     if (cap_atoms == 0 || cap_frames == 0) return hipSuccess;
     const int nb = (neigh_block == 64 || neigh_block == 128) ? neigh_block : kBlock;
     const int T = nl.T;
@@ -559,6 +678,9 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
         k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                  w.key_of, w.bucket_start, w.bucket_pos, rc_radial,
                                                                  rc_angular, nl, cl, d_flags);
+    if (triclinic)
+        k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
+                                                               w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
     if (followers)
         k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                   rc_radial, rc_angular, nl, cl, d_flags);

@@ -141,6 +141,8 @@ struct FrameGeom {
     int nc[3] = {1, 1, 1};
     int per[3] = {0, 0, 0};
     double L[3] = {0, 0, 0};
+    int tric = 0;  // triclinic cell (then L = 0; H, Hinv, w below)
+    double H[9] = {0}, Hinv[9] = {0}, w[3] = {0, 0, 0};
     int n_cells() const { return mode == 1 ? nc[0] * nc[1] * nc[2] : 0; }
 };
 
