@@ -275,6 +275,26 @@ def eval_frames(m, frames, per_atom=False):
     return (out, pa) if per_atom else out
 
 
+def population_loss(base, params, frames, reference, lambda1=0.0, lambda2=0.0):
+    """Loss of every individual z_p of a population (Sec. 2.4): the RMSE of the
+    model's tensors over all frames and components against reference, plus
+    regularization lambda1 * sum|z| / N + lambda2 * sqrt(sum z^2 / N), N the
+    number of parameters.  params [P, N] in the layout of synth.pack_params.
+    Returns (loss [P], rmse [P])."""
+    import synth
+
+    params = np.asarray(params, np.float64)
+    ref = np.asarray(reference, np.float64).reshape(frames.n_frames, -1)
+    loss, rmse = [], []
+    for z in params:
+        pred = np.asarray(eval_frames(synth.unpack_params(base, z), frames)).reshape(frames.n_frames, -1)
+        e = float(np.sqrt(np.mean((pred - ref) ** 2)))
+        n = z.size
+        rmse.append(e)
+        loss.append(e + lambda1 * np.abs(z).sum() / n + lambda2 * np.sqrt((z * z).sum() / n))
+    return np.array(loss), np.array(rmse)
+
+
 def dipole_charged(m, frames, charges, species_masses, length_unit=1.0):
     """Dipole of charged molecules (Sec. 3, charged molecules): the model gives
     mu_r, the permanent dipole relative to the centre of mass, and the absolute

@@ -319,9 +319,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
 
     // models with the same cutoffs and species count share one neighbour build
     const Model* m0 = job.models[0];
-    const bool shared = job.n_models == 1 ||
-                        (job.models[1]->rc_radial == m0->rc_radial && job.models[1]->rc_angular == m0->rc_angular &&
-                         job.models[1]->T == m0->T);
+    bool shared = true;
+    for (int k = 1; k < job.n_models; ++k)
+        shared = shared && job.models[k]->rc_radial == m0->rc_radial &&
+                 job.models[k]->rc_angular == m0->rc_angular && job.models[k]->T == m0->T;
 
     for (int group = 0; group < (shared ? 1 : job.n_models); ++group) {
         const Model* gm = job.models[group];
@@ -542,10 +543,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 nl.slots = slots;
                 // per model: per-atom records, per-frame outputs (a: tensor or
                 // energy, b: virial of a potential-energy model)
-                double* pa_of[2];
-                double* out_of[2];
-                double* aux_of[2] = {nullptr, nullptr};
-                int nt_of[2], na_of[2];
+                double* pa_of[EvalJob::kMax];
+                double* out_of[EvalJob::kMax];
+                double* aux_of[EvalJob::kMax] = {};
+                int nt_of[EvalJob::kMax], na_of[EvalJob::kMax];
                 double *forces_dst = nullptr, *energies_dst = nullptr;
                 for (int k = first; k < last; ++k) {
                     const int kind = job.models[k]->kind;

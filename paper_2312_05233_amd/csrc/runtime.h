@@ -127,10 +127,11 @@ struct Model {
 // virials [F][9] (or NULL), per_atom = site energies [A] (or NULL), forces
 // [A][3] (or NULL).
 struct EvalJob {
-    const Model* models[2] = {nullptr, nullptr};
-    double* out[2] = {nullptr, nullptr};
-    double* aux[2] = {nullptr, nullptr};
-    double* per_atom[2] = {nullptr, nullptr};
+    static constexpr int kMax = 64;  // models per job (one neighbour build serves all)
+    const Model* models[kMax] = {};
+    double* out[kMax] = {};
+    double* aux[kMax] = {};
+    double* per_atom[kMax] = {};
     double* forces = nullptr;
     int n_models = 0;
 };

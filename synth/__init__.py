@@ -336,6 +336,39 @@ def with_descriptor_of(m: "Model", ref: "Model") -> "Model":
                  ref.c_angular, ref.q_scaler, m.heads, m.per_species)
 
 
+def pack_params(m: "Model") -> np.ndarray:
+    """Trainable parameters of a shared-network model as one vector:
+    c_radial, c_angular, then per head w0 [H, D], b0 [H], w1 [H], b1."""
+    parts = [np.ravel(m.c_radial), np.ravel(m.c_angular)]
+    for h in m.heads:
+        parts += [np.ravel(h.w0), np.ravel(h.b0), np.ravel(h.w1), np.array([h.b1], np.float64)]
+    return np.concatenate(parts).astype(np.float64)
+
+
+def unpack_params(base: "Model", z) -> "Model":
+    """The model with base's hyperparameters and descriptor scaler and the
+    trainable parameters z (layout of pack_params)."""
+    z = np.asarray(z, np.float64)
+    o = 0
+
+    def take(shape):
+        nonlocal o
+        n = int(np.prod(shape))
+        out = z[o:o + n].reshape(shape)
+        o += n
+        return out
+
+    cr = take(base.c_radial.shape)
+    ca = take(base.c_angular.shape)
+    heads = []
+    for h in base.heads:
+        heads.append(Head(take(h.w0.shape), take(h.b0.shape), take(h.w1.shape), float(take((1,))[0])))
+    assert o == z.size, "parameter vector of the wrong length"
+    return Model(base.kind, base.species, base.rc_radial, base.rc_angular, base.n_max_radial, base.n_max_angular,
+                 base.basis_radial, base.basis_angular, base.l_max, base.four_body, base.n_hidden, cr, ca,
+                 base.q_scaler, heads)
+
+
 MODEL_SPECS = {
     "water_dipole_small": (100, KIND_DIPOLE, WATER_SPECIES, WATER_DESCRIPTOR),
     "water_dipole": (101, KIND_DIPOLE, WATER_SPECIES, WATER_DESCRIPTOR),
