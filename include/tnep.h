@@ -336,6 +336,25 @@ int tnep_acf_stream_raman_map(tnep_acf_stream* s, double dt_fs, int32_t window, 
                               const double* n_hat, const double* e_hat, double* freq_cm1, double* intensity);
 void tnep_acf_stream_free(tnep_acf_stream* s);
 
+/* ---- training loss of a population ------------------------------------- */
+/* Loss of each individual of an evolution-strategy population (Sec. 2.4, loss
+ * function of the training; the optimiser draws the individuals):
+ *   L(z) = RMSE(z) + lambda1 * sum_i |z_i| / N + lambda2 * sqrt(sum_i z_i^2 / N),
+ * RMSE over all F * nt predicted frame-tensor components (nt = 3 dipole, 9
+ * polarizability) against reference [F][nt] (same units as the predictions).
+ * base: hyperparameters (kind, species, cutoffs, basis sizes, hidden width,
+ * four-body flag; shared networks only), its parameter pointers are ignored.
+ * params: [n_individuals][N] FP64 host array, each row in the order
+ * c_radial [T][T][nr][kr], c_angular [T][T][na][ka], then per output head
+ * (one dipole, two polarizability: anisotropic, scalar) w0 [H][D], b0 [H],
+ * w1 [H], b1.  frames: host or device; reference in the frames' location.
+ * loss_out, rmse_out (may be NULL): [n_individuals] host.  Up to 64
+ * individuals share one neighbour build.  Errors: TNEP_E_INVALID on bad
+ * arguments, TNEP_E_BUDGET / TNEP_E_HIP as for the evaluators. */
+int tnep_population_loss(tnep_ctx* ctx, const tnep_model_desc* base, int32_t n_individuals, const double* params,
+                         const tnep_frames* frames, const double* reference, double lambda1, double lambda2,
+                         double* loss_out, double* rmse_out);
+
 /* ---- serving (continuous batching) ------------------------------------- */
 typedef struct {
     uint64_t mem_budget_bytes; /* admission budget for in-flight requests (0 = ctx budget) */

@@ -40,7 +40,7 @@ EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_
             "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts", "tnep_eval_pes",
             "tnep_raman_map", "tnep_acf_stream_create", "tnep_acf_stream_push", "tnep_acf_stream_end_run",
             "tnep_acf_stream_spectrum", "tnep_acf_stream_raman_map", "tnep_acf_stream_free",
-            "tnep_ctx_reuse_fallbacks", "tnep_eval_dipole_charged"]
+            "tnep_ctx_reuse_fallbacks", "tnep_eval_dipole_charged", "tnep_population_loss"]
 
 
 class TnepError(RuntimeError):
@@ -105,6 +105,8 @@ def _load():
     lib.tnep_eval_dipole_polarizability.argtypes = [vp, vp, vp, P(FramesDesc), vp, vp]
     lib.tnep_eval_pes.argtypes = [vp, vp, P(FramesDesc), vp, vp, vp, vp]
     lib.tnep_eval_dipole_charged.argtypes = [vp, vp, P(FramesDesc), vp, vp, C.c_double, vp, vp]
+    lib.tnep_population_loss.argtypes = [vp, P(ModelDesc), C.c_int32, vp, P(FramesDesc), vp, C.c_double, C.c_double,
+                                         vp, vp]
     lib.tnep_raman_map.argtypes = [vp, P(SpectrumArgs), C.c_int32, vp, vp, vp, vp]
     lib.tnep_acf_stream_create.argtypes = [vp, C.c_int32, C.c_int64, C.c_int32, vp, vp, P(vp)]
     lib.tnep_acf_stream_push.argtypes = [vp, vp, C.c_int64, C.c_int32]
@@ -218,29 +220,7 @@ class Model:
     def __init__(self, ctx: Context, m):
         self.ctx = ctx
         self.kind = m.kind
-        keep = []
-
-        def arr(x):
-            a = np.ascontiguousarray(np.asarray(x, np.float64))
-            keep.append(a)
-            return a.ctypes.data_as(P(C.c_double))
-
-        d = ModelDesc()
-        d.kind = m.kind
-        d.n_species = len(m.species) if hasattr(m, "species") else m.n_species
-        d.rc_radial, d.rc_angular = m.rc_radial, m.rc_angular
-        d.n_max_radial, d.n_max_angular = m.n_max_radial, m.n_max_angular
-        d.basis_radial, d.basis_angular = m.basis_radial, m.basis_angular
-        d.l_max, d.four_body, d.n_hidden = m.l_max, int(bool(m.four_body)), m.n_hidden
-        d.c_radial, d.c_angular, d.q_scaler = arr(m.c_radial), arr(m.c_angular), arr(m.q_scaler)
-        per_species = bool(getattr(m, "per_species", False))
-        d.per_species = int(per_species)
-        for k, head in enumerate(m.heads):
-            d.w0[k], d.b0[k], d.w1[k] = arr(head.w0), arr(head.b0), arr(head.w1)
-            if per_species:
-                d.b1_species[k] = arr(head.b1)
-            else:
-                d.b1[k] = head.b1
+        d, keep = model_desc(m)
         h = C.c_void_p()
         ctx.check(lib.tnep_model_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
@@ -255,6 +235,35 @@ class Model:
             self.close()
         except Exception:
             pass
+
+
+def model_desc(m):
+    """tnep_model_desc of a model object, and the arrays it points into (keep
+    them alive while the descriptor is used)."""
+    keep = []
+
+    def arr(x):
+        a = np.ascontiguousarray(np.asarray(x, np.float64))
+        keep.append(a)
+        return a.ctypes.data_as(P(C.c_double))
+
+    d = ModelDesc()
+    d.kind = m.kind
+    d.n_species = len(m.species) if hasattr(m, "species") else m.n_species
+    d.rc_radial, d.rc_angular = m.rc_radial, m.rc_angular
+    d.n_max_radial, d.n_max_angular = m.n_max_radial, m.n_max_angular
+    d.basis_radial, d.basis_angular = m.basis_radial, m.basis_angular
+    d.l_max, d.four_body, d.n_hidden = m.l_max, int(bool(m.four_body)), m.n_hidden
+    d.c_radial, d.c_angular, d.q_scaler = arr(m.c_radial), arr(m.c_angular), arr(m.q_scaler)
+    per_species = bool(getattr(m, "per_species", False))
+    d.per_species = int(per_species)
+    for k, head in enumerate(m.heads):
+        d.w0[k], d.b0[k], d.w1[k] = arr(head.w0), arr(head.b0), arr(head.w1)
+        if per_species:
+            d.b1_species[k] = arr(head.b1)
+        else:
+            d.b1[k] = head.b1
+    return d, keep
 
 
 def frames_desc(frames, location=None):
@@ -337,6 +346,23 @@ def tnep_eval_dipole_charged(ctx: Context, model: Model, frames, charges, specie
     ctx.check(lib.tnep_eval_dipole_charged(ctx.h, model.h, C.byref(fd), _ptr(charges), _ptr(masses),
                                            float(length_unit), _ptr(mu_out), _ptr(per_atom)))
     return mu_out
+
+
+def tnep_population_loss(ctx: Context, base, params, frames, reference, lambda1=0.0, lambda2=0.0):
+    """Loss and RMSE [P] of each parameter vector params [P, N] (layout of
+    synth.pack_params) with base's hyperparameters, over frames against
+    reference [F, nt] (numpy for host frames, device tensor for device frames)."""
+    d, keep = model_desc(base)
+    params = np.ascontiguousarray(params, np.float64)
+    fd = frames_desc(frames)
+    if fd.location == HOST:
+        reference = np.ascontiguousarray(reference, np.float64)
+    n = params.shape[0]
+    loss, rmse = np.zeros(n), np.zeros(n)
+    ctx.check(lib.tnep_population_loss(ctx.h, C.byref(d), n, _ptr(params), C.byref(fd), _ptr(reference),
+                                       float(lambda1), float(lambda2), _ptr(loss), _ptr(rmse)))
+    del keep
+    return loss, rmse
 
 
 def tnep_eval_pes(ctx: Context, model: Model, frames, energy=None, virial=None, forces=None, per_atom_energy=None,
