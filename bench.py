@@ -227,6 +227,73 @@ def bench_pes(args):
         "kernels_ms_per_step": kt, "errors_vs_oracle_frame0": errs}), flush=True)
 
 
+def bench_population(args):
+    """Loss of an evolution-strategy population (Sec. 2.4): 50 individuals of
+    the susceptibility model over a training set of 800 perovskite structures
+    (4x4x4 supercells, 320 atoms), against synthetic reference tensors; all
+    inputs device-resident.  Errors against the oracle and the oracle's own
+    rate on a sample of individuals and structures."""
+    import torch
+
+    import oracle
+    from paper_2312_05233_amd import tnep
+
+    n_pop, n_struct = 50, 800
+    frames = synth.perovskite_frames(4, 4.19, n_struct, 5)
+    base = synth.model("perovskite_susceptibility")
+    z0 = synth.pack_params(base)
+    rng = np.random.default_rng(6)
+    zs = z0[None, :] * (1.0 + 0.02 * rng.normal(size=(n_pop, z0.size)))
+    ref = rng.normal(size=(n_struct, 9))
+    ctx = tnep.Context(0)
+    dfr = tnep.DeviceFrames(frames)
+    dref = torch.as_tensor(ref).cuda()
+    step = lambda: tnep.tnep_population_loss(ctx, base, zs, dfr, dref, 0.05, 0.05)  # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_option(tnep.OPT_TIMING, 1)
+    ctx.reset_timing()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    ms, n = ctx.kernel_time(tnep.KERNEL_EVAL_POLARIZABILITY)
+    atoms, rad, ang = ctx.pair_counts()
+    kt = {name: ctx.kernel_time(k)[0] / args.steps for name, k in (
+        ("neighbors", tnep.KERNEL_NEIGHBORS), ("eval_polarizability", tnep.KERNEL_EVAL_POLARIZABILITY),
+        ("frame_reduce", tnep.KERNEL_FRAME_REDUCE))}
+    flop = flops_per_atom_frame(base, rad / atoms, ang / atoms)
+    atoms_per_launch = frames.n_atoms * n_pop / (n / args.steps)
+    achieved = flop * atoms_per_launch / (ms / n * 1e-3) / 1e12
+    evals = frames.n_atoms * n_pop
+    # oracle on a sample: 4 individuals x 160 structures (also the error check)
+    sub = frames.subset(list(range(160)))
+    t1 = time.perf_counter()
+    loss_r, rmse_r = oracle.population_loss(base, zs[:4], sub, ref[:160], 0.05, 0.05)
+    t_cpu = time.perf_counter() - t1
+    loss_g, rmse_g = tnep.tnep_population_loss(ctx, base, zs[:4], sub, ref[:160], 0.05, 0.05)
+    print(json.dumps({
+        "metric": "population loss: atom-evaluations/s (individuals x atoms) at FP32 tol", "value": evals / t,
+        "unit": "atom-evaluations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * t, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "population of %d susceptibility models (rc 7/5 A, n_max 6/4, H=50) x %d perovskite "
+                               "structures (4x4x4 Ba/Zr/O, 320 atoms, sigma 0.08 A), synthetic reference tensors"
+                               % (n_pop, n_struct)},
+        "generations_per_s": 1.0 / t,
+        "roofline": {"kernel": "k_eval (polarizability)", "bound": "alu", "achieved": achieved, "peak": 157.3,
+                     "unit": "TFLOP/s", "frac": achieved / 157.3, "flop_per_atom_frame": flop,
+                     "atoms_per_launch": atoms_per_launch, "avg_launch_ms": ms / n},
+        "kernels_ms_per_step": kt,
+        "errors_vs_oracle_sample": {"rmse_abs_max": float(np.abs(rmse_g - rmse_r).max()),
+                                    "loss_abs_max": float(np.abs(loss_g - loss_r).max()),
+                                    "rmse_ref_min": float(rmse_r.min())},
+        "cpu_baseline": {"value": 4 * sub.n_atoms / t_cpu, "unit": "atom-evaluations/s",
+                         "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                         "kind": "oracle", "sample": "4 individuals x 160 structures (51,200 atoms)"}}), flush=True)
+
+
 def bench_spectra(args):
     """Paper-scale Raman spectra of a recorded susceptibility: 20 runs of
     10^5 samples (500 ps at 5 fs), pushed through the streaming accumulator in
@@ -466,7 +533,8 @@ def main():
     ap.add_argument("--trajectory-window", type=int, default=0,
                     help="frames per neighbour-candidate window of the trajectory (0 = plain searches)")
     ap.add_argument("--skin", type=float, default=1.0, help="candidate skin in Angstrom")
-    ap.add_argument("--workload", default="water", choices=["water", "perovskite", "molecules", "serving", "pes", "spectra"],
+    ap.add_argument("--workload", default="water", choices=["water", "perovskite", "molecules", "serving", "pes", "spectra",
+                                                              "population"],
                     help="water: the headline line; the others print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
@@ -492,7 +560,7 @@ def main():
 
     if args.workload != "water":
         {"perovskite": bench_perovskite, "molecules": bench_molecules, "serving": bench_serving,
-         "pes": bench_pes, "spectra": bench_spectra}[args.workload](args)
+         "pes": bench_pes, "spectra": bench_spectra, "population": bench_population}[args.workload](args)
         return
 
     dev = torch.device("cuda:0")

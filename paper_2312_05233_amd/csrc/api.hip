@@ -120,6 +120,7 @@ tnep::Ctx::~Ctx() {
     for (hipEvent_t ev : event_pool) (void)hipEventDestroy(ev);
     for (DevBuf* b : all_buffers()) release(*b);
     if (h_flags) (void)hipHostFree(h_flags);
+    if (pop_host) (void)hipHostFree(pop_host);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -288,37 +289,38 @@ extern "C" int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value) {
 // ---------------------------------------------------------------------------
 // models
 
-extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_model** out) {
-    if (!ctx || !d || !out) return TNEP_E_INVALID;
-    Ctx* c = reinterpret_cast<Ctx*>(ctx);
-    *out = nullptr;
+// Model validation error: the message goes to the context when there is one
+// (staging on worker threads passes none).
+#define model_error(c, ...) ((c) ? (c)->fail(TNEP_E_MODEL, __VA_ARGS__) : TNEP_E_MODEL)
+
+int tnep::stage_model(Ctx* c, const tnep_model_desc* d, std::vector<float>& h, Model& m, ModelLayout& lay) {
     if (d->kind != TNEP_KIND_DIPOLE && d->kind != TNEP_KIND_POLARIZABILITY && d->kind != TNEP_KIND_PES)
-        return c->fail(TNEP_E_MODEL, "unknown model kind %d", d->kind);
-    if (d->n_species < 1 || d->n_species > 8) return c->fail(TNEP_E_MODEL, "n_species must be 1..8");
+        return model_error(c, "unknown model kind %d", d->kind);
+    if (d->n_species < 1 || d->n_species > 8) return model_error(c, "n_species must be 1..8");
     if (!(d->rc_radial > 0) || !(d->rc_angular > 0) || d->rc_angular > d->rc_radial)
-        return c->fail(TNEP_E_MODEL, "need 0 < rc_angular <= rc_radial");
-    if (d->l_max != 4) return c->fail(TNEP_E_MODEL, "only l_max = 4 is compiled");
-    if (d->n_hidden < 1 || d->n_hidden > 128) return c->fail(TNEP_E_MODEL, "n_hidden must be 1..128");
+        return model_error(c, "need 0 < rc_angular <= rc_radial");
+    if (d->l_max != 4) return model_error(c, "only l_max = 4 is compiled");
+    if (d->n_hidden < 1 || d->n_hidden > 128) return model_error(c, "n_hidden must be 1..128");
     Shape sh{d->n_max_radial + 1, d->n_max_angular + 1, d->basis_radial + 1, d->basis_angular + 1,
              d->four_body ? 1 : 0, d->kind};
     if (!eval_shape_supported(sh))
-        return c->fail(TNEP_E_MODEL, "descriptor shape (nR=%d, nA=%d, KR=%d, KA=%d, 4b=%d) is not compiled",
+        return model_error(c, "descriptor shape (nR=%d, nA=%d, KR=%d, KA=%d, 4b=%d) is not compiled",
                        d->n_max_radial, d->n_max_angular, d->basis_radial, d->basis_angular, d->four_body);
     if (!d->c_radial || !d->c_angular || !d->q_scaler || !d->w0[0] || !d->b0[0] || !d->w1[0])
-        return c->fail(TNEP_E_MODEL, "missing parameter arrays");
+        return model_error(c, "missing parameter arrays");
     const int heads = d->kind == TNEP_KIND_POLARIZABILITY ? 2 : 1;
     if (heads == 2 && (!d->w0[1] || !d->b0[1] || !d->w1[1]))
-        return c->fail(TNEP_E_MODEL, "polarizability model needs the scalar head");
+        return model_error(c, "polarizability model needs the scalar head");
     const bool per_species = d->per_species != 0;
     for (int hd = 0; hd < heads && per_species; ++hd)
-        if (!d->b1_species[hd]) return c->fail(TNEP_E_MODEL, "per-species model needs b1_species");
+        if (!d->b1_species[hd]) return model_error(c, "per-species model needs b1_species");
     const int T = d->n_species, H = d->n_hidden;
     const size_t NS = per_species ? (size_t)T : 1;  // networks per head
     const int D = sh.nr + 4 * sh.na + (sh.four_body ? sh.na : 0);
     const size_t ncr = (size_t)T * T * sh.nr * sh.kr, nca = (size_t)T * T * sh.na * sh.ka;
 
-    // host staging in FP32, fixed layout
-    std::vector<float> h;
+    // host staging in FP32, fixed layout, appended to h at a 256-byte boundary
+    while (h.size() % 64) h.push_back(0.f);
     auto put = [&](const double* src, size_t n) {
         size_t off = h.size();
         for (size_t k = 0; k < n; ++k) h.push_back((float)src[k]);
@@ -326,7 +328,7 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
         return off;
     };
     for (size_t k = 0; k < ncr; ++k)
-        if (!std::isfinite(d->c_radial[k])) return c->fail(TNEP_E_MODEL, "non-finite c_radial");
+        if (!std::isfinite(d->c_radial[k])) return model_error(c, "non-finite c_radial");
     size_t o_cr = put(d->c_radial, ncr);
     size_t o_ca = put(d->c_angular, nca);
     size_t o_s = put(d->q_scaler, D);
@@ -342,7 +344,7 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
         o_w0t[hd] = put(t.data(), t.size());
     }
     for (float v : h)
-        if (!std::isfinite(v)) return c->fail(TNEP_E_MODEL, "non-finite model parameter");
+        if (!std::isfinite(v)) return model_error(c, "non-finite model parameter");
 
     // matrix-core fragments (see DevModel)
     auto rup = [](int x, int m) { return (x + m - 1) / m * m; };
@@ -416,17 +418,77 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
     }
 
     static std::atomic<uint64_t> next_serial{1};
+    m.serial = next_serial++;
+    m.ctx = c;
+    m.device = c ? c->device : 0;
+    m.shape = sh;
+    m.kind = d->kind;
+    m.T = T;
+    m.D = D;
+    m.H = H;
+    m.rc_radial = d->rc_radial;
+    m.rc_angular = d->rc_angular;
+    lay.cr = o_cr;
+    lay.ca = o_ca;
+    lay.s = o_s;
+    for (int hd = 0; hd < 2; ++hd) {
+        const int src = hd < heads ? hd : 0;
+        lay.w0[hd] = o_w0[src];
+        lay.b0[hd] = o_b0[src];
+        lay.w1[hd] = o_w1[src];
+        lay.w0t[hd] = o_w0t[src];
+        lay.b1[hd] = (float)d->b1[src];
+        lay.b1s[hd] = per_species ? (int64_t)o_b1s[src] : -1;
+        lay.f32_fwd[hd] = o_f32_fwd[src];
+        lay.bf_fwd_hi[hd] = o_bf_fwd_hi[src];
+        lay.bf_fwd_lo[hd] = o_bf_fwd_lo[src];
+    }
+    lay.f32_bwd = o_f32_bwd;
+    lay.bf_bwd_hi = o_bf_bwd_hi;
+    lay.bf_bwd_lo = o_bf_bwd_lo;
+    lay.per_species = per_species;
+    return TNEP_OK;
+}
+
+void tnep::bind_model(Model& m, const float* base, const ModelLayout& lay) {
+    DevModel& dm = m.dm;
+    dm.c_radial = base + lay.cr;
+    dm.c_angular = base + lay.ca;
+    dm.scaler = base + lay.s;
+    for (int hd = 0; hd < 2; ++hd) {
+        dm.w0[hd] = base + lay.w0[hd];
+        dm.b0[hd] = base + lay.b0[hd];
+        dm.w1[hd] = base + lay.w1[hd];
+        dm.w0t[hd] = base + lay.w0t[hd];
+        dm.b1[hd] = lay.b1[hd];
+        dm.b1s[hd] = lay.b1s[hd] >= 0 ? base + lay.b1s[hd] : nullptr;
+        dm.f32_fwd[hd] = base + lay.f32_fwd[hd];
+        dm.bf_fwd_hi[hd] = reinterpret_cast<const uint4*>(base + lay.bf_fwd_hi[hd]);
+        dm.bf_fwd_lo[hd] = reinterpret_cast<const uint4*>(base + lay.bf_fwd_lo[hd]);
+    }
+    dm.f32_bwd = base + lay.f32_bwd;
+    dm.bf_bwd_hi = reinterpret_cast<const uint4*>(base + lay.bf_bwd_hi);
+    dm.bf_bwd_lo = reinterpret_cast<const uint4*>(base + lay.bf_bwd_lo);
+    dm.sp_w0 = lay.per_species ? m.H * m.D : 0;
+    dm.sp_h = lay.per_species ? m.H : 0;
+    dm.rc_radial = (float)m.rc_radial;
+    dm.rc_angular = (float)m.rc_angular;
+    dm.n_species = m.T;
+    dm.n_hidden = m.H;
+}
+
+extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_model** out) {
+    if (!ctx || !d || !out) return TNEP_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    *out = nullptr;
+    std::vector<float> h;
+    ModelLayout lay;
     Model* m = new Model();
-    m->serial = next_serial++;
-    m->ctx = c;
-    m->device = c->device;
-    m->shape = sh;
-    m->kind = d->kind;
-    m->T = T;
-    m->D = D;
-    m->H = H;
-    m->rc_radial = d->rc_radial;
-    m->rc_angular = d->rc_angular;
+    int e = stage_model(c, d, h, *m, lay);
+    if (e) {
+        delete m;
+        return e;
+    }
     (void)hipSetDevice(c->device);
     if (hipMalloc(&m->dbuf, h.size() * sizeof(float)) != hipSuccess) {
         delete m;
@@ -438,32 +500,7 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
         delete m;
         return c->fail(TNEP_E_HIP, "model upload failed");
     }
-    const float* base = (const float*)m->dbuf;
-    DevModel& dm = m->dm;
-    dm.c_radial = base + o_cr;
-    dm.c_angular = base + o_ca;
-    dm.scaler = base + o_s;
-    for (int hd = 0; hd < 2; ++hd) {
-        const int src = hd < heads ? hd : 0;
-        dm.w0[hd] = base + o_w0[src];
-        dm.b0[hd] = base + o_b0[src];
-        dm.w1[hd] = base + o_w1[src];
-        dm.w0t[hd] = base + o_w0t[src];
-        dm.b1[hd] = (float)d->b1[src];
-        dm.b1s[hd] = per_species ? base + o_b1s[src] : nullptr;
-        dm.f32_fwd[hd] = base + o_f32_fwd[src];
-        dm.bf_fwd_hi[hd] = reinterpret_cast<const uint4*>(base + o_bf_fwd_hi[src]);
-        dm.bf_fwd_lo[hd] = reinterpret_cast<const uint4*>(base + o_bf_fwd_lo[src]);
-    }
-    dm.f32_bwd = base + o_f32_bwd;
-    dm.bf_bwd_hi = reinterpret_cast<const uint4*>(base + o_bf_bwd_hi);
-    dm.bf_bwd_lo = reinterpret_cast<const uint4*>(base + o_bf_bwd_lo);
-    dm.sp_w0 = per_species ? H * D : 0;
-    dm.sp_h = per_species ? H : 0;
-    dm.rc_radial = (float)d->rc_radial;
-    dm.rc_angular = (float)d->rc_angular;
-    dm.n_species = T;
-    dm.n_hidden = H;
+    bind_model(*m, (const float*)m->dbuf, lay);
     *out = reinterpret_cast<tnep_model*>(m);
     return TNEP_OK;
 }

@@ -225,31 +225,41 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 
 // Sort each bucket by atom index, place it into the tile permutation and
 // store its positions contiguously in bucket order (w = the atom's tile slot
-// in the low 32 bits, its batch index in the high 32 bits).
-__global__ void k_sort_place(const int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_atoms,
-                             const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm,
-                             int32_t* __restrict__ slot_of, const double* __restrict__ pos,
-                             double4* __restrict__ bucket_pos, const int32_t* __restrict__ meta, int T) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// in the low 32 bits, its batch index in the high 32 bits).  One wave per
+// bucket: an atom's place is the number of smaller atom indices in its bucket
+// (indices are distinct), counted against LDS-staged chunks of the bucket, so
+// buckets of hundreds of atoms (whole small frames) sort in parallel.
+constexpr int kSortChunk = 1024;
+__global__ void __launch_bounds__(64) k_sort_place(const int32_t* __restrict__ bucket_start,
+                                                   const int32_t* __restrict__ bucket_atoms,
+                                                   const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm,
+                                                   int32_t* __restrict__ slot_of, const double* __restrict__ pos,
+                                                   double4* __restrict__ bucket_pos, const int32_t* __restrict__ meta,
+                                                   int T) {
+    __shared__ int32_t chunk[kSortChunk];
+    const int k = blockIdx.x;
     if (k >= meta[kMetaNCells] * T) return;
-    const int b = bucket_start[k], e = bucket_start[k + 1];
-    for (int i = b + 1; i < e; ++i) {
-        const int32_t v = bucket_atoms[i];
-        int j = i - 1;
-        while (j >= b && bucket_atoms[j] > v) {
-            bucket_atoms[j + 1] = bucket_atoms[j];
-            --j;
-        }
-        bucket_atoms[j + 1] = v;
-    }
+    const int b = bucket_start[k], n = bucket_start[k + 1] - b;
     const int p = perm_start[k];
-    for (int i = b; i < e; ++i) {
-        const int a = bucket_atoms[i];
-        const int slot = p + (i - b);
-        perm[slot] = a;
-        slot_of[a] = slot;
-        bucket_pos[i] = make_double4(pos[3 * a], pos[3 * a + 1], pos[3 * a + 2],
-                                     __longlong_as_double((long long)(((uint64_t)(uint32_t)a << 32) | (uint32_t)slot)));
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int i = i0 + (int)threadIdx.x;
+        const int32_t v = i < n ? bucket_atoms[b + i] : 0;
+        int rank = 0;
+        for (int j0 = 0; j0 < n; j0 += kSortChunk) {
+            const int m = min(kSortChunk, n - j0);
+            __syncthreads();
+            for (int j = threadIdx.x; j < m; j += 64) chunk[j] = bucket_atoms[b + j0 + j];
+            __syncthreads();
+            for (int j = 0; j < m; ++j) rank += chunk[j] < v ? 1 : 0;
+        }
+        if (i < n) {
+            const int slot = p + rank;
+            perm[slot] = v;
+            slot_of[v] = slot;
+            bucket_pos[b + rank] =
+                make_double4(pos[3 * v], pos[3 * v + 1], pos[3 * v + 2],
+                             __longlong_as_double((long long)(((uint64_t)(uint32_t)v << 32) | (uint32_t)slot)));
+        }
     }
 }
 
@@ -669,7 +679,7 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                            w.bucket_fill, w.perm_start);
     k_scatter<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill,
                                                               w.bucket_atoms, nl.meta);
-    k_sort_place<<<blocks_for(cap_buckets, kBlock), kBlock, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
+    k_sort_place<<<cap_buckets, 64, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
                                                                    w.perm, w.slot_of, pos, w.bucket_pos, nl.meta, T);
     k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                               w.key_of, w.bucket_start, w.bucket_pos, rc_radial,

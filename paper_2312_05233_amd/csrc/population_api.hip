@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "runtime.h"
@@ -122,7 +123,9 @@ extern "C" int tnep_population_loss(tnep_ctx* ctx, const tnep_model_desc* base, 
     const hipMemcpyKind to_host = frames->location == TNEP_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
     HIP_CHECK_RET(c, hipMemcpy(offs.data(), frames->atom_offsets, sizeof(int64_t) * (F + 1), to_host));
     const int64_t A = offs[F];
-    DevBuf stage, work;
+    DevBuf& stage = c->pop_stage;
+    DevBuf& work = c->pop_work;
+    DevBuf& mimg = c->pop_img;
     tnep_frames dfr = *frames;
     const size_t n_values = (size_t)F * nt;
     int e;
@@ -157,59 +160,100 @@ extern "C" int tnep_population_loss(tnep_ctx* ctx, const tnep_model_desc* base, 
         auto rr = put(reference, sizeof(double) * n_values);
         reference = (const double*)rr.first;
         if (rr.second != hipSuccess) he = rr.second;
-        if (he != hipSuccess) {
-            c->release(stage);
-            return c->fail(TNEP_E_HIP, "staging frames failed: %s", hipGetErrorString(he));
-        }
+        if (he != hipSuccess) return c->fail(TNEP_E_HIP, "staging frames failed: %s", hipGetErrorString(he));
         dfr.location = TNEP_DEVICE;
     }
     // predictions [P][F][nt], parameters [P][N], per-individual sums
     const size_t wbytes = sizeof(double) * ((size_t)P * n_values + (size_t)P * L.total + 5 * (size_t)P) + 4096;
-    if ((e = c->reserve(work, wbytes))) {
-        c->release(stage);
-        return e;
-    }
+    if ((e = c->reserve(work, wbytes))) return e;
     double* pred = (double*)work.p;
     double* zdev = pred + (size_t)P * n_values;
     double* sse = zdev + (size_t)P * L.total;
     double *l1 = sse + P, *l2 = l1 + P, *dloss = l2 + P, *drmse = dloss + P;
     auto cleanup = [&](int code) {
-        c->release(work);
-        c->release(stage);
+        (void)hipStreamSynchronize(c->stream);  // the uploads read host memory owned by this call
         return code;
     };
     if (hipMemcpyAsync(zdev, params, sizeof(double) * (size_t)P * L.total, hipMemcpyHostToDevice, c->stream) !=
         hipSuccess)
         return cleanup(c->fail(TNEP_E_HIP, "parameter upload failed"));
 
-    // individuals in jobs of up to EvalJob::kMax models
-    for (int p0 = 0; p0 < P; p0 += EvalJob::kMax) {
-        const int np = std::min(EvalJob::kMax, P - p0);
-        std::vector<tnep_model*> models(np, nullptr);
-        EvalJob job;
-        int err = TNEP_OK;
-        for (int k = 0; k < np && !err; ++k) {
-            const double* z = params + (size_t)(p0 + k) * L.total;
-            tnep_model_desc d = *base;
-            d.c_radial = z;
-            d.c_angular = z + L.ncr;
-            for (int h = 0; h < L.heads; ++h) {
-                const double* hz = z + L.ncr + L.nca + h * L.per_head;
-                d.w0[h] = hz;
-                d.b0[h] = hz + L.nw0;
-                d.w1[h] = hz + L.nw0 + L.nh;
-                d.b1[h] = hz[L.nw0 + 2 * L.nh];
-            }
-            err = tnep_model_create(ctx, &d, &models[k]);
-            if (!err) {
-                job.models[k] = reinterpret_cast<const Model*>(models[k]);
-                job.out[k] = pred + (size_t)(p0 + k) * n_values;
-            }
+    // all individuals' model images (built on host threads) in one upload
+    std::vector<Model> models(P);
+    std::vector<ModelLayout> lays(P);
+    std::vector<std::vector<float>> imgs(P);
+    std::vector<int> errs(P, TNEP_OK);
+    auto desc_of = [&](int p) {
+        const double* z = params + (size_t)p * L.total;
+        tnep_model_desc d = *base;
+        d.c_radial = z;
+        d.c_angular = z + L.ncr;
+        for (int h = 0; h < L.heads; ++h) {
+            const double* hz = z + L.ncr + L.nca + h * L.per_head;
+            d.w0[h] = hz;
+            d.b0[h] = hz + L.nw0;
+            d.w1[h] = hz + L.nw0 + L.nh;
+            d.b1[h] = hz[L.nw0 + 2 * L.nh];
         }
-        job.n_models = np;
-        if (!err) err = run_eval(c, dfr, job);
-        for (tnep_model* m : models) tnep_model_free(m);
-        if (err) return cleanup(err);
+        return d;
+    };
+    // the first individual on this thread (structural errors get their message), the rest in parallel
+    {
+        const tnep_model_desc d = desc_of(0);
+        if ((e = stage_model(c, &d, imgs[0], models[0], lays[0]))) return cleanup(e);
+    }
+    auto stage_range = [&](int pa, int pb) {
+        for (int p = pa; p < pb; ++p) {
+            const tnep_model_desc d = desc_of(p);
+            errs[p] = stage_model(nullptr, &d, imgs[p], models[p], lays[p]);
+        }
+    };
+    const int rest = P - 1;
+    const int n_threads = std::max(1, std::min({rest, 16, (int)std::thread::hardware_concurrency()}));
+    if (rest > 0) {
+        std::vector<std::thread> pool;
+        const int per = (rest + n_threads - 1) / n_threads;
+        for (int t = 1; t < n_threads; ++t)
+            if (1 + t * per < P) pool.emplace_back(stage_range, 1 + t * per, std::min(P, 1 + (t + 1) * per));
+        stage_range(1, std::min(P, 1 + per));
+        for (auto& th : pool) th.join();
+    }
+    // every individual has the same image layout; pack them into pinned memory for one DMA
+    const size_t isz = imgs[0].size();
+    for (int p = 0; p < P; ++p) {
+        if (errs[p]) return cleanup(c->fail(errs[p], "individual %d: non-finite parameters", p));
+        if (imgs[p].size() != isz) return cleanup(c->fail(TNEP_E_INVALID, "individual %d: image size differs", p));
+    }
+    const size_t img_bytes = (size_t)P * isz * sizeof(float);
+    if (c->pop_host_bytes < img_bytes) {
+        if (c->pop_host) (void)hipHostFree(c->pop_host);
+        c->pop_host = nullptr;
+        c->pop_host_bytes = 0;
+        if (hipHostMalloc((void**)&c->pop_host, img_bytes, hipHostMallocDefault) != hipSuccess) {
+            c->pop_host = nullptr;
+            return cleanup(c->fail(TNEP_E_HIP, "pinned staging of %zu bytes failed", img_bytes));
+        }
+        c->pop_host_bytes = img_bytes;
+    }
+    for (int p = 0; p < P; ++p) std::memcpy(c->pop_host + (size_t)p * isz, imgs[p].data(), isz * sizeof(float));
+    if ((e = c->reserve(mimg, img_bytes))) return cleanup(e);
+    if (hipMemcpyAsync(mimg.p, c->pop_host, img_bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return cleanup(c->fail(TNEP_E_HIP, "model upload failed"));
+    for (int p = 0; p < P; ++p) {
+        models[p].ctx = c;
+        models[p].device = c->device;
+        bind_model(models[p], (const float*)mimg.p + (size_t)p * isz, lays[p]);
+    }
+
+    // individuals in jobs of up to EvalJob::kMax models sharing a neighbour build
+    for (int p0 = 0; p0 < P; p0 += EvalJob::kMax) {
+        EvalJob job;
+        job.n_models = std::min(EvalJob::kMax, P - p0);
+        for (int k = 0; k < job.n_models; ++k) {
+            job.models[k] = &models[p0 + k];
+            job.out[k] = pred + (size_t)(p0 + k) * n_values;
+        }
+        if ((e = run_eval(c, dfr, job))) return cleanup(e);
     }
     k_pop_sse<<<P, 256, 0, c->stream>>>(pred, reference, (int64_t)n_values, sse);
     k_pop_reg<<<P, 256, 0, c->stream>>>(zdev, (int64_t)L.total, l1, l2);

@@ -65,11 +65,15 @@ struct Ctx {
     DevBuf pes_rec, pes_stage;  // potential-energy models: per-atom records, host-bound staging
     DevBuf slot_of, cand, cand_count;  // tile slot per atom; trajectory candidate lists
     DevBuf com;                        // charged-dipole shift: staging of frames, masses, charges, mu
+    DevBuf pop_stage, pop_work, pop_img;  // population loss: staged frames, predictions, model images
+    float* pop_host = nullptr;            // pinned host staging of the population's model images
+    size_t pop_host_bytes = 0;
 
     std::vector<DevBuf*> all_buffers() {
         return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
-                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &slot_of, &cand, &cand_count, &com};
+                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &slot_of, &cand, &cand_count, &com,
+                &pop_stage, &pop_work, &pop_img};
     }
 
     Server* server = nullptr;
@@ -122,7 +126,23 @@ struct Model {
     double rc_radial = 0, rc_angular = 0;
 };
 
-// One evaluation request: up to two models over the same frames.
+// Offsets (in floats) of a model's arrays inside its FP32 device image.
+struct ModelLayout {
+    size_t cr = 0, ca = 0, s = 0;
+    size_t w0[2] = {}, b0[2] = {}, w1[2] = {}, w0t[2] = {}, f32_fwd[2] = {}, bf_fwd_hi[2] = {}, bf_fwd_lo[2] = {};
+    int64_t b1s[2] = {-1, -1};
+    float b1[2] = {};
+    size_t f32_bwd = 0, bf_bwd_hi = 0, bf_bwd_lo = 0;
+    bool per_species = false;
+};
+
+// Validate d and append its device image to h (256-byte aligned); fills the
+// model's host fields and the image layout, not its device pointers.
+int stage_model(Ctx* c, const tnep_model_desc* d, std::vector<float>& h, Model& m, ModelLayout& lay);
+// Point the model's DevModel at an uploaded image (base = device address of h[0]).
+void bind_model(Model& m, const float* base, const ModelLayout& lay);
+
+// One evaluation request: up to kMax models over the same frames.
 // Potential-energy model (one model per job): out = energies [F], aux =
 // virials [F][9] (or NULL), per_atom = site energies [A] (or NULL), forces
 // [A][3] (or NULL).
