@@ -62,6 +62,7 @@ class _Model(C.Structure):
         ("w0", C.POINTER(C.c_double) * 2), ("b0", C.POINTER(C.c_double) * 2),
         ("w1", C.POINTER(C.c_double) * 2), ("b1", C.c_double * 2),
         ("per_species", C.c_int32), ("b1_species", C.POINTER(C.c_double) * 2),
+        ("five_body", C.c_int32),
     ]
 
 
@@ -141,6 +142,7 @@ class OracleModel:
             else:
                 s.b1[h] = head.b1
         s.per_species = int(bool(getattr(m, "per_species", False)))
+        s.five_body = int(bool(getattr(m, "five_body", False)))
         self.s = s
 
 

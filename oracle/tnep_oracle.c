@@ -26,6 +26,8 @@
  *   q_nl     = sum_m A_nlm^2                     (l = 1..l_max)
  *   q4_n     = sum_{m1+m2+m3=0} (2 2 2; m1 m2 m3) At_{n2m1} At_{n2m2} At_{n2m3}
  *              with At the complex-basis (Condon-Shortley) sums
+ *   q5_n     = (sum_m A_n1m^2)^2  (optional five-body term: the only degree-4
+ *              rotation invariant of the l = 1 vector A_n1)
  *   U        = sum_mu w1_mu tanh(sum_nu W0_{mu nu} s_nu q_nu - b0_mu) - b1
  *
  * Every Y_lm is built at start-up as an explicit polynomial from the
@@ -69,6 +71,7 @@ typedef struct {
     int32_t per_species;         /* 1: one network per centre species: w0 [T][H][D], b0 and
                                     w1 [T][H], output biases b1_species[head] [T] */
     const double* b1_species[2];
+    int32_t five_body;           /* 1: the l = 1 five-body invariants q5_n (after q4) */
 } or_model;
 
 /* ------------------------------------------------------------------------ */
@@ -263,7 +266,7 @@ static void radial_functions(double r, double rc, int nmax, int K, const double*
 
 int or_descriptor_size(const or_model* m) {
     return (m->n_max_radial + 1) + (m->n_max_angular + 1) * m->l_max +
-           (m->four_body ? (m->n_max_angular + 1) : 0);
+           (m->four_body ? (m->n_max_angular + 1) : 0) + (m->five_body ? (m->n_max_angular + 1) : 0);
 }
 
 /* Map the real l=2 sums A[m+2] to complex Condon-Shortley sums At[m+2].
@@ -413,6 +416,16 @@ int or_atom_eval(const or_model* mdl, int head, int ti, int n, const double* vec
         int off4 = nR + 1 + lmax * (nA + 1);
         for (int k = 0; k <= nA; ++k) q[off4 + k] = four_body(&A[k][4], d4[k]);
     }
+    /* five-body: the one degree-4 rotation invariant of the l = 1 vector
+     * A_n1 = (A_n1m)_m, its squared norm squared: q5_n = (sum_m A_n1m^2)^2 */
+    const int off5 = nR + 1 + lmax * (nA + 1) + (mdl->four_body ? nA + 1 : 0);
+    if (mdl->five_body) {
+        for (int k = 0; k <= nA; ++k) {
+            double s = 0.0;
+            for (int m = -1; m <= 1; ++m) s += A[k][2 + m] * A[k][2 + m];
+            q[off5 + k] = s * s;
+        }
+    }
     if (q_out) memcpy(q_out, q, sizeof(double) * D);
 
     /* network (the centre species' own network when per_species is set) */
@@ -450,6 +463,14 @@ int or_atom_eval(const or_model* mdl, int head, int ti, int n, const double* vec
         int off4 = nR + 1 + lmax * (nA + 1);
         for (int k = 0; k <= nA; ++k)
             for (int mm = 0; mm < 5; ++mm) G[k][4 + mm] += dUdq[off4 + k] * d4[k][mm];
+    }
+    if (mdl->five_body) {
+        /* d q5 / d A_n1m = 2 (sum_m' A_n1m'^2) * 2 A_n1m */
+        for (int k = 0; k <= nA; ++k) {
+            double s = 0.0;
+            for (int m = -1; m <= 1; ++m) s += A[k][2 + m] * A[k][2 + m];
+            for (int m = -1; m <= 1; ++m) G[k][2 + m] += dUdq[off5 + k] * 4.0 * s * A[k][2 + m];
+        }
     }
     /* backward pass over neighbours: partial forces */
     for (int j = 0; j < n; ++j) {

@@ -248,6 +248,7 @@ class Model:
     q_scaler: np.ndarray  # [D]
     heads: List[Head]
     per_species: bool = False  # one network per centre species
+    five_body: bool = False  # l = 1 five-body invariants (after the four-body block)
 
     @property
     def n_species(self) -> int:
@@ -255,9 +256,10 @@ class Model:
 
     @property
     def dim(self) -> int:
-        """Descriptor length: radial, then l = 1..l_max angular blocks, then 4-body."""
+        """Descriptor length: radial, then l = 1..l_max angular blocks, then 4-body, then 5-body."""
         na = self.n_max_angular + 1
-        return self.n_max_radial + 1 + na * self.l_max + (na if self.four_body else 0)
+        return self.n_max_radial + 1 + na * self.l_max + (na if self.four_body else 0) + \
+            (na if self.five_body else 0)
 
     def to_json(self) -> dict:
         return {
@@ -269,7 +271,7 @@ class Model:
             "q_scaler": self.q_scaler.tolist(),
             "heads": [{"w0": np.asarray(h.w0).tolist(), "b0": np.asarray(h.b0).tolist(),
                        "w1": np.asarray(h.w1).tolist(), "b1": np.asarray(h.b1).tolist()} for h in self.heads],
-            "per_species": bool(self.per_species),
+            "per_species": bool(self.per_species), "five_body": bool(self.five_body),
         }
 
     @staticmethod
@@ -281,27 +283,27 @@ class Model:
             np.array(d["q_scaler"], np.float64),
             [Head(np.array(h["w0"], np.float64), np.array(h["b0"], np.float64), np.array(h["w1"], np.float64),
                   np.array(h["b1"], np.float64) if d.get("per_species") else float(h["b1"])) for h in d["heads"]],
-            bool(d.get("per_species", False)),
+            bool(d.get("per_species", False)), bool(d.get("five_body", False)),
         )
 
 
 def make_model(seed: int, kind: int, species, rc_radial: float, rc_angular: float, n_max_radial: int,
                n_max_angular: int, basis_radial: int, basis_angular: int, l_max: int, four_body: bool,
-               n_hidden: int, scale: float = 0.1, q_scaler=None) -> Model:
+               n_hidden: int, scale: float = 0.1, q_scaler=None, five_body: bool = False) -> Model:
     """All parameters ~ N(0, scale^2) from `seed`; q_scaler defaults to ones."""
     rng = np.random.default_rng(seed)
     T = len(species)
     cr = rng.normal(0.0, scale, (T, T, n_max_radial + 1, basis_radial + 1))
     ca = rng.normal(0.0, scale, (T, T, n_max_angular + 1, basis_angular + 1))
     na = n_max_angular + 1
-    D = n_max_radial + 1 + na * l_max + (na if four_body else 0)
+    D = n_max_radial + 1 + na * l_max + (na if four_body else 0) + (na if five_body else 0)
     heads = []
     for _ in range(2 if kind == KIND_POLARIZABILITY else 1):
         heads.append(Head(rng.normal(0.0, scale, (n_hidden, D)), rng.normal(0.0, scale, n_hidden),
                           rng.normal(0.0, scale, n_hidden), float(rng.normal(0.0, scale))))
     qs = np.ones(D) if q_scaler is None else np.asarray(q_scaler, np.float64)
     return Model(kind, tuple(species), rc_radial, rc_angular, n_max_radial, n_max_angular, basis_radial,
-                 basis_angular, l_max, four_body, n_hidden, cr, ca, qs, heads)
+                 basis_angular, l_max, four_body, n_hidden, cr, ca, qs, heads, five_body=five_body)
 
 
 # --------------------------------------------------------------------------
@@ -309,6 +311,7 @@ def make_model(seed: int, kind: int, species, rc_radial: float, rc_angular: floa
 
 WATER_DESCRIPTOR = dict(rc_radial=6.0, rc_angular=4.0, n_max_radial=4, n_max_angular=4, basis_radial=8,
                         basis_angular=8, l_max=4, four_body=True, n_hidden=30)
+WATER5_DESCRIPTOR = dict(WATER_DESCRIPTOR, five_body=True)
 PEROVSKITE_DESCRIPTOR = dict(rc_radial=7.0, rc_angular=5.0, n_max_radial=6, n_max_angular=4, basis_radial=8,
                              basis_angular=8, l_max=4, four_body=False, n_hidden=50)
 
@@ -326,14 +329,14 @@ def per_species_model(networks: List["Model"], species_network: List[int]) -> "M
     d = networks[0]
     return Model(d.kind, d.species, d.rc_radial, d.rc_angular, d.n_max_radial, d.n_max_angular, d.basis_radial,
                  d.basis_angular, d.l_max, d.four_body, d.n_hidden, d.c_radial, d.c_angular, d.q_scaler, heads,
-                 True)
+                 True, d.five_body)
 
 
 def with_descriptor_of(m: "Model", ref: "Model") -> "Model":
     """m's network heads on ref's descriptor coefficients and scaler."""
     return Model(m.kind, ref.species, ref.rc_radial, ref.rc_angular, ref.n_max_radial, ref.n_max_angular,
                  ref.basis_radial, ref.basis_angular, ref.l_max, ref.four_body, ref.n_hidden, ref.c_radial,
-                 ref.c_angular, ref.q_scaler, m.heads, m.per_species)
+                 ref.c_angular, ref.q_scaler, m.heads, m.per_species, ref.five_body)
 
 
 def pack_params(m: "Model") -> np.ndarray:
@@ -366,7 +369,7 @@ def unpack_params(base: "Model", z) -> "Model":
     assert o == z.size, "parameter vector of the wrong length"
     return Model(base.kind, base.species, base.rc_radial, base.rc_angular, base.n_max_radial, base.n_max_angular,
                  base.basis_radial, base.basis_angular, base.l_max, base.four_body, base.n_hidden, cr, ca,
-                 base.q_scaler, heads)
+                 base.q_scaler, heads, five_body=base.five_body)
 
 
 MODEL_SPECS = {
@@ -378,6 +381,9 @@ MODEL_SPECS = {
     "molecule_polarizability": (105, KIND_POLARIZABILITY, MOLECULE_SPECIES, WATER_DESCRIPTOR),
     "water_pes": (106, KIND_PES, WATER_SPECIES, WATER_DESCRIPTOR),
     "molecule_pes": (107, KIND_PES, MOLECULE_SPECIES, WATER_DESCRIPTOR),
+    "water_dipole_5b": (108, KIND_DIPOLE, WATER_SPECIES, WATER5_DESCRIPTOR),
+    "water_polarizability_5b": (109, KIND_POLARIZABILITY, WATER_SPECIES, WATER5_DESCRIPTOR),
+    "water_pes_5b": (110, KIND_PES, WATER_SPECIES, WATER5_DESCRIPTOR),
 }
 
 

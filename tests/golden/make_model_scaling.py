@@ -20,7 +20,7 @@ import synth  # noqa: E402
 
 
 def reference_frames(name):
-    if name == "water_dipole_small":
+    if name in ("water_dipole_small", "water_dipole_5b", "water_polarizability_5b", "water_pes_5b"):
         return synth.water_small(1), [0]
     if name in ("water_dipole", "water_polarizability", "water_pes"):
         pos, spc, cell = synth.water_large_reference()
