@@ -16,7 +16,8 @@
  * U_i is the output of a single-hidden-layer tanh network acting on the NEP
  * descriptor of atom i (Sec. 2.1, Eq. site-energy); the descriptor is the
  * NEP radial/angular form with Chebyshev radial functions, a cosine cutoff,
- * angular invariants l = 1..4 and the l = 2 four-body term.
+ * angular invariants l = 1..4, the l = 2 four-body term and optionally the
+ * l = 1 five-body term.
  *
  * Conventions
  *   - Every call returns TNEP_OK (0) or a negative error code; nothing is
@@ -118,8 +119,9 @@ typedef struct tnep_model tnep_model;
 /* ---- model ------------------------------------------------------------- */
 /* Parameters of one TNEP model, FP64, host memory (copied at creation).
  * Descriptor length D = (n_max_radial+1) + l_max*(n_max_angular+1)
- *                       + (four_body ? n_max_angular+1 : 0),
- * ordered [q^R_0..q^R_nR | l=1: q_{0,1}..q_{nA,1} | ... | l=l_max | q4_0..q4_nA].
+ *                       + (four_body ? n_max_angular+1 : 0) + (five_body ? n_max_angular+1 : 0),
+ * ordered [q^R_0..q^R_nR | l=1: q_{0,1}..q_{nA,1} | ... | l=l_max | q4_0..q4_nA | q5_0..q5_nA],
+ * q5_n = (sum_m A_n1m^2)^2 (the degree-4 invariant of the l = 1 sums).
  * Network (per head): U = sum_m w1[m] tanh(sum_n w0[m][n] q_scaler[n] q[n] - b0[m]) - b1. */
 typedef struct {
     int32_t kind;          /* TNEP_KIND_DIPOLE, TNEP_KIND_POLARIZABILITY or TNEP_KIND_PES */
@@ -144,6 +146,8 @@ typedef struct {
                                 [T][H], output biases b1_species[head] [T] (b1 unused); the
                                 hidden layer then always runs on the FP32 vector ALU      */
     const double* b1_species[2];
+    int32_t five_body;       /* 0 / 1: the l = 1 five-body invariants q5 (after q4; compiled for
+                                nR = nA = 4, KR = KA = 8 with the four-body term)            */
 } tnep_model_desc;
 
 /* ---- frames ------------------------------------------------------------ */

@@ -302,10 +302,11 @@ int tnep::stage_model(Ctx* c, const tnep_model_desc* d, std::vector<float>& h, M
     if (d->l_max != 4) return model_error(c, "only l_max = 4 is compiled");
     if (d->n_hidden < 1 || d->n_hidden > 128) return model_error(c, "n_hidden must be 1..128");
     Shape sh{d->n_max_radial + 1, d->n_max_angular + 1, d->basis_radial + 1, d->basis_angular + 1,
-             d->four_body ? 1 : 0, d->kind};
+             d->four_body ? 1 : 0, d->kind, d->five_body ? 1 : 0};
     if (!eval_shape_supported(sh))
-        return model_error(c, "descriptor shape (nR=%d, nA=%d, KR=%d, KA=%d, 4b=%d) is not compiled",
-                       d->n_max_radial, d->n_max_angular, d->basis_radial, d->basis_angular, d->four_body);
+        return model_error(c, "descriptor shape (nR=%d, nA=%d, KR=%d, KA=%d, 4b=%d, 5b=%d) is not compiled",
+                           d->n_max_radial, d->n_max_angular, d->basis_radial, d->basis_angular, d->four_body,
+                           d->five_body);
     if (!d->c_radial || !d->c_angular || !d->q_scaler || !d->w0[0] || !d->b0[0] || !d->w1[0])
         return model_error(c, "missing parameter arrays");
     const int heads = d->kind == TNEP_KIND_POLARIZABILITY ? 2 : 1;
@@ -316,7 +317,7 @@ int tnep::stage_model(Ctx* c, const tnep_model_desc* d, std::vector<float>& h, M
         if (!d->b1_species[hd]) return model_error(c, "per-species model needs b1_species");
     const int T = d->n_species, H = d->n_hidden;
     const size_t NS = per_species ? (size_t)T : 1;  // networks per head
-    const int D = sh.nr + 4 * sh.na + (sh.four_body ? sh.na : 0);
+    const int D = sh.nr + 4 * sh.na + (sh.four_body ? sh.na : 0) + (sh.five_body ? sh.na : 0);
     const size_t ncr = (size_t)T * T * sh.nr * sh.kr, nca = (size_t)T * T * sh.na * sh.ka;
 
     // host staging in FP32, fixed layout, appended to h at a 256-byte boundary

@@ -233,7 +233,7 @@ int run_eval(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
     char key[160];
     const Shape& sh = job.models[0]->shape;
     snprintf(key, sizeof(key), "%d.%d.%d.%d.%d.%d/T%d/H%d/n%d/m%d/loc%d/mlp%d", sh.nr, sh.na, sh.kr, sh.ka,
-             sh.four_body, sh.kind, job.models[0]->T, job.models[0]->H, size_class, job.n_models, fr.location,
+             sh.four_body + 2 * sh.five_body, sh.kind, job.models[0]->T, job.models[0]->H, size_class, job.n_models, fr.location,
              c->launch.mlp_mode);
     auto it = c->tuned.find(key);
     if (it == c->tuned.end()) {

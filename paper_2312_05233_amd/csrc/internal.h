@@ -69,7 +69,7 @@ struct DevModel {
 
 // Shape key of a compiled evaluation kernel.
 struct Shape {
-    int nr, na, kr, ka, four_body, kind;
+    int nr, na, kr, ka, four_body, kind, five_body;
 };
 
 // Neighbour lists of a batch.

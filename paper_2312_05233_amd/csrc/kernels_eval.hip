@@ -237,10 +237,11 @@ __device__ __forceinline__ constexpr float parity_sign(int c) {
 // wave-uniform and read with scalar loads.  MODE selects the hidden layer:
 // FP32 vector ALU (no LDS) or one of the matrix-core variants (LDS tile per
 // wavefront).  Padding lanes run with empty neighbour lists and store nothing.
-template <int NR, int NA, int KR, int KA, bool FOURB, int KIND, int MODE>
+template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE>
 __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, double* __restrict__ per_atom,
                                                  PesOut pes) {
-    constexpr int D = NR + 4 * NA + (FOURB ? NA : 0);
+    constexpr bool FOURB = (MB & 1) != 0, FIVEB = (MB & 2) != 0;
+    constexpr int D = NR + 4 * NA + (FOURB ? NA : 0) + (FIVEB ? NA : 0);
     constexpr int NT = KIND == 1 ? 3 : 9;  // accumulated tensor: mu, or the virial-like W
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int T = nl.T;
@@ -342,6 +343,15 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             qs[NR + 4 * NA + n] = four_body_l2(&A[n][3], d4);
         }
     }
+    // five-body: the squared l = 1 invariant, q5_n = (sum_m A_n1m^2)^2
+    constexpr int kOff5 = NR + 4 * NA + (FOURB ? NA : 0);
+    if constexpr (FIVEB) {
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            const float s1 = A[n][0] * A[n][0] + A[n][1] * A[n][1] + A[n][2] * A[n][2];
+            qs[kOff5 + n] = s1 * s1;
+        }
+    }
 #pragma unroll
     for (int v = 0; v < D; ++v) qs[v] *= m.scaler[v];
 
@@ -392,12 +402,18 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     for (int n = 0; n < NA; ++n) {
         float d4[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         if constexpr (FOURB) four_body_l2(&A[n][3], d4);
+        // d q5_n / d A_n1m = 4 (sum_m' A_n1m'^2) A_n1m, folded into the l = 1 factor
+        float w5 = 0.f;
+        if constexpr (FIVEB) w5 = 4.f * dq[kOff5 + n] * (A[n][0] * A[n][0] + A[n][1] * A[n][1] + A[n][2] * A[n][2]);
 #pragma unroll
         for (int c = 0; c < kLM; ++c) {
             const int l = c < 3 ? 1 : (c < 8 ? 2 : (c < 15 ? 3 : 4));
             float g = 2.f * dq[NR + (l - 1) * NA + n] * A[n][c];
             if constexpr (FOURB) {
                 if (l == 2) g += dq[NR + 4 * NA + n] * d4[c - 3];
+            }
+            if constexpr (FIVEB) {
+                if (l == 1) g += w5 * A[n][c];
             }
             A[n][c] = g;
         }
@@ -633,7 +649,7 @@ __global__ void __launch_bounds__(256) k_com_shift(const int64_t* __restrict__ o
 // j's coefficients c_{t_j t_k}; angular part from G_j, whose stored sign
 // (-1)^l turns Y_lm(-u) and its gradient back into functions of u.  Every
 // term is summed in the lane's fixed list order: no atomics.
-template <int NR, int NA, int KR, int KA, bool FOURB>
+template <int NR, int NA, int KR, int KA, int MB>
 __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl, PesOut pes,
                                                     const double* __restrict__ per_atom,
                                                     double* __restrict__ forces, double* __restrict__ energies) {
@@ -748,68 +764,71 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
     if (energies) energies[a] = per_atom[10 * (int64_t)a];
 }
 
-template <int NR, int NA, int KR, int KA, bool FOURB, int KIND, int MODE>
+template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE>
 hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom, const PesOut& pes, int block,
                     hipStream_t s) {
-    constexpr int D = NR + 4 * NA + (FOURB ? NA : 0);
+    constexpr int D = NR + 4 * NA + ((MB & 1) ? NA : 0) + ((MB & 2) ? NA : 0);
     if constexpr (MODE == TNEP_MLP_FP32_VALU) {
         const int bs = (block == 64 || block == 128) ? block : 256;
         const unsigned grid = (unsigned)((nl.n_pad + bs - 1) / bs);
-        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom, pes);
+        k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom, pes);
     } else {
         // two wavefronts per work-group keep the LDS tiles at <= 2 x 27 KB
         const unsigned grid = (unsigned)((nl.n_pad + 127) / 128);
         const size_t lds = sizeof(float) * 2 * (size_t)mlp_lds_floats(D, m.n_hidden);
-        k_eval<NR, NA, KR, KA, FOURB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom, pes);
+        k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom, pes);
     }
     return hipGetLastError();
 }
 
-template <int NR, int NA, int KR, int KA, bool FOURB, int KIND>
+template <int NR, int NA, int KR, int KA, int MB, int KIND>
 hipError_t launch_mode(int mode, bool matrix, const DevModel& m, const NeighborLists& nl, double* per_atom,
                        const PesOut& pes, int block, hipStream_t s) {
     if (matrix) {
         if (mode == TNEP_MLP_FP32_MFMA)
-            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, pes, block, s);
+            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, pes, block, s);
         if (mode == TNEP_MLP_BF16_MFMA)
-            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, pes, block, s);
+            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, pes, block, s);
         if (mode == TNEP_MLP_BF16X3_MFMA)
-            return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, pes, block, s);
+            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, pes, block, s);
     }
-    return launch_t<NR, NA, KR, KA, FOURB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
+    return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
 }
 
 // Potential-energy models always use the FP32 vector hidden layer.
-template <int NR, int NA, int KR, int KA, bool FOURB, bool MX>
+template <int NR, int NA, int KR, int KA, int MB, bool MX>
 hipError_t dispatch(const Shape& shape, int mode, bool matrix, const DevModel& m, const NeighborLists& nl,
                     double* per_atom, const PesOut& pes, int block, hipStream_t s) {
     if (shape.kind == 3)
-        return launch_t<NR, NA, KR, KA, FOURB, 3, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
+        return launch_t<NR, NA, KR, KA, MB, 3, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
     if constexpr (MX) {
         if (shape.kind == 1)
-            return launch_mode<NR, NA, KR, KA, FOURB, 1>(mode, matrix, m, nl, per_atom, pes, block, s);
-        return launch_mode<NR, NA, KR, KA, FOURB, 2>(mode, matrix, m, nl, per_atom, pes, block, s);
+            return launch_mode<NR, NA, KR, KA, MB, 1>(mode, matrix, m, nl, per_atom, pes, block, s);
+        return launch_mode<NR, NA, KR, KA, MB, 2>(mode, matrix, m, nl, per_atom, pes, block, s);
     } else {
         if (shape.kind == 1)
-            return launch_t<NR, NA, KR, KA, FOURB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
-        return launch_t<NR, NA, KR, KA, FOURB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
+            return launch_t<NR, NA, KR, KA, MB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
+        return launch_t<NR, NA, KR, KA, MB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
     }
 }
 
 }  // namespace
 
 // Compiled descriptor shapes (radial functions, angular functions, radial and
-// angular Chebyshev terms, four-body) and whether the matrix-core hidden
-// layers are compiled for them.
-#define TNEP_SHAPES(X)         \
-    X(5, 5, 9, 9, true, true)   \
-    X(5, 5, 9, 9, false, false) \
-    X(7, 5, 9, 9, false, true)  \
-    X(7, 5, 9, 9, true, false)
+// angular Chebyshev terms, many-body terms: 1 four-body, 2 five-body) and
+// whether the matrix-core hidden layers are compiled for them.
+#define TNEP_SHAPES(X)      \
+    X(5, 5, 9, 9, 1, true)  \
+    X(5, 5, 9, 9, 0, false) \
+    X(7, 5, 9, 9, 0, true)  \
+    X(7, 5, 9, 9, 1, false) \
+    X(5, 5, 9, 9, 3, false)
+
+static int shape_bodies(const Shape& s) { return (s.four_body ? 1 : 0) | (s.five_body ? 2 : 0); }
 
 bool eval_shape_supported(const Shape& s) {
 #define X(NR_, NA_, KR_, KA_, FB_, MX_) \
-    if (s.nr == NR_ && s.na == NA_ && s.kr == KR_ && s.ka == KA_ && (bool)s.four_body == FB_) return true;
+    if (s.nr == NR_ && s.na == NA_ && s.kr == KR_ && s.ka == KA_ && shape_bodies(s) == FB_) return true;
     TNEP_SHAPES(X)
 #undef X
     return false;
@@ -818,7 +837,7 @@ bool eval_shape_supported(const Shape& s) {
 bool eval_matrix_supported(const Shape& s, int n_hidden) {
     if (n_hidden > 64) return false;
 #define X(NR_, NA_, KR_, KA_, FB_, MX_) \
-    if (s.nr == NR_ && s.na == NA_ && s.kr == KR_ && s.ka == KA_ && (bool)s.four_body == FB_) return MX_;
+    if (s.nr == NR_ && s.na == NA_ && s.kr == KR_ && s.ka == KA_ && shape_bodies(s) == FB_) return MX_;
     TNEP_SHAPES(X)
 #undef X
     return false;
@@ -832,7 +851,7 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
         cfg.mlp_mode != TNEP_MLP_FP32_VALU && eval_matrix_supported(shape, m.n_hidden) && m.sp_w0 == 0;
 #define X(NR_, NA_, KR_, KA_, FB_, MX_)                                                             \
     if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                \
-        (bool)shape.four_body == FB_)                                                             \
+        shape_bodies(shape) == FB_)                                                             \
         return dispatch<NR_, NA_, KR_, KA_, FB_, MX_>(shape, cfg.mlp_mode, matrix, m, nl, per_atom, pes,      \
                                                       cfg.atoms_per_block, s);
     TNEP_SHAPES(X)
@@ -861,7 +880,7 @@ hipError_t launch_pes_forces(const Shape& shape, const DevModel& m, const Neighb
     const unsigned grid = (unsigned)((nl.n_pad + bs - 1) / bs);
 #define X(NR_, NA_, KR_, KA_, FB_, MX_)                                                                 \
     if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                    \
-        (bool)shape.four_body == FB_) {                                                               \
+        shape_bodies(shape) == FB_) {                                                               \
         k_pes_forces<NR_, NA_, KR_, KA_, FB_><<<grid, bs, 0, s>>>(m, nl, pes, per_atom, forces, energies); \
         return hipGetLastError();                                                                     \
     }

@@ -83,7 +83,7 @@ ParamLayout layout_of(const tnep_model_desc* d) {
     const int T = d->n_species;
     const int nr = d->n_max_radial + 1, na = d->n_max_angular + 1, kr = d->basis_radial + 1,
               ka = d->basis_angular + 1;
-    const int D = nr + d->l_max * na + (d->four_body ? na : 0);
+    const int D = nr + d->l_max * na + (d->four_body ? na : 0) + (d->five_body ? na : 0);
     L.ncr = (size_t)T * T * nr * kr;
     L.nca = (size_t)T * T * na * ka;
     L.nw0 = (size_t)d->n_hidden * D;

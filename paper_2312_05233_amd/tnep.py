@@ -59,7 +59,7 @@ class ModelDesc(C.Structure):
         ("basis_angular", C.c_int32), ("l_max", C.c_int32), ("four_body", C.c_int32), ("n_hidden", C.c_int32),
         ("c_radial", P(C.c_double)), ("c_angular", P(C.c_double)), ("q_scaler", P(C.c_double)),
         ("w0", P(C.c_double) * 2), ("b0", P(C.c_double) * 2), ("w1", P(C.c_double) * 2), ("b1", C.c_double * 2),
-        ("per_species", C.c_int32), ("b1_species", P(C.c_double) * 2),
+        ("per_species", C.c_int32), ("b1_species", P(C.c_double) * 2), ("five_body", C.c_int32),
     ]
 
 
@@ -257,6 +257,7 @@ def model_desc(m):
     d.c_radial, d.c_angular, d.q_scaler = arr(m.c_radial), arr(m.c_angular), arr(m.q_scaler)
     per_species = bool(getattr(m, "per_species", False))
     d.per_species = int(per_species)
+    d.five_body = int(bool(getattr(m, "five_body", False)))
     for k, head in enumerate(m.heads):
         d.w0[k], d.b0[k], d.w1[k] = arr(head.w0), arr(head.b0), arr(head.w1)
         if per_species:
