@@ -266,39 +266,47 @@ __global__ void __launch_bounds__(64) k_sort_place(const int32_t* __restrict__ b
 // Minimum image along one axis; Linv = 1/L on periodic axes, 0 otherwise.
 __device__ __forceinline__ double min_image(double d, double L, double Linv) { return d - L * rint(d * Linv); }
 
-// Four entries buffered in registers, written as one 64-byte group.
-// A group row (4 entries x 64 lanes) is 256 float4.
-struct Stream {
-    float4 b0, b1, b2, b3;
-    int n;
-    __device__ __forceinline__ void push(const float4& e, float4* base, int cap) {
-        b0 = b1;
-        b1 = b2;
-        b2 = b3;
-        b3 = e;
-        ++n;
-        if ((n & 3) == 0 && n <= cap) {
-            float4* g = base + (int64_t)((n - 4) >> 2) * 256;
-            g[0] = b0;
-            g[1] = b1;
-            g[2] = b2;
-            g[3] = b3;
+// The entries of one (atom, neighbour species) pass: angular segment (r <
+// r_c^A) and radial-only segment.  Each lane stages four entries per segment
+// in LDS and writes them as one 64-byte group; staging in LDS instead of
+// registers keeps a push to one store and one address, where a register
+// buffer costs a shift of four entries per push and copies of both buffers at
+// every divergent branch.  Slot (segment s, entry k) of a lane is
+// stage[(4 s + k) * stride] (consecutive lanes at consecutive 16-byte words).
+struct PairSink {
+    float4* stage;
+    int stride;
+    float4* ga;
+    float4* gr;
+    int capA, capR;
+    int na, nr;
+    __device__ __forceinline__ void push(const float4& e, bool ang) {
+        const int n = ang ? na : nr;
+        const int s4 = ang ? 0 : 4;
+        stage[(s4 + (n & 3)) * stride] = e;
+        const int m = n + 1;
+        if (ang)
+            na = m;
+        else
+            nr = m;
+        if ((m & 3) == 0 && m <= (ang ? capA : capR)) {
+            float4* g = (ang ? ga : gr) + (int64_t)((m - 4) >> 2) * 256;
+            const float4* src = stage + s4 * stride;
+            g[0] = src[0];
+            g[1] = src[stride];
+            g[2] = src[2 * stride];
+            g[3] = src[3 * stride];
         }
     }
-    __device__ __forceinline__ void flush(float4* base, int cap) {
+    __device__ __forceinline__ void flush_one(int n, int cap, float4* base, const float4* src) {
         const int k = n & 3;
         if (k == 0 || n > cap) return;
         float4* g = base + (int64_t)((n - k) >> 2) * 256;
-        if (k == 3) {
-            g[0] = b1;
-            g[1] = b2;
-            g[2] = b3;
-        } else if (k == 2) {
-            g[0] = b2;
-            g[1] = b3;
-        } else {
-            g[0] = b3;
-        }
+        for (int i = 0; i < k; ++i) g[i] = src[i * stride];
+    }
+    __device__ __forceinline__ void flush() {
+        flush_one(na, capA, ga, stage);
+        flush_one(nr, capR, gr, stage + 4 * stride);
     }
 };
 
@@ -317,6 +325,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                                                       const double4* __restrict__ bucket_pos, float rc_radial,
                                                       float rc_angular, NeighborLists nl, CandLists cl,
                                                       int32_t* __restrict__ flags) {
+    extern __shared__ float4 nb_stage[];  // 8 entries per lane (PairSink)
+    float4* stage = nb_stage + threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nl.n_pad) return;
     const int T = nl.T;
@@ -365,12 +375,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     }
     bool overlap = false;
     for (int t = 0; t < T; ++t) {
-        Stream sa, sr;
-        sa.n = 0;
-        sr.n = 0;
-        float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
-        float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
-        const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
+        PairSink ps{stage, (int)blockDim.x,
+                    lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
+                    lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
+                    nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0};
         int n_cand = 0;
         int32_t* cand = REF ? cl.idx + ((fi.cl_base + (a - fi.atom_begin)) * T + t) * cl.cap : nullptr;
         const int n_visit = fi.mode == 1 ? 27 : 1;
@@ -411,11 +419,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                     }
                     if (r2 >= rc2r) continue;
                     if (r2 < 1e-8) overlap = true;
-                    const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
-                    if (r2 < rc2a)
-                        sa.push(ent, ga, capA);
-                    else
-                        sr.push(ent, gr, capR);
+                    ps.push(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)), r2 < rc2a);
                 }
             }
         }
@@ -423,12 +427,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
             cl.count[(fi.cl_base + (a - fi.atom_begin)) * T + t] = n_cand;
             if (n_cand > cl.cap) atomicMax(&flags[kFlagCapCand], n_cand);
         }
-        sa.flush(ga, capA);
-        sr.flush(gr, capR);
-        nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(sa.n, capA);
-        nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(sr.n, capR);
-        if (sa.n > capA) atomicMax(&flags[kFlagCapAng + t], sa.n);
-        if (sr.n > capR) atomicMax(&flags[kFlagCapRad + t], sr.n);
+        ps.flush();
+        nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(ps.na, ps.capA);
+        nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(ps.nr, ps.capR);
+        if (ps.na > ps.capA) atomicMax(&flags[kFlagCapAng + t], ps.na);
+        if (ps.nr > ps.capR) atomicMax(&flags[kFlagCapRad + t], ps.nr);
     }
     if (overlap) {
         atomicOr(&flags[kFlagError], kErrOverlap);
@@ -446,6 +449,8 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
                                                              const int32_t* __restrict__ slot_of, float rc_radial,
                                                              float rc_angular, NeighborLists nl, CandLists cl,
                                                              int32_t* __restrict__ flags) {
+    extern __shared__ float4 nb_stage[];  // 8 entries per lane (PairSink)
+    float4* stage = nb_stage + threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nl.n_pad) return;
     const int T = nl.T;
@@ -466,12 +471,10 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
         atomicOr(&flags[kFlagReuse], 1);
     bool overlap = false;
     for (int t = 0; t < T; ++t) {
-        Stream sa, sr;
-        sa.n = 0;
-        sr.n = 0;
-        float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
-        float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
-        const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
+        PairSink ps{stage, (int)blockDim.x,
+                    lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
+                    lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
+                    nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0};
         const int64_t list = (fi.cl_base + il) * T + t;
         const int n = min(cl.count[list], cl.cap);
         const int4* idx4 = reinterpret_cast<const int4*>(cl.idx + list * cl.cap);
@@ -497,18 +500,14 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
                 if (r2 < 1e-8) overlap = true;
                 const int js = slot_of[fi.atom_begin + jl[u]];
                 const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(js));
-                if (r2 < rc2a)
-                    sa.push(ent, ga, capA);
-                else
-                    sr.push(ent, gr, capR);
+                ps.push(ent, r2 < rc2a);
             }
         }
-        sa.flush(ga, capA);
-        sr.flush(gr, capR);
-        nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(sa.n, capA);
-        nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(sr.n, capR);
-        if (sa.n > capA) atomicMax(&flags[kFlagCapAng + t], sa.n);
-        if (sr.n > capR) atomicMax(&flags[kFlagCapRad + t], sr.n);
+        ps.flush();
+        nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(ps.na, ps.capA);
+        nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(ps.nr, ps.capR);
+        if (ps.na > ps.capA) atomicMax(&flags[kFlagCapAng + t], ps.na);
+        if (ps.nr > ps.capR) atomicMax(&flags[kFlagCapRad + t], ps.nr);
     }
     if (overlap) {
         atomicOr(&flags[kFlagError], kErrOverlap);
@@ -533,6 +532,8 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                                                           const double4* __restrict__ bucket_pos, float rc_radial,
                                                           float rc_angular, NeighborLists nl,
                                                           int32_t* __restrict__ flags) {
+    extern __shared__ float4 nb_stage[];  // 8 entries per lane (PairSink)
+    float4* stage = nb_stage + threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nl.n_pad) return;
     const int T = nl.T;
@@ -566,12 +567,10 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
     }
     bool overlap = false;
     for (int t = 0; t < T; ++t) {
-        Stream sa, sr;
-        sa.n = 0;
-        sr.n = 0;
-        float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
-        float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
-        const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
+        PairSink ps{stage, (int)blockDim.x,
+                    lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
+                    lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
+                    nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0};
         const int n_visit = mode == 1 ? 27 : 1;
         for (int vb = 0; vb < n_visit; ++vb) {
             int bucket = cell_base * T + t;
@@ -606,18 +605,14 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                 if (r2 >= rc2r) continue;
                 if (r2 < 1e-8) overlap = true;
                 const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
-                if (r2 < rc2a)
-                    sa.push(ent, ga, capA);
-                else
-                    sr.push(ent, gr, capR);
+                ps.push(ent, r2 < rc2a);
             }
         }
-        sa.flush(ga, capA);
-        sr.flush(gr, capR);
-        nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(sa.n, capA);
-        nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(sr.n, capR);
-        if (sa.n > capA) atomicMax(&flags[kFlagCapAng + t], sa.n);
-        if (sr.n > capR) atomicMax(&flags[kFlagCapRad + t], sr.n);
+        ps.flush();
+        nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(ps.na, ps.capA);
+        nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(ps.nr, ps.capR);
+        if (ps.na > ps.capA) atomicMax(&flags[kFlagCapAng + t], ps.na);
+        if (ps.nr > ps.capR) atomicMax(&flags[kFlagCapRad + t], ps.nr);
     }
     if (overlap) {
         atomicOr(&flags[kFlagError], kErrOverlap);
@@ -681,18 +676,19 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                                               w.bucket_atoms, nl.meta);
     k_sort_place<<<cap_buckets, 64, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
                                                                    w.perm, w.slot_of, pos, w.bucket_pos, nl.meta, T);
-    k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+    const size_t stage_bytes = sizeof(float4) * 8 * nb;
+    k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                               w.key_of, w.bucket_start, w.bucket_pos, rc_radial,
                                                               rc_angular, nl, cl, d_flags);
     if (references)
-        k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+        k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                  w.key_of, w.bucket_start, w.bucket_pos, rc_radial,
                                                                  rc_angular, nl, cl, d_flags);
     if (triclinic)
-        k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
+        k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
                                                                w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
     if (followers)
-        k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, 0, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+        k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                   rc_radial, rc_angular, nl, cl, d_flags);
     return hipGetLastError();
 }
