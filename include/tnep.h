@@ -204,6 +204,27 @@ int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* desc, tnep_model** o
 /* Free a model (waits for the device first); valid before or after its
  * context is destroyed. */
 void tnep_model_free(tnep_model* model);
+/* Model files: a plain-text form of tnep_model_desc (Sec. 2.1: the descriptor
+ * hyperparameters and coefficients, the descriptor scaler and the networks),
+ * FP64 values written with 17 significant digits (exact round trip).  Layout,
+ * one keyword per item, '#' comments allowed:
+ *   tnep_model 1 / kind dipole|polarizability|pes / n_species T / rc rR rA /
+ *   n_max nR nA / basis KR KA / l_max 4 / four_body 0|1 / five_body 0|1 /
+ *   n_hidden H / per_species 0|1 / c_radial ... / c_angular ... / q_scaler ... /
+ *   head 0 w0 ... b0 ... w1 ... b1 ... [head 1 ... for polarizability] / end
+ * with each array's values in the order of tnep_model_desc.
+ * tnep_model_save: writes desc (host arrays) to path; no context or GPU needed;
+ *   TNEP_E_INVALID if the file cannot be written, TNEP_E_MODEL for a bad
+ *   desc; the message is tnep_last_error(NULL).
+ * tnep_model_load: parses path and creates the model as tnep_model_create
+ *   does; TNEP_E_INVALID if the file cannot be read, TNEP_E_MODEL (with the
+ *   line number in tnep_last_error) if it is malformed or the shape is not
+ *   supported. */
+int tnep_model_save(const tnep_model_desc* desc, const char* path);
+int tnep_model_load(tnep_ctx* ctx, const char* path, tnep_model** out);
+/* Kind (TNEP_KIND_*), species count and descriptor length D of a model;
+ * any output pointer may be NULL.  TNEP_E_INVALID for a NULL model. */
+int tnep_model_info(const tnep_model* model, int32_t* kind, int32_t* n_species, int32_t* descriptor_length);
 
 /* ---- evaluation -------------------------------------------------------- */
 /* Dipole of every frame (Sec. 2.2, Eq. mu).  mu_out: [n_frames][3] FP64.

@@ -21,6 +21,8 @@ using namespace tnep;
 
 static thread_local std::string g_create_error;
 
+void tnep::set_create_error(const std::string& msg) { g_create_error = msg; }
+
 int tnep::Ctx::fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -503,6 +505,16 @@ extern "C" int tnep_model_create(tnep_ctx* ctx, const tnep_model_desc* d, tnep_m
     }
     bind_model(*m, (const float*)m->dbuf, lay);
     *out = reinterpret_cast<tnep_model*>(m);
+    return TNEP_OK;
+}
+
+extern "C" int tnep_model_info(const tnep_model* model, int32_t* kind, int32_t* n_species,
+                               int32_t* descriptor_length) {
+    if (!model) return TNEP_E_INVALID;
+    const Model* m = reinterpret_cast<const Model*>(model);
+    if (kind) *kind = m->kind;
+    if (n_species) *n_species = m->T;
+    if (descriptor_length) *descriptor_length = m->D;
     return TNEP_OK;
 }
 

@@ -168,6 +168,8 @@ struct FrameGeom {
 };
 
 int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc_radial, FrameGeom& g);
+// Message for tnep_last_error(NULL) (calls without a context, on this thread).
+void set_create_error(const std::string& msg);
 int run_eval(Ctx* c, const tnep_frames& frames, const EvalJob& job);
 void server_shutdown(Ctx* c);
 void server_graph_counts(const Ctx* c, uint64_t& captures, uint64_t& launches);  // adds the slots' counts

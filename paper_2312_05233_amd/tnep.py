@@ -40,7 +40,8 @@ EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_
             "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts", "tnep_eval_pes",
             "tnep_raman_map", "tnep_acf_stream_create", "tnep_acf_stream_push", "tnep_acf_stream_end_run",
             "tnep_acf_stream_spectrum", "tnep_acf_stream_raman_map", "tnep_acf_stream_free",
-            "tnep_ctx_reuse_fallbacks", "tnep_eval_dipole_charged", "tnep_population_loss"]
+            "tnep_ctx_reuse_fallbacks", "tnep_eval_dipole_charged", "tnep_population_loss", "tnep_model_save",
+            "tnep_model_load", "tnep_model_info"]
 
 
 class TnepError(RuntimeError):
@@ -105,6 +106,9 @@ def _load():
     lib.tnep_eval_dipole_polarizability.argtypes = [vp, vp, vp, P(FramesDesc), vp, vp]
     lib.tnep_eval_pes.argtypes = [vp, vp, P(FramesDesc), vp, vp, vp, vp]
     lib.tnep_eval_dipole_charged.argtypes = [vp, vp, P(FramesDesc), vp, vp, C.c_double, vp, vp]
+    lib.tnep_model_save.argtypes = [P(ModelDesc), C.c_char_p]
+    lib.tnep_model_load.argtypes = [vp, C.c_char_p, P(vp)]
+    lib.tnep_model_info.argtypes = [vp, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
     lib.tnep_population_loss.argtypes = [vp, P(ModelDesc), C.c_int32, vp, P(FramesDesc), vp, C.c_double, C.c_double,
                                          vp, vp]
     lib.tnep_raman_map.argtypes = [vp, P(SpectrumArgs), C.c_int32, vp, vp, vp, vp]
@@ -225,6 +229,19 @@ class Model:
         ctx.check(lib.tnep_model_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
 
+    @classmethod
+    def load(cls, ctx: Context, path):
+        """tnep_model_load: a model from a model file."""
+        self = cls.__new__(cls)
+        self.ctx, self.h = ctx, None
+        h = C.c_void_p()
+        ctx.check(lib.tnep_model_load(ctx.h, os.fsencode(path), C.byref(h)))
+        self.h = h
+        kind = C.c_int32()
+        ctx.check(lib.tnep_model_info(h, C.byref(kind), None, None))
+        self.kind = kind.value
+        return self
+
     def close(self):
         if self.h:
             lib.tnep_model_free(self.h)
@@ -265,6 +282,15 @@ def model_desc(m):
         else:
             d.b1[k] = head.b1
     return d, keep
+
+
+def tnep_model_save(m, path):
+    """Write a model object (tnep_model_desc fields, e.g. synth.Model) as a model file."""
+    d, keep = model_desc(m)
+    r = lib.tnep_model_save(C.byref(d), os.fsencode(path))
+    del keep
+    if r != TNEP_OK:
+        raise TnepError(r, (lib.tnep_last_error(None) or b"").decode())
 
 
 def frames_desc(frames, location=None):
