@@ -426,7 +426,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             // host FrameInfo and batch sizes per batch, alive until the sync below
             struct BatchHost {
                 std::vector<FrameInfo> fi;
-                int32_t sizes[3];
+                int32_t sizes[4];
             };
             std::vector<std::unique_ptr<BatchHost>> keep;
             int f0 = 0;
@@ -510,6 +510,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 bh.sizes[0] = (int32_t)na;
                 bh.sizes[1] = nf;
                 bh.sizes[2] = n_cells;
+                bh.sizes[3] = (int32_t)std::min<int64_t>(a0, INT32_MAX);
                 HIP_CHECK_RET(c, hipMemcpyAsync((int32_t*)c->tile_base.p + kMetaNAtoms, bh.sizes, sizeof(bh.sizes),
                                                 hipMemcpyHostToDevice, c->stream));
                 HIP_CHECK_RET(c, hipMemcpyAsync(c->frames.p, fi.data(), sizeof(FrameInfo) * nf,
@@ -665,11 +666,15 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 const int code = (fl[kFlagError] & kErrNonFinite) ? TNEP_E_NONFINITE
                                  : (fl[kFlagError] & kErrSpecies) ? TNEP_E_SPECIES
                                                                   : TNEP_E_OVERLAP;
-                return c->fail(code, "invalid input (%s) near batch-local atom %d",
+                // the first offending atom (index in the call) and its frame
+                const int64_t bad = fl[kFlagBadAtom];
+                int bad_frame = 0;
+                while (bad_frame + 1 < F && meta.offs[bad_frame + 1] <= bad) ++bad_frame;
+                return c->fail(code, "invalid input (%s) at atom %lld of frame %d",
                                code == TNEP_E_NONFINITE ? "non-finite position"
                                : code == TNEP_E_SPECIES ? "species out of range"
                                                         : "atoms closer than 1e-4 A",
-                               fl[kFlagBadAtom]);
+                               (long long)(bad - meta.offs[bad_frame]), bad_frame);
             }
             bool grow = false;
             for (int t = 0; t < T; ++t) {

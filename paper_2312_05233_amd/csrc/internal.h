@@ -96,6 +96,7 @@ enum Meta {
     kMetaNAtoms = 48,
     kMetaNFrames = 49,
     kMetaNCells = 50,
+    kMetaAtomBase = 51,  // index of the batch's first atom in the call (saturated at INT32_MAX)
     kMetaInts = 56
 };
 

@@ -41,6 +41,12 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// Index of batch atom a in the whole call (for error reports), saturated.
+__device__ __forceinline__ int call_atom(const int32_t* meta, int64_t a) {
+    const int64_t g = (int64_t)meta[kMetaAtomBase] + a;
+    return g > INT32_MAX ? INT32_MAX : (int)g;
+}
+
 __device__ __forceinline__ int cell_coord(double p, double L, int nc) {
     const double s = p - L * floor(p / L);
     const int c = (int)(s * (double)nc / L);
@@ -62,7 +68,7 @@ __global__ void k_bin(const FrameInfo* __restrict__ frames, const int32_t* __res
     if (t < 0 || t >= T) err |= kErrSpecies;
     if (err) {
         atomicOr(&flags[kFlagError], err);
-        atomicMin(&flags[kFlagBadAtom], (int)a);
+        atomicMin(&flags[kFlagBadAtom], call_atom(meta, a));
         key_of[a] = -1;
         return;
     }
@@ -435,7 +441,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     }
     if (overlap) {
         atomicOr(&flags[kFlagError], kErrOverlap);
-        atomicMin(&flags[kFlagBadAtom], a);
+        atomicMin(&flags[kFlagBadAtom], call_atom(nl.meta, a));
     }
 }
 
@@ -511,7 +517,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
     }
     if (overlap) {
         atomicOr(&flags[kFlagError], kErrOverlap);
-        atomicMin(&flags[kFlagBadAtom], a);
+        atomicMin(&flags[kFlagBadAtom], call_atom(nl.meta, a));
     }
     return;
 }
@@ -616,7 +622,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
     }
     if (overlap) {
         atomicOr(&flags[kFlagError], kErrOverlap);
-        atomicMin(&flags[kFlagBadAtom], a);
+        atomicMin(&flags[kFlagBadAtom], call_atom(nl.meta, a));
     }
 }
 

@@ -170,6 +170,33 @@ def test_error_codes(gpu_lib, ctx):
     _check(gpu_lib.tnep_eval_dipole(ctx, mdl, fr), m, fr, "after errors")
 
 
+@pytest.mark.parametrize("batch_atoms", [0, 400])
+def test_error_names_frame_and_atom(gpu_lib, batch_atoms):
+    """The first offending atom is reported by frame and atom index within it,
+    also when the call is split into several launch batches."""
+    c = gpu_lib.Context(0)
+    if batch_atoms:
+        c.set_option(gpu_lib.OPT_MAX_BATCH_ATOMS, batch_atoms)
+    mdl = gpu_lib.Model(c, synth.model("water_dipole_small"))
+    fr = synth.water_small(5, seed=33)
+    o = fr.offsets
+    cases = [("nan", 3, 17, -5), ("species", 4, 0, -2), ("overlap", 2, 5, -4)]
+    for label, f, i, code in cases:
+        bad = synth.Frames(fr.offsets, fr.positions.copy(), fr.species.copy(), fr.cells, fr.pbc)
+        a = o[f] + i
+        if label == "nan":
+            bad.positions[a, 2] = np.nan
+        elif label == "species":
+            bad.species[a] = 9
+        else:
+            bad.positions[a + 4] = bad.positions[a]
+        with pytest.raises(gpu_lib.TnepError) as e:
+            gpu_lib.tnep_eval_dipole(c, mdl, bad)
+        assert e.value.code == code, label
+        assert f"at atom {i} of frame {f}" in str(e.value), (label, str(e.value))
+    c.close()
+
+
 # ---------------------------------------------------------------------------
 # spectra
 
