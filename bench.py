@@ -294,6 +294,89 @@ def bench_population(args):
                          "kind": "oracle", "sample": "4 individuals x 160 structures (51,200 atoms)"}}), flush=True)
 
 
+def bench_variants(args):
+    """Model and cell variants on the water trajectory (340 frames x 12,288
+    atoms, dipole + polarizability in one call): the shared four-body models
+    (reference), per-species networks, the five-body term, and the same
+    lattice described by a skewed basis, and a rotated copy (a triclinic cell in
+    every basis); then charged molecules (8192
+    ragged molecules, mu_r + Q e r_COM) against the plain dipole call.  Each
+    with its largest frame error against the FP64 oracle on a sample."""
+    import torch
+
+    import oracle
+    from paper_2312_05233_amd import tnep
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import frame_errors
+
+    n_frames = min(args.frames, 340)
+    base = synth.water_trajectory(n_frames)
+    shear = np.array([[1, 0, 0], [1, 1, 0], [0, 1, 1]], np.float64)  # same lattice, skewed basis
+    tri_cells = np.stack([(shear @ c.reshape(3, 3)).reshape(9) for c in base.cells])
+    tric = synth.Frames(base.offsets, base.positions, base.species, tri_cells, base.pbc)
+    # a rotated copy: the lattice vectors are not along the axes in any basis
+    rot, _ = np.linalg.qr(np.random.default_rng(8).normal(size=(3, 3)))
+    rot_cells = np.stack([(c.reshape(3, 3) @ rot.T).reshape(9) for c in base.cells])
+    rotated = synth.Frames(base.offsets, base.positions @ rot.T, base.species, rot_cells, base.pbc)
+
+    def second(name):
+        seed, kind, species, desc = synth.MODEL_SPECS[name]
+        return synth.with_descriptor_of(synth.make_model(seed + 50, kind, species, **desc), synth.model(name))
+
+    variants = {
+        "shared_4body": (synth.model("water_dipole"), synth.model("water_polarizability"), base),
+        "per_species": (synth.per_species_model([synth.model("water_dipole"), second("water_dipole")], [0, 1]),
+                        synth.per_species_model([synth.model("water_polarizability"),
+                                                 second("water_polarizability")], [1, 0]), base),
+        "five_body": (synth.model("water_dipole_5b"), synth.model("water_polarizability_5b"), base),
+        "skewed_basis": (synth.model("water_dipole"), synth.model("water_polarizability"), tric),
+        "triclinic_rotated": (synth.model("water_dipole"), synth.model("water_polarizability"), rotated),
+    }
+    results = {}
+    ctx = tnep.Context(0)
+    for name, (md, mp, fr) in variants.items():
+        gd, gp = tnep.Model(ctx, md), tnep.Model(ctx, mp)
+        dfr = tnep.DeviceFrames(fr)
+        mu = torch.zeros((fr.n_frames, 3), dtype=torch.float64, device="cuda")
+        al = torch.zeros((fr.n_frames, 9), dtype=torch.float64, device="cuda")
+        t = _timed(lambda: tnep.tnep_eval_dipole_polarizability(ctx, gd, gp, dfr, mu, al), args.steps, args.warmup)
+        sub = fr.subset([0])
+        rm, pm = oracle.eval_frames(md, sub, per_atom=True)
+        ra, pa = oracle.eval_frames(mp, sub, per_atom=True)
+        err = max(frame_errors(mu[:1].cpu().numpy(), rm, pm, sub.offsets).max(),
+                  frame_errors(al[:1].cpu().numpy(), ra.reshape(1, 9), pa, sub.offsets).max())
+        results[name] = {"atom_frames_per_s": fr.n_atoms / t, "ms_per_call": 1e3 * t,
+                         "max_frame_error_vs_oracle": float(err)}
+        gd.close()
+        gp.close()
+    # charged molecules
+    masses = [12.011, 1.008, 14.007, 15.999, 18.998]
+    mol = synth.molecules(8192)
+    q = np.random.default_rng(7).integers(-2, 3, mol.n_frames).astype(np.float64)
+    md = synth.model("molecule_dipole")
+    gd = tnep.Model(ctx, md)
+    dmol = tnep.DeviceFrames(mol)
+    dq = torch.as_tensor(q).cuda()
+    mu = torch.zeros((mol.n_frames, 3), dtype=torch.float64, device="cuda")
+    t_plain = _timed(lambda: tnep.tnep_eval_dipole(ctx, gd, dmol, mu), args.steps, args.warmup)
+    t_ch = _timed(lambda: tnep.tnep_eval_dipole_charged(ctx, gd, dmol, dq, masses, 1.0, mu), args.steps, args.warmup)
+    sub = mol.subset(list(range(32)))
+    ref = oracle.dipole_charged(md, sub, q[:32], masses, 1.0)
+    results["charged_molecules"] = {"atom_frames_per_s": mol.n_atoms / t_ch, "ms_per_call": 1e3 * t_ch,
+                                    "plain_dipole_ms_per_call": 1e3 * t_plain,
+                                    "max_frame_error_vs_oracle": float(frame_errors(mu[:32].cpu().numpy(), ref).max())}
+    print(json.dumps({
+        "metric": "TNEP atom-frames/s of model and cell variants at FP32 tol",
+        "value": results["shared_4body"]["atom_frames_per_s"], "unit": "atom-frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "water 4096 H2O (12288 atoms, 49.7 A) x %d-frame OU trajectory, dipole + "
+                               "polarizability per call; variants: per-species networks, five-body term, a skewed "
+                               "basis of the same lattice, a rotated (triclinic) copy; 8192 charged vacuum molecules"
+                               % n_frames},
+        "variants": results}), flush=True)
+
+
 def bench_spectra(args):
     """Paper-scale Raman spectra of a recorded susceptibility: 20 runs of
     10^5 samples (500 ps at 5 fs), pushed through the streaming accumulator in
@@ -534,7 +617,7 @@ def main():
                     help="frames per neighbour-candidate window of the trajectory (0 = plain searches)")
     ap.add_argument("--skin", type=float, default=1.0, help="candidate skin in Angstrom")
     ap.add_argument("--workload", default="water", choices=["water", "perovskite", "molecules", "serving", "pes", "spectra",
-                                                              "population"],
+                                                              "population", "variants"],
                     help="water: the headline line; the others print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
@@ -560,7 +643,8 @@ def main():
 
     if args.workload != "water":
         {"perovskite": bench_perovskite, "molecules": bench_molecules, "serving": bench_serving,
-         "pes": bench_pes, "spectra": bench_spectra, "population": bench_population}[args.workload](args)
+         "pes": bench_pes, "spectra": bench_spectra, "population": bench_population,
+         "variants": bench_variants}[args.workload](args)
         return
 
     dev = torch.device("cuda:0")

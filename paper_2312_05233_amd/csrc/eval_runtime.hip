@@ -32,6 +32,71 @@ hipError_t launch_init_flags(int32_t* d_flags, hipStream_t s) {
     return hipGetLastError();
 }
 
+namespace {
+
+// Inverse of the row-vector cell H (rows = lattice vectors) and its
+// face-to-face widths; false if singular.
+bool cell_inverse(const double* H, double* Hinv, double* w) {
+    double cof[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            cof[3 * i + j] = H[3 * i1 + j1] * H[3 * i2 + j2] - H[3 * i1 + j2] * H[3 * i2 + j1];
+        }
+    const double det = H[0] * cof[0] + H[1] * cof[1] + H[2] * cof[2];
+    if (!(std::fabs(det) > 0.0)) return false;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Hinv[3 * i + j] = cof[3 * j + i] / det;
+    for (int k = 0; k < 3; ++k)
+        w[k] = std::fabs(det) /
+               std::sqrt(cof[3 * k] * cof[3 * k] + cof[3 * k + 1] * cof[3 * k + 1] + cof[3 * k + 2] * cof[3 * k + 2]);
+    return true;
+}
+
+// The same lattice in a reduced basis: each row is shortened by integer
+// multiples of the others (a_i -= round(a_i.a_j / a_j.a_j) a_j) until no row
+// changes.  Integer row operations of determinant 1 keep the lattice, so the
+// periodic system, its images and every pair vector are unchanged; the rows
+// get shorter and more orthogonal, the face widths larger.
+void reduce_lattice(const double* H, double* R) {
+    for (int i = 0; i < 9; ++i) R[i] = H[i];
+    for (int it = 0; it < 64; ++it) {
+        bool changed = false;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                if (i == j) continue;
+                const double* aj = R + 3 * j;
+                double* ai = R + 3 * i;
+                const double jj = aj[0] * aj[0] + aj[1] * aj[1] + aj[2] * aj[2];
+                const double mu = std::nearbyint((ai[0] * aj[0] + ai[1] * aj[1] + ai[2] * aj[2]) / jj);
+                if (mu == 0.0) continue;
+                for (int k = 0; k < 3; ++k) ai[k] -= mu * aj[k];
+                changed = true;
+            }
+        if (!changed) break;
+    }
+}
+
+// Rows along distinct coordinate axes (a signed permutation of a diagonal):
+// the lattice is orthorhombic, L[axis] = |row component|.
+bool axis_aligned(const double* R, double* L) {
+    bool used[3] = {false, false, false};
+    for (int i = 0; i < 3; ++i) {
+        int nz = -1, count = 0;
+        for (int k = 0; k < 3; ++k)
+            if (R[3 * i + k] != 0.0) {
+                nz = k;
+                ++count;
+            }
+        if (count != 1 || used[nz]) return false;
+        used[nz] = true;
+        L[nz] = std::fabs(R[3 * i + nz]);
+    }
+    return true;
+}
+
+}  // namespace
+
 int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc, FrameGeom& g) {
     g = FrameGeom();
     bool any = false;
@@ -46,36 +111,43 @@ int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double
     bool skew = false;
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) skew = skew || (a != b && cell[3 * a + b] != 0.0);
+    double ortho[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (skew) {
-        // triclinic: all axes periodic, every face-to-face width >= 2 r_c
+        // triclinic: all axes periodic, every face-to-face width of the cell as given >= 2 r_c
         if (!(g.per[0] && g.per[1] && g.per[2]))
             return c->fail(TNEP_E_BOX, "frame %d: a skewed cell needs all three axes periodic", f);
-        double cof[9];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-                cof[3 * i + j] = cell[3 * i1 + j1] * cell[3 * i2 + j2] - cell[3 * i1 + j2] * cell[3 * i2 + j1];
+        double Hinv[9], w[3];
+        if (!cell_inverse(cell, Hinv, w)) return c->fail(TNEP_E_BOX, "frame %d: singular cell", f);
+        for (int k = 0; k < 3; ++k)
+            if (!(w[k] >= 2.0 * rc))
+                return c->fail(TNEP_E_BOX, "frame %d: cell width %g shorter than 2 r_c = %g", f, w[k], 2.0 * rc);
+        // the search runs on a reduced basis of the same lattice
+        double R[9], Rinv[9], wr[3], L[3];
+        reduce_lattice(cell, R);
+        const bool reduced = cell_inverse(R, Rinv, wr) && wr[0] >= 2.0 * rc && wr[1] >= 2.0 * rc && wr[2] >= 2.0 * rc;
+        if (reduced && axis_aligned(R, L)) {
+            // a skewed description of an orthorhombic lattice: the orthorhombic path below
+            for (int d = 0; d < 3; ++d) ortho[4 * d] = L[d];
+            cell = ortho;
+        } else {
+            const double* H = reduced ? R : cell;
+            g.tric = 1;
+            bool ok = true;
+            for (int i = 0; i < 9; ++i) {
+                g.H[i] = H[i];
+                g.Hinv[i] = reduced ? Rinv[i] : Hinv[i];
             }
-        const double det = cell[0] * cof[0] + cell[1] * cof[1] + cell[2] * cof[2];
-        if (!(std::fabs(det) > 0.0)) return c->fail(TNEP_E_BOX, "frame %d: singular cell", f);
-        g.tric = 1;
-        bool ok = true;
-        for (int i = 0; i < 9; ++i) g.H[i] = cell[i];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) g.Hinv[3 * i + j] = cof[3 * j + i] / det;
-        for (int k = 0; k < 3; ++k) {
-            g.w[k] = std::fabs(det) / std::sqrt(cof[3 * k] * cof[3 * k] + cof[3 * k + 1] * cof[3 * k + 1] +
-                                                cof[3 * k + 2] * cof[3 * k + 2]);
-            if (!(g.w[k] >= 2.0 * rc))
-                return c->fail(TNEP_E_BOX, "frame %d: cell width %g shorter than 2 r_c = %g", f, g.w[k], 2.0 * rc);
-            g.nc[k] = (int)std::floor(g.w[k] / rc);
-            if (g.nc[k] > 256) g.nc[k] = 256;
-            ok = ok && g.nc[k] >= 3;
+            for (int k = 0; k < 3; ++k) {
+                g.w[k] = reduced ? wr[k] : w[k];
+                g.nc[k] = (int)std::floor(g.w[k] / rc);
+                if (g.nc[k] > 256) g.nc[k] = 256;
+                ok = ok && g.nc[k] >= 3;
+            }
+            if (ok) g.mode = 1;
+            else
+                for (int k = 0; k < 3; ++k) g.nc[k] = 1;
+            return TNEP_OK;
         }
-        if (ok) g.mode = 1;
-        else
-            for (int k = 0; k < 3; ++k) g.nc[k] = 1;
-        return TNEP_OK;
     }
     bool all = true;
     for (int d = 0; d < 3; ++d) {

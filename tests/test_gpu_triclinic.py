@@ -46,6 +46,23 @@ def test_sheared_and_rotated_boxes(gpu_lib):
     ctx.close()
 
 
+def test_skewed_basis_of_orthorhombic_lattice_is_reduced(gpu_lib):
+    """A skewed basis of a cubic lattice is reduced to the cubic one before the
+    search (integer row operations keep the lattice): bitwise the result of
+    the cubic description, for several skews."""
+    pos, spc, cell = synth.water_box(8, 24.84, seed=95)
+    H = cell.reshape(3, 3)
+    skews = [SHEAR, np.array([[1, 0, 0], [0, 1, 0], [-1, 1, 1]], np.float64),
+             np.array([[0, 1, 0], [1, 0, 1], [0, 0, -1]], np.float64)]
+    ctx = gpu_lib.Context(0)
+    g = gpu_lib.Model(ctx, synth.model("water_polarizability"))
+    plain = gpu_lib.tnep_eval_polarizability(ctx, g, _frames([pos], spc, [H]))
+    for U in skews:
+        out = gpu_lib.tnep_eval_polarizability(ctx, g, _frames([pos], spc, [U @ H]))
+        assert np.array_equal(out, plain), U
+    ctx.close()
+
+
 def test_small_sheared_box_all_pairs_and_pes(gpu_lib):
     """A 12.42 A water box with a 0.2 L shear: widths just above 2 r_c, fewer
     than three bins per axis, so the frame is searched all-pairs."""
