@@ -236,7 +236,9 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 // (indices are distinct), counted against LDS-staged chunks of the bucket, so
 // buckets of hundreds of atoms (whole small frames) sort in parallel.
 constexpr int kSortChunk = 1024;
-__global__ void __launch_bounds__(64) k_sort_place(const int32_t* __restrict__ bucket_start,
+__global__ void __launch_bounds__(64) k_sort_place(const FrameInfo* __restrict__ frames,
+                                                   const int32_t* __restrict__ frame_of,
+                                                   const int32_t* __restrict__ bucket_start,
                                                    const int32_t* __restrict__ bucket_atoms,
                                                    const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm,
                                                    int32_t* __restrict__ slot_of, const double* __restrict__ pos,
@@ -262,9 +264,22 @@ __global__ void __launch_bounds__(64) k_sort_place(const int32_t* __restrict__ b
             const int slot = p + rank;
             perm[slot] = v;
             slot_of[v] = slot;
+            double x = pos[3 * v], y = pos[3 * v + 1], z = pos[3 * v + 2];
+            const FrameInfo& fi = frames[frame_of[v]];
+            if (fi.tric) {
+                // triclinic frames: the wrapped fractional coordinates (as k_bin bins them)
+                double sf[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    sf[q] = x * fi.Hinv[q] + y * fi.Hinv[3 + q] + z * fi.Hinv[6 + q];
+                    sf[q] -= floor(sf[q]);
+                }
+                x = sf[0];
+                y = sf[1];
+                z = sf[2];
+            }
             bucket_pos[b + rank] =
-                make_double4(pos[3 * v], pos[3 * v + 1], pos[3 * v + 2],
-                             __longlong_as_double((long long)(((uint64_t)(uint32_t)v << 32) | (uint32_t)slot)));
+                make_double4(x, y, z, __longlong_as_double((long long)(((uint64_t)(uint32_t)v << 32) | (uint32_t)slot)));
         }
     }
 }
@@ -554,7 +569,17 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
     const float prune = rc_radial + 1e-3f;
     float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
     const int mode = fi.mode, cell_base = fi.cell_base;
-    const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
+    const int ny = fi.nc[1], nz = fi.nc[2];
+    double H[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) H[q] = fi.H[q];
+    // wrapped fractional coordinates of the atom (bucket records hold the candidates')
+    double si[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        si[q] = xi * fi.Hinv[q] + yi * fi.Hinv[3 + q] + zi * fi.Hinv[6 + q];
+        si[q] -= floor(si[q]);
+    }
     int ib[3] = {0, 0, 0};
     float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
     if (mode == 1) {
@@ -564,11 +589,9 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
         ib[0] = local / (nz * ny);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            double sk = xi * fi.Hinv[k] + yi * fi.Hinv[3 + k] + zi * fi.Hinv[6 + k];
-            sk -= floor(sk);
             const double inv = 1.0 / (double)fi.nc[k];
-            lo[k] = (float)fmax((sk - ib[k] * inv) * fi.w[k], 0.0);
-            hi[k] = (float)fmax(((ib[k] + 1) * inv - sk) * fi.w[k], 0.0);
+            lo[k] = (float)fmax((si[k] - ib[k] * inv) * fi.w[k], 0.0);
+            hi[k] = (float)fmax(((ib[k] + 1) * inv - si[k]) * fi.w[k], 0.0);
         }
     }
     bool overlap = false;
@@ -580,38 +603,51 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
         const int n_visit = mode == 1 ? 27 : 1;
         for (int vb = 0; vb < n_visit; ++vb) {
             int bucket = cell_base * T + t;
+            // fractional offset of the candidates' image relative to the atom:
+            // cell lists: the visited bin's lattice shift (its unwrapped index is
+            // ib + o, within one bin of the atom's), so f = s_j + shift - s_i is the
+            // image within r_c; all-pairs frames: rounding of s_j - s_i
+            double sh[3] = {-si[0], -si[1], -si[2]};
             if (mode == 1) {
                 const int o[3] = {vb / 9 - 1, (vb / 3) % 3 - 1, vb % 3 - 1};
                 float g = 0.f;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) g = fmaxf(g, o[k] < 0 ? lo[k] : (o[k] > 0 ? hi[k] : 0.f));
                 if (g >= prune) continue;
-                const int cx = (ib[0] + o[0] + nx) % nx;
-                const int cy = (ib[1] + o[1] + ny) % ny;
-                const int cz = (ib[2] + o[2] + nz) % nz;
-                bucket = (cell_base + (cx * ny + cy) * nz + cz) * T + t;
+                int cc[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int u = ib[k] + o[k];
+                    cc[k] = u < 0 ? u + fi.nc[k] : (u >= fi.nc[k] ? u - fi.nc[k] : u);
+                    sh[k] += (double)(u < 0 ? -1 : (u >= fi.nc[k] ? 1 : 0));
+                }
+                bucket = (cell_base + (cc[0] * ny + cc[1]) * nz + cc[2]) * T + t;
             }
             const int b = bucket_start[bucket], e = bucket_start[bucket + 1];
-            for (int k = b; k < e; ++k) {
-                const double4 cur = bucket_pos[k];
-                const uint64_t wj = (uint64_t)__double_as_longlong(cur.w);
-                const int j = (int)(uint32_t)wj;
-                if (j == (int)p) continue;
-                const double d0[3] = {cur.x - xi, cur.y - yi, cur.z - zi};
-                double f[3];
+            // candidates two at a time: both loads in flight before either is used
+            for (int k0 = b; k0 < e; k0 += 2) {
+                const double4 q0 = bucket_pos[k0];
+                const double4 q1 = k0 + 1 < e ? bucket_pos[k0 + 1] : make_double4(0.0, 0.0, 0.0, 0.0);
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    f[q] = d0[0] * fi.Hinv[q] + d0[1] * fi.Hinv[3 + q] + d0[2] * fi.Hinv[6 + q];
-                    f[q] -= rint(f[q]);
+                for (int u = 0; u < 2; ++u) {
+                    if (k0 + u >= e) break;
+                    const double4 cur = u == 0 ? q0 : q1;
+                    const int j = (int)(uint32_t)(uint64_t)__double_as_longlong(cur.w);
+                    if (j == (int)p) continue;
+                    double f0 = cur.x + sh[0], f1 = cur.y + sh[1], f2 = cur.z + sh[2];
+                    if (mode != 1) {
+                        f0 -= rint(f0);
+                        f1 -= rint(f1);
+                        f2 -= rint(f2);
+                    }
+                    const double dx = f0 * H[0] + f1 * H[3] + f2 * H[6];
+                    const double dy = f0 * H[1] + f1 * H[4] + f2 * H[7];
+                    const double dz = f0 * H[2] + f1 * H[5] + f2 * H[8];
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 >= rc2r) continue;
+                    if (r2 < 1e-8) overlap = true;
+                    ps.push(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)), r2 < rc2a);
                 }
-                const double dx = f[0] * fi.H[0] + f[1] * fi.H[3] + f[2] * fi.H[6];
-                const double dy = f[0] * fi.H[1] + f[1] * fi.H[4] + f[2] * fi.H[7];
-                const double dz = f[0] * fi.H[2] + f[1] * fi.H[5] + f[2] * fi.H[8];
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 >= rc2r) continue;
-                if (r2 < 1e-8) overlap = true;
-                const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
-                ps.push(ent, r2 < rc2a);
             }
         }
         ps.flush();
@@ -680,7 +716,7 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                            w.bucket_fill, w.perm_start);
     k_scatter<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill,
                                                               w.bucket_atoms, nl.meta);
-    k_sort_place<<<cap_buckets, 64, 0, s>>>(w.bucket_start, w.bucket_atoms, w.perm_start,
+    k_sort_place<<<cap_buckets, 64, 0, s>>>(d_frames, w.frame_of, w.bucket_start, w.bucket_atoms, w.perm_start,
                                                                    w.perm, w.slot_of, pos, w.bucket_pos, nl.meta, T);
     const size_t stage_bytes = sizeof(float4) * 8 * nb;
     k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
