@@ -185,19 +185,22 @@ extern "C" int tnep_model_load(tnep_ctx* ctx, const char* path, tnep_model** out
     std::string kind;
     int32_t version = 0;
     std::vector<double> cr, ca, qs, w0[2], b0[2], w1[2], b1[2];
-    bool ok = r.keyed_int("tnep_model", version, 1, 1) && r.expect("kind") && r.next(kind);
+    bool ok = r.keyed_int("tnep_model", version, 1, 1) && r.expect("kind") &&
+              (r.next(kind) || r.fail("expected a model kind, found end of file"));
     if (ok) {
         if (kind == "dipole") d.kind = TNEP_KIND_DIPOLE;
         else if (kind == "polarizability") d.kind = TNEP_KIND_POLARIZABILITY;
         else if (kind == "pes") d.kind = TNEP_KIND_PES;
         else ok = r.fail("unknown kind '" + kind + "'");
     }
+    // size limits keep a malformed header from asking for large arrays; the
+    // supported shapes are checked by tnep_model_create
     ok = ok && r.keyed_int("n_species", d.n_species, 1, 8) && r.expect("rc") && r.number(d.rc_radial) &&
-         r.number(d.rc_angular) && r.expect("n_max") && r.integer(d.n_max_radial, 0, 63) &&
-         r.integer(d.n_max_angular, 0, 63) && r.expect("basis") && r.integer(d.basis_radial, 0, 63) &&
-         r.integer(d.basis_angular, 0, 63) && r.keyed_int("l_max", d.l_max, 1, 8) &&
+         r.number(d.rc_angular) && r.expect("n_max") && r.integer(d.n_max_radial, 0, 31) &&
+         r.integer(d.n_max_angular, 0, 31) && r.expect("basis") && r.integer(d.basis_radial, 0, 31) &&
+         r.integer(d.basis_angular, 0, 31) && r.keyed_int("l_max", d.l_max, 1, 8) &&
          r.keyed_int("four_body", d.four_body, 0, 1) && r.keyed_int("five_body", d.five_body, 0, 1) &&
-         r.keyed_int("n_hidden", d.n_hidden, 1, 4096) && r.keyed_int("per_species", d.per_species, 0, 1);
+         r.keyed_int("n_hidden", d.n_hidden, 1, 128) && r.keyed_int("per_species", d.per_species, 0, 1);
     const size_t T = d.n_species, H = d.n_hidden;
     const size_t D = ok ? descriptor_length(d) : 0;
     const size_t NS = d.per_species ? T : 1;
