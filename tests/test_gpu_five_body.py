@@ -83,3 +83,17 @@ def test_population_loss_with_five_body(gpu_lib, ctx):
     scale = np.sqrt((oracle.eval_frames(base, fr) ** 2).mean())
     assert np.all(np.abs(rmse - rmse_r) <= TENSOR_TOL * scale)
     assert np.all(np.abs((loss - rmse) - (loss_r - rmse_r)) <= 1e-12 * np.abs(loss_r - rmse_r))
+
+
+def test_per_species_five_body(gpu_lib, ctx):
+    """Per-species networks on a five-body descriptor."""
+    a = synth.model("water_polarizability_5b")
+    seed, kind, species, desc = synth.MODEL_SPECS["water_polarizability_5b"]
+    b = synth.with_descriptor_of(synth.make_model(seed + 50, kind, species, **desc), a)
+    m = synth.per_species_model([a, b], [1, 0])
+    fr = synth.water_small(2, seed=97)
+    out = gpu_lib.tnep_eval_polarizability(ctx, gpu_lib.Model(ctx, m), fr)
+    ref, pa = oracle.eval_frames(m, fr, per_atom=True)
+    err = frame_errors(out, ref, pa, fr.offsets)
+    print("per-species five-body", err.max(), flush=True)
+    assert np.all(err <= TENSOR_TOL)
