@@ -109,6 +109,23 @@ def test_deterministic_and_batch_invariant(gpu_lib, ctx):
     c2.close()
 
 
+def test_frame_larger_than_launch_batch(gpu_lib, ctx):
+    """A frame larger than the launch-batch size runs in a batch of its own;
+    results equal the default batching bitwise."""
+    m = synth.model("water_polarizability")
+    mdl = gpu_lib.Model(ctx, m)
+    pos, spc, cell = synth.water_box(8, 24.84, seed=34)
+    big = synth.Frames(np.array([0, len(spc)], np.int64), pos, spc, cell[None], np.ones((1, 3), np.uint8))
+    fr = synth.Frames.concat([synth.water_small(2, seed=35), big, synth.water_small(1, seed=36)])
+    a = gpu_lib.tnep_eval_polarizability(ctx, mdl, fr)
+    c2 = gpu_lib.Context(0)
+    c2.set_option(gpu_lib.OPT_MAX_BATCH_ATOMS, 1000)
+    b = gpu_lib.tnep_eval_polarizability(c2, gpu_lib.Model(c2, m), fr)
+    assert np.array_equal(a, b)
+    _check(a, m, fr, "mixed sizes")
+    c2.close()
+
+
 def test_device_resident_inputs(gpu_lib, ctx):
     import torch
 
