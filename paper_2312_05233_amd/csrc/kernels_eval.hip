@@ -59,6 +59,36 @@ __device__ __forceinline__ void cutoff_fc_d(float v, float rc_inv, float& fc, fl
     dfc = -3.14159265358979323846f * rc_inv * s * c;
 }
 
+// Chebyshev polynomials T_k(x), k = 0..K-1 (three-term recurrence).  The
+// radial basis is f_k = (T_k(x) + 1)/2 f_c, so sums of f_k and of their
+// contractions with coefficients are formed from sums of T_k (one fused
+// multiply-add per term) instead of building every f_k.
+template <int K>
+__device__ __forceinline__ void cheb_T(float x, float* T) {
+    T[0] = 1.f;
+    if (K > 1) T[1] = x;
+    const float x2 = x + x;
+#pragma unroll
+    for (int k = 2; k < K; ++k) T[k] = x2 * T[k - 1] - T[k - 2];
+}
+
+// T_k(x) and dT_k/dx.
+template <int K>
+__device__ __forceinline__ void cheb_T_d(float x, float* T, float* dT) {
+    T[0] = 1.f;
+    dT[0] = 0.f;
+    if (K > 1) {
+        T[1] = x;
+        dT[1] = 1.f;
+    }
+    const float x2 = x + x;
+#pragma unroll
+    for (int k = 2; k < K; ++k) {
+        T[k] = x2 * T[k - 1] - T[k - 2];
+        dT[k] = 2.f * T[k - 1] + x2 * dT[k - 1] - dT[k - 2];
+    }
+}
+
 // Tile species: wave-uniform (tiles are species-pure).
 __device__ __forceinline__ int tile_species(const int32_t* tile_base, int T, int tile) {
     int ti = 0;
@@ -270,9 +300,18 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
         const int n_rad = nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
         const float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
         const float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
-        float F[KR];  // sum over neighbours of species t of f_k(r_ij)
+        // sum over neighbours of species t of f_k(r_ij) = (sum fc T_k + sum fc) / 2
+        float FT[KR], Fs = 0.f;
 #pragma unroll
-        for (int k = 0; k < KR; ++k) F[k] = 0.f;
+        for (int k = 0; k < KR; ++k) FT[k] = 0.f;
+        float Cs[NA];  // sum_k c_nk (wave-uniform)
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            float c = 0.f;
+#pragma unroll
+            for (int k = 0; k < KA; ++k) c += cA[n * KA + k];
+            Cs[n] = c;
+        }
         float4 nxt = n_ang > 0 ? ga[0] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int s = 0; s < n_ang; ++s) {
             const float4 e = nxt;
@@ -280,20 +319,26 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
             const float rinv = rsqrtf(r2);
             const float r = r2 * rinv;
-            float f[KR > KA ? KR : KA];
-            float v = 1.f - r * rcR_inv;
-            cheb_basis<KR>(r, rcR_inv, cutoff_fc(v), f);
+            float Tk[KR > KA ? KR : KA];
+            {
+                const float fc = cutoff_fc(1.f - r * rcR_inv);
+                const float tt = r * rcR_inv - 1.f;
+                cheb_T<KR>(2.f * tt * tt - 1.f, Tk);
+                Fs += fc;
 #pragma unroll
-            for (int k = 0; k < KR; ++k) F[k] += f[k];
-            v = 1.f - r * rcA_inv;
-            cheb_basis<KA>(r, rcA_inv, cutoff_fc(v), f);
+                for (int k = 0; k < KR; ++k) FT[k] += fc * Tk[k];
+            }
+            const float hfc = 0.5f * cutoff_fc(1.f - r * rcA_inv);
+            const float ta = r * rcA_inv - 1.f;
+            cheb_T<KA>(2.f * ta * ta - 1.f, Tk);
+            // g_n = sum_k c_nk f_k = fc/2 (sum_k c_nk T_k + sum_k c_nk)
             float gA[NA];
 #pragma unroll
             for (int n = 0; n < NA; ++n) {
-                float g = 0.f;
+                float g = Cs[n];
 #pragma unroll
-                for (int k = 0; k < KA; ++k) g += cA[n * KA + k] * f[k];
-                gA[n] = g;
+                for (int k = 0; k < KA; ++k) g += cA[n * KA + k] * Tk[k];
+                gA[n] = hfc * g;
             }
             sh_foreach(e.x * rinv, e.y * rinv, e.z * rinv, [&](int idx, int, float P, float, float, float) {
 #pragma unroll
@@ -305,11 +350,17 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float4 e = nxt;
             if (s + 1 < n_rad) nxt = gr[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
             const float r = sqrtf(e.x * e.x + e.y * e.y + e.z * e.z);
-            float f[KR];
-            cheb_basis<KR>(r, rcR_inv, cutoff_fc(1.f - r * rcR_inv), f);
+            const float fc = cutoff_fc(1.f - r * rcR_inv);
+            const float tt = r * rcR_inv - 1.f;
+            float Tk[KR];
+            cheb_T<KR>(2.f * tt * tt - 1.f, Tk);
+            Fs += fc;
 #pragma unroll
-            for (int k = 0; k < KR; ++k) F[k] += f[k];
+            for (int k = 0; k < KR; ++k) FT[k] += fc * Tk[k];
         }
+        float F[KR];
+#pragma unroll
+        for (int k = 0; k < KR; ++k) F[k] = 0.5f * (FT[k] + Fs);
 #pragma unroll
         for (int n = 0; n < NR; ++n)
 #pragma unroll
@@ -492,14 +543,30 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             for (int n = 0; n < NR; ++n) d += dq[n] * cR[n * KR + k];
             Dk[k] = d;
         }
-        auto radial_slope = [&](float r) {
-            float fc, dfc, f[KR], df[KR];
-            cutoff_fc_d(1.f - r * rcR_inv, rcR_inv, fc, dfc);
-            cheb_basis_d<KR>(r, rcR_inv, fc, dfc, f, df);
-            float sr = 0.f;
+        // sum_k Dk f_k'(r) = (fc x' sum_k Dk T_k' + fc' (sum_k Dk T_k + sum_k Dk)) / 2
+        float Dsum = 0.f;
 #pragma unroll
-            for (int k = 0; k < KR; ++k) sr += Dk[k] * df[k];
-            return sr;
+        for (int k = 0; k < KR; ++k) Dsum += Dk[k];
+        float CsA[NA];  // sum_k c_nk of the angular coefficients (wave-uniform)
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            float c = 0.f;
+#pragma unroll
+            for (int k = 0; k < KA; ++k) c += cA[n * KA + k];
+            CsA[n] = c;
+        }
+        auto radial_slope = [&](float r) {
+            float fc, dfc, Tk[KR], dT[KR];
+            cutoff_fc_d(1.f - r * rcR_inv, rcR_inv, fc, dfc);
+            const float tt = r * rcR_inv - 1.f;
+            cheb_T_d<KR>(2.f * tt * tt - 1.f, Tk, dT);
+            float s0 = Dsum, s1 = 0.f;
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                s0 += Dk[k] * Tk[k];
+                s1 += Dk[k] * dT[k];
+            }
+            return 0.5f * (fc * (4.f * tt * rcR_inv) * s1 + dfc * s0);
         };
         float4 nxt = n_ang > 0 ? ga[0] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int s = 0; s < n_ang; ++s) {
@@ -510,20 +577,24 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float r = r2 * rinv;
             const float ux = e.x * rinv, uy = e.y * rinv, uz = e.z * rinv;
             const float sr = radial_slope(r);
-            float fc, dfc, f[KA], df[KA];
+            float fc, dfc, Tk[KA], dT[KA];
             cutoff_fc_d(1.f - r * rcA_inv, rcA_inv, fc, dfc);
-            cheb_basis_d<KA>(r, rcA_inv, fc, dfc, f, df);
+            const float ta = r * rcA_inv - 1.f;
+            cheb_T_d<KA>(2.f * ta * ta - 1.f, Tk, dT);
+            // g_n = fc/2 (P_n + C_n), g_n' = (fc x' Q_n + fc' (P_n + C_n)) / 2 with
+            // P_n = sum_k c_nk T_k, Q_n = sum_k c_nk T_k', C_n = sum_k c_nk
+            const float hfc = 0.5f * fc, hdfc = 0.5f * dfc, hfx = hfc * (4.f * ta * rcA_inv);
             float gA[NA], dgA[NA];
 #pragma unroll
             for (int n = 0; n < NA; ++n) {
-                float g = 0.f, dg = 0.f;
+                float pn = CsA[n], qn = 0.f;
 #pragma unroll
                 for (int k = 0; k < KA; ++k) {
-                    g += cA[n * KA + k] * f[k];
-                    dg += cA[n * KA + k] * df[k];
+                    pn += cA[n * KA + k] * Tk[k];
+                    qn += cA[n * KA + k] * dT[k];
                 }
-                gA[n] = g;
-                dgA[n] = dg;
+                gA[n] = hfc * pn;
+                dgA[n] = hfx * qn + hdfc * pn;
             }
             float Fx = 0.f, Fy = 0.f, Fz = 0.f, sc = 0.f;
             sh_foreach(ux, uy, uz, [&](int idx, int l, float P, float px, float py, float pz) {
