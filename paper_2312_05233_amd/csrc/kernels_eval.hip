@@ -742,22 +742,35 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
         const int n_rad = nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
         const float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
         const float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
+        // sum_k D_k f_k'(r) from Chebyshev sums (as in k_eval)
         auto radial_slope = [&](const float* rj, float r) {
-            float fc, dfc, f[KR], df[KR];
+            float fc, dfc, Tk[KRP], dT[KRP];
             cutoff_fc_d(1.f - r * rcR_inv, rcR_inv, fc, dfc);
-            cheb_basis_d<KR>(r, rcR_inv, fc, dfc, f, df);
+            const float tt = r * rcR_inv - 1.f;
+            cheb_T_d<KR>(2.f * tt * tt - 1.f, Tk, dT);
             const float4* d4 = reinterpret_cast<const float4*>(rj + tk * KRP);
-            float sr = 0.f;
+            float s0 = 0.f, s1 = 0.f;
 #pragma unroll
             for (int k = 0; k < KRP; k += 4) {
                 const float4 d = d4[k / 4];
-                sr += d.x * df[k];
-                if (k + 1 < KR) sr += d.y * df[k + 1];
-                if (k + 2 < KR) sr += d.z * df[k + 2];
-                if (k + 3 < KR) sr += d.w * df[k + 3];
+                const float dd[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (k + u < KR) {
+                        s0 += dd[u] * (Tk[k + u] + 1.f);
+                        s1 += dd[u] * dT[k + u];
+                    }
             }
-            return sr;
+            return 0.5f * (fc * (4.f * tt * rcR_inv) * s1 + dfc * s0);
         };
+        float CsA[NA];  // sum_k c_nk of c_{t, t_k} (wave-uniform)
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            float c = 0.f;
+#pragma unroll
+            for (int k = 0; k < KA; ++k) c += cA[n * KA + k];
+            CsA[n] = c;
+        }
         float4 nxt = n_ang > 0 ? ga[0] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int s = 0; s < n_ang; ++s) {
             const float4 e = nxt;
@@ -768,9 +781,11 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
             const float r = r2 * rinv;
             const float ux = e.x * rinv, uy = e.y * rinv, uz = e.z * rinv;
             const float sr = radial_slope(rj, r);
-            float fc, dfc, f[KA], df[KA];
+            float fc, dfc, Tk[KA], dT[KA];
             cutoff_fc_d(1.f - r * rcA_inv, rcA_inv, fc, dfc);
-            cheb_basis_d<KA>(r, rcA_inv, fc, dfc, f, df);
+            const float ta = r * rcA_inv - 1.f;
+            cheb_T_d<KA>(2.f * ta * ta - 1.f, Tk, dT);
+            const float hfc = 0.5f * fc, hdfc = 0.5f * dfc, hfx = hfc * (4.f * ta * rcA_inv);
             // a_c = sum_n G~_j[n][c] g_n(r), b_c = sum_n G~_j[n][c] g_n'(r)
             float av[kLM], bv[kLM];
 #pragma unroll
@@ -781,12 +796,13 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
             const float4* gj = reinterpret_cast<const float4*>(rj + T * KRP);
 #pragma unroll
             for (int n = 0; n < NA; ++n) {
-                float g = 0.f, dg = 0.f;
+                float pn = CsA[n], qn = 0.f;
 #pragma unroll
                 for (int k = 0; k < KA; ++k) {
-                    g += cA[n * KA + k] * f[k];
-                    dg += cA[n * KA + k] * df[k];
+                    pn += cA[n * KA + k] * Tk[k];
+                    qn += cA[n * KA + k] * dT[k];
                 }
+                const float g = hfc * pn, dg = hfx * qn + hdfc * pn;
 #pragma unroll
                 for (int c = 0; c < kLM; c += 4) {
                     const float4 w = gj[(n * kLM + c) / 4];
