@@ -642,14 +642,17 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     }
 }
 
-// One work-group of 256 lanes per frame: lane l sums atoms l, l + 256, ... in
-// FP64, then a fixed pairwise tree in LDS; the order depends only on the
-// frame's atom count, never on how frames were batched.
-__global__ void __launch_bounds__(256) k_frame_reduce(const FrameInfo* __restrict__ frames,
-                                                      const int32_t* __restrict__ meta,
-                                                      const double* __restrict__ per_atom, int nt, int na,
-                                                      double* __restrict__ out_a, double* __restrict__ out_b) {
-    __shared__ double part[10][256];
+// One work-group of 1024 lanes per frame: lane l sums atoms l, l + 1024, ...
+// in FP64, then a fixed tree: within each wavefront by shuffles, then over
+// the 16 wavefronts in LDS.  The order depends only on the frame's atom
+// count, never on how frames were batched.
+constexpr int kReduceBlock = 1024;
+__global__ void __launch_bounds__(kReduceBlock) k_frame_reduce(const FrameInfo* __restrict__ frames,
+                                                               const int32_t* __restrict__ meta,
+                                                               const double* __restrict__ per_atom, int nt, int na,
+                                                               double* __restrict__ out_a, double* __restrict__ out_b) {
+    constexpr int kWaves = kReduceBlock / 64;
+    __shared__ double part[10][kWaves];
     const int f = blockIdx.x;
     if (f >= meta[kMetaNFrames]) return;
     const FrameInfo fi = frames[f];
@@ -657,25 +660,31 @@ __global__ void __launch_bounds__(256) k_frame_reduce(const FrameInfo* __restric
     double s[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) s[k] = 0.0;
-    for (int64_t a = lane; a < fi.n_atoms; a += 256) {
+    for (int64_t a = lane; a < fi.n_atoms; a += kReduceBlock) {
         const double* q = per_atom + (fi.atom_begin + a) * nt;
 #pragma unroll
         for (int k = 0; k < 10; ++k)
             if (k < nt) s[k] += q[k];
     }
 #pragma unroll
-    for (int k = 0; k < 10; ++k) part[k][lane] = s[k];
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (lane < off)
+    for (int k = 0; k < 10; ++k) {
+        if (k < nt) {
+            double v = s[k];
 #pragma unroll
-            for (int k = 0; k < 10; ++k) part[k][lane] += part[k][lane + off];
-        __syncthreads();
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if ((lane & 63) == 0) part[k][lane >> 6] = v;
+        }
     }
-    if (lane < na)
-        out_a[(int64_t)f * na + lane] = part[lane][0];
-    else if (lane < nt && out_b)
-        out_b[(int64_t)f * (nt - na) + lane - na] = part[lane][0];
+    __syncthreads();
+    if (lane < nt) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) v += part[lane][w];
+        if (lane < na)
+            out_a[(int64_t)f * na + lane] = v;
+        else if (out_b)
+            out_b[(int64_t)f * (nt - na) + lane - na] = v;
+    }
 }
 
 // Charged molecules (the dipole of a charged system depends on the reference
@@ -949,7 +958,7 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
 hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const int32_t* meta, const double* per_atom,
                                int nt, int na, double* out_a, double* out_b, hipStream_t s) {
     if (cap_frames == 0) return hipSuccess;
-    k_frame_reduce<<<cap_frames, 256, 0, s>>>(d_frames, meta, per_atom, nt, na, out_a, out_b);
+    k_frame_reduce<<<cap_frames, kReduceBlock, 0, s>>>(d_frames, meta, per_atom, nt, na, out_a, out_b);
     return hipGetLastError();
 }
 
