@@ -97,7 +97,7 @@ bool axis_aligned(const double* R, double* L) {
 
 }  // namespace
 
-int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc, FrameGeom& g) {
+int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc, int64_t n_atoms, FrameGeom& g) {
     g = FrameGeom();
     bool any = false;
     for (int d = 0; d < 3; ++d) {
@@ -157,13 +157,23 @@ int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double
         all = all && g.per[d];
     }
     if (all) {
+        // cells of edge >= rc / 2 (the search reaches two cells each way), at
+        // least five per axis so that the reach holds distinct cells; a sparse
+        // frame gets larger cells (about two cells per atom at most)
         bool ok = true;
         for (int d = 0; d < 3; ++d) {
-            g.nc[d] = (int)std::floor(g.L[d] / rc);
-            if (g.nc[d] > 256) g.nc[d] = 256;
-            ok = ok && g.nc[d] >= 3;
+            g.nc[d] = (int)std::min(512.0, std::floor(2.0 * g.L[d] / rc));
+            ok = ok && g.nc[d] >= 5;
         }
-        if (ok) g.mode = 1;
+        if (ok) {
+            const double lim = std::max(2.0 * (double)n_atoms, 125.0);
+            const double prod = (double)g.nc[0] * g.nc[1] * g.nc[2];
+            if (prod > lim) {
+                const double s = std::cbrt(prod / lim);
+                for (int d = 0; d < 3; ++d) g.nc[d] = std::max(5, (int)std::floor(g.nc[d] / s));
+            }
+            g.mode = 1;
+        }
     }
     return TNEP_OK;
 }
@@ -403,11 +413,12 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
         std::vector<FrameGeom> geom(F);
         for (int f = 0; f < F; ++f) {
             e = frame_geometry(c, f, fr.cells ? meta.cells.data() + 9 * (size_t)f : nullptr,
-                               fr.pbc ? meta.pbc.data() + 3 * (size_t)f : nullptr, gm->rc_radial, geom[f]);
+                               fr.pbc ? meta.pbc.data() + 3 * (size_t)f : nullptr, gm->rc_radial,
+                               meta.offs[f + 1] - meta.offs[f], geom[f]);
             if (e) return e;
         }
-        // trajectory reuse: frames whose cell grid can hold r_c + skin (all
-        // axes periodic, every edge >= 2 (r_c + skin), >= 3 cells per axis)
+        // trajectory reuse: frames with a cell grid for r_c + skin (all axes
+        // periodic, every edge >= 2 (r_c + skin), >= 5 cells per axis)
         const double rc_search = gm->rc_radial + c->skin;
         bool reuse = c->traj_window > 1;
         std::vector<FrameGeom> geom_rs(reuse ? F : 0);
@@ -418,7 +429,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             for (int d = 0; d < 3 && ok; ++d) ok = g.L[d] >= 2.0 * rc_search;
             if (ok) {
                 e = frame_geometry(c, f, meta.cells.data() + 9 * (size_t)f, meta.pbc.data() + 3 * (size_t)f,
-                                   rc_search, geom_rs[f]);
+                                   rc_search, meta.offs[f + 1] - meta.offs[f], geom_rs[f]);
                 if (e) return e;
                 ok = geom_rs[f].mode == 1;
             }
@@ -477,7 +488,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if ((e = c->reserve(c->slot_of, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->key_of, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->bucket_atoms, (size_t)B_res * 4))) return e;
-            if ((e = c->reserve(c->bucket_pos, (size_t)B_res * 32))) return e;
+            if ((e = c->reserve(c->bucket_pos, (size_t)n_pad_max * 32))) return e;  // indexed by tile slot
             if ((e = c->reserve(c->per_atom, (size_t)B_res * 10 * sizeof(double) * (last - first)))) return e;
             if (pes) {
                 if ((e = c->reserve(c->pes_rec, (size_t)n_pad_max * rec_stride * sizeof(float)))) return e;
@@ -575,7 +586,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if ((e = c->reserve(c->bucket_count, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->bucket_start, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->bucket_fill, (size_t)4 * (n_buckets + 1)))) return e;
-                if ((e = c->reserve(c->perm_start, (size_t)4 * (n_buckets + 1)))) return e;
+                if ((e = c->reserve(c->perm_start, (size_t)4 * (n_buckets + T + 1)))) return e;
                 if ((e = c->reserve(c->scan_chunks, (size_t)4 * 18 * (cap_cells / 1024 + 1)))) return e;
                 const int nt_max = 10;
                 if ((e = c->reserve(c->out, sizeof(double) * nt_max * cap_frames * (last - first)))) return e;

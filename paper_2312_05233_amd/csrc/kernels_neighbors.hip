@@ -7,17 +7,25 @@
 //
 // Pipeline (all on the device):
 //   1. bin every atom into a bucket (cell, species).  Fully periodic
-//      orthorhombic frames with >= 3 cells of edge >= rc_radial per axis use a
-//      cell grid; every other frame (vacuum molecules, small boxes) is one cell;
+//      orthorhombic frames with >= 5 cells of edge >= rc_radial / 2 per axis
+//      use a cell grid, triclinic ones a grid of >= 3 bins of width >=
+//      rc_radial per axis; every other frame (vacuum molecules, small boxes) is
+//      one cell;
 //   2. scan the bucket counts twice: in (cell, species) order for the
-//      candidate lists and in (species, cell) order for the atom tiles;
-//   3. scatter atoms into buckets and sort each bucket by atom index, which
-//      makes the whole result independent of thread scheduling;
+//      scatter and in (species, cell) order for the atom tiles;
+//   3. scatter atoms into buckets; each atom's place in its bucket is its rank
+//      by atom index, which makes the whole result independent of thread
+//      scheduling;
 //   4. build the tile permutation: atoms ordered by (species, cell, index),
-//      each species padded to whole 64-atom tiles (species-pure wavefronts);
-//   5. one lane per tile slot walks the 27-cell stencil (or its frame) once per
-//      neighbour species t and writes the neighbours of species t into that
-//      species' angular (r < rc_angular) and radial-only segments.
+//      each species padded to whole 64-atom tiles (species-pure wavefronts),
+//      and store the positions in the same (slot) order, so that the atoms of
+//      one species in consecutive cells of a frame are one contiguous range;
+//   5. one lane per tile slot walks the cells within reach (or its frame) once
+//      per neighbour species t and writes the neighbours of species t into
+//      that species' angular (r < rc_angular) and radial-only segments.
+//      Orthorhombic grids are walked as 25 columns of cells along z, each
+//      trimmed to the z-cells within reach of the atom: one contiguous range of
+//      candidates per column (two where the column crosses the box face).
 // Entries are grouped four to a lane (64 contiguous bytes), so every store and
 // load of a wavefront covers one contiguous 4 KB block.
 #include "internal.h"
@@ -206,7 +214,8 @@ __global__ void __launch_bounds__(256) k_scan_final(const int32_t* __restrict__ 
                 run += count[c * T + u];
             }
     }
-    // species-major order
+    // species-major order; perm_start[n_cells * T + t] closes species t, so
+    // perm_start[(c + 1) * T + t] always ends the bucket (c, t)
     for (int t = 0; t < T; ++t) {
         int32_t s = 0;
         for (int c = c0; c < c1; ++c) s += count[c * T + t];
@@ -215,6 +224,7 @@ __global__ void __launch_bounds__(256) k_scan_final(const int32_t* __restrict__ 
             perm_start[c * T + t] = run;
             run += count[c * T + t];
         }
+        if (c0 < c1 && c1 == n_cells) perm_start[n_cells * T + t] = run;
     }
 }
 
@@ -229,63 +239,53 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
     bucket_atoms[bucket_start[k] + slot] = (int32_t)a;
 }
 
-// Sort each bucket by atom index, place it into the tile permutation and
-// store its positions contiguously in bucket order (w = the atom's tile slot
-// in the low 32 bits, its batch index in the high 32 bits).  One wave per
-// bucket: an atom's place is the number of smaller atom indices in its bucket
-// (indices are distinct), counted against LDS-staged chunks of the bucket, so
-// buckets of hundreds of atoms (whole small frames) sort in parallel.
-constexpr int kSortChunk = 1024;
-__global__ void __launch_bounds__(64) k_sort_place(const FrameInfo* __restrict__ frames,
-                                                   const int32_t* __restrict__ frame_of,
-                                                   const int32_t* __restrict__ bucket_start,
-                                                   const int32_t* __restrict__ bucket_atoms,
-                                                   const int32_t* __restrict__ perm_start, int32_t* __restrict__ perm,
-                                                   int32_t* __restrict__ slot_of, const double* __restrict__ pos,
-                                                   double4* __restrict__ bucket_pos, const int32_t* __restrict__ meta,
-                                                   int T) {
-    __shared__ int32_t chunk[kSortChunk];
-    const int k = blockIdx.x;
-    if (k >= meta[kMetaNCells] * T) return;
+// Place every atom into the tile permutation at (first slot of its bucket) +
+// (number of smaller atom indices in its bucket) and store its position at
+// that slot (w = the atom's batch index in the high 32 bits).  One thread per
+// atom: buckets hold a few atoms on cell grids and a whole frame otherwise, so
+// the rank loop is never longer than the frame's own neighbour loop.
+__global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ frame_of,
+                             const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
+                             const int32_t* __restrict__ bucket_atoms, const int32_t* __restrict__ perm_start,
+                             int32_t* __restrict__ perm, int32_t* __restrict__ slot_of, const double* __restrict__ pos,
+                             double4* __restrict__ bucket_pos, const int32_t* __restrict__ meta) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= meta[kMetaNAtoms]) return;
+    const int k = key_of[a];
+    if (k < 0) return;
     const int b = bucket_start[k], n = bucket_start[k + 1] - b;
-    const int p = perm_start[k];
-    for (int i0 = 0; i0 < n; i0 += 64) {
-        const int i = i0 + (int)threadIdx.x;
-        const int32_t v = i < n ? bucket_atoms[b + i] : 0;
-        int rank = 0;
-        for (int j0 = 0; j0 < n; j0 += kSortChunk) {
-            const int m = min(kSortChunk, n - j0);
-            __syncthreads();
-            for (int j = threadIdx.x; j < m; j += 64) chunk[j] = bucket_atoms[b + j0 + j];
-            __syncthreads();
-            for (int j = 0; j < m; ++j) rank += chunk[j] < v ? 1 : 0;
-        }
-        if (i < n) {
-            const int slot = p + rank;
-            perm[slot] = v;
-            slot_of[v] = slot;
-            double x = pos[3 * v], y = pos[3 * v + 1], z = pos[3 * v + 2];
-            const FrameInfo& fi = frames[frame_of[v]];
-            if (fi.tric) {
-                // triclinic frames: the wrapped fractional coordinates (as k_bin bins them)
-                double sf[3];
+    int rank = 0;
+    for (int i = 0; i < n; ++i) rank += bucket_atoms[b + i] < (int32_t)a ? 1 : 0;
+    const int slot = perm_start[k] + rank;
+    perm[slot] = (int32_t)a;
+    slot_of[a] = slot;
+    double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
+    const FrameInfo& fi = frames[frame_of[a]];
+    if (fi.tric) {
+        // triclinic frames: the wrapped fractional coordinates (as k_bin bins them)
+        double sf[3];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    sf[q] = x * fi.Hinv[q] + y * fi.Hinv[3 + q] + z * fi.Hinv[6 + q];
-                    sf[q] -= floor(sf[q]);
-                }
-                x = sf[0];
-                y = sf[1];
-                z = sf[2];
-            }
-            bucket_pos[b + rank] =
-                make_double4(x, y, z, __longlong_as_double((long long)(((uint64_t)(uint32_t)v << 32) | (uint32_t)slot)));
+        for (int q = 0; q < 3; ++q) {
+            sf[q] = x * fi.Hinv[q] + y * fi.Hinv[3 + q] + z * fi.Hinv[6 + q];
+            sf[q] -= floor(sf[q]);
         }
+        x = sf[0];
+        y = sf[1];
+        z = sf[2];
     }
+    bucket_pos[slot] = make_double4(x, y, z, __longlong_as_double((long long)((uint64_t)(uint32_t)a << 32)));
 }
 
 // Minimum image along one axis; Linv = 1/L on periodic axes, 0 otherwise.
 __device__ __forceinline__ double min_image(double d, double L, double Linv) { return d - L * rint(d * Linv); }
+
+// Distance along one axis from an atom to the cell o steps away (|o| <= 2),
+// given its distances lo, hi to its own cell's faces and the cell edge h.
+__device__ __forceinline__ float cell_gap(int o, float lo, float hi, float h) {
+    return o == 0 ? 0.f : (o < 0 ? lo + (o == -2 ? h : 0.f) : hi + (o == 2 ? h : 0.f));
+}
+
+__device__ __forceinline__ int wrap_cell(int u, int n) { return u < 0 ? u + n : (u >= n ? u - n : u); }
 
 // The entries of one (atom, neighbour species) pass: angular segment (r <
 // r_c^A) and radial-only segment.  Each lane stages four entries per segment
@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                                                       const int32_t* __restrict__ species,
                                                       const int32_t* __restrict__ slot_of,
                                                       const int32_t* __restrict__ key_of,
-                                                      const int32_t* __restrict__ bucket_start,
+                                                      const int32_t* __restrict__ perm_start,
                                                       const double4* __restrict__ bucket_pos, float rc_radial,
                                                       float rc_angular, NeighborLists nl, CandLists cl,
                                                       int32_t* __restrict__ flags) {
@@ -378,6 +378,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
     // distances from the atom to the lower / upper faces of its cell (cell list)
     float lo_x = 0, hi_x = 0, lo_y = 0, hi_y = 0, lo_z = 0, hi_z = 0;
+    float hxf = 0, hyf = 0, hzf = 0;
     if (fi.mode == 1) {
         const int local = key_of[a] / T - fi.cell_base;
         iz = local % nz;
@@ -393,6 +394,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         hi_y = (float)fmax((iy + 1) * hy - wy, 0.0);
         lo_z = (float)fmax(wz - iz * hz, 0.0);
         hi_z = (float)fmax((iz + 1) * hz - wz, 0.0);
+        hxf = (float)hx;
+        hyf = (float)hy;
+        hzf = (float)hz;
     }
     bool overlap = false;
     for (int t = 0; t < T; ++t) {
@@ -402,32 +406,52 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                     nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0};
         int n_cand = 0;
         int32_t* cand = REF ? cl.idx + ((fi.cl_base + (a - fi.atom_begin)) * T + t) * cl.cap : nullptr;
-        const int n_visit = fi.mode == 1 ? 27 : 1;
-        for (int vb = 0; vb < n_visit; ++vb) {
-            int bucket = fi.cell_base * T + t;
+        // cell grids: cells of edge >= rs / 2, so every candidate within rs is
+        // at most two cells away per axis; visited as 25 z-columns
+        const int n_col = fi.mode == 1 ? 25 : 1;
+        for (int col = 0; col < n_col; ++col) {
+            // slot ranges [b0, e0) and [b1, e1) of species t
+            int b0, e0, b1 = 0, e1 = 0;
             if (fi.mode == 1) {
-                const int ox = vb / 9 - 1, oy = (vb / 3) % 3 - 1, oz = vb % 3 - 1;
-                // skip cells whose nearest point is beyond the radial cutoff
-                const float gx = ox < 0 ? lo_x : (ox > 0 ? hi_x : 0.f);
-                const float gy = oy < 0 ? lo_y : (oy > 0 ? hi_y : 0.f);
-                const float gz = oz < 0 ? lo_z : (oz > 0 ? hi_z : 0.f);
-                if (gx * gx + gy * gy + gz * gz >= prune2) continue;
-                const int cx = (ix + ox + nx) % nx;
-                const int cy = (iy + oy + ny) % ny;
-                const int cz = (iz + oz + nz) % nz;
-                bucket = (fi.cell_base + (cx * ny + cy) * nz + cz) * T + t;
+                const int ox = col / 5 - 2, oy = col % 5 - 2;
+                // skip columns whose nearest point is beyond the search radius
+                const float gx = cell_gap(ox, lo_x, hi_x, hxf), gy = cell_gap(oy, lo_y, hi_y, hyf);
+                const float gxy = gx * gx + gy * gy;
+                if (gxy >= prune2) continue;
+                // the z-cells of the column within reach: iz - below .. iz + above
+                const float l2 = lo_z + hzf, h2 = hi_z + hzf;
+                const int z0 = iz - (gxy + lo_z * lo_z < prune2 ? 1 : 0) - (gxy + l2 * l2 < prune2 ? 1 : 0);
+                const int z1 = iz + (gxy + hi_z * hi_z < prune2 ? 1 : 0) + (gxy + h2 * h2 < prune2 ? 1 : 0);
+                const int col0 = (fi.cell_base + (wrap_cell(ix + ox, nx) * ny + wrap_cell(iy + oy, ny)) * nz) * T + t;
+                if (z0 >= 0 && z1 < nz) {
+                    b0 = perm_start[col0 + z0 * T];
+                    e0 = perm_start[col0 + (z1 + 1) * T];
+                } else {
+                    // across the box face in z (nz >= 5 keeps the two parts apart)
+                    b0 = perm_start[col0 + (z0 < 0 ? z0 + nz : z0) * T];
+                    e0 = perm_start[col0 + nz * T];
+                    b1 = perm_start[col0];
+                    e1 = perm_start[col0 + ((z1 >= nz ? z1 - nz : z1) + 1) * T];
+                }
+            } else {
+                b0 = perm_start[fi.cell_base * T + t];
+                e0 = perm_start[(fi.cell_base + 1) * T + t];
             }
-            const int b = bucket_start[bucket], e = bucket_start[bucket + 1];
+            // one loop over both ranges (candidate q is slot b0 + q for q < n0,
+            // else b1 + q - n0), so a wavefront runs as long as its longest lane
+            const int n0 = e0 - b0, n = n0 + (e1 - b1), d1 = b1 - n0;
             // candidates two at a time: both loads in flight before either is used
-            for (int k0 = b; k0 < e; k0 += 2) {
+            for (int q = 0; q < n; q += 2) {
+                const int k0 = q < n0 ? b0 + q : d1 + q;
+                const int k1 = q + 1 < n0 ? b0 + q + 1 : d1 + q + 1;
                 const double4 q0 = bucket_pos[k0];
-                const double4 q1 = k0 + 1 < e ? bucket_pos[k0 + 1] : make_double4(0.0, 0.0, 0.0, 0.0);
+                const double4 q1 = q + 1 < n ? bucket_pos[k1] : make_double4(0.0, 0.0, 0.0, 0.0);
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    if (k0 + u >= e) break;
+                    if (q + u >= n) break;
                     const double4 cur = u == 0 ? q0 : q1;
                     const uint64_t wj = (uint64_t)__double_as_longlong(cur.w);
-                    const int j = (int)(uint32_t)wj;  // tile slot of the candidate
+                    const int j = u == 0 ? k0 : k1;  // tile slot of the candidate
                     if (j == (int)p) continue;
                     const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
                     const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
@@ -549,7 +573,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                                                           const int32_t* __restrict__ frame_of,
                                                           const double* __restrict__ pos,
                                                           const int32_t* __restrict__ key_of,
-                                                          const int32_t* __restrict__ bucket_start,
+                                                          const int32_t* __restrict__ perm_start,
                                                           const double4* __restrict__ bucket_pos, float rc_radial,
                                                           float rc_angular, NeighborLists nl,
                                                           int32_t* __restrict__ flags) {
@@ -623,7 +647,8 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                 }
                 bucket = (cell_base + (cc[0] * ny + cc[1]) * nz + cc[2]) * T + t;
             }
-            const int b = bucket_start[bucket], e = bucket_start[bucket + 1];
+            // bucket (c, t) is the slot range perm_start[c T + t] .. perm_start[(c + 1) T + t]
+            const int b = perm_start[bucket], e = perm_start[bucket + T];
             // candidates two at a time: both loads in flight before either is used
             for (int k0 = b; k0 < e; k0 += 2) {
                 const double4 q0 = bucket_pos[k0];
@@ -632,7 +657,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                 for (int u = 0; u < 2; ++u) {
                     if (k0 + u >= e) break;
                     const double4 cur = u == 0 ? q0 : q1;
-                    const int j = (int)(uint32_t)(uint64_t)__double_as_longlong(cur.w);
+                    const int j = k0 + u;  // tile slot of the candidate
                     if (j == (int)p) continue;
                     double f0 = cur.x + sh[0], f1 = cur.y + sh[1], f2 = cur.z + sh[2];
                     if (mode != 1) {
@@ -716,18 +741,19 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                            w.bucket_fill, w.perm_start);
     k_scatter<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill,
                                                               w.bucket_atoms, nl.meta);
-    k_sort_place<<<cap_buckets, 64, 0, s>>>(d_frames, w.frame_of, w.bucket_start, w.bucket_atoms, w.perm_start,
-                                                                   w.perm, w.slot_of, pos, w.bucket_pos, nl.meta, T);
+    k_sort_place<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, w.key_of, w.bucket_start,
+                                                                 w.bucket_atoms, w.perm_start, w.perm, w.slot_of, pos,
+                                                                 w.bucket_pos, nl.meta);
     const size_t stage_bytes = sizeof(float4) * 8 * nb;
     k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
-                                                              w.key_of, w.bucket_start, w.bucket_pos, rc_radial,
+                                                              w.key_of, w.perm_start, w.bucket_pos, rc_radial,
                                                               rc_angular, nl, cl, d_flags);
     if (references)
         k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
-                                                                 w.key_of, w.bucket_start, w.bucket_pos, rc_radial,
+                                                                 w.key_of, w.perm_start, w.bucket_pos, rc_radial,
                                                                  rc_angular, nl, cl, d_flags);
     if (triclinic)
-        k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, w.key_of, w.bucket_start,
+        k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, w.key_of, w.perm_start,
                                                                w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
     if (followers)
         k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,

@@ -167,7 +167,8 @@ struct FrameGeom {
     int n_cells() const { return mode == 1 ? nc[0] * nc[1] * nc[2] : 0; }
 };
 
-int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc_radial, FrameGeom& g);
+int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc_radial, int64_t n_atoms,
+                   FrameGeom& g);
 // Message for tnep_last_error(NULL) (calls without a context, on this thread).
 void set_create_error(const std::string& msg);
 int run_eval(Ctx* c, const tnep_frames& frames, const EvalJob& job);
