@@ -329,7 +329,62 @@ struct PairSink {
         flush_one(na, capA, ga, stage);
         flush_one(nr, capR, gr, stage + 4 * stride);
     }
+
+    // Deferred form of push: a completed group is not stored by its lane but
+    // left for the wave's next coop_flush (pend_src = LDS index of its first
+    // entry relative to lds, pend_dst = its destination).
+    int pend_src;
+    float4* pend_dst;
+    __device__ __forceinline__ void push_deferred(const float4& e, bool ang, const float4* lds) {
+        const int n = ang ? na : nr;
+        const int s4 = ang ? 0 : 4;
+        stage[(s4 + (n & 3)) * stride] = e;
+        const int m = n + 1;
+        if (ang)
+            na = m;
+        else
+            nr = m;
+        if ((m & 3) == 0 && m <= (ang ? capA : capR)) {
+            pend_dst = (ang ? ga : gr) + (int64_t)((m - 4) >> 2) * 256;
+            pend_src = (int)(stage + s4 * stride - lds);
+        }
+    }
 };
+
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Cooperative store of the groups that lanes completed since the last call
+// (every active lane calls it): each completing lane posts (destination, LDS
+// source) to the wave's list, then the active lanes store one 16-byte quarter
+// of a group each, so a 64-byte group leaves as one coalesced request and one
+// store instruction carries up to 16 groups (instead of four sparse store
+// instructions per completing lane).  LDS accesses of one wave complete in
+// order, so the list and the staged entries are read after they are written.
+__device__ __forceinline__ void coop_flush(PairSink& ps, const float4* lds, int4* list) {
+    const bool mine = ps.pend_src >= 0;
+    const uint64_t pend = __ballot(mine);
+    if (pend == 0) return;
+    const uint64_t act = __ballot(1);
+    if (mine) {
+        const uint64_t d = (uint64_t)ps.pend_dst;
+        list[lanes_below(pend)] = make_int4((int)(uint32_t)d, (int)(uint32_t)(d >> 32), ps.pend_src, 0);
+        ps.pend_src = -1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int rank = lanes_below(act), n_act = __popcll(act), pieces = 4 * __popcll(pend);
+    for (int pb = 0; pb < pieces; pb += n_act) {
+        const int piece = pb + rank;
+        if (piece < pieces) {
+            const int4 L = list[piece >> 2];
+            const int part = piece & 3;
+            float4* dst = (float4*)(((uint64_t)(uint32_t)L.y << 32) | (uint32_t)L.x) + part;
+            *dst = lds[L.z + part * ps.stride];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
 
 // Four waves per SIMD (<= 128 VGPRs): the candidate loop is bound by load
 // latency, so occupancy matters more than anything the registers could buy.
@@ -346,8 +401,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                                                       const double4* __restrict__ bucket_pos, float rc_radial,
                                                       float rc_angular, NeighborLists nl, CandLists cl,
                                                       int32_t* __restrict__ flags) {
-    extern __shared__ float4 nb_stage[];  // 8 entries per lane (PairSink)
+    // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
+    extern __shared__ float4 nb_stage[];
     float4* stage = nb_stage + threadIdx.x;
+    int4* list = reinterpret_cast<int4*>(nb_stage + 8 * blockDim.x) + (threadIdx.x & ~63u);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nl.n_pad) return;
     const int T = nl.T;
@@ -403,7 +460,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         PairSink ps{stage, (int)blockDim.x,
                     lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
                     lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
-                    nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0};
+                    nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0, -1, nullptr};
         int n_cand = 0;
         int32_t* cand = REF ? cl.idx + ((fi.cl_base + (a - fi.atom_begin)) * T + t) * cl.cap : nullptr;
         // cell grids: cells of edge >= rs / 2, so every candidate within rs is
@@ -448,23 +505,27 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                 const double4 q1 = q + 1 < n ? bucket_pos[k1] : make_double4(0.0, 0.0, 0.0, 0.0);
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    if (q + u >= n) break;
                     const double4 cur = u == 0 ? q0 : q1;
                     const uint64_t wj = (uint64_t)__double_as_longlong(cur.w);
                     const int j = u == 0 ? k0 : k1;  // tile slot of the candidate
-                    if (j == (int)p) continue;
                     const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
                     const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
                     const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 >= rcs2) continue;
-                    if constexpr (REF) {
-                        if (n_cand < cl.cap) cand[n_cand] = (int)(wj >> 32) - (int)fi.atom_begin;
-                        ++n_cand;
+                    // one branch per candidate: a real candidate, not the atom itself, within reach
+                    const bool in = (q + u < n) & (j != (int)p) & (r2 < rcs2);
+                    if (in) {
+                        if constexpr (REF) {
+                            if (n_cand < cl.cap) cand[n_cand] = (int)(wj >> 32) - (int)fi.atom_begin;
+                            ++n_cand;
+                        }
+                        if (!REF || r2 < rc2r) {
+                            overlap |= r2 < 1e-8;
+                            ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)),
+                                             r2 < rc2a, nb_stage);
+                        }
                     }
-                    if (r2 >= rc2r) continue;
-                    if (r2 < 1e-8) overlap = true;
-                    ps.push(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)), r2 < rc2a);
+                    coop_flush(ps, nb_stage, list);
                 }
             }
         }
@@ -519,7 +580,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
         PairSink ps{stage, (int)blockDim.x,
                     lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
                     lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
-                    nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0};
+                    nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0, -1, nullptr};
         const int64_t list = (fi.cl_base + il) * T + t;
         const int n = min(cl.count[list], cl.cap);
         const int4* idx4 = reinterpret_cast<const int4*>(cl.idx + list * cl.cap);
@@ -623,7 +684,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
         PairSink ps{stage, (int)blockDim.x,
                     lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
                     lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
-                    nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0};
+                    nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0, -1, nullptr};
         const int n_visit = mode == 1 ? 27 : 1;
         for (int vb = 0; vb < n_visit; ++vb) {
             int bucket = cell_base * T + t;
@@ -745,11 +806,12 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                                                  w.bucket_atoms, w.perm_start, w.perm, w.slot_of, pos,
                                                                  w.bucket_pos, nl.meta);
     const size_t stage_bytes = sizeof(float4) * 8 * nb;
-    k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+    const size_t list_bytes = sizeof(float4) * 9 * nb;  // staging + per-wave flush lists
+    k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                               w.key_of, w.perm_start, w.bucket_pos, rc_radial,
                                                               rc_angular, nl, cl, d_flags);
     if (references)
-        k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+        k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                  w.key_of, w.perm_start, w.bucket_pos, rc_radial,
                                                                  rc_angular, nl, cl, d_flags);
     if (triclinic)
