@@ -488,7 +488,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if ((e = c->reserve(c->slot_of, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->key_of, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->bucket_atoms, (size_t)B_res * 4))) return e;
-            if ((e = c->reserve(c->bucket_pos, (size_t)n_pad_max * 32))) return e;  // indexed by tile slot
+            // by tile slot: FP64 positions, then the 16-byte cell records
+            if ((e = c->reserve(c->bucket_pos, (size_t)n_pad_max * 48))) return e;
             if ((e = c->reserve(c->per_atom, (size_t)B_res * 10 * sizeof(double) * (last - first)))) return e;
             if (pes) {
                 if ((e = c->reserve(c->pes_rec, (size_t)n_pad_max * rec_stride * sizeof(float)))) return e;
@@ -561,6 +562,13 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         x.Linv[d] = (g.per[d] && !g.tric) ? 1.0 / g.L[d] : 0.0;
                     }
                     x.tric = g.tric;
+                    if (g.mode == 1 && !g.tric) {
+                        // fixed-point unit of the cell records: offsets within a cell stay below 2^30 units
+                        double hmax = 0;
+                        for (int d = 0; d < 3; ++d) hmax = std::max(hmax, g.L[d] / g.nc[d]);
+                        const int kq = std::min(60, std::max(0, (int)std::floor(std::log2(std::ldexp(1.0, 30) / hmax))));
+                        x.q_unit = std::ldexp(1.0, -kq);
+                    }
                     if (g.tric) {
                         triclinic = true;
                         for (int i = 0; i < 9; ++i) {
@@ -613,7 +621,9 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 }
                 NeighborWork w{(int32_t*)c->frame_of.p,     (int32_t*)c->key_of.p,       (int32_t*)c->bucket_count.p,
                                (int32_t*)c->bucket_start.p, (int32_t*)c->bucket_fill.p,  (int32_t*)c->bucket_atoms.p,
-                               (double4*)c->bucket_pos.p,   (int32_t*)c->perm_start.p,   (int32_t*)c->perm.p,
+                               (double4*)c->bucket_pos.p,
+                               (int4*)((char*)c->bucket_pos.p + (size_t)n_pad_max * 32),
+                               (int32_t*)c->perm_start.p,   (int32_t*)c->perm.p,
                                (int32_t*)c->tile_base.p,    (int32_t*)c->scan_chunks.p,  (int32_t*)c->slot_of.p};
                 const CandLists cl{(int32_t*)c->cand.p, (int32_t*)c->cand_count.p, c->cap_cand,
                                    (float)rc_search, (float)(0.25 * c->skin * c->skin)};

@@ -34,6 +34,9 @@ struct FrameInfo {
     int32_t tric;
     int32_t pad_;
     double H[9], Hinv[9], w[3];
+    // Orthorhombic cell grids: unit (a power of two, A) of the fixed-point
+    // offsets from the cell origin in the candidate records.
+    double q_unit;
 };
 
 // Device-resident FP32 model parameters.
@@ -133,7 +136,8 @@ struct NeighborWork {
     int32_t* bucket_start;  // [n_buckets + 1]
     int32_t* bucket_fill;   // [n_buckets]
     int32_t* bucket_atoms;  // [n_atoms]
-    double4* bucket_pos;    // [n_atoms] positions in bucket order, w = atom index
+    double4* bucket_pos;    // [n_pad] FP64 positions by tile slot (frames without an orthorhombic cell grid)
+    int4* cell_rec;         // [n_pad] orthorhombic cell grids: (q_x, q_y, q_z, cell z) by tile slot
     int32_t* perm_start;    // [n_buckets]
     int32_t* perm;          // [n_pad]
     int32_t* meta;          // [kMetaInts], tile_base part written on the device

@@ -3,7 +3,8 @@
 // The sums over j != i of the method (Sec. 2.1, Eq. virial; Sec. 2.2, Eq. mu;
 // Sec. 2.3, Eq. polarizability-model) run over the atoms inside the radial
 // cutoff.  Pair vectors are formed in FP64 with the minimum-image convention
-// and stored as FP32.
+// (on orthorhombic cell grids from fixed-point offsets within the cells, to
+// within 2^-30 of a cell edge) and stored as FP32.
 //
 // Pipeline (all on the device):
 //   1. bin every atom into a bucket (cell, species).  Fully periodic
@@ -241,14 +242,19 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 
 // Place every atom into the tile permutation at (first slot of its bucket) +
 // (number of smaller atom indices in its bucket) and store its position at
-// that slot (w = the atom's batch index in the high 32 bits).  One thread per
-// atom: buckets hold a few atoms on cell grids and a whole frame otherwise, so
-// the rank loop is never longer than the frame's own neighbour loop.
+// that slot.  One thread per atom: buckets hold a few atoms on cell grids and
+// a whole frame otherwise, so the rank loop is never longer than the frame's
+// own neighbour loop.  Orthorhombic cell grids get a 16-byte record: the
+// offsets of the wrapped position from its cell's origin as integers in units
+// of q_unit (a power of two, so the scaling is exact), and the cell's z index;
+// all other frames the FP64 position (triclinic frames: wrapped fractional
+// coordinates).
 __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ frame_of,
                              const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
                              const int32_t* __restrict__ bucket_atoms, const int32_t* __restrict__ perm_start,
                              int32_t* __restrict__ perm, int32_t* __restrict__ slot_of, const double* __restrict__ pos,
-                             double4* __restrict__ bucket_pos, const int32_t* __restrict__ meta) {
+                             double4* __restrict__ bucket_pos, int4* __restrict__ cell_rec,
+                             const int32_t* __restrict__ meta, int T) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= meta[kMetaNAtoms]) return;
     const int k = key_of[a];
@@ -261,6 +267,20 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t
     slot_of[a] = slot;
     double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
     const FrameInfo& fi = frames[frame_of[a]];
+    if (fi.mode == 1 && !fi.tric) {
+        const int local = k / T - fi.cell_base;
+        const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
+        const int c[3] = {local / (nz * ny), (local / nz) % ny, local % nz};
+        const double r[3] = {x, y, z};
+        int q[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double s = r[d] - fi.L[d] * floor(r[d] * fi.Linv[d]);
+            q[d] = (int)rint((s - c[d] * (fi.L[d] / fi.nc[d])) / fi.q_unit);
+        }
+        cell_rec[slot] = make_int4(q[0], q[1], q[2], c[2]);
+        return;
+    }
     if (fi.tric) {
         // triclinic frames: the wrapped fractional coordinates (as k_bin bins them)
         double sf[3];
@@ -273,7 +293,7 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t
         y = sf[1];
         z = sf[2];
     }
-    bucket_pos[slot] = make_double4(x, y, z, __longlong_as_double((long long)((uint64_t)(uint32_t)a << 32)));
+    bucket_pos[slot] = make_double4(x, y, z, 0.0);
 }
 
 // Minimum image along one axis; Linv = 1/L on periodic axes, 0 otherwise.
@@ -386,6 +406,24 @@ __device__ __forceinline__ void coop_flush(PairSink& ps, const float4* lds, int4
     __builtin_amdgcn_wave_barrier();
 }
 
+// One candidate of k_neighbors: pair vector d = r_j - r_i (FP64), in = a real
+// candidate other than the atom itself within the search radius.
+template <bool REF>
+__device__ __forceinline__ void take_candidate(PairSink& ps, const float4* lds, bool in, double dx, double dy, double dz,
+                                               double r2, int j, double rc2r, double rc2a, bool& overlap, int& n_cand,
+                                               int32_t* cand, int cand_cap, const int32_t* perm, int atom_begin) {
+    if (in) {
+        if constexpr (REF) {
+            if (n_cand < cand_cap) cand[n_cand] = perm[j] - atom_begin;
+            ++n_cand;
+        }
+        if (!REF || r2 < rc2r) {
+            overlap |= r2 < 1e-8;
+            ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)), r2 < rc2a, lds);
+        }
+    }
+}
+
 // Four waves per SIMD (<= 128 VGPRs): the candidate loop is bound by load
 // latency, so occupancy matters more than anything the registers could buy.
 // REF = false: plain frames and padding slots; REF = true: reference frames,
@@ -398,7 +436,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                                                       const int32_t* __restrict__ slot_of,
                                                       const int32_t* __restrict__ key_of,
                                                       const int32_t* __restrict__ perm_start,
-                                                      const double4* __restrict__ bucket_pos, float rc_radial,
+                                                      const double4* __restrict__ bucket_pos,
+                                                      const int4* __restrict__ cell_rec, float rc_radial,
                                                       float rc_angular, NeighborLists nl, CandLists cl,
                                                       int32_t* __restrict__ flags) {
     // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
@@ -436,12 +475,17 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     // distances from the atom to the lower / upper faces of its cell (cell list)
     float lo_x = 0, hi_x = 0, lo_y = 0, hi_y = 0, lo_z = 0, hi_z = 0;
     float hxf = 0, hyf = 0, hzf = 0;
+    double hx = 0, hy = 0, hz = 0;
+    int4 own = make_int4(0, 0, 0, 0);  // the atom's own cell record
     if (fi.mode == 1) {
+        own = cell_rec[p];
         const int local = key_of[a] / T - fi.cell_base;
         iz = local % nz;
         iy = (local / nz) % ny;
         ix = local / (nz * ny);
-        const double hx = fi.L[0] / nx, hy = fi.L[1] / ny, hz = fi.L[2] / nz;
+        hx = fi.L[0] / nx;
+        hy = fi.L[1] / ny;
+        hz = fi.L[2] / nz;
         const double wx = xi - fi.L[0] * floor(xi * fi.Linv[0]);
         const double wy = yi - fi.L[1] * floor(yi * fi.Linv[1]);
         const double wz = zi - fi.L[2] * floor(zi * fi.Linv[2]);
@@ -469,8 +513,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         for (int col = 0; col < n_col; ++col) {
             // slot ranges [b0, e0) and [b1, e1) of species t
             int b0, e0, b1 = 0, e1 = 0;
+            int ox = 0, oy = 0;
             if (fi.mode == 1) {
-                const int ox = col / 5 - 2, oy = col % 5 - 2;
+                ox = col / 5 - 2;
+                oy = col % 5 - 2;
                 // skip columns whose nearest point is beyond the search radius
                 const float gx = cell_gap(ox, lo_x, hi_x, hxf), gy = cell_gap(oy, lo_y, hi_y, hyf);
                 const float gxy = gx * gx + gy * gy;
@@ -497,35 +543,49 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
             // one loop over both ranges (candidate q is slot b0 + q for q < n0,
             // else b1 + q - n0), so a wavefront runs as long as its longest lane
             const int n0 = e0 - b0, n = n0 + (e1 - b1), d1 = b1 - n0;
-            // candidates two at a time: both loads in flight before either is used
-            for (int q = 0; q < n; q += 2) {
-                const int k0 = q < n0 ? b0 + q : d1 + q;
-                const int k1 = q + 1 < n0 ? b0 + q + 1 : d1 + q + 1;
-                const double4 q0 = bucket_pos[k0];
-                const double4 q1 = q + 1 < n ? bucket_pos[k1] : make_double4(0.0, 0.0, 0.0, 0.0);
+            if (fi.mode == 1) {
+                // pair vector from the cell records: (cell offset) h + (q_j - q_i) q_unit
+                const double offx = ox * hx, offy = oy * hy, qu = fi.q_unit;
+                for (int q = 0; q < n; q += 2) {
+                    const int k0 = q < n0 ? b0 + q : d1 + q;
+                    const int k1 = q + 1 < n0 ? b0 + q + 1 : d1 + q + 1;
+                    const int4 c0 = cell_rec[k0];
+                    const int4 c1 = q + 1 < n ? cell_rec[k1] : make_int4(0, 0, 0, 0);
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const double4 cur = u == 0 ? q0 : q1;
-                    const uint64_t wj = (uint64_t)__double_as_longlong(cur.w);
-                    const int j = u == 0 ? k0 : k1;  // tile slot of the candidate
-                    const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
-                    const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
-                    const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    // one branch per candidate: a real candidate, not the atom itself, within reach
-                    const bool in = (q + u < n) & (j != (int)p) & (r2 < rcs2);
-                    if (in) {
-                        if constexpr (REF) {
-                            if (n_cand < cl.cap) cand[n_cand] = (int)(wj >> 32) - (int)fi.atom_begin;
-                            ++n_cand;
-                        }
-                        if (!REF || r2 < rc2r) {
-                            overlap |= r2 < 1e-8;
-                            ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)),
-                                             r2 < rc2a, nb_stage);
-                        }
+                    for (int u = 0; u < 2; ++u) {
+                        const int4 cr = u == 0 ? c0 : c1;
+                        const int j = u == 0 ? k0 : k1;  // tile slot of the candidate
+                        int oz = cr.w - iz;
+                        oz = oz > 2 ? oz - nz : (oz < -2 ? oz + nz : oz);
+                        const double dx = fma((double)(cr.x - own.x), qu, offx);
+                        const double dy = fma((double)(cr.y - own.y), qu, offy);
+                        const double dz = fma((double)(cr.z - own.z), qu, oz * hz);
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        take_candidate<REF>(ps, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2), dx, dy, dz, r2,
+                                            j, rc2r, rc2a, overlap, n_cand, cand, cl.cap, nl.perm,
+                                            (int)fi.atom_begin);
+                        coop_flush(ps, nb_stage, list);
                     }
-                    coop_flush(ps, nb_stage, list);
+                }
+            } else {
+                // one cell per frame: FP64 positions and the rounding minimum image
+                for (int q = 0; q < n; q += 2) {
+                    const int k0 = b0 + q, k1 = b0 + q + 1;
+                    const double4 q0 = bucket_pos[k0];
+                    const double4 q1 = q + 1 < n ? bucket_pos[k1] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const double4 cur = u == 0 ? q0 : q1;
+                        const int j = u == 0 ? k0 : k1;
+                        const double dx = min_image(cur.x - xi, fi.L[0], fi.Linv[0]);
+                        const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
+                        const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        take_candidate<REF>(ps, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2), dx, dy, dz, r2,
+                                            j, rc2r, rc2a, overlap, n_cand, cand, cl.cap, nl.perm,
+                                            (int)fi.atom_begin);
+                        coop_flush(ps, nb_stage, list);
+                    }
                 }
             }
         }
@@ -804,16 +864,16 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                                               w.bucket_atoms, nl.meta);
     k_sort_place<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, w.key_of, w.bucket_start,
                                                                  w.bucket_atoms, w.perm_start, w.perm, w.slot_of, pos,
-                                                                 w.bucket_pos, nl.meta);
+                                                                 w.bucket_pos, w.cell_rec, nl.meta, T);
     const size_t stage_bytes = sizeof(float4) * 8 * nb;
     const size_t list_bytes = sizeof(float4) * 9 * nb;  // staging + per-wave flush lists
     k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
-                                                              w.key_of, w.perm_start, w.bucket_pos, rc_radial,
-                                                              rc_angular, nl, cl, d_flags);
+                                                              w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
+                                                              rc_radial, rc_angular, nl, cl, d_flags);
     if (references)
         k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
-                                                                 w.key_of, w.perm_start, w.bucket_pos, rc_radial,
-                                                                 rc_angular, nl, cl, d_flags);
+                                                                 w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
+                                                                 rc_radial, rc_angular, nl, cl, d_flags);
     if (triclinic)
         k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, w.key_of, w.perm_start,
                                                                w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
