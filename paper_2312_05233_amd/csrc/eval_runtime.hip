@@ -598,6 +598,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if ((e = c->reserve(c->scan_chunks, (size_t)4 * 18 * (cap_cells / 1024 + 1)))) return e;
                 const int nt_max = 10;
                 if ((e = c->reserve(c->out, sizeof(double) * nt_max * cap_frames * (last - first)))) return e;
+                if ((e = c->reserve(c->red_part, sizeof(double) * 10 * kReduceChunks * cap_frames))) return e;
                 bh.sizes[0] = (int32_t)na;
                 bh.sizes[1] = nf;
                 bh.sizes[2] = n_cells;
@@ -690,7 +691,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         if (he != hipSuccess) return he;
                         tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);
                         he = launch_frame_reduce((const FrameInfo*)c->frames.p, cap_frames, nl.meta, pa_of[q],
-                                                 nt_of[q], na_of[q], out_of[q], aux_of[q], c->stream);
+                                                 nt_of[q], na_of[q], (double*)c->red_part.p, out_of[q], aux_of[q],
+                                                 c->stream);
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;
                         if (m->kind == TNEP_KIND_PES) {

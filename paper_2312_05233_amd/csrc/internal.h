@@ -204,9 +204,11 @@ hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* count
 // Per-frame sums of per-atom records (nt <= 10 values) in a fixed order:
 // values 0..na-1 go to out_a[f][na], values na..nt-1 to out_b[f][nt - na]
 // (out_b may be NULL).  Frames beyond meta[kMetaNFrames] are skipped
-// (cap_frames sizes the grid).
+// (cap_frames sizes the grid).  part: scratch of kReduceChunks * 10 doubles
+// per frame.
+constexpr int kReduceChunks = 4;
 hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const int32_t* meta, const double* per_atom,
-                               int nt, int na, double* out_a, double* out_b, hipStream_t s);
+                               int nt, int na, double* part, double* out_a, double* out_b, hipStream_t s);
 
 // ---- spectra (kernels_spectrum.hip) ----
 struct SpectrumPlan {

@@ -711,25 +711,30 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     }
 }
 
-// One work-group of 1024 lanes per frame: lane l sums atoms l, l + 1024, ...
-// in FP64, then a fixed tree: within each wavefront by shuffles, then over
-// the 16 wavefronts in LDS.  The order depends only on the frame's atom
-// count, never on how frames were batched.
-constexpr int kReduceBlock = 1024;
+// Frame sums in two steps.  k_frame_reduce: work-group (f, c) sums chunk c of
+// frame f (atoms [c L, (c + 1) L), L = ceil(n / kReduceChunks)): lane l takes
+// atoms l, l + 256, ... of the chunk in FP64, then a fixed tree, within each
+// wavefront by shuffles and over the 4 wavefronts in LDS.  k_frame_finish adds
+// the chunk sums in chunk order.  The order depends only on the frame's atom
+// count, never on how frames were batched; the chunks spread a launch batch of
+// large frames over all compute units.
+constexpr int kReduceBlock = 256;
 __global__ void __launch_bounds__(kReduceBlock) k_frame_reduce(const FrameInfo* __restrict__ frames,
                                                                const int32_t* __restrict__ meta,
-                                                               const double* __restrict__ per_atom, int nt, int na,
-                                                               double* __restrict__ out_a, double* __restrict__ out_b) {
+                                                               const double* __restrict__ per_atom, int nt,
+                                                               double* __restrict__ part_out) {
     constexpr int kWaves = kReduceBlock / 64;
     __shared__ double part[10][kWaves];
-    const int f = blockIdx.x;
+    const int f = blockIdx.x, c = blockIdx.y;
     if (f >= meta[kMetaNFrames]) return;
     const FrameInfo fi = frames[f];
+    const int64_t len = (fi.n_atoms + kReduceChunks - 1) / kReduceChunks;
+    const int64_t a0 = c * len, a1 = min((int64_t)fi.n_atoms, a0 + len);
     const int lane = threadIdx.x;
     double s[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) s[k] = 0.0;
-    for (int64_t a = lane; a < fi.n_atoms; a += kReduceBlock) {
+    for (int64_t a = a0 + lane; a < a1; a += kReduceBlock) {
         const double* q = per_atom + (fi.atom_begin + a) * nt;
 #pragma unroll
         for (int k = 0; k < 10; ++k)
@@ -749,11 +754,22 @@ __global__ void __launch_bounds__(kReduceBlock) k_frame_reduce(const FrameInfo* 
         double v = 0.0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) v += part[lane][w];
-        if (lane < na)
-            out_a[(int64_t)f * na + lane] = v;
-        else if (out_b)
-            out_b[(int64_t)f * (nt - na) + lane - na] = v;
+        part_out[((int64_t)f * kReduceChunks + c) * 10 + lane] = v;
     }
+}
+
+__global__ void k_frame_finish(const int32_t* __restrict__ meta, const double* __restrict__ part, int nt, int na,
+                               double* __restrict__ out_a, double* __restrict__ out_b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = (int)(i / nt), k = (int)(i % nt);
+    if (f >= meta[kMetaNFrames]) return;
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < kReduceChunks; ++c) v += part[((int64_t)f * kReduceChunks + c) * 10 + k];
+    if (k < na)
+        out_a[(int64_t)f * na + k] = v;
+    else if (out_b)
+        out_b[(int64_t)f * (nt - na) + k - na] = v;
 }
 
 // Charged molecules (the dipole of a charged system depends on the reference
@@ -1025,9 +1041,11 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
 }
 
 hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const int32_t* meta, const double* per_atom,
-                               int nt, int na, double* out_a, double* out_b, hipStream_t s) {
+                               int nt, int na, double* part, double* out_a, double* out_b, hipStream_t s) {
     if (cap_frames == 0) return hipSuccess;
-    k_frame_reduce<<<cap_frames, kReduceBlock, 0, s>>>(d_frames, meta, per_atom, nt, na, out_a, out_b);
+    k_frame_reduce<<<dim3(cap_frames, kReduceChunks), kReduceBlock, 0, s>>>(d_frames, meta, per_atom, nt, part);
+    const int64_t n = (int64_t)cap_frames * nt;
+    k_frame_finish<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(meta, part, nt, na, out_a, out_b);
     return hipGetLastError();
 }
 
