@@ -157,20 +157,23 @@ int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double
         all = all && g.per[d];
     }
     if (all) {
-        // cells of edge >= rc / 2 (the search reaches two cells each way), at
-        // least five per axis so that the reach holds distinct cells; a sparse
-        // frame gets larger cells (about two cells per atom at most)
+        // cells of edge >= rc / reach along each axis (the search reaches that
+        // many cells each way), at least 2 reach + 1 cells per axis so that the
+        // reach holds distinct cells; a sparse frame gets larger cells (about
+        // two cells per atom at most)
+        const int reach[3] = {kCellReachXY, kCellReachXY, kCellReachZ};
         bool ok = true;
         for (int d = 0; d < 3; ++d) {
-            g.nc[d] = (int)std::min(512.0, std::floor(2.0 * g.L[d] / rc));
-            ok = ok && g.nc[d] >= 5;
+            g.nc[d] = (int)std::min(1024.0, std::floor(reach[d] * g.L[d] / rc));
+            ok = ok && g.nc[d] >= 2 * reach[d] + 1;
         }
         if (ok) {
-            const double lim = std::max(2.0 * (double)n_atoms, 125.0);
+            const double lim = std::max(2.0 * (double)n_atoms,
+                                        (2.0 * reach[0] + 1) * (2.0 * reach[1] + 1) * (2.0 * reach[2] + 1));
             const double prod = (double)g.nc[0] * g.nc[1] * g.nc[2];
             if (prod > lim) {
                 const double s = std::cbrt(prod / lim);
-                for (int d = 0; d < 3; ++d) g.nc[d] = std::max(5, (int)std::floor(g.nc[d] / s));
+                for (int d = 0; d < 3; ++d) g.nc[d] = std::max(2 * reach[d] + 1, (int)std::floor(g.nc[d] / s));
             }
             g.mode = 1;
         }

@@ -16,6 +16,12 @@ namespace tnep {
 // image) and kept its species, else the call is redone with plain searches.
 enum FrameRole { kRolePlain = 0, kRoleReference = 1, kRoleFollower = 2 };
 
+// Orthorhombic cell grids: cells of edge >= r / kCellReachXY along x, y and
+// >= r / kCellReachZ along z for the search radius r, so every neighbour lies
+// within that many cells of the atom's own cell along each axis.
+constexpr int kCellReachXY = 2;
+constexpr int kCellReachZ = 2;
+
 struct FrameInfo {
     int64_t atom_begin;  // first atom, batch-local index
     int32_t n_atoms;

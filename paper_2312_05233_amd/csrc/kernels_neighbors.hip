@@ -8,10 +8,10 @@
 //
 // Pipeline (all on the device):
 //   1. bin every atom into a bucket (cell, species).  Fully periodic
-//      orthorhombic frames with >= 5 cells of edge >= rc_radial / 2 per axis
-//      use a cell grid, triclinic ones a grid of >= 3 bins of width >=
-//      rc_radial per axis; every other frame (vacuum molecules, small boxes) is
-//      one cell;
+//      orthorhombic frames use a cell grid of edge >= rc_radial / 2 (at least
+//      5 cells per axis), triclinic ones
+//      a grid of >= 3 bins of width >= rc_radial per axis; every other frame
+//      (vacuum molecules, small boxes) is one cell;
 //   2. scan the bucket counts twice: in (cell, species) order for the
 //      scatter and in (species, cell) order for the atom tiles;
 //   3. scatter atoms into buckets; each atom's place in its bucket is its rank
@@ -301,6 +301,7 @@ __device__ __forceinline__ double min_image(double d, double L, double Linv) { r
 
 // Distance along one axis from an atom to the cell o steps away (|o| <= 2),
 // given its distances lo, hi to its own cell's faces and the cell edge h.
+static_assert(kCellReachXY == 2, "the column walk visits the 5 x 5 columns within two cells");
 __device__ __forceinline__ float cell_gap(int o, float lo, float hi, float h) {
     return o == 0 ? 0.f : (o < 0 ? lo + (o == -2 ? h : 0.f) : hi + (o == 2 ? h : 0.f));
 }
@@ -474,7 +475,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
     // distances from the atom to the lower / upper faces of its cell (cell list)
     float lo_x = 0, hi_x = 0, lo_y = 0, hi_y = 0, lo_z = 0, hi_z = 0;
-    float hxf = 0, hyf = 0, hzf = 0;
+    float hxf = 0, hyf = 0, hz_inv = 0;
     double hx = 0, hy = 0, hz = 0;
     int4 own = make_int4(0, 0, 0, 0);  // the atom's own cell record
     if (fi.mode == 1) {
@@ -497,7 +498,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         hi_z = (float)fmax((iz + 1) * hz - wz, 0.0);
         hxf = (float)hx;
         hyf = (float)hy;
-        hzf = (float)hz;
+        hz_inv = (float)(1.0 / hz);
     }
     bool overlap = false;
     for (int t = 0; t < T; ++t) {
@@ -507,8 +508,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                     nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0, -1, nullptr};
         int n_cand = 0;
         int32_t* cand = REF ? cl.idx + ((fi.cl_base + (a - fi.atom_begin)) * T + t) * cl.cap : nullptr;
-        // cell grids: cells of edge >= rs / 2, so every candidate within rs is
-        // at most two cells away per axis; visited as 25 z-columns
+        // cell grids: every candidate within rs is at most kCellReachXY cells
+        // away along x, y and kCellReachZ along z; visited as 25 z-columns
         const int n_col = fi.mode == 1 ? 25 : 1;
         for (int col = 0; col < n_col; ++col) {
             // slot ranges [b0, e0) and [b1, e1) of species t
@@ -521,16 +522,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                 const float gx = cell_gap(ox, lo_x, hi_x, hxf), gy = cell_gap(oy, lo_y, hi_y, hyf);
                 const float gxy = gx * gx + gy * gy;
                 if (gxy >= prune2) continue;
-                // the z-cells of the column within reach: iz - below .. iz + above
-                const float l2 = lo_z + hzf, h2 = hi_z + hzf;
-                const int z0 = iz - (gxy + lo_z * lo_z < prune2 ? 1 : 0) - (gxy + l2 * l2 < prune2 ? 1 : 0);
-                const int z1 = iz + (gxy + hi_z * hi_z < prune2 ? 1 : 0) + (gxy + h2 * h2 < prune2 ? 1 : 0);
+                // the z-cells of the column within reach, iz - below .. iz + above:
+                // cell iz - k is in reach when lo_z + (k - 1) hz < dz = sqrt(prune2 - gxy)
+                const float dz_left = __builtin_amdgcn_sqrtf(prune2 - gxy);
+                const int below = min(kCellReachZ, max(0, (int)floorf((dz_left - lo_z) * hz_inv) + 1));
+                const int above = min(kCellReachZ, max(0, (int)floorf((dz_left - hi_z) * hz_inv) + 1));
+                const int z0 = iz - below, z1 = iz + above;
                 const int col0 = (fi.cell_base + (wrap_cell(ix + ox, nx) * ny + wrap_cell(iy + oy, ny)) * nz) * T + t;
                 if (z0 >= 0 && z1 < nz) {
                     b0 = perm_start[col0 + z0 * T];
                     e0 = perm_start[col0 + (z1 + 1) * T];
                 } else {
-                    // across the box face in z (nz >= 5 keeps the two parts apart)
+                    // across the box face in z (nz >= 2 kCellReachZ + 1 keeps the two parts apart)
                     b0 = perm_start[col0 + (z0 < 0 ? z0 + nz : z0) * T];
                     e0 = perm_start[col0 + nz * T];
                     b1 = perm_start[col0];
@@ -556,7 +559,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                         const int4 cr = u == 0 ? c0 : c1;
                         const int j = u == 0 ? k0 : k1;  // tile slot of the candidate
                         int oz = cr.w - iz;
-                        oz = oz > 2 ? oz - nz : (oz < -2 ? oz + nz : oz);
+                        oz = oz > kCellReachZ ? oz - nz : (oz < -kCellReachZ ? oz + nz : oz);
                         const double dx = fma((double)(cr.x - own.x), qu, offx);
                         const double dy = fma((double)(cr.y - own.y), qu, offy);
                         const double dz = fma((double)(cr.z - own.z), qu, oz * hz);
