@@ -122,6 +122,7 @@ tnep::Ctx::~Ctx() {
     for (hipEvent_t ev : event_pool) (void)hipEventDestroy(ev);
     for (DevBuf* b : all_buffers()) release(*b);
     if (h_flags) (void)hipHostFree(h_flags);
+    if (meta_host) (void)hipHostFree(meta_host);
     if (pop_host) (void)hipHostFree(pop_host);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

@@ -510,12 +510,20 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             }
             HIP_CHECK_RET(c, launch_init_flags((int32_t*)c->flags.p, c->stream));
 
-            // host FrameInfo and batch sizes per batch, alive until the sync below
-            struct BatchHost {
-                std::vector<FrameInfo> fi;
-                int32_t sizes[4];
-            };
-            std::vector<std::unique_ptr<BatchHost>> keep;
+            // FrameInfo and sizes of every launch batch, staged in pinned host
+            // memory (alive until the sync below) so that their copies are
+            // plain DMA: copies from pageable memory went through host-side
+            // staging and left the device idle before every batch
+            const size_t fi_bytes = sizeof(FrameInfo) * (size_t)F, meta_need = fi_bytes + 16 * (size_t)F + 256;
+            if (c->meta_host_bytes < meta_need) {
+                if (c->meta_host) (void)hipHostFree(c->meta_host);
+                c->meta_host = nullptr;
+                c->meta_host_bytes = 0;
+                HIP_CHECK_RET(c, hipHostMalloc((void**)&c->meta_host, meta_need, hipHostMallocDefault));
+                c->meta_host_bytes = meta_need;
+            }
+            FrameInfo* fi_next = reinterpret_cast<FrameInfo*>(c->meta_host);
+            int32_t* sizes_next = reinterpret_cast<int32_t*>(c->meta_host + fi_bytes);
             int f0 = 0;
             while (f0 < F) {
                 int f1 = f0;
@@ -523,10 +531,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if (f1 == f0) f1 = f0 + 1;
                 const int nf = f1 - f0;
                 const int64_t a0 = meta.offs[f0], na = meta.offs[f1] - a0;
-                keep.emplace_back(new BatchHost());
-                BatchHost& bh = *keep.back();
-                bh.fi.resize(nf);
-                std::vector<FrameInfo>& fi = bh.fi;
+                FrameInfo* fi = fi_next;
+                int32_t* sizes = sizes_next;
+                fi_next += nf;
+                sizes_next += 4;
                 int n_cells = 0;
                 int64_t n_ref_atoms = 0;
                 bool followers = false, triclinic = false;
@@ -602,14 +610,14 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 const int nt_max = 10;
                 if ((e = c->reserve(c->out, sizeof(double) * nt_max * cap_frames * (last - first)))) return e;
                 if ((e = c->reserve(c->red_part, sizeof(double) * 10 * kReduceChunks * cap_frames))) return e;
-                bh.sizes[0] = (int32_t)na;
-                bh.sizes[1] = nf;
-                bh.sizes[2] = n_cells;
-                bh.sizes[3] = (int32_t)std::min<int64_t>(a0, INT32_MAX);
-                HIP_CHECK_RET(c, hipMemcpyAsync((int32_t*)c->tile_base.p + kMetaNAtoms, bh.sizes, sizeof(bh.sizes),
+                sizes[0] = (int32_t)na;
+                sizes[1] = nf;
+                sizes[2] = n_cells;
+                sizes[3] = (int32_t)std::min<int64_t>(a0, INT32_MAX);
+                HIP_CHECK_RET(c, hipMemcpyAsync((int32_t*)c->tile_base.p + kMetaNAtoms, sizes, sizeof(int32_t) * 4,
                                                 hipMemcpyHostToDevice, c->stream));
-                HIP_CHECK_RET(c, hipMemcpyAsync(c->frames.p, fi.data(), sizeof(FrameInfo) * nf,
-                                                hipMemcpyHostToDevice, c->stream));
+                HIP_CHECK_RET(c, hipMemcpyAsync(c->frames.p, fi, sizeof(FrameInfo) * nf, hipMemcpyHostToDevice,
+                                                c->stream));
                 const double* pos;
                 const int32_t* spc;
                 if (fr.location == TNEP_HOST) {

@@ -57,6 +57,8 @@ struct Ctx {
     double skin = 1.0;                                   // TNEP_OPT_SKIN_MA / 1000, Angstrom
     uint64_t reuse_fallbacks = 0;                        // calls redone with plain searches
     int32_t* h_flags = nullptr;       // pinned
+    char* meta_host = nullptr;        // pinned staging of the launch batches' frame records and sizes
+    size_t meta_host_bytes = 0;
 
     // work buffers
     DevBuf frames, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, bucket_pos, perm_start;
