@@ -456,7 +456,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if (job.models[k]->kind == TNEP_KIND_PES) rec_stride = pes_rec_stride(job.models[k]->shape, T);
             const bool pes = rec_stride > 0;
             const int64_t per_atom_bytes = (int64_t)slots * 16 + 8 * T + 24 + 80 * (last - first) +
-                                           (fr.location == TNEP_HOST ? 28 : 0) + (pes ? 4 * rec_stride + 32 : 0);
+                                           (fr.location == TNEP_HOST ? 28 : 0) + (pes ? 4 * rec_stride + 32 + (int64_t)slots * 16 : 0);
             int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
             B = std::max(B, largest);
             const int64_t room = (int64_t)c->budget - (int64_t)(c->in_use - c->nbr.bytes - c->per_atom.bytes);
@@ -496,6 +496,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if ((e = c->reserve(c->per_atom, (size_t)B_res * 10 * sizeof(double) * (last - first)))) return e;
             if (pes) {
                 if ((e = c->reserve(c->pes_rec, (size_t)n_pad_max * rec_stride * sizeof(float)))) return e;
+                if ((e = c->reserve(c->pes_pair, (size_t)n_pad_max * slots * sizeof(float4)))) return e;
                 if (fr.location == TNEP_HOST && (e = c->reserve(c->pes_stage, (size_t)B_res * 4 * sizeof(double))))
                     return e;
             }
@@ -676,7 +677,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         }
                     }
                 }
-                const PesOut pes_out{(float*)c->pes_rec.p, rec_stride};
+                const PesOut pes_out{(float*)c->pes_rec.p, rec_stride, (float4*)c->pes_pair.p};
                 // the batch's kernels; with graphs on, captured once and replayed
                 auto launch_batch = [&]() -> hipError_t {
                     hipError_t he;

@@ -173,16 +173,18 @@ struct EvalLaunch {
 // Potential-energy models: the evaluation kernel leaves, per atom a in tile
 // slot p, a record of rec_stride floats at rec + p * rec_stride (slots keep
 // atoms of one cell together, so the records of a lane's neighbours are close):
-//   [t * KRP + k]        sum_n dU_a/dq^R_n c^R_{t_a t}[n][k]   (t < T, KRP = KR rounded up to 4)
-//   [T * KRP + 24 n + c] (-1)^l(c) dU_a/dA_{a,n,c}             (n < NA, the 24 (l, m) channels)
-//   [T * KRP + 24 NA + d] sum_j dU_a/dr_aj, component d < 3
-// from which the second kernel forms, for every pair (k, j), the term that
-// U_j contributes to the force on k.
+//   [t * KRP + k]   sum_n dU_a/dq^R_n c^R_{t_a t}[n][k]   (t < T, KRP = KR rounded up to 4)
+//   [T * KRP + d]   sum_j dU_a/dr_aj, component d < 3
+// and, for every entry of an angular segment (r_aj < r_c^A), the pair force
+// dU_a/dr_aj at the entry's place in `pair` (same layout as the neighbour
+// entries).  From these the second kernel forms, for every pair (k, j), the
+// term that U_j contributes to the force on k.
 struct PesOut {
     float* rec;
     int32_t rec_stride;
+    float4* pair;
 };
-inline int pes_rec_stride(const Shape& s, int T) { return T * ((s.kr + 3) / 4 * 4) + 24 * s.na + 4; }
+inline int pes_rec_stride(const Shape& s, int T) { return T * ((s.kr + 3) / 4 * 4) + 4; }
 
 // Per-atom records (FP64, batch atom order) of one model: dipole [n][3],
 // polarizability [n][9], potential energy [n][10] = (U_i, W_i row-major).

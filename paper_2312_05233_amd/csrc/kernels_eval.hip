@@ -315,11 +315,6 @@ __host__ __device__ constexpr int mlp_lds_floats(int D, int H) {
     return 64 * (((D + 31) / 32 * 32 + 4) + ((H + 31) / 32 * 32 + 4));
 }
 
-// Sign of the (l, m) channel c of sh_foreach under r -> -r: (-1)^l.
-__device__ __forceinline__ constexpr float parity_sign(int c) {
-    return (c < 3 || (c >= 8 && c < 15)) ? -1.f : 1.f;
-}
-
 // One lane per tile slot (atom).  The coefficient blocks c[t_i][t] are
 // wave-uniform and read with scalar loads.  MODE selects the hidden layer:
 // FP32 vector ALU (no LDS) or one of the matrix-core variants (LDS tile per
@@ -549,14 +544,6 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
                     rec[t * KRP + k] = v;
                 }
             }
-            float* g = rec + T * KRP;
-#pragma unroll
-            for (int n = 0; n < NA; ++n)
-#pragma unroll
-                for (int c = 0; c < kLM; c += 4)
-                    *reinterpret_cast<float4*>(g + n * kLM + c) =
-                        make_float4(parity_sign(c) * A[n][c], parity_sign(c + 1) * A[n][c + 1],
-                                    parity_sign(c + 2) * A[n][c + 2], parity_sign(c + 3) * A[n][c + 3]);
         }
     }
 
@@ -679,7 +666,11 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
                 sa[l] += av * P;
             });
             const float su = sb - rinv * (sa[1] + 2.f * sa[2] + 3.f * sa[3] + 4.f * sa[4]) + sr;
-            contract(e.x, e.y, e.z, r2, Fx * rinv + ux * su, Fy * rinv + uy * su, Fz * rinv + uz * su);
+            const float fx = Fx * rinv + ux * su, fy = Fy * rinv + uy * su, fz = Fz * rinv + uz * su;
+            contract(e.x, e.y, e.z, r2, fx, fy, fz);
+            if constexpr (KIND == 3) {
+                if (a >= 0) pes.pair[(ga - nl.entries) + ((s >> 2) * 256 + (s & 3))] = make_float4(fx, fy, fz, 0.f);
+            }
         }
         nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int s = 0; s < n_rad; ++s) {
@@ -698,7 +689,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
         out[0] = (double)Us;
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[1 + k] = (double)acc[k];
-        *reinterpret_cast<float4*>(rec + T * KRP + NA * kLM) = make_float4(own[0], own[1], own[2], 0.f);
+        *reinterpret_cast<float4*>(rec + T * KRP) = make_float4(own[0], own[1], own[2], 0.f);
         return;
     }
     double* out = per_atom + (int64_t)a * NT;
@@ -809,11 +800,16 @@ __global__ void __launch_bounds__(256) k_com_shift(const int64_t* __restrict__ o
 // Forces of a potential-energy model (Sec. 2.1): with r_ij = r_j - r_i,
 //   F_k = -dU/dr_k = sum_j dU_k/dr_kj - sum_j dU_j/dr_jk.
 // The first sum is in the atom's record (evaluation kernel).  For the second,
-// the lane of atom k evaluates, for every neighbour j, the partial force of
-// U_j at r_jk = -r_kj from j's record: radial part sum_k' Dk_j[k'] f'_k'(r) with
-// j's coefficients c_{t_j t_k}; angular part from G_j, whose stored sign
-// (-1)^l turns Y_lm(-u) and its gradient back into functions of u.  Every
-// term is summed in the lane's fixed list order: no atomics.
+// the lane of atom k takes, for every neighbour j:
+//   r_kj < r_c^A: the pair force dU_j/dr_jk that j's evaluation stored at k's
+//     entry in j's angular segment of k's species; the lane finds that entry by
+//     its slot (the segment holds ~10-20 entries, read in 64-byte groups);
+//   otherwise: the radial part sum_k' Dk_j[k'] f'_k'(r) from j's record with
+//     j's coefficients c_{t_j t_k} (48 bytes and ~60 instructions per pair).
+// A pair that j's search classified on the other side of r_c^A (rounding at
+// the boundary) is not in that segment and takes the radial form, the angular
+// terms vanishing there with f_c(r_c^A).  Every term is summed in the lane's
+// fixed list order: no atomics.
 template <int NR, int NA, int KR, int KA, int MB>
 __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl, PesOut pes,
                                                     const double* __restrict__ per_atom,
@@ -826,117 +822,72 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
     if (tile >= nl.meta[kMetaTileBase + T]) return;
     const int a = nl.perm[p];
     const int tk = tile_species(nl.meta + kMetaTileBase, T, tile);
-    const float rcR_inv = 1.f / m.rc_radial, rcA_inv = 1.f / m.rc_angular;
+    const float rcR_inv = 1.f / m.rc_radial;
     const float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
+    const int64_t seg_a_k = (int64_t)(nl.meta[kMetaSegA + tk] >> 2) * 256;  // angular segment of k's species
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;  // - sum_j dU_j/dr_jk
+    // sum_k D_k f_k'(r) from Chebyshev sums (as in k_eval), D from j's record
+    auto radial_slope = [&](const float* rj, float r) {
+        float fc, dfc, Tk[KRP], dT[KRP];
+        cutoff_fc_d(1.f - r * rcR_inv, rcR_inv, fc, dfc);
+        const float tt = r * rcR_inv - 1.f;
+        cheb_T_d<KR>(2.f * tt * tt - 1.f, Tk, dT);
+        const float4* d4 = reinterpret_cast<const float4*>(rj + tk * KRP);
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int k = 0; k < KRP; k += 4) {
+            const float4 d = d4[k / 4];
+            const float dd[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (k + u < KR) {
+                    s0 += dd[u] * (Tk[k + u] + 1.f);
+                    s1 += dd[u] * dT[k + u];
+                }
+        }
+        return 0.5f * (fc * (4.f * tt * rcR_inv) * s1 + dfc * s0);
+    };
+    // - dU_j/dr_jk, radial part, for the entry vector e = r_kj
+    auto radial_term = [&](const float4& e) {
+        const float* rj = pes.rec + (int64_t)__float_as_int(e.w) * pes.rec_stride;
+        const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
+        const float rinv = pair_rsqrt(r2);
+        const float su = radial_slope(rj, r2 * rinv) * rinv;
+        Fx += e.x * su;
+        Fy += e.y * su;
+        Fz += e.z * su;
+    };
     for (int t = 0; t < T; ++t) {
-        // neighbours of species t see atom k through c_{t, t_k}
-        const float* __restrict__ cA = m.c_angular + (t * T + tk) * (NA * KA);
         const int n_ang = nl.counts[(int64_t)(2 * t) * nl.n_pad + p];
         const int n_rad = nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
         const float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
         const float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
-        // sum_k D_k f_k'(r) from Chebyshev sums (as in k_eval)
-        auto radial_slope = [&](const float* rj, float r) {
-            float fc, dfc, Tk[KRP], dT[KRP];
-            cutoff_fc_d(1.f - r * rcR_inv, rcR_inv, fc, dfc);
-            const float tt = r * rcR_inv - 1.f;
-            cheb_T_d<KR>(2.f * tt * tt - 1.f, Tk, dT);
-            const float4* d4 = reinterpret_cast<const float4*>(rj + tk * KRP);
-            float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-            for (int k = 0; k < KRP; k += 4) {
-                const float4 d = d4[k / 4];
-                const float dd[4] = {d.x, d.y, d.z, d.w};
+        for (int s = 0; s < n_ang; ++s) {
+            const float4 e = ga[(s >> 2) * 256 + (s & 3)];
+            const int j = __float_as_int(e.w);
+            // j's angular segment of species t_k, searched for this lane's slot
+            const int64_t ja = ((int64_t)(j >> 6) * (nl.slots >> 2) * 64 + (j & 63)) * 4 + seg_a_k;
+            const int n_ja = nl.counts[(int64_t)(2 * tk) * nl.n_pad + j];
+            int row = -1;
+            for (int r0 = 0; r0 < n_ja && row < 0; r0 += 4) {
+                const float4* g = nl.entries + ja + (int64_t)(r0 >> 2) * 256;
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if (k + u < KR) {
-                        s0 += dd[u] * (Tk[k + u] + 1.f);
-                        s1 += dd[u] * dT[k + u];
-                    }
+                    if (r0 + u < n_ja && __float_as_int(g[u].w) == (int)p) row = r0 + u;
             }
-            return 0.5f * (fc * (4.f * tt * rcR_inv) * s1 + dfc * s0);
-        };
-        float CsA[NA];  // sum_k c_nk of c_{t, t_k} (wave-uniform)
-#pragma unroll
-        for (int n = 0; n < NA; ++n) {
-            float c = 0.f;
-#pragma unroll
-            for (int k = 0; k < KA; ++k) c += cA[n * KA + k];
-            CsA[n] = c;
-        }
-        float4 nxt = n_ang > 0 ? ga[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int s = 0; s < n_ang; ++s) {
-            const float4 e = nxt;
-            if (s + 1 < n_ang) nxt = ga[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
-            const float* rj = pes.rec + (int64_t)__float_as_int(e.w) * pes.rec_stride;
-            const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
-            const float rinv = pair_rsqrt(r2);
-            const float r = r2 * rinv;
-            const float ux = e.x * rinv, uy = e.y * rinv, uz = e.z * rinv;
-            const float sr = radial_slope(rj, r);
-            float fc, dfc, Tk[KA], dT[KA];
-            cutoff_fc_d(1.f - r * rcA_inv, rcA_inv, fc, dfc);
-            const float ta = r * rcA_inv - 1.f;
-            cheb_T_d<KA>(2.f * ta * ta - 1.f, Tk, dT);
-            const float hfc = 0.5f * fc, hdfc = 0.5f * dfc, hfx = hfc * (4.f * ta * rcA_inv);
-            // a_c = sum_n G~_j[n][c] g_n(r), b_c = sum_n G~_j[n][c] g_n'(r)
-            float av[kLM], bv[kLM];
-#pragma unroll
-            for (int c = 0; c < kLM; ++c) {
-                av[c] = 0.f;
-                bv[c] = 0.f;
+            if (row >= 0) {
+                const float4 f = pes.pair[ja + (int64_t)(row >> 2) * 256 + (row & 3)];
+                Fx -= f.x;
+                Fy -= f.y;
+                Fz -= f.z;
+            } else {
+                radial_term(e);
             }
-            const float4* gj = reinterpret_cast<const float4*>(rj + T * KRP);
-#pragma unroll
-            for (int n = 0; n < NA; ++n) {
-                float pn = CsA[n], qn = 0.f;
-#pragma unroll
-                for (int k = 0; k < KA; ++k) {
-                    pn += cA[n * KA + k] * Tk[k];
-                    qn += cA[n * KA + k] * dT[k];
-                }
-                const float g = hfc * pn, dg = hfx * qn + hdfc * pn;
-#pragma unroll
-                for (int c = 0; c < kLM; c += 4) {
-                    const float4 w = gj[(n * kLM + c) / 4];
-                    av[c] += w.x * g;
-                    av[c + 1] += w.y * g;
-                    av[c + 2] += w.z * g;
-                    av[c + 3] += w.w * g;
-                    bv[c] += w.x * dg;
-                    bv[c + 1] += w.y * dg;
-                    bv[c + 2] += w.z * dg;
-                    bv[c + 3] += w.w * dg;
-                }
-            }
-            float Px = 0.f, Py = 0.f, Pz = 0.f, sc = 0.f;
-            sh_foreach(ux, uy, uz, [&](int idx, int l, float P, float px, float py, float pz) {
-                Px += av[idx] * px;
-                Py += av[idx] * py;
-                Pz += av[idx] * pz;
-                sc += (bv[idx] - (float)l * av[idx] * rinv) * P;
-            });
-            const float su = sc + sr;
-            Fx += Px * rinv + ux * su;
-            Fy += Py * rinv + uy * su;
-            Fz += Pz * rinv + uz * su;
         }
-        nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int s = 0; s < n_rad; ++s) {
-            const float4 e = nxt;
-            if (s + 1 < n_rad) nxt = gr[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
-            const float* rj = pes.rec + (int64_t)__float_as_int(e.w) * pes.rec_stride;
-            const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
-            const float rinv = pair_rsqrt(r2);
-            const float su = radial_slope(rj, r2 * rinv) * rinv;
-            Fx += e.x * su;
-            Fy += e.y * su;
-            Fz += e.z * su;
-        }
+        for (int s = 0; s < n_rad; ++s) radial_term(gr[(s >> 2) * 256 + (s & 3)]);
     }
     if (a < 0) return;
-    const float4 own = *reinterpret_cast<const float4*>(pes.rec + p * pes.rec_stride + T * KRP + NA * kLM);
+    const float4 own = *reinterpret_cast<const float4*>(pes.rec + p * pes.rec_stride + T * KRP);
     if (forces) {
         forces[3 * (int64_t)a] = (double)own.x + (double)Fx;
         forces[3 * (int64_t)a + 1] = (double)own.y + (double)Fy;

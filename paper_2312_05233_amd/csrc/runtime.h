@@ -64,7 +64,7 @@ struct Ctx {
     DevBuf frames, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, bucket_pos, perm_start;
     DevBuf perm, tile_base, scan_chunks, nbr, counts, per_atom, out, pos, species;
     DevBuf spec_work, spec_series, spec_out;
-    DevBuf pes_rec, pes_stage;  // potential-energy models: per-atom records, host-bound staging
+    DevBuf pes_rec, pes_stage, pes_pair;  // potential-energy models: per-atom records, host-bound staging, pair forces
     DevBuf slot_of, cand, cand_count;  // tile slot per atom; trajectory candidate lists
     DevBuf com;                        // charged-dipole shift: staging of frames, masses, charges, mu
     DevBuf red_part;                   // frame sums: per-chunk partial sums
@@ -75,7 +75,7 @@ struct Ctx {
     std::vector<DevBuf*> all_buffers() {
         return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
-                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &slot_of, &cand, &cand_count, &com,
+                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &pes_pair, &slot_of, &cand, &cand_count, &com,
                 &pop_stage, &pop_work, &pop_img, &red_part};
     }
 
