@@ -310,8 +310,9 @@ __device__ __forceinline__ int wrap_cell(int u, int n) { return u < 0 ? u + n : 
 
 // The entries of one (atom, neighbour species) pass: angular segment (r <
 // r_c^A) and radial-only segment.  Each lane stages four entries per segment
-// in LDS and writes them as one 64-byte group; staging in LDS instead of
-// registers keeps a push to one store and one address, where a register
+// in LDS; a completed 64-byte group is stored by the whole wave (coop_flush),
+// the partial groups at the end by the lane (flush).  Staging in LDS instead
+// of registers keeps a push to one store and one address, where a register
 // buffer costs a shift of four entries per push and copies of both buffers at
 // every divergent branch.  Slot (segment s, entry k) of a lane is
 // stage[(4 s + k) * stride] (consecutive lanes at consecutive 16-byte words).
@@ -322,24 +323,6 @@ struct PairSink {
     float4* gr;
     int capA, capR;
     int na, nr;
-    __device__ __forceinline__ void push(const float4& e, bool ang) {
-        const int n = ang ? na : nr;
-        const int s4 = ang ? 0 : 4;
-        stage[(s4 + (n & 3)) * stride] = e;
-        const int m = n + 1;
-        if (ang)
-            na = m;
-        else
-            nr = m;
-        if ((m & 3) == 0 && m <= (ang ? capA : capR)) {
-            float4* g = (ang ? ga : gr) + (int64_t)((m - 4) >> 2) * 256;
-            const float4* src = stage + s4 * stride;
-            g[0] = src[0];
-            g[1] = src[stride];
-            g[2] = src[2 * stride];
-            g[3] = src[3 * stride];
-        }
-    }
     __device__ __forceinline__ void flush_one(int n, int cap, float4* base, const float4* src) {
         const int k = n & 3;
         if (k == 0 || n > cap) return;
@@ -351,9 +334,9 @@ struct PairSink {
         flush_one(nr, capR, gr, stage + 4 * stride);
     }
 
-    // Deferred form of push: a completed group is not stored by its lane but
-    // left for the wave's next coop_flush (pend_src = LDS index of its first
-    // entry relative to lds, pend_dst = its destination).
+    // A completed group is not stored by its lane but left for the wave's
+    // next coop_flush (pend_src = LDS index of its first entry relative to
+    // lds, pend_dst = its destination).
     int pend_src;
     float4* pend_dst;
     __device__ __forceinline__ void push_deferred(const float4& e, bool ang, const float4* lds) {
@@ -618,8 +601,10 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
                                                              const int32_t* __restrict__ slot_of, float rc_radial,
                                                              float rc_angular, NeighborLists nl, CandLists cl,
                                                              int32_t* __restrict__ flags) {
-    extern __shared__ float4 nb_stage[];  // 8 entries per lane (PairSink)
+    // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
+    extern __shared__ float4 nb_stage[];
     float4* stage = nb_stage + threadIdx.x;
+    int4* wlist = reinterpret_cast<int4*>(nb_stage + 8 * blockDim.x) + (threadIdx.x & ~63u);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nl.n_pad) return;
     const int T = nl.T;
@@ -660,16 +645,17 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                if (k0 + u >= n) break;
                 const double dx = min_image(cx[u] - xi, fi.L[0], fi.Linv[0]);
                 const double dy = min_image(cy[u] - yi, fi.L[1], fi.Linv[1]);
                 const double dz = min_image(cz[u] - zi, fi.L[2], fi.Linv[2]);
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 >= rc2r) continue;
-                if (r2 < 1e-8) overlap = true;
-                const int js = slot_of[fi.atom_begin + jl[u]];
-                const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(js));
-                ps.push(ent, r2 < rc2a);
+                if ((k0 + u < n) & (r2 < rc2r)) {
+                    overlap |= r2 < 1e-8;
+                    const int js = slot_of[fi.atom_begin + jl[u]];
+                    ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(js)), r2 < rc2a,
+                                     nb_stage);
+                }
+                coop_flush(ps, nb_stage, wlist);
             }
         }
         ps.flush();
@@ -701,8 +687,10 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                                                           const double4* __restrict__ bucket_pos, float rc_radial,
                                                           float rc_angular, NeighborLists nl,
                                                           int32_t* __restrict__ flags) {
-    extern __shared__ float4 nb_stage[];  // 8 entries per lane (PairSink)
+    // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
+    extern __shared__ float4 nb_stage[];
     float4* stage = nb_stage + threadIdx.x;
+    int4* list = reinterpret_cast<int4*>(nb_stage + 8 * blockDim.x) + (threadIdx.x & ~63u);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nl.n_pad) return;
     const int T = nl.T;
@@ -779,10 +767,8 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                 const double4 q1 = k0 + 1 < e ? bucket_pos[k0 + 1] : make_double4(0.0, 0.0, 0.0, 0.0);
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    if (k0 + u >= e) break;
                     const double4 cur = u == 0 ? q0 : q1;
                     const int j = k0 + u;  // tile slot of the candidate
-                    if (j == (int)p) continue;
                     double f0 = cur.x + sh[0], f1 = cur.y + sh[1], f2 = cur.z + sh[2];
                     if (mode != 1) {
                         f0 -= rint(f0);
@@ -793,9 +779,13 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                     const double dy = f0 * H[1] + f1 * H[4] + f2 * H[7];
                     const double dz = f0 * H[2] + f1 * H[5] + f2 * H[8];
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 >= rc2r) continue;
-                    if (r2 < 1e-8) overlap = true;
-                    ps.push(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)), r2 < rc2a);
+                    // one branch per candidate: a real candidate, not the atom itself, within r_c
+                    if ((k0 + u < e) & (j != (int)p) & (r2 < rc2r)) {
+                        overlap |= r2 < 1e-8;
+                        ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)), r2 < rc2a,
+                                         nb_stage);
+                    }
+                    coop_flush(ps, nb_stage, list);
                 }
             }
         }
@@ -872,7 +862,6 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
     k_sort_place<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, w.key_of, w.bucket_start,
                                                                  w.bucket_atoms, w.perm_start, w.perm, w.slot_of, pos,
                                                                  w.bucket_pos, w.cell_rec, nl.meta, T);
-    const size_t stage_bytes = sizeof(float4) * 8 * nb;
     const size_t list_bytes = sizeof(float4) * 9 * nb;  // staging + per-wave flush lists
     k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                               w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
@@ -882,10 +871,10 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                                                  w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
                                                                  rc_radial, rc_angular, nl, cl, d_flags);
     if (triclinic)
-        k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, w.key_of, w.perm_start,
+        k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, w.key_of, w.perm_start,
                                                                w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
     if (followers)
-        k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, stage_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+        k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                   rc_radial, rc_angular, nl, cl, d_flags);
     return hipGetLastError();
 }
