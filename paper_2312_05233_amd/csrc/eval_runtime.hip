@@ -137,15 +137,26 @@ int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double
                 g.H[i] = H[i];
                 g.Hinv[i] = reduced ? Rinv[i] : Hinv[i];
             }
+            // fractional bins of perpendicular width >= rc / reach, as for the
+            // orthorhombic grid below
+            const int reach[3] = {kCellReachXY, kCellReachXY, kCellReachZ};
             for (int k = 0; k < 3; ++k) {
                 g.w[k] = reduced ? wr[k] : w[k];
-                g.nc[k] = (int)std::floor(g.w[k] / rc);
-                if (g.nc[k] > 256) g.nc[k] = 256;
-                ok = ok && g.nc[k] >= 3;
+                g.nc[k] = (int)std::min(1024.0, std::floor(reach[k] * g.w[k] / rc));
+                ok = ok && g.nc[k] >= 2 * reach[k] + 1;
             }
-            if (ok) g.mode = 1;
-            else
+            if (ok) {
+                const double lim = std::max(2.0 * (double)n_atoms,
+                                            (2.0 * reach[0] + 1) * (2.0 * reach[1] + 1) * (2.0 * reach[2] + 1));
+                const double prod = (double)g.nc[0] * g.nc[1] * g.nc[2];
+                if (prod > lim) {
+                    const double s = std::cbrt(prod / lim);
+                    for (int k = 0; k < 3; ++k) g.nc[k] = std::max(2 * reach[k] + 1, (int)std::floor(g.nc[k] / s));
+                }
+                g.mode = 1;
+            } else {
                 for (int k = 0; k < 3; ++k) g.nc[k] = 1;
+            }
             return TNEP_OK;
         }
     }
@@ -574,10 +585,11 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         x.Linv[d] = (g.per[d] && !g.tric) ? 1.0 / g.L[d] : 0.0;
                     }
                     x.tric = g.tric;
-                    if (g.mode == 1 && !g.tric) {
-                        // fixed-point unit of the cell records: offsets within a cell stay below 2^30 units
+                    if (g.mode == 1) {
+                        // fixed-point unit of the cell records: offsets within a cell (in A,
+                        // or in fractional units for triclinic bins) stay below 2^30 units
                         double hmax = 0;
-                        for (int d = 0; d < 3; ++d) hmax = std::max(hmax, g.L[d] / g.nc[d]);
+                        for (int d = 0; d < 3; ++d) hmax = std::max(hmax, g.tric ? 1.0 / g.nc[d] : g.L[d] / g.nc[d]);
                         const int kq = std::min(60, std::max(0, (int)std::floor(std::log2(std::ldexp(1.0, 30) / hmax))));
                         x.q_unit = std::ldexp(1.0, -kq);
                     }

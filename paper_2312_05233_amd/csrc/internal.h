@@ -40,8 +40,9 @@ struct FrameInfo {
     int32_t tric;
     int32_t pad_;
     double H[9], Hinv[9], w[3];
-    // Orthorhombic cell grids: unit (a power of two, A) of the fixed-point
-    // offsets from the cell origin in the candidate records.
+    // Cell grids: unit (a power of two; A, or fractional units for triclinic
+    // bins) of the fixed-point offsets from the cell origin in the candidate
+    // records.
     double q_unit;
 };
 
@@ -143,7 +144,7 @@ struct NeighborWork {
     int32_t* bucket_fill;   // [n_buckets]
     int32_t* bucket_atoms;  // [n_atoms]
     double4* bucket_pos;    // [n_pad] FP64 positions by tile slot (frames without an orthorhombic cell grid)
-    int4* cell_rec;         // [n_pad] orthorhombic cell grids: (q_x, q_y, q_z, cell z) by tile slot
+    int4* cell_rec;         // [n_pad] cell grids: (q_0, q_1, q_2, cell index along axis 2) by tile slot
     int32_t* perm_start;    // [n_buckets]
     int32_t* perm;          // [n_pad]
     int32_t* meta;          // [kMetaInts], tile_base part written on the device

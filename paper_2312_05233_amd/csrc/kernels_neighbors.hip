@@ -244,10 +244,12 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 // (number of smaller atom indices in its bucket) and store its position at
 // that slot.  One thread per atom: buckets hold a few atoms on cell grids and
 // a whole frame otherwise, so the rank loop is never longer than the frame's
-// own neighbour loop.  Orthorhombic cell grids get a 16-byte record: the
-// offsets of the wrapped position from its cell's origin as integers in units
-// of q_unit (a power of two, so the scaling is exact), and the cell's z index;
-// all other frames the FP64 position (triclinic frames: wrapped fractional
+// own neighbour loop.  Cell grids get a 16-byte record: the offsets of the
+// wrapped position from its cell's origin as integers in units of q_unit (a
+// power of two, so the scaling is exact), and the cell's index along the third
+// axis (z, or the third lattice vector); the position is in A on orthorhombic
+// grids and in fractional coordinates on triclinic bins.  Frames without a
+// grid keep the FP64 position (triclinic ones: wrapped fractional
 // coordinates).
 __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ frame_of,
                              const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
@@ -267,16 +269,25 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t
     slot_of[a] = slot;
     double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
     const FrameInfo& fi = frames[frame_of[a]];
-    if (fi.mode == 1 && !fi.tric) {
+    if (fi.mode == 1) {
         const int local = k / T - fi.cell_base;
-        const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
+        const int ny = fi.nc[1], nz = fi.nc[2];
         const int c[3] = {local / (nz * ny), (local / nz) % ny, local % nz};
         const double r[3] = {x, y, z};
         int q[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const double s = r[d] - fi.L[d] * floor(r[d] * fi.Linv[d]);
-            q[d] = (int)rint((s - c[d] * (fi.L[d] / fi.nc[d])) / fi.q_unit);
+            double s, h;
+            if (fi.tric) {
+                // wrapped fractional coordinate, as k_bin bins it
+                s = x * fi.Hinv[d] + y * fi.Hinv[3 + d] + z * fi.Hinv[6 + d];
+                s -= floor(s);
+                h = 1.0 / fi.nc[d];
+            } else {
+                s = r[d] - fi.L[d] * floor(r[d] * fi.Linv[d]);
+                h = fi.L[d] / fi.nc[d];
+            }
+            q[d] = (int)rint((s - c[d] * h) / fi.q_unit);
         }
         cell_rec[slot] = make_int4(q[0], q[1], q[2], c[2]);
         return;
@@ -671,20 +682,25 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
     return;
 }
 
-// Triclinic frames: one lane per tile slot.  Pair vectors by the minimum
-// image in fractional coordinates, f = d Hinv, f -= rint(f), d = f H: with
-// every width >= 2 r_c an image within r_c has all |f_k| < 1/2, so rounding
-// finds it.  Cell-list frames visit the 27 neighbouring fractional bins
-// (a neighbour within r_c is at most one bin away per axis since the bin
-// width w_k / nc_k >= r_c); a bin is skipped when the perpendicular distance
-// to it along one axis already reaches r_c (the sum of squares would not be
-// a lower bound on skewed cells).
+// Triclinic frames: one lane per tile slot.  Bins in fractional coordinates
+// s = r Hinv of perpendicular width w_k / nc_k >= r_c / 2, so a neighbour
+// within r_c is at most two bins away along each lattice vector (the distance
+// between two lattice planes bounds the pair distance from below).  As for
+// orthorhombic grids, the bins are walked as 25 columns along the third
+// lattice vector, each trimmed to the bins within reach; a column or bin is
+// skipped when the perpendicular distance to it along one axis reaches r_c
+// (the sum of squares would not be a lower bound on skewed cells).  The
+// fractional difference of a pair is (bin offset) / nc + (q_j - q_i) q_unit
+// from the cell records, and d = f H.  Frames without bins (cells narrower
+// than 2.5 r_c) take the minimum image by rounding, f -= rint(f): with every
+// width >= 2 r_c an image within r_c has all |f_k| < 1/2.
 __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __restrict__ frames,
                                                           const int32_t* __restrict__ frame_of,
                                                           const double* __restrict__ pos,
                                                           const int32_t* __restrict__ key_of,
                                                           const int32_t* __restrict__ perm_start,
-                                                          const double4* __restrict__ bucket_pos, float rc_radial,
+                                                          const double4* __restrict__ bucket_pos,
+                                                          const int4* __restrict__ cell_rec, float rc_radial,
                                                           float rc_angular, NeighborLists nl,
                                                           int32_t* __restrict__ flags) {
     // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
@@ -705,11 +721,11 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
     const float prune = rc_radial + 1e-3f;
     float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
     const int mode = fi.mode, cell_base = fi.cell_base;
-    const int ny = fi.nc[1], nz = fi.nc[2];
+    const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
     double H[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) H[q] = fi.H[q];
-    // wrapped fractional coordinates of the atom (bucket records hold the candidates')
+    // wrapped fractional coordinates of the atom
     double si[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -717,51 +733,82 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
         si[q] -= floor(si[q]);
     }
     int ib[3] = {0, 0, 0};
-    float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+    float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f}, hb[3] = {0.f, 0.f, 0.f};
+    int4 own = make_int4(0, 0, 0, 0);  // the atom's own cell record
     if (mode == 1) {
+        own = cell_rec[p];
         const int local = key_of[a] / T - cell_base;
         ib[2] = local % nz;
         ib[1] = (local / nz) % ny;
         ib[0] = local / (nz * ny);
+        // perpendicular distances (A) to the faces of the atom's bin, and bin widths
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double inv = 1.0 / (double)fi.nc[k];
             lo[k] = (float)fmax((si[k] - ib[k] * inv) * fi.w[k], 0.0);
             hi[k] = (float)fmax(((ib[k] + 1) * inv - si[k]) * fi.w[k], 0.0);
+            hb[k] = (float)(fi.w[k] * inv);
         }
     }
+    const float hb2_inv = mode == 1 ? 1.f / hb[2] : 0.f;
     bool overlap = false;
     for (int t = 0; t < T; ++t) {
         PairSink ps{stage, (int)blockDim.x,
                     lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
                     lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
                     nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0, -1, nullptr};
-        const int n_visit = mode == 1 ? 27 : 1;
-        for (int vb = 0; vb < n_visit; ++vb) {
-            int bucket = cell_base * T + t;
-            // fractional offset of the candidates' image relative to the atom:
-            // cell lists: the visited bin's lattice shift (its unwrapped index is
-            // ib + o, within one bin of the atom's), so f = s_j + shift - s_i is the
-            // image within r_c; all-pairs frames: rounding of s_j - s_i
-            double sh[3] = {-si[0], -si[1], -si[2]};
-            if (mode == 1) {
-                const int o[3] = {vb / 9 - 1, (vb / 3) % 3 - 1, vb % 3 - 1};
-                float g = 0.f;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) g = fmaxf(g, o[k] < 0 ? lo[k] : (o[k] > 0 ? hi[k] : 0.f));
-                if (g >= prune) continue;
-                int cc[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int u = ib[k] + o[k];
-                    cc[k] = u < 0 ? u + fi.nc[k] : (u >= fi.nc[k] ? u - fi.nc[k] : u);
-                    sh[k] += (double)(u < 0 ? -1 : (u >= fi.nc[k] ? 1 : 0));
+        if (mode == 1) {
+            for (int col = 0; col < 25; ++col) {
+                const int o0 = col / 5 - 2, o1 = col % 5 - 2;
+                if (fmaxf(cell_gap(o0, lo[0], hi[0], hb[0]), cell_gap(o1, lo[1], hi[1], hb[1])) >= prune) continue;
+                // bins ib2 - below .. ib2 + above: bin ib2 - k is in reach when lo_2 + (k - 1) hb_2 < prune
+                const int below = min(kCellReachZ, max(0, (int)floorf((prune - lo[2]) * hb2_inv) + 1));
+                const int above = min(kCellReachZ, max(0, (int)floorf((prune - hi[2]) * hb2_inv) + 1));
+                const int z0 = ib[2] - below, z1 = ib[2] + above;
+                const int col0 = (cell_base + (wrap_cell(ib[0] + o0, nx) * ny + wrap_cell(ib[1] + o1, ny)) * nz) * T + t;
+                int b0, e0, b1 = 0, e1 = 0;
+                if (z0 >= 0 && z1 < nz) {
+                    b0 = perm_start[col0 + z0 * T];
+                    e0 = perm_start[col0 + (z1 + 1) * T];
+                } else {
+                    b0 = perm_start[col0 + (z0 < 0 ? z0 + nz : z0) * T];
+                    e0 = perm_start[col0 + nz * T];
+                    b1 = perm_start[col0];
+                    e1 = perm_start[col0 + ((z1 >= nz ? z1 - nz : z1) + 1) * T];
                 }
-                bucket = (cell_base + (cc[0] * ny + cc[1]) * nz + cc[2]) * T + t;
+                const int n0 = e0 - b0, n = n0 + (e1 - b1), d1 = b1 - n0;
+                const double f0_off = (double)o0 / nx, f1_off = (double)o1 / ny, inv_nz = 1.0 / nz, qu = fi.q_unit;
+                for (int q = 0; q < n; q += 2) {
+                    const int k0 = q < n0 ? b0 + q : d1 + q;
+                    const int k1 = q + 1 < n0 ? b0 + q + 1 : d1 + q + 1;
+                    const int4 c0 = cell_rec[k0];
+                    const int4 c1 = q + 1 < n ? cell_rec[k1] : make_int4(0, 0, 0, 0);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int4 cr = u == 0 ? c0 : c1;
+                        const int j = u == 0 ? k0 : k1;  // tile slot of the candidate
+                        int oz = cr.w - ib[2];
+                        oz = oz > kCellReachZ ? oz - nz : (oz < -kCellReachZ ? oz + nz : oz);
+                        const double f0 = fma((double)(cr.x - own.x), qu, f0_off);
+                        const double f1 = fma((double)(cr.y - own.y), qu, f1_off);
+                        const double f2 = fma((double)(cr.z - own.z), qu, oz * inv_nz);
+                        const double dx = f0 * H[0] + f1 * H[3] + f2 * H[6];
+                        const double dy = f0 * H[1] + f1 * H[4] + f2 * H[7];
+                        const double dz = f0 * H[2] + f1 * H[5] + f2 * H[8];
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        // one branch per candidate: a real candidate, not the atom itself, within r_c
+                        if ((q + u < n) & (j != (int)p) & (r2 < rc2r)) {
+                            overlap |= r2 < 1e-8;
+                            ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)),
+                                             r2 < rc2a, nb_stage);
+                        }
+                        coop_flush(ps, nb_stage, list);
+                    }
+                }
             }
-            // bucket (c, t) is the slot range perm_start[c T + t] .. perm_start[(c + 1) T + t]
-            const int b = perm_start[bucket], e = perm_start[bucket + T];
-            // candidates two at a time: both loads in flight before either is used
+        } else {
+            // one bin per frame: wrapped fractional positions, minimum image by rounding
+            const int b = perm_start[cell_base * T + t], e = perm_start[(cell_base + 1) * T + t];
             for (int k0 = b; k0 < e; k0 += 2) {
                 const double4 q0 = bucket_pos[k0];
                 const double4 q1 = k0 + 1 < e ? bucket_pos[k0 + 1] : make_double4(0.0, 0.0, 0.0, 0.0);
@@ -769,17 +816,14 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                 for (int u = 0; u < 2; ++u) {
                     const double4 cur = u == 0 ? q0 : q1;
                     const int j = k0 + u;  // tile slot of the candidate
-                    double f0 = cur.x + sh[0], f1 = cur.y + sh[1], f2 = cur.z + sh[2];
-                    if (mode != 1) {
-                        f0 -= rint(f0);
-                        f1 -= rint(f1);
-                        f2 -= rint(f2);
-                    }
+                    double f0 = cur.x - si[0], f1 = cur.y - si[1], f2 = cur.z - si[2];
+                    f0 -= rint(f0);
+                    f1 -= rint(f1);
+                    f2 -= rint(f2);
                     const double dx = f0 * H[0] + f1 * H[3] + f2 * H[6];
                     const double dy = f0 * H[1] + f1 * H[4] + f2 * H[7];
                     const double dz = f0 * H[2] + f1 * H[5] + f2 * H[8];
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    // one branch per candidate: a real candidate, not the atom itself, within r_c
                     if ((k0 + u < e) & (j != (int)p) & (r2 < rc2r)) {
                         overlap |= r2 < 1e-8;
                         ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)), r2 < rc2a,
@@ -872,7 +916,8 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                                                  rc_radial, rc_angular, nl, cl, d_flags);
     if (triclinic)
         k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, w.key_of, w.perm_start,
-                                                               w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
+                                                               w.bucket_pos, w.cell_rec, rc_radial, rc_angular, nl,
+                                                               d_flags);
     if (followers)
         k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                   rc_radial, rc_angular, nl, cl, d_flags);

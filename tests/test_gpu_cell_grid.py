@@ -7,7 +7,8 @@ the cells.  These cases exercise the grid shapes that the water benchmark
 does not: exactly five cells per axis (edges between 2.5 and 3 r_c, which a
 grid of r_c cells could not serve), unequal cell counts per axis, a sparse
 frame whose grid is coarsened, atoms given far outside the box, trajectory
-reuse on such a grid, and all of them in one call.  Bound: per-frame
+reuse on such a grid, and all of them in one call; and the same shapes for
+the fractional bins of skewed cells.  Bound: per-frame
 relative Frobenius error <= 1e-5 (tests/parity.py).
 """
 import numpy as np
@@ -128,3 +129,45 @@ def test_trajectory_reuse_on_unequal_grid(gpu_lib):
     _check(b[[0, 5, 11]], m, sub, "reuse")
     for c in (plain, reuse):
         c.close()
+
+
+def _skewed_frame(L, shear, n, seed, min_sep=1.3):
+    """Random atoms (no two closer than min_sep under the minimum image) in a
+    skewed, rotated cell; fractional coordinates drawn from [-0.5, 1.5) so that
+    many atoms lie outside the cell as given."""
+    rng = np.random.default_rng(seed)
+    R, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    H = np.array([[L, 0, 0], [shear * L, L, 0], [0.1 * L, -shear * L, 1.1 * L]]) @ R.T
+    Hinv = np.linalg.inv(H)
+    pts = []
+    while len(pts) < n:
+        r = rng.uniform(-0.5, 1.5, 3) @ H
+        if all(np.linalg.norm(((((r - q) @ Hinv) + 0.5) % 1.0 - 0.5) @ H) >= min_sep for q in pts):
+            pts.append(r)
+    return np.array(pts), rng.integers(0, 2, n).astype(np.int32), H.reshape(9)
+
+
+SKEWED = {
+    # perpendicular widths ~15.1, 15.4, 17.6 A: 5 bins of >= r_c / 2 per axis
+    "skewed_five_bins": (16.0, 0.3, 200, 31),
+    # widths ~17.2, 18.2, 22.0 A: 5, 6 and 7 bins
+    "skewed_5_6_7": (20.0, 0.5, 300, 32),
+    # widths ~29-33 A with 120 atoms: the grid is coarsened to about two bins per atom
+    "skewed_coarsened": (30.0, 0.2, 120, 33),
+}
+
+
+@pytest.mark.parametrize("name", ["water_dipole_small", "water_polarizability"])
+def test_triclinic_bins(gpu_lib, name):
+    m = synth.model(name)
+    ctx = gpu_lib.Context(0)
+    g = gpu_lib.Model(ctx, m)
+    f = gpu_lib.tnep_eval_dipole if m.kind == synth.KIND_DIPOLE else gpu_lib.tnep_eval_polarizability
+    items = [_skewed_frame(*args) for args in SKEWED.values()]
+    for label, item in zip(SKEWED, items):
+        fr = _frames([item])
+        _check(f(ctx, g, fr), m, fr, f"{name} {label}")
+    batched = f(ctx, g, _frames(items))
+    for k, item in enumerate(items):
+        assert np.array_equal(batched[k], f(ctx, g, _frames([item]))[0]), k
+    ctx.close()
