@@ -171,3 +171,30 @@ def test_triclinic_bins(gpu_lib, name):
     for k, item in enumerate(items):
         assert np.array_equal(batched[k], f(ctx, g, _frames([item]))[0]), k
     ctx.close()
+
+
+def test_pes_forces_on_grids(gpu_lib):
+    """Potential-energy model on the grid shapes above, orthorhombic and
+    skewed: energy, virial and forces against the oracle, and the forces of a
+    frame summing to zero.  The force kernel reads each pair force that the
+    neighbour's evaluation stored at its own entry for the atom, so it relies
+    on both atoms of a pair sorting it into the same (angular or radial-only)
+    segment."""
+    m = synth.model("water_pes")
+    ctx = gpu_lib.Context(0)
+    g = gpu_lib.Model(ctx, m)
+    items = [_lattice_frame(*CASES["five_cells"][:3], unwrap=10), _skewed_frame(*SKEWED["skewed_5_6_7"]),
+             _skewed_frame(*SKEWED["skewed_five_bins"])]
+    fr = _frames(items)
+    E, W, F = gpu_lib.tnep_eval_pes(ctx, g, fr)
+    Er, Wr, Fr, Ur = oracle.eval_pes(m, fr, per_atom=True)
+    off = fr.offsets
+    for f in range(fr.n_frames):
+        sl = slice(off[f], off[f + 1])
+        assert abs(E[f] - Er[f]) <= TENSOR_TOL * np.abs(Ur[sl]).sum(), f
+        ferr = np.linalg.norm(F[sl] - Fr[sl]) / np.linalg.norm(Fr[sl])
+        net = np.linalg.norm(F[sl].sum(0)) / np.abs(F[sl]).sum()
+        print(f"pes frame {f}: forces {ferr:.2e}, net force / sum |F| {net:.1e}", flush=True)
+        assert ferr <= TENSOR_TOL and net <= 1e-6, f
+    assert np.all(frame_errors(W, Wr) <= TENSOR_TOL)
+    ctx.close()

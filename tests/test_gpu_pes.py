@@ -5,8 +5,8 @@ Tolerances (FP32 arithmetic, FP64 sums):
           energies' size, since their sum can cancel);
   virial: per-frame relative Frobenius error <= 1e-5 (tests/parity.py metric);
   forces: per-frame ||F_gpu - F_ref||_F / ||F_ref||_F <= 1e-5.
-Forces are fixed-point sums, so they are bitwise reproducible whatever the
-batching and the order of the atomic additions.
+Forces are summed in each atom's fixed neighbour-list order (no atomics), so
+they are bitwise reproducible whatever the batching.
 """
 import numpy as np
 import pytest
