@@ -467,7 +467,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if (job.models[k]->kind == TNEP_KIND_PES) rec_stride = pes_rec_stride(job.models[k]->shape, T);
             const bool pes = rec_stride > 0;
             const int64_t per_atom_bytes = (int64_t)slots * 16 + 8 * T + 24 + 80 * (last - first) +
-                                           (fr.location == TNEP_HOST ? 28 : 0) + (pes ? 4 * rec_stride + 32 + (int64_t)slots * 16 : 0);
+                                           (fr.location == TNEP_HOST ? 28 : 0) + (pes ? 4 * rec_stride + 32 + (int64_t)slots * 16 : 0) +
+                                           (last - first >= 2 ? 4 * T * 32 : 0);  // shared radial sums (KR <= 32)
             int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
             B = std::max(B, largest);
             const int64_t room = (int64_t)c->budget - (int64_t)(c->in_use - c->nbr.bytes - c->per_atom.bytes);
@@ -511,6 +512,15 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if (fr.location == TNEP_HOST && (e = c->reserve(c->pes_stage, (size_t)B_res * 4 * sizeof(double))))
                     return e;
             }
+            // the radial descriptor sums depend only on the lists, r_c^R and KR: with
+            // the FP32 vector hidden layer (which can load them) the first model
+            // stores them and the others load them
+            bool share_rad = last - first >= 2 && c->launch.mlp_mode == TNEP_MLP_FP32_VALU;
+            for (int k = first; k < last && share_rad; ++k)
+                share_rad = job.models[k]->kind != TNEP_KIND_PES && job.models[k]->shape.kr == job.models[first]->shape.kr;
+            if (share_rad &&
+                (e = c->reserve(c->rad_sums, (size_t)n_pad_max * T * job.models[first]->shape.kr * sizeof(float))))
+                return e;
             if ((e = c->reserve(c->flags, 32 * 4))) return e;
             if (fr.location == TNEP_HOST) {
                 if ((e = c->reserve(c->pos, (size_t)B_res * 24))) return e;
@@ -710,7 +720,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE           ? TNEP_KERNEL_EVAL_DIPOLE
                                             : m->kind == TNEP_KIND_POLARIZABILITY ? TNEP_KERNEL_EVAL_POLARIZABILITY
                                                                                   : TNEP_KERNEL_EVAL_PES);
-                        he = launch_eval(m->shape, m->dm, nl, pa_of[q], pes_out, c->launch, c->stream);
+                        const RadSums rs{(float*)c->rad_sums.p, share_rad ? (q == 0 ? 1 : 2) : 0};
+                        he = launch_eval(m->shape, m->dm, nl, pa_of[q], pes_out, rs, c->launch, c->stream);
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;
                         tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);

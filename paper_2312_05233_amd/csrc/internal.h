@@ -193,8 +193,19 @@ bool eval_shape_supported(const Shape& s);
 // Whether the matrix-core hidden layer is compiled for this shape (else the
 // FP32 vector path runs whatever TNEP_OPT_MLP says).
 bool eval_matrix_supported(const Shape& s, int n_hidden);
+// Radial descriptor sums shared by the models of one call: the per-slot sums
+// over the neighbours of species t of f_k(r_ij) (T * KR floats per slot at
+// v[(t * KR + k) * n_pad + p]) depend only on the lists, r_c^R and KR, not on
+// a model's coefficients.  mode 0: compute; 1: compute and store; 2: load
+// (a model of the same lists, r_c^R and KR stored them earlier on the stream).
+// Loading is used with the FP32 vector hidden layer only; the caller asks for
+// 1 and 2 only when every model of the call runs that layer.
+struct RadSums {
+    float* v;
+    int32_t mode;
+};
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
-                       const PesOut& pes, const EvalLaunch& cfg, hipStream_t s);
+                       const PesOut& pes, const RadSums& rs, const EvalLaunch& cfg, hipStream_t s);
 
 // Potential-energy models, after launch_eval over the same lists: forces[a]
 // (FP64, NULL to skip) = sum_j dU_a/dr_aj - sum_j dU_j/dr_ja, summed in a fixed

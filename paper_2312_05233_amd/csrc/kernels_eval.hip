@@ -319,9 +319,15 @@ __host__ __device__ constexpr int mlp_lds_floats(int D, int H) {
 // wave-uniform and read with scalar loads.  MODE selects the hidden layer:
 // FP32 vector ALU (no LDS) or one of the matrix-core variants (LDS tile per
 // wavefront).  Padding lanes run with empty neighbour lists and store nothing.
-template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE>
+// LOAD: the radial descriptor sums come from rad_v (another model of the same
+// lists stored them); otherwise they are computed, and stored when rad_mode ==
+// 1.  rad_v, pes_rec and pes_pair (the potential-energy outputs of PesOut) are
+// restrict parameters, so that their stores cannot clobber the model's
+// parameters and these stay wave-uniform scalar loads.
+template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE, bool LOAD = false>
 __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, double* __restrict__ per_atom,
-                                                 PesOut pes) {
+                                                 PesOut pes, float* __restrict__ rad_v, int rad_mode,
+                                                 float* __restrict__ pes_rec, float4* __restrict__ pes_pair) {
     constexpr bool FOURB = (MB & 1) != 0, FIVEB = (MB & 2) != 0;
     constexpr int D = NR + 4 * NA + (FOURB ? NA : 0) + (FIVEB ? NA : 0);
     constexpr int NT = KIND == 1 ? 3 : 9;  // accumulated tensor: mu, or the virial-like W
@@ -372,7 +378,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float rinv = pair_rsqrt(r2);
             const float r = r2 * rinv;
             float Tk[KR > KA ? KR : KA];
-            {
+            if constexpr (!LOAD) {
                 const float fc = cutoff_fc(1.f - r * rcR_inv);
                 const float tt = r * rcR_inv - 1.f;
                 cheb_T<KR>(2.f * tt * tt - 1.f, Tk);
@@ -397,22 +403,30 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
                 for (int n = 0; n < NA; ++n) A[n][idx] += gA[n] * P;
             });
         }
-        nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int s = 0; s < n_rad; ++s) {
-            const float4 e = nxt;
-            if (s + 1 < n_rad) nxt = gr[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
-            const float r = pair_sqrt(e.x * e.x + e.y * e.y + e.z * e.z);
-            const float fc = cutoff_fc(1.f - r * rcR_inv);
-            const float tt = r * rcR_inv - 1.f;
-            float Tk[KR];
-            cheb_T<KR>(2.f * tt * tt - 1.f, Tk);
-            Fs += fc;
-#pragma unroll
-            for (int k = 0; k < KR; ++k) FT[k] += fc * Tk[k];
-        }
         float F[KR];
+        if constexpr (LOAD) {
 #pragma unroll
-        for (int k = 0; k < KR; ++k) F[k] = 0.5f * (FT[k] + Fs);
+            for (int k = 0; k < KR; ++k) F[k] = rad_v[(int64_t)(t * KR + k) * nl.n_pad + p];
+        } else {
+            nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int s = 0; s < n_rad; ++s) {
+                const float4 e = nxt;
+                if (s + 1 < n_rad) nxt = gr[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
+                const float r = pair_sqrt(e.x * e.x + e.y * e.y + e.z * e.z);
+                const float fc = cutoff_fc(1.f - r * rcR_inv);
+                const float tt = r * rcR_inv - 1.f;
+                float Tk[KR];
+                cheb_T<KR>(2.f * tt * tt - 1.f, Tk);
+                Fs += fc;
+#pragma unroll
+                for (int k = 0; k < KR; ++k) FT[k] += fc * Tk[k];
+            }
+#pragma unroll
+            for (int k = 0; k < KR; ++k) F[k] = 0.5f * (FT[k] + Fs);
+            if (rad_mode == 1)
+#pragma unroll
+                for (int k = 0; k < KR; ++k) rad_v[(int64_t)(t * KR + k) * nl.n_pad + p] = F[k];
+        }
 #pragma unroll
         for (int n = 0; n < NR; ++n)
 #pragma unroll
@@ -532,7 +546,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     float* rec = nullptr;
     if constexpr (KIND == 3) {
         if (a >= 0) {
-            rec = pes.rec + p * pes.rec_stride;
+            rec = pes_rec + p * pes.rec_stride;
             for (int t = 0; t < T; ++t) {
                 const float* __restrict__ cR = m.c_radial + (ti * T + t) * (NR * KR);
 #pragma unroll
@@ -669,7 +683,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float fx = Fx * rinv + ux * su, fy = Fy * rinv + uy * su, fz = Fz * rinv + uz * su;
             contract(e.x, e.y, e.z, r2, fx, fy, fz);
             if constexpr (KIND == 3) {
-                if (a >= 0) pes.pair[(ga - nl.entries) + ((s >> 2) * 256 + (s & 3))] = make_float4(fx, fy, fz, 0.f);
+                if (a >= 0) pes_pair[(ga - nl.entries) + ((s >> 2) * 256 + (s & 3))] = make_float4(fx, fy, fz, 0.f);
             }
         }
         nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -897,50 +911,53 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
 }
 
 template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE>
-hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom, const PesOut& pes, int block,
-                    hipStream_t s) {
+hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom, const PesOut& pes,
+                    const RadSums& rs, int block, hipStream_t s) {
     constexpr int D = NR + 4 * NA + ((MB & 1) ? NA : 0) + ((MB & 2) ? NA : 0);
     if constexpr (MODE == TNEP_MLP_FP32_VALU) {
         const int bs = (block == 64 || block == 128) ? block : 256;
         const unsigned grid = (unsigned)((nl.n_pad + bs - 1) / bs);
-        k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom, pes);
+        if (KIND != 3 && rs.mode == 2)
+            k_eval<NR, NA, KR, KA, MB, KIND, MODE, KIND != 3><<<grid, bs, 0, s>>>(m, nl, per_atom, pes, rs.v, rs.mode, pes.rec, pes.pair);
+        else
+            k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom, pes, rs.v, rs.mode, pes.rec, pes.pair);
     } else {
         // two wavefronts per work-group keep the LDS tiles at <= 2 x 27 KB
         const unsigned grid = (unsigned)((nl.n_pad + 127) / 128);
         const size_t lds = sizeof(float) * 2 * (size_t)mlp_lds_floats(D, m.n_hidden);
-        k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom, pes);
+        k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom, pes, nullptr, 0, pes.rec, pes.pair);
     }
     return hipGetLastError();
 }
 
 template <int NR, int NA, int KR, int KA, int MB, int KIND>
 hipError_t launch_mode(int mode, bool matrix, const DevModel& m, const NeighborLists& nl, double* per_atom,
-                       const PesOut& pes, int block, hipStream_t s) {
+                       const PesOut& pes, const RadSums& rs, int block, hipStream_t s) {
     if (matrix) {
         if (mode == TNEP_MLP_FP32_MFMA)
-            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, pes, block, s);
+            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, pes, rs, block, s);
         if (mode == TNEP_MLP_BF16_MFMA)
-            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, pes, block, s);
+            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, pes, rs, block, s);
         if (mode == TNEP_MLP_BF16X3_MFMA)
-            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, pes, block, s);
+            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, pes, rs, block, s);
     }
-    return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
+    return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, s);
 }
 
 // Potential-energy models always use the FP32 vector hidden layer.
 template <int NR, int NA, int KR, int KA, int MB, bool MX>
 hipError_t dispatch(const Shape& shape, int mode, bool matrix, const DevModel& m, const NeighborLists& nl,
-                    double* per_atom, const PesOut& pes, int block, hipStream_t s) {
+                    double* per_atom, const PesOut& pes, const RadSums& rs, int block, hipStream_t s) {
     if (shape.kind == 3)
-        return launch_t<NR, NA, KR, KA, MB, 3, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
+        return launch_t<NR, NA, KR, KA, MB, 3, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, s);
     if constexpr (MX) {
         if (shape.kind == 1)
-            return launch_mode<NR, NA, KR, KA, MB, 1>(mode, matrix, m, nl, per_atom, pes, block, s);
-        return launch_mode<NR, NA, KR, KA, MB, 2>(mode, matrix, m, nl, per_atom, pes, block, s);
+            return launch_mode<NR, NA, KR, KA, MB, 1>(mode, matrix, m, nl, per_atom, pes, rs, block, s);
+        return launch_mode<NR, NA, KR, KA, MB, 2>(mode, matrix, m, nl, per_atom, pes, rs, block, s);
     } else {
         if (shape.kind == 1)
-            return launch_t<NR, NA, KR, KA, MB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
-        return launch_t<NR, NA, KR, KA, MB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, block, s);
+            return launch_t<NR, NA, KR, KA, MB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, s);
+        return launch_t<NR, NA, KR, KA, MB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, s);
     }
 }
 
@@ -976,7 +993,7 @@ bool eval_matrix_supported(const Shape& s, int n_hidden) {
 }
 
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
-                       const PesOut& pes, const EvalLaunch& cfg, hipStream_t s) {
+                       const PesOut& pes, const RadSums& rs, const EvalLaunch& cfg, hipStream_t s) {
     if (nl.n_pad == 0) return hipSuccess;
     // the matrix-core hidden layer holds one shared network
     const bool matrix =
@@ -984,7 +1001,7 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
 #define X(NR_, NA_, KR_, KA_, FB_, MX_)                                                             \
     if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                \
         shape_bodies(shape) == FB_)                                                             \
-        return dispatch<NR_, NA_, KR_, KA_, FB_, MX_>(shape, cfg.mlp_mode, matrix, m, nl, per_atom, pes,      \
+        return dispatch<NR_, NA_, KR_, KA_, FB_, MX_>(shape, cfg.mlp_mode, matrix, m, nl, per_atom, pes, rs,  \
                                                       cfg.atoms_per_block, s);
     TNEP_SHAPES(X)
 #undef X

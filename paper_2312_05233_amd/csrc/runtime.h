@@ -68,6 +68,7 @@ struct Ctx {
     DevBuf slot_of, cand, cand_count;  // tile slot per atom; trajectory candidate lists
     DevBuf com;                        // charged-dipole shift: staging of frames, masses, charges, mu
     DevBuf red_part;                   // frame sums: per-chunk partial sums
+    DevBuf rad_sums;                   // radial descriptor sums shared by the models of a call
     DevBuf pop_stage, pop_work, pop_img;  // population loss: staged frames, predictions, model images
     float* pop_host = nullptr;            // pinned host staging of the population's model images
     size_t pop_host_bytes = 0;
@@ -76,7 +77,7 @@ struct Ctx {
         return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
                 &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &pes_pair, &slot_of, &cand, &cand_count, &com,
-                &pop_stage, &pop_work, &pop_img, &red_part};
+                &pop_stage, &pop_work, &pop_img, &red_part, &rad_sums};
     }
 
     Server* server = nullptr;

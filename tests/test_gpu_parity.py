@@ -88,6 +88,10 @@ def test_full_size_water_frame(gpu_lib, ctx):
     mu, al = gpu_lib.tnep_eval_dipole_polarizability(ctx, gd, gp, fr)
     _check(mu, md, fr, "water 12288 dipole")
     _check(al, mp, fr, "water 12288 polarizability")
+    # the combined call shares the radial descriptor sums between the models:
+    # bit for bit the single-model calls
+    assert np.array_equal(gpu_lib.tnep_eval_dipole(ctx, gd, fr), mu)
+    assert np.array_equal(gpu_lib.tnep_eval_polarizability(ctx, gp, fr), al)
 
 
 def test_deterministic_and_batch_invariant(gpu_lib, ctx):
