@@ -35,18 +35,25 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X, published FP32 vector peak
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "eval_polarizability_water12288_traffic.md")
 
 
+RADIAL_TERMS_SEARCHED = 9  # radial basis size whose sums the neighbour search forms
+
+
 def radial_forward_flops(model):
-    """Forward share of f_R: basis, contraction and accumulation of the radial
-    descriptor, which a model that loads the radial sums shared by the models
-    of a call does not compute."""
+    """Forward share of f_R: basis and accumulation of the radial sums, which
+    the neighbour search forms for models of RADIAL_TERMS_SEARCHED radial
+    terms, so that their evaluation kernels load them."""
     nR, KR = model.n_max_radial + 1, model.basis_radial + 1
     return 2 * nR * KR + 4 * KR + nR + 20
 
 
-def flops_per_atom_frame(model, n_rad_mean, n_ang_mean, radial_forward=True):
-    """Algorithmic FP32 work per atom-frame (FMA = 2 flops), no recomputation:
-    f_R per radial pair, f_A per angular pair, f_atom per atom; without the
-    forward radial share when the kernel loads the shared radial sums."""
+def flops_per_atom_frame(model, n_rad_mean, n_ang_mean, radial_forward=None):
+    """Algorithmic FP32 work per atom-frame of the evaluation kernel (FMA = 2
+    flops), no recomputation: f_R per radial pair, f_A per angular pair, f_atom
+    per atom; without the forward radial share when the kernel loads the
+    radial sums that the neighbour search formed (by default: when the model
+    has RADIAL_TERMS_SEARCHED radial terms)."""
+    if radial_forward is None:
+        radial_forward = model.basis_radial + 1 != RADIAL_TERMS_SEARCHED
     nR, nA = model.n_max_radial + 1, model.n_max_angular + 1
     KR, KA = model.basis_radial + 1, model.basis_angular + 1
     L = (model.l_max + 1) ** 2 - 1
@@ -62,7 +69,7 @@ def flops_per_atom_frame(model, n_rad_mean, n_ang_mean, radial_forward=True):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels_eval.hip", "tnep_math.h"):
+    for f in ("kernels_eval.hip", "tnep_math.h", "radial_basis.h"):
         with open(os.path.join(ROOT, "paper_2312_05233_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -274,10 +281,7 @@ def bench_population(args):
     kt = {name: ctx.kernel_time(k)[0] / args.steps for name, k in (
         ("neighbors", tnep.KERNEL_NEIGHBORS), ("eval_polarizability", tnep.KERNEL_EVAL_POLARIZABILITY),
         ("frame_reduce", tnep.KERNEL_FRAME_REDUCE))}
-    # the first individual of the call computes the radial descriptor sums, the
-    # others load them
-    flop = (flops_per_atom_frame(base, rad / atoms, ang / atoms) +
-            (n_pop - 1) * flops_per_atom_frame(base, rad / atoms, ang / atoms, radial_forward=False)) / n_pop
+    flop = flops_per_atom_frame(base, rad / atoms, ang / atoms)
     atoms_per_launch = frames.n_atoms * n_pop / (n / args.steps)
     achieved = flop * atoms_per_launch / (ms / n * 1e-3) / 1e12
     evals = frames.n_atoms * n_pop
@@ -713,9 +717,9 @@ def main():
     n_ang = ang_pairs / atoms
     pol_ms, pol_launches = kt["eval_polarizability"]
     atoms_per_launch = atoms / pol_launches
-    # in the combined call the polarizability kernel loads the radial descriptor
-    # sums that the dipole kernel computed: their forward flops are not its work
-    flop_af = flops_per_atom_frame(mp, n_rad, n_ang, radial_forward=False)
+    # the kernel loads the radial descriptor sums that the neighbour search
+    # formed: their forward flops are not its work
+    flop_af = flops_per_atom_frame(mp, n_rad, n_ang)
     achieved = flop_af * atoms_per_launch / (pol_ms / pol_launches * 1e-3) / 1e12
     traffic = read_traffic(atoms_per_launch)
 
@@ -756,8 +760,8 @@ def main():
             "avg_launch_ms": pol_ms / pol_launches,
             "mean_radial_neighbors": n_rad,
             "mean_angular_neighbors": n_ang,
-            "note": "radial descriptor sums shared with the dipole kernel of the call; their forward flops are "
-                    "not counted for this kernel",
+            "note": "radial descriptor sums formed by the neighbour search; their forward flops are not counted "
+                    "for this kernel",
         },
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "autotune": ctx.autotune_report(),

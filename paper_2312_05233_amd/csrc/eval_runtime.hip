@@ -468,7 +468,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             const bool pes = rec_stride > 0;
             const int64_t per_atom_bytes = (int64_t)slots * 16 + 8 * T + 24 + 80 * (last - first) +
                                            (fr.location == TNEP_HOST ? 28 : 0) + (pes ? 4 * rec_stride + 32 + (int64_t)slots * 16 : 0) +
-                                           (last - first >= 2 ? 4 * T * 32 : 0);  // shared radial sums (KR <= 32)
+                                           4 * T * kRadialTerms;  // radial descriptor sums
             int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
             B = std::max(B, largest);
             const int64_t room = (int64_t)c->budget - (int64_t)(c->in_use - c->nbr.bytes - c->per_atom.bytes);
@@ -512,15 +512,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if (fr.location == TNEP_HOST && (e = c->reserve(c->pes_stage, (size_t)B_res * 4 * sizeof(double))))
                     return e;
             }
-            // the radial descriptor sums depend only on the lists, r_c^R and KR: with
-            // the FP32 vector hidden layer (which can load them) the first model
-            // stores them and the others load them
-            bool share_rad = last - first >= 2 && c->launch.mlp_mode == TNEP_MLP_FP32_VALU;
-            for (int k = first; k < last && share_rad; ++k)
-                share_rad = job.models[k]->kind != TNEP_KIND_PES && job.models[k]->shape.kr == job.models[first]->shape.kr;
-            if (share_rad &&
-                (e = c->reserve(c->rad_sums, (size_t)n_pad_max * T * job.models[first]->shape.kr * sizeof(float))))
-                return e;
+            // the radial descriptor sums depend only on the lists, r_c^R and KR: the
+            // neighbour search accumulates them, and the FP32 vector kernels of models
+            // with KR = kRadialTerms load them
+            if ((e = c->reserve(c->rad_sums, (size_t)n_pad_max * T * kRadialTerms * sizeof(float)))) return e;
             if ((e = c->reserve(c->flags, 32 * 4))) return e;
             if (fr.location == TNEP_HOST) {
                 if ((e = c->reserve(c->pos, (size_t)B_res * 24))) return e;
@@ -707,7 +702,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     he = launch_neighbors((const FrameInfo*)c->frames.p, cap_frames, pos, spc, cap_atoms,
                                           (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl, cl,
                                           n_ref_atoms > 0, followers, triclinic, (int32_t*)c->flags.p,
-                                          c->launch.neigh_block, c->stream);
+                                          c->launch.neigh_block, (float*)c->rad_sums.p, c->stream);
                     c->timer_end(tr);
                     if (he != hipSuccess) return he;
                     if (c->timing) {
@@ -720,7 +715,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE           ? TNEP_KERNEL_EVAL_DIPOLE
                                             : m->kind == TNEP_KIND_POLARIZABILITY ? TNEP_KERNEL_EVAL_POLARIZABILITY
                                                                                   : TNEP_KERNEL_EVAL_PES);
-                        const RadSums rs{(float*)c->rad_sums.p, share_rad ? (q == 0 ? 1 : 2) : 0};
+                        const RadSums rs{(float*)c->rad_sums.p, 2};
                         he = launch_eval(m->shape, m->dm, nl, pa_of[q], pes_out, rs, c->launch, c->stream);
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;

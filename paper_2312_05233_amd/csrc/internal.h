@@ -22,6 +22,10 @@ enum FrameRole { kRolePlain = 0, kRoleReference = 1, kRoleFollower = 2 };
 constexpr int kCellReachXY = 2;
 constexpr int kCellReachZ = 2;
 
+// Radial basis terms (K_R + 1) of every compiled descriptor shape: the
+// neighbour search accumulates the radial descriptor sums for this size.
+constexpr int kRadialTerms = 9;
+
 struct FrameInfo {
     int64_t atom_begin;  // first atom, batch-local index
     int32_t n_atoms;
@@ -162,7 +166,7 @@ struct NeighborWork {
 hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
-                            bool triclinic, int32_t* d_flags, int neigh_block, hipStream_t s);
+                            bool triclinic, int32_t* d_flags, int neigh_block, float* rad_sums, hipStream_t s);
 
 // ---- evaluation (kernels_eval.hip) ----
 struct EvalLaunch {
@@ -193,13 +197,13 @@ bool eval_shape_supported(const Shape& s);
 // Whether the matrix-core hidden layer is compiled for this shape (else the
 // FP32 vector path runs whatever TNEP_OPT_MLP says).
 bool eval_matrix_supported(const Shape& s, int n_hidden);
-// Radial descriptor sums shared by the models of one call: the per-slot sums
-// over the neighbours of species t of f_k(r_ij) (T * KR floats per slot at
-// v[(t * KR + k) * n_pad + p]) depend only on the lists, r_c^R and KR, not on
-// a model's coefficients.  mode 0: compute; 1: compute and store; 2: load
-// (a model of the same lists, r_c^R and KR stored them earlier on the stream).
-// Loading is used with the FP32 vector hidden layer only; the caller asks for
-// 1 and 2 only when every model of the call runs that layer.
+// Radial descriptor sums: per slot, the sums over the neighbours of species t
+// of f_k(r_ij) (T * kRadialTerms floats at v[(t * kRadialTerms + k) * n_pad +
+// p]), which depend only on the lists, r_c^R and KR, not on a model's
+// coefficients; the neighbour search accumulates them.  mode 0: the
+// evaluation forms them itself; 2: v holds them, and the FP32 vector kernel of
+// a model with KR = kRadialTerms loads them (the matrix-core kernels, which
+// also serve other basis sizes, form them).
 struct RadSums {
     float* v;
     int32_t mode;

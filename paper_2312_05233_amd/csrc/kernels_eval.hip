@@ -16,86 +16,11 @@
 #include "../../include/tnep.h"
 #include "internal.h"
 #include "tnep_math.h"
+#include "radial_basis.h"
 
 namespace tnep {
 
 namespace {
-
-// Cosine cutoff f_c(r) = (1 + cos(pi r / r_c)) / 2 = sin^2(w), w = (pi/2)(1 - r/r_c),
-// which keeps relative accuracy as r -> r_c; f_c'(r) = -(pi / r_c) sin(w) cos(w).
-// sin and cos of w in [0, pi/2] from their Taylor series to w^13 / w^14
-// (truncation below 1e-9).  v = 1 - r / r_c.
-__device__ __forceinline__ float sin_half_pi(float w) {
-    const float w2 = w * w;
-    float p = 1.f / 6227020800.f;
-    p = p * w2 - 1.f / 39916800.f;
-    p = p * w2 + 1.f / 362880.f;
-    p = p * w2 - 1.f / 5040.f;
-    p = p * w2 + 1.f / 120.f;
-    p = p * w2 - 1.f / 6.f;
-    p = p * w2 + 1.f;
-    return w * p;
-}
-__device__ __forceinline__ float cos_half_pi(float w) {
-    const float w2 = w * w;
-    float p = -1.f / 87178291200.f;
-    p = p * w2 + 1.f / 479001600.f;
-    p = p * w2 - 1.f / 3628800.f;
-    p = p * w2 + 1.f / 40320.f;
-    p = p * w2 - 1.f / 720.f;
-    p = p * w2 + 1.f / 24.f;
-    p = p * w2 - 0.5f;
-    p = p * w2 + 1.f;
-    return p;
-}
-__device__ __forceinline__ float cutoff_fc(float v) {
-    const float s = sin_half_pi(1.57079632679489662f * v);
-    return s * s;
-}
-__device__ __forceinline__ void cutoff_fc_d(float v, float rc_inv, float& fc, float& dfc) {
-    const float w = 1.57079632679489662f * v;
-    const float s = sin_half_pi(w), c = cos_half_pi(w);
-    fc = s * s;
-    dfc = -3.14159265358979323846f * rc_inv * s * c;
-}
-
-// Pair distances from the hardware square root and reciprocal square root
-// (about 1 ulp): squared pair distances lie far inside the normal range, so
-// the scaling and correction steps that the library forms add (about 16 and 6
-// instructions) buy nothing here.
-__device__ __forceinline__ float pair_rsqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
-__device__ __forceinline__ float pair_sqrt(float r2) { return __builtin_amdgcn_sqrtf(r2); }
-
-// Chebyshev polynomials T_k(x), k = 0..K-1 (three-term recurrence).  The
-// radial basis is f_k = (T_k(x) + 1)/2 f_c, so sums of f_k and of their
-// contractions with coefficients are formed from sums of T_k (one fused
-// multiply-add per term) instead of building every f_k.
-template <int K>
-__device__ __forceinline__ void cheb_T(float x, float* T) {
-    T[0] = 1.f;
-    if (K > 1) T[1] = x;
-    const float x2 = x + x;
-#pragma unroll
-    for (int k = 2; k < K; ++k) T[k] = x2 * T[k - 1] - T[k - 2];
-}
-
-// T_k(x) and dT_k/dx.
-template <int K>
-__device__ __forceinline__ void cheb_T_d(float x, float* T, float* dT) {
-    T[0] = 1.f;
-    dT[0] = 0.f;
-    if (K > 1) {
-        T[1] = x;
-        dT[1] = 1.f;
-    }
-    const float x2 = x + x;
-#pragma unroll
-    for (int k = 2; k < K; ++k) {
-        T[k] = x2 * T[k - 1] - T[k - 2];
-        dT[k] = 2.f * T[k - 1] + x2 * dT[k - 1] - dT[k - 2];
-    }
-}
-
 
 // The real spherical harmonics of sh_foreach without their normalisation
 // constants: Y_lm = kShNorm[idx] * P_lm(u) with P_lm the integer-coefficient
@@ -319,14 +244,14 @@ __host__ __device__ constexpr int mlp_lds_floats(int D, int H) {
 // wave-uniform and read with scalar loads.  MODE selects the hidden layer:
 // FP32 vector ALU (no LDS) or one of the matrix-core variants (LDS tile per
 // wavefront).  Padding lanes run with empty neighbour lists and store nothing.
-// LOAD: the radial descriptor sums come from rad_v (another model of the same
-// lists stored them); otherwise they are computed, and stored when rad_mode ==
-// 1.  rad_v, pes_rec and pes_pair (the potential-energy outputs of PesOut) are
-// restrict parameters, so that their stores cannot clobber the model's
-// parameters and these stay wave-uniform scalar loads.
+// LOAD: the radial descriptor sums come from rad_v (the neighbour search
+// accumulated them); otherwise the kernel forms them.  pes_rec and pes_pair
+// (the potential-energy outputs of PesOut) are restrict parameters, so that
+// their stores cannot clobber the model's parameters and these stay
+// wave-uniform scalar loads.
 template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE, bool LOAD = false>
 __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, double* __restrict__ per_atom,
-                                                 PesOut pes, float* __restrict__ rad_v, int rad_mode,
+                                                 PesOut pes, const float* __restrict__ rad_v,
                                                  float* __restrict__ pes_rec, float4* __restrict__ pes_pair) {
     constexpr bool FOURB = (MB & 1) != 0, FIVEB = (MB & 2) != 0;
     constexpr int D = NR + 4 * NA + (FOURB ? NA : 0) + (FIVEB ? NA : 0);
@@ -423,9 +348,6 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             }
 #pragma unroll
             for (int k = 0; k < KR; ++k) F[k] = 0.5f * (FT[k] + Fs);
-            if (rad_mode == 1)
-#pragma unroll
-                for (int k = 0; k < KR; ++k) rad_v[(int64_t)(t * KR + k) * nl.n_pad + p] = F[k];
         }
 #pragma unroll
         for (int n = 0; n < NR; ++n)
@@ -917,15 +839,16 @@ hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom
     if constexpr (MODE == TNEP_MLP_FP32_VALU) {
         const int bs = (block == 64 || block == 128) ? block : 256;
         const unsigned grid = (unsigned)((nl.n_pad + bs - 1) / bs);
-        if (KIND != 3 && rs.mode == 2)
-            k_eval<NR, NA, KR, KA, MB, KIND, MODE, KIND != 3><<<grid, bs, 0, s>>>(m, nl, per_atom, pes, rs.v, rs.mode, pes.rec, pes.pair);
+        if (rs.mode == 2 && KR == kRadialTerms)
+            k_eval<NR, NA, KR, KA, MB, KIND, MODE, KR == kRadialTerms><<<grid, bs, 0, s>>>(m, nl, per_atom, pes, rs.v,
+                                                                                        pes.rec, pes.pair);
         else
-            k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom, pes, rs.v, rs.mode, pes.rec, pes.pair);
+            k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom, pes, nullptr, pes.rec, pes.pair);
     } else {
         // two wavefronts per work-group keep the LDS tiles at <= 2 x 27 KB
         const unsigned grid = (unsigned)((nl.n_pad + 127) / 128);
         const size_t lds = sizeof(float) * 2 * (size_t)mlp_lds_floats(D, m.n_hidden);
-        k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom, pes, nullptr, 0, pes.rec, pes.pair);
+        k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom, pes, nullptr, pes.rec, pes.pair);
     }
     return hipGetLastError();
 }

@@ -30,6 +30,7 @@
 // Entries are grouped four to a lane (64 contiguous bytes), so every store and
 // load of a wavefront covers one contiguous 4 KB block.
 #include "internal.h"
+#include "radial_basis.h"
 
 namespace tnep {
 
@@ -401,12 +402,44 @@ __device__ __forceinline__ void coop_flush(PairSink& ps, const float4* lds, int4
     __builtin_amdgcn_wave_barrier();
 }
 
+// Radial descriptor sums of one (atom, neighbour species) pass: over the
+// accepted pairs, sum f_c T_k(x) and sum f_c (Sec. 2.1, radial functions
+// f_k = (T_k(x) + 1) / 2 f_c), from the FP32 pair vector that the entry
+// stores.  They depend on the lists, r_c^R and the basis size only, so every
+// model evaluated on the lists loads them instead of forming them again.
+struct RadialSums {
+    float FT[kRadialTerms];
+    float Fs;
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int k = 0; k < kRadialTerms; ++k) FT[k] = 0.f;
+        Fs = 0.f;
+    }
+    __device__ __forceinline__ void add(float x, float y, float z, float rcR_inv) {
+        const float r = pair_sqrt(x * x + y * y + z * z);
+        const float fc = cutoff_fc(1.f - r * rcR_inv);
+        const float tt = r * rcR_inv - 1.f;
+        float Tk[kRadialTerms];
+        cheb_T<kRadialTerms>(2.f * tt * tt - 1.f, Tk);
+        Fs += fc;
+#pragma unroll
+        for (int k = 0; k < kRadialTerms; ++k) FT[k] += fc * Tk[k];
+    }
+    // sum_j f_k(r_ij) for species t of slot p
+    __device__ __forceinline__ void store(float* __restrict__ v, int t, int64_t n_pad, int64_t p) const {
+        if (!v) return;
+#pragma unroll
+        for (int k = 0; k < kRadialTerms; ++k) v[(int64_t)(t * kRadialTerms + k) * n_pad + p] = 0.5f * (FT[k] + Fs);
+    }
+};
+
 // One candidate of k_neighbors: pair vector d = r_j - r_i (FP64), in = a real
 // candidate other than the atom itself within the search radius.
 template <bool REF>
-__device__ __forceinline__ void take_candidate(PairSink& ps, const float4* lds, bool in, double dx, double dy, double dz,
-                                               double r2, int j, double rc2r, double rc2a, bool& overlap, int& n_cand,
-                                               int32_t* cand, int cand_cap, const int32_t* perm, int atom_begin) {
+__device__ __forceinline__ void take_candidate(PairSink& ps, RadialSums& rs, float rcR_inv, const float4* lds, bool in,
+                                               double dx, double dy, double dz, double r2, int j, double rc2r,
+                                               double rc2a, bool& overlap, int& n_cand, int32_t* cand, int cand_cap,
+                                               const int32_t* perm, int atom_begin) {
     if (in) {
         if constexpr (REF) {
             if (n_cand < cand_cap) cand[n_cand] = perm[j] - atom_begin;
@@ -414,7 +447,9 @@ __device__ __forceinline__ void take_candidate(PairSink& ps, const float4* lds, 
         }
         if (!REF || r2 < rc2r) {
             overlap |= r2 < 1e-8;
-            ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)), r2 < rc2a, lds);
+            const float4 e = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
+            ps.push_deferred(e, r2 < rc2a, lds);
+            rs.add(e.x, e.y, e.z, rcR_inv);
         }
     }
 }
@@ -434,7 +469,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                                                       const double4* __restrict__ bucket_pos,
                                                       const int4* __restrict__ cell_rec, float rc_radial,
                                                       float rc_angular, NeighborLists nl, CandLists cl,
-                                                      int32_t* __restrict__ flags) {
+                                                      int32_t* __restrict__ flags, float* __restrict__ rad_v) {
     // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
     extern __shared__ float4 nb_stage[];
     float4* stage = nb_stage + threadIdx.x;
@@ -446,9 +481,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const int tile = (int)(p >> 6), lane = (int)(p & 63);
     if (a < 0) {
         if (REF) return;
+        RadialSums none;
+        none.clear();
         for (int t = 0; t < T; ++t) {
             nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = 0;
             nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = 0;
+            none.store(rad_v, t, nl.n_pad, p);
         }
         return;
     }
@@ -458,6 +496,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     if (fi.role != (REF ? kRoleReference : kRolePlain) || fi.tric) return;
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
+    const float rcR_inv = 1.f / rc_radial;
     // references collect candidates out to r_c + skin
     const float rs = REF ? cl.rc_search : rc_radial;
     const double rcs2 = (double)rs * rs;
@@ -500,6 +539,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                     lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
                     lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
                     nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0, -1, nullptr};
+        RadialSums rsum;
+        rsum.clear();
         int n_cand = 0;
         int32_t* cand = REF ? cl.idx + ((fi.cl_base + (a - fi.atom_begin)) * T + t) * cl.cap : nullptr;
         // cell grids: every candidate within rs is at most kCellReachXY cells
@@ -558,8 +599,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                         const double dy = fma((double)(cr.y - own.y), qu, offy);
                         const double dz = fma((double)(cr.z - own.z), qu, oz * hz);
                         const double r2 = dx * dx + dy * dy + dz * dz;
-                        take_candidate<REF>(ps, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2), dx, dy, dz, r2,
-                                            j, rc2r, rc2a, overlap, n_cand, cand, cl.cap, nl.perm,
+                        take_candidate<REF>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2),
+                                            dx, dy, dz, r2, j, rc2r, rc2a, overlap, n_cand, cand, cl.cap, nl.perm,
                                             (int)fi.atom_begin);
                         coop_flush(ps, nb_stage, list);
                     }
@@ -578,8 +619,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                         const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
                         const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
                         const double r2 = dx * dx + dy * dy + dz * dz;
-                        take_candidate<REF>(ps, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2), dx, dy, dz, r2,
-                                            j, rc2r, rc2a, overlap, n_cand, cand, cl.cap, nl.perm,
+                        take_candidate<REF>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2),
+                                            dx, dy, dz, r2, j, rc2r, rc2a, overlap, n_cand, cand, cl.cap, nl.perm,
                                             (int)fi.atom_begin);
                         coop_flush(ps, nb_stage, list);
                     }
@@ -590,6 +631,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
             cl.count[(fi.cl_base + (a - fi.atom_begin)) * T + t] = n_cand;
             if (n_cand > cl.cap) atomicMax(&flags[kFlagCapCand], n_cand);
         }
+        rsum.store(rad_v, t, nl.n_pad, p);
         ps.flush();
         nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(ps.na, ps.capA);
         nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(ps.nr, ps.capR);
@@ -611,7 +653,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
                                                              const int32_t* __restrict__ species,
                                                              const int32_t* __restrict__ slot_of, float rc_radial,
                                                              float rc_angular, NeighborLists nl, CandLists cl,
-                                                             int32_t* __restrict__ flags) {
+                                                             int32_t* __restrict__ flags, float* __restrict__ rad_v) {
     // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
     extern __shared__ float4 nb_stage[];
     float4* stage = nb_stage + threadIdx.x;
@@ -626,6 +668,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
     const int tile = (int)(p >> 6), lane = (int)(p & 63);
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
+    const float rcR_inv = 1.f / rc_radial;
     float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
     const int64_t il = a - fi.atom_begin;
     const int64_t aref = fi.ref_begin + il;
@@ -640,6 +683,8 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
                     lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
                     lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
                     nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0, -1, nullptr};
+        RadialSums rsum;
+        rsum.clear();
         const int64_t list = (fi.cl_base + il) * T + t;
         const int n = min(cl.count[list], cl.cap);
         const int4* idx4 = reinterpret_cast<const int4*>(cl.idx + list * cl.cap);
@@ -663,12 +708,14 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
                 if ((k0 + u < n) & (r2 < rc2r)) {
                     overlap |= r2 < 1e-8;
                     const int js = slot_of[fi.atom_begin + jl[u]];
-                    ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(js)), r2 < rc2a,
-                                     nb_stage);
+                    const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(js));
+                    ps.push_deferred(ent, r2 < rc2a, nb_stage);
+                    rsum.add(ent.x, ent.y, ent.z, rcR_inv);
                 }
                 coop_flush(ps, nb_stage, wlist);
             }
         }
+        rsum.store(rad_v, t, nl.n_pad, p);
         ps.flush();
         nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(ps.na, ps.capA);
         nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(ps.nr, ps.capR);
@@ -702,7 +749,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                                                           const double4* __restrict__ bucket_pos,
                                                           const int4* __restrict__ cell_rec, float rc_radial,
                                                           float rc_angular, NeighborLists nl,
-                                                          int32_t* __restrict__ flags) {
+                                                          int32_t* __restrict__ flags, float* __restrict__ rad_v) {
     // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
     extern __shared__ float4 nb_stage[];
     float4* stage = nb_stage + threadIdx.x;
@@ -751,12 +798,15 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
         }
     }
     const float hb2_inv = mode == 1 ? 1.f / hb[2] : 0.f;
+    const float rcR_inv = 1.f / rc_radial;
     bool overlap = false;
     for (int t = 0; t < T; ++t) {
         PairSink ps{stage, (int)blockDim.x,
                     lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
                     lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256,
                     nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0, -1, nullptr};
+        RadialSums rsum;
+        rsum.clear();
         if (mode == 1) {
             for (int col = 0; col < 25; ++col) {
                 const int o0 = col / 5 - 2, o1 = col % 5 - 2;
@@ -799,8 +849,9 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                         // one branch per candidate: a real candidate, not the atom itself, within r_c
                         if ((q + u < n) & (j != (int)p) & (r2 < rc2r)) {
                             overlap |= r2 < 1e-8;
-                            ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)),
-                                             r2 < rc2a, nb_stage);
+                            const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
+                            ps.push_deferred(ent, r2 < rc2a, nb_stage);
+                            rsum.add(ent.x, ent.y, ent.z, rcR_inv);
                         }
                         coop_flush(ps, nb_stage, list);
                     }
@@ -826,13 +877,15 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     if ((k0 + u < e) & (j != (int)p) & (r2 < rc2r)) {
                         overlap |= r2 < 1e-8;
-                        ps.push_deferred(make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j)), r2 < rc2a,
-                                         nb_stage);
+                        const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
+                        ps.push_deferred(ent, r2 < rc2a, nb_stage);
+                        rsum.add(ent.x, ent.y, ent.z, rcR_inv);
                     }
                     coop_flush(ps, nb_stage, list);
                 }
             }
         }
+        rsum.store(rad_v, t, nl.n_pad, p);
         ps.flush();
         nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(ps.na, ps.capA);
         nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(ps.nr, ps.capR);
@@ -886,7 +939,7 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
-                            bool triclinic, int32_t* d_flags, int neigh_block, hipStream_t s) {
+                            bool triclinic, int32_t* d_flags, int neigh_block, float* rad_sums, hipStream_t s) {
     if (cap_atoms == 0 || cap_frames == 0) return hipSuccess;
     const int nb = (neigh_block == 64 || neigh_block == 128) ? neigh_block : kBlock;
     const int T = nl.T;
@@ -909,18 +962,18 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
     const size_t list_bytes = sizeof(float4) * 9 * nb;  // staging + per-wave flush lists
     k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                               w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
-                                                              rc_radial, rc_angular, nl, cl, d_flags);
+                                                              rc_radial, rc_angular, nl, cl, d_flags, rad_sums);
     if (references)
         k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                  w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
-                                                                 rc_radial, rc_angular, nl, cl, d_flags);
+                                                                 rc_radial, rc_angular, nl, cl, d_flags, rad_sums);
     if (triclinic)
         k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, w.key_of, w.perm_start,
                                                                w.bucket_pos, w.cell_rec, rc_radial, rc_angular, nl,
-                                                               d_flags);
+                                                               d_flags, rad_sums);
     if (followers)
         k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
-                                                                  rc_radial, rc_angular, nl, cl, d_flags);
+                                                                  rc_radial, rc_angular, nl, cl, d_flags, rad_sums);
     return hipGetLastError();
 }
 
