@@ -733,6 +733,9 @@ __global__ void __launch_bounds__(256) k_com_shift(const int64_t* __restrict__ o
     if (lane < 3 && part[3][0] > 0.0) mu[3 * (int64_t)f + lane] += charges[f] * unit * part[lane][0] / part[3][0];
 }
 
+// angular pairs whose lookups k_pes_forces overlaps
+constexpr int kLookups = 8;
+
 // Forces of a potential-energy model (Sec. 2.1): with r_ij = r_j - r_i,
 //   F_k = -dU/dr_k = sum_j dU_k/dr_kj - sum_j dU_j/dr_jk.
 // The first sum is in the atom's record (evaluation kernel).  For the second,
@@ -798,28 +801,57 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
         const int n_rad = nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
         const float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
         const float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
-        for (int s = 0; s < n_ang; ++s) {
-            const float4 e = ga[(s >> 2) * 256 + (s & 3)];
-            const int j = __float_as_int(e.w);
-            // j's angular segment of species t_k, searched for this lane's slot
-            const int64_t ja = ((int64_t)(j >> 6) * (nl.slots >> 2) * 64 + (j & 63)) * 4 + seg_a_k;
-            const int n_ja = nl.counts[(int64_t)(2 * tk) * nl.n_pad + j];
-            int row = -1;
-            for (int r0 = 0; r0 < n_ja && row < 0; r0 += 4) {
-                const float4* g = nl.entries + ja + (int64_t)(r0 >> 2) * 256;
+        // kLookups pairs at a time: the loads of their lookups (the neighbour's count
+        // and the slot fields of the first four rows of its segment, in bounds since
+        // segment capacities are multiples of four) are issued before any is used
+        const int* __restrict__ slots_of = reinterpret_cast<const int*>(nl.entries);
+        for (int s = 0; s < n_ang; s += kLookups) {
+            float4 e[kLookups];
+            int g[kLookups][4];
+            int64_t ja[kLookups];
+            int nj[kLookups], row[kLookups];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (r0 + u < n_ja && __float_as_int(g[u].w) == (int)p) row = r0 + u;
+            for (int w = 0; w < kLookups; ++w) {
+                const int sw = min(s + w, n_ang - 1);  // past the end: repeat the last pair, unused
+                e[w] = ga[(sw >> 2) * 256 + (sw & 3)];
+                const int j = __float_as_int(e[w].w);
+                // j's angular segment of species t_k, searched for this lane's slot
+                ja[w] = ((int64_t)(j >> 6) * (nl.slots >> 2) * 64 + (j & 63)) * 4 + seg_a_k;
+                nj[w] = s + w < n_ang ? nl.counts[(int64_t)(2 * tk) * nl.n_pad + j] : 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) g[w][u] = slots_of[4 * (ja[w] + u) + 3];
             }
-            if (row >= 0) {
-                const float4 f = pes.pair[ja + (int64_t)(row >> 2) * 256 + (row & 3)];
-                Fx -= f.x;
-                Fy -= f.y;
-                Fz -= f.z;
-            } else {
-                radial_term(e);
+#pragma unroll
+            for (int w = 0; w < kLookups; ++w) {
+                row[w] = -1;
+#pragma unroll
+                for (int u = 3; u >= 0; --u)
+                    if (u < nj[w] && g[w][u] == (int)p) row[w] = u;
+                for (int r0 = 4; r0 < nj[w] && row[w] < 0; r0 += 4) {
+                    const float4* gg = nl.entries + ja[w] + (int64_t)(r0 >> 2) * 256;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (r0 + u < nj[w] && __float_as_int(gg[u].w) == (int)p) row[w] = r0 + u;
+                }
+            }
+            float4 f[kLookups];
+#pragma unroll
+            for (int w = 0; w < kLookups; ++w)
+                f[w] = row[w] >= 0 ? pes.pair[ja[w] + (int64_t)(row[w] >> 2) * 256 + (row[w] & 3)]
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int w = 0; w < kLookups; ++w) {
+                if (s + w >= n_ang) break;
+                if (row[w] >= 0) {
+                    Fx -= f[w].x;
+                    Fy -= f[w].y;
+                    Fz -= f[w].z;
+                } else {
+                    radial_term(e[w]);
+                }
             }
         }
+#pragma unroll 2
         for (int s = 0; s < n_rad; ++s) radial_term(gr[(s >> 2) * 256 + (s & 3)]);
     }
     if (a < 0) return;
