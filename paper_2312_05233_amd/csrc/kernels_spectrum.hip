@@ -117,6 +117,49 @@ __global__ void k_fft_pass(const cplx* __restrict__ in, cplx* __restrict__ out, 
     dst[j * 2 * m + k + m] = {a.re - w.re, a.im - w.im};
 }
 
+// R = 2^r consecutive radix-2 passes (half spans m, 2m, ..., (R/2) m) in one
+// launch, each butterfly with the twiddle and arithmetic of k_fft_pass, so the
+// result is that of the r passes.  Thread tid < P/R (k = tid % m, j = tid / m)
+// reads in[tid + a P/R], a < R.  Before pass s (half span M = 2^s m) it holds
+// the elements j 2^s m + k + c m + a 2^s P/R (c < 2^s, a < R/2^s) at x[c + 2^s a];
+// the pass pairs a with a + R/2^(s+1) (index t and t + P/2) under the twiddle
+// of K = k + c m, and the thread ends with out[j R m + k + c m], c < R.
+template <int R>
+__global__ void k_fft_radix(const cplx* __restrict__ in, cplx* __restrict__ out, int64_t P, int64_t m, double sign) {
+    const int64_t tid = (int64_t)blockIdx.x * kB + threadIdx.x;
+    const int64_t q = P / R;
+    if (tid >= q) return;
+    const int64_t b = blockIdx.y;
+    const cplx* src = in + b * P;
+    cplx* dst = out + b * P;
+    const int64_t k = tid % m;
+    const int64_t j = tid / m;
+    cplx x[R], y[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) x[a] = src[tid + a * q];
+#pragma unroll
+    for (int S = 1; S < R; S <<= 1) {  // S = 2^s
+        const int64_t M = S * m;
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            double sn, cs;
+            sincospi(sign * (double)(k + c * m) / (double)M, &sn, &cs);
+#pragma unroll
+            for (int a = 0; a < R / (2 * S); ++a) {
+                const cplx lo = x[c + S * a], hi = x[c + S * (a + R / (2 * S))];
+                const cplx w = cmul({cs, sn}, hi);
+                y[c + 2 * S * a] = {lo.re + w.re, lo.im + w.im};
+                y[c + S + 2 * S * a] = {lo.re - w.re, lo.im - w.im};
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) x[i] = y[i];
+    }
+    cplx* o = dst + j * R * m + k;
+#pragma unroll
+    for (int c = 0; c < R; ++c) o[c * m] = x[c];
+}
+
 // Per series: combine the signal spectra into the channel's cross power.
 __global__ void k_power(const cplx* __restrict__ X, int64_t P, int kind, int nsig, cplx* __restrict__ Z) {
     const int64_t f = (int64_t)blockIdx.x * kB + threadIdx.x;
@@ -399,6 +442,28 @@ __global__ void k_zero(double* __restrict__ a, int64_t n) {
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 
+// Unnormalised FFTs (sign -1 forward, +1 inverse) of `batch` sequences of
+// length P (a power of two) in a, ping-ponging with b: radix-8 launches while
+// three passes remain, then one radix-4 or radix-2 launch.  On return a holds
+// the result.
+void fft_batch(cplx*& a, cplx*& b, int64_t P, unsigned batch, double sign, hipStream_t s) {
+    for (int64_t m = 1; m < P;) {
+        if (8 * m <= P) {
+            k_fft_radix<8><<<dim3(nblk(P / 8), batch), kB, 0, s>>>(a, b, P, m, sign);
+            m *= 8;
+        } else if (4 * m <= P) {
+            k_fft_radix<4><<<dim3(nblk(P / 4), batch), kB, 0, s>>>(a, b, P, m, sign);
+            m *= 4;
+        } else {
+            k_fft_pass<<<dim3(nblk(P / 2), batch), kB, 0, s>>>(a, b, P, m, sign);
+            m *= 2;
+        }
+        cplx* t = a;
+        a = b;
+        b = t;
+    }
+}
+
 }  // namespace
 
 size_t spectrum_workspace_bytes(const SpectrumPlan& p) {
@@ -438,22 +503,12 @@ hipError_t launch_spectrum(const SpectrumPlan& p, const double* d_series, double
     const unsigned batch = (unsigned)(p.n_series * nsig);
     cplx* a = X;
     cplx* b = Y;
-    for (int64_t m = 1; m < P; m <<= 1) {
-        k_fft_pass<<<dim3(nblk(P / 2), batch), kB, 0, s>>>(a, b, P, m, -1.0);
-        cplx* t = a;
-        a = b;
-        b = t;
-    }
+    fft_batch(a, b, P, batch, -1.0, s);
     // channel power into b (first n_series sequences), inverse FFT
     k_power<<<dim3(nblk(P), p.n_series), kB, 0, s>>>(a, P, p.kind, nsig, b);
     cplx* c = b;
     cplx* d = a;
-    for (int64_t m = 1; m < P; m <<= 1) {
-        k_fft_pass<<<dim3(nblk(P / 2), p.n_series), kB, 0, s>>>(c, d, P, m, 1.0);
-        cplx* t = c;
-        c = d;
-        d = t;
-    }
+    fft_batch(c, d, P, p.n_series, 1.0, s);
     k_acf<<<nblk(p.max_lag), kB, 0, s>>>(c, P, p.n_series, p.n_steps, p.max_lag, acf);
     k_cos_table<<<nblk(2 * p.max_lag), kB, 0, s>>>(p.max_lag, tab);
     const int omega2 = (p.kind == 0 && !(p.flags & 2)) ? 1 : 0;
@@ -504,21 +559,11 @@ hipError_t launch_raman_map(const SpectrumPlan& p, const double* d_series, const
                                                         0, 0, 0, 0, X);
     cplx* a = X;
     cplx* b = Y;
-    for (int64_t m = 1; m < P; m <<= 1) {
-        k_fft_pass<<<dim3(nblk(P / 2), (unsigned)(p.n_series * 9)), kB, 0, s>>>(a, b, P, m, -1.0);
-        cplx* t = a;
-        a = b;
-        b = t;
-    }
+    fft_batch(a, b, P, (unsigned)(p.n_series * 9), -1.0, s);
     k_power_sym<<<dim3(nblk(P), 45), kB, 0, s>>>(a, P, p.n_series, Z1);
     cplx* c = Z1;
     cplx* d = Z2;
-    for (int64_t m = 1; m < P; m <<= 1) {
-        k_fft_pass<<<dim3(nblk(P / 2), 45), kB, 0, s>>>(c, d, P, m, 1.0);
-        cplx* t = c;
-        c = d;
-        d = t;
-    }
+    fft_batch(c, d, P, 45, 1.0, s);
     k_acf_channels<<<dim3(nblk(M), 45), kB, 0, s>>>(c, P, p.n_series, p.n_steps, M, acf);
     k_cos_table<<<nblk(2 * M), kB, 0, s>>>(M, tab);
     k_transform<<<dim3(nblk(M + 1), 45), kB, 0, s>>>(acf, M, tab, M, p.window, 0, p.laser_cm1, p.dt_fs, d_freq, L,
@@ -555,22 +600,12 @@ hipError_t launch_stream_push(const StreamState& st, const double* d_chunk, int6
                                           st.M, st.totals);
     cplx* a = UV;
     cplx* b = UV2;
-    for (int64_t m = 1; m < P; m <<= 1) {
-        k_fft_pass<<<dim3(nblk(P / 2), (unsigned)(2 * st.nsig)), kB, 0, s>>>(a, b, P, m, -1.0);
-        cplx* t = a;
-        a = b;
-        b = t;
-    }
+    fft_batch(a, b, P, (unsigned)(2 * st.nsig), -1.0, s);
     k_stream_power<<<dim3(nblk(P), (unsigned)st.nch), kB, 0, s>>>(a, a + (size_t)P * st.nsig, P, st.chx, st.chy,
                                                                   st.chsym, Z1);
     cplx* c = Z1;
     cplx* d = Z2;
-    for (int64_t m = 1; m < P; m <<= 1) {
-        k_fft_pass<<<dim3(nblk(P / 2), (unsigned)st.nch), kB, 0, s>>>(c, d, P, m, 1.0);
-        cplx* t = c;
-        c = d;
-        d = t;
-    }
+    fft_batch(c, d, P, (unsigned)st.nch, 1.0, s);
     k_stream_accum<<<dim3(nblk(st.M), (unsigned)st.nch), kB, 0, s>>>(c, P, st.M, st.S);
     return hipGetLastError();
 }
