@@ -27,6 +27,8 @@ namespace tnep {
 namespace {
 
 constexpr int kB = 256;
+constexpr int kFftBlock = 64;      // FFT launches: small batches still spread over every compute unit
+constexpr int kStateBlock = 1024;  // k_stream_state: one work-group per signal
 
 struct cplx {
     double re, im;
@@ -100,7 +102,7 @@ __global__ void k_signals(const double* __restrict__ series, const double* __res
 // Pass with half-size span m = 2^p: out[j*2m + k] and out[j*2m + k + m] from
 // in[j*m + k] and in[j*m + k + P/2], twiddle exp(-+ 2 pi i k / (2m)).
 __global__ void k_fft_pass(const cplx* __restrict__ in, cplx* __restrict__ out, int64_t P, int64_t m, double sign) {
-    const int64_t tid = (int64_t)blockIdx.x * kB + threadIdx.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t half = P >> 1;
     if (tid >= half) return;
     const int64_t b = blockIdx.y;
@@ -126,7 +128,7 @@ __global__ void k_fft_pass(const cplx* __restrict__ in, cplx* __restrict__ out, 
 // of K = k + c m, and the thread ends with out[j R m + k + c m], c < R.
 template <int R>
 __global__ void k_fft_radix(const cplx* __restrict__ in, cplx* __restrict__ out, int64_t P, int64_t m, double sign) {
-    const int64_t tid = (int64_t)blockIdx.x * kB + threadIdx.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t q = P / R;
     if (tid >= q) return;
     const int64_t b = blockIdx.y;
@@ -341,24 +343,24 @@ __global__ void k_stream_build(const double* __restrict__ chunk, int64_t n, int 
 // Run state from U before its transform: new carry (last min(M-1, c+n)
 // samples), the first M samples of the run (head) and per-signal totals.
 // One work-group per signal.
-__global__ void k_stream_state(const cplx* __restrict__ U, int64_t P_len, int64_t c, int64_t n,
+__global__ void __launch_bounds__(kStateBlock) k_stream_state(const cplx* __restrict__ U, int64_t P_len, int64_t c, int64_t n,
                                int64_t carry_cap, double* __restrict__ carry_new, int64_t run_len,
                                double* __restrict__ head, int64_t M, double* __restrict__ totals) {
     const int g = blockIdx.x;
     const cplx* u = U + (int64_t)g * P_len;
     const int64_t L = c + n;
     const int64_t keep = L < carry_cap ? L : carry_cap;
-    for (int64_t i = threadIdx.x; i < keep; i += kB) carry_new[(int64_t)g * carry_cap + i] = u[L - keep + i].re;
-    for (int64_t i = threadIdx.x; i < n; i += kB) {
+    for (int64_t i = threadIdx.x; i < keep; i += kStateBlock) carry_new[(int64_t)g * carry_cap + i] = u[L - keep + i].re;
+    for (int64_t i = threadIdx.x; i < n; i += kStateBlock) {
         const int64_t r = run_len + i;  // position in the run
         if (r < M) head[(int64_t)g * M + r] = u[c + i].re;
     }
-    __shared__ double part[kB];
+    __shared__ double part[kStateBlock];
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kB) acc += u[c + i].re;
+    for (int64_t i = threadIdx.x; i < n; i += kStateBlock) acc += u[c + i].re;
     part[threadIdx.x] = acc;
     __syncthreads();
-    for (int off = kB / 2; off > 0; off >>= 1) {
+    for (int off = kStateBlock / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
         __syncthreads();
     }
@@ -441,6 +443,7 @@ __global__ void k_zero(double* __restrict__ a, int64_t n) {
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+inline unsigned nfft(int64_t n) { return (unsigned)((n + kFftBlock - 1) / kFftBlock); }
 
 // Unnormalised FFTs (sign -1 forward, +1 inverse) of `batch` sequences of
 // length P (a power of two) in a, ping-ponging with b: radix-8 launches while
@@ -449,13 +452,13 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 void fft_batch(cplx*& a, cplx*& b, int64_t P, unsigned batch, double sign, hipStream_t s) {
     for (int64_t m = 1; m < P;) {
         if (8 * m <= P) {
-            k_fft_radix<8><<<dim3(nblk(P / 8), batch), kB, 0, s>>>(a, b, P, m, sign);
+            k_fft_radix<8><<<dim3(nfft(P / 8), batch), kFftBlock, 0, s>>>(a, b, P, m, sign);
             m *= 8;
         } else if (4 * m <= P) {
-            k_fft_radix<4><<<dim3(nblk(P / 4), batch), kB, 0, s>>>(a, b, P, m, sign);
+            k_fft_radix<4><<<dim3(nfft(P / 4), batch), kFftBlock, 0, s>>>(a, b, P, m, sign);
             m *= 4;
         } else {
-            k_fft_pass<<<dim3(nblk(P / 2), batch), kB, 0, s>>>(a, b, P, m, sign);
+            k_fft_pass<<<dim3(nfft(P / 2), batch), kFftBlock, 0, s>>>(a, b, P, m, sign);
             m *= 2;
         }
         cplx* t = a;
@@ -596,7 +599,7 @@ hipError_t launch_stream_push(const StreamState& st, const double* d_chunk, int6
     k_stream_build<<<nblk(P), kB, 0, s>>>(d_chunk, n, comps, st.kind, st.nsig, st.n_hat[0], st.n_hat[1],
                                           st.n_hat[2], st.e_hat[0], st.e_hat[1], st.e_hat[2], st.carry,
                                           st.carry_cap, st.carry_len, P, U, V);
-    k_stream_state<<<st.nsig, kB, 0, s>>>(U, P, st.carry_len, n, st.carry_cap, st.carry_next, st.run_len, st.head,
+    k_stream_state<<<st.nsig, kStateBlock, 0, s>>>(U, P, st.carry_len, n, st.carry_cap, st.carry_next, st.run_len, st.head,
                                           st.M, st.totals);
     cplx* a = UV;
     cplx* b = UV2;
