@@ -446,12 +446,15 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 inline unsigned nfft(int64_t n) { return (unsigned)((n + kFftBlock - 1) / kFftBlock); }
 
 // Unnormalised FFTs (sign -1 forward, +1 inverse) of `batch` sequences of
-// length P (a power of two) in a, ping-ponging with b: radix-8 launches while
-// three passes remain, then one radix-4 or radix-2 launch.  On return a holds
-// the result.
+// length P (a power of two) in a, ping-ponging with b: radix-16 launches while
+// four passes remain, then one radix-8, radix-4 or radix-2 launch.  On return a
+// holds the result.
 void fft_batch(cplx*& a, cplx*& b, int64_t P, unsigned batch, double sign, hipStream_t s) {
     for (int64_t m = 1; m < P;) {
-        if (8 * m <= P) {
+        if (16 * m <= P) {
+            k_fft_radix<16><<<dim3(nfft(P / 16), batch), kFftBlock, 0, s>>>(a, b, P, m, sign);
+            m *= 16;
+        } else if (8 * m <= P) {
             k_fft_radix<8><<<dim3(nfft(P / 8), batch), kFftBlock, 0, s>>>(a, b, P, m, sign);
             m *= 8;
         } else if (4 * m <= P) {
