@@ -22,55 +22,6 @@ namespace tnep {
 
 namespace {
 
-// The real spherical harmonics of sh_foreach without their normalisation
-// constants: Y_lm = kShNorm[idx] * P_lm(u) with P_lm the integer-coefficient
-// polynomial below (and its gradient).  The per-pair loops use P_lm and fold
-// the constants into the per-atom sums A_nlm and dU/dA_nlm once per atom.
-__device__ constexpr float kShNorm[24] = {
-    0.48860251190291992f, 0.48860251190291992f, 0.48860251190291992f,                         // l = 1
-    1.0925484305920792f,  1.0925484305920792f,  0.31539156525252005f, 1.0925484305920792f,   // l = 2
-    0.54627421529603959f,
-    0.59004358992664352f, 2.8906114426405538f,  0.45704579946446572f, 0.37317633259011540f,  // l = 3
-    0.45704579946446572f, 1.4453057213202769f,  0.59004358992664352f,
-    2.5033429417967046f,  1.7701307697799304f,  0.94617469575756008f, 0.66904654355728917f,  // l = 4
-    0.10578554691520431f, 0.66904654355728917f, 0.47308734787878004f, 1.7701307697799304f,
-    0.62583573544917614f};
-
-template <typename F>
-__device__ __forceinline__ void sh_foreach_raw(float x, float y, float z, F&& f) {
-    const float x2 = x * x, y2 = y * y, z2 = z * z;
-    const float xy = x * y, yz = y * z, xz = x * z;
-    f(0, 1, y, 0.f, 1.f, 0.f);
-    f(1, 1, z, 0.f, 0.f, 1.f);
-    f(2, 1, x, 1.f, 0.f, 0.f);
-    f(3, 2, xy, y, x, 0.f);
-    f(4, 2, yz, 0.f, z, y);
-    f(5, 2, 2.f * z2 - x2 - y2, -2.f * x, -2.f * y, 4.f * z);
-    f(6, 2, xz, z, 0.f, x);
-    f(7, 2, x2 - y2, 2.f * x, -2.f * y, 0.f);
-    f(8, 3, 3.f * x2 * y - y2 * y, 6.f * xy, 3.f * (x2 - y2), 0.f);
-    f(9, 3, xy * z, yz, xz, xy);
-    f(10, 3, y * (4.f * z2 - x2 - y2), -2.f * xy, 4.f * z2 - x2 - 3.f * y2, 8.f * yz);
-    f(11, 3, z * (2.f * z2 - 3.f * x2 - 3.f * y2), -6.f * xz, -6.f * yz, 3.f * (2.f * z2 - x2 - y2));
-    f(12, 3, x * (4.f * z2 - x2 - y2), 4.f * z2 - 3.f * x2 - y2, -2.f * xy, 8.f * xz);
-    f(13, 3, z * (x2 - y2), 2.f * xz, -2.f * yz, x2 - y2);
-    f(14, 3, x2 * x - 3.f * x * y2, 3.f * (x2 - y2), -6.f * xy, 0.f);
-    const float xyz = xy * z;
-    f(15, 4, xy * (x2 - y2), y * (3.f * x2 - y2), x * (x2 - 3.f * y2), 0.f);
-    f(16, 4, yz * (3.f * x2 - y2), 6.f * xyz, 3.f * z * (x2 - y2), y * (3.f * x2 - y2));
-    f(17, 4, xy * (6.f * z2 - x2 - y2), y * (6.f * z2 - 3.f * x2 - y2), x * (6.f * z2 - x2 - 3.f * y2), 12.f * xyz);
-    f(18, 4, yz * (4.f * z2 - 3.f * x2 - 3.f * y2), -6.f * xyz, z * (4.f * z2 - 3.f * x2 - 9.f * y2),
-      3.f * y * (4.f * z2 - x2 - y2));
-    f(19, 4, 8.f * z2 * z2 - 24.f * (x2 + y2) * z2 + 3.f * (x2 + y2) * (x2 + y2), 12.f * x * (x2 + y2 - 4.f * z2),
-      12.f * y * (x2 + y2 - 4.f * z2), 16.f * z * (2.f * z2 - 3.f * (x2 + y2)));
-    f(20, 4, xz * (4.f * z2 - 3.f * x2 - 3.f * y2), z * (4.f * z2 - 9.f * x2 - 3.f * y2), -6.f * xyz,
-      3.f * x * (4.f * z2 - x2 - y2));
-    f(21, 4, 6.f * (x2 - y2) * z2 - x2 * x2 + y2 * y2, 4.f * x * (3.f * z2 - x2), 4.f * y * (y2 - 3.f * z2),
-      12.f * z * (x2 - y2));
-    f(22, 4, xz * (x2 - 3.f * y2), 3.f * z * (x2 - y2), -6.f * xyz, x * (x2 - 3.f * y2));
-    f(23, 4, x2 * x2 - 6.f * x2 * y2 + y2 * y2, 4.f * x * (x2 - 3.f * y2), 4.f * y * (y2 - 3.f * x2), 0.f);
-}
-
 // Tile species: wave-uniform (tiles are species-pure).
 __device__ __forceinline__ int tile_species(const int32_t* tile_base, int T, int tile) {
     int ti = 0;

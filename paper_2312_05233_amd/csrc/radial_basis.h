@@ -1,6 +1,8 @@
 // Radial basis of the descriptor (Sec. 2.1, NEP radial functions) and pair
 // distances, shared by the neighbour search (which accumulates the radial
-// descriptor sums) and the evaluation kernels.
+// descriptor sums) and the evaluation kernels.  The basis functions are also
+// compiled for the host by the CPU self-check; the pair distances use the
+// hardware square roots and are device-only.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,7 +13,7 @@ namespace tnep {
 // which keeps relative accuracy as r -> r_c; f_c'(r) = -(pi / r_c) sin(w) cos(w).
 // sin and cos of w in [0, pi/2] from their Taylor series to w^13 / w^14
 // (truncation below 1e-9).  v = 1 - r / r_c.
-__device__ __forceinline__ float sin_half_pi(float w) {
+__host__ __device__ __forceinline__ float sin_half_pi(float w) {
     const float w2 = w * w;
     float p = 1.f / 6227020800.f;
     p = p * w2 - 1.f / 39916800.f;
@@ -22,7 +24,7 @@ __device__ __forceinline__ float sin_half_pi(float w) {
     p = p * w2 + 1.f;
     return w * p;
 }
-__device__ __forceinline__ float cos_half_pi(float w) {
+__host__ __device__ __forceinline__ float cos_half_pi(float w) {
     const float w2 = w * w;
     float p = -1.f / 87178291200.f;
     p = p * w2 + 1.f / 479001600.f;
@@ -34,11 +36,11 @@ __device__ __forceinline__ float cos_half_pi(float w) {
     p = p * w2 + 1.f;
     return p;
 }
-__device__ __forceinline__ float cutoff_fc(float v) {
+__host__ __device__ __forceinline__ float cutoff_fc(float v) {
     const float s = sin_half_pi(1.57079632679489662f * v);
     return s * s;
 }
-__device__ __forceinline__ void cutoff_fc_d(float v, float rc_inv, float& fc, float& dfc) {
+__host__ __device__ __forceinline__ void cutoff_fc_d(float v, float rc_inv, float& fc, float& dfc) {
     const float w = 1.57079632679489662f * v;
     const float s = sin_half_pi(w), c = cos_half_pi(w);
     fc = s * s;
@@ -57,7 +59,7 @@ __device__ __forceinline__ float pair_sqrt(float r2) { return __builtin_amdgcn_s
 // contractions with coefficients are formed from sums of T_k (one fused
 // multiply-add per term) instead of building every f_k.
 template <int K>
-__device__ __forceinline__ void cheb_T(float x, float* T) {
+__host__ __device__ __forceinline__ void cheb_T(float x, float* T) {
     T[0] = 1.f;
     if (K > 1) T[1] = x;
     const float x2 = x + x;
@@ -67,7 +69,7 @@ __device__ __forceinline__ void cheb_T(float x, float* T) {
 
 // T_k(x) and dT_k/dx.
 template <int K>
-__device__ __forceinline__ void cheb_T_d(float x, float* T, float* dT) {
+__host__ __device__ __forceinline__ void cheb_T_d(float x, float* T, float* dT) {
     T[0] = 1.f;
     dT[0] = 0.f;
     if (K > 1) {

@@ -1,5 +1,6 @@
-"""CPU self-check of the kernels' per-pair arithmetic (csrc/tnep_math.h,
-compiled for the host) against the FP64 oracle, through quantities that do
+"""CPU self-check of the kernels' per-pair arithmetic (the inline functions of
+csrc/tnep_math.h and csrc/radial_basis.h that the evaluation kernels call,
+compiled for the host by csrc/host_check.cpp) against the FP64 oracle, through quantities that do
 not depend on sign or basis conventions: the addition theorem, contracted
 gradients, and the rotation invariants q_nl and the four-body term."""
 import ctypes as C
@@ -14,14 +15,15 @@ import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_2312_05233_amd", "_host_check.so")
-SRC = os.path.join(ROOT, "paper_2312_05233_amd", "csrc", "host_check.cpp")
+SRCS = [os.path.join(ROOT, "paper_2312_05233_amd", "csrc", f)
+        for f in ("host_check.cpp", "tnep_math.h", "radial_basis.h")]
 RNG = np.random.default_rng(99)
 LRANGE = {1: (0, 3), 2: (3, 8), 3: (8, 15), 4: (15, 24)}
 
 
 @pytest.fixture(scope="module")
 def hc():
-    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(s) for s in SRCS):
         from paper_2312_05233_amd import build as b
 
         b.build_host_check(verbose=False)
