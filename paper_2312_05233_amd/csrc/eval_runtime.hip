@@ -225,6 +225,28 @@ int fetch_meta(Ctx* c, const tnep_frames& fr, HostMeta& m) {
 
 }  // namespace
 
+int64_t BatchBytes::per_atom() const {
+    // tile slots: entries, counts, perm, FP64 positions + cell records, radial sums
+    const int64_t per_slot = (int64_t)slots * 16 + 8 * T + 4 + 48 + 4 * T * kRadialTerms +
+                             (pes_rec_stride > 0 ? 4 * (int64_t)pes_rec_stride + (int64_t)slots * 16 : 0);
+    // per atom: frame_of, slot_of, key_of, bucket_atoms; per-atom records; staged inputs
+    const int64_t per_atom = 16 + 80 * (int64_t)n_models + (host ? 28 : 0) + (pes_rec_stride > 0 && host ? 32 : 0);
+    return per_slot + per_atom;
+}
+
+uint64_t BatchBytes::bound(int64_t atoms, int64_t frames) const {
+    const int64_t n_pad = (atoms + 63) / 64 * 64 + 64 * (int64_t)T;
+    // cells: a periodic frame gets at most max(2 atoms, 125) of them, a vacuum frame one
+    const int64_t cells = 2 * atoms + 125 * frames;
+    const int64_t buckets = cells * T + T + 1;
+    const int64_t fixed = 16 * buckets + 72 * (cells / 1024 + 1) + (int64_t)frames * (sizeof(FrameInfo) + 80 * n_models +
+                                                                                        80 * kReduceChunks) +
+                          4 * kMetaInts + 32 * 4 + 64;
+    const int64_t bytes = per_atom() * atoms + (per_atom() - 16 - 80 * (int64_t)n_models) * (n_pad - atoms) + fixed;
+    // reserve() grows a buffer to at least 1.25 times its previous size
+    return (uint64_t)bytes / 4 * 5 + 4096;
+}
+
 static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job);
 
 // Autotuning of launch parameters that do not change results: the work-group
@@ -466,9 +488,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             for (int k = first; k < last; ++k)
                 if (job.models[k]->kind == TNEP_KIND_PES) rec_stride = pes_rec_stride(job.models[k]->shape, T);
             const bool pes = rec_stride > 0;
-            const int64_t per_atom_bytes = (int64_t)slots * 16 + 8 * T + 24 + 80 * (last - first) +
-                                           (fr.location == TNEP_HOST ? 28 : 0) + (pes ? 4 * rec_stride + 32 + (int64_t)slots * 16 : 0) +
-                                           4 * T * kRadialTerms;  // radial descriptor sums
+            const BatchBytes bb{T, slots, last - first, fr.location == TNEP_HOST, rec_stride};
+            const int64_t per_atom_bytes = bb.per_atom();
             int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
             B = std::max(B, largest);
             const int64_t room = (int64_t)c->budget - (int64_t)(c->in_use - c->nbr.bytes - c->per_atom.bytes);
@@ -739,8 +760,17 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     std::string key = graph_key(c, job, first, last, T, cap_atoms, cap_frames, cap_cells, B_res);
                     if (n_ref_atoms > 0) {
                         char rb[64];
-                        snprintf(rb, sizeof(rb), "/r%d.%d", c->cap_cand, followers ? 1 : 0);
+                        // the candidate radius and displacement guard are kernel arguments
+                        snprintf(rb, sizeof(rb), "/r%d.%d.%a.%a", c->cap_cand, followers ? 1 : 0, (double)cl.rc_search,
+                                 (double)cl.half_skin2);
                         key += rb;
+                    }
+                    // potential-energy outputs: k_pes_forces runs only when forces or site
+                    // energies are asked for, and writes them to fixed staging places
+                    if (pes) {
+                        char pb[16];
+                        snprintf(pb, sizeof(pb), "/p%d%d", forces_dst ? 1 : 0, energies_dst ? 1 : 0);
+                        key += pb;
                     }
                     if (triclinic) key += "/tric";
                     if ((e = replay_graph(c, key, launch_batch)))

@@ -145,3 +145,63 @@ def test_server_slots_use_graphs(gpu_lib):
         assert np.array_equal(ref, results[i]), i
     for c in (plain, ctx):
         c.close()
+
+
+def test_pes_outputs_switch_between_replays(gpu_lib):
+    """Energy-only, forces and site-energy calls alternate on one graph context:
+    each call's graph matches the outputs it asks for (the forces and site
+    energies of a call are those of the plain launches, never left over from
+    a graph captured for another output set)."""
+    plain, graph = _ctx_pair(gpu_lib)
+    m = synth.model("water_pes")
+    pm, gm = gpu_lib.Model(plain, m), gpu_lib.Model(graph, m)
+    fr = synth.water_small(2, seed=21)
+    Er, Wr, Fr, Ur = oracle.eval_pes(m, fr, per_atom=True)
+    A = fr.n_atoms
+    for rep in range(2):
+        for want_forces, want_sites in ((False, False), (True, False), (False, True), (True, True), (False, False)):
+            Fg = np.full((A, 3), np.nan) if want_forces else None
+            Ug = np.full(A, np.nan) if want_sites else None
+            Fp = np.full((A, 3), np.nan) if want_forces else None
+            Up = np.full(A, np.nan) if want_sites else None
+            Eg, Wg, _ = gpu_lib.tnep_eval_pes(graph, gm, fr, forces=Fg, per_atom_energy=Ug, want_forces=want_forces)
+            _eager_noise(rep)
+            Ep, Wp, _ = gpu_lib.tnep_eval_pes(plain, pm, fr, forces=Fp, per_atom_energy=Up, want_forces=want_forces)
+            assert np.array_equal(Eg, Ep) and np.array_equal(Wg, Wp)
+            if want_forces:
+                assert np.array_equal(Fg, Fp), (rep, want_forces, want_sites)
+                assert np.linalg.norm(Fg - Fr) <= TENSOR_TOL * np.linalg.norm(Fr)
+            if want_sites:
+                assert np.array_equal(Ug, Up), (rep, want_forces, want_sites)
+                assert np.abs(Ug - Ur).max() <= TENSOR_TOL * np.abs(Ur).max()
+    captures, launches = graph.graph_counts()
+    assert captures >= 4 and launches >= 10
+    for c in (plain, graph):
+        c.close()
+
+
+def test_skin_change_between_trajectory_replays(gpu_lib):
+    """Trajectory candidate reuse under graphs: changing the skin between two
+    calls uses the new search radius and displacement guard (results equal to
+    plain launches with the same options)."""
+    pos, spc, cell = synth.water_box(8, 24.84, seed=3)
+    fr = synth.ou_trajectory(pos, spc, cell, 12, seed=4)
+    md = synth.model("water_dipole_small")
+    plain, graph = _ctx_pair(gpu_lib)
+    for c in (plain, graph):
+        c.set_option(gpu_lib.OPT_TRAJECTORY_WINDOW, 6)
+    pm, gm = gpu_lib.Model(plain, md), gpu_lib.Model(graph, md)
+    for rep, skin_ma in enumerate((1000, 200, 1000, 600)):
+        for c in (plain, graph):
+            c.set_option(gpu_lib.OPT_SKIN_MA, skin_ma)
+        g = gpu_lib.tnep_eval_dipole(graph, gm, fr)
+        _eager_noise(rep)
+        p = gpu_lib.tnep_eval_dipole(plain, pm, fr)
+        assert np.array_equal(g, p), skin_ma
+        assert graph.reuse_fallbacks() == plain.reuse_fallbacks()
+    ref, pa = oracle.eval_frames(md, fr, per_atom=True)
+    assert np.all(frame_errors(g, ref, pa, fr.offsets) <= TENSOR_TOL)
+    captures, _ = graph.graph_counts()
+    assert captures >= 3
+    for c in (plain, graph):
+        c.close()
