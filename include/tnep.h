@@ -388,26 +388,41 @@ typedef struct {
 } tnep_server_opts;
 
 /* Start the server thread of ctx.  After this, only tnep_submit / tnep_wait /
- * tnep_server_stop / tnep_server_stats / tnep_ctx_graph_counts may be used on
- * ctx.  Slot contexts inherit the launch options of ctx, TNEP_OPT_GRAPHS included. */
+ * tnep_server_stop / tnep_server_stats / tnep_server_memory /
+ * tnep_ctx_graph_counts may be used on ctx.  Slot contexts inherit the launch
+ * options of ctx, TNEP_OPT_GRAPHS included.
+ * Memory: the slots draw their device work buffers from one pool of
+ * mem_budget_bytes.  A slot about to evaluate a batch makes its grant cover
+ * that batch; if the pool cannot give even what the batch's largest frame
+ * needs, the slot returns its buffers and waits until other slots return
+ * theirs (they do so after their current batch), so such requests are queued
+ * until memory frees up instead of failing. */
 int tnep_server_start(tnep_ctx* ctx, const tnep_server_opts* opts);
 /* Queue one request: `kind` selects dipole (out [n_frames][3]) or
  * polarizability (out [n_frames][9]); potential-energy models are not served
  * (TNEP_E_INVALID).  frames and out must be host memory and
  * stay valid until tnep_wait returns for the ticket.  Returns TNEP_E_BUDGET
- * if the request alone can never fit the admission budget. */
+ * if the request's largest frame alone needs more device memory than the
+ * whole pool (it could never run); every other request is queued. */
 int tnep_submit(tnep_ctx* ctx, const tnep_model* model, int32_t kind, const tnep_frames* frames, double* out,
                 uint64_t* ticket);
-/* Block until the request is done.  status: the request's own TNEP_* code;
- * latency_s: submit-to-completion time in seconds.  Each ticket is waited
- * for once. */
+/* Block until the request is done.  status: the request's own TNEP_* code
+ * (TNEP_E_CANCELLED if the server stopped first); latency_s:
+ * submit-to-completion time in seconds.  Each ticket is waited for once: a
+ * second call for the same ticket, also while the first still waits, returns
+ * TNEP_E_INVALID.  tnep_server_stop waits for wait calls in progress to
+ * return before it frees the server. */
 int tnep_wait(tnep_ctx* ctx, uint64_t ticket, int32_t* status, double* latency_s);
 /* Drain and stop the server thread. */
 int tnep_server_stop(tnep_ctx* ctx);
 /* Counters since start: requests done, fused launches, atom-frames done,
- * peak admitted bytes. */
+ * peak bytes granted to the slots from the pool (an upper bound of the
+ * device memory their work buffers held at any time). */
 int tnep_server_stats(tnep_ctx* ctx, uint64_t* requests, uint64_t* launches, uint64_t* atom_frames,
                       uint64_t* peak_bytes);
+/* The memory pool: its size, the bytes granted to slots now, and how many
+ * times a slot had to wait for pool memory.  Any pointer may be NULL. */
+int tnep_server_memory(tnep_ctx* ctx, uint64_t* pool_bytes, uint64_t* granted_bytes, uint64_t* memory_waits);
 
 #ifdef __cplusplus
 }

@@ -171,6 +171,21 @@ struct FrameGeom {
     int n_cells() const { return mode == 1 ? nc[0] * nc[1] * nc[2] : 0; }
 };
 
+// Device bytes of the work buffers that an evaluation reserves: per atom of a
+// launch batch (used to size launch batches to the budget), and an upper
+// bound for a whole launch batch of `atoms` atoms in `frames` frames (cells
+// as many as the grid rules allow, every buffer grown by reserve's factor
+// 1.25), used by the server's admission.  slots: neighbour rows per tile slot
+// (sum of the per-species capacities); pes_rec_stride: floats per atom record
+// of a potential-energy model, 0 otherwise.
+struct BatchBytes {
+    int T, slots, n_models;
+    bool host;
+    int pes_rec_stride;
+    int64_t per_atom() const;
+    uint64_t bound(int64_t atoms, int64_t frames) const;
+};
+
 int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double rc_radial, int64_t n_atoms,
                    FrameGeom& g);
 // Message for tnep_last_error(NULL) (calls without a context, on this thread).

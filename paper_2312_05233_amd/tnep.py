@@ -36,7 +36,7 @@ SUBTRACT_MEAN, NO_OMEGA2 = 1, 2
 EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_option", "tnep_ctx_memory_in_use",
             "tnep_model_create", "tnep_model_free", "tnep_eval_dipole", "tnep_eval_polarizability",
             "tnep_eval_dipole_polarizability", "tnep_spectrum", "tnep_server_start", "tnep_submit", "tnep_wait",
-            "tnep_server_stop", "tnep_server_stats", "tnep_ctx_kernel_time", "tnep_ctx_pair_counts",
+            "tnep_server_stop", "tnep_server_stats", "tnep_server_memory", "tnep_ctx_kernel_time", "tnep_ctx_pair_counts",
             "tnep_ctx_reset_timing", "tnep_autotune_report", "tnep_ctx_graph_counts", "tnep_eval_pes",
             "tnep_raman_map", "tnep_acf_stream_create", "tnep_acf_stream_push", "tnep_acf_stream_end_run",
             "tnep_acf_stream_spectrum", "tnep_acf_stream_raman_map", "tnep_acf_stream_free",
@@ -125,6 +125,7 @@ def _load():
     lib.tnep_wait.argtypes = [vp, C.c_uint64, P(C.c_int32), P(C.c_double)]
     lib.tnep_server_stop.argtypes = [vp]
     lib.tnep_server_stats.argtypes = [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+    lib.tnep_server_memory.argtypes = [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
     lib.tnep_ctx_kernel_time.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_uint64)]
     lib.tnep_ctx_pair_counts.argtypes = [vp, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
     lib.tnep_ctx_reset_timing.argtypes = [vp]
@@ -540,6 +541,12 @@ class Server:
         r, l, a, p = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_uint64()
         self.ctx.check(lib.tnep_server_stats(self.ctx.h, C.byref(r), C.byref(l), C.byref(a), C.byref(p)))
         return {"requests": r.value, "launches": l.value, "atom_frames": a.value, "peak_bytes": p.value}
+
+    def memory(self):
+        """(pool bytes, bytes granted to slots now, times a slot waited for pool memory)."""
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        self.ctx.check(lib.tnep_server_memory(self.ctx.h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
 
     def stop(self):
         self.ctx.check(lib.tnep_server_stop(self.ctx.h))
