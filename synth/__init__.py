@@ -132,6 +132,27 @@ def water_box(n_side: int, box: float, seed: int, jitter: float = 0.3, oh: float
     return pos, spc, cell
 
 
+def water_box_orthorhombic(counts, spacing: float, seed: int, jitter: float = 0.3, oh: float = 0.96,
+                           angle_deg: float = 104.5, o_species: int = 0, h_species: int = 1):
+    """Like water_box on an orthorhombic lattice of counts = (nx, ny, nz)
+    molecules with the given O spacing (e.g. 16 x 16 x 32 = 8192 H2O, 24,576
+    atoms, in a 49.7 x 49.7 x 99.4 A box at the 3.105 A spacing of the water
+    workloads).  Returns (positions, species, cell [9])."""
+    rng = np.random.default_rng(seed)
+    counts = np.asarray(counts, np.int64)
+    n_mol = int(np.prod(counts))
+    box = counts * spacing
+    grid = np.stack(np.meshgrid(*[np.arange(c) for c in counts], indexing="ij"), -1)
+    o = (grid.reshape(-1, 3) + 0.5) * spacing + rng.normal(0.0, jitter, (n_mol, 3))
+    half = np.deg2rad(angle_deg) / 2.0
+    local = np.array([[np.sin(half), 0.0, np.cos(half)], [-np.sin(half), 0.0, np.cos(half)]]) * oh
+    rot = _random_rotations(rng, n_mol)
+    h = o[:, None, :] + np.einsum("mij,hj->mhi", rot, local)
+    pos = np.mod(np.concatenate([o[:, None, :], h], axis=1).reshape(-1, 3), box)
+    spc = np.tile(np.array([o_species, h_species, h_species], np.int32), n_mol)
+    return pos, spc, np.diag(box.astype(np.float64)).reshape(9)
+
+
 def water_frames(n_side: int, box: float, n_frames: int, seed: int, **kw) -> Frames:
     """n_frames independent water boxes (seeds seed*1000 + f)."""
     parts = []
