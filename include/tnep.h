@@ -318,6 +318,26 @@ typedef struct {
 int tnep_spectrum(tnep_ctx* ctx, const tnep_spectrum_args* args, double* freq_cm1, double* intensity,
                   double* acf);
 
+/* tnep_spectrum for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and results as tnep_spectrum, with two differences:
+ *   - args->location must be TNEP_DEVICE (series and outputs in device memory
+ *     of the context's GPU); TNEP_HOST is TNEP_E_INVALID;
+ *   - the call enqueues its kernels on the context's stream and returns
+ *     without waiting: results are complete when the stream reaches that
+ *     point.
+ * The workspace (the signals, their FFTs and the cosine table:
+ * 32 n_series s P + 72 n_series + 24 M + 1040 bytes plus alignment, s = 3
+ * (IR), 1 (iso, proj) or 9 (aniso) signals, P the FFT length, the power of
+ * two >= 2 n_steps) lives
+ * in one fixed 64 MiB device array per GPU, held by the library until the
+ * process ends; larger requests are TNEP_E_BUDGET with a message.  The call
+ * allocates nothing (no hipMalloc / hipFree, no events).  All calls on one
+ * GPU share that array: calls that overlap in time on one GPU (other streams,
+ * contexts or threads) race and must be serialised by the caller. */
+int tnep_spectrum_noalloc(tnep_ctx* ctx, const tnep_spectrum_args* args, double* freq_cm1, double* intensity,
+                          double* acf);
+
 /* Orientation-resolved Raman lineshapes (Sec. 2.7, Eqs. raman-cross-section
  * and raman-lineshape; Sec. 4 maps the crystal-orientation dependence): for
  * each polarisation pair o, sum_{g d m n} n_g n_m L_{g d m n}(w) e_d e_n, i.e.

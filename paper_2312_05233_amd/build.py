@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtnep.so")
 SOURCES = ["api.hip", "eval_runtime.hip", "kernels_neighbors.hip", "kernels_eval.hip", "kernels_spectrum.hip",
-           "spectra_api.hip", "population_api.hip", "model_file.hip", "server.hip"]
+           "spectra_api.hip", "population_api.hip", "model_file.hip", "server.hip", "noalloc_api.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions anywhere in the device code

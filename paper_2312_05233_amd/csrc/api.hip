@@ -164,6 +164,13 @@ extern "C" int tnep_ctx_create(int device, void* hip_stream, uint64_t mem_budget
         g_create_error = "hipHostMalloc failed";
         return TNEP_E_HIP;
     }
+    // device address of this device's fixed workspace (tnep_spectrum_noalloc)
+    std::string err;
+    if (noalloc_scratch_setup(device, err) != TNEP_OK) {
+        delete c;
+        g_create_error = err;
+        return TNEP_E_HIP;
+    }
     *out = reinterpret_cast<tnep_ctx*>(c);
     return TNEP_OK;
 }

@@ -196,4 +196,10 @@ void server_graph_counts(const Ctx* c, uint64_t& captures, uint64_t& launches); 
 
 hipError_t launch_init_flags(int32_t* d_flags, hipStream_t s);
 
+// Fixed device workspace of tnep_spectrum_noalloc (noalloc_api.hip): its
+// size, and the per-device resolution of its address, done once per device
+// by tnep_ctx_create with that device current.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+int noalloc_scratch_setup(int device, std::string& err);
+
 }  // namespace tnep

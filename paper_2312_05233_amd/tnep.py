@@ -41,7 +41,7 @@ EXPORTED = ["tnep_ctx_create", "tnep_ctx_destroy", "tnep_last_error", "tnep_set_
             "tnep_raman_map", "tnep_acf_stream_create", "tnep_acf_stream_push", "tnep_acf_stream_end_run",
             "tnep_acf_stream_spectrum", "tnep_acf_stream_raman_map", "tnep_acf_stream_free",
             "tnep_ctx_reuse_fallbacks", "tnep_eval_dipole_charged", "tnep_population_loss", "tnep_model_save",
-            "tnep_model_load", "tnep_model_info"]
+            "tnep_model_load", "tnep_model_info", "tnep_spectrum_noalloc"]
 
 
 class TnepError(RuntimeError):
@@ -120,6 +120,7 @@ def _load():
     lib.tnep_acf_stream_free.argtypes = [vp]
     lib.tnep_acf_stream_free.restype = None
     lib.tnep_spectrum.argtypes = [vp, P(SpectrumArgs), vp, vp, vp]
+    lib.tnep_spectrum_noalloc.argtypes = [vp, P(SpectrumArgs), vp, vp, vp]
     lib.tnep_server_start.argtypes = [vp, P(ServerOpts)]
     lib.tnep_submit.argtypes = [vp, vp, C.c_int32, P(FramesDesc), vp, P(C.c_uint64)]
     lib.tnep_wait.argtypes = [vp, C.c_uint64, P(C.c_int32), P(C.c_double)]
@@ -433,6 +434,26 @@ def tnep_spectrum(ctx: Context, series, kind, dt_fs, max_lag, window=WIN_HANN, f
         a.location = DEVICE
     a.series = _ptr(series)
     ctx.check(lib.tnep_spectrum(ctx.h, C.byref(a), _ptr(freq), _ptr(intensity), _ptr(acf)))
+    return freq, intensity, acf
+
+
+def tnep_spectrum_noalloc(ctx: Context, series, kind, dt_fs, max_lag, freq, intensity, acf=None, window=WIN_HANN,
+                          flags=0, n_hat=(0, 0, 0), e_hat=(0, 0, 0), laser_cm1=0.0):
+    """tnep_spectrum on device tensors with the library's fixed workspace (no
+    device allocation); enqueued on the context's stream, not waited for.
+    series [S, N_t, 3|9], freq and intensity [M+1], acf [M] or None: torch
+    CUDA tensors."""
+    a = SpectrumArgs()
+    a.kind = kind
+    a.n_series, a.n_steps = int(series.shape[0]), int(series.shape[1])
+    a.dt_fs, a.max_lag, a.window, a.flags = dt_fs, int(max_lag), window, flags
+    a.laser_cm1 = float(laser_cm1)
+    for k in range(3):
+        a.n_hat[k], a.e_hat[k] = n_hat[k], e_hat[k]
+    # numpy input is reported as host memory, which the library rejects
+    a.location = HOST if isinstance(series, np.ndarray) else DEVICE
+    a.series = _ptr(series)
+    ctx.check(lib.tnep_spectrum_noalloc(ctx.h, C.byref(a), _ptr(freq), _ptr(intensity), _ptr(acf)))
     return freq, intensity, acf
 
 
