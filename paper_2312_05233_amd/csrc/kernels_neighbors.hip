@@ -2,9 +2,12 @@
 //
 // The sums over j != i of the method (Sec. 2.1, Eq. virial; Sec. 2.2, Eq. mu;
 // Sec. 2.3, Eq. polarizability-model) run over the atoms inside the radial
-// cutoff.  Pair vectors are formed in FP64 with the minimum-image convention
-// (on orthorhombic cell grids from fixed-point offsets within the cells, to
-// within 2^-30 of a cell edge) and stored as FP32.
+// cutoff, with the minimum-image convention.  On orthorhombic cell grids a
+// pair vector is formed in FP32 from the two atoms' FP32 offsets within their
+// cells and the cells' offset (a few 1e-7 A from the exact vector, about the
+// FP32 rounding of the stored entry); triclinic bins use fixed-point
+// fractional offsets and FP64, frames without a grid FP64 positions.  Entries
+// are stored as FP32.
 //
 // Pipeline (all on the device):
 //   1. bin every atom into a bucket (cell, species).  Fully periodic
@@ -246,12 +249,11 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 // that slot.  One thread per atom: buckets hold a few atoms on cell grids and
 // a whole frame otherwise, so the rank loop is never longer than the frame's
 // own neighbour loop.  Cell grids get a 16-byte record: the offsets of the
-// wrapped position from its cell's origin as integers in units of q_unit (a
-// power of two, so the scaling is exact), and the cell's index along the third
-// axis (z, or the third lattice vector); the position is in A on orthorhombic
-// grids and in fractional coordinates on triclinic bins.  Frames without a
-// grid keep the FP64 position (triclinic ones: wrapped fractional
-// coordinates).
+// wrapped position from its cell's centre (orthorhombic grids: FP32, in A) or
+// origin (triclinic bins: fractional, as integers in units of q_unit, a power
+// of two so the scaling is exact), and the cell's index along the third axis
+// (z, or the third lattice vector).  Frames without a grid keep the FP64 position
+// (triclinic ones: wrapped fractional coordinates).
 __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ frame_of,
                              const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
                              const int32_t* __restrict__ bucket_atoms, const int32_t* __restrict__ perm_start,
@@ -288,7 +290,9 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t
                 s = r[d] - fi.L[d] * floor(r[d] * fi.Linv[d]);
                 h = fi.L[d] / fi.nc[d];
             }
-            q[d] = (int)rint((s - c[d] * h) / fi.q_unit);
+            // triclinic: fixed point in units of q_unit from the bin origin;
+            // orthorhombic: FP32 offset (A) from the cell centre, |offset| <= h / 2
+            q[d] = fi.tric ? (int)rint((s - c[d] * h) / fi.q_unit) : __float_as_int((float)(s - (c[d] + 0.5) * h));
         }
         cell_rec[slot] = make_int4(q[0], q[1], q[2], c[2]);
         return;
@@ -435,24 +439,30 @@ struct RadialSums {
 
 // One candidate of k_neighbors: pair vector d = r_j - r_i (FP64), in = a real
 // candidate other than the atom itself within the search radius.
-template <bool REF>
+template <bool REF, typename R>
 __device__ __forceinline__ void take_candidate(PairSink& ps, RadialSums& rs, float rcR_inv, const float4* lds, bool in,
-                                               double dx, double dy, double dz, double r2, int j, double rc2r,
-                                               double rc2a, bool& overlap, int& n_cand, int32_t* cand, int cand_cap,
-                                               const int32_t* perm, int atom_begin) {
+                                               R dx, R dy, R dz, R r2, int j, R rc2r, R rc2a, bool& overlap,
+                                               int& n_cand, int32_t* cand, int cand_cap, const int32_t* perm,
+                                               int atom_begin) {
     if (in) {
         if constexpr (REF) {
             if (n_cand < cand_cap) cand[n_cand] = perm[j] - atom_begin;
             ++n_cand;
         }
         if (!REF || r2 < rc2r) {
-            overlap |= r2 < 1e-8;
+            overlap |= r2 < (R)1e-8;
             const float4 e = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
             ps.push_deferred(e, r2 < rc2a, lds);
             rs.add(e.x, e.y, e.z, rcR_inv);
         }
     }
 }
+
+// Candidates per iteration of the cell-grid walk (their record loads are
+// issued together): four for plain searches, two for reference frames, whose
+// candidate-list bookkeeping leaves no registers for four.
+template <bool REF>
+constexpr int cand_per_iter() { return REF ? 2 : 4; }
 
 // Four waves per SIMD (<= 128 VGPRs): the candidate loop is bound by load
 // latency, so occupancy matters more than anything the registers could buy.
@@ -500,6 +510,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     // references collect candidates out to r_c + skin
     const float rs = REF ? cl.rc_search : rc_radial;
     const double rcs2 = (double)rs * rs;
+    const float rc2rf = rc_radial * rc_radial, rc2af = rc_angular * rc_angular, rcs2f = rs * rs;
     // cell pruning in FP32 with a 1e-3 A margin: a cell is skipped only when surely beyond the radius
     const float prune2 = (rs + 1e-3f) * (rs + 1e-3f);
     // entry (row r) of this lane: lane_base + (r / 4) * 256 + r % 4
@@ -549,7 +560,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         for (int col = 0; col < n_col; ++col) {
             // slot ranges [b0, e0) and [b1, e1) of species t
             int b0, e0, b1 = 0, e1 = 0;
-            int ox = 0, oy = 0;
+            int ox = 0, oy = 0, z0 = 0, z1 = 0;
             if (fi.mode == 1) {
                 ox = col / 5 - 2;
                 oy = col % 5 - 2;
@@ -562,7 +573,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                 const float dz_left = __builtin_amdgcn_sqrtf(prune2 - gxy);
                 const int below = min(kCellReachZ, max(0, (int)floorf((dz_left - lo_z) * hz_inv) + 1));
                 const int above = min(kCellReachZ, max(0, (int)floorf((dz_left - hi_z) * hz_inv) + 1));
-                const int z0 = iz - below, z1 = iz + above;
+                z0 = iz - below;
+                z1 = iz + above;
                 const int col0 = (fi.cell_base + (wrap_cell(ix + ox, nx) * ny + wrap_cell(iy + oy, ny)) * nz) * T + t;
                 if (z0 >= 0 && z1 < nz) {
                     b0 = perm_start[col0 + z0 * T];
@@ -582,26 +594,32 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
             // else b1 + q - n0), so a wavefront runs as long as its longest lane
             const int n0 = e0 - b0, n = n0 + (e1 - b1), d1 = b1 - n0;
             if (fi.mode == 1) {
-                // pair vector from the cell records: (cell offset) h + (q_j - q_i) q_unit
-                const double offx = ox * hx, offy = oy * hy, qu = fi.q_unit;
-                for (int q = 0; q < n; q += 2) {
-                    const int k0 = q < n0 ? b0 + q : d1 + q;
-                    const int k1 = q + 1 < n0 ? b0 + q + 1 : d1 + q + 1;
-                    const int4 c0 = cell_rec[k0];
-                    const int4 c1 = q + 1 < n ? cell_rec[k1] : make_int4(0, 0, 0, 0);
+                // pair vector from the cell records (FP32 offsets from the cell centres):
+                // (q_j + column offset - q_i) in x and y, (q_j - q_i) + oz h_z in z
+                auto slot_at = [&](int q) { return q < n0 ? b0 + q : d1 + q; };
+                const float bxf = (float)(ox * hx - (double)__int_as_float(own.x));
+                const float byf = (float)(oy * hy - (double)__int_as_float(own.y));
+                const float ozf = __int_as_float(own.z), hzf = (float)hz;
+                // z-cell offset = record's z index + shift of the column part (below / above the box face)
+                const int zadd0 = (z0 < 0 ? -nz : 0) - iz, zadd1 = (z1 >= nz ? nz : 0) - iz;
+                constexpr int kCand = cand_per_iter<REF>();
+                for (int q = 0; q < n; q += kCand) {
+                    // candidates past the end re-read the last one (never taken: q + u >= n)
+                    int4 cur[kCand];
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        const int4 cr = u == 0 ? c0 : c1;
-                        const int j = u == 0 ? k0 : k1;  // tile slot of the candidate
-                        int oz = cr.w - iz;
-                        oz = oz > kCellReachZ ? oz - nz : (oz < -kCellReachZ ? oz + nz : oz);
-                        const double dx = fma((double)(cr.x - own.x), qu, offx);
-                        const double dy = fma((double)(cr.y - own.y), qu, offy);
-                        const double dz = fma((double)(cr.z - own.z), qu, oz * hz);
-                        const double r2 = dx * dx + dy * dy + dz * dz;
-                        take_candidate<REF>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2),
-                                            dx, dy, dz, r2, j, rc2r, rc2a, overlap, n_cand, cand, cl.cap, nl.perm,
-                                            (int)fi.atom_begin);
+                    for (int u = 0; u < kCand; ++u) cur[u] = cell_rec[slot_at(min(q + u, n - 1))];
+#pragma unroll
+                    for (int u = 0; u < kCand; ++u) {
+                        const int4 cr = cur[u];
+                        const int j = slot_at(q + u);  // tile slot of the candidate
+                        const int oz = cr.w + (q + u < n0 ? zadd0 : zadd1);
+                        const float dx = __int_as_float(cr.x) + bxf;
+                        const float dy = __int_as_float(cr.y) + byf;
+                        const float dz = fmaf((float)oz, hzf, __int_as_float(cr.z) - ozf);
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        take_candidate<REF, float>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2f),
+                                                   dx, dy, dz, r2, j, rc2rf, rc2af, overlap, n_cand, cand, cl.cap,
+                                                   nl.perm, (int)fi.atom_begin);
                         coop_flush(ps, nb_stage, list);
                     }
                 }
@@ -619,9 +637,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                         const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
                         const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
                         const double r2 = dx * dx + dy * dy + dz * dz;
-                        take_candidate<REF>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2),
-                                            dx, dy, dz, r2, j, rc2r, rc2a, overlap, n_cand, cand, cl.cap, nl.perm,
-                                            (int)fi.atom_begin);
+                        take_candidate<REF, double>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2),
+                                                    dx, dy, dz, r2, j, rc2r, rc2a, overlap, n_cand, cand, cl.cap,
+                                                    nl.perm, (int)fi.atom_begin);
                         coop_flush(ps, nb_stage, list);
                     }
                 }
