@@ -342,6 +342,15 @@ int tnep::stage_model(Ctx* c, const tnep_model_desc* d, std::vector<float>& h, M
         if (!std::isfinite(d->c_radial[k])) return model_error(c, "non-finite c_radial");
     size_t o_cr = put(d->c_radial, ncr);
     size_t o_ca = put(d->c_angular, nca);
+    // derivative series of every angular radial function: b_k = b_{k+2} + 2 (k+1) c_{k+1}, b_0 halved
+    std::vector<double> cad(nca, 0.0);
+    for (size_t row = 0; row < nca / sh.ka; ++row) {
+        const double* cr = d->c_angular + row * sh.ka;
+        double* b = cad.data() + row * sh.ka;
+        for (int k = sh.ka - 2; k >= 0; --k) b[k] = (k + 2 <= sh.ka - 2 ? b[k + 2] : 0.0) + 2.0 * (k + 1) * cr[k + 1];
+        b[0] *= 0.5;
+    }
+    size_t o_cad = put(cad.data(), nca);
     size_t o_s = put(d->q_scaler, D);
     size_t o_w0[2] = {0, 0}, o_b0[2] = {0, 0}, o_w1[2] = {0, 0}, o_w0t[2] = {0, 0}, o_b1s[2] = {0, 0};
     for (int hd = 0; hd < heads; ++hd) {
@@ -441,6 +450,7 @@ int tnep::stage_model(Ctx* c, const tnep_model_desc* d, std::vector<float>& h, M
     m.rc_angular = d->rc_angular;
     lay.cr = o_cr;
     lay.ca = o_ca;
+    lay.cad = o_cad;
     lay.s = o_s;
     for (int hd = 0; hd < 2; ++hd) {
         const int src = hd < heads ? hd : 0;
@@ -465,6 +475,7 @@ void tnep::bind_model(Model& m, const float* base, const ModelLayout& lay) {
     DevModel& dm = m.dm;
     dm.c_radial = base + lay.cr;
     dm.c_angular = base + lay.ca;
+    dm.c_angular_d = base + lay.cad;
     dm.scaler = base + lay.s;
     for (int hd = 0; hd < 2; ++hd) {
         dm.w0[hd] = base + lay.w0[hd];

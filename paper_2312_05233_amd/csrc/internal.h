@@ -54,6 +54,8 @@ struct FrameInfo {
 struct DevModel {
     const float* c_radial;   // [T][T][NR][KR]
     const float* c_angular;  // [T][T][NA][KA]
+    const float* c_angular_d;  // [T][T][NA][KA]: Chebyshev coefficients of d/dx sum_k c_nk T_k(x)
+                               // (last one 0), so sum_k c_nk T_k'(x) = sum_k c_angular_d[n][k] T_k(x)
     const float* scaler;     // [D]
     const float* w0[2];      // [H][D]
     const float* b0[2];      // [H]

@@ -440,7 +440,10 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     for (int n = 0; n < NA; ++n)
 #pragma unroll
         for (int c = 0; c < kLM; ++c) A[n][c] *= kShNorm[c];
+    // the dipole's atom term sums FP32 pair terms r^2 dU_i/dr_ij that can cancel
+    // (a molecule's dipole can be a small remainder of its atom terms): FP64 sum
     float acc[NT];
+    double accd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < NT; ++k) acc[k] = 0.f;
     float own[3] = {0.f, 0.f, 0.f};  // potential: sum_j dU_i/dr_ij, the atom's own force term
@@ -452,9 +455,10 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             own[2] += Fz;
         }
         if constexpr (KIND == 1) {
-            acc[0] -= r2 * Fx;
-            acc[1] -= r2 * Fy;
-            acc[2] -= r2 * Fz;
+            const double r2d = (double)r2;
+            accd[0] -= r2d * (double)Fx;
+            accd[1] -= r2d * (double)Fy;
+            accd[2] -= r2d * (double)Fz;
         } else {
             acc[0] -= dx * Fx;
             acc[1] -= dx * Fy;
@@ -471,6 +475,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     for (int t = 0; t < T; ++t) {
         const float* __restrict__ cR = m.c_radial + (ti * T + t) * (NR * KR);
         const float* __restrict__ cA = m.c_angular + (ti * T + t) * (NA * KA);
+        const float* __restrict__ cAd = m.c_angular_d + (ti * T + t) * (NA * KA);
         const int n_ang = nl.counts[(int64_t)(2 * t) * nl.n_pad + p];
         const int n_rad = nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
         const float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
@@ -484,10 +489,17 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             for (int n = 0; n < NR; ++n) d += dq[n] * cR[n * KR + k];
             Dk[k] = d;
         }
-        // sum_k Dk f_k'(r) = (fc x' sum_k Dk T_k' + fc' (sum_k Dk T_k + sum_k Dk)) / 2
+        // sum_k Dk f_k'(r) = (fc x' sum_k Dk T_k' + fc' (sum_k Dk T_k + sum_k Dk)) / 2, with
+        // sum_k Dk T_k'(x) = sum_k Ek T_k(x): Ek the Chebyshev coefficients of the
+        // derivative series (E_k = E_{k+2} + 2 (k+1) D_{k+1}, E_0 halved), so a pair
+        // needs the T_k only, not their derivatives
         float Dsum = 0.f;
 #pragma unroll
         for (int k = 0; k < KR; ++k) Dsum += Dk[k];
+        float Ek[KR > 1 ? KR - 1 : 1];
+#pragma unroll
+        for (int k = KR - 2; k >= 0; --k) Ek[k] = (k + 2 <= KR - 2 ? Ek[k + 2] : 0.f) + (float)(2 * (k + 1)) * Dk[k + 1];
+        Ek[0] *= 0.5f;
         float CsA[NA];  // sum_k c_nk of the angular coefficients (wave-uniform)
 #pragma unroll
         for (int n = 0; n < NA; ++n) {
@@ -497,16 +509,15 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             CsA[n] = c;
         }
         auto radial_slope = [&](float r) {
-            float fc, dfc, Tk[KR], dT[KR];
+            float fc, dfc, Tk[KR];
             cutoff_fc_d(1.f - r * rcR_inv, rcR_inv, fc, dfc);
             const float tt = r * rcR_inv - 1.f;
-            cheb_T_d<KR>(2.f * tt * tt - 1.f, Tk, dT);
+            cheb_T<KR>(2.f * tt * tt - 1.f, Tk);
             float s0 = Dsum, s1 = 0.f;
 #pragma unroll
-            for (int k = 0; k < KR; ++k) {
-                s0 += Dk[k] * Tk[k];
-                s1 += Dk[k] * dT[k];
-            }
+            for (int k = 0; k < KR; ++k) s0 += Dk[k] * Tk[k];
+#pragma unroll
+            for (int k = 0; k + 1 < KR; ++k) s1 += Ek[k] * Tk[k];
             return 0.5f * (fc * (4.f * tt * rcR_inv) * s1 + dfc * s0);
         };
         float4 nxt = n_ang > 0 ? ga[0] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -518,22 +529,22 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float r = r2 * rinv;
             const float ux = e.x * rinv, uy = e.y * rinv, uz = e.z * rinv;
             const float sr = radial_slope(r);
-            float fc, dfc, Tk[KA], dT[KA];
+            float fc, dfc, Tk[KA];
             cutoff_fc_d(1.f - r * rcA_inv, rcA_inv, fc, dfc);
             const float ta = r * rcA_inv - 1.f;
-            cheb_T_d<KA>(2.f * ta * ta - 1.f, Tk, dT);
+            cheb_T<KA>(2.f * ta * ta - 1.f, Tk);
             // g_n = fc/2 (P_n + C_n), g_n' = (fc x' Q_n + fc' (P_n + C_n)) / 2 with
-            // P_n = sum_k c_nk T_k, Q_n = sum_k c_nk T_k', C_n = sum_k c_nk
+            // P_n = sum_k c_nk T_k, Q_n = sum_k c_nk T_k' = sum_k c'_nk T_k (the model's
+            // derivative-series coefficients), C_n = sum_k c_nk
             const float hfc = 0.5f * fc, hdfc = 0.5f * dfc, hfx = hfc * (4.f * ta * rcA_inv);
             float gA[NA], dgA[NA];
 #pragma unroll
             for (int n = 0; n < NA; ++n) {
                 float pn = CsA[n], qn = 0.f;
 #pragma unroll
-                for (int k = 0; k < KA; ++k) {
-                    pn += cA[n * KA + k] * Tk[k];
-                    qn += cA[n * KA + k] * dT[k];
-                }
+                for (int k = 0; k < KA; ++k) pn += cA[n * KA + k] * Tk[k];
+#pragma unroll
+                for (int k = 0; k + 1 < KA; ++k) qn += cAd[n * KA + k] * Tk[k];
                 gA[n] = hfc * pn;
                 dgA[n] = hfx * qn + hdfc * pn;
             }
@@ -582,7 +593,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     double* out = per_atom + (int64_t)a * NT;
     if constexpr (KIND == 1) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) out[k] = (double)acc[k];
+        for (int k = 0; k < 3; ++k) out[k] = accd[k];
     } else {
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[k] = (double)acc[k] + ((k % 4 == 0) ? (double)Us : 0.0);

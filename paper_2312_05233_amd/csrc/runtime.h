@@ -132,7 +132,7 @@ struct Model {
 
 // Offsets (in floats) of a model's arrays inside its FP32 device image.
 struct ModelLayout {
-    size_t cr = 0, ca = 0, s = 0;
+    size_t cr = 0, ca = 0, cad = 0, s = 0;
     size_t w0[2] = {}, b0[2] = {}, w1[2] = {}, w0t[2] = {}, f32_fwd[2] = {}, bf_fwd_hi[2] = {}, bf_fwd_lo[2] = {};
     int64_t b1s[2] = {-1, -1};
     float b1[2] = {};

@@ -46,7 +46,10 @@ def test_all_molecules_one_call(gpu_lib):
     ref_al, pa_al = oracle.eval_frames(mp, fr, per_atom=True)
     e_mu = frame_errors(mu, ref_mu, pa_mu, fr.offsets)
     e_al = frame_errors(np.asarray(al).reshape(-1, 9), ref_al.reshape(-1, 9), pa_al, fr.offsets)
-    print(f"8192 molecules ({fr.n_atoms} atoms): dipole {e_mu.max():.2e} polarizability {e_al.max():.2e}", flush=True)
+    w = int(np.argmax(e_mu))
+    pa_norm = np.linalg.norm(pa_mu[fr.offsets[w]:fr.offsets[w + 1]], axis=1).sum()
+    print(f"8192 molecules ({fr.n_atoms} atoms): dipole {e_mu.max():.2e} (frame {w}, |mu| / sum |mu_i| = "
+          f"{np.linalg.norm(ref_mu[w]) / pa_norm:.2e}) polarizability {e_al.max():.2e}", flush=True)
     assert e_mu.shape == (8192,) and np.all(e_mu <= TENSOR_TOL)
     assert np.all(e_al <= TENSOR_TOL)
     ctx.close()
