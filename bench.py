@@ -173,12 +173,25 @@ def bench_molecules(args):
     dfr = tnep.DeviceFrames(frames)
     mu = torch.zeros((frames.n_frames, 3), dtype=torch.float64, device="cuda")
     al = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
-    t = _timed(lambda: tnep.tnep_eval_dipole_polarizability(ctx, gd, gp, dfr, mu, al), args.steps, args.warmup)
+    step = lambda: tnep.tnep_eval_dipole_polarizability(ctx, gd, gp, dfr, mu, al)  # noqa: E731
+    t = _timed(step, args.steps, args.warmup)
+    # kernel times and pair counts from an instrumented pass
+    ctx.set_option(tnep.OPT_TIMING, 1)
+    ctx.reset_timing()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    kt = {name: ctx.kernel_time(k)[0] / args.steps for name, k in (
+        ("neighbors", tnep.KERNEL_NEIGHBORS), ("eval_dipole", tnep.KERNEL_EVAL_DIPOLE),
+        ("eval_polarizability", tnep.KERNEL_EVAL_POLARIZABILITY), ("frame_reduce", tnep.KERNEL_FRAME_REDUCE))}
+    atoms, rad, ang = ctx.pair_counts()
     print(json.dumps({"metric": "TNEP atom-frames/s (dipole+polarizability) at FP32 tol", "value": frames.n_atoms / t,
                       "unit": "atom-frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                       "ms_per_step": 1e3 * t, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": "8192 vacuum molecules, 20-80 atoms (%d atoms), C/H/N/O/F, dipole + "
-                                             "polarizability" % frames.n_atoms}}), flush=True)
+                                             "polarizability" % frames.n_atoms},
+                      "kernels_ms_per_step": kt, "mean_radial_neighbors": rad / atoms,
+                      "mean_angular_neighbors": ang / atoms}), flush=True)
 
 
 def bench_pes(args):

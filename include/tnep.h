@@ -360,14 +360,21 @@ int tnep_raman_map(tnep_ctx* ctx, const tnep_spectrum_args* args, int32_t n_orie
  * run means removed under TNEP_SUBTRACT_MEAN) joins the average over runs.
  * The results equal tnep_spectrum / tnep_raman_map on the whole runs (up to
  * rounding).  A stream belongs to its context, which must outlive it; calls
- * on a stream are synchronous and not thread-safe. */
+ * on a stream are synchronous (device pushes excepted, see below) and not
+ * thread-safe. */
 typedef struct tnep_acf_stream tnep_acf_stream;
 /* kind: TNEP_IR (samples [.][3]), TNEP_RAMAN_ISO / ANISO / PROJ (with n_hat,
  * e_hat) or TNEP_RAMAN_MAP (samples [.][9]); max_lag M >= 1; flags:
  * TNEP_SUBTRACT_MEAN | TNEP_NO_OMEGA2. */
 int tnep_acf_stream_create(tnep_ctx* ctx, int32_t kind, int64_t max_lag, int32_t flags, const double* n_hat,
                            const double* e_hat, tnep_acf_stream** out);
-/* Append n_samples samples ([n_samples][3 or 9] FP64, host or device) to the current run. */
+/* Append n_samples samples ([n_samples][3 or 9] FP64, host or device) to the current run.
+ * Host samples are consumed before the call returns.  Device samples
+ * (TNEP_DEVICE, with TNEP_OPT_TIMING off) are only enqueued on the context's
+ * stream: the call returns without waiting, so consecutive pushes run back to
+ * back on the GPU, and the caller keeps the chunk unchanged until the next
+ * tnep_acf_stream_end_run / _spectrum / _raman_map call on the stream (these
+ * wait) or until the stream is otherwise synchronised. */
 int tnep_acf_stream_push(tnep_acf_stream* s, const double* samples, int64_t n_samples, int32_t location);
 /* Close the current run (it needs at least max_lag samples). */
 int tnep_acf_stream_end_run(tnep_acf_stream* s);

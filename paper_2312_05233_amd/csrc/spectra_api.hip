@@ -237,8 +237,12 @@ extern "C" int tnep_acf_stream_push(tnep_acf_stream* s, const double* samples, i
     const int tr = c->timer_begin(TNEP_KERNEL_SPECTRUM);
     HIP_CHECK_RET(c, launch_stream_push(st, d_chunk, n_samples, P, s->work.p, c->stream));
     c->timer_end(tr);
-    HIP_CHECK_RET(c, hipStreamSynchronize(c->stream));
-    c->timer_flush();
+    // device chunks: no wait, so that consecutive pushes queue back to back
+    // (the run state is device-resident and the kernels run in stream order)
+    if (location == TNEP_HOST || c->timing) {
+        HIP_CHECK_RET(c, hipStreamSynchronize(c->stream));
+        c->timer_flush();
+    }
     std::swap(st.carry, st.carry_next);
     st.carry_len = std::min(st.carry_cap, st.carry_len + n_samples);
     st.run_len += n_samples;
