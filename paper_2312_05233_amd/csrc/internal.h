@@ -271,7 +271,19 @@ struct StreamState {
     double* run_sum;                   // [nch][M] sum over finished runs of C(tau)
     int64_t run_len;                   // samples in the current run
     int64_t n_runs;                    // finished runs
+    const void* blk_tw;                // [kBlkN / 2] twiddles of the blocked path (max lag <= kBlkMaxLag)
 };
+// Blocked streaming path: a chunk is split into blocks of kBlkN - (M - 1) new
+// samples whose kBlkN-point transforms run inside one work-group (LDS), at most
+// kBlkRound blocks per launch round; used when M <= kBlkMaxLag.
+constexpr int kBlkN = 4096;
+constexpr int64_t kBlkMaxLag = kBlkN / 2;
+constexpr int kBlkRound = 32;
+size_t stream_blk_workspace_bytes(int nsig, int nch, int64_t M, int64_t n);
+size_t stream_blk_twiddle_bytes();
+hipError_t launch_stream_twiddles(void* tw, hipStream_t s);
+hipError_t launch_stream_push_blocked(const StreamState& st, const double* d_chunk, int64_t n, void* d_work,
+                                      hipStream_t s);
 size_t stream_push_workspace_bytes(int nsig, int nch, int64_t P);
 hipError_t launch_stream_push(const StreamState& st, const double* d_chunk, int64_t n, int64_t P, void* d_work,
                               hipStream_t s);

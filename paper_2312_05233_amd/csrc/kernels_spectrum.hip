@@ -20,6 +20,8 @@
 // IR spectra carry the classical w^2 prefactor (Eq. ir-intensity); Raman
 // spectra optionally the ((w_in - w) / c)^4 factor of Eq. raman-cross-section.
 // Long series can also be fed in chunks (streaming accumulators below).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace tnep {
@@ -29,6 +31,7 @@ namespace {
 constexpr int kB = 256;
 constexpr int kFftBlock = 64;      // FFT launches: small batches still spread over every compute unit
 constexpr int kStateBlock = 1024;  // k_stream_state: one work-group per signal
+constexpr int kBlkThreads = 256;   // blocked streaming transforms: 16 points per lane per pass
 
 struct cplx {
     double re, im;
@@ -432,6 +435,208 @@ __global__ void k_stream_combine(const double* __restrict__ run_sum, int nch, in
     acf[tau] = s * inv_runs;
 }
 
+// ---- streaming, blocked: 4096-point transforms inside one work-group ------
+// For max lags M <= kBlkMaxLag a chunk's new samples are split into blocks of
+// B = kBlkN - (M - 1).  Block [s0, s1) adds the pairs whose later sample lies
+// in it: with u = samples s0 - (M - 1) .. s1 - 1 (zero before the run's first
+// sample) and v = (M - 1 zeros | samples s0 .. s1 - 1), both kBlkN long,
+// IFFT(conj(U) V)[tau] / kBlkN = sum_s u(s) v(s + tau) for tau < M: a
+// circular wrap-around would need s + tau >= kBlkN + M - 1, beyond the last
+// sample of u plus the largest lag, so those lags are the linear ones.
+// u and v of a signal share one complex transform (z = u + i v, then
+// U(f) = (Z(f) + conj Z(-f)) / 2, V(f) = (Z(f) - conj Z(-f)) / 2i), and two
+// channels share one inverse transform (both correlations are real:
+// IFFT(P1 + i P2) = c1 + i c2).  Transforms run in LDS, so a block costs one
+// global read of its samples and one write of its spectrum or lags.
+
+// Element i of a transform lives at LDS index i + i / 16: the strided stores
+// of the first two radix-16 passes (stride 16 and 256 elements) then fall on
+// distinct banks.
+__device__ __forceinline__ int blk_pad(int i) { return i + (i >> 4); }
+
+// Unnormalised 4096-point transform of buf (padded layout) by the 256 threads
+// of the work-group, in place: three radix-16 Stockham passes (half spans m =
+// 1, 16, 256), each four radix-2 sub-stages with the butterflies and index
+// scheme of k_fft_radix<16> (thread t holds elements t + 256 a; every thread
+// reads its sixteen before any thread writes).  Twiddles exp(sign i pi K / M)
+// from tw[j] = exp(2 pi i j / kBlkN), j < kBlkN / 2, at j = K kBlkN / (2 M).
+__device__ __forceinline__ void blk_fft(cplx* buf, const cplx* __restrict__ tw, double sign) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int lm = 0; lm < 12; lm += 4) {
+        const int m = 1 << lm;
+        const int k = t & (m - 1), j = t >> lm;
+        cplx x[16], y[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) x[a] = buf[blk_pad(t + a * (kBlkN / 16))];
+        __syncthreads();
+#pragma unroll
+        for (int S = 1; S < 16; S <<= 1) {
+            const int Ms = S * m;
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                cplx w = tw[(k + c * m) * (kBlkN / (2 * Ms))];
+                w.im *= sign;
+#pragma unroll
+                for (int a = 0; a < 16 / (2 * S); ++a) {
+                    const cplx lo = x[c + S * a], hi = x[c + S * (a + 16 / (2 * S))];
+                    const cplx wh = cmul(w, hi);
+                    y[c + 2 * S * a] = {lo.re + wh.re, lo.im + wh.im};
+                    y[c + S + 2 * S * a] = {lo.re - wh.re, lo.im - wh.im};
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) x[i] = y[i];
+        }
+        const int o = j * 16 * m + k;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) buf[blk_pad(o + c * m)] = x[c];
+        __syncthreads();
+    }
+}
+
+__global__ void k_blk_twiddles(cplx* __restrict__ tw) {
+    const int j = blockIdx.x * kB + threadIdx.x;
+    if (j >= kBlkN / 2) return;
+    double sn, cs;
+    sincospi((double)j / (double)(kBlkN / 2), &sn, &cs);
+    tw[j] = {cs, sn};
+}
+
+// Signal g of one sample (a row of 3 or 9 components), as derive_signals.
+__device__ __forceinline__ double signal_value(int kind, int g, const double* row, double nx, double ny, double nz,
+                                               double ex, double ey, double ez) {
+    if (kind == 0 || kind == 4) return row[g];
+    const double gamma = (row[0] + row[4] + row[8]) / 3.0;
+    if (kind == 1) return gamma;
+    if (kind == 2) return row[g] - (g % 4 == 0 ? gamma : 0.0);
+    const double n[3] = {nx, ny, nz}, e[3] = {ex, ey, ez};
+    double p = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) p += n[a] * row[3 * a + b] * e[b];
+    return p;
+}
+
+struct BlkChunk {
+    const double* chunk;  // [n][comps]
+    int64_t n;
+    int comps, kind;
+    double nx, ny, nz, ex, ey, ez;
+    const double* carry;  // [nsig][carry_cap]: the last c samples before the chunk
+    int64_t carry_cap, c;
+    // sample p of the sequence (carry | chunk), 0 <= p < c + n
+    __device__ __forceinline__ double at(int g, int64_t p) const {
+        return p < c ? carry[(int64_t)g * carry_cap + p]
+                     : signal_value(kind, g, chunk + (p - c) * comps, nx, ny, nz, ex, ey, ez);
+    }
+};
+
+// grid (blocks of this launch [+ 1 state work-group], nsig), kBlkThreads lanes:
+// the spectrum Z of z = u + i v of block blk0 + blockIdx.x and signal
+// blockIdx.y into Zf[blockIdx.x][g]; with `state`, work-group x = nb also writes
+// the run state of signal g: the new carry (last min(M - 1, c + n) samples),
+// the run's first M samples and the run total.
+__global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(2))) k_blk_forward(BlkChunk ch, int64_t M, int64_t blk0, int64_t B, int nb,
+                                                             const cplx* __restrict__ tw, cplx* __restrict__ Zf,
+                                                             int state, double* __restrict__ carry_new,
+                                                             int64_t run_len, double* __restrict__ head,
+                                                             double* __restrict__ totals) {
+    __shared__ cplx buf[kBlkN + kBlkN / 16];
+    const int g = blockIdx.y, nsig = gridDim.y;
+    if ((int)blockIdx.x == nb) {
+        if (!state) return;
+        const int64_t L = ch.c + ch.n;
+        const int64_t keep = L < ch.carry_cap ? L : ch.carry_cap;
+        for (int64_t i = threadIdx.x; i < keep; i += kBlkThreads)
+            carry_new[(int64_t)g * ch.carry_cap + i] = ch.at(g, L - keep + i);
+        double acc = 0.0;
+        for (int64_t i = threadIdx.x; i < ch.n; i += kBlkThreads) {
+            const double v = ch.at(g, ch.c + i);
+            if (run_len + i < M) head[(int64_t)g * M + run_len + i] = v;
+            acc += v;
+        }
+        double* part = reinterpret_cast<double*>(buf);
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        for (int off = kBlkThreads / 2; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) totals[g] += part[0];
+        return;
+    }
+    const int64_t s0 = ch.c + (blk0 + blockIdx.x) * B;
+    const int64_t s1 = s0 + B < ch.c + ch.n ? s0 + B : ch.c + ch.n;
+    const int64_t base = s0 - (M - 1);
+    for (int i = threadIdx.x; i < kBlkN; i += kBlkThreads) {
+        const int64_t p = base + i;
+        const double val = (p >= 0 && p < s1) ? ch.at(g, p) : 0.0;
+        buf[blk_pad(i)] = {val, i >= M - 1 ? val : 0.0};
+    }
+    __syncthreads();
+    blk_fft(buf, tw, -1.0);
+    cplx* out = Zf + ((int64_t)blockIdx.x * nsig + g) * kBlkN;
+    for (int f = threadIdx.x; f < kBlkN; f += kBlkThreads) out[f] = buf[blk_pad(f)];
+}
+
+// grid (blocks, ceil(nch / 2)): channels 2q and 2q + 1 of a block, from the
+// signal spectra: P = conj(U_x) V_y (symmetric channels (conj(U_x) V_y +
+// conj(U_y) V_x) / 2), one inverse transform of P1 + i P2, lags tau < M of
+// both divided by kBlkN into part[block][ch].
+__global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(2))) k_blk_inverse(const cplx* __restrict__ Zf, int nsig,
+                                                             const int32_t* __restrict__ chx,
+                                                             const int32_t* __restrict__ chy,
+                                                             const int32_t* __restrict__ chsym, int nch, int64_t M,
+                                                             const cplx* __restrict__ tw, double* __restrict__ part) {
+    __shared__ cplx buf[kBlkN + kBlkN / 16];
+    const int ch1 = 2 * blockIdx.y, ch2 = ch1 + 1;
+    const cplx* Z = Zf + (int64_t)blockIdx.x * nsig * kBlkN;
+    auto U = [&](int x, int f, int fm) {
+        const cplx a = Z[(int64_t)x * kBlkN + f], b = Z[(int64_t)x * kBlkN + fm];
+        return cplx{0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
+    };
+    auto V = [&](int x, int f, int fm) {
+        const cplx a = Z[(int64_t)x * kBlkN + f], b = Z[(int64_t)x * kBlkN + fm];
+        return cplx{0.5 * (a.im + b.im), -0.5 * (a.re - b.re)};
+    };
+    auto power = [&](int q, int f, int fm) {
+        const int x = chx[q], y = chy[q];
+        const cplx ux = U(x, f, fm), vy = V(y, f, fm);
+        cplx z = {ux.re * vy.re + ux.im * vy.im, ux.re * vy.im - ux.im * vy.re};
+        if (chsym[q]) {
+            const cplx uy = U(y, f, fm), vx = V(x, f, fm);
+            z.re = 0.5 * (z.re + uy.re * vx.re + uy.im * vx.im);
+            z.im = 0.5 * (z.im + uy.re * vx.im - uy.im * vx.re);
+        }
+        return z;
+    };
+    for (int f = threadIdx.x; f < kBlkN; f += kBlkThreads) {
+        const int fm = (kBlkN - f) & (kBlkN - 1);
+        const cplx p1 = power(ch1, f, fm);
+        const cplx p2 = ch2 < nch ? power(ch2, f, fm) : cplx{0.0, 0.0};
+        buf[blk_pad(f)] = {p1.re - p2.im, p1.im + p2.re};
+    }
+    __syncthreads();
+    blk_fft(buf, tw, 1.0);
+    const double scale = 1.0 / (double)kBlkN;
+    double* o1 = part + ((int64_t)blockIdx.x * nch + ch1) * M;
+    for (int64_t tau = threadIdx.x; tau < M; tau += kBlkThreads) {
+        const cplx v = buf[blk_pad((int)tau)];
+        o1[tau] = v.re * scale;
+        if (ch2 < nch) o1[M + tau] = v.im * scale;
+    }
+}
+
+// S[ch][tau] += sum over the launch's blocks, in block order, of part[block][ch][tau]
+__global__ void k_blk_accum(const double* __restrict__ part, int nb, int nch, int64_t M, double* __restrict__ S) {
+    const int64_t tau = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (tau >= M) return;
+    const int ch = blockIdx.y;
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += part[((int64_t)b * nch + ch) * M + tau];
+    S[(int64_t)ch * M + tau] += acc;
+}
+
 __global__ void k_scale(const double* __restrict__ a, int64_t n, double f, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (i < n) out[i] = a[i] * f;
@@ -613,6 +818,43 @@ hipError_t launch_stream_push(const StreamState& st, const double* d_chunk, int6
     cplx* d = Z2;
     fft_batch(c, d, P, (unsigned)st.nch, 1.0, s);
     k_stream_accum<<<dim3(nblk(st.M), (unsigned)st.nch), kB, 0, s>>>(c, P, st.M, st.S);
+    return hipGetLastError();
+}
+
+size_t stream_blk_twiddle_bytes() { return sizeof(cplx) * (kBlkN / 2); }
+
+hipError_t launch_stream_twiddles(void* tw, hipStream_t s) {
+    k_blk_twiddles<<<nblk(kBlkN / 2), kB, 0, s>>>((cplx*)tw);
+    return hipGetLastError();
+}
+
+size_t stream_blk_workspace_bytes(int nsig, int nch, int64_t M, int64_t n) {
+    const int64_t B = kBlkN - (M - 1);
+    const size_t nbr = (size_t)std::min<int64_t>((n + B - 1) / B, kBlkRound);
+    return sizeof(cplx) * nbr * nsig * kBlkN + 256 + sizeof(double) * nbr * nch * (size_t)M + 256;
+}
+
+hipError_t launch_stream_push_blocked(const StreamState& st, const double* d_chunk, int64_t n, void* d_work,
+                                      hipStream_t s) {
+    const int64_t M = st.M, B = kBlkN - (M - 1);
+    const int64_t nb_all = (n + B - 1) / B;
+    const size_t nbr = (size_t)std::min<int64_t>(nb_all, kBlkRound);
+    cplx* Zf = (cplx*)d_work;
+    double* part = (double*)((char*)d_work + ((sizeof(cplx) * nbr * st.nsig * kBlkN + 255) & ~(size_t)255));
+    const BlkChunk ch{d_chunk, n, st.kind == 0 ? 3 : 9, st.kind, st.n_hat[0], st.n_hat[1], st.n_hat[2],
+                      st.e_hat[0], st.e_hat[1], st.e_hat[2], st.carry, st.carry_cap, st.carry_len};
+    const cplx* tw = (const cplx*)st.blk_tw;
+    const unsigned npair = (unsigned)((st.nch + 1) / 2);
+    for (int64_t b0 = 0; b0 < nb_all; b0 += kBlkRound) {
+        const int nb = (int)std::min<int64_t>(nb_all - b0, kBlkRound);
+        const int state = b0 == 0 ? 1 : 0;
+        k_blk_forward<<<dim3(nb + state, st.nsig), kBlkThreads, 0, s>>>(ch, M, b0, B, nb, tw, Zf, state,
+                                                                         st.carry_next, st.run_len, st.head,
+                                                                         st.totals);
+        k_blk_inverse<<<dim3(nb, npair), kBlkThreads, 0, s>>>(Zf, st.nsig, st.chx, st.chy, st.chsym, st.nch, M, tw,
+                                                               part);
+        k_blk_accum<<<dim3(nblk(M), st.nch), kB, 0, s>>>(part, nb, st.nch, M, st.S);
+    }
     return hipGetLastError();
 }
 

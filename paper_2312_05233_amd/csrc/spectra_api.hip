@@ -175,7 +175,10 @@ extern "C" int tnep_acf_stream_create(tnep_ctx* ctx, int32_t kind, int64_t max_l
         tnep_acf_stream_free(s);
         return code;
     };
-    if ((e = c->reserve(s->tables, nch * (3 * sizeof(int32_t) + sizeof(double)) + 64))) return fail_free(e);
+    const bool blocked = max_lag <= kBlkMaxLag;
+    const size_t tab_bytes = (nch * (3 * sizeof(int32_t) + sizeof(double)) + 255) & ~(size_t)255;
+    if ((e = c->reserve(s->tables, tab_bytes + (blocked ? stream_blk_twiddle_bytes() : 0) + 64)))
+        return fail_free(e);
     if ((e = c->reserve(s->carry_a, sizeof(double) * nsig * st.carry_cap))) return fail_free(e);
     if ((e = c->reserve(s->carry_b, sizeof(double) * nsig * st.carry_cap))) return fail_free(e);
     if ((e = c->reserve(s->head, sizeof(double) * nsig * M))) return fail_free(e);
@@ -195,6 +198,7 @@ extern "C" int tnep_acf_stream_create(tnep_ctx* ctx, int32_t kind, int64_t max_l
     st.chx = (const int32_t*)(d + nch * 8);
     st.chy = (const int32_t*)(d + nch * 12);
     st.chsym = (const int32_t*)(d + nch * 16);
+    st.blk_tw = blocked ? (const void*)(d + tab_bytes) : nullptr;
     st.carry = (double*)s->carry_a.p;
     st.carry_next = (double*)s->carry_b.p;
     st.head = (double*)s->head.p;
@@ -204,7 +208,8 @@ extern "C" int tnep_acf_stream_create(tnep_ctx* ctx, int32_t kind, int64_t max_l
     st.carry_len = 0;
     st.run_len = 0;
     st.n_runs = 0;
-    hipError_t he = launch_fill_zero(st.S, (int64_t)(nch * M), c->stream);
+    hipError_t he = blocked ? launch_stream_twiddles(d + tab_bytes, c->stream) : hipSuccess;
+    if (he == hipSuccess) he = launch_fill_zero(st.S, (int64_t)(nch * M), c->stream);
     if (he == hipSuccess) he = launch_fill_zero(st.run_sum, (int64_t)(nch * M), c->stream);
     if (he == hipSuccess) he = launch_fill_zero(st.totals, (int64_t)nsig, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
@@ -224,9 +229,14 @@ extern "C" int tnep_acf_stream_push(tnep_acf_stream* s, const double* samples, i
     (void)hipGetLastError();
     StreamState& st = s->st;
     const int comps = st.kind == TNEP_IR ? 3 : 9;
-    const int64_t P = fft_len_for(st.carry_len + n_samples + st.M);
+    // max lags up to kBlkMaxLag: blocks of kBlkN-point transforms in LDS;
+    // longer lags: one zero-padded transform of the whole chunk
+    const bool blocked = st.blk_tw != nullptr;
+    const int64_t P = blocked ? 0 : fft_len_for(st.carry_len + n_samples + st.M);
     int e;
-    if ((e = c->reserve(s->work, stream_push_workspace_bytes(st.nsig, st.nch, P)))) return e;
+    if ((e = c->reserve(s->work, blocked ? stream_blk_workspace_bytes(st.nsig, st.nch, st.M, n_samples)
+                                         : stream_push_workspace_bytes(st.nsig, st.nch, P))))
+        return e;
     const double* d_chunk = samples;
     if (location == TNEP_HOST) {
         const size_t bytes = sizeof(double) * (size_t)n_samples * comps;
@@ -235,7 +245,8 @@ extern "C" int tnep_acf_stream_push(tnep_acf_stream* s, const double* samples, i
         d_chunk = (const double*)s->chunk.p;
     }
     const int tr = c->timer_begin(TNEP_KERNEL_SPECTRUM);
-    HIP_CHECK_RET(c, launch_stream_push(st, d_chunk, n_samples, P, s->work.p, c->stream));
+    HIP_CHECK_RET(c, blocked ? launch_stream_push_blocked(st, d_chunk, n_samples, s->work.p, c->stream)
+                             : launch_stream_push(st, d_chunk, n_samples, P, s->work.p, c->stream));
     c->timer_end(tr);
     // device chunks: no wait, so that consecutive pushes queue back to back
     // (the run state is device-resident and the kernels run in stream order)

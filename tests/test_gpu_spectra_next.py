@@ -142,6 +142,32 @@ def test_stream_long_runs_and_device_chunks(gpu_lib, ctx):
     assert rng is not None
 
 
+def test_stream_blocks_and_long_lags(gpu_lib, ctx):
+    """Max lags up to 2048 split each chunk into blocks of 4096 - (M - 1) new
+    samples, 32 blocks per launch round: one 70,000-sample push at M = 2048
+    takes two rounds (35 blocks).  Longer lags (M = 2500) take one padded
+    transform per chunk.  Both against the oracle's direct lag sums."""
+    rng = np.random.default_rng(50)
+    for M, sizes in ((2048, [70000, 3, 5000]), (2500, [1, 4000, 999, 3000])):
+        runs = [_alpha_series(1, sum(sizes), 51 + M)[0], _alpha_series(1, 2 * M + 7, 52 + M)[0]]
+        st = gpu_lib.AcfStream(ctx, 1, M, flags=1)
+        for r, chunks in zip(runs, (sizes, [len(runs[1])])):
+            pos = 0
+            for sz in chunks:
+                st.push(r[pos:pos + sz])
+                pos += sz
+            st.end_run()
+        _, S, a = st.spectrum(2.0)
+        st.close()
+        _, Sr, Cr = oracle.spectrum(runs, 1, 2.0, M, subtract_mean=True)
+        err = spectrum_error(S, Sr)
+        acf_err = np.abs(a - Cr).max() / np.abs(Cr).max()
+        print(f"max lag {M}: spectrum {err:.2e} acf {acf_err:.2e}", flush=True)
+        assert acf_err <= 1e-9
+        assert err <= SPECTRUM_TOL
+    assert rng is not None
+
+
 def test_stream_errors(gpu_lib, ctx):
     st = gpu_lib.AcfStream(ctx, 1, 50)
     st.push(np.zeros((20, 9)))
