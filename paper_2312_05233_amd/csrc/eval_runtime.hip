@@ -576,6 +576,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 int n_cells = 0;
                 int64_t n_ref_atoms = 0;
                 bool followers = false, triclinic = false;
+                bool small_frames = false, large_frames = false;  // frame-sum kernels the batch needs
                 int ref_k = -1;  // reference frame of the open window
                 for (int k = 0; k < nf; ++k) {
                     const int f = f0 + k;
@@ -583,6 +584,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     std::memset(&x, 0, sizeof(x));
                     x.atom_begin = meta.offs[f] - a0;
                     x.n_atoms = (int32_t)(meta.offs[f + 1] - meta.offs[f]);
+                    (x.n_atoms <= kSmallFrame ? small_frames : large_frames) = true;
                     x.role = kRolePlain;
                     if (reuse && eligible[f]) {
                         const FrameInfo* r = ref_k >= 0 ? &fi[ref_k] : nullptr;
@@ -743,7 +745,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);
                         he = launch_frame_reduce((const FrameInfo*)c->frames.p, cap_frames, nl.meta, pa_of[q],
                                                  nt_of[q], na_of[q], (double*)c->red_part.p, out_of[q], aux_of[q],
-                                                 c->stream);
+                                                 small_frames, large_frames, c->stream);
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;
                         if (m->kind == TNEP_KIND_PES) {
@@ -773,6 +775,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         key += pb;
                     }
                     if (triclinic) key += "/tric";
+                    // which frame-sum kernels run (frames of at most / above kSmallFrame atoms)
+                    key += small_frames ? (large_frames ? "/s11" : "/s10") : "/s01";
                     if ((e = replay_graph(c, key, launch_batch)))
                         return e;
                 } else {

@@ -231,10 +231,14 @@ hipError_t launch_count_pairs(const NeighborLists& nl, unsigned long long* count
 // values 0..na-1 go to out_a[f][na], values na..nt-1 to out_b[f][nt - na]
 // (out_b may be NULL).  Frames beyond meta[kMetaNFrames] are skipped
 // (cap_frames sizes the grid).  part: scratch of kReduceChunks * 10 doubles
-// per frame.
+// per frame.  Frames of at most kSmallFrame atoms are summed by one wavefront
+// each, larger ones in kReduceChunks chunks; small / large: whether the batch
+// holds frames of that class (the other kernel is not launched).
 constexpr int kReduceChunks = 4;
+constexpr int kSmallFrame = 256;
 hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const int32_t* meta, const double* per_atom,
-                               int nt, int na, double* part, double* out_a, double* out_b, hipStream_t s);
+                               int nt, int na, double* part, double* out_a, double* out_b, bool small, bool large,
+                               hipStream_t s);
 
 // ---- spectra (kernels_spectrum.hip) ----
 struct SpectrumPlan {

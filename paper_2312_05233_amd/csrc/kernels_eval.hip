@@ -603,11 +603,50 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 // Frame sums in two steps.  k_frame_reduce: work-group (f, c) sums chunk c of
 // frame f (atoms [c L, (c + 1) L), L = ceil(n / kReduceChunks)): lane l takes
 // atoms l, l + 256, ... of the chunk in FP64, then a fixed tree, within each
-// wavefront by shuffles and over the 4 wavefronts in LDS.  k_frame_finish adds
-// the chunk sums in chunk order.  The order depends only on the frame's atom
-// count, never on how frames were batched; the chunks spread a launch batch of
-// large frames over all compute units.
+// wavefront by shuffles and over the 4 wavefronts in LDS.  Frames of at most
+// kSmallFrame atoms are left to k_frame_reduce_small: one wavefront per frame,
+// lane l takes atoms l, l + 64, ..., then the shuffle tree; it stores the sum
+// as chunk 0 and zeros as chunks 1..3.  k_frame_finish adds the chunk sums in
+// chunk order.  The order depends only on the frame's atom count, never on
+// how frames were batched; the chunks spread a launch batch of large frames
+// over all compute units, and a batch of small frames takes one wavefront,
+// not sixteen, per frame.
 constexpr int kReduceBlock = 256;
+__global__ void __launch_bounds__(kReduceBlock) k_frame_reduce_small(const FrameInfo* __restrict__ frames,
+                                                                     const int32_t* __restrict__ meta,
+                                                                     const double* __restrict__ per_atom, int nt,
+                                                                     double* __restrict__ part_out) {
+    const int f = blockIdx.x * (kReduceBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (f >= meta[kMetaNFrames]) return;
+    const FrameInfo fi = frames[f];
+    if (fi.n_atoms > kSmallFrame) return;
+    double s[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) s[k] = 0.0;
+    for (int64_t a = lane; a < fi.n_atoms; a += 64) {
+        const double* q = per_atom + (fi.atom_begin + a) * nt;
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            if (k < nt) s[k] += q[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        if (k < nt) {
+            double v = s[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            s[k] = v;
+        }
+    }
+    if (lane < kReduceChunks) {
+        double* o = part_out + ((int64_t)f * kReduceChunks + lane) * 10;
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            if (k < nt) o[k] = lane == 0 ? s[k] : 0.0;
+    }
+}
+
 __global__ void __launch_bounds__(kReduceBlock) k_frame_reduce(const FrameInfo* __restrict__ frames,
                                                                const int32_t* __restrict__ meta,
                                                                const double* __restrict__ per_atom, int nt,
@@ -617,6 +656,7 @@ __global__ void __launch_bounds__(kReduceBlock) k_frame_reduce(const FrameInfo* 
     const int f = blockIdx.x, c = blockIdx.y;
     if (f >= meta[kMetaNFrames]) return;
     const FrameInfo fi = frames[f];
+    if (fi.n_atoms <= kSmallFrame) return;
     const int64_t len = (fi.n_atoms + kReduceChunks - 1) / kReduceChunks;
     const int64_t a0 = c * len, a1 = min((int64_t)fi.n_atoms, a0 + len);
     const int lane = threadIdx.x;
@@ -926,9 +966,14 @@ hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborList
 }
 
 hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const int32_t* meta, const double* per_atom,
-                               int nt, int na, double* part, double* out_a, double* out_b, hipStream_t s) {
+                               int nt, int na, double* part, double* out_a, double* out_b, bool small, bool large,
+                               hipStream_t s) {
     if (cap_frames == 0) return hipSuccess;
-    k_frame_reduce<<<dim3(cap_frames, kReduceChunks), kReduceBlock, 0, s>>>(d_frames, meta, per_atom, nt, part);
+    if (small)
+        k_frame_reduce_small<<<(unsigned)((cap_frames + kReduceBlock / 64 - 1) / (kReduceBlock / 64)), kReduceBlock, 0,
+                               s>>>(d_frames, meta, per_atom, nt, part);
+    if (large)
+        k_frame_reduce<<<dim3(cap_frames, kReduceChunks), kReduceBlock, 0, s>>>(d_frames, meta, per_atom, nt, part);
     const int64_t n = (int64_t)cap_frames * nt;
     k_frame_finish<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(meta, part, nt, na, out_a, out_b);
     return hipGetLastError();

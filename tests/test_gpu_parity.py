@@ -113,6 +113,34 @@ def test_deterministic_and_batch_invariant(gpu_lib, ctx):
     c2.close()
 
 
+def test_frame_sums_small_and_large_frames(gpu_lib, ctx):
+    """Frames of up to 256 atoms are summed by one wavefront each, larger ones in
+    four chunks: frames on both sides of the bound (1 to 300 atoms) in one batch
+    equal the oracle and, bitwise, each frame evaluated alone, with plain
+    launches and with graph replay."""
+    rng = np.random.default_rng(81)
+    sizes = [255, 256, 257, 64, 1, 300]
+    parts = [synth.molecule(rng, n) for n in sizes]
+    offs = np.zeros(len(sizes) + 1, np.int64)
+    offs[1:] = np.cumsum(sizes)
+    fr = synth.Frames(offs, np.concatenate([p for p, _ in parts]),
+                      np.concatenate([s for _, s in parts]).astype(np.int32), None, None)
+    m = synth.model("molecule_polarizability")
+    mdl = gpu_lib.Model(ctx, m)
+    a = gpu_lib.tnep_eval_polarizability(ctx, mdl, fr)
+    _check(a, m, fr, "frames of 1-300 atoms")
+    for i in range(len(sizes)):
+        assert np.array_equal(gpu_lib.tnep_eval_polarizability(ctx, mdl, fr.subset([i]))[0], a[i]), sizes[i]
+    c2 = gpu_lib.Context(0)
+    c2.set_option(gpu_lib.OPT_GRAPHS, 1)
+    mdl2 = gpu_lib.Model(c2, m)
+    for _ in range(3):
+        assert np.array_equal(gpu_lib.tnep_eval_polarizability(c2, mdl2, fr), a)
+    assert np.array_equal(gpu_lib.tnep_eval_polarizability(c2, mdl2, fr.subset([1, 2]))[1], a[2])
+    mdl2.close()
+    c2.close()
+
+
 def test_frame_larger_than_launch_batch(gpu_lib, ctx):
     """A frame larger than the launch-batch size runs in a batch of its own;
     results equal the default batching bitwise."""
