@@ -608,6 +608,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                     int4 cur[kCand];
 #pragma unroll
                     for (int u = 0; u < kCand; ++u) cur[u] = cell_rec[slot_at(min(q + u, n - 1))];
+                    // all loads issued before the first use (else the compiler waits on
+                    // the first two before it issues the others)
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int u = 0; u < kCand; ++u) {
                         const int4 cr = cur[u];
