@@ -228,7 +228,7 @@ int fetch_meta(Ctx* c, const tnep_frames& fr, HostMeta& m) {
 int64_t BatchBytes::per_atom() const {
     // tile slots: entries, counts, perm, FP64 positions + cell records, radial sums
     const int64_t per_slot = (int64_t)slots * 16 + 8 * T + 4 + 48 + 4 * T * kRadialTerms +
-                             (pes_rec_stride > 0 ? 4 * (int64_t)pes_rec_stride + (int64_t)slots * 16 : 0);
+                             (pes_rec_stride > 0 ? 4 * (int64_t)pes_rec_stride + (int64_t)slots * 20 : 0);
     // per atom: frame_of, slot_of, key_of, bucket_atoms; per-atom records; staged inputs
     const int64_t per_atom = 16 + 80 * (int64_t)n_models + (host ? 28 : 0) + (pes_rec_stride > 0 && host ? 32 : 0);
     return per_slot + per_atom;
@@ -530,6 +530,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if (pes) {
                 if ((e = c->reserve(c->pes_rec, (size_t)n_pad_max * rec_stride * sizeof(float)))) return e;
                 if ((e = c->reserve(c->pes_pair, (size_t)n_pad_max * slots * sizeof(float4)))) return e;
+                if ((e = c->reserve(c->pes_slot, (size_t)n_pad_max * slots * sizeof(int32_t)))) return e;
                 if (fr.location == TNEP_HOST && (e = c->reserve(c->pes_stage, (size_t)B_res * 4 * sizeof(double))))
                     return e;
             }
@@ -717,7 +718,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         }
                     }
                 }
-                const PesOut pes_out{(float*)c->pes_rec.p, rec_stride, (float4*)c->pes_pair.p};
+                const PesOut pes_out{(float*)c->pes_rec.p, rec_stride, (float4*)c->pes_pair.p, (int32_t*)c->pes_slot.p};
                 // the batch's kernels; with graphs on, captured once and replayed
                 auto launch_batch = [&]() -> hipError_t {
                     hipError_t he;

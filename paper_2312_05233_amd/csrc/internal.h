@@ -184,12 +184,15 @@ struct EvalLaunch {
 //   [T * KRP + d]   sum_j dU_a/dr_aj, component d < 3
 // and, for every entry of an angular segment (r_aj < r_c^A), the pair force
 // dU_a/dr_aj at the entry's place in `pair` (same layout as the neighbour
-// entries).  From these the second kernel forms, for every pair (k, j), the
-// term that U_j contributes to the force on k.
+// entries) and the neighbour's slot at the same index of `slot` (four rows of
+// a lane in one 16-byte word, so that a lookup reads four rows at once).  From
+// these the second kernel forms, for every pair (k, j), the term that U_j
+// contributes to the force on k.
 struct PesOut {
     float* rec;
     int32_t rec_stride;
     float4* pair;
+    int32_t* slot;
 };
 inline int pes_rec_stride(const Shape& s, int T) { return T * ((s.kr + 3) / 4 * 4) + 4; }
 

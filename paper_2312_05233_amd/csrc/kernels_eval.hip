@@ -196,14 +196,15 @@ __host__ __device__ constexpr int mlp_lds_floats(int D, int H) {
 // FP32 vector ALU (no LDS) or one of the matrix-core variants (LDS tile per
 // wavefront).  Padding lanes run with empty neighbour lists and store nothing.
 // LOAD: the radial descriptor sums come from rad_v (the neighbour search
-// accumulated them); otherwise the kernel forms them.  pes_rec and pes_pair
-// (the potential-energy outputs of PesOut) are restrict parameters, so that
+// accumulated them); otherwise the kernel forms them.  pes_rec, pes_pair and
+// pes_slot (the potential-energy outputs of PesOut) are restrict parameters, so that
 // their stores cannot clobber the model's parameters and these stay
 // wave-uniform scalar loads.
 template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE, bool LOAD = false>
 __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, double* __restrict__ per_atom,
                                                  PesOut pes, const float* __restrict__ rad_v,
-                                                 float* __restrict__ pes_rec, float4* __restrict__ pes_pair) {
+                                                 float* __restrict__ pes_rec, float4* __restrict__ pes_pair,
+                                                 int32_t* __restrict__ pes_slot) {
     constexpr bool FOURB = (MB & 1) != 0, FIVEB = (MB & 2) != 0;
     constexpr int D = NR + 4 * NA + (FOURB ? NA : 0) + (FIVEB ? NA : 0);
     constexpr int NT = KIND == 1 ? 3 : 9;  // accumulated tensor: mu, or the virial-like W
@@ -447,6 +448,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 #pragma unroll
     for (int k = 0; k < NT; ++k) acc[k] = 0.f;
     float own[3] = {0.f, 0.f, 0.f};  // potential: sum_j dU_i/dr_ij, the atom's own force term
+    int sq0 = -1, sq1 = -1, sq2 = -1, sq3 = -1;  // potential: slots of the current group of angular rows
     // (Fx, Fy, Fz) = dU_i/dr_ij for the pair vector (dx, dy, dz)
     auto contract = [&](float dx, float dy, float dz, float r2, float Fx, float Fy, float Fz) {
         if constexpr (KIND == 3) {
@@ -567,7 +569,19 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float fx = Fx * rinv + ux * su, fy = Fy * rinv + uy * su, fz = Fz * rinv + uz * su;
             contract(e.x, e.y, e.z, r2, fx, fy, fz);
             if constexpr (KIND == 3) {
-                if (a >= 0) pes_pair[(ga - nl.entries) + ((s >> 2) * 256 + (s & 3))] = make_float4(fx, fy, fz, 0.f);
+                if (a >= 0) {
+                    const int u = s & 3;
+                    const int64_t at = (ga - nl.entries) + ((s >> 2) * 256 + u);
+                    pes_pair[at] = make_float4(fx, fy, fz, 0.f);
+                    // the slots of a group of four rows leave as one 16-byte store
+                    const int v = __float_as_int(e.w);
+                    sq0 = u == 0 ? v : sq0;
+                    sq1 = u == 1 ? v : sq1;
+                    sq2 = u == 2 ? v : sq2;
+                    sq3 = u == 3 ? v : sq3;
+                    if (u == 3 || s + 1 == n_ang)
+                        *reinterpret_cast<int4*>(pes_slot + (at - u)) = make_int4(sq0, sq1, sq2, sq3);
+                }
             }
         }
         nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -744,7 +758,8 @@ constexpr int kLookups = 8;
 // the lane of atom k takes, for every neighbour j:
 //   r_kj < r_c^A: the pair force dU_j/dr_jk that j's evaluation stored at k's
 //     entry in j's angular segment of k's species; the lane finds that entry by
-//     its slot (the segment holds ~10-20 entries, read in 64-byte groups);
+//     its slot (the segment holds ~10-20 entries; j's evaluation also stored the
+//     entries' slots compactly, four rows per 16-byte load);
 //   otherwise: the radial part sum_k' Dk_j[k'] f'_k'(r) from j's record with
 //     j's coefficients c_{t_j t_k} (48 bytes and ~60 instructions per pair).
 // A pair that j's search classified on the other side of r_c^A (rounding at
@@ -804,9 +819,9 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
         const float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
         const float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
         // kLookups pairs at a time: the loads of their lookups (the neighbour's count
-        // and the slot fields of the first four rows of its segment, in bounds since
-        // segment capacities are multiples of four) are issued before any is used
-        const int* __restrict__ slots_of = reinterpret_cast<const int*>(nl.entries);
+        // and the slots of the first four rows of its segment, one 16-byte word, in
+        // bounds since segment capacities are multiples of four) are issued before any
+        // is used
         for (int s = 0; s < n_ang; s += kLookups) {
             float4 e[kLookups];
             int g[kLookups][4];
@@ -820,8 +835,11 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
                 // j's angular segment of species t_k, searched for this lane's slot
                 ja[w] = ((int64_t)(j >> 6) * (nl.slots >> 2) * 64 + (j & 63)) * 4 + seg_a_k;
                 nj[w] = s + w < n_ang ? nl.counts[(int64_t)(2 * tk) * nl.n_pad + j] : 0;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) g[w][u] = slots_of[4 * (ja[w] + u) + 3];
+                const int4 q = *reinterpret_cast<const int4*>(pes.slot + ja[w]);
+                g[w][0] = q.x;
+                g[w][1] = q.y;
+                g[w][2] = q.z;
+                g[w][3] = q.w;
             }
 #pragma unroll
             for (int w = 0; w < kLookups; ++w) {
@@ -830,10 +848,11 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
                 for (int u = 3; u >= 0; --u)
                     if (u < nj[w] && g[w][u] == (int)p) row[w] = u;
                 for (int r0 = 4; r0 < nj[w] && row[w] < 0; r0 += 4) {
-                    const float4* gg = nl.entries + ja[w] + (int64_t)(r0 >> 2) * 256;
+                    const int4 q = *reinterpret_cast<const int4*>(pes.slot + ja[w] + (int64_t)(r0 >> 2) * 256);
+                    const int gq[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-                        if (r0 + u < nj[w] && __float_as_int(gg[u].w) == (int)p) row[w] = r0 + u;
+                        if (r0 + u < nj[w] && gq[u] == (int)p) row[w] = r0 + u;
                 }
             }
             float4 f[kLookups];
@@ -875,14 +894,14 @@ hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom
         const unsigned grid = (unsigned)((nl.n_pad + bs - 1) / bs);
         if (rs.mode == 2 && KR == kRadialTerms)
             k_eval<NR, NA, KR, KA, MB, KIND, MODE, KR == kRadialTerms><<<grid, bs, 0, s>>>(m, nl, per_atom, pes, rs.v,
-                                                                                        pes.rec, pes.pair);
+                                                                                        pes.rec, pes.pair, pes.slot);
         else
-            k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom, pes, nullptr, pes.rec, pes.pair);
+            k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, bs, 0, s>>>(m, nl, per_atom, pes, nullptr, pes.rec, pes.pair, pes.slot);
     } else {
         // two wavefronts per work-group keep the LDS tiles at <= 2 x 27 KB
         const unsigned grid = (unsigned)((nl.n_pad + 127) / 128);
         const size_t lds = sizeof(float) * 2 * (size_t)mlp_lds_floats(D, m.n_hidden);
-        k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom, pes, nullptr, pes.rec, pes.pair);
+        k_eval<NR, NA, KR, KA, MB, KIND, MODE><<<grid, 128, lds, s>>>(m, nl, per_atom, pes, nullptr, pes.rec, pes.pair, pes.slot);
     }
     return hipGetLastError();
 }

@@ -64,7 +64,8 @@ struct Ctx {
     DevBuf frames, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, bucket_pos, perm_start;
     DevBuf perm, tile_base, scan_chunks, nbr, counts, per_atom, out, pos, species;
     DevBuf spec_work, spec_series, spec_out;
-    DevBuf pes_rec, pes_stage, pes_pair;  // potential-energy models: per-atom records, host-bound staging, pair forces
+    DevBuf pes_rec, pes_stage, pes_pair, pes_slot;  // potential-energy models: per-atom records, host-bound staging,
+                                                    // pair forces, slots of the angular entries
     DevBuf slot_of, cand, cand_count;  // tile slot per atom; trajectory candidate lists
     DevBuf com;                        // charged-dipole shift: staging of frames, masses, charges, mu
     DevBuf red_part;                   // frame sums: per-chunk partial sums
@@ -76,7 +77,7 @@ struct Ctx {
     std::vector<DevBuf*> all_buffers() {
         return {&frames,   &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
-                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &pes_pair, &slot_of, &cand, &cand_count, &com,
+                &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &pes_pair, &pes_slot, &slot_of, &cand, &cand_count, &com,
                 &pop_stage, &pop_work, &pop_img, &red_part, &rad_sums};
     }
 
