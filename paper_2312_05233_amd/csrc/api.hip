@@ -123,6 +123,7 @@ tnep::Ctx::~Ctx() {
     for (DevBuf* b : all_buffers()) release(*b);
     if (h_flags) (void)hipHostFree(h_flags);
     if (meta_host) (void)hipHostFree(meta_host);
+    if (rb_host) (void)hipHostFree(rb_host);
     if (pop_host) (void)hipHostFree(pop_host);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

@@ -210,11 +210,30 @@ int fetch_meta(Ctx* c, const tnep_frames& fr, HostMeta& m) {
         if (fr.cells) std::memcpy(m.cells.data(), fr.cells, sizeof(double) * 9 * F);
         if (fr.pbc) std::memcpy(m.pbc.data(), fr.pbc, 3 * (size_t)F);
     } else {
-        hipError_t e = hipMemcpy(m.offs.data(), fr.atom_offsets, sizeof(int64_t) * (F + 1), hipMemcpyDeviceToHost);
+        // through pinned memory (a pageable destination costs a staged copy), on the
+        // legacy default stream like a synchronous hipMemcpy, so that work the caller
+        // queued there first has completed
+        const size_t ob = sizeof(int64_t) * (F + 1), cb = fr.cells ? sizeof(double) * 9 * F : 0,
+                     pb = fr.pbc ? 3 * (size_t)F : 0;
+        const size_t need = ob + cb + pb;
+        hipError_t e = hipSuccess;
+        if (c->rb_host_bytes < need) {
+            if (c->rb_host) (void)hipHostFree(c->rb_host);
+            c->rb_host = nullptr;
+            c->rb_host_bytes = 0;
+            e = hipHostMalloc((void**)&c->rb_host, need, hipHostMallocDefault);
+            if (e == hipSuccess) c->rb_host_bytes = need;
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(c->rb_host, fr.atom_offsets, ob, hipMemcpyDeviceToHost, nullptr);
         if (e == hipSuccess && fr.cells)
-            e = hipMemcpy(m.cells.data(), fr.cells, sizeof(double) * 9 * F, hipMemcpyDeviceToHost);
-        if (e == hipSuccess && fr.pbc) e = hipMemcpy(m.pbc.data(), fr.pbc, 3 * (size_t)F, hipMemcpyDeviceToHost);
+            e = hipMemcpyAsync(c->rb_host + ob, fr.cells, cb, hipMemcpyDeviceToHost, nullptr);
+        if (e == hipSuccess && fr.pbc)
+            e = hipMemcpyAsync(c->rb_host + ob + cb, fr.pbc, pb, hipMemcpyDeviceToHost, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) return c->fail(TNEP_E_HIP, "reading frame metadata: %s", hipGetErrorString(e));
+        std::memcpy(m.offs.data(), c->rb_host, ob);
+        if (fr.cells) std::memcpy(m.cells.data(), c->rb_host + ob, cb);
+        if (fr.pbc) std::memcpy(m.pbc.data(), c->rb_host + ob + cb, pb);
     }
     if (m.offs[0] != 0) return c->fail(TNEP_E_INVALID, "atom_offsets[0] must be 0");
     for (int f = 0; f < F; ++f)
@@ -553,7 +572,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             // memory (alive until the sync below) so that their copies are
             // plain DMA: copies from pageable memory went through host-side
             // staging and left the device idle before every batch
-            const size_t fi_bytes = sizeof(FrameInfo) * (size_t)F, meta_need = fi_bytes + 16 * (size_t)F + 256;
+            const size_t fi_bytes = sizeof(FrameInfo) * (size_t)F, sizes_bytes = 16 * (size_t)F + 256;
+            const size_t meta_need = fi_bytes + sizes_bytes + sizeof(FrameTric) * (size_t)F;
             if (c->meta_host_bytes < meta_need) {
                 if (c->meta_host) (void)hipHostFree(c->meta_host);
                 c->meta_host = nullptr;
@@ -563,6 +583,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             }
             FrameInfo* fi_next = reinterpret_cast<FrameInfo*>(c->meta_host);
             int32_t* sizes_next = reinterpret_cast<int32_t*>(c->meta_host + fi_bytes);
+            FrameTric* tri_next = reinterpret_cast<FrameTric*>(c->meta_host + fi_bytes + sizes_bytes);
             int f0 = 0;
             while (f0 < F) {
                 int f1 = f0;
@@ -572,7 +593,9 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 const int64_t a0 = meta.offs[f0], na = meta.offs[f1] - a0;
                 FrameInfo* fi = fi_next;
                 int32_t* sizes = sizes_next;
+                FrameTric* tri = tri_next;
                 fi_next += nf;
+                tri_next += nf;
                 sizes_next += 4;
                 int n_cells = 0;
                 int64_t n_ref_atoms = 0;
@@ -625,10 +648,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     if (g.tric) {
                         triclinic = true;
                         for (int i = 0; i < 9; ++i) {
-                            x.H[i] = g.H[i];
-                            x.Hinv[i] = g.Hinv[i];
+                            tri[k].H[i] = g.H[i];
+                            tri[k].Hinv[i] = g.Hinv[i];
                         }
-                        for (int k = 0; k < 3; ++k) x.w[k] = g.w[k];
+                        for (int d = 0; d < 3; ++d) tri[k].w[d] = g.w[d];
                     }
                     x.cell_base = n_cells;
                     n_cells += g.mode == 1 ? g.n_cells() : 1;
@@ -640,6 +663,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 const int64_t n_buckets = cap_cells * T;
                 if (n_buckets >= ((int64_t)1 << 30)) return c->fail(TNEP_E_INVALID, "too many cells in one batch");
                 if ((e = c->reserve(c->frames, sizeof(FrameInfo) * cap_frames))) return e;
+                if (triclinic && (e = c->reserve(c->frames_tric, sizeof(FrameTric) * cap_frames))) return e;
                 if (n_ref_atoms > 0) {
                     if ((e = c->reserve(c->cand, (size_t)n_ref_atoms * T * c->cap_cand * 4))) return e;
                     if ((e = c->reserve(c->cand_count, (size_t)n_ref_atoms * T * 4))) return e;
@@ -660,6 +684,9 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                                 hipMemcpyHostToDevice, c->stream));
                 HIP_CHECK_RET(c, hipMemcpyAsync(c->frames.p, fi, sizeof(FrameInfo) * nf, hipMemcpyHostToDevice,
                                                 c->stream));
+                if (triclinic)
+                    HIP_CHECK_RET(c, hipMemcpyAsync(c->frames_tric.p, tri, sizeof(FrameTric) * nf, hipMemcpyHostToDevice,
+                                                    c->stream));
                 const double* pos;
                 const int32_t* spc;
                 if (fr.location == TNEP_HOST) {
@@ -723,7 +750,9 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 auto launch_batch = [&]() -> hipError_t {
                     hipError_t he;
                     int tr = c->timer_begin(TNEP_KERNEL_NEIGHBORS);
-                    he = launch_neighbors((const FrameInfo*)c->frames.p, cap_frames, pos, spc, cap_atoms,
+                    he = launch_neighbors((const FrameInfo*)c->frames.p,
+                                          triclinic ? (const FrameTric*)c->frames_tric.p : nullptr, cap_frames, pos,
+                                          spc, cap_atoms,
                                           (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl, cl,
                                           n_ref_atoms > 0, followers, triclinic, (int32_t*)c->flags.p,
                                           c->launch.neigh_block, (float*)c->rad_sums.p, c->stream);

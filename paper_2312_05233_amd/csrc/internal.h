@@ -38,16 +38,21 @@ struct FrameInfo {
     double Linv[3];      // 1 / L (periodic axes), else 0
     int64_t ref_begin;   // follower: atom_begin of its reference frame
     int64_t cl_base;     // reference / follower: first candidate list of the reference's atoms
-    // Triclinic cells (all axes periodic): lattice vectors as the rows of H,
-    // fractional coordinates s = r Hinv, cells binned in s, widths w[k] between
-    // opposite faces (>= 2 r_c).  tric = 0: orthorhombic or non-periodic.
+    // tric = 1: triclinic cell (all axes periodic), its lattice in the batch's
+    // FrameTric array at the frame's index; 0: orthorhombic or non-periodic.
     int32_t tric;
     int32_t pad_;
-    double H[9], Hinv[9], w[3];
-    // Cell grids: unit (a power of two; A, or fractional units for triclinic
-    // bins) of the fixed-point offsets from the cell origin in the candidate
-    // records.
+    // Triclinic bins: unit (a power of two, fractional units) of the fixed-point
+    // offsets from the bin origin in the candidate records.
     double q_unit;
+};
+
+// Lattice of a triclinic frame, kept apart from FrameInfo so that the frame
+// records of other frames stay small (they are copied to the device for every
+// launch batch): lattice vectors as the rows of H, fractional coordinates
+// s = r Hinv, cells binned in s, widths w[k] between opposite faces (>= 2 r_c).
+struct FrameTric {
+    double H[9], Hinv[9], w[3];
 };
 
 // Device-resident FP32 model parameters.
@@ -165,7 +170,8 @@ struct NeighborWork {
 // role has a pass over the slots of its own; followers run after the
 // reference frames' lists are complete).
 // triclinic: the batch has triclinic frames (a pass of their own).
-hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
+hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, int cap_frames, const double* pos,
+                            const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
                             bool triclinic, int32_t* d_flags, int neigh_block, float* rad_sums, hipStream_t s);

@@ -67,13 +67,15 @@ __device__ __forceinline__ int cell_coord(double p, double L, int nc) {
 }
 
 // key = (frame cell) * T + species; invalid atoms get key -1.
-__global__ void k_bin(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ frame_of,
+__global__ void k_bin(const FrameInfo* __restrict__ frames, const FrameTric* __restrict__ tric,
+                      const int32_t* __restrict__ frame_of,
                       const double* __restrict__ pos, const int32_t* __restrict__ species,
                       const int32_t* __restrict__ meta, int T, int32_t* __restrict__ key_of,
                       int32_t* __restrict__ bucket_count, int32_t* __restrict__ flags) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= meta[kMetaNAtoms]) return;
-    const FrameInfo& fi = frames[frame_of[a]];
+    const int f = frame_of[a];
+    const FrameInfo& fi = frames[f];
     const double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
     const int t = species[a];
     int err = 0;
@@ -90,7 +92,7 @@ __global__ void k_bin(const FrameInfo* __restrict__ frames, const int32_t* __res
         // triclinic: bins of the wrapped fractional coordinates s = r Hinv
         int b[3];
         for (int k = 0; k < 3; ++k) {
-            double sk = x * fi.Hinv[k] + y * fi.Hinv[3 + k] + z * fi.Hinv[6 + k];
+            double sk = x * tric[f].Hinv[k] + y * tric[f].Hinv[3 + k] + z * tric[f].Hinv[6 + k];
             sk -= floor(sk);
             const int q = (int)(sk * (double)fi.nc[k]);
             b[k] = q < 0 ? 0 : (q >= fi.nc[k] ? fi.nc[k] - 1 : q);
@@ -254,7 +256,8 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 // of two so the scaling is exact), and the cell's index along the third axis
 // (z, or the third lattice vector).  Frames without a grid keep the FP64 position
 // (triclinic ones: wrapped fractional coordinates).
-__global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ frame_of,
+__global__ void k_sort_place(const FrameInfo* __restrict__ frames, const FrameTric* __restrict__ tric,
+                             const int32_t* __restrict__ frame_of,
                              const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
                              const int32_t* __restrict__ bucket_atoms, const int32_t* __restrict__ perm_start,
                              int32_t* __restrict__ perm, int32_t* __restrict__ slot_of, const double* __restrict__ pos,
@@ -271,7 +274,8 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t
     perm[slot] = (int32_t)a;
     slot_of[a] = slot;
     double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
-    const FrameInfo& fi = frames[frame_of[a]];
+    const int f = frame_of[a];
+    const FrameInfo& fi = frames[f];
     if (fi.mode == 1) {
         const int local = k / T - fi.cell_base;
         const int ny = fi.nc[1], nz = fi.nc[2];
@@ -283,7 +287,7 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t
             double s, h;
             if (fi.tric) {
                 // wrapped fractional coordinate, as k_bin bins it
-                s = x * fi.Hinv[d] + y * fi.Hinv[3 + d] + z * fi.Hinv[6 + d];
+                s = x * tric[f].Hinv[d] + y * tric[f].Hinv[3 + d] + z * tric[f].Hinv[6 + d];
                 s -= floor(s);
                 h = 1.0 / fi.nc[d];
             } else {
@@ -302,7 +306,7 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const int32_t
         double sf[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            sf[q] = x * fi.Hinv[q] + y * fi.Hinv[3 + q] + z * fi.Hinv[6 + q];
+            sf[q] = x * tric[f].Hinv[q] + y * tric[f].Hinv[3 + q] + z * tric[f].Hinv[6 + q];
             sf[q] -= floor(sf[q]);
         }
         x = sf[0];
@@ -763,6 +767,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
 // than 2.5 r_c) take the minimum image by rounding, f -= rint(f): with every
 // width >= 2 r_c an image within r_c has all |f_k| < 1/2.
 __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __restrict__ frames,
+                                                          const FrameTric* __restrict__ tric,
                                                           const int32_t* __restrict__ frame_of,
                                                           const double* __restrict__ pos,
                                                           const int32_t* __restrict__ key_of,
@@ -783,6 +788,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
     const int fidx = frame_of[a];
     if (!frames[fidx].tric) return;
     const FrameInfo& fi = frames[fidx];
+    const FrameTric& ft = tric[fidx];
     const int tile = (int)(p >> 6), lane = (int)(p & 63);
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
@@ -792,12 +798,12 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
     const int nx = fi.nc[0], ny = fi.nc[1], nz = fi.nc[2];
     double H[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) H[q] = fi.H[q];
+    for (int q = 0; q < 9; ++q) H[q] = ft.H[q];
     // wrapped fractional coordinates of the atom
     double si[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        si[q] = xi * fi.Hinv[q] + yi * fi.Hinv[3 + q] + zi * fi.Hinv[6 + q];
+        si[q] = xi * ft.Hinv[q] + yi * ft.Hinv[3 + q] + zi * ft.Hinv[6 + q];
         si[q] -= floor(si[q]);
     }
     int ib[3] = {0, 0, 0};
@@ -813,9 +819,9 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_tri(const FrameInfo* __res
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double inv = 1.0 / (double)fi.nc[k];
-            lo[k] = (float)fmax((si[k] - ib[k] * inv) * fi.w[k], 0.0);
-            hi[k] = (float)fmax(((ib[k] + 1) * inv - si[k]) * fi.w[k], 0.0);
-            hb[k] = (float)(fi.w[k] * inv);
+            lo[k] = (float)fmax((si[k] - ib[k] * inv) * ft.w[k], 0.0);
+            hi[k] = (float)fmax(((ib[k] + 1) * inv - si[k]) * ft.w[k], 0.0);
+            hb[k] = (float)(ft.w[k] * inv);
         }
     }
     const float hb2_inv = mode == 1 ? 1.f / hb[2] : 0.f;
@@ -957,7 +963,8 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
-hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const double* pos, const int32_t* species,
+hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, int cap_frames, const double* pos,
+                            const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
                             bool triclinic, int32_t* d_flags, int neigh_block, float* rad_sums, hipStream_t s) {
@@ -969,7 +976,7 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
     k_frame_of<<<cap_frames, kBlock, 0, s>>>(d_frames, nl.meta, w.frame_of);
     k_fill_i32<<<blocks_for(cap_buckets, kBlock), kBlock, 0, s>>>(w.bucket_count, cap_buckets, 0);
     k_fill_i32<<<blocks_for(nl.n_pad, kBlock), kBlock, 0, s>>>(w.perm, nl.n_pad, -1);
-    k_bin<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, pos, species, nl.meta, T, w.key_of,
+    k_bin<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, d_tric, w.frame_of, pos, species, nl.meta, T, w.key_of,
                                                           w.bucket_count, d_flags);
     k_scan_partials<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk);
     k_scan_chunks<<<1, 256, 0, s>>>(w.chunk, T, w.chunk + 9 * cap_chunks, w.meta, w.bucket_start);
@@ -977,7 +984,7 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                            w.bucket_fill, w.perm_start);
     k_scatter<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill,
                                                               w.bucket_atoms, nl.meta);
-    k_sort_place<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, w.frame_of, w.key_of, w.bucket_start,
+    k_sort_place<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, d_tric, w.frame_of, w.key_of, w.bucket_start,
                                                                  w.bucket_atoms, w.perm_start, w.perm, w.slot_of, pos,
                                                                  w.bucket_pos, w.cell_rec, nl.meta, T);
     const size_t list_bytes = sizeof(float4) * 9 * nb;  // staging + per-wave flush lists
@@ -989,7 +996,7 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, int cap_frames, const dou
                                                                  w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
                                                                  rc_radial, rc_angular, nl, cl, d_flags, rad_sums);
     if (triclinic)
-        k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, w.key_of, w.perm_start,
+        k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, d_tric, w.frame_of, pos, w.key_of, w.perm_start,
                                                                w.bucket_pos, w.cell_rec, rc_radial, rc_angular, nl,
                                                                d_flags, rad_sums);
     if (followers)
