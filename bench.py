@@ -175,6 +175,16 @@ def bench_molecules(args):
     al = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
     step = lambda: tnep.tnep_eval_dipole_polarizability(ctx, gd, gp, dfr, mu, al)  # noqa: E731
     t = _timed(step, args.steps, args.warmup)
+    # the same call with its launch batch replayed as a HIP graph (TNEP_OPT_GRAPHS)
+    gctx = tnep.Context(0)
+    gctx.set_option(tnep.OPT_GRAPHS, 1)
+    ggd, ggp = tnep.Model(gctx, md), tnep.Model(gctx, mp)
+    gmu, gal = torch.zeros_like(mu), torch.zeros_like(al)
+    t_graph = _timed(lambda: tnep.tnep_eval_dipole_polarizability(gctx, ggd, ggp, dfr, gmu, gal), args.steps,
+                     args.warmup)
+    torch.cuda.synchronize()
+    graph_equal = bool(torch.equal(gmu, mu) and torch.equal(gal, al))
+    gctx.close()
     # kernel times and pair counts from an instrumented pass
     ctx.set_option(tnep.OPT_TIMING, 1)
     ctx.reset_timing()
@@ -191,7 +201,9 @@ def bench_molecules(args):
                       "config": {"workload": "8192 vacuum molecules, 20-80 atoms (%d atoms), C/H/N/O/F, dipole + "
                                              "polarizability" % frames.n_atoms},
                       "kernels_ms_per_step": kt, "mean_radial_neighbors": rad / atoms,
-                      "mean_angular_neighbors": ang / atoms}), flush=True)
+                      "mean_angular_neighbors": ang / atoms,
+                      "graph_replay": {"atom_frames_per_s": frames.n_atoms / t_graph, "ms_per_step": 1e3 * t_graph,
+                                       "bitwise_equal_to_plain": graph_equal}}), flush=True)
 
 
 def bench_pes(args):

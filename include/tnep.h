@@ -83,10 +83,12 @@ extern "C" {
 #define TNEP_OPT_MAX_BATCH_ATOMS 5 /* atoms per launch batch (default 2^20)       */
 #define TNEP_OPT_TIMING 6         /* 1 = time every launch with HIP events and count pairs */
 #define TNEP_OPT_NEIGH_BLOCK 7    /* work-group size of the neighbour kernel: 64, 128, 256 */
-#define TNEP_OPT_GRAPHS 8         /* 1 = for TNEP_HOST frames (timing off), capture each launch
-                                     batch's kernels once per signature (models, neighbour
-                                     capacities, launch sizes, power-of-two bucket of atoms,
-                                     frames and cells) as a HIP graph and replay it; results are
+#define TNEP_OPT_GRAPHS 8         /* 1 = (timing off) capture each launch batch's kernels once
+                                     per signature (models, neighbour capacities, launch sizes,
+                                     power-of-two bucket of atoms, frames and cells; for
+                                     TNEP_DEVICE frames also the device addresses of the call's
+                                     inputs and outputs, so a call on other buffers captures a
+                                     graph of its own) as a HIP graph and replay it; results are
                                      bitwise those of the plain launches.  Needs a non-null
                                      stream.  A call on a context must not overlap another
                                      call on the same context (as for every entry point). */

@@ -515,10 +515,11 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if (room > 0 && B * per_atom_bytes > room) B = std::max(largest, room / per_atom_bytes);
             // Graph replay: grids are sized for power-of-two capacities of the
             // batch's atoms, frames and cells; kernels read the actual sizes
-            // from meta.  Host-resident frames only (every address a kernel
-            // sees is then a work buffer of this context).
+            // from meta.  Host-resident frames: every address a kernel sees is a
+            // work buffer of this context; device-resident frames: the caller's
+            // input and output addresses are part of the graph key.
             const int64_t B_graph = pow2_at_least(std::max<int64_t>(B, 64));
-            const bool graphs = c->use_graphs && !c->timing && fr.location == TNEP_HOST && c->stream &&
+            const bool graphs = c->use_graphs && !c->timing && c->stream &&
                                 (room <= 0 || B_graph * per_atom_bytes <= room);
             const int64_t B_res = graphs ? B_graph : B;
             const int64_t n_pad_max = (B_res + 63) / 64 * 64 + 64 * T;
@@ -807,6 +808,20 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     if (triclinic) key += "/tric";
                     // which frame-sum kernels run (frames of at most / above kSmallFrame atoms)
                     key += small_frames ? (large_frames ? "/s11" : "/s10") : "/s01";
+                    // device-resident frames: the caller's buffers the kernels read and write
+                    if (fr.location == TNEP_DEVICE) {
+                        char db[64];
+                        snprintf(db, sizeof(db), "/d%p.%p", (const void*)pos, (const void*)spc);
+                        key += db;
+                        for (int q = 0; q < last - first; ++q) {
+                            snprintf(db, sizeof(db), "/o%p.%p.%p", (void*)out_of[q], (void*)pa_of[q], (void*)aux_of[q]);
+                            key += db;
+                        }
+                        if (pes) {
+                            snprintf(db, sizeof(db), "/f%p.%p", (void*)forces_dst, (void*)energies_dst);
+                            key += db;
+                        }
+                    }
                     if ((e = replay_graph(c, key, launch_batch)))
                         return e;
                 } else {

@@ -205,3 +205,63 @@ def test_skin_change_between_trajectory_replays(gpu_lib):
     assert captures >= 3
     for c in (plain, graph):
         c.close()
+
+
+def test_device_frames_replay_and_buffer_switch(gpu_lib):
+    """Device-resident frames replay a graph keyed by the call's device
+    addresses: the same buffers replay it (bitwise equal to plain launches);
+    other output tensors, other input tensors and a per-atom output each get a
+    graph of their own, the earlier buffers untouched."""
+    plain, graph = _ctx_pair(gpu_lib)
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    pd_, pp_ = gpu_lib.Model(plain, md), gpu_lib.Model(plain, mp)
+    gd_, gp_ = gpu_lib.Model(graph, md), gpu_lib.Model(graph, mp)
+    mols = synth.molecules(40, seed=61)
+    other = synth.molecules(40, seed=62)
+    dev, dev2 = gpu_lib.DeviceFrames(mols), gpu_lib.DeviceFrames(other)
+    F = mols.n_frames
+
+    def outs():
+        return (torch.zeros((F, 3), dtype=torch.float64, device="cuda"),
+                torch.zeros((F, 9), dtype=torch.float64, device="cuda"))
+
+    ref_mu, ref_al = outs()
+    gpu_lib.tnep_eval_dipole_polarizability(plain, pd_, pp_, dev, ref_mu, ref_al)
+    ref2_mu, ref2_al = outs()
+    gpu_lib.tnep_eval_dipole_polarizability(plain, pd_, pp_, dev2, ref2_mu, ref2_al)
+    a_mu, a_al = outs()
+    for rep in range(3):
+        a_mu.zero_()
+        a_al.zero_()
+        gpu_lib.tnep_eval_dipole_polarizability(graph, gd_, gp_, dev, a_mu, a_al)
+        _eager_noise(rep)
+        assert torch.equal(a_mu, ref_mu) and torch.equal(a_al, ref_al), rep
+    captures, launches = graph.graph_counts()
+    assert captures == 1 and launches == 3, (captures, launches)
+    # other outputs: a new graph; the first outputs keep what they hold
+    a_mu.zero_()
+    a_al.zero_()
+    b_mu, b_al = outs()
+    gpu_lib.tnep_eval_dipole_polarizability(graph, gd_, gp_, dev, b_mu, b_al)
+    torch.cuda.synchronize()
+    assert torch.equal(b_mu, ref_mu) and torch.equal(b_al, ref_al)
+    assert not a_mu.any() and not a_al.any()
+    # other inputs (same sizes): a new graph with the new positions
+    c_mu, c_al = outs()
+    gpu_lib.tnep_eval_dipole_polarizability(graph, gd_, gp_, dev2, c_mu, c_al)
+    assert torch.equal(c_mu, ref2_mu) and torch.equal(c_al, ref2_al)
+    assert graph.graph_counts()[0] == 3
+    # per-atom device output (single-model call)
+    pa_ref = torch.zeros((mols.n_atoms, 3), dtype=torch.float64, device="cuda")
+    mu_p, _ = outs()
+    gpu_lib.tnep_eval_dipole(plain, pd_, dev, mu_p, pa_ref)
+    for rep in range(2):
+        pa = torch.zeros_like(pa_ref)
+        mu_g, _ = outs()
+        gpu_lib.tnep_eval_dipole(graph, gd_, dev, mu_g, pa)
+        assert torch.equal(pa, pa_ref) and torch.equal(mu_g, mu_p), rep
+    # and the replayed values are right
+    ref, pa_o = oracle.eval_frames(mp, mols, per_atom=True)
+    assert np.all(frame_errors(b_al.cpu().numpy(), ref, pa_o, mols.offsets) <= TENSOR_TOL)
+    for c in (plain, graph):
+        c.close()
