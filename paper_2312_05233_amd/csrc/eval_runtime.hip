@@ -480,7 +480,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
         std::vector<char> eligible(reuse ? F : 0, 0);
         for (int f = 0; reuse && f < F; ++f) {
             const FrameGeom& g = geom[f];
-            bool ok = g.per[0] && g.per[1] && g.per[2];
+            // (packed candidates hold a rank below 2^23)
+            bool ok = g.per[0] && g.per[1] && g.per[2] && meta.offs[f + 1] - meta.offs[f] < ((int64_t)1 << 23);
             for (int d = 0; d < 3 && ok; ++d) ok = g.L[d] >= 2.0 * rc_search;
             if (ok) {
                 e = frame_geometry(c, f, meta.cells.data() + 9 * (size_t)f, meta.pbc.data() + 3 * (size_t)f,
@@ -599,7 +600,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 tri_next += nf;
                 sizes_next += 4;
                 int n_cells = 0;
-                int64_t n_ref_atoms = 0;
+                int64_t n_ref_lists = 0;  // candidate lists of the batch's reference frames (CandLists)
                 bool followers = false, triclinic = false;
                 bool small_frames = false, large_frames = false;  // frame-sum kernels the batch needs
                 int ref_k = -1;  // reference frame of the open window
@@ -622,8 +623,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                             followers = true;
                         } else {
                             x.role = kRoleReference;
-                            x.cl_base = n_ref_atoms;
-                            n_ref_atoms += x.n_atoms;
+                            x.cl_base = n_ref_lists;
+                            n_ref_lists += (int64_t)T * ((x.n_atoms + 63) / 64 * 64);
                             ref_k = k;
                         }
                     } else {
@@ -665,9 +666,9 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if (n_buckets >= ((int64_t)1 << 30)) return c->fail(TNEP_E_INVALID, "too many cells in one batch");
                 if ((e = c->reserve(c->frames, sizeof(FrameInfo) * cap_frames))) return e;
                 if (triclinic && (e = c->reserve(c->frames_tric, sizeof(FrameTric) * cap_frames))) return e;
-                if (n_ref_atoms > 0) {
-                    if ((e = c->reserve(c->cand, (size_t)n_ref_atoms * T * c->cap_cand * 4))) return e;
-                    if ((e = c->reserve(c->cand_count, (size_t)n_ref_atoms * T * 4))) return e;
+                if (n_ref_lists > 0) {
+                    if ((e = c->reserve(c->cand, (size_t)n_ref_lists * T * c->cap_cand * 4))) return e;
+                    if ((e = c->reserve(c->cand_count, (size_t)n_ref_lists * T * 4))) return e;
                 }
                 if ((e = c->reserve(c->bucket_count, (size_t)4 * (n_buckets + 1)))) return e;
                 if ((e = c->reserve(c->bucket_start, (size_t)4 * (n_buckets + 1)))) return e;
@@ -755,7 +756,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                           triclinic ? (const FrameTric*)c->frames_tric.p : nullptr, cap_frames, pos,
                                           spc, cap_atoms,
                                           (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl, cl,
-                                          n_ref_atoms > 0, followers, triclinic, (int32_t*)c->flags.p,
+                                          n_ref_lists > 0, followers, triclinic, (int32_t*)c->flags.p,
                                           c->launch.neigh_block, (float*)c->rad_sums.p, c->stream);
                     c->timer_end(tr);
                     if (he != hipSuccess) return he;
@@ -791,7 +792,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 };
                 if (graphs) {
                     std::string key = graph_key(c, job, first, last, T, cap_atoms, cap_frames, cap_cells, B_res);
-                    if (n_ref_atoms > 0) {
+                    if (n_ref_lists > 0) {
                         char rb[64];
                         // the candidate radius and displacement guard are kernel arguments
                         snprintf(rb, sizeof(rb), "/r%d.%d.%a.%a", c->cap_cand, followers ? 1 : 0, (double)cl.rc_search,

@@ -139,9 +139,20 @@ enum ErrBits { kErrSpecies = 1, kErrNonFinite = 2, kErrOverlap = 4 };
 // ---- neighbour search (kernels_neighbors.hip) ----
 // Candidate lists of reference-frame atoms: list (cl_base + i) * T + t holds
 // up to cap frame-local indices of species-t candidates of atom i.
+// Candidate lists of trajectory reuse.  A reference frame's atom of species
+// t_i with rank k in the frame's species-t_i slot range has the list index
+// R = cl_base + t_i * A64 + k (A64: the frame's atom count rounded up to 64;
+// cl_base: the frame's first index, a multiple of 64); a follower frame's atom
+// has its reference atom's R.  Candidate q of neighbour species t of R is at
+// idx[(((R / 64) * T + t) * cap / 4 + q / 4) * 256 + (R % 64) * 4 + q % 4], so
+// four candidates are one 16-byte word and the lists of 64 consecutive R lie
+// side by side; count at [((R / 64) * T + t) * 64 + R % 64].  A candidate is
+// packed as (rank of the neighbour in its frame's species-t range) << 9 |
+// (ox + 3) << 6 | (oy + 3) << 3 | (oz + 3), o the offset of the neighbour's cell
+// from the atom's cell (|o| <= 2 on the grid for r_c + skin).
 struct CandLists {
-    int32_t* idx;      // [lists][cap]
-    int32_t* count;    // [lists]
+    int32_t* idx;      // [lists / 64][T][cap / 4][64][4]
+    int32_t* count;    // [lists / 64][T][64]
     int32_t cap;       // multiple of 4
     float rc_search;   // r_c + skin
     float half_skin2;  // (skin / 2)^2

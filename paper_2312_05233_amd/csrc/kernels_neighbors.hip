@@ -66,7 +66,10 @@ __device__ __forceinline__ int cell_coord(double p, double L, int nc) {
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
-// key = (frame cell) * T + species; invalid atoms get key -1.
+// key = (frame cell) * T + species; invalid atoms get key -1.  An atom of a
+// follower frame is binned where its reference atom is (the reference frame's
+// position), so the follower frame's slots mirror the reference frame's: the
+// same rank within each species range (CandLists).
 __global__ void k_bin(const FrameInfo* __restrict__ frames, const FrameTric* __restrict__ tric,
                       const int32_t* __restrict__ frame_of,
                       const double* __restrict__ pos, const int32_t* __restrict__ species,
@@ -99,9 +102,16 @@ __global__ void k_bin(const FrameInfo* __restrict__ frames, const FrameTric* __r
         }
         c += (b[0] * fi.nc[1] + b[1]) * fi.nc[2] + b[2];
     } else if (fi.mode == 1) {
-        const int ix = cell_coord(x, fi.L[0], fi.nc[0]);
-        const int iy = cell_coord(y, fi.L[1], fi.nc[1]);
-        const int iz = cell_coord(z, fi.L[2], fi.nc[2]);
+        double bx = x, by = y, bz = z;
+        if (fi.role == kRoleFollower) {
+            const int64_t ar = fi.ref_begin + (a - fi.atom_begin);
+            bx = pos[3 * ar];
+            by = pos[3 * ar + 1];
+            bz = pos[3 * ar + 2];
+        }
+        const int ix = cell_coord(bx, fi.L[0], fi.nc[0]);
+        const int iy = cell_coord(by, fi.L[1], fi.nc[1]);
+        const int iz = cell_coord(bz, fi.L[2], fi.nc[2]);
         c += (ix * fi.nc[1] + iy) * fi.nc[2] + iz;
     }
     const int key = c * T + t;
@@ -295,8 +305,12 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const FrameTr
                 h = fi.L[d] / fi.nc[d];
             }
             // triclinic: fixed point in units of q_unit from the bin origin;
-            // orthorhombic: FP32 offset (A) from the cell centre, |offset| <= h / 2
-            q[d] = fi.tric ? (int)rint((s - c[d] * h) / fi.q_unit) : __float_as_int((float)(s - (c[d] + 0.5) * h));
+            // orthorhombic: FP32 offset (A) from the cell centre, the minimum image
+            // (|offset| <= h / 2 for an atom in its own cell; a follower frame's atom
+            // is in its reference atom's cell, at most skin / 2 beyond it)
+            double o = s - (c[d] + 0.5) * h;
+            if (!fi.tric) o -= fi.L[d] * rint(o * fi.Linv[d]);
+            q[d] = fi.tric ? (int)rint((s - c[d] * h) / fi.q_unit) : __float_as_int((float)o);
         }
         cell_rec[slot] = make_int4(q[0], q[1], q[2], c[2]);
         return;
@@ -441,16 +455,16 @@ struct RadialSums {
     }
 };
 
-// One candidate of k_neighbors: pair vector d = r_j - r_i (FP64), in = a real
-// candidate other than the atom itself within the search radius.
+// One candidate of k_neighbors: pair vector d = r_j - r_i, in = a real
+// candidate other than the atom itself within the search radius.  Reference
+// frames also keep the candidate, packed (CandLists), in the lane's list.
 template <bool REF, typename R>
 __device__ __forceinline__ void take_candidate(PairSink& ps, RadialSums& rs, float rcR_inv, const float4* lds, bool in,
                                                R dx, R dy, R dz, R r2, int j, R rc2r, R rc2a, bool& overlap,
-                                               int& n_cand, int32_t* cand, int cand_cap, const int32_t* perm,
-                                               int atom_begin) {
+                                               int& n_cand, int32_t* cand, int cand_cap, int packed) {
     if (in) {
         if constexpr (REF) {
-            if (n_cand < cand_cap) cand[n_cand] = perm[j] - atom_begin;
+            if (n_cand < cand_cap) cand[(n_cand >> 2) * 256 + (n_cand & 3)] = packed;
             ++n_cand;
         }
         if (!REF || r2 < rc2r) {
@@ -513,7 +527,6 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const float rcR_inv = 1.f / rc_radial;
     // references collect candidates out to r_c + skin
     const float rs = REF ? cl.rc_search : rc_radial;
-    const double rcs2 = (double)rs * rs;
     const float rc2rf = rc_radial * rc_radial, rc2af = rc_angular * rc_angular, rcs2f = rs * rs;
     // cell pruning in FP32 with a 1e-3 A margin: a cell is skipped only when surely beyond the radius
     const float prune2 = (rs + 1e-3f) * (rs + 1e-3f);
@@ -549,6 +562,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         hz_inv = (float)(1.0 / hz);
     }
     bool overlap = false;
+    // reference frames: the atom's candidate-list index (CandLists)
+    int64_t R = 0;
+    if constexpr (REF) {
+        const int ti = species[a];
+        R = fi.cl_base + (int64_t)ti * ((fi.n_atoms + 63) & ~63) + ((int)p - perm_start[fi.cell_base * T + ti]);
+    }
     for (int t = 0; t < T; ++t) {
         PairSink ps{stage, (int)blockDim.x,
                     lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
@@ -557,7 +576,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         RadialSums rsum;
         rsum.clear();
         int n_cand = 0;
-        int32_t* cand = REF ? cl.idx + ((fi.cl_base + (a - fi.atom_begin)) * T + t) * cl.cap : nullptr;
+        int32_t* cand = nullptr;
+        int base_t = 0;  // first slot of the frame's species-t atoms
+        if constexpr (REF) {
+            cand = cl.idx + (((R >> 6) * T + t) * (cl.cap >> 2)) * 256 + (R & 63) * 4;
+            base_t = perm_start[fi.cell_base * T + t];
+        }
         // cell grids: every candidate within rs is at most kCellReachXY cells
         // away along x, y and kCellReachZ along z; visited as 25 z-columns
         const int n_col = fi.mode == 1 ? 25 : 1;
@@ -624,9 +648,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                         const float dy = __int_as_float(cr.y) + byf;
                         const float dz = fmaf((float)oz, hzf, __int_as_float(cr.z) - ozf);
                         const float r2 = dx * dx + dy * dy + dz * dz;
+                        const int packed = REF ? (int)(((unsigned)(j - base_t) << 9) | (unsigned)((ox + 3) << 6) |
+                                                       (unsigned)((oy + 3) << 3) | (unsigned)(oz + 3))
+                                               : 0;
                         take_candidate<REF, float>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2f),
                                                    dx, dy, dz, r2, j, rc2rf, rc2af, overlap, n_cand, cand, cl.cap,
-                                                   nl.perm, (int)fi.atom_begin);
+                                                   packed);
                         coop_flush(ps, nb_stage, list);
                     }
                 }
@@ -644,16 +671,16 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                         const double dy = min_image(cur.y - yi, fi.L[1], fi.Linv[1]);
                         const double dz = min_image(cur.z - zi, fi.L[2], fi.Linv[2]);
                         const double r2 = dx * dx + dy * dy + dz * dz;
-                        take_candidate<REF, double>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rcs2),
-                                                    dx, dy, dz, r2, j, rc2r, rc2a, overlap, n_cand, cand, cl.cap,
-                                                    nl.perm, (int)fi.atom_begin);
+                        // (reference frames always have a cell grid: no candidates kept here)
+                        take_candidate<false, double>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (j != (int)p) & (r2 < rc2r),
+                                                      dx, dy, dz, r2, j, rc2r, rc2a, overlap, n_cand, cand, cl.cap, 0);
                         coop_flush(ps, nb_stage, list);
                     }
                 }
             }
         }
         if constexpr (REF) {
-            cl.count[(fi.cl_base + (a - fi.atom_begin)) * T + t] = n_cand;
+            cl.count[((R >> 6) * T + t) * 64 + (R & 63)] = n_cand;
             if (n_cand > cl.cap) atomicMax(&flags[kFlagCapCand], n_cand);
         }
         rsum.store(rad_v, t, nl.n_pad, p);
@@ -669,16 +696,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     }
 }
 
-// Frames that follow a reference frame of their trajectory window: test the
-// reference atom's candidates (same frame-local indices) with the exact
-// r < r_c, and check the guard (displacement <= skin / 2, same species).
-__global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __restrict__ frames,
-                                                             const int32_t* __restrict__ frame_of,
-                                                             const double* __restrict__ pos,
-                                                             const int32_t* __restrict__ species,
-                                                             const int32_t* __restrict__ slot_of, float rc_radial,
-                                                             float rc_angular, NeighborLists nl, CandLists cl,
-                                                             int32_t* __restrict__ flags, float* __restrict__ rad_v) {
+// Frames that follow a reference frame of their trajectory window.  Their
+// atoms were binned where their reference atoms are (k_bin), so an atom has its
+// reference atom's rank in its species range and takes that atom's candidate
+// list (CandLists, read four candidates per 16-byte load, the lists of a
+// wavefront's lanes side by side).  A packed candidate gives the neighbour's
+// rank and the offset between the two atoms' cells; the pair vector is
+// (q_j - q_i) + offset x cell edge from the FP32 offsets of this frame's atoms
+// to those cell centres (k_sort_place), tested with the exact r < r_c.  Lists
+// are complete while no atom is more than skin / 2 from its reference
+// position (and species match), which the kernel checks in FP64.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_neighbors_follow(
+    const FrameInfo* __restrict__ frames, const int32_t* __restrict__ frame_of, const double* __restrict__ pos,
+    const int32_t* __restrict__ species, const int32_t* __restrict__ perm_start, const int4* __restrict__ cell_rec,
+    float rc_radial, float rc_angular, NeighborLists nl, CandLists cl, int32_t* __restrict__ flags,
+    float* __restrict__ rad_v) {
     // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
     extern __shared__ float4 nb_stage[];
     float4* stage = nb_stage + threadIdx.x;
@@ -691,18 +723,22 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
     const FrameInfo fi = frames[frame_of[a]];
     if (fi.role != kRoleFollower) return;
     const int tile = (int)(p >> 6), lane = (int)(p & 63);
-    const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
-    const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
-    const float rcR_inv = 1.f / rc_radial;
-    float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
-    const int64_t il = a - fi.atom_begin;
-    const int64_t aref = fi.ref_begin + il;
-    const double mx = min_image(xi - pos[3 * aref], fi.L[0], fi.Linv[0]);
-    const double my = min_image(yi - pos[3 * aref + 1], fi.L[1], fi.Linv[1]);
-    const double mz = min_image(zi - pos[3 * aref + 2], fi.L[2], fi.Linv[2]);
-    if (!(mx * mx + my * my + mz * mz <= (double)cl.half_skin2) || species[a] != species[aref])
+    const int ti = species[a];
+    const int64_t aref = fi.ref_begin + (a - fi.atom_begin);
+    const double mx = min_image(pos[3 * a] - pos[3 * aref], fi.L[0], fi.Linv[0]);
+    const double my = min_image(pos[3 * a + 1] - pos[3 * aref + 1], fi.L[1], fi.Linv[1]);
+    const double mz = min_image(pos[3 * a + 2] - pos[3 * aref + 2], fi.L[2], fi.Linv[2]);
+    if (!(mx * mx + my * my + mz * mz <= (double)cl.half_skin2) || ti != species[aref])
         atomicOr(&flags[kFlagReuse], 1);
+    const float rcR_inv = 1.f / rc_radial;
+    const float rc2rf = rc_radial * rc_radial, rc2af = rc_angular * rc_angular;
+    const float hx = (float)(fi.L[0] / fi.nc[0]), hy = (float)(fi.L[1] / fi.nc[1]), hz = (float)(fi.L[2] / fi.nc[2]);
+    const int4 own = cell_rec[p];
+    const float qx = __int_as_float(own.x), qy = __int_as_float(own.y), qz = __int_as_float(own.z);
+    float4* lane_base = nl.entries + ((int64_t)tile * (nl.slots >> 2) * 64 + lane) * 4;
+    const int64_t R = fi.cl_base + (int64_t)ti * ((fi.n_atoms + 63) & ~63) + ((int)p - perm_start[fi.cell_base * T + ti]);
     bool overlap = false;
+    int no_cand = 0;
     for (int t = 0; t < T; ++t) {
         PairSink ps{stage, (int)blockDim.x,
                     lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256,
@@ -710,33 +746,28 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
                     nl.meta[kMetaCapA + t], nl.meta[kMetaCapR + t], 0, 0, -1, nullptr};
         RadialSums rsum;
         rsum.clear();
-        const int64_t list = (fi.cl_base + il) * T + t;
-        const int n = min(cl.count[list], cl.cap);
-        const int4* idx4 = reinterpret_cast<const int4*>(cl.idx + list * cl.cap);
-        for (int k0 = 0; k0 < n; k0 += 4) {
-            const int4 jj = idx4[k0 >> 2];
-            const int jl[4] = {jj.x, jj.y, jj.z, jj.w};
-            double cx[4], cy[4], cz[4];
+        const int64_t li = (R >> 6) * T + t;
+        const int n = min(cl.count[li * 64 + (R & 63)], cl.cap);
+        const int4* c4 = reinterpret_cast<const int4*>(cl.idx) + li * (cl.cap >> 2) * 64 + (R & 63);
+        const int base_t = perm_start[fi.cell_base * T + t];
+        for (int q = 0; q < n; q += 4) {
+            const int4 cc = c4[(q >> 2) * 64];
+            // rows past the list's end hold no candidate: read slot base_t instead
+            const unsigned pk[4] = {q < n ? (unsigned)cc.x : 0u, q + 1 < n ? (unsigned)cc.y : 0u,
+                                    q + 2 < n ? (unsigned)cc.z : 0u, q + 3 < n ? (unsigned)cc.w : 0u};
+            int4 rec[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) rec[u] = cell_rec[base_t + (int)(pk[u] >> 9)];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int64_t j = fi.atom_begin + (k0 + u < n ? jl[u] : 0);
-                cx[u] = pos[3 * j];
-                cy[u] = pos[3 * j + 1];
-                cz[u] = pos[3 * j + 2];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double dx = min_image(cx[u] - xi, fi.L[0], fi.Linv[0]);
-                const double dy = min_image(cy[u] - yi, fi.L[1], fi.Linv[1]);
-                const double dz = min_image(cz[u] - zi, fi.L[2], fi.Linv[2]);
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if ((k0 + u < n) & (r2 < rc2r)) {
-                    overlap |= r2 < 1e-8;
-                    const int js = slot_of[fi.atom_begin + jl[u]];
-                    const float4 ent = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(js));
-                    ps.push_deferred(ent, r2 < rc2a, nb_stage);
-                    rsum.add(ent.x, ent.y, ent.z, rcR_inv);
-                }
+                const int j = base_t + (int)(pk[u] >> 9);
+                const float dx = (__int_as_float(rec[u].x) - qx) + (float)((int)((pk[u] >> 6) & 7u) - 3) * hx;
+                const float dy = (__int_as_float(rec[u].y) - qy) + (float)((int)((pk[u] >> 3) & 7u) - 3) * hy;
+                const float dz = (__int_as_float(rec[u].z) - qz) + (float)((int)(pk[u] & 7u) - 3) * hz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                take_candidate<false, float>(ps, rsum, rcR_inv, nb_stage, (q + u < n) & (r2 < rc2rf), dx, dy, dz, r2,
+                                             j, rc2rf, rc2af, overlap, no_cand, nullptr, 0, 0);
                 coop_flush(ps, nb_stage, wlist);
             }
         }
@@ -751,7 +782,6 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_follow(const FrameInfo* __
         atomicOr(&flags[kFlagError], kErrOverlap);
         atomicMin(&flags[kFlagBadAtom], call_atom(nl.meta, a));
     }
-    return;
 }
 
 // Triclinic frames: one lane per tile slot.  Bins in fractional coordinates
@@ -1000,8 +1030,9 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, 
                                                                w.bucket_pos, w.cell_rec, rc_radial, rc_angular, nl,
                                                                d_flags, rad_sums);
     if (followers)
-        k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
-                                                                  rc_radial, rc_angular, nl, cl, d_flags, rad_sums);
+        k_neighbors_follow<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species,
+                                                                  w.perm_start, w.cell_rec, rc_radial, rc_angular,
+                                                                  nl, cl, d_flags, rad_sums);
     return hipGetLastError();
 }
 
