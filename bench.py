@@ -89,6 +89,8 @@ def read_traffic(atoms_per_launch):
 
 
 def cpu_baseline(frames, md, mp, n_sample, gpu_mu, gpu_alpha):
+    """The FP64 oracle on frames 0..n_sample-1 with all its threads, then on
+    frame 0 with one thread (the per-core rate)."""
     import oracle
 
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -96,6 +98,7 @@ def cpu_baseline(frames, md, mp, n_sample, gpu_mu, gpu_alpha):
 
     idx = list(range(n_sample))
     sub = frames.subset(idx)
+    cores = oracle.max_threads()
     t0 = time.perf_counter()
     mu_ref, mu_pa = oracle.eval_frames(md, sub, per_atom=True)
     al_ref, al_pa = oracle.eval_frames(mp, sub, per_atom=True)
@@ -103,11 +106,22 @@ def cpu_baseline(frames, md, mp, n_sample, gpu_mu, gpu_alpha):
     atoms = sub.n_atoms
     err_mu = frame_errors(gpu_mu[idx], mu_ref, mu_pa, sub.offsets).max()
     err_al = frame_errors(gpu_alpha[idx], al_ref.reshape(-1, 9), al_pa, sub.offsets).max()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one = frames.subset([0])
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.eval_frames(md, one)
+        oracle.eval_frames(mp, one)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
     return {
         "value": atoms / dt, "unit": "atom-frames/s", "cores": cores, "kind": "oracle",
         "sample": f"frames 0..{n_sample - 1} of the trajectory ({atoms} atom-frames), dipole + polarizability "
                   f"models, FP64, {dt:.1f} s wall",
+        "single_thread": {"value": one.n_atoms / dt1, "unit": "atom-frames/s", "cores": 1,
+                          "sample": f"frame 0 ({one.n_atoms} atom-frames), dipole + polarizability models, FP64, "
+                                    f"{dt1:.1f} s wall"},
     }, float(err_mu), float(err_al)
 
 
@@ -738,6 +752,117 @@ def extra_legs(args, ctx, gd, gp, frames, dfr, md, mp, M, ms_step):
     return out
 
 
+def _eval_roofline(ctx, model, step, steps, kernel):
+    """Average launch time of one evaluation kernel (HIP events around its
+    launches on the context's stream) and its FP32 rate from the flop model."""
+    import torch
+
+    from paper_2312_05233_amd import tnep
+
+    ctx.set_option(tnep.OPT_TIMING, 1)
+    ctx.reset_timing()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms, launches = ctx.kernel_time(kernel)
+    atoms, rad, ang = ctx.pair_counts()
+    ctx.set_option(tnep.OPT_TIMING, 0)
+    flop_af = flops_per_atom_frame(model, rad / atoms, ang / atoms)
+    per_launch = atoms / launches
+    achieved = flop_af * per_launch / (ms / launches * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "flop_per_atom_frame": flop_af,
+            "atoms_per_launch": per_launch, "avg_launch_ms": ms / launches,
+            "mean_radial_neighbors": rad / atoms, "mean_angular_neighbors": ang / atoms}
+
+
+def config_legs(args):
+    """The other frame workloads beside the headline, one record each: the
+    throughput of one call over device-resident frames, the roofline of its
+    dominant evaluation kernel, and the largest per-frame error against the
+    FP64 oracle on the frames named in the record."""
+    import torch
+
+    import oracle
+    from paper_2312_05233_amd import tnep
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import frame_errors
+
+    legs = {}
+    steps = max(args.steps, 5)
+
+    # small periodic water, dipole model
+    frames = synth.water_small(10)
+    m = synth.model("water_dipole_small")
+    ctx = tnep.Context(0)
+    gm = tnep.Model(ctx, m)
+    dfr = tnep.DeviceFrames(frames)
+    mu = torch.zeros((frames.n_frames, 3), dtype=torch.float64, device="cuda")
+    step = lambda: tnep.tnep_eval_dipole(ctx, gm, dfr, mu)  # noqa: E731
+    t = _timed(step, 4 * steps, args.warmup + 1)
+    ref, pa = oracle.eval_frames(m, frames, per_atom=True)
+    err = frame_errors(mu.cpu().numpy(), ref, pa, frames.offsets).max()
+    rl = _eval_roofline(ctx, m, step, steps, tnep.KERNEL_EVAL_DIPOLE)
+    rl["kernel"] = "k_eval<dipole>"
+    legs["water_small_dipole"] = {
+        "workload": "64 H2O (192 atoms), 12.42 A periodic box, 10 independent frames, dipole model",
+        "value": frames.n_atoms / t, "unit": "atom-frames/s", "ms_per_call": 1e3 * t, "dtype": "f32",
+        "max_frame_error_vs_oracle": float(err), "error_frames": "all 10", "roofline": rl}
+    gm.close()
+    ctx.close()
+
+    # perovskite 12^3 supercell, susceptibility model, one batch of 64 frames
+    frames = synth.perovskite(64)
+    m = synth.model("perovskite_susceptibility")
+    ctx = tnep.Context(0)
+    gm = tnep.Model(ctx, m)
+    dfr = tnep.DeviceFrames(frames)
+    out = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
+    step = lambda: tnep.tnep_eval_polarizability(ctx, gm, dfr, out)  # noqa: E731
+    t = _timed(step, steps, args.warmup)
+    two = frames.subset([0, 1])
+    ref, pa = oracle.eval_frames(m, two, per_atom=True)
+    err = frame_errors(out[:2].cpu().numpy(), ref.reshape(2, 9), pa, two.offsets).max()
+    rl = _eval_roofline(ctx, m, step, steps, tnep.KERNEL_EVAL_POLARIZABILITY)
+    rl["kernel"] = "k_eval<7,5,9,9,polarizability>"
+    legs["perovskite_susceptibility"] = {
+        "workload": "Ba/Zr/O 12x12x12 supercell (8640 atoms, a = 4.19 A, sigma 0.08 A), batch of 64 frames, "
+                    "susceptibility model rc 7/5 A, n_max 6/4, H = 50, FP32 hidden layer",
+        "value": frames.n_atoms / t, "unit": "atom-frames/s", "ms_per_call": 1e3 * t, "dtype": "f32",
+        "max_frame_error_vs_oracle": float(err), "error_frames": "0 and 1", "roofline": rl}
+    gm.close()
+    ctx.close()
+
+    # ragged vacuum molecules, dipole + polarizability in one call
+    frames = synth.molecules(8192)
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    ctx = tnep.Context(0)
+    gd, gp = tnep.Model(ctx, md), tnep.Model(ctx, mp)
+    dfr = tnep.DeviceFrames(frames)
+    mu = torch.zeros((frames.n_frames, 3), dtype=torch.float64, device="cuda")
+    al = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
+    step = lambda: tnep.tnep_eval_dipole_polarizability(ctx, gd, gp, dfr, mu, al)  # noqa: E731
+    t = _timed(step, steps, args.warmup)
+    idx = list(range(256))
+    sub = frames.subset(idx)
+    ref_mu, pa_mu = oracle.eval_frames(md, sub, per_atom=True)
+    ref_al, pa_al = oracle.eval_frames(mp, sub, per_atom=True)
+    err = max(frame_errors(mu[:256].cpu().numpy(), ref_mu, pa_mu, sub.offsets).max(),
+              frame_errors(al[:256].cpu().numpy(), ref_al.reshape(-1, 9), pa_al, sub.offsets).max())
+    rl = _eval_roofline(ctx, mp, step, steps, tnep.KERNEL_EVAL_POLARIZABILITY)
+    rl["kernel"] = "k_eval<5,5,9,9,4-body,polarizability>"
+    legs["molecules"] = {
+        "workload": "8192 vacuum molecules of 20-80 atoms (%d atoms), C/H/N/O/F, dipole + polarizability in one "
+                    "call" % frames.n_atoms,
+        "value": frames.n_atoms / t, "unit": "atom-frames/s", "ms_per_call": 1e3 * t, "dtype": "f32",
+        "max_frame_error_vs_oracle": float(err), "error_frames": "molecules 0..255, both models", "roofline": rl}
+    gd.close()
+    gp.close()
+    ctx.close()
+    return legs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -749,7 +874,7 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serving workload: number of requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-legs", action="store_true",
-                    help="skip the host-input, plain per-frame and serving legs of the headline run")
+                    help="skip the host-input, plain per-frame, serving and other-workload legs of the headline run")
     ap.add_argument("--serving-requests", type=int, default=60, help="requests of the headline run's serving leg")
     ap.add_argument("--mlp", type=int, default=None, help="TNEP_MLP_* mode of the hidden layer")
     ap.add_argument("--atoms-per-block", type=int, default=None)
@@ -903,6 +1028,7 @@ def main():
     }
     if not args.no_extra_legs:
         result.update(extra_legs(args, ctx, gd, gp, frames, dfr, md, mp, M, ms_step))
+        result["other_configs"] = config_legs(args)
     if not args.no_cpu_baseline:
         cb, e_mu, e_al = cpu_baseline(frames, md, mp, min(args.cpu_frames, F), mu_h, al_h)
         result["cpu_baseline"] = cb

@@ -73,6 +73,8 @@ def _lib_handle():
             build()
             lib = C.CDLL(_LIB)
             P = C.POINTER
+            lib.or_set_threads.argtypes = [C.c_int]
+            lib.or_max_threads.restype = C.c_int
             lib.or_ylm.restype = C.c_double
             lib.or_ylm.argtypes = [C.c_int, C.c_int, P(C.c_double), P(C.c_double)]
             lib.or_wigner3j.restype = C.c_double
@@ -152,6 +154,16 @@ def _model(m):
 
 # -------------------------------------------------------------------------
 # Building blocks exposed for the pins
+
+
+def set_threads(n):
+    """Threads of the oracle's frame loops (OpenMP) from now on."""
+    _lib_handle().or_set_threads(int(n))
+
+
+def max_threads():
+    """Threads the oracle's frame loops use."""
+    return int(_lib_handle().or_max_threads())
 
 
 def ylm(l, m, v):

@@ -37,6 +37,7 @@
  * with the minimum-image convention (orthorhombic cells).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -178,6 +179,10 @@ void or_init(void) {
     build_poly();
     g_ready = 1;
 }
+
+/* Threads of the frame loops (OpenMP); for timing the oracle on one core. */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_max_threads(void) { return omp_get_max_threads(); }
 
 /* Y_lm(r/|r|) and its gradient with respect to the vector r.
  * With P = r^l Y_lm (homogeneous of degree l): Y = P(r)/r^l,
