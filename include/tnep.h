@@ -104,6 +104,16 @@ extern "C" {
                                      differs).  0 (default) = off */
 #define TNEP_OPT_SKIN_MA 10       /* skin for TNEP_OPT_TRAJECTORY_WINDOW in 1e-3 Angstrom
                                      (1..5000, default 1000) */
+#define TNEP_OPT_PAIR_PARALLEL 11 /* 1 = evaluation of the dipole and polarizability models with
+                                     16 lanes per atom (each takes every 16th neighbour row and
+                                     hidden neuron; the lanes' shares are added by a fixed tree)
+                                     and the FP32 vector hidden layer: for calls of few atoms,
+                                     whose time one lane per atom sets by its serial work per
+                                     atom; large calls take more device time per atom.  Results
+                                     agree with the default layout to FP32 summation order, and
+                                     within the layout they do not depend on batching.
+                                     Potential-energy models keep the default layout.
+                                     0 (default) = one lane per atom */
 
 /* kernel classes for tnep_ctx_kernel_time */
 #define TNEP_KERNEL_NEIGHBORS 0

@@ -288,6 +288,10 @@ extern "C" int tnep_set_option(tnep_ctx* ctx, int32_t key, int64_t value) {
             if (value < 1 || value > 5000) return c->fail(TNEP_E_INVALID, "skin must be 1..5000 mA");
             c->skin = (double)value * 1e-3;
             return TNEP_OK;
+        case TNEP_OPT_PAIR_PARALLEL:
+            if (value != 0 && value != 1) return c->fail(TNEP_E_INVALID, "pair-parallel layout must be 0 or 1");
+            c->launch.pair_parallel = (int)value;
+            return TNEP_OK;
         case TNEP_OPT_MAX_BATCH_ATOMS:
             if (value < 1) return c->fail(TNEP_E_INVALID, "max batch atoms must be positive");
             c->max_batch_atoms = value;

@@ -409,8 +409,9 @@ static std::string graph_key(const Ctx* c, const EvalJob& job, int first, int la
         snprintf(buf, sizeof(buf), "c%d.%d.", c->cap_ang[t], c->cap_rad[t]);
         k += buf;
     }
-    snprintf(buf, sizeof(buf), "l%d.%d.%d/a%lld/f%d/c%lld/b%lld", c->launch.mlp_mode, c->launch.atoms_per_block,
-             c->launch.neigh_block, (long long)cap_atoms, cap_frames, (long long)cap_cells, (long long)B_res);
+    snprintf(buf, sizeof(buf), "l%d.%d.%d.%d/a%lld/f%d/c%lld/b%lld", c->launch.mlp_mode, c->launch.atoms_per_block,
+             c->launch.neigh_block, c->launch.pair_parallel, (long long)cap_atoms, cap_frames, (long long)cap_cells,
+             (long long)B_res);
     return k + buf;
 }
 

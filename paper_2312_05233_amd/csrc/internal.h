@@ -192,7 +192,11 @@ struct EvalLaunch {
     int mlp_mode;         // TNEP_MLP_*
     int atoms_per_block;  // work-group size of the FP32-VALU evaluation kernel: 64, 128, 256
     int neigh_block;      // work-group size of the neighbour kernel: 64, 128, 256
+    int pair_parallel;    // 1: kPairLanes lanes per atom in the evaluation of the tensor models
 };
+
+// Lanes per atom of the pair-parallel evaluation layout (one 16-lane DPP row).
+constexpr int kPairLanes = 16;
 
 // Potential-energy models: the evaluation kernel leaves, per atom a in tile
 // slot p, a record of rec_stride floats at rec + p * rec_stride (slots keep

@@ -13,6 +13,15 @@
 //      -r_ij (x) dU_i/dr_ij plus U^s_i delta (Sec. 2.3, Eq. polarizability-model).
 // Per-pair work is FP32; the atom terms are written as FP64 and summed per
 // frame by k_frame_reduce in a fixed order.
+//
+// Two layouts of the same kernel: one lane per atom (G = 1, the throughput
+// layout), or G = 16 lanes per atom for launch batches of few atoms (one atom
+// per 16-lane DPP row): lane g takes the neighbour rows g, g + G, ... and the
+// hidden neurons g, g + G, ..., and group_sum adds the lanes' shares of the
+// descriptor sums, of dU/dq and of the atom's tensor term by a fixed tree, so
+// an atom's result still depends only on its own list.
+#include <type_traits>
+
 #include "../../include/tnep.h"
 #include "internal.h"
 #include "tnep_math.h"
@@ -32,6 +41,42 @@ __device__ __forceinline__ int tile_species(const int32_t* tile_base, int T, int
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+// Sum over the G lanes of an aligned group (G = 1, 8 or 16 within a DPP row),
+// the result in every lane of the group: lanes exchanged with lane ^ 1, then
+// lane ^ 2 (quad permutations), then lane i with 7 - i (half-row mirror), then
+// i with 15 - i (row mirror).  Each step adds two equal-rank partial sums in
+// both orders, which IEEE addition makes bitwise equal, so every lane of the
+// group ends with the same value.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <int G, class V>
+__device__ __forceinline__ V group_sum(V v) {
+    static_assert(G == 1 || G == 8 || G == 16, "groups of 1, 8 or 16 lanes");
+    auto step = [](V x, auto ctrl) {
+        constexpr int C = decltype(ctrl)::value;
+        if constexpr (sizeof(V) == 8)
+            return x + dpp_f64<C>(x);
+        else
+            return x + dpp_f32<C>(x);
+    };
+    if constexpr (G >= 8) {
+        v = step(v, std::integral_constant<int, 0xB1>{});   // quad_perm(1, 0, 3, 2)
+        v = step(v, std::integral_constant<int, 0x4E>{});   // quad_perm(2, 3, 0, 1)
+        v = step(v, std::integral_constant<int, 0x141>{});  // row_half_mirror
+    }
+    if constexpr (G == 16) v = step(v, std::integral_constant<int, 0x140>{});  // row_mirror
+    return v;
+}
 
 // Order the wavefront's LDS writes before its later LDS reads by other lanes.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -196,11 +241,13 @@ __host__ __device__ constexpr int mlp_lds_floats(int D, int H) {
 // FP32 vector ALU (no LDS) or one of the matrix-core variants (LDS tile per
 // wavefront).  Padding lanes run with empty neighbour lists and store nothing.
 // LOAD: the radial descriptor sums come from rad_v (the neighbour search
-// accumulated them); otherwise the kernel forms them.  pes_rec, pes_pair and
+// accumulated them); otherwise the kernel forms them.  G: lanes per atom (1, or
+// 16 for the pair-parallel layout of the dipole and polarizability models with
+// the FP32 vector hidden layer).  pes_rec, pes_pair and
 // pes_slot (the potential-energy outputs of PesOut) are restrict parameters, so that
 // their stores cannot clobber the model's parameters and these stay
 // wave-uniform scalar loads.
-template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE, bool LOAD = false>
+template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE, bool LOAD = false, int G = 1>
 __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, double* __restrict__ per_atom,
                                                  PesOut pes, const float* __restrict__ rad_v,
                                                  float* __restrict__ pes_rec, float4* __restrict__ pes_pair,
@@ -208,7 +255,11 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     constexpr bool FOURB = (MB & 1) != 0, FIVEB = (MB & 2) != 0;
     constexpr int D = NR + 4 * NA + (FOURB ? NA : 0) + (FIVEB ? NA : 0);
     constexpr int NT = KIND == 1 ? 3 : 9;  // accumulated tensor: mu, or the virial-like W
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    static_assert(G == 1 || (KIND != 3 && MODE == TNEP_MLP_FP32_VALU && !LOAD),
+                  "the pair-parallel layout serves the tensor models with the vector hidden layer");
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = G == 1 ? tid : tid / G;  // tile slot
+    const int g = G == 1 ? 0 : (int)(tid % G);  // lane within the atom's group
     const int T = nl.T;
     const int tile = __builtin_amdgcn_readfirstlane((int)(p >> 6));
     const int lane = (int)(p & 63);
@@ -247,10 +298,10 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             for (int k = 0; k < KA; ++k) c += cA[n * KA + k];
             Cs[n] = c;
         }
-        float4 nxt = n_ang > 0 ? ga[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int s = 0; s < n_ang; ++s) {
+        float4 nxt = n_ang > g ? ga[(g >> 2) * 256 + (g & 3)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int s = g; s < n_ang; s += G) {
             const float4 e = nxt;
-            if (s + 1 < n_ang) nxt = ga[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
+            if (s + G < n_ang) nxt = ga[((s + G) >> 2) * 256 + ((s + G) & 3)];
             const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
             const float rinv = pair_rsqrt(r2);
             const float r = r2 * rinv;
@@ -285,10 +336,10 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 #pragma unroll
             for (int k = 0; k < KR; ++k) F[k] = rad_v[(int64_t)(t * KR + k) * nl.n_pad + p];
         } else {
-            nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-            for (int s = 0; s < n_rad; ++s) {
+            nxt = n_rad > g ? gr[(g >> 2) * 256 + (g & 3)] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int s = g; s < n_rad; s += G) {
                 const float4 e = nxt;
-                if (s + 1 < n_rad) nxt = gr[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
+                if (s + G < n_rad) nxt = gr[((s + G) >> 2) * 256 + ((s + G) & 3)];
                 const float r = pair_sqrt(e.x * e.x + e.y * e.y + e.z * e.z);
                 const float fc = cutoff_fc(1.f - r * rcR_inv);
                 const float tt = r * rcR_inv - 1.f;
@@ -305,6 +356,14 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
         for (int n = 0; n < NR; ++n)
 #pragma unroll
             for (int k = 0; k < KR; ++k) qR[n] += cR[n * KR + k] * F[k];
+    }
+    if constexpr (G > 1) {  // the lanes' shares of the sums (linear in the pair terms)
+#pragma unroll
+        for (int n = 0; n < NR; ++n) qR[n] = group_sum<G>(qR[n]);
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+#pragma unroll
+            for (int c = 0; c < kLM; ++c) A[n][c] = group_sum<G>(A[n][c]);
     }
 
     // ---- 2. invariants, network forward and backward ---------------------
@@ -359,13 +418,15 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float* __restrict__ w0 = m.w0[1] + ti * m.sp_w0;
             const float* __restrict__ b0 = m.b0[1] + ti * m.sp_h;
             const float* __restrict__ w1 = m.w1[1] + ti * m.sp_h;
-            Us = -(m.b1s[1] ? m.b1s[1][ti] : m.b1[1]);
-            for (int mu = 0; mu < H; ++mu) {
+            const float b1 = m.b1s[1] ? m.b1s[1][ti] : m.b1[1];
+            Us = G == 1 ? -b1 : 0.f;
+            for (int mu = g; mu < H; mu += G) {
                 float x = -b0[mu];
 #pragma unroll
                 for (int v = 0; v < D; ++v) x += w0[mu * D + v] * qs[v];
                 Us += w1[mu] * tanhf(x);
             }
+            if constexpr (G > 1) Us = group_sum<G>(Us) - b1;
         }
 #pragma unroll
         for (int v = 0; v < D; ++v) dq[v] = 0.f;
@@ -374,7 +435,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             const float* __restrict__ b0 = m.b0[0] + ti * m.sp_h;
             const float* __restrict__ w1 = m.w1[0] + ti * m.sp_h;
             if constexpr (KIND == 3) Us = -(m.b1s[0] ? m.b1s[0][ti] : m.b1[0]);
-            for (int mu = 0; mu < H; ++mu) {
+            for (int mu = g; mu < H; mu += G) {
                 float x = -b0[mu];
 #pragma unroll
                 for (int v = 0; v < D; ++v) x += w0[mu * D + v] * qs[v];
@@ -384,6 +445,10 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 #pragma unroll
                 for (int v = 0; v < D; ++v) dq[v] += t * w0[mu * D + v];
             }
+        }
+        if constexpr (G > 1) {
+#pragma unroll
+            for (int v = 0; v < D; ++v) dq[v] = group_sum<G>(dq[v]);
         }
 #pragma unroll
         for (int v = 0; v < D; ++v) dq[v] *= m.scaler[v];
@@ -522,10 +587,10 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
             for (int k = 0; k + 1 < KR; ++k) s1 += Ek[k] * Tk[k];
             return 0.5f * (fc * (4.f * tt * rcR_inv) * s1 + dfc * s0);
         };
-        float4 nxt = n_ang > 0 ? ga[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int s = 0; s < n_ang; ++s) {
+        float4 nxt = n_ang > g ? ga[(g >> 2) * 256 + (g & 3)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int s = g; s < n_ang; s += G) {
             const float4 e = nxt;
-            if (s + 1 < n_ang) nxt = ga[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
+            if (s + G < n_ang) nxt = ga[((s + G) >> 2) * 256 + ((s + G) & 3)];
             const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
             const float rinv = pair_rsqrt(r2);
             const float r = r2 * rinv;
@@ -584,10 +649,10 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
                 }
             }
         }
-        nxt = n_rad > 0 ? gr[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int s = 0; s < n_rad; ++s) {
+        nxt = n_rad > g ? gr[(g >> 2) * 256 + (g & 3)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int s = g; s < n_rad; s += G) {
             const float4 e = nxt;
-            if (s + 1 < n_rad) nxt = gr[((s + 1) >> 2) * 256 + ((s + 1) & 3)];
+            if (s + G < n_rad) nxt = gr[((s + G) >> 2) * 256 + ((s + G) & 3)];
             const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
             const float rinv = pair_rsqrt(r2);
             const float su = radial_slope(r2 * rinv) * rinv;
@@ -595,7 +660,13 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
         }
     }
 
-    if (a < 0) return;
+    if constexpr (G > 1) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) acc[k] = group_sum<G>(acc[k]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) accd[k] = group_sum<G>(accd[k]);
+    }
+    if (a < 0 || g != 0) return;
     if constexpr (KIND == 3) {
         double* out = per_atom + (int64_t)a * 10;
         out[0] = (double)Us;
@@ -887,8 +958,16 @@ __global__ void __launch_bounds__(256) k_pes_forces(DevModel m, NeighborLists nl
 
 template <int NR, int NA, int KR, int KA, int MB, int KIND, int MODE>
 hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom, const PesOut& pes,
-                    const RadSums& rs, int block, hipStream_t s) {
+                    const RadSums& rs, int block, bool pair_parallel, hipStream_t s) {
     constexpr int D = NR + 4 * NA + ((MB & 1) ? NA : 0) + ((MB & 2) ? NA : 0);
+    if constexpr (MODE == TNEP_MLP_FP32_VALU && KIND != 3) {
+        if (pair_parallel) {  // kPairLanes lanes per tile slot; n_pad is a multiple of 64
+            const unsigned grid = (unsigned)(nl.n_pad * kPairLanes / 256);
+            k_eval<NR, NA, KR, KA, MB, KIND, MODE, false, kPairLanes><<<grid, 256, 0, s>>>(
+                m, nl, per_atom, pes, nullptr, pes.rec, pes.pair, pes.slot);
+            return hipGetLastError();
+        }
+    }
     if constexpr (MODE == TNEP_MLP_FP32_VALU) {
         const int bs = (block == 64 || block == 128) ? block : 256;
         const unsigned grid = (unsigned)((nl.n_pad + bs - 1) / bs);
@@ -908,32 +987,33 @@ hipError_t launch_t(const DevModel& m, const NeighborLists& nl, double* per_atom
 
 template <int NR, int NA, int KR, int KA, int MB, int KIND>
 hipError_t launch_mode(int mode, bool matrix, const DevModel& m, const NeighborLists& nl, double* per_atom,
-                       const PesOut& pes, const RadSums& rs, int block, hipStream_t s) {
+                       const PesOut& pes, const RadSums& rs, int block, bool pp, hipStream_t s) {
     if (matrix) {
         if (mode == TNEP_MLP_FP32_MFMA)
-            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, pes, rs, block, s);
+            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_MFMA>(m, nl, per_atom, pes, rs, block, pp, s);
         if (mode == TNEP_MLP_BF16_MFMA)
-            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, pes, rs, block, s);
+            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16_MFMA>(m, nl, per_atom, pes, rs, block, pp, s);
         if (mode == TNEP_MLP_BF16X3_MFMA)
-            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, pes, rs, block, s);
+            return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_BF16X3_MFMA>(m, nl, per_atom, pes, rs, block, pp, s);
     }
-    return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, s);
+    return launch_t<NR, NA, KR, KA, MB, KIND, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, pp, s);
 }
 
 // Potential-energy models always use the FP32 vector hidden layer.
+// pp: the pair-parallel layout (tensor models, FP32 vector hidden layer).
 template <int NR, int NA, int KR, int KA, int MB, bool MX>
 hipError_t dispatch(const Shape& shape, int mode, bool matrix, const DevModel& m, const NeighborLists& nl,
-                    double* per_atom, const PesOut& pes, const RadSums& rs, int block, hipStream_t s) {
+                    double* per_atom, const PesOut& pes, const RadSums& rs, int block, bool pp, hipStream_t s) {
     if (shape.kind == 3)
-        return launch_t<NR, NA, KR, KA, MB, 3, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, s);
+        return launch_t<NR, NA, KR, KA, MB, 3, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, false, s);
     if constexpr (MX) {
         if (shape.kind == 1)
-            return launch_mode<NR, NA, KR, KA, MB, 1>(mode, matrix, m, nl, per_atom, pes, rs, block, s);
-        return launch_mode<NR, NA, KR, KA, MB, 2>(mode, matrix, m, nl, per_atom, pes, rs, block, s);
+            return launch_mode<NR, NA, KR, KA, MB, 1>(mode, matrix, m, nl, per_atom, pes, rs, block, pp, s);
+        return launch_mode<NR, NA, KR, KA, MB, 2>(mode, matrix, m, nl, per_atom, pes, rs, block, pp, s);
     } else {
         if (shape.kind == 1)
-            return launch_t<NR, NA, KR, KA, MB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, s);
-        return launch_t<NR, NA, KR, KA, MB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, s);
+            return launch_t<NR, NA, KR, KA, MB, 1, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, pp, s);
+        return launch_t<NR, NA, KR, KA, MB, 2, TNEP_MLP_FP32_VALU>(m, nl, per_atom, pes, rs, block, pp, s);
     }
 }
 
@@ -971,14 +1051,16 @@ bool eval_matrix_supported(const Shape& s, int n_hidden) {
 hipError_t launch_eval(const Shape& shape, const DevModel& m, const NeighborLists& nl, double* per_atom,
                        const PesOut& pes, const RadSums& rs, const EvalLaunch& cfg, hipStream_t s) {
     if (nl.n_pad == 0) return hipSuccess;
-    // the matrix-core hidden layer holds one shared network
-    const bool matrix =
-        cfg.mlp_mode != TNEP_MLP_FP32_VALU && eval_matrix_supported(shape, m.n_hidden) && m.sp_w0 == 0;
+    // the matrix-core hidden layer holds one shared network; the pair-parallel
+    // layout takes the vector hidden layer
+    const bool pp = cfg.pair_parallel != 0;
+    const bool matrix = !pp && cfg.mlp_mode != TNEP_MLP_FP32_VALU && eval_matrix_supported(shape, m.n_hidden) &&
+                        m.sp_w0 == 0;
 #define X(NR_, NA_, KR_, KA_, FB_, MX_)                                                             \
     if (shape.nr == NR_ && shape.na == NA_ && shape.kr == KR_ && shape.ka == KA_ &&                \
         shape_bodies(shape) == FB_)                                                             \
         return dispatch<NR_, NA_, KR_, KA_, FB_, MX_>(shape, cfg.mlp_mode, matrix, m, nl, per_atom, pes, rs,  \
-                                                      cfg.atoms_per_block, s);
+                                                      cfg.atoms_per_block, pp, s);
     TNEP_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

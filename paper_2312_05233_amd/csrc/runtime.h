@@ -40,7 +40,7 @@ struct Ctx {
     uint64_t in_use = 0;
     uint64_t peak = 0;
     std::string err;
-    EvalLaunch launch{0, 256, 256};
+    EvalLaunch launch{0, 256, 256, 0};
     bool autotune = false;
     // autotuned launch parameters per (shape, species count, frame-size class, location)
     struct Tuned {

@@ -27,6 +27,7 @@ OPT_MLP, OPT_ATOMS_PER_BLOCK, OPT_AUTOTUNE, OPT_DETERMINISTIC, OPT_MAX_BATCH_ATO
 OPT_NEIGH_BLOCK = 7
 OPT_GRAPHS = 8
 OPT_TRAJECTORY_WINDOW, OPT_SKIN_MA = 9, 10
+OPT_PAIR_PARALLEL = 11
 KERNEL_NEIGHBORS, KERNEL_EVAL_DIPOLE, KERNEL_EVAL_POLARIZABILITY, KERNEL_FRAME_REDUCE, KERNEL_SPECTRUM = 0, 1, 2, 3, 4
 KERNEL_EVAL_PES, KERNEL_PES_FORCES = 5, 6
 IR, RAMAN_ISO, RAMAN_ANISO, RAMAN_PROJ, RAMAN_MAP = 0, 1, 2, 3, 4

@@ -1,0 +1,128 @@
+"""The pair-parallel evaluation layout (TNEP_OPT_PAIR_PARALLEL: 16 lanes per
+atom, the lanes' shares added by a fixed tree) against the FP64 oracle, the
+default layout, and itself under rebatching.
+
+Tensors: per-frame relative Frobenius error <= 1e-5 against the oracle
+(tests/parity.py); the two layouts sum the same FP32 pair terms in another
+order, so they agree to a few FP32 roundings of the atom terms.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import TENSOR_TOL, frame_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctxs(gpu_lib):
+    pp = gpu_lib.Context(0)
+    pp.set_option(gpu_lib.OPT_PAIR_PARALLEL, 1)
+    plain = gpu_lib.Context(0)
+    yield pp, plain
+    pp.close()
+    plain.close()
+
+
+def _eval(gpu_lib, ctx, m, fr, per_atom=None):
+    mdl = gpu_lib.Model(ctx, m)
+    f = gpu_lib.tnep_eval_dipole if m.kind == 1 else gpu_lib.tnep_eval_polarizability
+    out = f(ctx, mdl, fr, per_atom=per_atom)
+    mdl.close()
+    return out
+
+
+def _check(gpu, m, fr, label):
+    ref, pa = oracle.eval_frames(m, fr, per_atom=True)
+    err = frame_errors(gpu.reshape(len(ref), -1), ref.reshape(len(ref), -1), pa, fr.offsets)
+    print(f"{label}: max frame error {err.max():.3e}", flush=True)
+    assert np.all(err <= TENSOR_TOL), (label, err)
+
+
+def _five_body_box():
+    pos, spc, cell = synth.water_box(8, 24.84, seed=91)
+    return synth.Frames(np.array([0, len(spc)], np.int64), pos, spc, cell[None], np.ones((1, 3), np.uint8))
+
+
+CASES = [
+    ("water_dipole_small", lambda: synth.water_small(10), "water 10 x 192"),
+    ("water_polarizability", lambda: synth.water_small(3, seed=2), "water 3 x 192"),
+    ("molecule_dipole", lambda: synth.molecules(96, seed=5), "96 molecules"),
+    ("molecule_polarizability", lambda: synth.molecules(96, seed=6), "96 molecules"),
+    ("perovskite_susceptibility", lambda: synth.perovskite(2, n_rep=4), "perovskite 4^3"),
+    ("water_dipole_5b", _five_body_box, "water 1536, five-body"),
+    ("water_polarizability_5b", lambda: synth.water_small(2, seed=3), "water 2 x 192, five-body"),
+]
+
+
+@pytest.mark.parametrize("name,make,label", CASES, ids=[c[0] for c in CASES])
+def test_matches_oracle_and_default_layout(gpu_lib, ctxs, name, make, label):
+    pp, plain = ctxs
+    m = synth.model(name)
+    fr = make()
+    nt = 3 if m.kind == 1 else 9
+    pa_pp, pa_plain = np.zeros((fr.n_atoms, nt)), np.zeros((fr.n_atoms, nt))
+    a = _eval(gpu_lib, pp, m, fr, per_atom=pa_pp)
+    b = _eval(gpu_lib, plain, m, fr, per_atom=pa_plain)
+    _check(a, m, fr, label + " (pair-parallel)")
+    # the same pair terms in another order: per-atom terms agree to FP32 rounding
+    scale = np.abs(pa_plain).max()
+    assert np.abs(pa_pp - pa_plain).max() <= 1e-5 * scale, np.abs(pa_pp - pa_plain).max() / scale
+
+
+def test_per_species_networks(gpu_lib, ctxs):
+    pp, _ = ctxs
+    a = synth.model("molecule_polarizability")
+    seed, kind, species, desc = synth.MODEL_SPECS["molecule_polarizability"]
+    b = synth.with_descriptor_of(synth.make_model(seed + 50, kind, species, **desc), a)
+    m = synth.per_species_model([a, b], [0, 1, 0, 1, 0])
+    fr = synth.molecules(64, seed=82)
+    _check(_eval(gpu_lib, pp, m, fr), m, fr, "per-species networks (pair-parallel)")
+
+
+def test_deterministic_and_batch_invariant(gpu_lib, ctxs):
+    pp, _ = ctxs
+    m = synth.model("molecule_polarizability")
+    fr = synth.molecules(120, seed=9)
+    a = _eval(gpu_lib, pp, m, fr)
+    assert np.array_equal(a, _eval(gpu_lib, pp, m, fr))
+    c2 = gpu_lib.Context(0)
+    c2.set_option(gpu_lib.OPT_PAIR_PARALLEL, 1)
+    c2.set_option(gpu_lib.OPT_MAX_BATCH_ATOMS, 400)  # many small launch batches
+    assert np.array_equal(a, _eval(gpu_lib, c2, m, fr))
+    c2.close()
+    assert np.array_equal(_eval(gpu_lib, pp, m, fr.subset([41]))[0], a[41])
+
+
+def test_both_models_one_call_and_edge_cases(gpu_lib, ctxs):
+    pp, _ = ctxs
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    mol = synth.molecules(3, seed=4)
+    parts = [synth.Frames(np.array([0, 0], np.int64), np.zeros((0, 3)), np.zeros(0, np.int32)),
+             mol.subset([0]),
+             synth.Frames(np.array([0, 1], np.int64), np.zeros((1, 3)), np.array([2], np.int32)),
+             synth.Frames(np.array([0, 2], np.int64), np.array([[0, 0, 0], [10.0, 0, 0]]), np.array([1, 3], np.int32)),
+             mol.subset([1, 2])]
+    fr = synth.Frames.concat(parts)
+    gd, gp = gpu_lib.Model(pp, md), gpu_lib.Model(pp, mp)
+    mu, al = gpu_lib.tnep_eval_dipole_polarizability(pp, gd, gp, fr)
+    gd.close()
+    gp.close()
+    assert np.all(mu[[0, 2, 3]] == 0.0) and np.all(al[0] == 0.0)
+    _check(mu, md, fr, "edge cases, dipole (pair-parallel)")
+    _check(al, mp, fr, "edge cases, polarizability (pair-parallel)")
+
+
+def test_potential_energy_keeps_default_layout(gpu_lib, ctxs):
+    pp, plain = ctxs
+    m = synth.model("water_pes")
+    fr = synth.water_small(2, seed=5)
+    outs = []
+    for c in (pp, plain):
+        mdl = gpu_lib.Model(c, m)
+        outs.append(gpu_lib.tnep_eval_pes(c, mdl, fr))
+        mdl.close()
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y)
