@@ -805,10 +805,24 @@ def config_legs(args):
     err = frame_errors(mu.cpu().numpy(), ref, pa, frames.offsets).max()
     rl = _eval_roofline(ctx, m, step, steps, tnep.KERNEL_EVAL_DIPOLE)
     rl["kernel"] = "k_eval<dipole>"
+    # the same call in the pair-parallel layout (16 lanes per atom, for calls of few atoms)
+    pctx = tnep.Context(0)
+    pctx.set_option(tnep.OPT_PAIR_PARALLEL, 1)
+    pgm = tnep.Model(pctx, m)
+    pmu = torch.zeros_like(mu)
+    pstep = lambda: tnep.tnep_eval_dipole(pctx, pgm, dfr, pmu)  # noqa: E731
+    tp = _timed(pstep, 4 * steps, args.warmup + 1)
+    perr = frame_errors(pmu.cpu().numpy(), ref, pa, frames.offsets).max()
+    prl = _eval_roofline(pctx, m, pstep, steps, tnep.KERNEL_EVAL_DIPOLE)
+    prl["kernel"] = "k_eval<dipole>, 16 lanes per atom"
     legs["water_small_dipole"] = {
         "workload": "64 H2O (192 atoms), 12.42 A periodic box, 10 independent frames, dipole model",
         "value": frames.n_atoms / t, "unit": "atom-frames/s", "ms_per_call": 1e3 * t, "dtype": "f32",
-        "max_frame_error_vs_oracle": float(err), "error_frames": "all 10", "roofline": rl}
+        "max_frame_error_vs_oracle": float(err), "error_frames": "all 10", "roofline": rl,
+        "pair_parallel": {"value": frames.n_atoms / tp, "ms_per_call": 1e3 * tp,
+                          "max_frame_error_vs_oracle": float(perr), "roofline": prl}}
+    pgm.close()
+    pctx.close()
     gm.close()
     ctx.close()
 

@@ -509,6 +509,10 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             for (int k = first; k < last; ++k)
                 if (job.models[k]->kind == TNEP_KIND_PES) rec_stride = pes_rec_stride(job.models[k]->shape, T);
             const bool pes = rec_stride > 0;
+            // the pair-parallel layout searches frames without a cell grid with its own
+            // kernel (no radial sums: potential-energy models, which load them, keep
+            // the default search)
+            const bool pair_search = c->launch.pair_parallel != 0 && !pes;
             const BatchBytes bb{T, slots, last - first, fr.location == TNEP_HOST, rec_stride};
             const int64_t per_atom_bytes = bb.per_atom();
             int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
@@ -757,7 +761,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                           triclinic ? (const FrameTric*)c->frames_tric.p : nullptr, cap_frames, pos,
                                           spc, cap_atoms,
                                           (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl, cl,
-                                          n_ref_lists > 0, followers, triclinic, (int32_t*)c->flags.p,
+                                          n_ref_lists > 0, followers, triclinic, pair_search, (int32_t*)c->flags.p,
                                           c->launch.neigh_block, (float*)c->rad_sums.p, c->stream);
                     c->timer_end(tr);
                     if (he != hipSuccess) return he;

@@ -497,7 +497,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                                                       const double4* __restrict__ bucket_pos,
                                                       const int4* __restrict__ cell_rec, float rc_radial,
                                                       float rc_angular, NeighborLists nl, CandLists cl,
-                                                      int32_t* __restrict__ flags, float* __restrict__ rad_v) {
+                                                      int32_t* __restrict__ flags, float* __restrict__ rad_v,
+                                                      bool pair_parallel) {
     // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
     extern __shared__ float4 nb_stage[];
     float4* stage = nb_stage + threadIdx.x;
@@ -520,8 +521,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     }
     const FrameInfo fi = frames[frame_of[a]];  // by value: kept in registers across the stores below
     // followers: k_neighbors_follow, after the reference lists are complete;
-    // triclinic frames: k_neighbors_tri
-    if (fi.role != (REF ? kRoleReference : kRolePlain) || fi.tric) return;
+    // triclinic frames: k_neighbors_tri; with pair_parallel, frames without a
+    // cell grid: k_neighbors_pp
+    if (fi.role != (REF ? kRoleReference : kRolePlain) || fi.tric || (pair_parallel && fi.mode == 0)) return;
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
     const float rcR_inv = 1.f / rc_radial;
@@ -689,6 +691,90 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(ps.nr, ps.capR);
         if (ps.na > ps.capA) atomicMax(&flags[kFlagCapAng + t], ps.na);
         if (ps.nr > ps.capR) atomicMax(&flags[kFlagCapRad + t], ps.nr);
+    }
+    if (overlap) {
+        atomicOr(&flags[kFlagError], kErrOverlap);
+        atomicMin(&flags[kFlagBadAtom], call_atom(nl.meta, a));
+    }
+}
+
+// Frames without a cell grid (vacuum frames and boxes narrower than 2.5 r_c,
+// where every atom of the frame is a candidate, with the rounding minimum
+// image), for the pair-parallel evaluation layout: kPairLanes lanes per atom,
+// lane g testing the candidates g, g + G, ... of each species range, two per
+// iteration.  Accepted pairs keep the candidates' order: a pair's row is the
+// number of pairs accepted before it, counted over the group's lanes with a
+// ballot, and each lane stores its rows itself.  The radial descriptor sums
+// are left to the evaluation kernel, which forms them in this layout.
+__global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __restrict__ frames,
+                                                         const int32_t* __restrict__ frame_of,
+                                                         const double* __restrict__ pos,
+                                                         const int32_t* __restrict__ perm_start,
+                                                         const double4* __restrict__ bucket_pos, float rc_radial,
+                                                         float rc_angular, NeighborLists nl,
+                                                         int32_t* __restrict__ flags) {
+    constexpr int G = kPairLanes;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = tid / G;  // tile slot (the whole group takes the same branches below)
+    const int g = (int)(tid % G);
+    if (p >= nl.n_pad) return;
+    const int a = nl.perm[p];
+    if (a < 0) return;  // padding: k_neighbors writes its zero counts
+    const FrameInfo fi = frames[frame_of[a]];
+    if (fi.mode != 0 || fi.tric || fi.role != kRolePlain) return;
+    const int T = nl.T;
+    const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
+    const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
+    float4* lane_base = nl.entries + ((int64_t)(p >> 6) * (nl.slots >> 2) * 64 + (p & 63)) * 4;
+    const int first = (int)(threadIdx.x & 63) & ~(G - 1);  // first lane of the group in the wave
+    const uint32_t before = (1u << g) - 1;                  // lanes of the group below this one
+    bool overlap = false;
+    for (int t = 0; t < T; ++t) {
+        const int b0 = perm_start[fi.cell_base * T + t];
+        const int n = perm_start[(fi.cell_base + 1) * T + t] - b0;
+        float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
+        float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
+        const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
+        int na = 0, nr = 0;  // rows so far (equal in the group's lanes)
+        for (int q0 = 0; q0 < n; q0 += 2 * G) {
+            double4 cur[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int q = q0 + u * G + g;
+                cur[u] = q < n ? bucket_pos[b0 + q] : make_double4(0.0, 0.0, 0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int q = q0 + u * G + g;
+                const int j = b0 + q;
+                const double dx = min_image(cur[u].x - xi, fi.L[0], fi.Linv[0]);
+                const double dy = min_image(cur[u].y - yi, fi.L[1], fi.Linv[1]);
+                const double dz = min_image(cur[u].z - zi, fi.L[2], fi.Linv[2]);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const bool in = (q < n) & (j != (int)p) & (r2 < rc2r);
+                const bool ang = in && r2 < rc2a, rad = in && !(r2 < rc2a);
+                overlap |= in && r2 < 1e-8;
+                const uint32_t ma = (uint32_t)(__ballot(ang) >> first) & 0xFFFFu;
+                const uint32_t mr = (uint32_t)(__ballot(rad) >> first) & 0xFFFFu;
+                const float4 e = make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
+                if (ang) {
+                    const int row = na + __popc(ma & before);
+                    if (row < capA) ga[(int64_t)(row >> 2) * 256 + (row & 3)] = e;
+                }
+                if (rad) {
+                    const int row = nr + __popc(mr & before);
+                    if (row < capR) gr[(int64_t)(row >> 2) * 256 + (row & 3)] = e;
+                }
+                na += __popc(ma);
+                nr += __popc(mr);
+            }
+        }
+        if (g == 0) {
+            nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(na, capA);
+            nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(nr, capR);
+            if (na > capA) atomicMax(&flags[kFlagCapAng + t], na);
+            if (nr > capR) atomicMax(&flags[kFlagCapRad + t], nr);
+        }
     }
     if (overlap) {
         atomicOr(&flags[kFlagError], kErrOverlap);
@@ -997,7 +1083,8 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, 
                             const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
-                            bool triclinic, int32_t* d_flags, int neigh_block, float* rad_sums, hipStream_t s) {
+                            bool triclinic, bool pair_parallel, int32_t* d_flags, int neigh_block, float* rad_sums,
+                            hipStream_t s) {
     if (cap_atoms == 0 || cap_frames == 0) return hipSuccess;
     const int nb = (neigh_block == 64 || neigh_block == 128) ? neigh_block : kBlock;
     const int T = nl.T;
@@ -1020,11 +1107,15 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, 
     const size_t list_bytes = sizeof(float4) * 9 * nb;  // staging + per-wave flush lists
     k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                               w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
-                                                              rc_radial, rc_angular, nl, cl, d_flags, rad_sums);
+                                                              rc_radial, rc_angular, nl, cl, d_flags, rad_sums,
+                                                              pair_parallel);
+    if (pair_parallel)  // n_pad is a multiple of 64: whole work-groups
+        k_neighbors_pp<<<(unsigned)(nl.n_pad * kPairLanes / kBlock), kBlock, 0, s>>>(
+            d_frames, w.frame_of, pos, w.perm_start, w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
     if (references)
         k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                  w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
-                                                                 rc_radial, rc_angular, nl, cl, d_flags, rad_sums);
+                                                                 rc_radial, rc_angular, nl, cl, d_flags, rad_sums, false);
     if (triclinic)
         k_neighbors_tri<<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, d_tric, w.frame_of, pos, w.key_of, w.perm_start,
                                                                w.bucket_pos, w.cell_rec, rc_radial, rc_angular, nl,

@@ -126,3 +126,46 @@ def test_potential_energy_keeps_default_layout(gpu_lib, ctxs):
         mdl.close()
     for x, y in zip(outs[0], outs[1]):
         assert np.array_equal(x, y)
+
+
+def test_grid_and_all_pairs_frames_in_one_call(gpu_lib, ctxs):
+    """One call mixing frames searched on a cell grid (24.84 A box: the default
+    search) and frames searched all-pairs (molecules, 12.42 A boxes: the
+    pair-parallel search), both evaluated in the pair-parallel layout."""
+    pp, _ = ctxs
+    m = synth.model("water_polarizability")
+    mp = synth.model("molecule_polarizability")
+    pos, spc, cell = synth.water_box(8, 24.84, seed=93)
+    big = synth.Frames(np.array([0, len(spc)], np.int64), pos, spc, cell[None], np.ones((1, 3), np.uint8))
+    fr = synth.Frames.concat([synth.water_small(2, seed=11), big, synth.water_small(1, seed=12)])
+    _check(_eval(gpu_lib, pp, m, fr), m, fr, "mixed grid / all-pairs water (pair-parallel)")
+    mol = synth.molecules(40, seed=13)
+    _check(_eval(gpu_lib, pp, mp, mol), mp, mol, "molecules (pair-parallel)")
+
+
+def test_graph_replay_matches_plain_launches(gpu_lib):
+    import torch
+
+    plain = gpu_lib.Context(0)
+    graph = gpu_lib.Context(0)
+    for c in (plain, graph):
+        c.set_option(gpu_lib.OPT_PAIR_PARALLEL, 1)
+    graph.set_option(gpu_lib.OPT_GRAPHS, 1)
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    pd_, pp_ = gpu_lib.Model(plain, md), gpu_lib.Model(plain, mp)
+    gd_, gp_ = gpu_lib.Model(graph, md), gpu_lib.Model(graph, mp)
+    mols = synth.molecules(32, seed=33)
+    for rep in range(3):
+        for s, n in [(0, 5), (9, 6), (20, 7)]:
+            fr = mols.subset(range(s, s + n))
+            g = gpu_lib.tnep_eval_dipole_polarizability(graph, gd_, gp_, fr)
+            torch.cuda.synchronize()
+            p = gpu_lib.tnep_eval_dipole_polarizability(plain, pd_, pp_, fr)
+            for a, b in zip(g, p):
+                assert np.array_equal(a, b), (rep, s, n)
+    captures, launches = graph.graph_counts()
+    assert launches >= 9
+    for x in (pd_, pp_, gd_, gp_):
+        x.close()
+    plain.close()
+    graph.close()
