@@ -433,6 +433,58 @@ def bench_variants(args):
         "variants": results}), flush=True)
 
 
+def bench_latency(args):
+    """Calls of few atoms on device-resident frames, one synchronous call at a
+    time, in the default layout (one lane per atom) and the pair-parallel
+    layout (TNEP_OPT_PAIR_PARALLEL: 16 lanes per atom): mean wall time per call
+    and the evaluation kernels' mean time per call (HIP events)."""
+    import torch
+
+    from paper_2312_05233_amd import tnep
+
+    mol = synth.molecules(64, seed=3)
+    water = synth.water_small(10)
+    mu_m, al_m = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    cases = [("10 x 192 water atoms, dipole", water, [synth.model("water_dipole_small")]),
+             ("1 x 192 water atoms, dipole + polarizability", water.subset([0]),
+              [synth.model("water_dipole"), synth.model("water_polarizability")]),
+             ("1 molecule, dipole + polarizability", mol.subset([0]), [mu_m, al_m]),
+             ("64 molecules, dipole + polarizability", mol, [mu_m, al_m])]
+    n = max(args.steps, 50)
+    out = []
+    for label, frames, models in cases:
+        rec = {"workload": label, "atoms": frames.n_atoms}
+        for pp in (0, 1):
+            ctx = tnep.Context(0)
+            ctx.set_option(tnep.OPT_PAIR_PARALLEL, pp)
+            gm = [tnep.Model(ctx, m) for m in models]
+            dfr = tnep.DeviceFrames(frames)
+            mu = torch.zeros((frames.n_frames, 3), dtype=torch.float64, device="cuda")
+            al = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
+            if len(gm) == 2:
+                step = lambda: tnep.tnep_eval_dipole_polarizability(ctx, gm[0], gm[1], dfr, mu, al)  # noqa: E731
+            else:
+                step = lambda: tnep.tnep_eval_dipole(ctx, gm[0], dfr, mu)  # noqa: E731
+
+            def one_call():
+                step()
+                torch.cuda.synchronize()
+
+            t = _timed(one_call, n, 5)
+            ctx.set_option(tnep.OPT_TIMING, 1)
+            ctx.reset_timing()
+            for _ in range(n):
+                one_call()
+            ev = sum(ctx.kernel_time(k)[0] for k in (tnep.KERNEL_EVAL_DIPOLE, tnep.KERNEL_EVAL_POLARIZABILITY)) / n
+            rec["pair_parallel" if pp else "default"] = {"us_per_call": 1e6 * t, "eval_kernels_us_per_call": 1e3 * ev}
+            for g in gm:
+                g.close()
+            ctx.close()
+        out.append(rec)
+    print(json.dumps({"metric": "latency of one synchronous call", "unit": "us", "n_gpus": 1, "calls": n,
+                      "data": "synthetic", "cases": out}), flush=True)
+
+
 def bench_spectra(args):
     """Paper-scale Raman spectra of a recorded susceptibility: 20 runs of
     10^5 samples (500 ps at 5 fs), pushed through the streaming accumulator in
@@ -897,7 +949,7 @@ def main():
                     help="frames per neighbour-candidate window of the trajectory (0 = plain searches)")
     ap.add_argument("--skin", type=float, default=1.0, help="candidate skin in Angstrom")
     ap.add_argument("--workload", default="water", choices=["water", "perovskite", "molecules", "serving", "pes", "spectra",
-                                                              "population", "variants"],
+                                                              "population", "variants", "latency"],
                     help="water: the headline line; the others print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
@@ -924,7 +976,7 @@ def main():
     if args.workload != "water":
         {"perovskite": bench_perovskite, "molecules": bench_molecules, "serving": bench_serving,
          "pes": bench_pes, "spectra": bench_spectra, "population": bench_population,
-         "variants": bench_variants}[args.workload](args)
+         "variants": bench_variants, "latency": bench_latency}[args.workload](args)
         return
 
     dev = torch.device("cuda:0")

@@ -608,6 +608,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 int64_t n_ref_lists = 0;  // candidate lists of the batch's reference frames (CandLists)
                 bool followers = false, triclinic = false;
                 bool small_frames = false, large_frames = false;  // frame-sum kernels the batch needs
+                bool plain_grid = false;  // plain frames on an orthorhombic cell grid
                 int ref_k = -1;  // reference frame of the open window
                 for (int k = 0; k < nf; ++k) {
                     const int f = f0 + k;
@@ -644,6 +645,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         x.Linv[d] = (g.per[d] && !g.tric) ? 1.0 / g.L[d] : 0.0;
                     }
                     x.tric = g.tric;
+                    if (g.mode == 1 && !g.tric && x.role == kRolePlain) plain_grid = true;
                     if (g.mode == 1) {
                         // fixed-point unit of the cell records: offsets within a cell (in A,
                         // or in fractional units for triclinic bins) stay below 2^30 units
@@ -761,7 +763,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                           triclinic ? (const FrameTric*)c->frames_tric.p : nullptr, cap_frames, pos,
                                           spc, cap_atoms,
                                           (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl, cl,
-                                          n_ref_lists > 0, followers, triclinic, pair_search, (int32_t*)c->flags.p,
+                                          n_ref_lists > 0, followers, triclinic, pair_search, plain_grid,
+                                          (int32_t*)c->flags.p,
                                           c->launch.neigh_block, (float*)c->rad_sums.p, c->stream);
                     c->timer_end(tr);
                     if (he != hipSuccess) return he;
@@ -814,6 +817,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     if (triclinic) key += "/tric";
                     // which frame-sum kernels run (frames of at most / above kSmallFrame atoms)
                     key += small_frames ? (large_frames ? "/s11" : "/s10") : "/s01";
+                    // whether the plain cell-grid search runs beside the pair-parallel one
+                    if (pair_search) key += plain_grid ? "/g1" : "/g0";
                     // device-resident frames: the caller's buffers the kernels read and write
                     if (fr.location == TNEP_DEVICE) {
                         char db[64];

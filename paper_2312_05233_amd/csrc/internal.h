@@ -183,13 +183,14 @@ struct NeighborWork {
 // triclinic: the batch has triclinic frames (a pass of their own).
 // pair_parallel: frames without a cell grid are searched with kPairLanes lanes
 // per atom (for the pair-parallel evaluation layout, which forms the radial
-// sums itself: rad_sums are not written for them).
+// sums itself: rad_sums are not written for them).  plain_grid: the batch has
+// plain (not trajectory, not triclinic) frames on an orthorhombic cell grid.
 hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, int cap_frames, const double* pos,
                             const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
-                            bool triclinic, bool pair_parallel, int32_t* d_flags, int neigh_block, float* rad_sums,
-                            hipStream_t s);
+                            bool triclinic, bool pair_parallel, bool plain_grid, int32_t* d_flags, int neigh_block,
+                            float* rad_sums, hipStream_t s);
 
 // ---- evaluation (kernels_eval.hip) ----
 struct EvalLaunch {

@@ -692,7 +692,9 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 // kSmallFrame atoms are left to k_frame_reduce_small: one wavefront per frame,
 // lane l takes atoms l, l + 64, ..., then the shuffle tree; it stores the sum
 // as chunk 0 and zeros as chunks 1..3.  k_frame_finish adds the chunk sums in
-// chunk order.  The order depends only on the frame's atom count, never on
+// chunk order.  A batch of small frames only skips k_frame_finish: the small
+// kernel stores 0 + sum itself, which is what the chunk order gives bit for bit
+// (the zero chunks add nothing; 0 + (-0) = +0 as there).  The order depends only on the frame's atom count, never on
 // how frames were batched; the chunks spread a launch batch of large frames
 // over all compute units, and a batch of small frames takes one wavefront,
 // not sixteen, per frame.
@@ -700,7 +702,9 @@ constexpr int kReduceBlock = 256;
 __global__ void __launch_bounds__(kReduceBlock) k_frame_reduce_small(const FrameInfo* __restrict__ frames,
                                                                      const int32_t* __restrict__ meta,
                                                                      const double* __restrict__ per_atom, int nt,
-                                                                     double* __restrict__ part_out) {
+                                                                     double* __restrict__ part_out, int na,
+                                                                     double* __restrict__ out_a,
+                                                                     double* __restrict__ out_b, bool direct) {
     const int f = blockIdx.x * (kReduceBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (f >= meta[kMetaNFrames]) return;
@@ -723,6 +727,19 @@ __global__ void __launch_bounds__(kReduceBlock) k_frame_reduce_small(const Frame
             for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
             s[k] = v;
         }
+    }
+    if (direct) {
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                if (k >= nt) continue;
+                const double v = 0.0 + s[k];
+                if (k < na)
+                    out_a[(int64_t)f * na + k] = v;
+                else if (out_b)
+                    out_b[(int64_t)f * (nt - na) + k - na] = v;
+            }
+        return;
     }
     if (lane < kReduceChunks) {
         double* o = part_out + ((int64_t)f * kReduceChunks + lane) * 10;
@@ -1070,9 +1087,11 @@ hipError_t launch_frame_reduce(const FrameInfo* d_frames, int cap_frames, const 
                                int nt, int na, double* part, double* out_a, double* out_b, bool small, bool large,
                                hipStream_t s) {
     if (cap_frames == 0) return hipSuccess;
+    const bool direct = small && !large;
     if (small)
         k_frame_reduce_small<<<(unsigned)((cap_frames + kReduceBlock / 64 - 1) / (kReduceBlock / 64)), kReduceBlock, 0,
-                               s>>>(d_frames, meta, per_atom, nt, part);
+                               s>>>(d_frames, meta, per_atom, nt, part, na, out_a, out_b, direct);
+    if (direct) return hipGetLastError();
     if (large)
         k_frame_reduce<<<dim3(cap_frames, kReduceChunks), kReduceBlock, 0, s>>>(d_frames, meta, per_atom, nt, part);
     const int64_t n = (int64_t)cap_frames * nt;

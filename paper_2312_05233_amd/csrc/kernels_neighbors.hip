@@ -32,6 +32,8 @@
 //      candidates per column (two where the column crosses the box face).
 // Entries are grouped four to a lane (64 contiguous bytes), so every store and
 // load of a wavefront covers one contiguous 4 KB block.
+#include <algorithm>
+
 #include "internal.h"
 #include "radial_basis.h"
 
@@ -41,17 +43,19 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__global__ void k_frame_of(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ meta,
-                           int32_t* __restrict__ frame_of) {
+// Set-up of a launch batch in one launch: work-group f < (frames) writes the
+// frame index of frame f's atoms; thread i clears bucket count i and marks tile
+// slot i as padding.
+__global__ void k_batch_setup(const FrameInfo* __restrict__ frames, const int32_t* __restrict__ meta,
+                              int32_t* __restrict__ frame_of, int32_t* __restrict__ bucket_count, int64_t n_buckets,
+                              int32_t* __restrict__ perm, int64_t n_pad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_buckets) bucket_count[i] = 0;
+    if (i < n_pad) perm[i] = -1;
     const int f = blockIdx.x;
     if (f >= meta[kMetaNFrames]) return;
     const FrameInfo fi = frames[f];
     for (int64_t a = threadIdx.x; a < fi.n_atoms; a += blockDim.x) frame_of[fi.atom_begin + a] = f;
-}
-
-__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
 }
 
 // Index of batch atom a in the whole call (for error reports), saturated.
@@ -243,6 +247,52 @@ __global__ void __launch_bounds__(256) k_scan_final(const int32_t* __restrict__ 
         }
         if (c0 < c1 && c1 == n_cells) perm_start[n_cells * T + t] = run;
     }
+}
+
+// All three scan phases in one work-group, for batches of at most kScanCells
+// cells (one chunk): the same offsets as k_scan_partials, k_scan_chunks and
+// k_scan_final give for a single chunk.
+__global__ void __launch_bounds__(256) k_scan_one(const int32_t* __restrict__ count, int32_t* __restrict__ meta,
+                                                  int T, int32_t* __restrict__ bucket_start,
+                                                  int32_t* __restrict__ bucket_fill, int32_t* __restrict__ perm_start) {
+    __shared__ int32_t part[256];
+    __shared__ int32_t s_total;
+    const int n_cells = meta[kMetaNCells];
+    const int c0 = threadIdx.x * 4;
+    const int c1 = min(c0 + 4, n_cells);
+    // key order (cell-major, species-minor)
+    {
+        int32_t s = 0;
+        for (int c = c0; c < c1; ++c)
+            for (int u = 0; u < T; ++u) s += count[c * T + u];
+        int32_t run = block_exclusive_256(s, part);
+        for (int c = c0; c < c1; ++c)
+            for (int u = 0; u < T; ++u) {
+                bucket_start[c * T + u] = run;
+                bucket_fill[c * T + u] = 0;
+                run += count[c * T + u];
+            }
+        if (threadIdx.x == 255) bucket_start[n_cells * T] = run;
+    }
+    // species-major order, each species padded to whole 64-slot tiles
+    int32_t tiles = 0;
+    for (int t = 0; t < T; ++t) {
+        int32_t s = 0;
+        for (int c = c0; c < c1; ++c) s += count[c * T + t];
+        int32_t run = block_exclusive_256(s, part) + tiles * 64;
+        for (int c = c0; c < c1; ++c) {
+            perm_start[c * T + t] = run;
+            run += count[c * T + t];
+        }
+        if (c0 < c1 && c1 == n_cells) perm_start[n_cells * T + t] = run;
+        if (threadIdx.x == 255) s_total = run - tiles * 64;
+        __syncthreads();
+        const int32_t total = s_total;
+        if (threadIdx.x == 0) meta[kMetaTileBase + t] = tiles;
+        tiles += (total + 63) / 64;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) meta[kMetaTileBase + T] = tiles;
 }
 
 __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
@@ -719,10 +769,17 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __rest
     const int g = (int)(tid % G);
     if (p >= nl.n_pad) return;
     const int a = nl.perm[p];
-    if (a < 0) return;  // padding: k_neighbors writes its zero counts
+    const int T = nl.T;
+    if (a < 0) {  // padding slot (k_neighbors writes the same zeros when it runs)
+        if (g == 0)
+            for (int t = 0; t < T; ++t) {
+                nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = 0;
+                nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = 0;
+            }
+        return;
+    }
     const FrameInfo fi = frames[frame_of[a]];
     if (fi.mode != 0 || fi.tric || fi.role != kRolePlain) return;
-    const int T = nl.T;
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
     float4* lane_base = nl.entries + ((int64_t)(p >> 6) * (nl.slots >> 2) * 64 + (p & 63)) * 4;
@@ -1083,29 +1140,36 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, 
                             const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
-                            bool triclinic, bool pair_parallel, int32_t* d_flags, int neigh_block, float* rad_sums,
-                            hipStream_t s) {
+                            bool triclinic, bool pair_parallel, bool plain_grid, int32_t* d_flags, int neigh_block,
+                            float* rad_sums, hipStream_t s) {
     if (cap_atoms == 0 || cap_frames == 0) return hipSuccess;
     const int nb = (neigh_block == 64 || neigh_block == 128) ? neigh_block : kBlock;
     const int T = nl.T;
     const int cap_buckets = cap_cells * T;
     const int cap_chunks = (cap_cells + kScanCells - 1) / kScanCells;
-    k_frame_of<<<cap_frames, kBlock, 0, s>>>(d_frames, nl.meta, w.frame_of);
-    k_fill_i32<<<blocks_for(cap_buckets, kBlock), kBlock, 0, s>>>(w.bucket_count, cap_buckets, 0);
-    k_fill_i32<<<blocks_for(nl.n_pad, kBlock), kBlock, 0, s>>>(w.perm, nl.n_pad, -1);
+    const int64_t setup_threads = std::max<int64_t>({(int64_t)cap_frames * kBlock, (int64_t)cap_buckets, nl.n_pad});
+    k_batch_setup<<<blocks_for(setup_threads, kBlock), kBlock, 0, s>>>(d_frames, nl.meta, w.frame_of, w.bucket_count,
+                                                                      cap_buckets, w.perm, nl.n_pad);
     k_bin<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, d_tric, w.frame_of, pos, species, nl.meta, T, w.key_of,
                                                           w.bucket_count, d_flags);
-    k_scan_partials<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk);
-    k_scan_chunks<<<1, 256, 0, s>>>(w.chunk, T, w.chunk + 9 * cap_chunks, w.meta, w.bucket_start);
-    k_scan_final<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk + 9 * cap_chunks, w.bucket_start,
-                                           w.bucket_fill, w.perm_start);
+    if (cap_chunks == 1) {
+        k_scan_one<<<1, 256, 0, s>>>(w.bucket_count, w.meta, T, w.bucket_start, w.bucket_fill, w.perm_start);
+    } else {
+        k_scan_partials<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk);
+        k_scan_chunks<<<1, 256, 0, s>>>(w.chunk, T, w.chunk + 9 * cap_chunks, w.meta, w.bucket_start);
+        k_scan_final<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk + 9 * cap_chunks, w.bucket_start,
+                                               w.bucket_fill, w.perm_start);
+    }
     k_scatter<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill,
                                                               w.bucket_atoms, nl.meta);
     k_sort_place<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, d_tric, w.frame_of, w.key_of, w.bucket_start,
                                                                  w.bucket_atoms, w.perm_start, w.perm, w.slot_of, pos,
                                                                  w.bucket_pos, w.cell_rec, nl.meta, T);
     const size_t list_bytes = sizeof(float4) * 9 * nb;  // staging + per-wave flush lists
-    k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
+    // with pair_parallel and no plain cell-grid frame, k_neighbors_pp covers every
+    // slot k_neighbors would (frames without a grid and the padding)
+    if (!pair_parallel || plain_grid)
+        k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                               w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
                                                               rc_radial, rc_angular, nl, cl, d_flags, rad_sums,
                                                               pair_parallel);
