@@ -25,6 +25,16 @@ __global__ void k_init_flags(int32_t* f) {
     if (threadIdx.x < 32) f[threadIdx.x] = threadIdx.x == kFlagBadAtom ? INT_MAX : 0;
 }
 
+// Device-resident frame metadata (atom offsets, cells, periodic flags) gathered
+// into pinned host memory by one launch: dst = [offsets | cells | pbc].
+__global__ void k_gather_meta(const int64_t* __restrict__ offs, int64_t n_offs, const double* __restrict__ cells,
+                              int64_t n_cells, const uint8_t* __restrict__ pbc, int64_t n_pbc, char* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_offs) reinterpret_cast<int64_t*>(dst)[i] = offs[i];
+    if (i < n_cells) reinterpret_cast<double*>(dst + 8 * n_offs)[i] = cells[i];
+    if (i < n_pbc) reinterpret_cast<uint8_t*>(dst + 8 * (n_offs + n_cells))[i] = pbc[i];
+}
+
 }  // namespace
 
 hipError_t launch_init_flags(int32_t* d_flags, hipStream_t s) {
@@ -224,11 +234,15 @@ int fetch_meta(Ctx* c, const tnep_frames& fr, HostMeta& m) {
             e = hipHostMalloc((void**)&c->rb_host, need, hipHostMallocDefault);
             if (e == hipSuccess) c->rb_host_bytes = need;
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(c->rb_host, fr.atom_offsets, ob, hipMemcpyDeviceToHost, nullptr);
-        if (e == hipSuccess && fr.cells)
-            e = hipMemcpyAsync(c->rb_host + ob, fr.cells, cb, hipMemcpyDeviceToHost, nullptr);
-        if (e == hipSuccess && fr.pbc)
-            e = hipMemcpyAsync(c->rb_host + ob + cb, fr.pbc, pb, hipMemcpyDeviceToHost, nullptr);
+        if (e == hipSuccess && !fr.cells && !fr.pbc) {
+            e = hipMemcpyAsync(c->rb_host, fr.atom_offsets, ob, hipMemcpyDeviceToHost, nullptr);
+        } else if (e == hipSuccess) {
+            // one gather launch instead of a copy per array
+            const int64_t n_max = std::max<int64_t>({(int64_t)F + 1, (int64_t)(cb / 8), (int64_t)pb});
+            k_gather_meta<<<(unsigned)((n_max + 255) / 256), 256, 0, nullptr>>>(
+                fr.atom_offsets, F + 1, fr.cells, (int64_t)(cb / 8), fr.pbc, (int64_t)pb, c->rb_host);
+            e = hipGetLastError();
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) return c->fail(TNEP_E_HIP, "reading frame metadata: %s", hipGetErrorString(e));
         std::memcpy(m.offs.data(), c->rb_host, ob);
@@ -532,20 +546,6 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             if ((e = c->reserve(c->nbr, (size_t)n_pad_max * slots * sizeof(float4)))) return e;
             if ((e = c->reserve(c->counts, (size_t)n_pad_max * 2 * T * 4))) return e;
             if ((e = c->reserve(c->perm, (size_t)n_pad_max * 4))) return e;
-            if ((e = c->reserve(c->tile_base, sizeof(int32_t) * kMetaInts))) return e;
-            {
-                int32_t h[kMetaInts] = {0};
-                for (int t = 0; t < T; ++t) {
-                    h[kMetaSegA + t] = segA[t];
-                    h[kMetaSegR + t] = segR[t];
-                    h[kMetaCapA + t] = c->cap_ang[t];
-                    h[kMetaCapR + t] = c->cap_rad[t];
-                }
-                // only the host part: the tile bases are written by the scan kernel
-                HIP_CHECK_RET(c, hipMemcpyAsync((int32_t*)c->tile_base.p + kMetaSegA, h + kMetaSegA,
-                                                sizeof(int32_t) * (kMetaNAtoms - kMetaSegA), hipMemcpyHostToDevice,
-                                                c->stream));
-            }
             if ((e = c->reserve(c->frame_of, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->slot_of, (size_t)B_res * 4))) return e;
             if ((e = c->reserve(c->key_of, (size_t)B_res * 4))) return e;
@@ -575,11 +575,16 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             }
             HIP_CHECK_RET(c, launch_init_flags((int32_t*)c->flags.p, c->stream));
 
-            // FrameInfo and sizes of every launch batch, staged in pinned host
-            // memory (alive until the sync below) so that their copies are
-            // plain DMA: copies from pageable memory went through host-side
-            // staging and left the device idle before every batch
-            const size_t fi_bytes = sizeof(FrameInfo) * (size_t)F, sizes_bytes = 16 * (size_t)F + 256;
+            // Header of every launch batch, staged in pinned host memory (alive
+            // until the sync below) so that its copy is plain DMA: the meta ints
+            // the host writes (segment table, capacities, sizes) followed by the
+            // FrameInfo records, one copy per batch into the device header
+            // (tile_base: the meta ints, then the records at kHeaderFrames).
+            // Copies from pageable memory went through host-side staging and
+            // left the device idle before every batch.
+            constexpr size_t kHostMeta = sizeof(int32_t) * (kMetaInts - kMetaSegA);
+            static_assert(kHostMeta % 32 == 0 && kHeaderFrames == sizeof(int32_t) * kMetaInts, "header layout");
+            const size_t fi_bytes = (sizeof(FrameInfo) + kHostMeta) * (size_t)F, sizes_bytes = 256;
             const size_t meta_need = fi_bytes + sizes_bytes + sizeof(FrameTric) * (size_t)F;
             if (c->meta_host_bytes < meta_need) {
                 if (c->meta_host) (void)hipHostFree(c->meta_host);
@@ -588,8 +593,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 HIP_CHECK_RET(c, hipHostMalloc((void**)&c->meta_host, meta_need, hipHostMallocDefault));
                 c->meta_host_bytes = meta_need;
             }
-            FrameInfo* fi_next = reinterpret_cast<FrameInfo*>(c->meta_host);
-            int32_t* sizes_next = reinterpret_cast<int32_t*>(c->meta_host + fi_bytes);
+            char* hdr_next = c->meta_host;
             FrameTric* tri_next = reinterpret_cast<FrameTric*>(c->meta_host + fi_bytes + sizes_bytes);
             int f0 = 0;
             while (f0 < F) {
@@ -598,12 +602,12 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if (f1 == f0) f1 = f0 + 1;
                 const int nf = f1 - f0;
                 const int64_t a0 = meta.offs[f0], na = meta.offs[f1] - a0;
-                FrameInfo* fi = fi_next;
-                int32_t* sizes = sizes_next;
+                // host meta ints kMetaSegA.. (int index k at hmeta[k - kMetaSegA]), then the records
+                int32_t* hmeta = reinterpret_cast<int32_t*>(hdr_next);
+                FrameInfo* fi = reinterpret_cast<FrameInfo*>(hdr_next + kHostMeta);
                 FrameTric* tri = tri_next;
-                fi_next += nf;
+                hdr_next += kHostMeta + sizeof(FrameInfo) * nf;
                 tri_next += nf;
-                sizes_next += 4;
                 int n_cells = 0;
                 int64_t n_ref_lists = 0;  // candidate lists of the batch's reference frames (CandLists)
                 bool followers = false, triclinic = false;
@@ -671,7 +675,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 const int64_t cap_cells = graphs ? pow2_at_least(n_cells) : n_cells;
                 const int64_t n_buckets = cap_cells * T;
                 if (n_buckets >= ((int64_t)1 << 30)) return c->fail(TNEP_E_INVALID, "too many cells in one batch");
-                if ((e = c->reserve(c->frames, sizeof(FrameInfo) * cap_frames))) return e;
+                if ((e = c->reserve(c->tile_base, kHeaderFrames + sizeof(FrameInfo) * cap_frames))) return e;
                 if (triclinic && (e = c->reserve(c->frames_tric, sizeof(FrameTric) * cap_frames))) return e;
                 if (n_ref_lists > 0) {
                     if ((e = c->reserve(c->cand, (size_t)n_ref_lists * T * c->cap_cand * 4))) return e;
@@ -685,14 +689,20 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 const int nt_max = 10;
                 if ((e = c->reserve(c->out, sizeof(double) * nt_max * cap_frames * (last - first)))) return e;
                 if ((e = c->reserve(c->red_part, sizeof(double) * 10 * kReduceChunks * cap_frames))) return e;
-                sizes[0] = (int32_t)na;
-                sizes[1] = nf;
-                sizes[2] = n_cells;
-                sizes[3] = (int32_t)std::min<int64_t>(a0, INT32_MAX);
-                HIP_CHECK_RET(c, hipMemcpyAsync((int32_t*)c->tile_base.p + kMetaNAtoms, sizes, sizeof(int32_t) * 4,
-                                                hipMemcpyHostToDevice, c->stream));
-                HIP_CHECK_RET(c, hipMemcpyAsync(c->frames.p, fi, sizeof(FrameInfo) * nf, hipMemcpyHostToDevice,
-                                                c->stream));
+                std::memset(hmeta, 0, kHostMeta);
+                for (int t = 0; t < T; ++t) {
+                    hmeta[kMetaSegA - kMetaSegA + t] = segA[t];
+                    hmeta[kMetaSegR - kMetaSegA + t] = segR[t];
+                    hmeta[kMetaCapA - kMetaSegA + t] = c->cap_ang[t];
+                    hmeta[kMetaCapR - kMetaSegA + t] = c->cap_rad[t];
+                }
+                hmeta[kMetaNAtoms - kMetaSegA] = (int32_t)na;
+                hmeta[kMetaNFrames - kMetaSegA] = nf;
+                hmeta[kMetaNCells - kMetaSegA] = n_cells;
+                hmeta[kMetaAtomBase - kMetaSegA] = (int32_t)std::min<int64_t>(a0, INT32_MAX);
+                // not the tile bases (ints below kMetaSegA): the scan kernel writes them
+                HIP_CHECK_RET(c, hipMemcpyAsync((int32_t*)c->tile_base.p + kMetaSegA, hmeta,
+                                                kHostMeta + sizeof(FrameInfo) * nf, hipMemcpyHostToDevice, c->stream));
                 if (triclinic)
                     HIP_CHECK_RET(c, hipMemcpyAsync(c->frames_tric.p, tri, sizeof(FrameTric) * nf, hipMemcpyHostToDevice,
                                                     c->stream));
@@ -759,7 +769,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 auto launch_batch = [&]() -> hipError_t {
                     hipError_t he;
                     int tr = c->timer_begin(TNEP_KERNEL_NEIGHBORS);
-                    he = launch_neighbors((const FrameInfo*)c->frames.p,
+                    he = launch_neighbors((const FrameInfo*)((char*)c->tile_base.p + kHeaderFrames),
                                           triclinic ? (const FrameTric*)c->frames_tric.p : nullptr, cap_frames, pos,
                                           spc, cap_atoms,
                                           (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl, cl,
@@ -783,7 +793,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;
                         tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);
-                        he = launch_frame_reduce((const FrameInfo*)c->frames.p, cap_frames, nl.meta, pa_of[q],
+                        he = launch_frame_reduce((const FrameInfo*)((char*)c->tile_base.p + kHeaderFrames), cap_frames, nl.meta, pa_of[q],
                                                  nt_of[q], na_of[q], (double*)c->red_part.p, out_of[q], aux_of[q],
                                                  small_frames, large_frames, c->stream);
                         c->timer_end(tr);

@@ -120,6 +120,10 @@ enum Meta {
     kMetaAtomBase = 51,  // index of the batch's first atom in the call (saturated at INT32_MAX)
     kMetaInts = 56
 };
+// Device header of a launch batch: the kMetaInts meta ints, then the batch's
+// FrameInfo records from this byte offset on (one host-to-device copy fills
+// both, from kMetaSegA on).
+constexpr size_t kHeaderFrames = sizeof(int32_t) * kMetaInts;
 
 struct NeighborLists {
     float4* entries;

@@ -63,7 +63,8 @@ struct Ctx {
     size_t rb_host_bytes = 0;
 
     // work buffers
-    DevBuf frames, frames_tric, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, bucket_pos, perm_start;
+    DevBuf frames_tric, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, bucket_pos, perm_start;
+    // tile_base: the launch batch's device header (meta ints, then its FrameInfo records)
     DevBuf perm, tile_base, scan_chunks, nbr, counts, per_atom, out, pos, species;
     DevBuf spec_work, spec_series, spec_out;
     DevBuf pes_rec, pes_stage, pes_pair, pes_slot;  // potential-energy models: per-atom records, host-bound staging,
@@ -77,7 +78,7 @@ struct Ctx {
     size_t pop_host_bytes = 0;
 
     std::vector<DevBuf*> all_buffers() {
-        return {&frames,   &frames_tric, &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
+        return {&frames_tric, &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
                 &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &pes_pair, &pes_slot, &slot_of, &cand, &cand_count, &com,
                 &pop_stage, &pop_work, &pop_img, &red_part, &rad_sums};
