@@ -169,3 +169,25 @@ def test_graph_replay_matches_plain_launches(gpu_lib):
         x.close()
     plain.close()
     graph.close()
+
+
+def test_triclinic_and_trajectory_frames(gpu_lib):
+    """Lists from the triclinic search and from trajectory candidate reuse
+    (reference and follower frames) evaluated in the pair-parallel layout."""
+    shear = np.array([[1, 0, 0], [1, 1, 0], [0, 1, 1]], np.float64)
+    pos, spc, cell = synth.water_box(8, 24.84, seed=94)
+    R, _ = np.linalg.qr(np.random.default_rng(95).normal(size=(3, 3)))
+    H = cell.reshape(3, 3)
+    n = len(spc)
+    tri = synth.Frames(np.array([0, n, 2 * n], np.int64), np.concatenate([pos, pos @ R.T]),
+                       np.tile(spc, 2).astype(np.int32), np.stack([shear @ H, H @ R.T]).reshape(2, 9),
+                       np.ones((2, 3), np.uint8))
+    traj = synth.ou_trajectory(pos, spc, cell, 6, seed=96)
+    m = synth.model("water_polarizability")
+    c = gpu_lib.Context(0)
+    c.set_option(gpu_lib.OPT_PAIR_PARALLEL, 1)
+    _check(_eval(gpu_lib, c, m, tri), m, tri, "triclinic (pair-parallel)")
+    c.set_option(gpu_lib.OPT_TRAJECTORY_WINDOW, 3)
+    _check(_eval(gpu_lib, c, m, traj), m, traj, "trajectory reuse (pair-parallel)")
+    assert c.reuse_fallbacks() == 0
+    c.close()
