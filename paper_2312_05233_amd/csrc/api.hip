@@ -125,6 +125,10 @@ tnep::Ctx::~Ctx() {
     if (meta_host) (void)hipHostFree(meta_host);
     if (rb_host) (void)hipHostFree(rb_host);
     if (pop_host) (void)hipHostFree(pop_host);
+    if (side) (void)hipStreamSynchronize(side);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    if (side) (void)hipStreamDestroy(side);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 

@@ -273,7 +273,7 @@ uint64_t BatchBytes::bound(int64_t atoms, int64_t frames) const {
     const int64_t cells = 2 * atoms + 125 * frames;
     const int64_t buckets = cells * T + T + 1;
     const int64_t fixed = 16 * buckets + 72 * (cells / 1024 + 1) + (int64_t)frames * (sizeof(FrameInfo) + 80 * n_models +
-                                                                                        80 * kReduceChunks) +
+                                                                                        80 * kReduceChunks * n_models) +
                           4 * kMetaInts + 32 * 4 + 64;
     const int64_t bytes = per_atom() * atoms + (per_atom() - 16 - 80 * (int64_t)n_models) * (n_pad - atoms) + fixed;
     // reserve() grows a buffer to at least 1.25 times its previous size
@@ -688,7 +688,16 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 if ((e = c->reserve(c->scan_chunks, (size_t)4 * 18 * (cap_cells / 1024 + 1)))) return e;
                 const int nt_max = 10;
                 if ((e = c->reserve(c->out, sizeof(double) * nt_max * cap_frames * (last - first)))) return e;
-                if ((e = c->reserve(c->red_part, sizeof(double) * 10 * kReduceChunks * cap_frames))) return e;
+                if ((e = c->reserve(c->red_part, sizeof(double) * 10 * kReduceChunks * cap_frames * (last - first))))
+                    return e;
+                // models after the first alternate with it on a second stream (not while
+                // timing: the timing events are recorded on the context's stream)
+                const bool two_streams = last - first >= 2 && !c->timing && c->stream != nullptr;
+                if (two_streams && !c->side) {
+                    HIP_CHECK_RET(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+                    HIP_CHECK_RET(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+                    HIP_CHECK_RET(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+                }
                 std::memset(hmeta, 0, kHostMeta);
                 for (int t = 0; t < T; ++t) {
                     hmeta[kMetaSegA - kMetaSegA + t] = segA[t];
@@ -782,29 +791,39 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         he = launch_count_pairs(nl, (unsigned long long*)c->counters.p, c->stream);
                         if (he != hipSuccess) return he;
                     }
+                    if (two_streams) {
+                        if ((he = hipEventRecord(c->fork_ev, c->stream)) != hipSuccess) return he;
+                        if ((he = hipStreamWaitEvent(c->side, c->fork_ev, 0)) != hipSuccess) return he;
+                    }
                     for (int k = first; k < last; ++k) {
                         const Model* m = job.models[k];
                         const int q = k - first;
+                        hipStream_t sq = (two_streams && (q & 1)) ? c->side : c->stream;
                         tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE           ? TNEP_KERNEL_EVAL_DIPOLE
                                             : m->kind == TNEP_KIND_POLARIZABILITY ? TNEP_KERNEL_EVAL_POLARIZABILITY
                                                                                   : TNEP_KERNEL_EVAL_PES);
                         const RadSums rs{(float*)c->rad_sums.p, 2};
-                        he = launch_eval(m->shape, m->dm, nl, pa_of[q], pes_out, rs, c->launch, c->stream);
+                        he = launch_eval(m->shape, m->dm, nl, pa_of[q], pes_out, rs, c->launch, sq);
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;
                         tr = c->timer_begin(TNEP_KERNEL_FRAME_REDUCE);
-                        he = launch_frame_reduce((const FrameInfo*)((char*)c->tile_base.p + kHeaderFrames), cap_frames, nl.meta, pa_of[q],
-                                                 nt_of[q], na_of[q], (double*)c->red_part.p, out_of[q], aux_of[q],
-                                                 small_frames, large_frames, c->stream);
+                        he = launch_frame_reduce((const FrameInfo*)((char*)c->tile_base.p + kHeaderFrames), cap_frames,
+                                                 nl.meta, pa_of[q], nt_of[q], na_of[q],
+                                                 (double*)c->red_part.p + (size_t)10 * kReduceChunks * cap_frames * q,
+                                                 out_of[q], aux_of[q], small_frames, large_frames, sq);
                         c->timer_end(tr);
                         if (he != hipSuccess) return he;
                         if (m->kind == TNEP_KIND_PES) {
                             tr = c->timer_begin(TNEP_KERNEL_PES_FORCES);
                             he = launch_pes_forces(m->shape, m->dm, nl, pes_out, pa_of[q], forces_dst, energies_dst,
-                                                   c->launch.atoms_per_block, c->stream);
+                                                   c->launch.atoms_per_block, sq);
                             c->timer_end(tr);
                             if (he != hipSuccess) return he;
                         }
+                    }
+                    if (two_streams) {
+                        if ((he = hipEventRecord(c->join_ev, c->side)) != hipSuccess) return he;
+                        if ((he = hipStreamWaitEvent(c->stream, c->join_ev, 0)) != hipSuccess) return he;
                     }
                     return hipSuccess;
                 };

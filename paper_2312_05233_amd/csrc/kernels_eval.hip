@@ -236,6 +236,15 @@ __host__ __device__ constexpr int mlp_lds_floats(int D, int H) {
     return 64 * (((D + 31) / 32 * 32 + 4) + ((H + 31) / 32 * 32 + 4));
 }
 
+// Row counts of one species' two segments of a slot.
+struct SegCounts {
+    int n_ang, n_rad;
+    __device__ __forceinline__ void fetch(const NeighborLists& nl, int64_t p, int t) {
+        n_ang = nl.counts[(int64_t)(2 * t) * nl.n_pad + p];
+        n_rad = nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
+    }
+};
+
 // One lane per tile slot (atom).  The coefficient blocks c[t_i][t] are
 // wave-uniform and read with scalar loads.  MODE selects the hidden layer:
 // FP32 vector ALU (no LDS) or one of the matrix-core variants (LDS tile per
@@ -279,11 +288,16 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
 #pragma unroll
         for (int c = 0; c < kLM; ++c) A[n][c] = 0.f;
 
+    // a species' row counts are loaded while the species before it runs, so that
+    // its pass does not begin with two dependent loads (counts, then entries)
+    SegCounts ahead;
+    ahead.fetch(nl, p, 0);
     for (int t = 0; t < T; ++t) {
         const float* __restrict__ cR = m.c_radial + (ti * T + t) * (NR * KR);
         const float* __restrict__ cA = m.c_angular + (ti * T + t) * (NA * KA);
-        const int n_ang = nl.counts[(int64_t)(2 * t) * nl.n_pad + p];
-        const int n_rad = nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
+        const SegCounts cur = ahead;
+        if (t + 1 < T) ahead.fetch(nl, p, t + 1);
+        const int n_ang = cur.n_ang, n_rad = cur.n_rad;
         const float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
         const float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
         // sum over neighbours of species t of f_k(r_ij) = (sum fc T_k + sum fc) / 2
@@ -455,7 +469,7 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
     } else {
         extern __shared__ float lds[];
         float* wl = lds + (threadIdx.x >> 6) * mlp_lds_floats(D, m.n_hidden);
-        mlp_matrix<D, KIND, MODE>(m, qs, dq, Us, wl, lane);
+        mlp_matrix<D, KIND, MODE>(m, qs, dq, Us, wl, (int)(threadIdx.x & 63));
     }
 
     // G_nlm = dU/dA_nlm, stored over A.
@@ -539,12 +553,14 @@ __global__ void __launch_bounds__(256, 2) k_eval(DevModel m, NeighborLists nl, d
         }
     };
 
+    ahead.fetch(nl, p, 0);
     for (int t = 0; t < T; ++t) {
         const float* __restrict__ cR = m.c_radial + (ti * T + t) * (NR * KR);
         const float* __restrict__ cA = m.c_angular + (ti * T + t) * (NA * KA);
         const float* __restrict__ cAd = m.c_angular_d + (ti * T + t) * (NA * KA);
-        const int n_ang = nl.counts[(int64_t)(2 * t) * nl.n_pad + p];
-        const int n_rad = nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p];
+        const SegCounts cur = ahead;
+        if (t + 1 < T) ahead.fetch(nl, p, t + 1);
+        const int n_ang = cur.n_ang, n_rad = cur.n_rad;
         const float4* ga = lane_base + (int64_t)(nl.meta[kMetaSegA + t] >> 2) * 256;
         const float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
         // d/dr of sum_n dU/dq^R_n g^R_n(r) = sum_k Dk[k] f_k'(r)

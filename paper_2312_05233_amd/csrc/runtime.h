@@ -36,6 +36,11 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // second stream for the models of a call after the first (every second model
+    // runs on it, forked from and joined back into stream by the two events), so
+    // that one model's last wavefronts overlap the next model's first
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     uint64_t budget = 0;
     uint64_t in_use = 0;
     uint64_t peak = 0;
