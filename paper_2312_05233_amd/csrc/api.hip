@@ -124,8 +124,15 @@ tnep::Ctx::~Ctx() {
     if (h_flags) (void)hipHostFree(h_flags);
     if (meta_host) (void)hipHostFree(meta_host);
     if (rb_host) (void)hipHostFree(rb_host);
+    if (in_host) (void)hipHostFree(in_host);
     if (pop_host) (void)hipHostFree(pop_host);
     if (side) (void)hipStreamSynchronize(side);
+    if (copy_stream) (void)hipStreamSynchronize(copy_stream);
+    for (int h = 0; h < 2; ++h) {
+        if (in_copied[h]) (void)hipEventDestroy(in_copied[h]);
+        if (in_used[h]) (void)hipEventDestroy(in_used[h]);
+    }
+    if (copy_stream) (void)hipStreamDestroy(copy_stream);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (join_ev) (void)hipEventDestroy(join_ev);
     if (side) (void)hipStreamDestroy(side);

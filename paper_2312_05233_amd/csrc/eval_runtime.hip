@@ -263,7 +263,7 @@ int64_t BatchBytes::per_atom() const {
     const int64_t per_slot = (int64_t)slots * 16 + 8 * T + 4 + 48 + 4 * T * kRadialTerms +
                              (pes_rec_stride > 0 ? 4 * (int64_t)pes_rec_stride + (int64_t)slots * 20 : 0);
     // per atom: frame_of, slot_of, key_of, bucket_atoms; per-atom records; staged inputs
-    const int64_t per_atom = 16 + 80 * (int64_t)n_models + (host ? 28 : 0) + (pes_rec_stride > 0 && host ? 32 : 0);
+    const int64_t per_atom = 16 + 80 * (int64_t)n_models + (host ? 56 : 0) + (pes_rec_stride > 0 && host ? 32 : 0);
     return per_slot + per_atom;
 }
 
@@ -565,9 +565,31 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             // with KR = kRadialTerms load them
             if ((e = c->reserve(c->rad_sums, (size_t)n_pad_max * T * kRadialTerms * sizeof(float)))) return e;
             if ((e = c->reserve(c->flags, 32 * 4))) return e;
+            // host frames in several launch batches: two input halves, the next batch's
+            // inputs copied on a stream of their own while this one is evaluated (a call
+            // of one batch copies on the context's stream: no stream more per context)
+            const bool overlap_inputs = fr.location == TNEP_HOST && A > B;
             if (fr.location == TNEP_HOST) {
-                if ((e = c->reserve(c->pos, (size_t)B_res * 24))) return e;
-                if ((e = c->reserve(c->species, (size_t)B_res * 4))) return e;
+                if ((e = c->reserve(c->pos, (size_t)B_res * (overlap_inputs ? 48 : 24)))) return e;
+                if ((e = c->reserve(c->species, (size_t)B_res * (overlap_inputs ? 8 : 4)))) return e;
+                // every frame's outputs, copied back to the caller once at the end
+                if ((e = c->reserve(c->out_call, sizeof(double) * 10 * (size_t)F * (last - first)))) return e;
+            }
+            if (overlap_inputs) {
+                if (c->in_host_bytes < (size_t)B_res * 56) {
+                    if (c->in_host) (void)hipHostFree(c->in_host);
+                    c->in_host = nullptr;
+                    c->in_host_bytes = 0;
+                    HIP_CHECK_RET(c, hipHostMalloc((void**)&c->in_host, (size_t)B_res * 56, hipHostMallocDefault));
+                    c->in_host_bytes = (size_t)B_res * 56;
+                }
+                if (!c->copy_stream) {
+                    HIP_CHECK_RET(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+                    for (int h = 0; h < 2; ++h) {
+                        HIP_CHECK_RET(c, hipEventCreateWithFlags(&c->in_copied[h], hipEventDisableTiming));
+                        HIP_CHECK_RET(c, hipEventCreateWithFlags(&c->in_used[h], hipEventDisableTiming));
+                    }
+                }
             }
             if (c->timing && !c->counters.p) {
                 if ((e = c->reserve(c->counters, 64))) return e;
@@ -596,6 +618,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             char* hdr_next = c->meta_host;
             FrameTric* tri_next = reinterpret_cast<FrameTric*>(c->meta_host + fi_bytes + sizes_bytes);
             int f0 = 0;
+            int batch = 0;  // launch batches of this pass (host frames alternate input halves)
             while (f0 < F) {
                 int f1 = f0;
                 while (f1 < F && meta.offs[f1 + 1] - meta.offs[f0] <= B) ++f1;
@@ -717,13 +740,32 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                                     c->stream));
                 const double* pos;
                 const int32_t* spc;
-                if (fr.location == TNEP_HOST) {
+                const int half = overlap_inputs ? (batch & 1) : 0;
+                if (fr.location == TNEP_HOST && !overlap_inputs) {
                     HIP_CHECK_RET(c, hipMemcpyAsync(c->pos.p, fr.positions + 3 * a0, (size_t)na * 24,
                                                     hipMemcpyHostToDevice, c->stream));
                     HIP_CHECK_RET(c, hipMemcpyAsync(c->species.p, fr.species + a0, (size_t)na * 4,
                                                     hipMemcpyHostToDevice, c->stream));
                     pos = (const double*)c->pos.p;
                     spc = (const int32_t*)c->species.p;
+                } else if (fr.location == TNEP_HOST) {
+                    // staging half: free once the copy out of it two batches ago is done;
+                    // device half: free once the batch that read it two batches ago is done
+                    char* stage = c->in_host + (size_t)half * B_res * 28;
+                    double* dpos = (double*)c->pos.p + (size_t)half * B_res * 3;
+                    int32_t* dspc = (int32_t*)c->species.p + (size_t)half * B_res;
+                    if (batch >= 2) HIP_CHECK_RET(c, hipEventSynchronize(c->in_copied[half]));
+                    std::memcpy(stage, fr.positions + 3 * a0, (size_t)na * 24);
+                    std::memcpy(stage + (size_t)B_res * 24, fr.species + a0, (size_t)na * 4);
+                    if (batch >= 2) HIP_CHECK_RET(c, hipStreamWaitEvent(c->copy_stream, c->in_used[half], 0));
+                    HIP_CHECK_RET(c, hipMemcpyAsync(dpos, stage, (size_t)na * 24, hipMemcpyHostToDevice,
+                                                    c->copy_stream));
+                    HIP_CHECK_RET(c, hipMemcpyAsync(dspc, stage + (size_t)B_res * 24, (size_t)na * 4,
+                                                    hipMemcpyHostToDevice, c->copy_stream));
+                    HIP_CHECK_RET(c, hipEventRecord(c->in_copied[half], c->copy_stream));
+                    HIP_CHECK_RET(c, hipStreamWaitEvent(c->stream, c->in_copied[half], 0));
+                    pos = dpos;
+                    spc = dspc;
                 } else {
                     pos = fr.positions + 3 * a0;
                     spc = fr.species + a0;
@@ -844,6 +886,8 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         key += pb;
                     }
                     if (triclinic) key += "/tric";
+                    // host frames: the input half the kernels read
+                    if (fr.location == TNEP_HOST) key += half ? "/h1" : "/h0";
                     // which frame-sum kernels run (frames of at most / above kSmallFrame atoms)
                     key += small_frames ? (large_frames ? "/s11" : "/s10") : "/s01";
                     // whether the plain cell-grid search runs beside the pair-parallel one
@@ -868,15 +912,19 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     HIP_CHECK_RET(c, launch_batch());
                 }
                 if (fr.location == TNEP_HOST) {
+                    if (overlap_inputs) HIP_CHECK_RET(c, hipEventRecord(c->in_used[half], c->stream));
                     for (int k = first; k < last; ++k) {
                         const int q = k - first;
                         const int na_ = na_of[q];
-                        HIP_CHECK_RET(c, hipMemcpyAsync(job.out[k] + (size_t)f0 * na_, out_of[q],
-                                                        sizeof(double) * na_ * nf, hipMemcpyDeviceToHost, c->stream));
+                        // tensors (and virials) into the call's output buffer: device copies,
+                        // so the host goes on staging the next batch
+                        double* oc = (double*)c->out_call.p + (size_t)10 * F * q;
+                        HIP_CHECK_RET(c, hipMemcpyAsync(oc + (size_t)f0 * na_, out_of[q], sizeof(double) * na_ * nf,
+                                                        hipMemcpyDeviceToDevice, c->stream));
                         if (job.models[k]->kind == TNEP_KIND_PES) {
                             if (job.aux[k])
-                                HIP_CHECK_RET(c, hipMemcpyAsync(job.aux[k] + (size_t)f0 * 9, aux_of[q],
-                                                                sizeof(double) * 9 * nf, hipMemcpyDeviceToHost,
+                                HIP_CHECK_RET(c, hipMemcpyAsync(oc + (size_t)F * na_ + (size_t)f0 * 9, aux_of[q],
+                                                                sizeof(double) * 9 * nf, hipMemcpyDeviceToDevice,
                                                                 c->stream));
                             if (job.forces)
                                 HIP_CHECK_RET(c, hipMemcpyAsync(job.forces + a0 * 3, forces_dst,
@@ -894,6 +942,20 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     }
                 }
                 f0 = f1;
+                ++batch;
+            }
+            if (fr.location == TNEP_HOST) {
+                for (int k = first; k < last; ++k) {
+                    const int q = k - first;
+                    const int kind = job.models[k]->kind;
+                    const int na_ = kind == TNEP_KIND_DIPOLE ? 3 : (kind == TNEP_KIND_POLARIZABILITY ? 9 : 1);
+                    const double* oc = (const double*)c->out_call.p + (size_t)10 * F * q;
+                    HIP_CHECK_RET(c, hipMemcpyAsync(job.out[k], oc, sizeof(double) * na_ * F, hipMemcpyDeviceToHost,
+                                                    c->stream));
+                    if (kind == TNEP_KIND_PES && job.aux[k])
+                        HIP_CHECK_RET(c, hipMemcpyAsync(job.aux[k], oc + (size_t)F * na_, sizeof(double) * 9 * F,
+                                                        hipMemcpyDeviceToHost, c->stream));
+                }
             }
             HIP_CHECK_RET(c, hipMemcpyAsync(c->h_flags, c->flags.p, sizeof(int32_t) * 32, hipMemcpyDeviceToHost,
                                             c->stream));

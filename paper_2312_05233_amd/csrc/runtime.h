@@ -66,6 +66,14 @@ struct Ctx {
     size_t meta_host_bytes = 0;
     char* rb_host = nullptr;          // pinned staging of device-resident frame metadata read back
     size_t rb_host_bytes = 0;
+    // Host frames: positions and species of two launch batches in pinned memory
+    // and in two device halves (pos, species), copied on copy_stream while the
+    // other half's batch is evaluated; in_copied[h] marks the copy into half h,
+    // in_used[h] the end of the batch that read it.
+    char* in_host = nullptr;
+    size_t in_host_bytes = 0;
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t in_copied[2] = {nullptr, nullptr}, in_used[2] = {nullptr, nullptr};
 
     // work buffers
     DevBuf frames_tric, flags, frame_of, key_of, bucket_count, bucket_start, bucket_fill, bucket_atoms, bucket_pos, perm_start;
@@ -76,6 +84,7 @@ struct Ctx {
                                                     // pair forces, slots of the angular entries
     DevBuf slot_of, cand, cand_count;  // tile slot per atom; trajectory candidate lists
     DevBuf com;                        // charged-dipole shift: staging of frames, masses, charges, mu
+    DevBuf out_call;                   // host frames: every frame's outputs of a call, copied back once
     DevBuf red_part;                   // frame sums: per-chunk partial sums
     DevBuf rad_sums;                   // radial descriptor sums shared by the models of a call
     DevBuf pop_stage, pop_work, pop_img;  // population loss: staged frames, predictions, model images
@@ -86,7 +95,7 @@ struct Ctx {
         return {&frames_tric, &flags, &frame_of, &key_of, &bucket_count, &bucket_start, &bucket_fill,
                 &bucket_atoms, &bucket_pos, &perm_start, &perm, &tile_base, &scan_chunks, &nbr, &counts, &per_atom, &out, &pos, &species,
                 &spec_work, &spec_series, &spec_out, &counters, &pes_rec, &pes_stage, &pes_pair, &pes_slot, &slot_of, &cand, &cand_count, &com,
-                &pop_stage, &pop_work, &pop_img, &red_part, &rad_sums};
+                &pop_stage, &pop_work, &pop_img, &red_part, &rad_sums, &out_call};
     }
 
     Server* server = nullptr;
