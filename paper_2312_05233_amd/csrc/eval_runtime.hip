@@ -523,10 +523,9 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
             for (int k = first; k < last; ++k)
                 if (job.models[k]->kind == TNEP_KIND_PES) rec_stride = pes_rec_stride(job.models[k]->shape, T);
             const bool pes = rec_stride > 0;
-            // the pair-parallel layout searches frames without a cell grid with its own
-            // kernel (no radial sums: potential-energy models, which load them, keep
-            // the default search)
-            const bool pair_search = c->launch.pair_parallel != 0 && !pes;
+            // the pair-parallel evaluation layout (tensor models) searches frames without
+            // a cell grid with 16 lanes per atom and forms no radial sums
+            const bool pp_eval = c->launch.pair_parallel != 0 && !pes;
             const BatchBytes bb{T, slots, last - first, fr.location == TNEP_HOST, rec_stride};
             const int64_t per_atom_bytes = bb.per_atom();
             int64_t B = std::min<int64_t>(A, c->max_batch_atoms);
@@ -816,6 +815,12 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     }
                 }
                 const PesOut pes_out{(float*)c->pes_rec.p, rec_stride, (float4*)c->pes_pair.p, (int32_t*)c->pes_slot.p};
+                // Frames without a cell grid: in the pair-parallel layout always the 16-lane
+                // search; otherwise in batches of few atoms (whose time the one-lane search
+                // sets by one atom's walk over its frame) the 16-lane search with the radial
+                // sums, which gives the one-lane search's rows and sums bit for bit.
+                const bool pair_search = pp_eval || na <= kPairSearchAtoms;
+                const bool pair_radial = !pp_eval;
                 // the batch's kernels; with graphs on, captured once and replayed
                 auto launch_batch = [&]() -> hipError_t {
                     hipError_t he;
@@ -824,7 +829,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                                           triclinic ? (const FrameTric*)c->frames_tric.p : nullptr, cap_frames, pos,
                                           spc, cap_atoms,
                                           (int)cap_cells, (float)gm->rc_radial, (float)gm->rc_angular, w, nl, cl,
-                                          n_ref_lists > 0, followers, triclinic, pair_search, plain_grid,
+                                          n_ref_lists > 0, followers, triclinic, pair_search, pair_radial, plain_grid,
                                           (int32_t*)c->flags.p,
                                           c->launch.neigh_block, (float*)c->rad_sums.p, c->stream);
                     c->timer_end(tr);
@@ -891,7 +896,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     // which frame-sum kernels run (frames of at most / above kSmallFrame atoms)
                     key += small_frames ? (large_frames ? "/s11" : "/s10") : "/s01";
                     // whether the plain cell-grid search runs beside the pair-parallel one
-                    if (pair_search) key += plain_grid ? "/g1" : "/g0";
+                    if (pair_search) key += pair_radial ? (plain_grid ? "/rg1" : "/rg0") : (plain_grid ? "/g1" : "/g0");
                     // device-resident frames: the caller's buffers the kernels read and write
                     if (fr.location == TNEP_DEVICE) {
                         char db[64];

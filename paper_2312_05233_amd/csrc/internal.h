@@ -185,16 +185,18 @@ struct NeighborWork {
 // role has a pass over the slots of its own; followers run after the
 // reference frames' lists are complete).
 // triclinic: the batch has triclinic frames (a pass of their own).
-// pair_parallel: frames without a cell grid are searched with kPairLanes lanes
-// per atom (for the pair-parallel evaluation layout, which forms the radial
-// sums itself: rad_sums are not written for them).  plain_grid: the batch has
-// plain (not trajectory, not triclinic) frames on an orthorhombic cell grid.
+// pair_search: frames without a cell grid are searched with kPairLanes lanes
+// per atom (the same rows in the same order); pair_radial: that search also
+// forms their radial sums, bit for bit as the one-lane search does (else they
+// are not written: the pair-parallel evaluation layout forms them itself).
+// plain_grid: the batch has plain (not trajectory, not triclinic) frames on an
+// orthorhombic cell grid.
 hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, int cap_frames, const double* pos,
                             const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
-                            bool triclinic, bool pair_parallel, bool plain_grid, int32_t* d_flags, int neigh_block,
-                            float* rad_sums, hipStream_t s);
+                            bool triclinic, bool pair_search, bool pair_radial, bool plain_grid, int32_t* d_flags,
+                            int neigh_block, float* rad_sums, hipStream_t s);
 
 // ---- evaluation (kernels_eval.hip) ----
 struct EvalLaunch {
@@ -206,6 +208,12 @@ struct EvalLaunch {
 
 // Lanes per atom of the pair-parallel evaluation layout (one 16-lane DPP row).
 constexpr int kPairLanes = 16;
+// Launch batches of at most this many atoms search frames without a cell grid
+// with kPairLanes lanes per atom in every layout.  Below it the one-lane search
+// takes as long as one atom's walk over its frame; above it (vacuum molecules of
+// 20-80 atoms and 192-atom boxes alike: crossing near 35k atoms) the sixteen
+// times as many lanes cost more than they save.
+constexpr int64_t kPairSearchAtoms = 32768;
 
 // Potential-energy models: the evaluation kernel leaves, per atom a in tile
 // slot p, a record of rec_stride floats at rec + p * rec_stride (slots keep

@@ -487,15 +487,32 @@ struct RadialSums {
         for (int k = 0; k < kRadialTerms; ++k) FT[k] = 0.f;
         Fs = 0.f;
     }
-    __device__ __forceinline__ void add(float x, float y, float z, float rcR_inv) {
-        const float r = pair_sqrt(x * x + y * y + z * z);
-        const float fc = cutoff_fc(1.f - r * rcR_inv);
-        const float tt = r * rcR_inv - 1.f;
-        float Tk[kRadialTerms];
-        cheb_T<kRadialTerms>(2.f * tt * tt - 1.f, Tk);
-        Fs += fc;
+    // The terms of one pair from its FP32 entry: sf with f_c = sf^2, and T_k(x).
+    // Every step is an explicit product or fused multiply-add, so the sums come
+    // out bit for bit the same in every kernel that forms them (the compiler
+    // would otherwise fuse f_c = sf^2 into some of the additions and not others).
+    static __device__ __forceinline__ void terms(float x, float y, float z, float rcR_inv, float& sf,
+                                                 float (&Tk)[kRadialTerms]) {
+        const float r = pair_sqrt(__builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x)));
+        sf = sin_half_pi(1.57079632679489662f * __builtin_fmaf(-r, rcR_inv, 1.f));
+        const float tt = __builtin_fmaf(r, rcR_inv, -1.f);
+        const float xc = __builtin_fmaf(tt + tt, tt, -1.f);
+        Tk[0] = 1.f;
+        Tk[1] = xc;
 #pragma unroll
-        for (int k = 0; k < kRadialTerms; ++k) FT[k] += fc * Tk[k];
+        for (int k = 2; k < kRadialTerms; ++k) Tk[k] = __builtin_fmaf(xc + xc, Tk[k - 1], -Tk[k - 2]);
+    }
+    __device__ __forceinline__ void accumulate(float sf, const float (&Tk)[kRadialTerms]) {
+        Fs = __builtin_fmaf(sf, sf, Fs);
+        FT[0] = __builtin_fmaf(sf, sf, FT[0]);
+        const float fc = sf * sf;
+#pragma unroll
+        for (int k = 1; k < kRadialTerms; ++k) FT[k] = __builtin_fmaf(fc, Tk[k], FT[k]);
+    }
+    __device__ __forceinline__ void add(float x, float y, float z, float rcR_inv) {
+        float sf, Tk[kRadialTerms];
+        terms(x, y, z, rcR_inv, sf, Tk);
+        accumulate(sf, Tk);
     }
     // sum_j f_k(r_ij) for species t of slot p
     __device__ __forceinline__ void store(float* __restrict__ v, int t, int64_t n_pad, int64_t p) const {
@@ -548,7 +565,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                                                       const int4* __restrict__ cell_rec, float rc_radial,
                                                       float rc_angular, NeighborLists nl, CandLists cl,
                                                       int32_t* __restrict__ flags, float* __restrict__ rad_v,
-                                                      bool pair_parallel) {
+                                                      bool pair_search) {
     // 8 staged entries per lane (PairSink), then a 64-entry list per wave (coop_flush)
     extern __shared__ float4 nb_stage[];
     float4* stage = nb_stage + threadIdx.x;
@@ -571,9 +588,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     }
     const FrameInfo fi = frames[frame_of[a]];  // by value: kept in registers across the stores below
     // followers: k_neighbors_follow, after the reference lists are complete;
-    // triclinic frames: k_neighbors_tri; with pair_parallel, frames without a
+    // triclinic frames: k_neighbors_tri; with pair_search, frames without a
     // cell grid: k_neighbors_pp
-    if (fi.role != (REF ? kRoleReference : kRolePlain) || fi.tric || (pair_parallel && fi.mode == 0)) return;
+    if (fi.role != (REF ? kRoleReference : kRolePlain) || fi.tric || (pair_search && fi.mode == 0)) return;
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
     const float rcR_inv = 1.f / rc_radial;
@@ -754,15 +771,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
 // lane g testing the candidates g, g + G, ... of each species range, two per
 // iteration.  Accepted pairs keep the candidates' order: a pair's row is the
 // number of pairs accepted before it, counted over the group's lanes with a
-// ballot, and each lane stores its rows itself.  The radial descriptor sums
-// are left to the evaluation kernel, which forms them in this layout.
+// ballot, and each lane stores its rows itself.  These are the rows k_neighbors
+// writes for such frames, in the same order.  With rad_v, the radial
+// descriptor sums are formed as k_neighbors forms them, bit for bit: every lane
+// computes its accepted candidates' terms, then the group adds them in candidate
+// order (each term fetched from its lane), so a call's results do not depend
+// on which of the two searches ran; RAD = false (the pair-parallel evaluation
+// layout, which forms them itself) leaves them out.
+template <bool RAD>
 __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __restrict__ frames,
                                                          const int32_t* __restrict__ frame_of,
                                                          const double* __restrict__ pos,
                                                          const int32_t* __restrict__ perm_start,
                                                          const double4* __restrict__ bucket_pos, float rc_radial,
                                                          float rc_angular, NeighborLists nl,
-                                                         int32_t* __restrict__ flags) {
+                                                         int32_t* __restrict__ flags, float* __restrict__ rad_v) {
     constexpr int G = kPairLanes;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t p = tid / G;  // tile slot (the whole group takes the same branches below)
@@ -771,17 +794,22 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __rest
     const int a = nl.perm[p];
     const int T = nl.T;
     if (a < 0) {  // padding slot (k_neighbors writes the same zeros when it runs)
-        if (g == 0)
+        if (g == 0) {
+            RadialSums none;
+            none.clear();
             for (int t = 0; t < T; ++t) {
                 nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = 0;
                 nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = 0;
+                none.store(rad_v, t, nl.n_pad, p);
             }
+        }
         return;
     }
     const FrameInfo fi = frames[frame_of[a]];
     if (fi.mode != 0 || fi.tric || fi.role != kRolePlain) return;
     const double xi = pos[3 * a], yi = pos[3 * a + 1], zi = pos[3 * a + 2];
     const double rc2r = (double)rc_radial * rc_radial, rc2a = (double)rc_angular * rc_angular;
+    const float rcR_inv = 1.f / rc_radial;
     float4* lane_base = nl.entries + ((int64_t)(p >> 6) * (nl.slots >> 2) * 64 + (p & 63)) * 4;
     const int first = (int)(threadIdx.x & 63) & ~(G - 1);  // first lane of the group in the wave
     const uint32_t before = (1u << g) - 1;                  // lanes of the group below this one
@@ -793,7 +821,11 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __rest
         float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
         const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
         int na = 0, nr = 0;  // rows so far (equal in the group's lanes)
+        RadialSums rsum;     // equal in the group's lanes
+        rsum.clear();
         for (int q0 = 0; q0 < n; q0 += 2 * G) {
+            float sf[2] = {0.f, 0.f}, Tk[2][kRadialTerms] = {};
+            uint32_t acc[2];
             double4 cur[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -824,9 +856,29 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __rest
                 }
                 na += __popc(ma);
                 nr += __popc(mr);
+                acc[u] = ma | mr;
+                if (RAD && in) RadialSums::terms(e.x, e.y, e.z, rcR_inv, sf[u], Tk[u]);
+            }
+            if constexpr (RAD) {
+                // candidate order: u = 0 (lanes 0..15), then u = 1
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    uint32_t m = acc[u];
+                    while (__ballot(m != 0u)) {
+                        const bool has = m != 0u;
+                        const int src = first + (has ? __builtin_ctz(m) : 0);
+                        m &= m - 1u;
+                        float fs, ts[kRadialTerms];
+                        fs = __shfl(sf[u], src, 64);
+#pragma unroll
+                        for (int k = 0; k < kRadialTerms; ++k) ts[k] = __shfl(Tk[u][k], src, 64);
+                        if (has) rsum.accumulate(fs, ts);
+                    }
+                }
             }
         }
         if (g == 0) {
+            rsum.store(rad_v, t, nl.n_pad, p);
             nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(na, capA);
             nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(nr, capR);
             if (na > capA) atomicMax(&flags[kFlagCapAng + t], na);
@@ -1140,8 +1192,8 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, 
                             const int32_t* species,
                             int64_t cap_atoms, int cap_cells, float rc_radial, float rc_angular, const NeighborWork& w,
                             const NeighborLists& nl, const CandLists& cl, bool references, bool followers,
-                            bool triclinic, bool pair_parallel, bool plain_grid, int32_t* d_flags, int neigh_block,
-                            float* rad_sums, hipStream_t s) {
+                            bool triclinic, bool pair_search, bool pair_radial, bool plain_grid, int32_t* d_flags,
+                            int neigh_block, float* rad_sums, hipStream_t s) {
     if (cap_atoms == 0 || cap_frames == 0) return hipSuccess;
     const int nb = (neigh_block == 64 || neigh_block == 128) ? neigh_block : kBlock;
     const int T = nl.T;
@@ -1166,16 +1218,22 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, 
                                                                  w.bucket_atoms, w.perm_start, w.perm, w.slot_of, pos,
                                                                  w.bucket_pos, w.cell_rec, nl.meta, T);
     const size_t list_bytes = sizeof(float4) * 9 * nb;  // staging + per-wave flush lists
-    // with pair_parallel and no plain cell-grid frame, k_neighbors_pp covers every
+    // with pair_search and no plain cell-grid frame, k_neighbors_pp covers every
     // slot k_neighbors would (frames without a grid and the padding)
-    if (!pair_parallel || plain_grid)
+    if (!pair_search || plain_grid)
         k_neighbors<false><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                               w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,
                                                               rc_radial, rc_angular, nl, cl, d_flags, rad_sums,
-                                                              pair_parallel);
-    if (pair_parallel)  // n_pad is a multiple of 64: whole work-groups
-        k_neighbors_pp<<<(unsigned)(nl.n_pad * kPairLanes / kBlock), kBlock, 0, s>>>(
-            d_frames, w.frame_of, pos, w.perm_start, w.bucket_pos, rc_radial, rc_angular, nl, d_flags);
+                                                              pair_search);
+    if (pair_search) {  // n_pad is a multiple of 64: whole work-groups
+        const unsigned grid = (unsigned)(nl.n_pad * kPairLanes / kBlock);
+        if (pair_radial)
+            k_neighbors_pp<true><<<grid, kBlock, 0, s>>>(d_frames, w.frame_of, pos, w.perm_start, w.bucket_pos, rc_radial,
+                                                         rc_angular, nl, d_flags, rad_sums);
+        else
+            k_neighbors_pp<false><<<grid, kBlock, 0, s>>>(d_frames, w.frame_of, pos, w.perm_start, w.bucket_pos, rc_radial,
+                                                          rc_angular, nl, d_flags, nullptr);
+    }
     if (references)
         k_neighbors<true><<<blocks_for(nl.n_pad, nb), nb, list_bytes, s>>>(d_frames, w.frame_of, pos, species, w.slot_of,
                                                                  w.key_of, w.perm_start, w.bucket_pos, w.cell_rec,

@@ -354,3 +354,34 @@ def test_small_frame_sums_direct_and_in_mixed_batches(gpu_lib, ctx):
     _check(al_p.reshape(len(al_p), -1), mp, mixed, "150 molecules + 300-atom frame")
     gd.close()
     gp.close()
+
+
+def test_small_and_large_batch_searches_agree_bitwise(gpu_lib, ctx):
+    """Frames without a cell grid are searched with 16 lanes per atom in launch
+    batches of at most 32,768 atoms and with one lane per atom in larger ones;
+    both give the same rows and radial sums, so every tensor (and the
+    potential-energy outputs) is bitwise the same in either kind of batch."""
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    mols = synth.molecules(1600, seed=23)  # about 80,000 atoms: one batch above the bound
+    few = mols.subset(range(120))
+    gd, gp = gpu_lib.Model(ctx, md), gpu_lib.Model(ctx, mp)
+    mu_s, al_s = gpu_lib.tnep_eval_dipole_polarizability(ctx, gd, gp, few)
+    mu_l, al_l = gpu_lib.tnep_eval_dipole_polarizability(ctx, gd, gp, mols)
+    assert mols.n_atoms > 32768 >= few.n_atoms
+    assert np.array_equal(mu_s, mu_l[:120]) and np.array_equal(al_s, al_l[:120])
+    _check(al_s.reshape(len(al_s), -1), mp, few, "120 molecules, 16-lane search")
+    gd.close()
+    gp.close()
+    wd = synth.model("water_dipole_small")
+    boxes = synth.water_small(400, seed=24)  # 76,800 atoms of 12.42 A boxes (no cell grid)
+    g = gpu_lib.Model(ctx, wd)
+    assert np.array_equal(gpu_lib.tnep_eval_dipole(ctx, g, boxes.subset(range(7))),
+                          gpu_lib.tnep_eval_dipole(ctx, g, boxes)[:7])
+    g.close()
+    pm = synth.model("molecule_pes")
+    g = gpu_lib.Model(ctx, pm)
+    e_s, v_s, f_s = gpu_lib.tnep_eval_pes(ctx, g, few)
+    e_l, v_l, f_l = gpu_lib.tnep_eval_pes(ctx, g, mols)
+    assert np.array_equal(e_s, e_l[:120]) and np.array_equal(v_s, v_l[:120])
+    assert np.array_equal(f_s, f_l[:few.n_atoms])
+    g.close()
