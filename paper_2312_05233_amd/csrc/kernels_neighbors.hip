@@ -772,12 +772,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
 // iteration.  Accepted pairs keep the candidates' order: a pair's row is the
 // number of pairs accepted before it, counted over the group's lanes with a
 // ballot, and each lane stores its rows itself.  These are the rows k_neighbors
-// writes for such frames, in the same order.  With rad_v, the radial
-// descriptor sums are formed as k_neighbors forms them, bit for bit: every lane
-// computes its accepted candidates' terms, then the group adds them in candidate
-// order (each term fetched from its lane), so a call's results do not depend
-// on which of the two searches ran; RAD = false (the pair-parallel evaluation
-// layout, which forms them itself) leaves them out.
+// writes for such frames, in the same order.  RAD = true forms the radial
+// descriptor sums as k_neighbors forms them, bit for bit: every lane computes
+// its accepted candidates' terms and puts them in LDS, then lane k of the group
+// adds term k of the accepted candidates in candidate order (the same fused
+// multiply-adds), so a call's results do not depend on which of the two
+// searches ran; RAD = false (the pair-parallel evaluation layout, which forms
+// them itself) leaves them out.
+constexpr int kPpTermStride = kRadialTerms + 1;  // floats per candidate in k_neighbors_pp's LDS
 template <bool RAD>
 __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __restrict__ frames,
                                                          const int32_t* __restrict__ frame_of,
@@ -787,6 +789,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __rest
                                                          float rc_angular, NeighborLists nl,
                                                          int32_t* __restrict__ flags, float* __restrict__ rad_v) {
     constexpr int G = kPairLanes;
+    __shared__ float pp_terms[RAD ? kBlock : 1][2 * kPpTermStride];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t p = tid / G;  // tile slot (the whole group takes the same branches below)
     const int g = (int)(tid % G);
@@ -821,8 +824,8 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __rest
         float4* gr = lane_base + (int64_t)(nl.meta[kMetaSegR + t] >> 2) * 256;
         const int capA = nl.meta[kMetaCapA + t], capR = nl.meta[kMetaCapR + t];
         int na = 0, nr = 0;  // rows so far (equal in the group's lanes)
-        RadialSums rsum;     // equal in the group's lanes
-        rsum.clear();
+        // lane g < kRadialTerms: sum over accepted pairs of f_c T_g (g = 0: of f_c)
+        float rsum = 0.f;
         for (int q0 = 0; q0 < n; q0 += 2 * G) {
             float sf[2] = {0.f, 0.f}, Tk[2][kRadialTerms] = {};
             uint32_t acc[2];
@@ -860,25 +863,37 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __rest
                 if (RAD && in) RadialSums::terms(e.x, e.y, e.z, rcR_inv, sf[u], Tk[u]);
             }
             if constexpr (RAD) {
-                // candidate order: u = 0 (lanes 0..15), then u = 1
+                // each lane's terms (sf, f_c = sf^2, T_1..T_8 per candidate half) in LDS;
+                // the wave's LDS accesses complete in order, so the reads below see
+                // these writes and the next iteration's writes follow the reads
+                float* mine = pp_terms[threadIdx.x];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    uint32_t m = acc[u];
-                    while (__ballot(m != 0u)) {
-                        const bool has = m != 0u;
-                        const int src = first + (has ? __builtin_ctz(m) : 0);
-                        m &= m - 1u;
-                        float fs, ts[kRadialTerms];
-                        fs = __shfl(sf[u], src, 64);
+                    mine[u * kPpTermStride] = sf[u];
+                    mine[u * kPpTermStride + 1] = sf[u] * sf[u];
 #pragma unroll
-                        for (int k = 0; k < kRadialTerms; ++k) ts[k] = __shfl(Tk[u][k], src, 64);
-                        if (has) rsum.accumulate(fs, ts);
+                    for (int k = 1; k < kRadialTerms; ++k) mine[u * kPpTermStride + 1 + k] = Tk[u][k];
+                }
+                // candidate order: u = 0 (lanes 0..15), then u = 1; the mask is the
+                // same in the group's lanes, so they run the loop together
+                const float(*wave_terms)[2 * kPpTermStride] = pp_terms + (threadIdx.x & ~63u);
+                if (g < kRadialTerms) {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        for (uint32_t m = acc[u]; m != 0u; m &= m - 1u) {
+                            const float* ts = wave_terms[first + __builtin_ctz(m)] + u * kPpTermStride;
+                            rsum = g == 0 ? __builtin_fmaf(ts[0], ts[0], rsum) : __builtin_fmaf(ts[1], ts[1 + g], rsum);
+                        }
                     }
                 }
             }
         }
+        if constexpr (RAD) {
+            // sum_j f_k(r_ij) = (sum f_c T_k + sum f_c) / 2, as RadialSums::store forms it
+            const float fs = __shfl(rsum, first, 64);
+            if (g < kRadialTerms) rad_v[(int64_t)(t * kRadialTerms + g) * nl.n_pad + p] = 0.5f * (rsum + fs);
+        }
         if (g == 0) {
-            rsum.store(rad_v, t, nl.n_pad, p);
             nl.counts[(int64_t)(2 * t) * nl.n_pad + p] = min(na, capA);
             nl.counts[(int64_t)(2 * t + 1) * nl.n_pad + p] = min(nr, capR);
             if (na > capA) atomicMax(&flags[kFlagCapAng + t], na);
