@@ -12,9 +12,10 @@ import this package.  It shares no code with the HIP library.
   isotropic/anisotropic Raman split) is written here in numpy as plain
   lag sums and cosine sums.
 
-Parity unpinned: no numerical example of either stage is printed in the
-paper; every part is pinned instead by closed forms, invariants and finite
-differences (see the tests).
+Pins: the paper prints no numerical example of either stage, so no pin is a
+value from the paper; every part is pinned instead by facts outside this
+package (closed forms, library routines of the special cases, invariants and
+finite differences: tests/test_oracle_*.py).
 """
 from __future__ import annotations
 
