@@ -74,15 +74,9 @@ __device__ __forceinline__ int cell_coord(double p, double L, int nc) {
 // follower frame is binned where its reference atom is (the reference frame's
 // position), so the follower frame's slots mirror the reference frame's: the
 // same rank within each species range (CandLists).
-__global__ void k_bin(const FrameInfo* __restrict__ frames, const FrameTric* __restrict__ tric,
-                      const int32_t* __restrict__ frame_of,
-                      const double* __restrict__ pos, const int32_t* __restrict__ species,
-                      const int32_t* __restrict__ meta, int T, int32_t* __restrict__ key_of,
-                      int32_t* __restrict__ bucket_count, int32_t* __restrict__ flags) {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= meta[kMetaNAtoms]) return;
-    const int f = frame_of[a];
-    const FrameInfo& fi = frames[f];
+__device__ __forceinline__ int bin_key(const FrameInfo& fi, const FrameTric* __restrict__ tric, int f, int64_t a,
+                                       const double* __restrict__ pos, const int32_t* __restrict__ species,
+                                       const int32_t* __restrict__ meta, int T, int32_t* __restrict__ flags) {
     const double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
     const int t = species[a];
     int err = 0;
@@ -91,8 +85,7 @@ __global__ void k_bin(const FrameInfo* __restrict__ frames, const FrameTric* __r
     if (err) {
         atomicOr(&flags[kFlagError], err);
         atomicMin(&flags[kFlagBadAtom], call_atom(meta, a));
-        key_of[a] = -1;
-        return;
+        return -1;
     }
     int c = fi.cell_base;
     if (fi.mode == 1 && fi.tric) {
@@ -118,9 +111,20 @@ __global__ void k_bin(const FrameInfo* __restrict__ frames, const FrameTric* __r
         const int iz = cell_coord(bz, fi.L[2], fi.nc[2]);
         c += (ix * fi.nc[1] + iy) * fi.nc[2] + iz;
     }
-    const int key = c * T + t;
+    return c * T + t;
+}
+
+__global__ void k_bin(const FrameInfo* __restrict__ frames, const FrameTric* __restrict__ tric,
+                      const int32_t* __restrict__ frame_of,
+                      const double* __restrict__ pos, const int32_t* __restrict__ species,
+                      const int32_t* __restrict__ meta, int T, int32_t* __restrict__ key_of,
+                      int32_t* __restrict__ bucket_count, int32_t* __restrict__ flags) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= meta[kMetaNAtoms]) return;
+    const int f = frame_of[a];
+    const int key = bin_key(frames[f], tric, f, a, pos, species, meta, T, flags);
     key_of[a] = key;
-    atomicAdd(&bucket_count[key], 1);
+    if (key >= 0) atomicAdd(&bucket_count[key], 1);
 }
 
 // Bucket scans in three phases over chunks of kScanCells cells (all T species
@@ -132,11 +136,12 @@ __global__ void k_bin(const FrameInfo* __restrict__ frames, const FrameTric* __r
 //            slot of the bucket in (species, cell) order).
 constexpr int kScanCells = 1024;  // cells per chunk; 256 threads x 4 cells
 
-__device__ int32_t block_exclusive_256(int32_t v, int32_t* part) {
+template <int NT>
+__device__ int32_t block_exclusive(int32_t v, int32_t* part) {
     const int tid = threadIdx.x;
     part[tid] = v;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
+    for (int off = 1; off < NT; off <<= 1) {
         const int32_t u = tid >= off ? part[tid - off] : 0;
         __syncthreads();
         part[tid] += u;
@@ -146,6 +151,7 @@ __device__ int32_t block_exclusive_256(int32_t v, int32_t* part) {
     __syncthreads();
     return incl - v;
 }
+__device__ int32_t block_exclusive_256(int32_t v, int32_t* part) { return block_exclusive<256>(v, part); }
 
 __global__ void __launch_bounds__(256) k_scan_partials(const int32_t* __restrict__ count,
                                                        const int32_t* __restrict__ meta, int T,
@@ -249,43 +255,44 @@ __global__ void __launch_bounds__(256) k_scan_final(const int32_t* __restrict__ 
     }
 }
 
-// All three scan phases in one work-group, for batches of at most kScanCells
-// cells (one chunk): the same offsets as k_scan_partials, k_scan_chunks and
-// k_scan_final give for a single chunk.
-__global__ void __launch_bounds__(256) k_scan_one(const int32_t* __restrict__ count, int32_t* __restrict__ meta,
-                                                  int T, int32_t* __restrict__ bucket_start,
-                                                  int32_t* __restrict__ bucket_fill, int32_t* __restrict__ perm_start) {
-    __shared__ int32_t part[256];
-    __shared__ int32_t s_total;
+// All three scan phases in one work-group of NT threads, for batches of at
+// most kScanCells cells (one chunk): the same offsets as k_scan_partials,
+// k_scan_chunks and k_scan_final give for a single chunk.  bucket_fill (if
+// given) is cleared for k_scatter.
+template <int NT>
+__device__ void scan_one_chunk(const int32_t* count, int32_t* __restrict__ meta, int T,
+                               int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_fill,
+                               int32_t* __restrict__ perm_start, int32_t* part, int32_t& s_total) {
+    constexpr int kPer = kScanCells / NT;  // cells per thread
     const int n_cells = meta[kMetaNCells];
-    const int c0 = threadIdx.x * 4;
-    const int c1 = min(c0 + 4, n_cells);
+    const int c0 = threadIdx.x * kPer;
+    const int c1 = min(c0 + kPer, n_cells);
     // key order (cell-major, species-minor)
     {
         int32_t s = 0;
         for (int c = c0; c < c1; ++c)
             for (int u = 0; u < T; ++u) s += count[c * T + u];
-        int32_t run = block_exclusive_256(s, part);
+        int32_t run = block_exclusive<NT>(s, part);
         for (int c = c0; c < c1; ++c)
             for (int u = 0; u < T; ++u) {
                 bucket_start[c * T + u] = run;
-                bucket_fill[c * T + u] = 0;
+                if (bucket_fill) bucket_fill[c * T + u] = 0;
                 run += count[c * T + u];
             }
-        if (threadIdx.x == 255) bucket_start[n_cells * T] = run;
+        if (threadIdx.x == NT - 1) bucket_start[n_cells * T] = run;
     }
     // species-major order, each species padded to whole 64-slot tiles
     int32_t tiles = 0;
     for (int t = 0; t < T; ++t) {
         int32_t s = 0;
         for (int c = c0; c < c1; ++c) s += count[c * T + t];
-        int32_t run = block_exclusive_256(s, part) + tiles * 64;
+        int32_t run = block_exclusive<NT>(s, part) + tiles * 64;
         for (int c = c0; c < c1; ++c) {
             perm_start[c * T + t] = run;
             run += count[c * T + t];
         }
         if (c0 < c1 && c1 == n_cells) perm_start[n_cells * T + t] = run;
-        if (threadIdx.x == 255) s_total = run - tiles * 64;
+        if (threadIdx.x == NT - 1) s_total = run - tiles * 64;
         __syncthreads();
         const int32_t total = s_total;
         if (threadIdx.x == 0) meta[kMetaTileBase + t] = tiles;
@@ -293,6 +300,14 @@ __global__ void __launch_bounds__(256) k_scan_one(const int32_t* __restrict__ co
         __syncthreads();
     }
     if (threadIdx.x == 0) meta[kMetaTileBase + T] = tiles;
+}
+
+__global__ void __launch_bounds__(256) k_scan_one(const int32_t* __restrict__ count, int32_t* __restrict__ meta,
+                                                  int T, int32_t* __restrict__ bucket_start,
+                                                  int32_t* __restrict__ bucket_fill, int32_t* __restrict__ perm_start) {
+    __shared__ int32_t part[256];
+    __shared__ int32_t s_total;
+    scan_one_chunk<256>(count, meta, T, bucket_start, bucket_fill, perm_start, part, s_total);
 }
 
 __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
@@ -316,17 +331,14 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 // of two so the scaling is exact), and the cell's index along the third axis
 // (z, or the third lattice vector).  Frames without a grid keep the FP64 position
 // (triclinic ones: wrapped fractional coordinates).
-__global__ void k_sort_place(const FrameInfo* __restrict__ frames, const FrameTric* __restrict__ tric,
-                             const int32_t* __restrict__ frame_of,
-                             const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
-                             const int32_t* __restrict__ bucket_atoms, const int32_t* __restrict__ perm_start,
-                             int32_t* __restrict__ perm, int32_t* __restrict__ slot_of, const double* __restrict__ pos,
-                             double4* __restrict__ bucket_pos, int4* __restrict__ cell_rec,
-                             const int32_t* __restrict__ meta, int T) {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= meta[kMetaNAtoms]) return;
-    const int k = key_of[a];
-    if (k < 0) return;
+// Atom a (bucket k >= 0, frame f) of k_sort_place; bucket_atoms holds the
+// members of every bucket (in any order) from bucket_start[k] on.
+__device__ __forceinline__ void place_atom(int64_t a, int k, int f, const FrameInfo* __restrict__ frames,
+                                           const FrameTric* __restrict__ tric, const int32_t* __restrict__ bucket_start,
+                                           const int32_t* bucket_atoms, const int32_t* __restrict__ perm_start,
+                                           int32_t* __restrict__ perm, int32_t* __restrict__ slot_of,
+                                           const double* __restrict__ pos, double4* __restrict__ bucket_pos,
+                                           int4* __restrict__ cell_rec, int T) {
     const int b = bucket_start[k], n = bucket_start[k + 1] - b;
     int rank = 0;
     for (int i = 0; i < n; ++i) rank += bucket_atoms[b + i] < (int32_t)a ? 1 : 0;
@@ -334,7 +346,6 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const FrameTr
     perm[slot] = (int32_t)a;
     slot_of[a] = slot;
     double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
-    const int f = frame_of[a];
     const FrameInfo& fi = frames[f];
     if (fi.mode == 1) {
         const int local = k / T - fi.cell_base;
@@ -378,6 +389,82 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const FrameTr
         z = sf[2];
     }
     bucket_pos[slot] = make_double4(x, y, z, 0.0);
+}
+
+__global__ void k_sort_place(const FrameInfo* __restrict__ frames, const FrameTric* __restrict__ tric,
+                             const int32_t* __restrict__ frame_of,
+                             const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
+                             const int32_t* __restrict__ bucket_atoms, const int32_t* __restrict__ perm_start,
+                             int32_t* __restrict__ perm, int32_t* __restrict__ slot_of, const double* __restrict__ pos,
+                             double4* __restrict__ bucket_pos, int4* __restrict__ cell_rec,
+                             const int32_t* __restrict__ meta, int T) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= meta[kMetaNAtoms]) return;
+    const int k = key_of[a];
+    if (k < 0) return;
+    place_atom(a, k, frame_of[a], frames, tric, bucket_start, bucket_atoms, perm_start, perm, slot_of, pos, bucket_pos,
+               cell_rec, T);
+}
+
+// The bucket pipeline of a small launch batch in one work-group: set-up,
+// binning, the one-chunk scan, scatter and placement as k_batch_setup, k_bin,
+// k_scan_one, k_scatter and k_sort_place do them (the same key, scan and
+// placement functions), with the bucket counts and members in LDS and barriers
+// in place of four launch boundaries.  The outputs are the same integers, so
+// every later kernel sees the same slots.  For batches of at most
+// kBucketSmallAtoms atoms and kScanCells cells, hence at most kScanCells frames
+// (a frame has at least one cell) and kScanCells x 8 buckets (at most 8 species).
+constexpr int kBucketSmallBlock = 1024;
+constexpr int kBucketSmallAtoms = 4096;
+constexpr int kBucketSmallBuckets = kScanCells * 8;
+__global__ void __launch_bounds__(kBucketSmallBlock) k_bucket_small(const FrameInfo* __restrict__ frames,
+                                                                    const FrameTric* __restrict__ tric,
+                                                                    const double* __restrict__ pos,
+                                                                    const int32_t* __restrict__ species, int T,
+                                                                    NeighborWork w, int64_t n_pad,
+                                                                    int32_t* __restrict__ flags) {
+    __shared__ int32_t s_begin[kScanCells];            // first atom of every frame
+    __shared__ int32_t s_count[kBucketSmallBuckets];   // bucket counts, then fill levels
+    __shared__ int32_t s_atoms[kBucketSmallAtoms];     // bucket members (bucket_atoms)
+    __shared__ int32_t s_part[kBucketSmallBlock];
+    __shared__ int32_t s_total;
+    const int n_atoms = w.meta[kMetaNAtoms], n_frames = w.meta[kMetaNFrames];
+    const int n_buckets = w.meta[kMetaNCells] * T;
+    for (int i = threadIdx.x; i < n_buckets; i += kBucketSmallBlock) s_count[i] = 0;
+    for (int64_t i = threadIdx.x; i < n_pad; i += kBucketSmallBlock) w.perm[i] = -1;
+    for (int f = threadIdx.x; f < n_frames; f += kBucketSmallBlock) s_begin[f] = (int)frames[f].atom_begin;
+    __syncthreads();
+    // frames are consecutive atom ranges (an empty frame begins where the next
+    // one does): atom a is in the last frame that begins at or before it
+    for (int a = threadIdx.x; a < n_atoms; a += kBucketSmallBlock) {
+        int lo = 0, hi = n_frames - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_begin[mid] <= a)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        w.frame_of[a] = lo;
+        const int key = bin_key(frames[lo], tric, lo, a, pos, species, w.meta, T, flags);
+        w.key_of[a] = key;
+        if (key >= 0) atomicAdd(&s_count[key], 1);
+    }
+    __syncthreads();
+    scan_one_chunk<kBucketSmallBlock>(s_count, w.meta, T, w.bucket_start, nullptr, w.perm_start, s_part, s_total);
+    for (int i = threadIdx.x; i < n_buckets; i += kBucketSmallBlock) s_count[i] = 0;
+    __syncthreads();
+    for (int a = threadIdx.x; a < n_atoms; a += kBucketSmallBlock) {
+        const int k = w.key_of[a];
+        if (k >= 0) s_atoms[w.bucket_start[k] + atomicAdd(&s_count[k], 1)] = a;
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < n_atoms; a += kBucketSmallBlock) {
+        const int k = w.key_of[a];
+        if (k >= 0)
+            place_atom(a, k, w.frame_of[a], frames, tric, w.bucket_start, s_atoms, w.perm_start, w.perm, w.slot_of, pos,
+                       w.bucket_pos, w.cell_rec, T);
+    }
 }
 
 // Minimum image along one axis; Linv = 1/L on periodic axes, 0 otherwise.
@@ -1214,24 +1301,29 @@ hipError_t launch_neighbors(const FrameInfo* d_frames, const FrameTric* d_tric, 
     const int T = nl.T;
     const int cap_buckets = cap_cells * T;
     const int cap_chunks = (cap_cells + kScanCells - 1) / kScanCells;
-    const int64_t setup_threads = std::max<int64_t>({(int64_t)cap_frames * kBlock, (int64_t)cap_buckets, nl.n_pad});
-    k_batch_setup<<<blocks_for(setup_threads, kBlock), kBlock, 0, s>>>(d_frames, nl.meta, w.frame_of, w.bucket_count,
-                                                                      cap_buckets, w.perm, nl.n_pad);
-    k_bin<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, d_tric, w.frame_of, pos, species, nl.meta, T, w.key_of,
-                                                          w.bucket_count, d_flags);
-    if (cap_chunks == 1) {
-        k_scan_one<<<1, 256, 0, s>>>(w.bucket_count, w.meta, T, w.bucket_start, w.bucket_fill, w.perm_start);
+    if (cap_atoms <= kBucketSmallAtoms && cap_cells <= kScanCells && cap_frames <= kScanCells &&
+        cap_buckets <= kBucketSmallBuckets) {
+        k_bucket_small<<<1, kBucketSmallBlock, 0, s>>>(d_frames, d_tric, pos, species, T, w, nl.n_pad, d_flags);
     } else {
-        k_scan_partials<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk);
-        k_scan_chunks<<<1, 256, 0, s>>>(w.chunk, T, w.chunk + 9 * cap_chunks, w.meta, w.bucket_start);
-        k_scan_final<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk + 9 * cap_chunks, w.bucket_start,
-                                               w.bucket_fill, w.perm_start);
+        const int64_t setup_threads = std::max<int64_t>({(int64_t)cap_frames * kBlock, (int64_t)cap_buckets, nl.n_pad});
+        k_batch_setup<<<blocks_for(setup_threads, kBlock), kBlock, 0, s>>>(d_frames, nl.meta, w.frame_of, w.bucket_count,
+                                                                          cap_buckets, w.perm, nl.n_pad);
+        k_bin<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, d_tric, w.frame_of, pos, species, nl.meta, T,
+                                                              w.key_of, w.bucket_count, d_flags);
+        if (cap_chunks == 1) {
+            k_scan_one<<<1, 256, 0, s>>>(w.bucket_count, w.meta, T, w.bucket_start, w.bucket_fill, w.perm_start);
+        } else {
+            k_scan_partials<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk);
+            k_scan_chunks<<<1, 256, 0, s>>>(w.chunk, T, w.chunk + 9 * cap_chunks, w.meta, w.bucket_start);
+            k_scan_final<<<cap_chunks, 256, 0, s>>>(w.bucket_count, nl.meta, T, w.chunk + 9 * cap_chunks, w.bucket_start,
+                                                   w.bucket_fill, w.perm_start);
+        }
+        k_scatter<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill,
+                                                                  w.bucket_atoms, nl.meta);
+        k_sort_place<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, d_tric, w.frame_of, w.key_of,
+                                                                     w.bucket_start, w.bucket_atoms, w.perm_start, w.perm,
+                                                                     w.slot_of, pos, w.bucket_pos, w.cell_rec, nl.meta, T);
     }
-    k_scatter<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(w.key_of, w.bucket_start, w.bucket_fill,
-                                                              w.bucket_atoms, nl.meta);
-    k_sort_place<<<blocks_for(cap_atoms, kBlock), kBlock, 0, s>>>(d_frames, d_tric, w.frame_of, w.key_of, w.bucket_start,
-                                                                 w.bucket_atoms, w.perm_start, w.perm, w.slot_of, pos,
-                                                                 w.bucket_pos, w.cell_rec, nl.meta, T);
     const size_t list_bytes = sizeof(float4) * 9 * nb;  // staging + per-wave flush lists
     // with pair_search and no plain cell-grid frame, k_neighbors_pp covers every
     // slot k_neighbors would (frames without a grid and the padding)

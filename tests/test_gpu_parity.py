@@ -385,3 +385,39 @@ def test_small_and_large_batch_searches_agree_bitwise(gpu_lib, ctx):
     assert np.array_equal(e_s, e_l[:120]) and np.array_equal(v_s, v_l[:120])
     assert np.array_equal(f_s, f_l[:few.n_atoms])
     g.close()
+
+
+def test_small_batch_bucket_pipeline_matches_large_batches(gpu_lib, ctx):
+    """Launch batches of at most 4,096 atoms and 1,024 cells are binned, scanned
+    and placed by one work-group, larger ones by the five-kernel pipeline; both
+    give the same tile slots, so grid frames (orthorhombic, triclinic, and
+    trajectory windows with reference and follower frames) are bitwise the same
+    alone and inside a large batch, and equal the oracle alone."""
+    m = synth.model("water_polarizability")
+    mdl = gpu_lib.Model(ctx, m)
+    pos, spc, cell = synth.water_box(8, 24.84, seed=97)  # 1,536 atoms, 8^3 cells
+    n = len(spc)
+    R, _ = np.linalg.qr(np.random.default_rng(98).normal(size=(3, 3)))
+    box = synth.Frames(np.array([0, n], np.int64), pos, spc, cell[None], np.ones((1, 3), np.uint8))
+    tri = synth.Frames(np.array([0, n], np.int64), pos @ R.T, spc, (cell.reshape(3, 3) @ R.T).reshape(1, 9),
+                       np.ones((1, 3), np.uint8))
+    for label, one in (("orthorhombic 1,536-atom box", box), ("rotated (triclinic) box", tri)):
+        a = gpu_lib.tnep_eval_polarizability(ctx, mdl, one)
+        _check(a, m, one, label + " alone")
+        many = synth.Frames.concat([one] * 24)  # 36,864 atoms, 12,288 cells
+        b = gpu_lib.tnep_eval_polarizability(ctx, mdl, many)
+        assert all(np.array_equal(b[i], a[0]) for i in range(24)), label
+    p6, s6, c6 = synth.water_box(6, 18.63, seed=99)  # 648 atoms, 6^3 cells
+    traj = synth.ou_trajectory(p6, s6, c6, 4, seed=100)
+    c3 = gpu_lib.Context(0)
+    c3.set_option(gpu_lib.OPT_TRAJECTORY_WINDOW, 3)
+    m3 = gpu_lib.Model(c3, m)
+    a = gpu_lib.tnep_eval_polarizability(c3, m3, traj)  # 2,592 atoms, 864 cells
+    _check(a, m, traj, "trajectory window alone")
+    longer = synth.Frames.concat([traj, synth.ou_trajectory(p6, s6, c6, 60, seed=101)])
+    b = gpu_lib.tnep_eval_polarizability(c3, m3, longer)
+    assert np.array_equal(b[:4], a)
+    assert c3.reuse_fallbacks() == 0
+    m3.close()
+    c3.close()
+    mdl.close()
