@@ -838,14 +838,15 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                         he = launch_count_pairs(nl, (unsigned long long*)c->counters.p, c->stream);
                         if (he != hipSuccess) return he;
                     }
-                    if (two_streams) {
-                        if ((he = hipEventRecord(c->fork_ev, c->stream)) != hipSuccess) return he;
-                        if ((he = hipStreamWaitEvent(c->side, c->fork_ev, 0)) != hipSuccess) return he;
-                    }
+                    // the side stream waits for the search (the fork event), enqueued after
+                    // the first model's kernels so that they reach the device sooner
+                    if (two_streams && (he = hipEventRecord(c->fork_ev, c->stream)) != hipSuccess) return he;
                     for (int k = first; k < last; ++k) {
                         const Model* m = job.models[k];
                         const int q = k - first;
                         hipStream_t sq = (two_streams && (q & 1)) ? c->side : c->stream;
+                        if (two_streams && q == 1 && (he = hipStreamWaitEvent(c->side, c->fork_ev, 0)) != hipSuccess)
+                            return he;
                         tr = c->timer_begin(m->kind == TNEP_KIND_DIPOLE           ? TNEP_KERNEL_EVAL_DIPOLE
                                             : m->kind == TNEP_KIND_POLARIZABILITY ? TNEP_KERNEL_EVAL_POLARIZABILITY
                                                                                   : TNEP_KERNEL_EVAL_PES);
