@@ -255,59 +255,107 @@ __global__ void __launch_bounds__(256) k_scan_final(const int32_t* __restrict__ 
     }
 }
 
+// Exclusive prefix sums of M values per thread over the NT threads of a
+// work-group, all M at once: a shuffle scan within each wavefront, then the
+// wavefronts' totals through LDS (wave_tot: NT / 64 x M ints), two barriers.
+// total[m]: the sum over all threads.
+template <int NT, int M>
+__device__ __forceinline__ void block_exclusive_multi(int32_t (&v)[M], int32_t (&total)[M], int32_t* wave_tot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t x[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) x[m] = v[m];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int32_t u = __shfl_up(x[m], off, 64);
+            if (lane >= off) x[m] += u;
+        }
+    if (lane == 63)
+#pragma unroll
+        for (int m = 0; m < M; ++m) wave_tot[wave * M + m] = x[m];
+    __syncthreads();
+    int32_t before[M] = {}, all[M] = {};
+#pragma unroll 1
+    for (int w = 0; w < NT / 64; ++w)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int32_t y = wave_tot[w * M + m];
+            before[m] += w < wave ? y : 0;
+            all[m] += y;
+        }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        v[m] = before[m] + x[m] - v[m];
+        total[m] = all[m];
+    }
+    __syncthreads();
+}
+
+constexpr int kScanMaxSpecies = 8;
+
 // All three scan phases in one work-group of NT threads, for batches of at
 // most kScanCells cells (one chunk): the same offsets as k_scan_partials,
-// k_scan_chunks and k_scan_final give for a single chunk.  bucket_fill (if
-// given) is cleared for k_scatter.
+// k_scan_chunks and k_scan_final give for a single chunk.  One scan of T + 1
+// sums per thread: its cells' buckets in key order and, per species, in
+// (species, cell) order; species t's tiles follow those of species < t, each
+// species padded to whole 64-slot tiles.  bucket_fill (if given) is cleared for
+// k_scatter.  wave_tot: NT / 64 x (kScanMaxSpecies + 1) ints of LDS.
 template <int NT>
 __device__ void scan_one_chunk(const int32_t* count, int32_t* __restrict__ meta, int T,
                                int32_t* __restrict__ bucket_start, int32_t* __restrict__ bucket_fill,
-                               int32_t* __restrict__ perm_start, int32_t* part, int32_t& s_total) {
+                               int32_t* __restrict__ perm_start, int32_t* wave_tot) {
     constexpr int kPer = kScanCells / NT;  // cells per thread
+    constexpr int M = kScanMaxSpecies + 1;
     const int n_cells = meta[kMetaNCells];
     const int c0 = threadIdx.x * kPer;
     const int c1 = min(c0 + kPer, n_cells);
-    // key order (cell-major, species-minor)
-    {
-        int32_t s = 0;
-        for (int c = c0; c < c1; ++c)
-            for (int u = 0; u < T; ++u) s += count[c * T + u];
-        int32_t run = block_exclusive<NT>(s, part);
-        for (int c = c0; c < c1; ++c)
-            for (int u = 0; u < T; ++u) {
-                bucket_start[c * T + u] = run;
-                if (bucket_fill) bucket_fill[c * T + u] = 0;
-                run += count[c * T + u];
-            }
-        if (threadIdx.x == NT - 1) bucket_start[n_cells * T] = run;
-    }
-    // species-major order, each species padded to whole 64-slot tiles
-    int32_t tiles = 0;
-    for (int t = 0; t < T; ++t) {
-        int32_t s = 0;
-        for (int c = c0; c < c1; ++c) s += count[c * T + t];
-        int32_t run = block_exclusive<NT>(s, part) + tiles * 64;
-        for (int c = c0; c < c1; ++c) {
-            perm_start[c * T + t] = run;
-            run += count[c * T + t];
+    int32_t v[M] = {}, tot[M];
+    for (int c = c0; c < c1; ++c)
+#pragma unroll
+        for (int u = 0; u < kScanMaxSpecies; ++u) {
+            const int32_t k = u < T ? count[c * T + u] : 0;
+            v[0] += k;
+            v[1 + u] += k;
         }
-        if (c0 < c1 && c1 == n_cells) perm_start[n_cells * T + t] = run;
-        if (threadIdx.x == NT - 1) s_total = run - tiles * 64;
-        __syncthreads();
-        const int32_t total = s_total;
-        if (threadIdx.x == 0) meta[kMetaTileBase + t] = tiles;
-        tiles += (total + 63) / 64;
-        __syncthreads();
+    block_exclusive_multi<NT, M>(v, tot, wave_tot);
+    // key order (cell-major, species-minor)
+    int32_t run = v[0];
+    for (int c = c0; c < c1; ++c)
+        for (int u = 0; u < T; ++u) {
+            bucket_start[c * T + u] = run;
+            if (bucket_fill) bucket_fill[c * T + u] = 0;
+            run += count[c * T + u];
+        }
+    // species-major order
+    int32_t tiles = 0;
+#pragma unroll
+    for (int t = 0; t < kScanMaxSpecies; ++t) {
+        if (t < T) {
+            int32_t r = v[1 + t] + tiles * 64;
+            for (int c = c0; c < c1; ++c) {
+                perm_start[c * T + t] = r;
+                r += count[c * T + t];
+            }
+            if (threadIdx.x == 0) {
+                perm_start[n_cells * T + t] = tot[1 + t] + tiles * 64;
+                meta[kMetaTileBase + t] = tiles;
+            }
+            tiles += (tot[1 + t] + 63) / 64;
+        }
     }
-    if (threadIdx.x == 0) meta[kMetaTileBase + T] = tiles;
+    if (threadIdx.x == 0) {
+        bucket_start[n_cells * T] = tot[0];
+        meta[kMetaTileBase + T] = tiles;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_scan_one(const int32_t* __restrict__ count, int32_t* __restrict__ meta,
                                                   int T, int32_t* __restrict__ bucket_start,
                                                   int32_t* __restrict__ bucket_fill, int32_t* __restrict__ perm_start) {
-    __shared__ int32_t part[256];
-    __shared__ int32_t s_total;
-    scan_one_chunk<256>(count, meta, T, bucket_start, bucket_fill, perm_start, part, s_total);
+    __shared__ int32_t wave_tot[256 / 64 * (kScanMaxSpecies + 1)];
+    scan_one_chunk<256>(count, meta, T, bucket_start, bucket_fill, perm_start, wave_tot);
 }
 
 __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __restrict__ bucket_start,
@@ -331,18 +379,12 @@ __global__ void k_scatter(const int32_t* __restrict__ key_of, const int32_t* __r
 // of two so the scaling is exact), and the cell's index along the third axis
 // (z, or the third lattice vector).  Frames without a grid keep the FP64 position
 // (triclinic ones: wrapped fractional coordinates).
-// Atom a (bucket k >= 0, frame f) of k_sort_place; bucket_atoms holds the
-// members of every bucket (in any order) from bucket_start[k] on.
-__device__ __forceinline__ void place_atom(int64_t a, int k, int f, const FrameInfo* __restrict__ frames,
-                                           const FrameTric* __restrict__ tric, const int32_t* __restrict__ bucket_start,
-                                           const int32_t* bucket_atoms, const int32_t* __restrict__ perm_start,
-                                           int32_t* __restrict__ perm, int32_t* __restrict__ slot_of,
-                                           const double* __restrict__ pos, double4* __restrict__ bucket_pos,
-                                           int4* __restrict__ cell_rec, int T) {
-    const int b = bucket_start[k], n = bucket_start[k + 1] - b;
-    int rank = 0;
-    for (int i = 0; i < n; ++i) rank += bucket_atoms[b + i] < (int32_t)a ? 1 : 0;
-    const int slot = perm_start[k] + rank;
+// Atom a (bucket k >= 0, frame f) of k_sort_place at tile slot `slot` (the
+// first slot of its bucket plus the number of smaller atom indices in it).
+__device__ __forceinline__ void place_atom(int64_t a, int k, int f, int slot, const FrameInfo* __restrict__ frames,
+                                           const FrameTric* __restrict__ tric, int32_t* __restrict__ perm,
+                                           int32_t* __restrict__ slot_of, const double* __restrict__ pos,
+                                           double4* __restrict__ bucket_pos, int4* __restrict__ cell_rec, int T) {
     perm[slot] = (int32_t)a;
     slot_of[a] = slot;
     double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
@@ -402,8 +444,10 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const FrameTr
     if (a >= meta[kMetaNAtoms]) return;
     const int k = key_of[a];
     if (k < 0) return;
-    place_atom(a, k, frame_of[a], frames, tric, bucket_start, bucket_atoms, perm_start, perm, slot_of, pos, bucket_pos,
-               cell_rec, T);
+    const int b = bucket_start[k], n = bucket_start[k + 1] - b;
+    int rank = 0;
+    for (int i = 0; i < n; ++i) rank += bucket_atoms[b + i] < (int32_t)a ? 1 : 0;
+    place_atom(a, k, frame_of[a], perm_start[k] + rank, frames, tric, perm, slot_of, pos, bucket_pos, cell_rec, T);
 }
 
 // The bucket pipeline of a small launch batch in one work-group: set-up,
@@ -416,7 +460,7 @@ __global__ void k_sort_place(const FrameInfo* __restrict__ frames, const FrameTr
 // (a frame has at least one cell) and kScanCells x 8 buckets (at most 8 species).
 constexpr int kBucketSmallBlock = 1024;
 constexpr int kBucketSmallAtoms = 4096;
-constexpr int kBucketSmallBuckets = kScanCells * 8;
+constexpr int kBucketSmallBuckets = kScanCells * kScanMaxSpecies;
 __global__ void __launch_bounds__(kBucketSmallBlock) k_bucket_small(const FrameInfo* __restrict__ frames,
                                                                     const FrameTric* __restrict__ tric,
                                                                     const double* __restrict__ pos,
@@ -426,8 +470,7 @@ __global__ void __launch_bounds__(kBucketSmallBlock) k_bucket_small(const FrameI
     __shared__ int32_t s_begin[kScanCells];            // first atom of every frame
     __shared__ int32_t s_count[kBucketSmallBuckets];   // bucket counts, then fill levels
     __shared__ int32_t s_atoms[kBucketSmallAtoms];     // bucket members (bucket_atoms)
-    __shared__ int32_t s_part[kBucketSmallBlock];
-    __shared__ int32_t s_total;
+    __shared__ int32_t s_wave[kBucketSmallBlock / 64 * (kScanMaxSpecies + 1)];
     const int n_atoms = w.meta[kMetaNAtoms], n_frames = w.meta[kMetaNFrames];
     const int n_buckets = w.meta[kMetaNCells] * T;
     for (int i = threadIdx.x; i < n_buckets; i += kBucketSmallBlock) s_count[i] = 0;
@@ -451,7 +494,8 @@ __global__ void __launch_bounds__(kBucketSmallBlock) k_bucket_small(const FrameI
         if (key >= 0) atomicAdd(&s_count[key], 1);
     }
     __syncthreads();
-    scan_one_chunk<kBucketSmallBlock>(s_count, w.meta, T, w.bucket_start, nullptr, w.perm_start, s_part, s_total);
+    scan_one_chunk<kBucketSmallBlock>(s_count, w.meta, T, w.bucket_start, nullptr, w.perm_start, s_wave);
+    __syncthreads();  // every thread's reads of the counts are done
     for (int i = threadIdx.x; i < n_buckets; i += kBucketSmallBlock) s_count[i] = 0;
     __syncthreads();
     for (int a = threadIdx.x; a < n_atoms; a += kBucketSmallBlock) {
@@ -461,9 +505,13 @@ __global__ void __launch_bounds__(kBucketSmallBlock) k_bucket_small(const FrameI
     __syncthreads();
     for (int a = threadIdx.x; a < n_atoms; a += kBucketSmallBlock) {
         const int k = w.key_of[a];
-        if (k >= 0)
-            place_atom(a, k, w.frame_of[a], frames, tric, w.bucket_start, s_atoms, w.perm_start, w.perm, w.slot_of, pos,
-                       w.bucket_pos, w.cell_rec, T);
+        if (k < 0) continue;
+        const int b = w.bucket_start[k], n = w.bucket_start[k + 1] - b;
+        int rank = 0;
+#pragma unroll 8
+        for (int i = 0; i < n; ++i) rank += s_atoms[b + i] < a ? 1 : 0;
+        place_atom(a, k, w.frame_of[a], w.perm_start[k] + rank, frames, tric, w.perm, w.slot_of, pos, w.bucket_pos,
+                   w.cell_rec, T);
     }
 }
 
