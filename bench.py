@@ -437,7 +437,9 @@ def bench_latency(args):
     """Calls of few atoms on device-resident frames, one synchronous call at a
     time, in the default layout (one lane per atom) and the pair-parallel
     layout (TNEP_OPT_PAIR_PARALLEL: 16 lanes per atom): mean wall time per call
-    and the evaluation kernels' mean time per call (HIP events)."""
+    and the evaluation kernels' mean time per call (HIP events); then both
+    layouts with the frames' layout (offsets, cells, pbc) in host memory
+    (TNEP_DEVICE_META_HOST: no metadata read back from the device)."""
     import torch
 
     from paper_2312_05233_amd import tnep
@@ -454,11 +456,11 @@ def bench_latency(args):
     out = []
     for label, frames, models in cases:
         rec = {"workload": label, "atoms": frames.n_atoms}
-        for pp in (0, 1):
+        for pp, host_meta in ((0, False), (1, False), (0, True), (1, True)):
             ctx = tnep.Context(0)
             ctx.set_option(tnep.OPT_PAIR_PARALLEL, pp)
             gm = [tnep.Model(ctx, m) for m in models]
-            dfr = tnep.DeviceFrames(frames)
+            dfr = tnep.DeviceFrames(frames, host_meta=host_meta)
             mu = torch.zeros((frames.n_frames, 3), dtype=torch.float64, device="cuda")
             al = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
             if len(gm) == 2:
@@ -476,7 +478,8 @@ def bench_latency(args):
             for _ in range(n):
                 one_call()
             ev = sum(ctx.kernel_time(k)[0] for k in (tnep.KERNEL_EVAL_DIPOLE, tnep.KERNEL_EVAL_POLARIZABILITY)) / n
-            rec["pair_parallel" if pp else "default"] = {"us_per_call": 1e6 * t, "eval_kernels_us_per_call": 1e3 * ev}
+            name = ("pair_parallel" if pp else "default") + ("_host_layout" if host_meta else "")
+            rec[name] = {"us_per_call": 1e6 * t, "eval_kernels_us_per_call": 1e3 * ev}
             for g in gm:
                 g.close()
             ctx.close()

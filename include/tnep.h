@@ -29,6 +29,13 @@
  *   - Memory location: tnep_frames.location says whether the pointers in
  *     that struct AND the output pointers of the call are host memory
  *     (TNEP_HOST) or device memory of the context's GPU (TNEP_DEVICE).
+ *     TNEP_DEVICE_META_HOST: positions, species and the outputs in device
+ *     memory, atom_offsets, cells and pbc in host memory, for callers that keep
+ *     the frame layout on the host (the call then reads no metadata back from
+ *     the device and does not synchronize with the legacy default stream before
+ *     it starts: order the work that writes the positions before the call on the
+ *     context's stream).  Accepted by tnep_eval_dipole, tnep_eval_polarizability,
+ *     tnep_eval_dipole_polarizability and tnep_eval_pes; TNEP_E_INVALID elsewhere.
  *   - Threading: a context is used by one host thread at a time, except the
  *     tnep_submit / tnep_wait pair, which is thread-safe.
  *   - Units: positions in Angstrom; tensors are returned in the model's own
@@ -61,6 +68,7 @@ extern "C" {
 /* ---- enums ------------------------------------------------------------- */
 #define TNEP_HOST 0
 #define TNEP_DEVICE 1
+#define TNEP_DEVICE_META_HOST 2   /* tnep_frames only: data on the device, layout on the host */
 
 #define TNEP_KIND_DIPOLE 1         /* rank-1: one tensor head               */
 #define TNEP_KIND_POLARIZABILITY 2 /* rank-2: tensor head + scalar head     */
@@ -172,7 +180,7 @@ typedef struct {
     const int32_t* species;      /* [total_atoms], 0..n_species-1                  */
     const double* cells;         /* [n_frames][9] row-major lattice vectors or NULL */
     const uint8_t* pbc;          /* [n_frames][3] periodic flags or NULL (vacuum)   */
-    int32_t location;            /* TNEP_HOST or TNEP_DEVICE                        */
+    int32_t location;            /* TNEP_HOST, TNEP_DEVICE or TNEP_DEVICE_META_HOST */
 } tnep_frames;
 
 /* ---- context ----------------------------------------------------------- */

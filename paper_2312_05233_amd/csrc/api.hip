@@ -570,7 +570,7 @@ extern "C" void tnep_model_free(tnep_model* model) {
 static int check_frames(Ctx* c, const tnep_frames* f) {
     if (!f) return c->fail(TNEP_E_INVALID, "frames is NULL");
     if (f->n_frames < 0) return c->fail(TNEP_E_INVALID, "negative n_frames");
-    if (f->location != TNEP_HOST && f->location != TNEP_DEVICE)
+    if (f->location != TNEP_HOST && f->location != TNEP_DEVICE && f->location != TNEP_DEVICE_META_HOST)
         return c->fail(TNEP_E_INVALID, "bad location %d", f->location);
     if (f->n_frames > 0 && (!f->atom_offsets || !f->positions || !f->species))
         return c->fail(TNEP_E_INVALID, "NULL frame arrays");
@@ -642,6 +642,8 @@ extern "C" int tnep_eval_dipole_charged(tnep_ctx* ctx, const tnep_model* model, 
     if (!m || m->kind != TNEP_KIND_DIPOLE) return c->fail(TNEP_E_INVALID, "a dipole model is required");
     int e = check_frames(c, frames);
     if (e) return e;
+    if (frames->location == TNEP_DEVICE_META_HOST)
+        return c->fail(TNEP_E_INVALID, "charged frames take TNEP_HOST or TNEP_DEVICE");
     const int F = frames->n_frames;
     if (F > 0 && (!charges || !species_masses || !mu_out)) return c->fail(TNEP_E_INVALID, "NULL argument");
     if (!(length_unit > 0) || !std::isfinite(length_unit)) return c->fail(TNEP_E_INVALID, "length_unit must be > 0");

@@ -215,7 +215,7 @@ int fetch_meta(Ctx* c, const tnep_frames& fr, HostMeta& m) {
     m.offs.resize(F + 1);
     if (fr.cells) m.cells.resize((size_t)9 * F);
     if (fr.pbc) m.pbc.resize((size_t)3 * F);
-    if (fr.location == TNEP_HOST) {
+    if (fr.location != TNEP_DEVICE) {  // TNEP_HOST, TNEP_DEVICE_META_HOST: the layout is in host memory
         std::memcpy(m.offs.data(), fr.atom_offsets, sizeof(int64_t) * (F + 1));
         if (fr.cells) std::memcpy(m.cells.data(), fr.cells, sizeof(double) * 9 * F);
         if (fr.pbc) std::memcpy(m.pbc.data(), fr.pbc, 3 * (size_t)F);
@@ -798,12 +798,12 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     nt_of[q] = kind == TNEP_KIND_DIPOLE ? 3 : (kind == TNEP_KIND_POLARIZABILITY ? 9 : 10);
                     na_of[q] = kind == TNEP_KIND_PES ? 1 : nt_of[q];
                     pa_of[q] = (double*)c->per_atom.p + (size_t)B_res * 10 * q;
-                    if (kind != TNEP_KIND_PES && job.per_atom[k] && fr.location == TNEP_DEVICE)
+                    if (kind != TNEP_KIND_PES && job.per_atom[k] && fr.location != TNEP_HOST)
                         pa_of[q] = job.per_atom[k] + a0 * nt_of[q];
                     double* staged = (double*)c->out.p + (size_t)nt_max * cap_frames * q;
-                    out_of[q] = fr.location == TNEP_DEVICE ? job.out[k] + (size_t)f0 * na_of[q] : staged;
+                    out_of[q] = fr.location != TNEP_HOST ? job.out[k] + (size_t)f0 * na_of[q] : staged;
                     if (kind == TNEP_KIND_PES) {
-                        if (fr.location == TNEP_DEVICE) {
+                        if (fr.location != TNEP_HOST) {
                             aux_of[q] = job.aux[k] ? job.aux[k] + (size_t)f0 * 9 : nullptr;
                             forces_dst = job.forces ? job.forces + a0 * 3 : nullptr;
                             energies_dst = job.per_atom[k] ? job.per_atom[k] + a0 : nullptr;
@@ -899,7 +899,7 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                     // whether the plain cell-grid search runs beside the pair-parallel one
                     if (pair_search) key += pair_radial ? (plain_grid ? "/rg1" : "/rg0") : (plain_grid ? "/g1" : "/g0");
                     // device-resident frames: the caller's buffers the kernels read and write
-                    if (fr.location == TNEP_DEVICE) {
+                    if (fr.location != TNEP_HOST) {
                         char db[64];
                         snprintf(db, sizeof(db), "/d%p.%p", (const void*)pos, (const void*)spc);
                         key += db;

@@ -20,7 +20,7 @@ TNEP_OK = 0
 ERRORS = {0: "TNEP_OK", -1: "TNEP_E_INVALID", -2: "TNEP_E_SPECIES", -3: "TNEP_E_BOX", -4: "TNEP_E_OVERLAP",
           -5: "TNEP_E_NONFINITE", -6: "TNEP_E_BUDGET", -7: "TNEP_E_MODEL", -8: "TNEP_E_HIP",
           -9: "TNEP_E_NEIGH_OVERFLOW", -10: "TNEP_E_CANCELLED"}
-HOST, DEVICE = 0, 1
+HOST, DEVICE, DEVICE_META_HOST = 0, 1, 2
 KIND_DIPOLE, KIND_POLARIZABILITY, KIND_PES = 1, 2, 3
 MLP_FP32_VALU, MLP_FP32_MFMA, MLP_BF16_MFMA, MLP_BF16X3_MFMA = 0, 1, 2, 3
 OPT_MLP, OPT_ATOMS_PER_BLOCK, OPT_AUTOTUNE, OPT_DETERMINISTIC, OPT_MAX_BATCH_ATOMS, OPT_TIMING = 1, 2, 3, 4, 5, 6
@@ -298,11 +298,15 @@ def tnep_model_save(m, path):
 
 def frames_desc(frames, location=None):
     """Build a tnep_frames from host numpy arrays (synth.Frames) or from an
-    object whose fields are torch CUDA tensors (DeviceFrames)."""
+    object whose fields are torch CUDA tensors (DeviceFrames; with host_meta,
+    its offsets, cells and pbc are numpy arrays: TNEP_DEVICE_META_HOST)."""
     d = FramesDesc()
     d.n_frames = int(frames.offsets.shape[0] - 1)
     if location is None:
-        location = HOST if isinstance(frames.positions, np.ndarray) else DEVICE
+        if isinstance(frames.positions, np.ndarray):
+            location = HOST
+        else:
+            location = DEVICE_META_HOST if isinstance(frames.offsets, np.ndarray) else DEVICE
     if location == HOST:
         keep = (np.ascontiguousarray(frames.offsets, np.int64), np.ascontiguousarray(frames.positions, np.float64),
                 np.ascontiguousarray(frames.species, np.int32),
@@ -317,16 +321,23 @@ def frames_desc(frames, location=None):
 
 
 class DeviceFrames:
-    """Frames resident in device memory as torch tensors."""
+    """Frames resident in device memory as torch tensors.  host_meta: keep the
+    layout (offsets, cells, pbc) as host numpy arrays (TNEP_DEVICE_META_HOST)."""
 
-    def __init__(self, frames, device="cuda"):
+    def __init__(self, frames, device="cuda", host_meta=False):
         import torch
 
-        self.offsets = torch.as_tensor(np.asarray(frames.offsets, np.int64)).to(device)
+        def meta(x, dtype):
+            if x is None:
+                return None
+            a = np.ascontiguousarray(x, dtype)
+            return a if host_meta else torch.as_tensor(a).to(device)
+
+        self.offsets = meta(frames.offsets, np.int64)
         self.positions = torch.as_tensor(np.asarray(frames.positions, np.float64)).to(device).contiguous()
         self.species = torch.as_tensor(np.asarray(frames.species, np.int32)).to(device)
-        self.cells = None if frames.cells is None else torch.as_tensor(np.asarray(frames.cells, np.float64)).to(device)
-        self.pbc = None if frames.pbc is None else torch.as_tensor(np.asarray(frames.pbc, np.uint8)).to(device)
+        self.cells = meta(frames.cells, np.float64)
+        self.pbc = meta(frames.pbc, np.uint8)
         self.n_frames = int(frames.offsets.shape[0] - 1)
         self.n_atoms = int(frames.offsets[-1])
 

@@ -421,3 +421,50 @@ def test_small_batch_bucket_pipeline_matches_large_batches(gpu_lib, ctx):
     m3.close()
     c3.close()
     mdl.close()
+
+
+def test_device_frames_with_host_layout(gpu_lib, ctx):
+    """TNEP_DEVICE_META_HOST (positions and species on the device; offsets,
+    cells and pbc on the host): tensors and potential-energy outputs bitwise
+    those of host and device frames, also under graph replay; the calls that do
+    not take it return TNEP_E_INVALID."""
+    import torch
+
+    md, mp, pm = synth.model("water_dipole"), synth.model("water_polarizability"), synth.model("water_pes")
+    pos, spc, cell = synth.water_box(8, 24.84, seed=102)
+    big = synth.Frames(np.array([0, len(spc)], np.int64), pos, spc, cell[None], np.ones((1, 3), np.uint8))
+    fr = synth.Frames.concat([synth.water_small(3, seed=103), big])
+    gd, gp, ge = gpu_lib.Model(ctx, md), gpu_lib.Model(ctx, mp), gpu_lib.Model(ctx, pm)
+    mu, al = gpu_lib.tnep_eval_dipole_polarizability(ctx, gd, gp, fr)
+    _check(al.reshape(len(al), -1), mp, fr, "water boxes (host frames)")
+    E, W, F = gpu_lib.tnep_eval_pes(ctx, ge, fr)
+    cg = gpu_lib.Context(0)
+    cg.set_option(gpu_lib.OPT_GRAPHS, 1)
+    hd, hp = gpu_lib.Model(cg, md), gpu_lib.Model(cg, mp)
+    for host_meta in (False, True):
+        dfr = gpu_lib.DeviceFrames(fr, host_meta=host_meta)
+        want = gpu_lib.DEVICE_META_HOST if host_meta else gpu_lib.DEVICE
+        assert gpu_lib.frames_desc(dfr).location == want
+        for c, a, b in ((ctx, gd, gp), (cg, hd, hp), (cg, hd, hp), (cg, hd, hp)):
+            dmu = torch.zeros((fr.n_frames, 3), dtype=torch.float64, device="cuda")
+            dal = torch.zeros((fr.n_frames, 9), dtype=torch.float64, device="cuda")
+            gpu_lib.tnep_eval_dipole_polarizability(c, a, b, dfr, dmu, dal)
+            torch.cuda.synchronize()
+            assert np.array_equal(dmu.cpu().numpy(), mu) and np.array_equal(dal.cpu().numpy(), al.reshape(-1, 9))
+        dE = torch.zeros(fr.n_frames, dtype=torch.float64, device="cuda")
+        dW = torch.zeros((fr.n_frames, 9), dtype=torch.float64, device="cuda")
+        dF = torch.zeros((fr.n_atoms, 3), dtype=torch.float64, device="cuda")
+        gpu_lib.tnep_eval_pes(ctx, ge, dfr, dE, dW, dF)
+        torch.cuda.synchronize()
+        assert np.array_equal(dE.cpu().numpy(), E) and np.array_equal(dW.cpu().numpy(), W.reshape(-1, 9))
+        assert np.array_equal(dF.cpu().numpy(), F)
+    assert cg.graph_counts()[1] >= 4
+    dfr = gpu_lib.DeviceFrames(fr, host_meta=True)
+    dmu = torch.zeros((fr.n_frames, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu_lib.TnepError) as e:
+        gpu_lib.tnep_eval_dipole_charged(ctx, gd, dfr, torch.zeros(fr.n_frames, dtype=torch.float64, device="cuda"),
+                                         [15.999, 1.008], mu_out=dmu)
+    assert e.value.code == -1
+    for x in (gd, gp, ge, hd, hp):
+        x.close()
+    cg.close()

@@ -41,3 +41,37 @@ def test_context_creation_fails_cleanly_without_gpu():
         assert e.code == -8
     else:
         raise AssertionError("context creation should fail without a GPU")
+
+
+def test_frames_location_follows_the_array_types():
+    """The binding's tnep_frames: numpy arrays are TNEP_HOST; tensors are
+    TNEP_DEVICE, or TNEP_DEVICE_META_HOST when offsets, cells and pbc are numpy
+    arrays (the values match include/tnep.h)."""
+    import numpy as np
+    import torch
+
+    from paper_2312_05233_amd import tnep
+
+    src = open(os.path.join(ROOT, "include", "tnep.h")).read()
+    for name, value in (("TNEP_HOST", tnep.HOST), ("TNEP_DEVICE", tnep.DEVICE),
+                        ("TNEP_DEVICE_META_HOST", tnep.DEVICE_META_HOST)):
+        assert re.search(r"#define %s %d\b" % (name, value), src), name
+
+    class F:
+        pass
+
+    host = F()
+    host.offsets, host.positions = np.array([0, 2], np.int64), np.zeros((2, 3))
+    host.species, host.cells, host.pbc = np.zeros(2, np.int32), None, None
+    mixed = F()
+    mixed.offsets, mixed.positions = host.offsets, torch.zeros((2, 3), dtype=torch.float64)
+    mixed.species, mixed.cells, mixed.pbc = torch.zeros(2, dtype=torch.int32), np.eye(3).reshape(1, 9), None
+    dev = F()
+    dev.offsets, dev.positions = torch.as_tensor(host.offsets), mixed.positions
+    dev.species, dev.cells, dev.pbc = mixed.species, None, None
+    assert tnep.frames_desc(host).location == tnep.HOST
+    d = tnep.frames_desc(mixed)
+    assert d.location == tnep.DEVICE_META_HOST
+    assert d.atom_offsets == host.offsets.ctypes.data and d.cells == mixed.cells.ctypes.data
+    assert d.positions == mixed.positions.data_ptr()
+    assert tnep.frames_desc(dev).location == tnep.DEVICE
