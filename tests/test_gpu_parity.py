@@ -468,3 +468,32 @@ def test_device_frames_with_host_layout(gpu_lib, ctx):
     for x in (gd, gp, ge, hd, hp):
         x.close()
     cg.close()
+
+
+def test_bucket_pipeline_size_bounds(gpu_lib, ctx):
+    """The one-work-group bucket pipeline at its bounds (4,096 atoms, 1,024
+    cells: 1,024 four-atom molecules) and one past each (a fifth atom in the
+    last molecule: the five-kernel pipeline with the one-work-group scan; a
+    1,025th molecule: the three-phase scan); the frames they share are bitwise
+    the same, and a sample equals the oracle."""
+    m = synth.model("molecule_dipole")
+    mdl = gpu_lib.Model(ctx, m)
+    rng = np.random.default_rng(105)
+    parts = [synth.molecule(rng, 4) for _ in range(1025)] + [synth.molecule(rng, 5)]
+
+    def frames(sel):
+        ps = [parts[i] for i in sel]
+        offs = np.zeros(len(ps) + 1, np.int64)
+        offs[1:] = np.cumsum([len(s) for _, s in ps])
+        return synth.Frames(offs, np.concatenate([p for p, _ in ps]),
+                            np.concatenate([s for _, s in ps]).astype(np.int32), None, None)
+
+    at_bound = frames(range(1024))  # 4,096 atoms, 1,024 cells
+    assert at_bound.n_atoms == 4096
+    a = gpu_lib.tnep_eval_dipole(ctx, mdl, at_bound)
+    b = gpu_lib.tnep_eval_dipole(ctx, mdl, frames(list(range(1023)) + [1025]))  # 4,097 atoms
+    c = gpu_lib.tnep_eval_dipole(ctx, mdl, frames(range(1025)))  # 1,025 cells
+    assert np.array_equal(a[:1023], b[:1023]) and np.array_equal(a, c[:1024])
+    sample = at_bound.subset(range(0, 1024, 16))
+    _check(a[::16], m, sample, "four-atom molecules at the pipeline bound")
+    mdl.close()
