@@ -574,14 +574,18 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 // every frame's outputs, copied back to the caller once at the end
                 if ((e = c->reserve(c->out_call, sizeof(double) * 10 * (size_t)F * (last - first)))) return e;
             }
+            // host frames are staged through pinned memory (one half, or two when the
+            // inputs of the next batch are copied during this one), so their copies
+            // are plain DMA that the host does not wait for
+            const size_t in_need = (size_t)B_res * (overlap_inputs ? 56 : 28);
+            if (fr.location == TNEP_HOST && c->in_host_bytes < in_need) {
+                if (c->in_host) (void)hipHostFree(c->in_host);
+                c->in_host = nullptr;
+                c->in_host_bytes = 0;
+                HIP_CHECK_RET(c, hipHostMalloc((void**)&c->in_host, in_need, hipHostMallocDefault));
+                c->in_host_bytes = in_need;
+            }
             if (overlap_inputs) {
-                if (c->in_host_bytes < (size_t)B_res * 56) {
-                    if (c->in_host) (void)hipHostFree(c->in_host);
-                    c->in_host = nullptr;
-                    c->in_host_bytes = 0;
-                    HIP_CHECK_RET(c, hipHostMalloc((void**)&c->in_host, (size_t)B_res * 56, hipHostMallocDefault));
-                    c->in_host_bytes = (size_t)B_res * 56;
-                }
                 if (!c->copy_stream) {
                     HIP_CHECK_RET(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
                     for (int h = 0; h < 2; ++h) {
@@ -741,9 +745,13 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 const int32_t* spc;
                 const int half = overlap_inputs ? (batch & 1) : 0;
                 if (fr.location == TNEP_HOST && !overlap_inputs) {
-                    HIP_CHECK_RET(c, hipMemcpyAsync(c->pos.p, fr.positions + 3 * a0, (size_t)na * 24,
-                                                    hipMemcpyHostToDevice, c->stream));
-                    HIP_CHECK_RET(c, hipMemcpyAsync(c->species.p, fr.species + a0, (size_t)na * 4,
+                    // the call's one batch (the staging is free: the previous call ended
+                    // with a sync of the stream)
+                    std::memcpy(c->in_host, fr.positions + 3 * a0, (size_t)na * 24);
+                    std::memcpy(c->in_host + (size_t)B_res * 24, fr.species + a0, (size_t)na * 4);
+                    HIP_CHECK_RET(c, hipMemcpyAsync(c->pos.p, c->in_host, (size_t)na * 24, hipMemcpyHostToDevice,
+                                                    c->stream));
+                    HIP_CHECK_RET(c, hipMemcpyAsync(c->species.p, c->in_host + (size_t)B_res * 24, (size_t)na * 4,
                                                     hipMemcpyHostToDevice, c->stream));
                     pos = (const double*)c->pos.p;
                     spc = (const int32_t*)c->species.p;
@@ -950,22 +958,34 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 f0 = f1;
                 ++batch;
             }
+            // host frames: every model's outputs back into pinned memory in one copy
+            // (the models' regions of out_call are adjacent), handed to the caller
+            // after the sync below
+            const size_t out_bytes = sizeof(double) * 10 * (size_t)F * (last - first);
+            if (fr.location == TNEP_HOST) {
+                if (c->rb_host_bytes < out_bytes) {
+                    if (c->rb_host) (void)hipHostFree(c->rb_host);
+                    c->rb_host = nullptr;
+                    c->rb_host_bytes = 0;
+                    HIP_CHECK_RET(c, hipHostMalloc((void**)&c->rb_host, out_bytes, hipHostMallocDefault));
+                    c->rb_host_bytes = out_bytes;
+                }
+                HIP_CHECK_RET(c, hipMemcpyAsync(c->rb_host, c->out_call.p, out_bytes, hipMemcpyDeviceToHost, c->stream));
+            }
+            HIP_CHECK_RET(c, hipMemcpyAsync(c->h_flags, c->flags.p, sizeof(int32_t) * 32, hipMemcpyDeviceToHost,
+                                            c->stream));
+            HIP_CHECK_RET(c, hipStreamSynchronize(c->stream));
             if (fr.location == TNEP_HOST) {
                 for (int k = first; k < last; ++k) {
                     const int q = k - first;
                     const int kind = job.models[k]->kind;
                     const int na_ = kind == TNEP_KIND_DIPOLE ? 3 : (kind == TNEP_KIND_POLARIZABILITY ? 9 : 1);
-                    const double* oc = (const double*)c->out_call.p + (size_t)10 * F * q;
-                    HIP_CHECK_RET(c, hipMemcpyAsync(job.out[k], oc, sizeof(double) * na_ * F, hipMemcpyDeviceToHost,
-                                                    c->stream));
+                    const double* oc = reinterpret_cast<const double*>(c->rb_host) + (size_t)10 * F * q;
+                    std::memcpy(job.out[k], oc, sizeof(double) * na_ * F);
                     if (kind == TNEP_KIND_PES && job.aux[k])
-                        HIP_CHECK_RET(c, hipMemcpyAsync(job.aux[k], oc + (size_t)F * na_, sizeof(double) * 9 * F,
-                                                        hipMemcpyDeviceToHost, c->stream));
+                        std::memcpy(job.aux[k], oc + (size_t)F * na_, sizeof(double) * 9 * F);
                 }
             }
-            HIP_CHECK_RET(c, hipMemcpyAsync(c->h_flags, c->flags.p, sizeof(int32_t) * 32, hipMemcpyDeviceToHost,
-                                            c->stream));
-            HIP_CHECK_RET(c, hipStreamSynchronize(c->stream));
             c->timer_flush();
             const int32_t* fl = c->h_flags;
             if (reuse && fl[kFlagReuse]) {
