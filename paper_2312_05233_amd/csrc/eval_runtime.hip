@@ -204,6 +204,10 @@ int frame_geometry(Ctx* c, int f, const double* cell, const uint8_t* pbc, double
 
 namespace {
 
+// Host frames of one launch batch up to this many atoms (1.8 MB of inputs) are
+// copied to the device through the context's pinned staging.
+constexpr int64_t kPinnedInputAtoms = 65536;
+
 struct HostMeta {
     std::vector<int64_t> offs;
     std::vector<double> cells;
@@ -574,11 +578,14 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 // every frame's outputs, copied back to the caller once at the end
                 if ((e = c->reserve(c->out_call, sizeof(double) * 10 * (size_t)F * (last - first)))) return e;
             }
-            // host frames are staged through pinned memory (one half, or two when the
-            // inputs of the next batch are copied during this one), so their copies
-            // are plain DMA that the host does not wait for
-            const size_t in_need = (size_t)B_res * (overlap_inputs ? 56 : 28);
-            if (fr.location == TNEP_HOST && c->in_host_bytes < in_need) {
+            // host frames are staged through pinned memory, so their copies are plain
+            // DMA that the host does not wait for: two halves when the inputs of the
+            // next batch are copied during this one; one for a call of one batch of at
+            // most kPinnedInputAtoms atoms (larger ones keep the runtime's pageable
+            // copy, which overlaps its own staging with the transfer)
+            const bool stage_inputs = fr.location == TNEP_HOST && !overlap_inputs && A <= kPinnedInputAtoms;
+            const size_t in_need = overlap_inputs ? (size_t)B_res * 56 : (stage_inputs ? (size_t)B_res * 28 : 0);
+            if (in_need > 0 && c->in_host_bytes < in_need) {
                 if (c->in_host) (void)hipHostFree(c->in_host);
                 c->in_host = nullptr;
                 c->in_host_bytes = 0;
@@ -745,14 +752,21 @@ static int run_eval_core(Ctx* c, const tnep_frames& fr, const EvalJob& job) {
                 const int32_t* spc;
                 const int half = overlap_inputs ? (batch & 1) : 0;
                 if (fr.location == TNEP_HOST && !overlap_inputs) {
-                    // the call's one batch (the staging is free: the previous call ended
-                    // with a sync of the stream)
-                    std::memcpy(c->in_host, fr.positions + 3 * a0, (size_t)na * 24);
-                    std::memcpy(c->in_host + (size_t)B_res * 24, fr.species + a0, (size_t)na * 4);
-                    HIP_CHECK_RET(c, hipMemcpyAsync(c->pos.p, c->in_host, (size_t)na * 24, hipMemcpyHostToDevice,
-                                                    c->stream));
-                    HIP_CHECK_RET(c, hipMemcpyAsync(c->species.p, c->in_host + (size_t)B_res * 24, (size_t)na * 4,
-                                                    hipMemcpyHostToDevice, c->stream));
+                    if (stage_inputs) {
+                        // the call's one batch (the staging is free: the previous call
+                        // ended with a sync of the stream)
+                        std::memcpy(c->in_host, fr.positions + 3 * a0, (size_t)na * 24);
+                        std::memcpy(c->in_host + (size_t)B_res * 24, fr.species + a0, (size_t)na * 4);
+                        HIP_CHECK_RET(c, hipMemcpyAsync(c->pos.p, c->in_host, (size_t)na * 24, hipMemcpyHostToDevice,
+                                                        c->stream));
+                        HIP_CHECK_RET(c, hipMemcpyAsync(c->species.p, c->in_host + (size_t)B_res * 24, (size_t)na * 4,
+                                                        hipMemcpyHostToDevice, c->stream));
+                    } else {
+                        HIP_CHECK_RET(c, hipMemcpyAsync(c->pos.p, fr.positions + 3 * a0, (size_t)na * 24,
+                                                        hipMemcpyHostToDevice, c->stream));
+                        HIP_CHECK_RET(c, hipMemcpyAsync(c->species.p, fr.species + a0, (size_t)na * 4,
+                                                        hipMemcpyHostToDevice, c->stream));
+                    }
                     pos = (const double*)c->pos.p;
                     spc = (const int32_t*)c->species.p;
                 } else if (fr.location == TNEP_HOST) {
