@@ -439,7 +439,8 @@ def bench_latency(args):
     layout (TNEP_OPT_PAIR_PARALLEL: 16 lanes per atom): mean wall time per call
     and the evaluation kernels' mean time per call (HIP events); then both
     layouts with the frames' layout (offsets, cells, pbc) in host memory
-    (TNEP_DEVICE_META_HOST: no metadata read back from the device)."""
+    (TNEP_DEVICE_META_HOST: no metadata read back from the device), and both
+    on host frames (inputs copied in and tensors returned within the call)."""
     import torch
 
     from paper_2312_05233_amd import tnep
@@ -456,13 +457,17 @@ def bench_latency(args):
     out = []
     for label, frames, models in cases:
         rec = {"workload": label, "atoms": frames.n_atoms}
-        for pp, host_meta in ((0, False), (1, False), (0, True), (1, True)):
+        for pp, where in ((0, "device"), (1, "device"), (0, "host_layout"), (1, "host_layout"), (0, "host"),
+                          (1, "host")):
             ctx = tnep.Context(0)
             ctx.set_option(tnep.OPT_PAIR_PARALLEL, pp)
             gm = [tnep.Model(ctx, m) for m in models]
-            dfr = tnep.DeviceFrames(frames, host_meta=host_meta)
-            mu = torch.zeros((frames.n_frames, 3), dtype=torch.float64, device="cuda")
-            al = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
+            if where == "host":
+                dfr, mu, al = frames, np.zeros((frames.n_frames, 3)), np.zeros((frames.n_frames, 3, 3))
+            else:
+                dfr = tnep.DeviceFrames(frames, host_meta=where == "host_layout")
+                mu = torch.zeros((frames.n_frames, 3), dtype=torch.float64, device="cuda")
+                al = torch.zeros((frames.n_frames, 9), dtype=torch.float64, device="cuda")
             if len(gm) == 2:
                 step = lambda: tnep.tnep_eval_dipole_polarizability(ctx, gm[0], gm[1], dfr, mu, al)  # noqa: E731
             else:
@@ -478,7 +483,7 @@ def bench_latency(args):
             for _ in range(n):
                 one_call()
             ev = sum(ctx.kernel_time(k)[0] for k in (tnep.KERNEL_EVAL_DIPOLE, tnep.KERNEL_EVAL_POLARIZABILITY)) / n
-            name = ("pair_parallel" if pp else "default") + ("_host_layout" if host_meta else "")
+            name = ("pair_parallel" if pp else "default") + ("" if where == "device" else "_" + where)
             rec[name] = {"us_per_call": 1e6 * t, "eval_kernels_us_per_call": 1e3 * ev}
             for g in gm:
                 g.close()
