@@ -1013,11 +1013,30 @@ __global__ void __launch_bounds__(kBlock) k_neighbors_pp(const FrameInfo* __rest
                 // same in the group's lanes, so they run the loop together
                 const float(*wave_terms)[2 * kPpTermStride] = pp_terms + (threadIdx.x & ~63u);
                 if (g < kRadialTerms) {
+                    // up to four accepted candidates per step: their terms are read
+                    // together, then added one after another in candidate order
+                    const int a = g == 0 ? 0 : 1, b = g == 0 ? 0 : 1 + g;  // rsum += t[a] * t[b]
 #pragma unroll
                     for (int u = 0; u < 2; ++u) {
-                        for (uint32_t m = acc[u]; m != 0u; m &= m - 1u) {
-                            const float* ts = wave_terms[first + __builtin_ctz(m)] + u * kPpTermStride;
-                            rsum = g == 0 ? __builtin_fmaf(ts[0], ts[0], rsum) : __builtin_fmaf(ts[1], ts[1 + g], rsum);
+                        uint32_t m = acc[u];
+                        while (m != 0u) {
+                            float x[4], y[4];
+                            int n_take = 0;
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                x[i] = 0.f;
+                                y[i] = 0.f;
+                                if (m != 0u) {
+                                    const float* ts = wave_terms[first + __builtin_ctz(m)] + u * kPpTermStride;
+                                    x[i] = ts[a];
+                                    y[i] = ts[b];
+                                    m &= m - 1u;
+                                    n_take = i + 1;
+                                }
+                            }
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                if (i < n_take) rsum = __builtin_fmaf(x[i], y[i], rsum);
                         }
                     }
                 }
