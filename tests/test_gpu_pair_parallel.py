@@ -191,3 +191,31 @@ def test_triclinic_and_trajectory_frames(gpu_lib):
     _check(_eval(gpu_lib, c, m, traj), m, traj, "trajectory reuse (pair-parallel)")
     assert c.reuse_fallbacks() == 0
     c.close()
+
+
+def test_edge_frames_with_host_layout(gpu_lib, ctxs):
+    """Empty frames, a single atom and isolated atoms as device frames with the
+    layout on the host, in both layouts: bitwise the host-frame results."""
+    import torch
+
+    md, mp = synth.model("molecule_dipole"), synth.model("molecule_polarizability")
+    mol = synth.molecules(3, seed=4)
+    parts = [synth.Frames(np.array([0, 0], np.int64), np.zeros((0, 3)), np.zeros(0, np.int32)),
+             mol.subset([0]),
+             synth.Frames(np.array([0, 1], np.int64), np.zeros((1, 3)), np.array([2], np.int32)),
+             synth.Frames(np.array([0, 0], np.int64), np.zeros((0, 3)), np.zeros(0, np.int32)),
+             synth.Frames(np.array([0, 2], np.int64), np.array([[0, 0, 0], [10.0, 0, 0]]), np.array([1, 3], np.int32)),
+             mol.subset([1, 2])]
+    fr = synth.Frames.concat(parts)
+    dfr = gpu_lib.DeviceFrames(fr, host_meta=True)
+    for c in ctxs:
+        gd, gp = gpu_lib.Model(c, md), gpu_lib.Model(c, mp)
+        mu, al = gpu_lib.tnep_eval_dipole_polarizability(c, gd, gp, fr)
+        dmu = torch.zeros((fr.n_frames, 3), dtype=torch.float64, device="cuda")
+        dal = torch.zeros((fr.n_frames, 9), dtype=torch.float64, device="cuda")
+        gpu_lib.tnep_eval_dipole_polarizability(c, gd, gp, dfr, dmu, dal)
+        torch.cuda.synchronize()
+        assert np.array_equal(dmu.cpu().numpy(), mu) and np.array_equal(dal.cpu().numpy(), al.reshape(-1, 9))
+        assert np.all(mu[[0, 2, 3, 4]] == 0.0)
+        gd.close()
+        gp.close()
